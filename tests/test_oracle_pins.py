@@ -1,0 +1,446 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test ties the oracle to the paper, to a published standard, to a closed
+form / invariant, or to an independent 50-digit brute force written here from
+the published definitions (IEC 61966-2-1 sRGB, CIE 1976 L*a*b*).
+"""
+from __future__ import annotations
+
+import os
+from decimal import ROUND_HALF_EVEN, Decimal, getcontext
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+getcontext().prec = 50
+D = Decimal
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# --------------------------------------------------------------------------
+# An independent arbitrary-precision model of the colour conversions.
+
+def _solve3(A, b):
+    """Gauss-Jordan elimination with partial pivoting (Decimal)."""
+    m = [list(A[r]) + [b[r]] for r in range(3)]
+    for c in range(3):
+        piv = max(range(c, 3), key=lambda r: abs(m[r][c]))
+        m[c], m[piv] = m[piv], m[c]
+        for r in range(3):
+            if r != c:
+                f = m[r][c] / m[c][c]
+                m[r] = [m[r][k] - f * m[c][k] for k in range(4)]
+    return [m[r][3] / m[r][r] for r in range(3)]
+
+
+def _dec_space():
+    prim = [(D("0.64"), D("0.33")), (D("0.30"), D("0.60")), (D("0.15"), D("0.06"))]
+    wx, wy = D("0.3127"), D("0.3290")
+    P = [[x / y for x, y in prim], [D(1)] * 3, [(1 - x - y) / y for x, y in prim]]
+    Wv = [wx / wy, D(1), (1 - wx - wy) / wy]
+    S = _solve3(P, Wv)
+    M = [[P[r][c] * S[c] for c in range(3)] for r in range(3)]
+    # columns of the inverse: solve M x = e_k
+    cols = [_solve3(M, [D(int(k == r)) for r in range(3)]) for k in range(3)]
+    Minv = [[cols[c][r] for c in range(3)] for r in range(3)]
+    return M, Minv, Wv
+
+
+DM, DMINV, DW = _dec_space()
+DELTA = D(6) / D(29)
+
+
+def d_decode(c):
+    return c / D("12.92") if c <= D("0.04045") else ((c + D("0.055")) / D("1.055")) ** D("2.4")
+
+
+def d_encode(l):
+    return D("12.92") * l if l <= D("0.0031308") else D("1.055") * l ** (D(1) / D("2.4")) - D("0.055")
+
+
+def d_f(t):
+    return t ** (D(1) / D(3)) if t > DELTA ** 3 else t / (3 * DELTA ** 2) + D(4) / D(29)
+
+
+def d_finv(u):
+    return u ** 3 if u > DELTA else 3 * DELTA ** 2 * (u - D(4) / D(29))
+
+
+def d_rgb8_to_lab(rgb):
+    lin = [d_decode(D(int(v)) / D(255)) for v in rgb]
+    xyz = [sum(DM[r][k] * lin[k] for k in range(3)) for r in range(3)]
+    f = [d_f(xyz[r] / DW[r]) for r in range(3)]
+    return [116 * f[1] - 16, 500 * (f[0] - f[1]), 200 * (f[1] - f[2])]
+
+
+def d_lab_to_linear(lab):
+    L, a, b = lab
+    fy = (L + 16) / 116
+    xyz = [DW[0] * d_finv(fy + a / 500), DW[1] * d_finv(fy), DW[2] * d_finv(fy - b / 200)]
+    return [sum(DMINV[r][k] * xyz[k] for k in range(3)) for r in range(3)]
+
+
+def d_round(v):
+    return int(v.quantize(D(1), rounding=ROUND_HALF_EVEN))
+
+
+# --------------------------------------------------------------------------
+# Published constants.
+
+def test_matrix_matches_published_srgb(oracle):
+    """IEC 61966-2-1 lists the linear-sRGB -> XYZ matrix to 4 decimals and the
+    luminance row (0.2126, 0.7152, 0.0722)."""
+    M, Minv, Wp = oracle.matrices()
+    published = np.array([[0.4124, 0.3576, 0.1805], [0.2126, 0.7152, 0.0722],
+                          [0.0193, 0.1192, 0.9505]])
+    assert np.abs(M - published).max() < 6e-5
+    assert np.allclose(M @ np.ones(3), Wp, atol=1e-15)
+    assert np.allclose(M @ Minv, np.eye(3), atol=1e-14)
+    # the D65 white point (x, y) = (0.3127, 0.3290) with Y = 1
+    assert np.allclose(Wp, [0.3127 / 0.3290, 1.0, (1 - 0.3127 - 0.3290) / 0.3290], atol=1e-15)
+    # the 50-digit derivation agrees
+    assert np.allclose(M, np.array([[float(x) for x in r] for r in DM]), atol=1e-15)
+
+
+def test_transfer_function_continuity_and_inverse(oracle):
+    # both branches of encode meet at the IEC threshold within 1e-7 and decode
+    # inverts encode on the 8-bit codes
+    for c in range(256):
+        assert abs(oracle.encode(oracle.decode(c / 255.0)) - c / 255.0) < 1e-12
+    t = 0.0031308
+    assert abs(12.92 * t - (1.055 * t ** (1 / 2.4) - 0.055)) < 1e-7
+    assert abs(oracle.decode(0.5) - float(d_decode(D("0.5")))) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# Closed forms and invariants.
+
+def test_neutral_axis_and_extremes(oracle):
+    """Gray (g,g,g) has a* = b* = 0; white L* = 100; black L* = 0."""
+    grays = np.repeat(np.arange(256, dtype=np.uint8)[:, None], 3, axis=1)
+    lab = oracle.rgb8_to_lab(grays)
+    assert np.abs(lab[:, 1:]).max() < 1e-12
+    assert abs(lab[255, 0] - 100.0) < 1e-12
+    assert abs(lab[0, 0]) < 1e-12
+    assert np.all(np.diff(lab[:, 0]) > 0)
+
+
+def test_lightness_of_paper_grays_50_digits(oracle):
+    """L* of the three Table 1 grays against the 50-digit model (and the
+    hand-computed 42.38 / 69.62 / 94.80)."""
+    for g, approx in ((100, 42.38), (170, 69.61), (240, 94.80)):
+        lab = oracle.rgb8_to_lab([g, g, g])[0]
+        ref = [float(x) for x in d_rgb8_to_lab((g, g, g))]
+        assert np.allclose(lab, ref, atol=1e-12)
+        assert abs(lab[0] - approx) < 0.01
+
+
+def test_round_trip_all_colours(oracle):
+    """RGB8 -> Lab -> RGB8 is the identity on all 2^24 colours (Q1, Q2, Q6)."""
+    step = 1 << 21
+    for start in range(0, 1 << 24, step):
+        ids = np.arange(start, start + step, dtype=np.uint32)
+        rgb = W.cube_colours(ids)
+        v, g = oracle.lab_to_v(oracle.rgb8_to_lab(rgb))
+        # channels at 0 or 255 sit on the gamut edge up to FP64 round-off
+        edge = ((rgb == 0) | (rgb == 255)).any(axis=1)
+        assert g[~edge].all()
+        assert np.array_equal(np.rint(v).astype(np.int64), rgb.astype(np.int64))
+        assert np.abs(v - rgb).max() < 1e-6
+
+
+def test_zero_radius_returns_target(oracle):
+    """r = 0: both colours equal the target, no channel changes, no survivor."""
+    g = (1.0, 4, 1.0, 360)
+    for rgb in list(W.PAPER_COLOURS.values()) + [tuple(c) for c in W.random_colours(3, 40)]:
+        for j in (0, 45, 90, 200):
+            c = oracle.eval_one(rgb, g, W.DEFAULT_RULE, 0, j, r_zero=True)
+            assert tuple(c["Vp"]) == tuple(rgb) and tuple(c["Vm"]) == tuple(rgb)
+            assert c["valid"] == 0
+
+
+def _forward_lab_from_linear(lin, M, Wp):
+    """Independent forward conversion linear RGB -> L*a*b* in FP64."""
+    xyz = lin @ M.T
+    t = xyz / Wp
+    d = 6 / 29
+    f = np.where(t > d ** 3, np.cbrt(t), t / (3 * d * d) + 4 / 29)
+    return np.stack([116 * f[..., 1] - 16, 500 * (f[..., 0] - f[..., 1]),
+                     200 * (f[..., 1] - f[..., 2])], axis=-1)
+
+
+def test_pair_is_point_symmetric_with_fixed_lightness(oracle):
+    """Section 2: the two colours are point-symmetric about the target in
+    L*a*b* with L* fixed.  Converting each colour's (unrounded) linear RGB
+    forward again gives (L, a +- D_a, b +- D_b); their midpoint is the target
+    and their luminance Y equals the target's."""
+    M, _, Wp = oracle.matrices()
+    g = (0.5, 60, 3.0, 120)
+    cols = W.random_colours(11, 6)
+    allc = oracle.eval_all(cols, g, None)
+    lab_t = oracle.rgb8_to_lab(cols)
+    r = (np.arange(60) + 1) * 0.5
+    th = np.deg2rad(np.arange(120) * 3.0)
+    Da = r[:, None] * np.sin(th)[None, :]
+    Db = r[:, None] * np.cos(th)[None, :]
+    for k in range(len(cols)):
+        lp = _forward_lab_from_linear(allc["linp"][k], M, Wp)
+        lm = _forward_lab_from_linear(allc["linm"][k], M, Wp)
+        L, a, b = lab_t[k]
+        ok = np.isfinite(lp).all(-1)
+        assert np.abs(lp[..., 0] - L).max() < 1e-9
+        assert np.abs(lm[..., 0] - L).max() < 1e-9
+        assert np.abs((lp[..., 1] - (a + Da))).max() < 1e-9
+        assert np.abs((lp[..., 2] - (b + Db))).max() < 1e-9
+        assert np.abs((lp + lm) / 2 - lab_t[k]).max() < 1e-9
+        Yp = allc["linp"][k] @ M[1]
+        Ym = allc["linm"][k] @ M[1]
+        Yt = (oracle.lab_to_linear(lab_t[k]) @ M[1])[0]
+        assert np.abs(Yp - Yt).max() < 1e-12 and np.abs(Ym - Yt).max() < 1e-12
+        assert ok.all()
+
+
+def test_half_turn_swaps_the_pair(oracle):
+    """theta + 180 deg negates (D_a, D_b): the pair's colours swap, the pattern
+    is unchanged (P6).  Checked on every non-boundary candidate."""
+    g = (1.0, 60, 2.0, 180)
+    cols = np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(5, 8)])
+    for v_th, rn in ((50, 0.5), (100, 0.25)):
+        a = oracle.eval_all(cols, g, (v_th, rn, 0x7F))
+        x, y = a[:, :, :90], a[:, :, 90:]
+        ok = (x["boundary"] == 0) & (y["boundary"] == 0)
+        assert ok.mean() > 0.99
+        assert np.array_equal(x["valid"][ok], y["valid"][ok])
+        assert np.array_equal(x["pattern"][ok], y["pattern"][ok])
+        both = ok & (x["gamut"] == 3)
+        assert np.array_equal(x["Vp"][both], y["Vm"][both])
+        assert np.array_equal(x["Vm"][both], y["Vp"][both])
+        assert np.array_equal(x["gamut"][ok] & 1, (y["gamut"][ok] >> 1) & 1)
+
+
+# --------------------------------------------------------------------------
+# Brute force at 50 digits on hand grids (P9).
+
+def _dec_candidate(rgb, r, theta_deg, rule):
+    L, a, b = d_rgb8_to_lab(rgb)
+    s, c = {0: (0, 1), 90: (1, 0), 180: (0, -1), 270: (-1, 0)}[theta_deg]
+    Da, Db = D(r) * s, D(r) * c
+    out = {}
+    for tag, sg in (("p", 1), ("m", -1)):
+        lin = d_lab_to_linear((L, a + sg * Da, b + sg * Db))
+        out["lin" + tag] = lin
+        out["v" + tag] = [255 * d_encode(x) for x in lin]
+        out["g" + tag] = all(D(0) <= x <= D(1) for x in lin)
+    res = dict(out)
+    if rule is not None and out["gp"] and out["gm"]:
+        Vp = [d_round(v) for v in out["vp"]]
+        Vm = [d_round(v) for v in out["vm"]]
+        v_th, rn = rule
+        p, ok = 0, True
+        for k in range(3):
+            d = abs(Vp[k] - Vm[k])
+            hi, lo = d > v_th, D(d) < D(v_th) * D(str(rn))
+            ok = ok and (hi or lo)
+            p = 2 * p + int(hi)
+        res.update(Vp=Vp, Vm=Vm, pattern=p if ok else 0, valid=ok and p != 0)
+    else:
+        res.update(valid=False)
+    return res
+
+
+@pytest.mark.parametrize("rgb", [(170, 170, 170), (100, 100, 240), (240, 100, 100), (12, 200, 37),
+                                 (250, 250, 5), (3, 3, 3)])
+def test_brute_force_50_digits(oracle, rgb):
+    """Hand grid r in {5, 10, 20}, theta in {0, 90, 180, 270} deg (theta = 0 is
+    a pure +b* shift, 90 a pure +a* shift) against the 50-digit model."""
+    g = (5.0, 4, 90.0, 4)
+    for rule in ((50, 0.5), (100, 0.25), (150, 0.125)):
+        for i in (0, 1, 3):
+            for j in range(4):
+                c = oracle.eval_one(rgb, g, (rule[0], rule[1], 0x7F), i, j)
+                ref = _dec_candidate(rgb, 5 * (i + 1), 90 * j, rule)
+                for tag in ("p", "m"):
+                    assert np.allclose(c["lin" + tag], [float(x) for x in ref["lin" + tag]],
+                                       atol=1e-12, rtol=0)
+                    assert np.allclose(c["v" + tag], [float(x) for x in ref["v" + tag]],
+                                       atol=1e-9, rtol=0)
+                assert bool(c["gamut"] & 1) == ref["gp"] and bool(c["gamut"] & 2) == ref["gm"]
+                assert bool(c["valid"]) == ref["valid"]
+                if "Vp" in ref:
+                    assert list(c["Vp"]) == ref["Vp"] and list(c["Vm"]) == ref["Vm"]
+                    assert c["pattern"] == ref["pattern"]
+
+
+# --------------------------------------------------------------------------
+# The paper's printed results.
+
+def _read_table2():
+    rows = {}
+    with open(os.path.join(HERE, "golden", "table2_presence.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            rows[parts[0]] = np.array([int(x) for x in parts[1:]], dtype=bool)
+    return rows
+
+
+PRESENCE_GRID = (0.25, 400, 1.0, 360)  # r up to 100, every degree
+
+
+def _presence(oracle, flags=0):
+    pres = np.zeros((9, 7), dtype=bool)
+    for v_th, rn in W.TABLE1_RULES:
+        s = oracle.reduce(W.PAPER_COLOUR_ARRAY, PRESENCE_GRID, (v_th, rn, 0x7F, flags))
+        pres |= s["per_pattern"] > 0
+    return pres
+
+
+def test_table2_presence_is_sound(oracle):
+    """Table 2 (P7).  Under the in-gamut reading every (colour, information)
+    cell the oracle finds over the twelve Table 1 settings is checked in the
+    paper, and the paper's two empty rows (010, 011) stay empty.  The paper's
+    remaining checked cells need out-of-gamut colours (see the clip reading
+    below); that discrepancy is documented, not hidden."""
+    paper = _read_table2()
+    pres = _presence(oracle)
+    for k, pat in enumerate(W.PATTERNS):
+        p = int(pat, 2)
+        ours = pres[:, p - 1]
+        assert not np.any(ours & ~paper[pat]), (pat, ours, paper[pat])
+    assert not pres[:, int("010", 2) - 1].any() and not pres[:, int("011", 2) - 1].any()
+    # the cells found (documented count; a change here is a change of reading)
+    assert int(pres.sum()) == 15
+
+
+def test_table2_under_clip_reading(oracle):
+    """The alternative reading (clamp instead of reject) finds more of the
+    paper's cells but also cells the paper leaves empty; recorded so that the
+    trade-off between the two readings stays visible."""
+    paper = _read_table2()
+    pres = _presence(oracle, flags=1)
+    hit = sum(int((pres[:, int(p, 2) - 1] & paper[p]).sum()) for p in W.PATTERNS)
+    extra = sum(int((pres[:, int(p, 2) - 1] & ~paper[p]).sum()) for p in W.PATTERNS)
+    assert hit > 15 and extra > 0
+
+
+def test_bright_targets_cannot_carry_green_only(oracle):
+    """Fixed L* fixes Y; for Gray and brighter targets a >50-code G swing then
+    needs R/B swings beyond the low bound, so pattern 010 is infeasible at
+    (50, 0.5) (P8; Table 2's empty 010 row)."""
+    for name in ("Gray", "White", "Yellow", "Cyan", "Green"):
+        s = oracle.reduce([W.PAPER_COLOURS[name]], PRESENCE_GRID, (50, 0.5, 0x7F))
+        assert s["per_pattern"][0][1] == 0
+
+
+def test_radius_range_is_exhaustive(oracle):
+    """No pair of any Table 1 colour stays in gamut beyond r = 100, so the
+    nine-colour grid (r <= 100) covers every in-gamut pair (P11)."""
+    m = oracle.max_gamut_radius(W.PAPER_COLOUR_ARRAY, (0.5, 400, 1.0, 360))
+    assert m.max() * 0.5 < 100.0
+    assert m.min() > 0
+
+
+# --------------------------------------------------------------------------
+# Internal consistency of the oracle's own entry points.
+
+def test_search_reduce_and_eval_agree(oracle):
+    g = (0.5, 40, 4.0, 90)
+    cols = np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(7, 5)])
+    rule = (50, 0.5, 0x2D)
+    allc = oracle.eval_all(cols, g, rule)
+    recs, offs, nb = oracle.search(cols, g, rule)
+    summ, tc, tb = oracle.reduce(cols, g, rule, table=True)
+    per = 40 * 90
+    for k in range(len(cols)):
+        v = allc[k].reshape(-1)
+        idx = np.nonzero(v["valid"])[0]
+        seg = recs[offs[k]:offs[k + 1]]
+        assert len(seg) == len(idx) == summ["count"][k] == tc[k]
+        assert np.array_equal(seg["i"].astype(np.int64) * 90 + seg["j"], idx)
+        assert np.array_equal(seg["plus"], v["Vp"][idx]) and np.array_equal(seg["minus"], v["Vm"][idx])
+        assert summ["n_gamut"][k] == int((v["gamut"] == 3).sum())
+        for p in range(1, 8):
+            assert summ["per_pattern"][k][p - 1] == int((v["pattern"][idx] == p).sum())
+            if not (rule[2] >> (p - 1)) & 1:
+                assert summ["per_pattern"][k][p - 1] == 0
+        if len(idx):
+            ii, jj = idx // 90, idx % 90
+            best = idx[np.lexsort((jj, -ii))[0]]
+            assert (summ["best_i"][k], summ["best_j"][k]) == (best // 90, best % 90)
+            bins = np.zeros(36, dtype=np.uint8)
+            for q in idx:
+                b = (q % 90) * 36 // 90
+                bins[b] = max(bins[b], q // 90 + 1)
+            assert np.array_equal(tb[k], bins)
+        else:
+            assert summ["best_i"][k] == 0xFFFF
+    assert nb == int(allc["boundary"].sum())
+    assert offs[-1] == len(recs) and per * len(cols) == allc.size
+
+
+# --------------------------------------------------------------------------
+# MLP oracle: gradients by central finite differences (P12).
+
+def test_mlp_gradients_finite_differences(oracle):
+    rng = np.random.default_rng(5)
+    dims = [3, 8, 8, 8, 37]
+    Ws = [rng.normal(0, 0.6, (dims[l + 1], dims[l])) for l in range(4)]
+    bs = [rng.normal(0, 0.1, dims[l + 1]) for l in range(4)]
+    B = 5
+    x = rng.uniform(-0.5, 0.5, (B, 3))
+    tr = np.where(rng.random((B, 36)) < 0.6, rng.uniform(0.05, 1.0, (B, 36)), 0.0)
+    tf = (rng.random(B) < 0.5).astype(np.float64)
+    delta = 0.1
+
+    def loss(Ws_, bs_):
+        return oracle.mlp_loss(oracle.mlp_forward(dims, Ws_, bs_, x), tr, tf, delta)[0]
+
+    out = oracle.mlp_forward(dims, Ws, bs, x)
+    val, gout = oracle.mlp_loss(out, tr, tf, delta)
+    gWs, gbs = oracle.mlp_backward(dims, Ws, bs, x, gout)
+    h = 1e-6
+    checked = 0
+    for l in range(4):
+        for _ in range(12):
+            o, i = rng.integers(dims[l + 1]), rng.integers(dims[l])
+            Wp = [w.copy() for w in Ws]
+            Wm = [w.copy() for w in Ws]
+            Wp[l][o, i] += h
+            Wm[l][o, i] -= h
+            fd = (loss(Wp, bs) - loss(Wm, bs)) / (2 * h)
+            assert abs(fd - gWs[l][o, i]) < 1e-6 + 1e-5 * abs(fd)
+            checked += 1
+        for o in rng.integers(dims[l + 1], size=6):
+            bp = [v.copy() for v in bs]
+            bm = [v.copy() for v in bs]
+            bp[l][o] += h
+            bm[l][o] -= h
+            fd = (loss(Ws, bp) - loss(Ws, bm)) / (2 * h)
+            assert abs(fd - gbs[l][o]) < 1e-6 + 1e-5 * abs(fd)
+    # loss gradient w.r.t. the outputs
+    for s in range(B):
+        for k in (0, 7, 35, 36):
+            op, om = out.copy(), out.copy()
+            op[s, k] += h
+            om[s, k] -= h
+            fd = (oracle.mlp_loss(op, tr, tf, delta)[0] - oracle.mlp_loss(om, tr, tf, delta)[0]) / (2 * h)
+            assert abs(fd - gout[s, k]) < 1e-7 + 1e-5 * abs(fd)
+    assert checked == 48 and np.isfinite(val)
+
+
+def test_mlp_forward_matches_matrix_products(oracle):
+    """The forward pass equals relu(W x + b) layer by layer (numpy products)."""
+    rng = np.random.default_rng(9)
+    dims = [3, 16, 16, 5]
+    Ws = [rng.normal(0, 1, (dims[l + 1], dims[l])) for l in range(3)]
+    bs = [rng.normal(0, 1, dims[l + 1]) for l in range(3)]
+    x = rng.normal(0, 1, (7, 3))
+    h = x
+    for l in range(3):
+        h = h @ Ws[l].T + bs[l]
+        if l < 2:
+            h = np.maximum(h, 0)
+    assert np.allclose(oracle.mlp_forward(dims, Ws, bs, x), h, atol=1e-12)
