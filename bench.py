@@ -1,0 +1,163 @@
+"""Benchmark: candidate pairs evaluated per second on one MI355X.
+
+Workload: the nine Table 1 colours, r = 0.01 .. 100 in steps of 0.01 (10,000
+radii) x theta = 0 .. 359.9 deg in steps of 0.1 deg (3,600 angles), rule
+V_th = 50, R_novib = 0.5, any pattern: 36 M candidate pairs per colour,
+324 M per step.  A step is one cv_pair_search call: per-colour prologue
+(RGB -> L*a*b*), the fused generate -> convert -> predicate -> compact kernel,
+and the per-colour summaries; inputs are resident in HBM before timing starts.
+
+Prints one JSON line (see the README of the measurement contract in the
+design notes).  `--gpus` above 1 is refused: this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and unit counts used by the roofline.
+CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
+VALU_FMA_PEAK = CUS * SIMDS_PER_CU * LANES_PER_SIMD * 2 * CLOCK_HZ  # 78.6e12 flop/s
+HBM_PEAK = 8e12
+
+# Algorithmic floating-point work per candidate pair (FMA = 2 flops,
+# transcendental = 1; compares, selects, conversions and rounding not counted):
+#   displacement (i+1)*dr/500*sin, (i+1)*dr/200*cos ........ 4 mul      =  4
+#   f(X), f(Z) of both colours ............................. 4 add      =  4
+#   inverse companding, cube branch x4 ..................... 8 mul      =  8
+#   XYZ -> linear RGB, Y column hoisted, 2 colours x 3 ..... 12 fma     = 24
+#   sRGB encode x6: log2, mul, exp2, fma ................... 6 x 5      = 30
+#   channel differences .................................... 3 sub      =  3
+FLOPS_PER_PAIR = 73
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(target_s: float):
+    """The FP64 oracle on a bounded sample of the same workload (the first
+    rows of radii of all nine colours), all host threads."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    g = W.GRID_NINE
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cols = W.PAPER_COLOUR_ARRAY
+    # calibrate on a small slice, then size the sample for ~target_s seconds
+    rows = 4
+    t0 = time.perf_counter()
+    oracle.reduce(cols, (g.dr, rows, g.dtheta_deg, g.ntheta), W.DEFAULT_RULE, nthreads=threads)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    rate = len(cols) * rows * g.ntheta / dt
+    rows = int(min(g.nr, max(8, target_s * rate / (len(cols) * g.ntheta))))
+    t0 = time.perf_counter()
+    oracle.reduce(cols, (g.dr, rows, g.dtheta_deg, g.ntheta), W.DEFAULT_RULE, nthreads=threads)
+    dt = time.perf_counter() - t0
+    pairs = len(cols) * rows * g.ntheta
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"nine colours x first {rows} of {g.nr} radii x {g.ntheta} angles "
+                      f"({pairs} pairs, {dt:.1f} s)",
+            "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures a single GPU; run with --gpus 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2507_22901_amd as cv
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    g = W.GRID_NINE
+    grid = cv.Grid(*g.astuple())
+    rule = cv.Rule(*W.DEFAULT_RULE)
+    cols = torch.from_numpy(W.PAPER_COLOUR_ARRAY.copy()).cuda()
+    ctx = cv.context(0)
+    pairs_per_step = len(W.PAPER_COLOUR_ARRAY) * g.per_colour
+
+    # size the survivor buffer once (outside the timed region)
+    first = cv.pair_search(cols, grid, rule, ctx=ctx)
+    out = torch.empty((first.total + 1024, 16), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        cv.pair_search(cols, grid, rule, out=out, ctx=ctx)
+    ctx.set_timing(True)
+    ctx.kernel_time(reset=True)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    start.record()
+    total = 0
+    for _ in range(args.steps):
+        total = cv.pair_search(cols, grid, rule, out=out, ctx=ctx).total
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms = start.elapsed_time(stop)
+    k_ms, k_n = ctx.kernel_time(reset=True)
+    ctx.set_timing(False)
+    ms_per_step = ms / args.steps
+    value = pairs_per_step / (ms_per_step * 1e-3)
+    k_avg = k_ms / max(k_n, 1)
+    achieved = FLOPS_PER_PAIR * pairs_per_step / (k_avg * 1e-3)
+
+    res = {
+        "metric": "candidate pairs evaluated/s + target colors resolved/s (exact vs surrogate)",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "nine Table 1 colours; r = 0.01..100 step 0.01 (10,000) x theta = "
+                        "0..359.9 deg step 0.1 (3,600); rule V_th=50, R_novib=0.5, any pattern",
+            "colours": int(len(W.PAPER_COLOUR_ARRAY)),
+            "pairs_per_step": pairs_per_step,
+            "survivors_per_step": int(total),
+        },
+        "colours_per_s_exact": len(W.PAPER_COLOUR_ARRAY) / (ms_per_step * 1e-3),
+        "wall_s": wall,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_pair_search",
+            "achieved": achieved / 1e12,
+            "peak": VALU_FMA_PEAK / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / VALU_FMA_PEAK,
+            "traffic": None,
+            "kernel_ms": k_avg,
+            "flops_per_pair": FLOPS_PER_PAIR,
+            "survivor_write_GBps": 16.0 * total / (k_avg * 1e-3) / 1e9,
+        },
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * cvib — colour-vibration pair search on AMD Instinct MI355X (gfx950).
+ *
+ * C-ABI of libcvib.so.  The operations follow Hattori & Hiraki, "Accelerated
+ * and Optimized Search of Imperceptible Color Vibration for Embedding
+ * Information into LCD images" (SIGGRAPH Asia 2022 Posters):
+ *   - Section 2: the target colour is split into L*, a*, b*; displacement arrays
+ *     D_a[i][j] = r_i sin(theta_j) and D_b[i][j] = r_i cos(theta_j) are added to
+ *     a* and b* for one colour of the pair and subtracted for the other, L* is
+ *     kept; both colours are turned back into RGB and the per-channel RGB
+ *     difference decides whether the pair carries information (Fig. 1b).
+ *   - Section 3: a channel bit is high (1) when its change exceeds V_th and low
+ *     (0) when it is below V_th * R_novib; Table 1 lists the colours, the seven
+ *     information patterns and the V_th / R_novib values.
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns an int status (CV_OK = 0 or a negative CV_E* code).
+ *     No C++ exception crosses this boundary.  cv_last_error() returns a
+ *     message for the calling thread's most recent failure.
+ *   - Array pointers are DEVICE pointers owned by the caller unless the name
+ *     ends in _host.  The library allocates device memory only inside a
+ *     cv_context (workspace, tables), never in the caller's arrays.
+ *   - Work is enqueued on the given stream (a hipStream_t passed as void*;
+ *     NULL = the null stream) and is asynchronous, except where a *_host
+ *     output forces a synchronisation (stated per call).
+ *   - Calls on one context must not overlap in time (the workspace is
+ *     shared); use one context per host thread / stream for concurrency.
+ *   - Results are bitwise deterministic for a given input.
+ *
+ * Colour space (the paper names only "L*a*b*"): CIE 1976 L*a*b* with the D65
+ * white and IEC 61966-2-1 sRGB primaries and transfer function.  A pair is in
+ * gamut when every linear channel of both colours lies in [0, 1]; 8-bit values
+ * use round-half-to-even; the channel change is |V+ - V-|; "exceeds" and
+ * "below" are strict; pattern p = 4*bit_R + 2*bit_G + bit_B and p = 0 is never
+ * a survivor.
+ */
+#ifndef CVIB_H
+#define CVIB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define CV_OK 0
+#define CV_EINVAL (-1)    /* bad argument (null pointer, bad grid or rule)  */
+#define CV_ECAPACITY (-2) /* output too small; required size reported      */
+#define CV_EHIP (-3)      /* a HIP runtime call failed                     */
+#define CV_ENOMEM (-4)    /* device allocation failed                      */
+#define CV_ESTATE (-5)    /* internal consistency check failed on device   */
+
+/* ---- cv_lab_convert directions ---------------------------------------- */
+#define CV_RGB8_TO_LAB 0  /* uint8 [n][3] sRGB -> float [n][3] L*, a*, b*   */
+#define CV_LAB_TO_RGBF 1  /* float [n][3] L*a*b* -> float [n][4]:           */
+                          /*   v_R, v_G, v_B = 255 * encode(linear), not     */
+                          /*   rounded; [3] = 1.0 if in gamut else 0.0       */
+
+/* ---- cv_pair_search flags --------------------------------------------- */
+#define CV_EMIT_ALL 0x1u  /* testing: emit every candidate; cv_pair.flags   */
+                          /* then tells gamut / validity                     */
+
+/* ---- rule flags -------------------------------------------------------- */
+#define CV_RULE_CLIP 0x1u /* alternative gamut reading: clamp each encoded  */
+                          /* value to [0, 255] instead of rejecting the pair */
+
+/*
+ * Search grid.  r_i = (i + 1) * dr for 0 <= i < nr; theta_j = j * dtheta_deg
+ * degrees for 0 <= j < ntheta, measured from +b* towards +a* (D_a = r sin,
+ * D_b = r cos, Section 2).  Requirements: dr > 0; 1 <= nr, ntheta <= 65535;
+ * nr * ntheta < 2^31; 360 / dtheta_deg is an even integer N <= 65536.
+ */
+typedef struct {
+    double dr;
+    int32_t nr;
+    int32_t _pad0;
+    double dtheta_deg;
+    int32_t ntheta;
+    int32_t _pad1;
+} cv_grid;
+
+/*
+ * Predicate (Section 3, Table 1).  d_k = |V+_k - V-_k| for k in R, G, B.
+ * high_k = d_k > v_th; low_k = d_k < v_th * r_novib.  A candidate survives when
+ * both colours are in gamut, every channel is high or low, p != 0 and bit
+ * (p - 1) of pattern_mask is set (0x7F accepts any pattern).
+ * Requirements: 0 < v_th <= 255; 0 < r_novib < 1; pattern_mask & 0x7F != 0.
+ */
+typedef struct {
+    int32_t v_th;
+    int32_t _pad0;
+    double r_novib;
+    uint32_t pattern_mask;
+    uint32_t flags; /* CV_RULE_* */
+} cv_rule;
+
+/* One surviving pair, 16 bytes, written in (colour, i, j) order. */
+typedef struct {
+    uint32_t colour;   /* index into the caller's colour array */
+    uint16_t i, j;     /* radius and angle index                */
+    uint8_t plus[3];   /* 8-bit RGB of (L, a + D_a, b + D_b)    */
+    uint8_t minus[3];  /* 8-bit RGB of (L, a - D_a, b - D_b)    */
+    uint8_t pattern;   /* p in 1..7 (0 in CV_EMIT_ALL rows that encode none) */
+    uint8_t flags;     /* bit0 + in gamut, bit1 - in gamut, bit2 survivor   */
+} cv_pair;
+
+/*
+ * Per-colour summary, 48 bytes.  best_* is the maximum-amplitude survivor:
+ * largest radius index i, ties broken by the smallest j (best_i = 0xFFFF and
+ * the rest zero when there is no survivor).
+ */
+typedef struct {
+    uint32_t count;          /* survivors                                   */
+    uint32_t n_gamut;        /* candidates with both colours in gamut       */
+    uint16_t best_i, best_j;
+    uint8_t best_plus[3], best_minus[3], best_p, _pad;
+    uint32_t per_pattern[7]; /* survivors with pattern p at index p - 1     */
+} cv_color_summary;
+
+/*
+ * Angle-bin table row, 40 bytes: the valid count and, for each of 36 bins of
+ * 10 degrees (bin = floor(theta_j / 10 deg)), the largest radius index i + 1
+ * that has a survivor in that bin (0 = none).  Requires nr <= 255.
+ */
+typedef struct {
+    uint32_t count;
+    uint8_t bin_ridx[36];
+} cv_table_row;
+
+typedef struct cv_context cv_context;
+
+/* Create a context on HIP device `device`.  *out receives the handle.
+ * Errors: CV_EINVAL (out NULL / bad device), CV_EHIP. */
+int cv_context_create(int device, cv_context** out);
+
+/* Destroy a context and free its device memory (synchronises the device).
+ * NULL is accepted and ignored. */
+int cv_context_destroy(cv_context* ctx);
+
+/* Message of the calling thread's most recent failed call ("" if none).
+ * The pointer stays valid until the thread's next cvib call. */
+const char* cv_last_error(void);
+
+/*
+ * Colour conversion (Section 2 and Fig. 2: the target colour is split into its
+ * L*, a*, b* components; the inverse turns a displaced candidate back into
+ * RGB).  `in` and `out` are device arrays of n items in the layouts of
+ * CV_RGB8_TO_LAB / CV_LAB_TO_RGBF above.  n == 0 is a no-op.
+ * Errors: CV_EINVAL (null pointer with n > 0, n < 0, unknown dir), CV_EHIP.
+ */
+int cv_lab_convert(cv_context* ctx, const void* in, void* out, int64_t n, int dir,
+                   void* stream);
+
+/*
+ * Full search with stream compaction (Sections 1-2: the candidate pairs are
+ * generated as arrays and the ones meeting both conditions are picked out).
+ * rgb: uint8 [n][3] device array of target colours.  Survivors are written to
+ * out[0 .. total) in (colour, i, j) order; offsets (int64 [n + 1], nullable)
+ * receives per-colour CSR offsets; summ (cv_color_summary [n], nullable)
+ * receives per-colour summaries.  *total_host receives the survivor total
+ * (this synchronises the stream).  If total > capacity the call returns
+ * CV_ECAPACITY, *total_host still holds the required total, out holds the
+ * first `capacity` survivors, and offsets / summ are complete (two-call idiom).
+ * Errors: CV_EINVAL, CV_ECAPACITY, CV_EHIP, CV_ENOMEM, CV_ESTATE.
+ */
+int cv_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,
+                   const cv_rule* rule, cv_pair* out, int64_t capacity, int64_t* offsets,
+                   cv_color_summary* summ, int64_t* total_host, uint32_t flags, void* stream);
+
+/*
+ * Search without materialising survivors: per-colour summaries and, if table
+ * is non-NULL, the angle-bin table rows.  Fully asynchronous.
+ * rgb: uint8 [n][3] device array.  summ: cv_color_summary [n] (nullable when
+ * table is given).  table: cv_table_row [n] (nullable; requires nr <= 255).
+ * Errors: CV_EINVAL, CV_EHIP, CV_ENOMEM.
+ */
+int cv_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,
+                   const cv_rule* rule, cv_color_summary* summ, cv_table_row* table,
+                   void* stream);
+
+/*
+ * Kernel timing for measurement.  When enabled, the library brackets the
+ * dominant kernel of cv_pair_search / cv_pair_reduce (the fused search or the
+ * reduce-only search) with HIP events on the caller's stream and accumulates
+ * their elapsed time.  cv_pair_reduce then synchronises its stream.
+ * cv_context_kernel_time returns the accumulated milliseconds and launch
+ * count (host pointers) and clears them when reset != 0.
+ * Errors: CV_EINVAL (null ctx / outputs), CV_EHIP.
+ */
+int cv_context_set_timing(cv_context* ctx, int on);
+int cv_context_kernel_time(cv_context* ctx, double* ms_host, int64_t* launches_host, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CVIB_H */

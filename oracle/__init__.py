@@ -59,10 +59,11 @@ REC_DTYPE = np.dtype([("colour", "<u4"), ("i", "<u2"), ("j", "<u2"), ("plus", "u
 assert REC_DTYPE.itemsize == 16
 
 SUMMARY_DTYPE = np.dtype([
-    ("count", "<u4"), ("n_gamut", "<u4"), ("n_boundary", "<u4"), ("best_i", "<u2"),
+    ("count", "<u4"), ("n_gamut", "<u4"), ("n_boundary", "<u4"), ("n_ambiguous", "<u4"),
+    ("best_i", "<u2"),
     ("best_j", "<u2"), ("best_plus", "u1", 3), ("best_minus", "u1", 3), ("best_p", "u1"),
     ("_pad", "u1"), ("per_pattern", "<u4", 7)])
-assert SUMMARY_DTYPE.itemsize == 52
+assert SUMMARY_DTYPE.itemsize == 56
 
 _lib = None
 
@@ -88,7 +89,7 @@ def lib():
         L.orc_eval_list.argtypes = [P, P, C.c_int64, C.POINTER(Grid), C.POINTER(Rule), P,
                                     C.c_int32]
         L.orc_search.argtypes = [P, C.c_int64, C.POINTER(Grid), C.POINTER(Rule), P, C.c_int64,
-                                 P, P]
+                                 P, P, C.c_int32]
         L.orc_search.restype = C.c_int64
         L.orc_reduce.argtypes = [P, C.c_int64, C.POINTER(Grid), C.POINTER(Rule), P, P, P,
                                  C.c_int32]
@@ -197,17 +198,19 @@ def eval_list(colors, idx, g, r=None, nthreads: int = 0) -> np.ndarray:
     return out
 
 
-def search(colors, g, r):
-    """(records [total] REC_DTYPE, offsets [n+1], n_boundary)."""
+def search(colors, g, r, nthreads: int = 0):
+    """(records [total] REC_DTYPE, offsets [n+1], n_boundary).  flags bit0 of a
+    record marks a boundary candidate."""
     rgb = _rgb(colors)
     gg, ru = _as_grid(g), _as_rule(r)
     n = rgb.shape[0]
     offs = np.zeros(n + 1, dtype=np.int64)
     nb = np.zeros(1, dtype=np.int64)
-    total = lib().orc_search(_ptr(rgb), n, C.byref(gg), C.byref(ru), None, 0, _ptr(offs), _ptr(nb))
+    total = lib().orc_search(_ptr(rgb), n, C.byref(gg), C.byref(ru), None, 0, _ptr(offs),
+                             _ptr(nb), int(nthreads))
     out = np.zeros(max(total, 1), dtype=REC_DTYPE)
     total2 = lib().orc_search(_ptr(rgb), n, C.byref(gg), C.byref(ru), _ptr(out), total,
-                              _ptr(offs), _ptr(nb))
+                              _ptr(offs), _ptr(nb), int(nthreads))
     assert total2 == total
     return out[:total], offs, int(nb[0])
 

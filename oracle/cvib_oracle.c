@@ -80,7 +80,8 @@ typedef struct {
     uint8_t gamut;      /* bit0: + in gamut, bit1: - in gamut                 */
     uint8_t pattern;    /* 4*hiR + 2*hiG + hiB when every channel is hi or lo */
     uint8_t valid;      /* survivor under the rule                            */
-    uint8_t boundary;   /* decision lies within the 1e-3 band                 */
+    uint8_t boundary;   /* bit0: some channel within the 1e-3 band; bit1: a    */
+                        /* value inside the band changes the decision         */
     uint8_t _pad[4];
 } orc_cand;
 
@@ -97,7 +98,8 @@ typedef struct {
 typedef struct {
     uint32_t count;          /* survivors                                    */
     uint32_t n_gamut;        /* candidates with both colours in gamut        */
-    uint32_t n_boundary;     /* boundary candidates                          */
+    uint32_t n_boundary;     /* boundary candidates (bit0)                   */
+    uint32_t n_ambiguous;    /* candidates whose decision the band can flip  */
     uint16_t best_i, best_j; /* max-amplitude survivor (0xFFFF if none)      */
     uint8_t best_plus[3], best_minus[3], best_p, _pad;
     uint32_t per_pattern[7]; /* survivors with pattern p at index p-1        */
@@ -253,6 +255,58 @@ static void target_init(orc_target* t, const uint8_t rgb[3]) {
     t->L = lab[0]; t->a = lab[1]; t->b = lab[2];
 }
 
+/* Decision of a candidate from its gamut flags and 8-bit values under rule
+ * ru: returns 0 when not a survivor, else 8 + pattern. */
+static int decide_codes(const orc_rule* ru, int clip, int gp, int gm, const int Vp[3],
+                        const int Vm[3]) {
+    if (!(clip || (gp && gm))) return 0;
+    double lo = (double)ru->v_th * ru->r_novib;
+    int p = 0, ok = 1;
+    for (int k = 0; k < 3; ++k) {
+        int d = abs(Vp[k] - Vm[k]);
+        int hi = d > ru->v_th;
+        int low = (double)d < lo;
+        if (!(hi || low)) ok = 0;
+        p = 2 * p + hi;
+    }
+    return (ok && p != 0 && ((ru->mask >> (p - 1)) & 1u)) ? 8 + p : 0;
+}
+
+/* Whether moving any channel by less than the band (rounding it to the other
+ * side of a nearby tie, or across a nearby gamut edge) changes the decision.
+ * Every combination of such moves is tried. */
+static int decision_ambiguous(const orc_rule* ru, int clip, const double vp[3], const double vm[3],
+                              int gp, int gm) {
+    const double v[6] = {vp[0], vp[1], vp[2], vm[0], vm[1], vm[2]};
+    int nom[6], alt[6];
+    int edge_p = 0, edge_m = 0, out_p = 0, out_m = 0;
+    for (int k = 0; k < 6; ++k) {
+        double a = v[k];
+        if (clip) a = a < 0.0 ? 0.0 : (a > 255.0 ? 255.0 : a);
+        nom[k] = (int)nearbyint(a);
+        alt[k] = nom[k];
+        if (near_tie(a)) {
+            const int f = (int)floor(a);
+            alt[k] = (nom[k] == f) ? f + 1 : f;
+        }
+        if (!clip) {
+            const int e = near_edge(v[k]), o = clearly_out(v[k]);
+            if (k < 3) { edge_p |= e; out_p |= o; } else { edge_m |= e; out_m |= o; }
+        }
+    }
+    const int gp_alt = (edge_p && !out_p) ? !gp : gp;
+    const int gm_alt = (edge_m && !out_m) ? !gm : gm;
+    const int nominal = decide_codes(ru, clip, gp, gm, nom, nom + 3);
+    for (int mask = 1; mask < 256; ++mask) {
+        int code[6];
+        for (int k = 0; k < 6; ++k) code[k] = ((mask >> k) & 1) ? alt[k] : nom[k];
+        const int g1 = ((mask >> 6) & 1) ? gp_alt : gp;
+        const int g2 = ((mask >> 7) & 1) ? gm_alt : gm;
+        if (decide_codes(ru, clip, g1, g2, code, code + 3) != nominal) return 1;
+    }
+    return 0;
+}
+
 /* Evaluate candidate (i, j) of target t under rule ru (ru may be NULL: then
  * only the pair itself and its gamut/boundary state are filled in). */
 static void eval_cand(const orc_target* t, const orc_grid* g, const orc_rule* ru,
@@ -293,7 +347,9 @@ static void eval_cand(const orc_target* t, const orc_grid* g, const orc_rule* ru
     c->boundary = (uint8_t)(clip ? tie : (!any_out && (edge || tie)));
     c->pattern = 0;
     c->valid = 0;
-    if (!ru || !(clip || (gp && gm))) return;
+    if (!ru) return;
+    if (c->boundary && decision_ambiguous(ru, clip, c->vp, c->vm, gp, gm)) c->boundary |= 2;
+    if (!(clip || (gp && gm))) return;
     double lo = (double)ru->v_th * ru->r_novib;
     int p = 0, ok = 1;
     for (int k = 0; k < 3; ++k) {
@@ -350,36 +406,71 @@ void orc_eval_list(const uint8_t* rgb, const int64_t* idx, int64_t m, const orc_
 /* Survivors of all colours in (colour, i, j) order.  Writes up to cap records;
  * returns the total number of survivors.  offsets[n+1] (nullable) receives the
  * per-colour CSR offsets; *nboundary (nullable) the boundary-candidate count
- * over all candidates (survivor or not). */
+ * over all candidates (survivor or not).  Rows (colour, i) are independent:
+ * the first pass counts each row's survivors, a prefix sum places the rows,
+ * the second pass writes them (both passes parallel over rows). */
 int64_t orc_search(const uint8_t* rgb, int64_t n, const orc_grid* g, const orc_rule* ru,
-                   orc_rec* out, int64_t cap, int64_t* offsets, int64_t* nboundary) {
-    int64_t total = 0, nb = 0;
-    for (int64_t col = 0; col < n; ++col) {
+                   orc_rec* out, int64_t cap, int64_t* offsets, int64_t* nboundary,
+                   int32_t nthreads) {
+    const int64_t rows = n * g->nr;
+    int64_t* cnt = (int64_t*)calloc((size_t)rows + 1, sizeof(int64_t));
+    int64_t* bnd = (int64_t*)calloc((size_t)rows + 1, sizeof(int64_t));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (int64_t row = 0; row < rows; ++row) {
         orc_target t;
-        target_init(&t, rgb + 3 * col);
-        if (offsets) offsets[col] = total;
-        for (int32_t i = 0; i < g->nr; ++i) {
-            for (int32_t j = 0; j < g->ntheta; ++j) {
+        target_init(&t, rgb + 3 * (row / g->nr));
+        const int32_t i = (int32_t)(row % g->nr);
+        for (int32_t j = 0; j < g->ntheta; ++j) {
+            orc_cand c;
+            eval_cand(&t, g, ru, i, j, 0, &c);
+            bnd[row] += c.boundary & 1;
+            cnt[row] += c.valid;
+        }
+    }
+    int64_t total = 0, nb = 0;
+    for (int64_t row = 0; row < rows; ++row) {
+        int64_t k = cnt[row];
+        cnt[row] = total; /* now the row's start */
+        total += k;
+        nb += bnd[row];
+    }
+    cnt[rows] = total;
+    if (offsets) {
+        for (int64_t col = 0; col < n; ++col) offsets[col] = cnt[col * g->nr];
+        offsets[n] = total;
+    }
+    if (out && cap > 0) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+        for (int64_t row = 0; row < rows; ++row) {
+            if (cnt[row] >= cap) continue;
+            orc_target t;
+            const int64_t col = row / g->nr;
+            target_init(&t, rgb + 3 * col);
+            const int32_t i = (int32_t)(row % g->nr);
+            int64_t pos = cnt[row];
+            for (int32_t j = 0; j < g->ntheta && pos < cap; ++j) {
                 orc_cand c;
                 eval_cand(&t, g, ru, i, j, 0, &c);
-                nb += c.boundary;
                 if (!c.valid) continue;
-                if (total < cap) {
-                    orc_rec* o = out + total;
-                    o->colour = (uint32_t)col;
-                    o->i = (uint16_t)i;
-                    o->j = (uint16_t)j;
-                    memcpy(o->plus, c.Vp, 3);
-                    memcpy(o->minus, c.Vm, 3);
-                    o->pattern = c.pattern;
-                    o->flags = c.boundary;
-                }
-                ++total;
+                orc_rec* o = out + pos++;
+                o->colour = (uint32_t)col;
+                o->i = (uint16_t)i;
+                o->j = (uint16_t)j;
+                memcpy(o->plus, c.Vp, 3);
+                memcpy(o->minus, c.Vm, 3);
+                o->pattern = c.pattern;
+                o->flags = c.boundary;
             }
         }
     }
-    if (offsets) offsets[n] = total;
     if (nboundary) *nboundary = nb;
+    free(cnt);
+    free(bnd);
     return total;
 }
 
@@ -406,7 +497,8 @@ void orc_reduce(const uint8_t* rgb, int64_t n, const orc_grid* g, const orc_rule
             for (int32_t j = 0; j < g->ntheta; ++j) {
                 orc_cand c;
                 eval_cand(&t, g, ru, i, j, 0, &c);
-                s.n_boundary += c.boundary;
+                s.n_boundary += c.boundary & 1;
+                s.n_ambiguous += (c.boundary >> 1) & 1;
                 if (c.gamut == 3) s.n_gamut++;
                 if (!c.valid) continue;
                 s.count++;

@@ -1,0 +1,264 @@
+"""cvib: colour-vibration pair search on AMD Instinct MI355X (gfx950).
+
+Python binding of ``libcvib.so`` (C-ABI declared in ``include/cvib.h``).  This
+module only marshals arguments: every step of the search runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the current HIP
+stream.  If the compiled library is missing the import of any entry point
+raises; there is no CPU fallback.
+
+Method: Hattori & Hiraki, "Accelerated and Optimized Search of Imperceptible
+Color Vibration for Embedding Information into LCD images" (SIGGRAPH Asia 2022
+Posters), Section 2 (pair construction in L*a*b* with L* fixed, displacement
+arrays D_a = r sin(theta), D_b = r cos(theta)) and Section 3 / Table 1
+(V_th / R_novib predicate).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcvib.so")
+
+CV_OK, CV_EINVAL, CV_ECAPACITY, CV_EHIP, CV_ENOMEM, CV_ESTATE = 0, -1, -2, -3, -4, -5
+CV_RGB8_TO_LAB, CV_LAB_TO_RGBF = 0, 1
+CV_EMIT_ALL = 0x1
+CV_RULE_CLIP = 0x1
+
+_ERRNAMES = {CV_EINVAL: "CV_EINVAL", CV_ECAPACITY: "CV_ECAPACITY", CV_EHIP: "CV_EHIP",
+             CV_ENOMEM: "CV_ENOMEM", CV_ESTATE: "CV_ESTATE"}
+
+
+class CvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class cv_grid(C.Structure):
+    _fields_ = [("dr", C.c_double), ("nr", C.c_int32), ("_pad0", C.c_int32),
+                ("dtheta_deg", C.c_double), ("ntheta", C.c_int32), ("_pad1", C.c_int32)]
+
+
+class cv_rule(C.Structure):
+    _fields_ = [("v_th", C.c_int32), ("_pad0", C.c_int32), ("r_novib", C.c_double),
+                ("pattern_mask", C.c_uint32), ("flags", C.c_uint32)]
+
+
+PAIR_DTYPE = np.dtype([("colour", "<u4"), ("i", "<u2"), ("j", "<u2"), ("plus", "u1", 3),
+                       ("minus", "u1", 3), ("pattern", "u1"), ("flags", "u1")])
+SUMMARY_DTYPE = np.dtype([("count", "<u4"), ("n_gamut", "<u4"), ("best_i", "<u2"),
+                          ("best_j", "<u2"), ("best_plus", "u1", 3), ("best_minus", "u1", 3),
+                          ("best_p", "u1"), ("_pad", "u1"), ("per_pattern", "<u4", 7)])
+TABLE_DTYPE = np.dtype([("count", "<u4"), ("bin_ridx", "u1", 36)])
+assert PAIR_DTYPE.itemsize == 16 and SUMMARY_DTYPE.itemsize == 48 and TABLE_DTYPE.itemsize == 40
+
+# Exported symbols (every one is declared in include/cvib.h).
+EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_convert",
+           "cv_pair_search", "cv_pair_reduce", "cv_context_set_timing", "cv_context_kernel_time")
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libcvib.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, I64 = C.c_void_p, C.c_int64
+        L.cv_context_create.argtypes = [C.c_int, C.POINTER(C.c_void_p)]
+        L.cv_context_destroy.argtypes = [P]
+        L.cv_last_error.restype = C.c_char_p
+        L.cv_lab_convert.argtypes = [P, P, P, I64, C.c_int, P]
+        L.cv_pair_search.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, I64,
+                                     P, P, C.POINTER(I64), C.c_uint32, P]
+        L.cv_pair_reduce.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P]
+        L.cv_context_set_timing.argtypes = [P, C.c_int]
+        L.cv_context_kernel_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(I64), C.c_int]
+        for name in EXPORTS:
+            if name != "cv_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc != CV_OK:
+        raise CvError(rc, lib().cv_last_error().decode())
+    return rc
+
+
+@dataclass(frozen=True)
+class Grid:
+    """r_i = (i+1) dr, i < nr; theta_j = j dtheta_deg degrees, j < ntheta."""
+    dr: float
+    nr: int
+    dtheta_deg: float
+    ntheta: int
+
+    def c(self) -> cv_grid:
+        return cv_grid(dr=self.dr, nr=self.nr, dtheta_deg=self.dtheta_deg, ntheta=self.ntheta)
+
+    @property
+    def per_colour(self) -> int:
+        return self.nr * self.ntheta
+
+
+@dataclass(frozen=True)
+class Rule:
+    """Section 3: high if change > v_th, low if change < v_th * r_novib."""
+    v_th: int = 50
+    r_novib: float = 0.5
+    pattern_mask: int = 0x7F
+    flags: int = 0
+
+    def c(self) -> cv_rule:
+        return cv_rule(v_th=self.v_th, r_novib=self.r_novib, pattern_mask=self.pattern_mask,
+                       flags=self.flags)
+
+
+class Context:
+    """Owns a cv_context (device workspace) on one GPU."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib().cv_context_create(int(device), C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def set_timing(self, on: bool = True):
+        """Bracket the dominant search kernel with HIP events on the call's stream."""
+        _check(lib().cv_context_set_timing(self.handle, int(bool(on))))
+
+    def kernel_time(self, reset: bool = False):
+        """(accumulated kernel milliseconds, number of timed launches)."""
+        ms, n = C.c_double(0.0), C.c_int64(0)
+        _check(lib().cv_context_kernel_time(self.handle, C.byref(ms), C.byref(n), int(reset)))
+        return ms.value, n.value
+
+    def close(self):
+        if self.handle:
+            lib().cv_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device: int | None = None) -> Context:
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _contexts:
+        _contexts[dev] = Context(dev)
+    return _contexts[dev]
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t: torch.Tensor | None):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _colours(colors: torch.Tensor) -> torch.Tensor:
+    if colors.dtype != torch.uint8 or colors.dim() != 2 or colors.shape[1] != 3:
+        raise ValueError("colours must be a uint8 tensor of shape [n, 3]")
+    if not colors.is_cuda:
+        raise ValueError("colours must be on the GPU")
+    return colors.contiguous()
+
+
+def rgb8_to_lab(rgb: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:
+    """uint8 [n,3] sRGB -> float32 [n,3] CIE L*a*b* (D65)."""
+    rgb = _colours(rgb)
+    ctx = ctx or context(rgb.device.index)
+    out = torch.empty((rgb.shape[0], 3), dtype=torch.float32, device=rgb.device)
+    _check(lib().cv_lab_convert(ctx.handle, _dptr(rgb), _dptr(out), rgb.shape[0], CV_RGB8_TO_LAB,
+                                _stream()))
+    return out
+
+
+def lab_to_rgbf(lab: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:
+    """float32 [n,3] L*a*b* -> float32 [n,4]: unrounded 0..255 code values + gamut flag."""
+    if lab.dtype != torch.float32 or lab.dim() != 2 or lab.shape[1] != 3 or not lab.is_cuda:
+        raise ValueError("lab must be a float32 CUDA tensor of shape [n, 3]")
+    lab = lab.contiguous()
+    ctx = ctx or context(lab.device.index)
+    out = torch.empty((lab.shape[0], 4), dtype=torch.float32, device=lab.device)
+    _check(lib().cv_lab_convert(ctx.handle, _dptr(lab), _dptr(out), lab.shape[0], CV_LAB_TO_RGBF,
+                                _stream()))
+    return out
+
+
+@dataclass
+class SearchResult:
+    pairs: torch.Tensor        # uint8 [total, 16] (PAIR_DTYPE records) on the GPU
+    offsets: torch.Tensor      # int64 [n + 1]
+    summaries: torch.Tensor | None  # uint8 [n, 48] (SUMMARY_DTYPE)
+    total: int
+
+
+def pair_search(colors: torch.Tensor, grid: Grid, rule: Rule, capacity: int | None = None,
+                summaries: bool = True, emit_all: bool = False,
+                out: torch.Tensor | None = None, ctx: Context | None = None) -> SearchResult:
+    """Full search with stream compaction; survivors in (colour, i, j) order.
+
+    With capacity None the output grows to fit (one extra search if the first
+    guess is too small)."""
+    colors = _colours(colors)
+    ctx = ctx or context(colors.device.index)
+    n = colors.shape[0]
+    dev = colors.device
+    offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    summ = torch.empty((n, 48), dtype=torch.uint8, device=dev) if summaries else None
+    flags = CV_EMIT_ALL if emit_all else 0
+    if out is None:
+        if capacity is None:
+            full = n * grid.per_colour
+            capacity = full if emit_all else min(full, max(1 << 20, full // 4))
+        out = torch.empty((max(capacity, 1), 16), dtype=torch.uint8, device=dev)
+    cap = out.shape[0] if capacity is None else min(capacity, out.shape[0])
+    total = C.c_int64(0)
+    g, r = grid.c(), rule.c()
+    rc = lib().cv_pair_search(ctx.handle, _dptr(colors), n, C.byref(g), C.byref(r), _dptr(out),
+                              cap, _dptr(offsets), _dptr(summ), C.byref(total), flags, _stream())
+    if rc == CV_ECAPACITY and capacity is None:
+        out = torch.empty((total.value, 16), dtype=torch.uint8, device=dev)
+        rc = lib().cv_pair_search(ctx.handle, _dptr(colors), n, C.byref(g), C.byref(r),
+                                  _dptr(out), out.shape[0], _dptr(offsets), _dptr(summ),
+                                  C.byref(total), flags, _stream())
+    _check(rc)
+    return SearchResult(out[:total.value], offsets, summ, total.value)
+
+
+def pair_reduce(colors: torch.Tensor, grid: Grid, rule: Rule, summaries: bool = True,
+                table: bool = False, ctx: Context | None = None):
+    """Search without survivor lists: (summaries uint8 [n,48] | None, table uint8 [n,40] | None)."""
+    colors = _colours(colors)
+    ctx = ctx or context(colors.device.index)
+    n = colors.shape[0]
+    dev = colors.device
+    summ = torch.empty((n, 48), dtype=torch.uint8, device=dev) if summaries else None
+    tab = torch.empty((n, 40), dtype=torch.uint8, device=dev) if table else None
+    g, r = grid.c(), rule.c()
+    _check(lib().cv_pair_reduce(ctx.handle, _dptr(colors), n, C.byref(g), C.byref(r), _dptr(summ),
+                                _dptr(tab), _stream()))
+    return summ, tab
+
+
+def as_records(t: torch.Tensor, dtype: np.dtype) -> np.ndarray:
+    """Copy a uint8 [k, itemsize] device tensor into a numpy structured array."""
+    a = t.detach().cpu().contiguous().numpy()
+    return a.reshape(-1).view(dtype) if a.size else np.zeros(0, dtype=dtype)

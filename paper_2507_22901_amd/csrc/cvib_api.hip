@@ -1,0 +1,331 @@
+// C-ABI entry points of libcvib: argument validation, error reporting, the
+// context and its workspace, and the colour-space constants.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <exception>
+#include <string>
+
+#include "cvib_internal.h"
+
+namespace cvib {
+
+namespace {
+thread_local std::string g_last_error;
+
+// det / inverse of a 3x3 matrix by the adjugate (FP64).
+double det3(const double m[3][3]) {
+    return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+           m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+           m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+}
+
+void invert3(const double m[3][3], double out[3][3]) {
+    const double d = det3(m);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            // cofactor of element (c, r), transposed into (r, c)
+            const int r0 = (c + 1) % 3, r1 = (c + 2) % 3, c0 = (r + 1) % 3, c1 = (r + 2) % 3;
+            out[r][c] = (m[r0][c0] * m[r1][c1] - m[r0][c1] * m[r1][c0]) / d;
+        }
+}
+
+ColorSpace build_color_space() {
+    // CIE xy of the sRGB primaries and of D65 (IEC 61966-2-1).
+    const double xy[4][2] = {{0.64, 0.33}, {0.30, 0.60}, {0.15, 0.06}, {0.3127, 0.3290}};
+    ColorSpace cs;
+    double P[3][3]; // columns: XYZ of each primary with Y = 1
+    for (int k = 0; k < 3; ++k) {
+        const double x = xy[k][0], y = xy[k][1];
+        P[0][k] = x / y;
+        P[1][k] = 1.0;
+        P[2][k] = (1.0 - x - y) / y;
+    }
+    const double wx = xy[3][0], wy = xy[3][1];
+    cs.W[0] = wx / wy;
+    cs.W[1] = 1.0;
+    cs.W[2] = (1.0 - wx - wy) / wy;
+    // scale each primary so that R = G = B = 1 reproduces the white point
+    double Pinv[3][3];
+    invert3(P, Pinv);
+    double S[3];
+    for (int k = 0; k < 3; ++k) S[k] = Pinv[k][0] * cs.W[0] + Pinv[k][1] * cs.W[1] + Pinv[k][2] * cs.W[2];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) cs.M[r][c] = P[r][c] * S[c];
+    invert3(cs.M, cs.Minv);
+    return cs;
+}
+} // namespace
+
+const ColorSpace& color_space() {
+    static const ColorSpace cs = build_color_space();
+    return cs;
+}
+
+Geom geom_constants() {
+    const ColorSpace& cs = color_space();
+    Geom g;
+    for (int k = 0; k < 3; ++k) {
+        g.A[k] = cs.Minv[k][0] * cs.W[0];
+        g.C[k] = cs.Minv[k][2] * cs.W[2];
+    }
+    return g;
+}
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? CV_ENOMEM : CV_EHIP;
+}
+
+int make_grid(const cv_grid* g, GridDev* out) {
+    if (!g) return fail(CV_EINVAL, "grid is NULL");
+    if (!(g->dr > 0.0) || !isfinite(g->dr)) return fail(CV_EINVAL, "grid.dr must be > 0");
+    if (g->nr < 1 || g->nr > 65535) return fail(CV_EINVAL, "grid.nr must be in [1, 65535]");
+    if (g->ntheta < 1 || g->ntheta > 65535)
+        return fail(CV_EINVAL, "grid.ntheta must be in [1, 65535]");
+    if ((int64_t)g->nr * g->ntheta >= (int64_t)1 << 31)
+        return fail(CV_EINVAL, "grid.nr * grid.ntheta must be < 2^31");
+    if (!(g->dtheta_deg > 0.0) || !isfinite(g->dtheta_deg))
+        return fail(CV_EINVAL, "grid.dtheta_deg must be > 0");
+    const double q = 360.0 / g->dtheta_deg;
+    const double Nr = nearbyint(q);
+    if (fabs(q - Nr) > 1e-9 * Nr || Nr < 2 || Nr > 65536 || fmod(Nr, 2.0) != 0.0)
+        return fail(CV_EINVAL, "360 / grid.dtheta_deg must be an even integer <= 65536");
+    const int32_t N = (int32_t)Nr;
+    if (g->ntheta > N) return fail(CV_EINVAL, "grid.ntheta exceeds one full turn");
+    out->dr = g->dr;
+    out->ra = g->dr / 500.0;
+    out->rb = g->dr / 200.0;
+    out->nr = g->nr;
+    out->ntheta = g->ntheta;
+    out->N = N;
+    if (N % 4 == 0) {
+        out->qoff = N / 4;
+        out->wrap = N;
+        out->tab_len = N;
+    } else {
+        out->qoff = N;
+        out->wrap = 2 * N;
+        out->tab_len = 2 * N;
+    }
+    out->per_colour = (int64_t)g->nr * g->ntheta;
+    return CV_OK;
+}
+
+int make_rule(const cv_rule* r, RuleDev* out) {
+    if (!r) return fail(CV_EINVAL, "rule is NULL");
+    if (r->v_th <= 0 || r->v_th > 255) return fail(CV_EINVAL, "rule.v_th must be in [1, 255]");
+    if (!(r->r_novib > 0.0 && r->r_novib < 1.0))
+        return fail(CV_EINVAL, "rule.r_novib must be in (0, 1)");
+    if ((r->pattern_mask & 0x7Fu) == 0) return fail(CV_EINVAL, "rule.pattern_mask is empty");
+    if (r->flags & ~(uint32_t)CV_RULE_CLIP) return fail(CV_EINVAL, "unknown rule flags");
+    // d < v_th * r_novib  <=>  d <= ceil(v_th * r_novib) - 1 for integer d
+    const double lo = (double)r->v_th * r->r_novib;
+    out->v_th = (float)r->v_th;
+    out->lo_max = (float)(ceil(lo) - 1.0);
+    out->mask = r->pattern_mask & 0x7Fu;
+    out->clip = (r->flags & CV_RULE_CLIP) ? 1u : 0u;
+    return CV_OK;
+}
+
+} // namespace cvib
+
+int cv_context::ensure(cvib::Buffer& b, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    if (b.bytes >= bytes) return CV_OK;
+    if (b.ptr) {
+        CV_HIP(hipFree(b.ptr)); // synchronises: earlier work on the old buffer is done
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 4; // grow with headroom
+    hipError_t e = hipMalloc(&b.ptr, want);
+    if (e != hipSuccess) {
+        b.ptr = nullptr;
+        return cvib::hip_fail(e, "hipMalloc(workspace)");
+    }
+    b.bytes = want;
+    return CV_OK;
+}
+
+int cv_context::time_begin(hipStream_t s) {
+    if (!timing) return CV_OK;
+    CV_HIP(hipEventRecord(ev0, s));
+    return CV_OK;
+}
+
+// Records the end event; with sync, waits for it and accumulates the time
+// (otherwise the caller accumulates after its own synchronisation).
+int cv_context::time_end(hipStream_t s, bool sync) {
+    if (!timing) return CV_OK;
+    CV_HIP(hipEventRecord(ev1, s));
+    if (sync) {
+        CV_HIP(hipEventSynchronize(ev1));
+        float ms = 0.0f;
+        CV_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        kernel_ms += ms;
+        kernel_launches += 1;
+    }
+    return CV_OK;
+}
+
+using cvib::fail;
+
+#define CV_GUARD_BEGIN try {
+#define CV_GUARD_END                                                     \
+    }                                                                    \
+    catch (const std::exception& ex) {                                   \
+        return fail(CV_ESTATE, std::string("internal error: ") + ex.what()); \
+    }                                                                    \
+    catch (...) {                                                        \
+        return fail(CV_ESTATE, "internal error");                        \
+    }
+
+namespace {
+// Make the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+} // namespace
+
+extern "C" {
+
+const char* cv_last_error(void) { return cvib::g_last_error.c_str(); }
+
+int cv_context_create(int device, cv_context** out) {
+    CV_GUARD_BEGIN
+    if (!out) return fail(CV_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    CV_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(CV_EINVAL, "no such device");
+    DeviceGuard dg(device);
+    if (!dg.ok) return fail(CV_EHIP, "hipSetDevice failed");
+    cv_context* c = new cv_context();
+    c->device = device;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete c;
+        return cvib::hip_fail(e, "hipGetDeviceProperties");
+    }
+    c->num_cu = prop.multiProcessorCount;
+    e = hipHostMalloc((void**)&c->host_misc, 64, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete c;
+        return cvib::hip_fail(e, "hipHostMalloc");
+    }
+    *out = c;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_context_destroy(cv_context* ctx) {
+    CV_GUARD_BEGIN
+    if (!ctx) return CV_OK;
+    DeviceGuard dg(ctx->device);
+    (void)hipDeviceSynchronize();
+    cvib::Buffer* bufs[] = {&ctx->colors, &ctx->table, &ctx->status, &ctx->acc, &ctx->misc};
+    for (cvib::Buffer* b : bufs)
+        if (b->ptr) (void)hipFree(b->ptr);
+    if (ctx->host_misc) (void)hipHostFree(ctx->host_misc);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_lab_convert(cv_context* ctx, const void* in, void* out, int64_t n, int dir, void* stream) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(CV_EINVAL, "n < 0");
+    if (dir != CV_RGB8_TO_LAB && dir != CV_LAB_TO_RGBF) return fail(CV_EINVAL, "unknown dir");
+    if (n > 0 && (!in || !out)) return fail(CV_EINVAL, "null array");
+    DeviceGuard dg(ctx->device);
+    return cvib::run_lab_convert(ctx, in, out, n, dir, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
+int cv_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,
+                   const cv_rule* rule, cv_pair* out, int64_t capacity, int64_t* offsets,
+                   cv_color_summary* summ, int64_t* total_host, uint32_t flags, void* stream) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    if (!total_host) return fail(CV_EINVAL, "total_host is NULL");
+    if (n < 0 || n > 0xFFFFFFFFll) return fail(CV_EINVAL, "n out of range");
+    if (capacity < 0) return fail(CV_EINVAL, "capacity < 0");
+    if (capacity > 0 && !out) return fail(CV_EINVAL, "out is NULL with capacity > 0");
+    if (n > 0 && !rgb) return fail(CV_EINVAL, "rgb is NULL");
+    if (flags & ~(uint32_t)CV_EMIT_ALL) return fail(CV_EINVAL, "unknown flags");
+    cvib::GridDev gd;
+    cvib::RuleDev rd;
+    int rc;
+    if ((rc = cvib::make_grid(grid, &gd)) != CV_OK) return rc;
+    if ((rc = cvib::make_rule(rule, &rd)) != CV_OK) return rc;
+    DeviceGuard dg(ctx->device);
+    return cvib::run_pair_search(ctx, rgb, n, gd, rd, out, capacity, offsets, summ, total_host,
+                                 flags, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
+int cv_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,
+                   const cv_rule* rule, cv_color_summary* summ, cv_table_row* table,
+                   void* stream) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    if (n < 0 || n > 0xFFFFFFFFll) return fail(CV_EINVAL, "n out of range");
+    if (n > 0 && !rgb) return fail(CV_EINVAL, "rgb is NULL");
+    if (!summ && !table) return fail(CV_EINVAL, "summ and table are both NULL");
+    cvib::GridDev gd;
+    cvib::RuleDev rd;
+    int rc;
+    if ((rc = cvib::make_grid(grid, &gd)) != CV_OK) return rc;
+    if ((rc = cvib::make_rule(rule, &rd)) != CV_OK) return rc;
+    if (table && gd.nr > 255) return fail(CV_EINVAL, "table rows need grid.nr <= 255");
+    if (table && gd.ntheta > 16384) return fail(CV_EINVAL, "table rows need grid.ntheta <= 16384");
+    DeviceGuard dg(ctx->device);
+    return cvib::run_pair_reduce(ctx, rgb, n, gd, rd, summ, table, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
+int cv_context_set_timing(cv_context* ctx, int on) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    DeviceGuard dg(ctx->device);
+    if (on && !ctx->ev0) {
+        CV_HIP(hipEventCreate(&ctx->ev0));
+        CV_HIP(hipEventCreate(&ctx->ev1));
+    }
+    ctx->timing = on != 0;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_context_kernel_time(cv_context* ctx, double* ms_host, int64_t* launches_host, int reset) {
+    CV_GUARD_BEGIN
+    if (!ctx || !ms_host || !launches_host) return fail(CV_EINVAL, "null argument");
+    *ms_host = ctx->kernel_ms;
+    *launches_host = ctx->kernel_launches;
+    if (reset) {
+        ctx->kernel_ms = 0.0;
+        ctx->kernel_launches = 0;
+    }
+    return CV_OK;
+    CV_GUARD_END
+}
+
+} // extern "C"

@@ -1,0 +1,149 @@
+// Device-side building blocks of the colour-vibration pair search (gfx950).
+//
+// Arithmetic split (chosen for MI355X):
+//   * geometry in FP64 -- the displaced f(X/Xn), f(Z/Zn) of both colours, the
+//     inverse L* companding (cube / linear branch) and the 3x3 XYZ -> linear
+//     RGB product.  The dark end of the sRGB curve magnifies an error in f by
+//     roughly 1.6e4 codes per unit, so FP32's 24-bit mantissa alone would put
+//     ~1e-3-code errors on dark channels; gfx950 issues FP64 FMA/ADD/MUL at the
+//     same per-lane rate as non-packed FP32, so this costs registers, not
+//     issue slots.
+//   * transfer in FP32 -- the sRGB encode (linear segment or
+//     1.055 * l^(1/2.4) - 0.055) on the hardware log2/exp2 units, the x255
+//     scale and round-half-to-even; error <= ~3e-5 codes against FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cvib {
+
+// Per-target constants (Section 2: the target split into L*, a*, b*).  Holding
+// L* fixed fixes f(Y) and Y, so the Y column of the XYZ -> RGB product is a
+// per-colour constant B_k.
+struct alignas(16) ColorConst {
+    double fx0;    // f(X/Xn) of the target = (L+16)/116 + a/500
+    double fz0;    // f(Z/Zn) of the target = (L+16)/116 - b/200
+    double B[3];   // Minv[k][1] * Y of the target
+    float L, a, b; // target L*a*b* (FP32 copy, reporting only)
+    uint32_t _pad;
+};
+static_assert(sizeof(ColorConst) == 64, "ColorConst layout");
+
+// Per-launch constants: the X and Z columns of the XYZ -> linear RGB matrix
+// with the white point folded in.
+struct Geom {
+    double A[3]; // Minv[k][0] * Xn
+    double C[3]; // Minv[k][2] * Zn
+};
+
+constexpr double kDelta = 6.0 / 29.0;
+constexpr double kLinSlope = 3.0 * kDelta * kDelta;            // 3 delta^2
+constexpr double kLinOffset = -3.0 * kDelta * kDelta * 4.0 / 29.0;
+
+// Inverse of the L* companding function f (CIE 1976).
+__device__ __forceinline__ double finv(double u) {
+    double cube = u * u * u;
+    double lin = __builtin_fma(kLinSlope, u, kLinOffset);
+    return u > kDelta ? cube : lin;
+}
+
+// sRGB encode of an FP32 linear value, in 0..255 code units (unrounded).
+// Outside [0,1] the two branches extend the curve monotonically.
+__device__ __forceinline__ float encode255(float l) {
+    float lg = __builtin_amdgcn_logf(l);                 // log2 (v_log_f32)
+    float p = __builtin_amdgcn_exp2f(lg * (1.0f / 2.4f)); // 2^(log2(l)/2.4)
+    float g = __builtin_fmaf(255.0f * 1.055f, p, -255.0f * 0.055f);
+    float s = l * (255.0f * 12.92f);
+    return l <= 0.0031308f ? s : g;
+}
+
+// One colour of a candidate pair: displaced (fx, fz) -> linear RGB (FP64).
+__device__ __forceinline__ void lab_f_to_linear(const Geom& g, const double B[3], double fx,
+                                                double fz, double lin[3]) {
+    double gx = finv(fx);
+    double gz = finv(fz);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lin[k] = __builtin_fma(g.A[k], gx, __builtin_fma(g.C[k], gz, B[k]));
+}
+
+// Outcome of evaluating one candidate (i, j) of one target.
+struct PairEval {
+    float vp[3], vm[3]; // encoded values of the + and - colour, 0..255, unrounded
+    bool gp, gm;        // gamut flags (all linear channels in [0,1])
+};
+
+// Evaluate the pair at displacement (dx, dz) = (r sin / 500, r cos / 200):
+// (L, a +- D_a, b +- D_b) in f-space is (fx0 +- dx, fz0 -+ dz) (Section 2).
+__device__ __forceinline__ void eval_pair(const ColorConst& cc, const Geom& g, double dx,
+                                          double dz, PairEval& e) {
+    double lp[3], lm[3];
+    lab_f_to_linear(g, cc.B, cc.fx0 + dx, cc.fz0 - dz, lp);
+    lab_f_to_linear(g, cc.B, cc.fx0 - dx, cc.fz0 + dz, lm);
+    float fp[3], fm[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        fp[k] = (float)lp[k];
+        fm[k] = (float)lm[k];
+    }
+    float mn = fminf(fminf(fminf(fp[0], fp[1]), fp[2]), 0.0f);
+    float mx = fmaxf(fmaxf(fp[0], fp[1]), fp[2]);
+    e.gp = (mn >= 0.0f) && (mx <= 1.0f);
+    mn = fminf(fminf(fm[0], fm[1]), fm[2]);
+    mx = fmaxf(fmaxf(fm[0], fm[1]), fm[2]);
+    e.gm = (mn >= 0.0f) && (mx <= 1.0f);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        e.vp[k] = encode255(fp[k]);
+        e.vm[k] = encode255(fm[k]);
+    }
+}
+
+// Integer form of a rule (Section 3): high = d > v_th, low = d <= lo_max where
+// lo_max = ceil(v_th * r_novib) - 1 is the largest integer change below
+// v_th * r_novib.
+struct RuleDev {
+    float v_th;
+    float lo_max;
+    uint32_t mask;  // bit (p-1) accepts pattern p
+    uint32_t clip;  // CV_RULE_CLIP reading
+};
+
+// Decide a candidate.  Returns the pattern p (1..7) if every channel is high or
+// low, 0 otherwise; V+/V- receive the rounded 8-bit values (as floats).
+__device__ __forceinline__ uint32_t decide(const PairEval& e, const RuleDev& r, float Vp[3],
+                                           float Vm[3], bool& in_gamut) {
+    uint32_t p = 0;
+    bool every = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float a = e.vp[k], b = e.vm[k];
+        if (r.clip) {
+            a = fminf(fmaxf(a, 0.0f), 255.0f);
+            b = fminf(fmaxf(b, 0.0f), 255.0f);
+        }
+        Vp[k] = __builtin_rintf(a);
+        Vm[k] = __builtin_rintf(b);
+        float d = fabsf(Vp[k] - Vm[k]);
+        bool hi = d > r.v_th;
+        bool lo = d <= r.lo_max;
+        every = every && (hi || lo);
+        p = 2u * p + (hi ? 1u : 0u);
+    }
+    in_gamut = r.clip ? true : (e.gp && e.gm);
+    return every ? p : 0u;
+}
+
+__device__ __forceinline__ bool accepts(const RuleDev& r, uint32_t p) {
+    return p != 0u && ((r.mask >> (p - 1u)) & 1u);
+}
+
+// 8-bit packing of a pair: lo = R+ | G+<<8 | B+<<16 | R-<<24,
+// hi = G- | B-<<8 | p<<16 | flags<<24.
+__device__ __forceinline__ void pack_pair(const float Vp[3], const float Vm[3], uint32_t p,
+                                          uint32_t flags, uint32_t& lo, uint32_t& hi) {
+    auto u8 = [](float v) { return (uint32_t)fminf(fmaxf(v, 0.0f), 255.0f); };
+    lo = u8(Vp[0]) | (u8(Vp[1]) << 8) | (u8(Vp[2]) << 16) | (u8(Vm[0]) << 24);
+    hi = u8(Vm[1]) | (u8(Vm[2]) << 8) | (p << 16) | (flags << 24);
+}
+
+} // namespace cvib

@@ -1,0 +1,80 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/cvib.h"
+#include "cvib_device.h"
+
+namespace cvib {
+
+// Colour-space constants derived in FP64 from the sRGB primaries and the D65
+// white (IEC 61966-2-1): M maps linear RGB to XYZ (Y of white = 1).
+struct ColorSpace {
+    double M[3][3];
+    double Minv[3][3];
+    double W[3]; // Xn, Yn = 1, Zn
+};
+const ColorSpace& color_space();
+Geom geom_constants();
+
+// Error reporting (thread-local message behind cv_last_error).
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+#define CV_HIP(call)                                        \
+    do {                                                    \
+        hipError_t _e = (call);                             \
+        if (_e != hipSuccess) return ::cvib::hip_fail(_e, #call); \
+    } while (0)
+
+// Validated, device-ready form of a grid.
+struct GridDev {
+    double dr;       // radius step
+    double ra, rb;   // dr / 500, dr / 200: radius step in f(X), f(Z) units
+    int32_t nr, ntheta;
+    int32_t N;       // 360 / dtheta: angles per full turn
+    int32_t qoff;    // table offset of cos(theta_j) = tab[j + qoff] (wrapped)
+    int32_t wrap;    // wrap bound for j + qoff
+    int32_t tab_len; // table length in doubles
+    int64_t per_colour;
+};
+int make_grid(const cv_grid* g, GridDev* out);
+int make_rule(const cv_rule* r, RuleDev* out);
+
+// Device workspace owned by a context, grown on demand.
+struct Buffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+int run_lab_convert(cv_context* ctx, const void* in, void* out, int64_t n, int dir,
+                    hipStream_t s);
+int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
+                    const RuleDev& rd, cv_pair* out, int64_t capacity, int64_t* offsets,
+                    cv_color_summary* summ, int64_t* total_host, uint32_t flags, hipStream_t s);
+int run_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
+                    const RuleDev& rd, cv_color_summary* summ, cv_table_row* table,
+                    hipStream_t s);
+
+} // namespace cvib
+
+struct cv_context {
+    int device = 0;
+    int num_cu = 0;
+    cvib::Buffer colors;  // ColorConst [n]
+    cvib::Buffer table;   // angle table
+    cvib::Buffer status;  // look-back tile status words
+    cvib::Buffer acc;     // per-colour accumulators
+    cvib::Buffer misc;    // ticket, total, error flag
+    uint64_t* host_misc = nullptr; // pinned mirror of misc for the total
+    // kernel timing (cv_context_set_timing)
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double kernel_ms = 0.0;
+    int64_t kernel_launches = 0;
+    int ensure(cvib::Buffer& b, size_t bytes);
+    int time_begin(hipStream_t s);
+    int time_end(hipStream_t s, bool sync);
+};

