@@ -493,6 +493,7 @@ void orc_reduce(const uint8_t* rgb, int64_t n, const orc_grid* g, const orc_rule
         s.best_j = 0xFFFF;
         uint8_t bins[36];
         memset(bins, 0, sizeof bins);
+        const int64_t turn = llround(360.0 / g->dtheta_deg);
         for (int32_t i = 0; i < g->nr; ++i) {
             for (int32_t j = 0; j < g->ntheta; ++j) {
                 orc_cand c;
@@ -511,7 +512,9 @@ void orc_reduce(const uint8_t* rgb, int64_t n, const orc_grid* g, const orc_rule
                     memcpy(s.best_minus, c.Vm, 3);
                     s.best_p = c.pattern;
                 }
-                int bin = (int)(((int64_t)j * 36) / g->ntheta);
+                /* bin = floor(theta_j / 10 deg) with theta_j = 360 j / N degrees,
+                 * N = 360 / dtheta (exact integer form) */
+                int bin = (int)(((int64_t)j * 36) / turn);
                 int ridx = i + 1 > 255 ? 255 : i + 1;
                 if (ridx > bins[bin]) bins[bin] = (uint8_t)ridx;
             }

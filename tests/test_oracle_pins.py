@@ -347,19 +347,24 @@ def test_radius_range_is_exhaustive(oracle):
 # Internal consistency of the oracle's own entry points.
 
 def test_search_reduce_and_eval_agree(oracle):
-    g = (0.5, 40, 4.0, 90)
+    """Survivor lists, summaries and the angle-bin table of the oracle agree
+    with its per-candidate evaluation, on a partial turn (80 of N = 90
+    angles) so that the bin of angle j, floor(4 j deg / 10 deg), differs from
+    any ntheta-based shortcut."""
+    nt = 80
+    g = (0.5, 40, 4.0, nt)
     cols = np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(7, 5)])
     rule = (50, 0.5, 0x2D)
     allc = oracle.eval_all(cols, g, rule)
     recs, offs, nb = oracle.search(cols, g, rule)
     summ, tc, tb = oracle.reduce(cols, g, rule, table=True)
-    per = 40 * 90
+    per = 40 * nt
     for k in range(len(cols)):
         v = allc[k].reshape(-1)
         idx = np.nonzero(v["valid"])[0]
         seg = recs[offs[k]:offs[k + 1]]
         assert len(seg) == len(idx) == summ["count"][k] == tc[k]
-        assert np.array_equal(seg["i"].astype(np.int64) * 90 + seg["j"], idx)
+        assert np.array_equal(seg["i"].astype(np.int64) * nt + seg["j"], idx)
         assert np.array_equal(seg["plus"], v["Vp"][idx]) and np.array_equal(seg["minus"], v["Vm"][idx])
         assert summ["n_gamut"][k] == int((v["gamut"] == 3).sum())
         for p in range(1, 8):
@@ -367,13 +372,14 @@ def test_search_reduce_and_eval_agree(oracle):
             if not (rule[2] >> (p - 1)) & 1:
                 assert summ["per_pattern"][k][p - 1] == 0
         if len(idx):
-            ii, jj = idx // 90, idx % 90
+            ii, jj = idx // nt, idx % nt
             best = idx[np.lexsort((jj, -ii))[0]]
-            assert (summ["best_i"][k], summ["best_j"][k]) == (best // 90, best % 90)
+            assert (summ["best_i"][k], summ["best_j"][k]) == (best // nt, best % nt)
             bins = np.zeros(36, dtype=np.uint8)
             for q in idx:
-                b = (q % 90) * 36 // 90
-                bins[b] = max(bins[b], q // 90 + 1)
+                deg = 4 * (q % nt)            # theta_j in whole degrees
+                b = deg // 10
+                bins[b] = max(bins[b], q // nt + 1)
             assert np.array_equal(tb[k], bins)
         else:
             assert summ["best_i"][k] == 0xFFFF
