@@ -69,7 +69,8 @@ extern "C" {
  * Search grid.  r_i = (i + 1) * dr for 0 <= i < nr; theta_j = j * dtheta_deg
  * degrees for 0 <= j < ntheta, measured from +b* towards +a* (D_a = r sin,
  * D_b = r cos, Section 2).  Requirements: dr > 0; 1 <= nr, ntheta <= 65535;
- * nr * ntheta < 2^31; 360 / dtheta_deg is an even integer N <= 65536.
+ * nr * ntheta < 2^31; 360 / dtheta_deg is an even integer N <= 8192 (the
+ * angle table lives in LDS); ntheta <= N.
  */
 typedef struct {
     double dr;
@@ -121,7 +122,8 @@ typedef struct {
 /*
  * Angle-bin table row, 40 bytes: the valid count and, for each of 36 bins of
  * 10 degrees (bin = floor(theta_j / 10 deg)), the largest radius index i + 1
- * that has a survivor in that bin (0 = none).  Requires nr <= 255.
+ * that has a survivor in that bin (0 = none).  Requires nr <= 255 and, for
+ * the per-angle maxima kept in LDS, N <= 4096 with ntheta <= 4096.
  */
 typedef struct {
     uint32_t count;
@@ -160,8 +162,12 @@ int cv_lab_convert(cv_context* ctx, const void* in, void* out, int64_t n, int di
  * receives per-colour CSR offsets; summ (cv_color_summary [n], nullable)
  * receives per-colour summaries.  *total_host receives the survivor total
  * (this synchronises the stream).  If total > capacity the call returns
- * CV_ECAPACITY, *total_host still holds the required total, out holds the
- * first `capacity` survivors, and offsets / summ are complete (two-call idiom).
+ * CV_ECAPACITY and *total_host still holds the required total; offsets and
+ * summ are complete and out holds the first `capacity` survivors (two-call
+ * idiom: call again with capacity >= total).  capacity = 0 with out = NULL
+ * is a pure count.  The context's workspace grows with the number of
+ * segments (one per row of radius when theta covers the full turn, else one
+ * per 512 candidates): 12 bytes each.
  * Errors: CV_EINVAL, CV_ECAPACITY, CV_EHIP, CV_ENOMEM, CV_ESTATE.
  */
 int cv_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,

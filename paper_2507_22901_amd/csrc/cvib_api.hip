@@ -95,8 +95,8 @@ int make_grid(const cv_grid* g, GridDev* out) {
         return fail(CV_EINVAL, "grid.dtheta_deg must be > 0");
     const double q = 360.0 / g->dtheta_deg;
     const double Nr = nearbyint(q);
-    if (fabs(q - Nr) > 1e-9 * Nr || Nr < 2 || Nr > 65536 || fmod(Nr, 2.0) != 0.0)
-        return fail(CV_EINVAL, "360 / grid.dtheta_deg must be an even integer <= 65536");
+    if (fabs(q - Nr) > 1e-9 * Nr || Nr < 2 || Nr > 8192 || fmod(Nr, 2.0) != 0.0)
+        return fail(CV_EINVAL, "360 / grid.dtheta_deg must be an even integer <= 8192");
     const int32_t N = (int32_t)Nr;
     if (g->ntheta > N) return fail(CV_EINVAL, "grid.ntheta exceeds one full turn");
     out->dr = g->dr;
@@ -105,15 +105,8 @@ int make_grid(const cv_grid* g, GridDev* out) {
     out->nr = g->nr;
     out->ntheta = g->ntheta;
     out->N = N;
-    if (N % 4 == 0) {
-        out->qoff = N / 4;
-        out->wrap = N;
-        out->tab_len = N;
-    } else {
-        out->qoff = N;
-        out->wrap = 2 * N;
-        out->tab_len = 2 * N;
-    }
+    // folded angle table: a quarter turn of sin, or a half turn of sin and cos
+    out->tab_len = (N % 4 == 0) ? N / 4 + 1 : 2 * (N / 2 + 1);
     out->per_colour = (int64_t)g->nr * g->ntheta;
     return CV_OK;
 }
@@ -238,7 +231,8 @@ int cv_context_destroy(cv_context* ctx) {
     if (!ctx) return CV_OK;
     DeviceGuard dg(ctx->device);
     (void)hipDeviceSynchronize();
-    cvib::Buffer* bufs[] = {&ctx->colors, &ctx->table, &ctx->status, &ctx->acc, &ctx->misc};
+    cvib::Buffer* bufs[] = {&ctx->colors, &ctx->table, &ctx->seg_cnt, &ctx->seg_prefix,
+                            &ctx->scan,   &ctx->acc,   &ctx->misc};
     for (cvib::Buffer* b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->host_misc) (void)hipHostFree(ctx->host_misc);
@@ -296,7 +290,8 @@ int cv_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
     if ((rc = cvib::make_grid(grid, &gd)) != CV_OK) return rc;
     if ((rc = cvib::make_rule(rule, &rd)) != CV_OK) return rc;
     if (table && gd.nr > 255) return fail(CV_EINVAL, "table rows need grid.nr <= 255");
-    if (table && gd.ntheta > 16384) return fail(CV_EINVAL, "table rows need grid.ntheta <= 16384");
+    if (table && (size_t)gd.tab_len * 8 + (size_t)gd.ntheta * 4 > 48 * 1024)
+        return fail(CV_EINVAL, "table rows need 8 * table + 4 * ntheta <= 48 KiB of LDS");
     DeviceGuard dg(ctx->device);
     return cvib::run_pair_reduce(ctx, rgb, n, gd, rd, summ, table, (hipStream_t)stream);
     CV_GUARD_END

@@ -66,36 +66,34 @@ __device__ __forceinline__ void lab_f_to_linear(const Geom& g, const double B[3]
     for (int k = 0; k < 3; ++k) lin[k] = __builtin_fma(g.A[k], gx, __builtin_fma(g.C[k], gz, B[k]));
 }
 
-// Outcome of evaluating one candidate (i, j) of one target.
-struct PairEval {
-    float vp[3], vm[3]; // encoded values of the + and - colour, 0..255, unrounded
-    bool gp, gm;        // gamut flags (all linear channels in [0,1])
-};
-
-// Evaluate the pair at displacement (dx, dz) = (r sin / 500, r cos / 200):
-// (L, a +- D_a, b +- D_b) in f-space is (fx0 +- dx, fz0 -+ dz) (Section 2).
-__device__ __forceinline__ void eval_pair(const ColorConst& cc, const Geom& g, double dx,
-                                          double dz, PairEval& e) {
+// Linear RGB of both colours of the pair at displacement (dx, dz) =
+// (r sin / 500, r cos / 200): (L, a +- D_a, b +- D_b) is (fx0 +- dx, fz0 -+ dz)
+// in f-space (Section 2).  Rounded to FP32 once the FP64 product is done.
+__device__ __forceinline__ void pair_linear(const ColorConst& cc, const Geom& g, double dx,
+                                           double dz, float fp[3], float fm[3]) {
     double lp[3], lm[3];
     lab_f_to_linear(g, cc.B, cc.fx0 + dx, cc.fz0 - dz, lp);
     lab_f_to_linear(g, cc.B, cc.fx0 - dx, cc.fz0 + dz, lm);
-    float fp[3], fm[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         fp[k] = (float)lp[k];
         fm[k] = (float)lm[k];
     }
-    float mn = fminf(fminf(fminf(fp[0], fp[1]), fp[2]), 0.0f);
-    float mx = fmaxf(fmaxf(fp[0], fp[1]), fp[2]);
-    e.gp = (mn >= 0.0f) && (mx <= 1.0f);
-    mn = fminf(fminf(fm[0], fm[1]), fm[2]);
-    mx = fmaxf(fmaxf(fm[0], fm[1]), fm[2]);
-    e.gm = (mn >= 0.0f) && (mx <= 1.0f);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        e.vp[k] = encode255(fp[k]);
-        e.vm[k] = encode255(fm[k]);
-    }
+}
+
+// All three linear channels in [0, 1]: the IEEE bit patterns of non-negative
+// floats order like the values, and every negative float (sign bit set)
+// compares above 1.0f's pattern as an unsigned integer.
+__device__ __forceinline__ bool in_unit_cube(const float l[3]) {
+    const uint32_t a = __float_as_uint(l[0]), b = __float_as_uint(l[1]), c = __float_as_uint(l[2]);
+    return max(max(a, b), c) <= 0x3F800000u;
+}
+
+// 8-bit code of a linear value: sRGB encode, clamp to [0, 255], round half to
+// even.  For values inside the gamut the clamp changes nothing; under the clip
+// reading it is the reading itself.
+__device__ __forceinline__ float code8(float l) {
+    return __builtin_rintf(__builtin_amdgcn_fmed3f(encode255(l), 0.0f, 255.0f));
 }
 
 // Integer form of a rule (Section 3): high = d > v_th, low = d <= lo_max where
@@ -108,28 +106,18 @@ struct RuleDev {
     uint32_t clip;  // CV_RULE_CLIP reading
 };
 
-// Decide a candidate.  Returns the pattern p (1..7) if every channel is high or
-// low, 0 otherwise; V+/V- receive the rounded 8-bit values (as floats).
-__device__ __forceinline__ uint32_t decide(const PairEval& e, const RuleDev& r, float Vp[3],
-                                           float Vm[3], bool& in_gamut) {
+// Pattern p = 4 hi_R + 2 hi_G + hi_B when every channel is high or low, else 0.
+__device__ __forceinline__ uint32_t pattern_of(const float Vp[3], const float Vm[3],
+                                               const RuleDev& r) {
     uint32_t p = 0;
     bool every = true;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        float a = e.vp[k], b = e.vm[k];
-        if (r.clip) {
-            a = fminf(fmaxf(a, 0.0f), 255.0f);
-            b = fminf(fmaxf(b, 0.0f), 255.0f);
-        }
-        Vp[k] = __builtin_rintf(a);
-        Vm[k] = __builtin_rintf(b);
-        float d = fabsf(Vp[k] - Vm[k]);
-        bool hi = d > r.v_th;
-        bool lo = d <= r.lo_max;
-        every = every && (hi || lo);
+        const float d = fabsf(Vp[k] - Vm[k]);
+        const bool hi = d > r.v_th;
+        every = every && (hi || d <= r.lo_max);
         p = 2u * p + (hi ? 1u : 0u);
     }
-    in_gamut = r.clip ? true : (e.gp && e.gm);
     return every ? p : 0u;
 }
 
@@ -137,13 +125,46 @@ __device__ __forceinline__ bool accepts(const RuleDev& r, uint32_t p) {
     return p != 0u && ((r.mask >> (p - 1u)) & 1u);
 }
 
-// 8-bit packing of a pair: lo = R+ | G+<<8 | B+<<16 | R-<<24,
-// hi = G- | B-<<8 | p<<16 | flags<<24.
+// Bytes of a pair record's last 8 bytes: lo = R+ | G+<<8 | B+<<16 | R-<<24,
+// hi = G- | B-<<8 | p<<16 | flags<<24 (codes are already integral in [0,255]).
 __device__ __forceinline__ void pack_pair(const float Vp[3], const float Vm[3], uint32_t p,
                                           uint32_t flags, uint32_t& lo, uint32_t& hi) {
-    auto u8 = [](float v) { return (uint32_t)fminf(fmaxf(v, 0.0f), 255.0f); };
-    lo = u8(Vp[0]) | (u8(Vp[1]) << 8) | (u8(Vp[2]) << 16) | (u8(Vm[0]) << 24);
-    hi = u8(Vm[1]) | (u8(Vm[2]) << 8) | (p << 16) | (flags << 24);
+    lo = __builtin_amdgcn_cvt_pk_u8_f32(Vp[0], 0, 0u);
+    lo = __builtin_amdgcn_cvt_pk_u8_f32(Vp[1], 1, lo);
+    lo = __builtin_amdgcn_cvt_pk_u8_f32(Vp[2], 2, lo);
+    lo = __builtin_amdgcn_cvt_pk_u8_f32(Vm[0], 3, lo);
+    hi = (p << 16) | (flags << 24);
+    hi = __builtin_amdgcn_cvt_pk_u8_f32(Vm[1], 0, hi);
+    hi = __builtin_amdgcn_cvt_pk_u8_f32(Vm[2], 1, hi);
+}
+
+// The same pair seen from the opposite ray (theta + 180 deg): + and - swap.
+// Gamut bits 0 and 1 of the flags swap as well.
+__device__ __forceinline__ void mirror_pair(uint32_t lo, uint32_t hi, uint32_t& mlo,
+                                            uint32_t& mhi) {
+    mlo = __builtin_amdgcn_perm(hi, lo, 0x00050403u); // R-, G-, B-, R+
+    const uint32_t fl = hi >> 24;
+    const uint32_t mfl = (fl & 4u) | ((fl & 1u) << 1) | ((fl >> 1) & 1u);
+    mhi = (__builtin_amdgcn_perm(hi, lo, 0x07060201u) & 0x00FFFFFFu) | (mfl << 24); // G+, B+, p
+}
+
+// Full evaluation of one candidate (used outside the hot loop).
+struct PairEval {
+    float Vp[3], Vm[3];
+    bool gp, gm;
+};
+
+__device__ __forceinline__ void eval_pair(const ColorConst& cc, const Geom& g, double dx,
+                                          double dz, PairEval& e) {
+    float fp[3], fm[3];
+    pair_linear(cc, g, dx, dz, fp, fm);
+    e.gp = in_unit_cube(fp);
+    e.gm = in_unit_cube(fm);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        e.Vp[k] = code8(fp[k]);
+        e.Vm[k] = code8(fm[k]);
+    }
 }
 
 } // namespace cvib

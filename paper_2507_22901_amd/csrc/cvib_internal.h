@@ -35,9 +35,7 @@ struct GridDev {
     double ra, rb;   // dr / 500, dr / 200: radius step in f(X), f(Z) units
     int32_t nr, ntheta;
     int32_t N;       // 360 / dtheta: angles per full turn
-    int32_t qoff;    // table offset of cos(theta_j) = tab[j + qoff] (wrapped)
-    int32_t wrap;    // wrap bound for j + qoff
-    int32_t tab_len; // table length in doubles
+    int32_t tab_len; // folded angle table length in doubles
     int64_t per_colour;
 };
 int make_grid(const cv_grid* g, GridDev* out);
@@ -65,9 +63,11 @@ struct cv_context {
     int num_cu = 0;
     cvib::Buffer colors;  // ColorConst [n]
     cvib::Buffer table;   // angle table
-    cvib::Buffer status;  // look-back tile status words
-    cvib::Buffer acc;     // per-colour accumulators
-    cvib::Buffer misc;    // ticket, total, error flag
+    cvib::Buffer seg_cnt;     // records per search segment
+    cvib::Buffer seg_prefix;  // output offset per search segment
+    cvib::Buffer scan;        // per-block partial sums of the segment scan
+    cvib::Buffer acc;         // per-colour accumulators
+    cvib::Buffer misc;        // ticket, -, survivor total
     uint64_t* host_misc = nullptr; // pinned mirror of misc for the total
     // kernel timing (cv_context_set_timing)
     bool timing = false;

@@ -167,13 +167,20 @@ __device__ double cos_turn(int64_t m, int64_t N) {
     return sgn * cos((double)m * (2.0 * M_PI / (double)N));
 }
 
-// tab[0, N) = sin; when 4 does not divide N, tab[N, 2N) = cos.  Otherwise
-// cos(theta_j) is read as tab[(j + N/4) mod N].
-__global__ void k_angle_table(double* __restrict__ tab, int32_t N, int32_t with_cos) {
+// Table layout.  N % 4 == 0: tab[k] = sin(2 pi k / N) for 0 <= k <= N/4 (a
+// quarter turn).  N % 4 == 2: tab[k] = sin, tab[H + 1 + k] = cos of
+// 2 pi k / N for 0 <= k <= H = N/2 (a half turn).
+__global__ void k_angle_table(double* __restrict__ tab, int32_t N) {
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
-    tab[k] = sin_turn(k, N);
-    if (with_cos) tab[N + k] = cos_turn(k, N);
+    if (N % 4 == 0) {
+        if (k <= N / 4) tab[k] = sin_turn(k, N);
+    } else {
+        const int32_t H = N / 2;
+        if (k <= H) {
+            tab[k] = sin_turn(k, N);
+            tab[H + 1 + k] = cos_turn(k, N);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -188,17 +195,31 @@ static_assert(sizeof(SumAcc) == 192, "SumAcc layout");
 
 struct TabArgs {
     const double* tab;
-    int32_t tab_len;       // doubles in the table
-    int32_t qoff, wrap, N; // cos(theta_j) = tab[j + qoff - (j + qoff >= wrap ? N : 0)]
+    int32_t tab_len;  // doubles in the table
+    int32_t N;        // angles per full turn
 };
 
-template <bool LDS>
-__device__ __forceinline__ void sincos_j(const double* tab, const TabArgs& t, int32_t j, double& s,
+// sin and cos of theta_j = 2 pi j / N (0 <= j < N) from the folded table.
+// The folds are exact integer steps, so ray j + N/2 reads the negated values
+// of ray j bit for bit.
+__device__ __forceinline__ void sincos_j(const double* tab, int32_t N, int32_t j, double& s,
                                          double& c) {
-    int32_t jc = j + t.qoff;
-    jc -= (jc >= t.wrap) ? t.N : 0;
-    s = tab[j];
-    c = tab[jc];
+    const int32_t H = N >> 1;
+    const bool back = j >= H;          // second half-turn: negate both
+    const int32_t jj = back ? j - H : j;
+    if ((N & 3) == 0) {
+        const int32_t Q = N >> 2;
+        const bool lo = jj <= Q;
+        const double a = tab[lo ? jj : H - jj];  // sin(jj) = sin(pi - jj)
+        const double b = tab[lo ? Q - jj : jj - Q];
+        s = back ? -a : a;
+        const double cc = lo ? b : -b;            // cos(jj) = -sin(jj - pi/2)
+        c = back ? -cc : cc;
+    } else {
+        const double a = tab[jj], b = tab[H + 1 + jj];
+        s = back ? -a : a;
+        c = back ? -b : b;
+    }
 }
 
 // Key of the maximum-amplitude pair: larger i wins, then smaller j.  0 = none.
@@ -220,71 +241,21 @@ struct SearchArgs {
     TabArgs tab;
     Geom g;
     RuleDev rule;
-    double ra, rb;        // dr / 500, dr / 200
+    double ra, rb;             // dr / 500, dr / 200
     int32_t nr, ntheta;
-    float inv_ntheta;
-    int32_t si, sj;       // block stride = si * ntheta + sj candidates
-    int32_t tiles_per_colour;
-    int64_t n, ntiles;
-    cv_pair* out;
-    int64_t capacity;
-    int64_t* offsets;     // nullable
-    uint64_t* status;     // look-back words [ntiles]
-    SumAcc* acc;          // nullable
-    uint64_t* misc;       // [0] ticket, [1] total, [2] error bits
+    int32_t W;                 // evaluations per row: ntheta, or N/2 in half-turn mode
+    float inv_W;
+    int32_t si64, sj64;        // a pass of 64 evaluations = si64 rows + sj64 rays
+    int32_t seg_len;           // evaluations per segment (one row in half-turn mode)
+    int32_t segs_per_colour;
+    int64_t n, nsegs;
+    uint32_t* seg_cnt;         // output records per segment (count pass writes)
+    const uint64_t* seg_prefix;// output offset per segment (write pass reads)
+    uint4* out;                // survivor records (write pass)
+    uint64_t capacity;         // records
+    SumAcc* acc;               // nullable
+    uint64_t* misc;            // [0] count-pass ticket, [2] survivor total
 };
-
-constexpr uint64_t kStAgg = 1ull << 62;
-constexpr uint64_t kStIncl = 2ull << 62;
-constexpr uint64_t kStVal = (1ull << 62) - 1;
-constexpr uint32_t kSpinLimit = 1u << 24;
-
-__device__ __forceinline__ void st_store(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t st_load(uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Decoupled look-back (Merrill & Garland, "Single-pass Parallel Prefix Scan
-// with Decoupled Look-back", 2016), run by one full wave.  Tiles are claimed
-// through an in-order ticket, so every predecessor is resident or finished
-// and publishes its aggregate without waiting: the wait always ends.  The
-// spin count is still bounded; on overrun the error bit is set and the wave
-// carries on with what it has (the host then reports CV_ESTATE).
-__device__ uint64_t lookback(uint64_t* status, int64_t t, uint64_t tile_total, uint32_t lane,
-                             uint64_t* err) {
-    if (t == 0) {
-        if (lane == 0) st_store(&status[0], kStIncl | tile_total);
-        return 0;
-    }
-    if (lane == 0) st_store(&status[t], kStAgg | tile_total);
-    uint64_t excl = 0;
-    int64_t p = t - 1;
-    uint32_t spins = 0;
-    for (;;) {
-        const int64_t q = p - (int64_t)lane;
-        uint64_t s = q >= 0 ? st_load(&status[q]) : kStIncl;
-        for (;;) {
-            uint64_t pend = __ballot((s >> 62) == 0);
-            if (pend == 0) break;
-            if (++spins > kSpinLimit) {
-                if (lane == 0) atomicOr((unsigned long long*)err, 1ull);
-                if ((s >> 62) == 0) s = kStAgg;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            if ((s >> 62) == 0) s = st_load(&status[q]);
-        }
-        const uint64_t incl = __ballot((s >> 62) == 2);
-        const uint32_t first = incl ? (uint32_t)__builtin_ctzll(incl) : 64u;
-        excl += wave_sum_u64(lane <= first ? (s & kStVal) : 0ull);
-        if (incl) break;
-        p -= 64;
-    }
-    if (lane == 0) st_store(&status[t], kStIncl | (excl + tile_total));
-    return excl;
-}
 
 // Per-wave flush of a thread's running summary into the colour accumulator.
 __device__ __forceinline__ void flush_summary(SumAcc* acc, int64_t col, uint32_t lane,
@@ -308,137 +279,259 @@ __device__ __forceinline__ void flush_summary(SumAcc* acc, int64_t col, uint32_t
     for (int p = 0; p < 7; ++p) pat[p] = 0;
 }
 
-// ---------------------------------------------------------------------------
-// Fused search with compaction.  A tile is TILE = BLOCK * K consecutive
-// candidates (i, j) of one colour in row-major order; tiles of a colour are
-// contiguous and colours follow each other, so the output order of the tiles
-// is the (colour, i, j) order.  Inside a tile, pass m of wave w covers
-// candidates [m*BLOCK + 64w, m*BLOCK + 64w + 64), so (m, w, lane) order is
-// candidate order as well.
-template <int BLOCK, int K, bool EMIT_ALL, bool SUMM, bool TAB_LDS>
-__global__ __launch_bounds__(BLOCK) void k_pair_search(SearchArgs a) {
-    constexpr int NW = BLOCK / 64;
-    constexpr int TILE = BLOCK * K;
-    static_assert(K * NW <= 64, "tile scan runs in one wave");
-    static_assert(K <= 15, "per-tile pattern nibbles");
-    extern __shared__ double s_tab[];
-    __shared__ uint32_t s_cnt[K * NW];
-    __shared__ uint32_t s_pre[K * NW];
-    __shared__ uint64_t s_base;
-    __shared__ int64_t s_tick;
+// One candidate of the hot loop: geometry in FP64, then (only if some lane of
+// the wave has both colours in gamut, or every candidate is to be emitted)
+// the FP32 transfer, rounding and the predicate.  Returns the packed record
+// bytes and the decision.
+template <bool EMIT_ALL>
+__device__ __forceinline__ void candidate(const ColorConst& cc, const SearchArgs& a, double s,
+                                          double co, int32_t i, bool live, uint32_t& lo,
+                                          uint32_t& hi, bool& surv, bool& both, uint32_t& pat) {
+    const double rr = (double)(i + 1);
+    float fp[3], fm[3];
+    pair_linear(cc, a.g, (rr * a.ra) * s, (rr * a.rb) * co, fp, fm);
+    const bool gp = in_unit_cube(fp), gm = in_unit_cube(fm);
+    both = live && gp && gm;
+    const bool need = a.rule.clip ? live : both;
+    surv = false;
+    pat = 0;
+    lo = hi = 0;
+    if (EMIT_ALL || __ballot(need) != 0ull) {
+        float Vp[3], Vm[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            Vp[k] = code8(fp[k]);
+            Vm[k] = code8(fm[k]);
+        }
+        const uint32_t p = pattern_of(Vp, Vm, a.rule);
+        surv = need && accepts(a.rule, p);
+        pat = (need || EMIT_ALL) && (a.rule.clip || (gp && gm)) ? p : 0u;
+        const uint32_t flags = (gp ? 1u : 0u) | (gm ? 2u : 0u) | (surv ? 4u : 0u);
+        pack_pair(Vp, Vm, pat, flags, lo, hi);
+    } else if (EMIT_ALL) {
+        hi = ((gp ? 1u : 0u) | (gm ? 2u : 0u)) << 24;
+    }
+}
 
+// ---------------------------------------------------------------------------
+// Fused search with compaction.
+//
+// General mode: a tile is TILE = BLOCK * K consecutive candidates of one
+// colour in row-major (i, j) order; pass m of wave w covers evaluations
+// [m*BLOCK + 64w, +64), so (m, w, lane) order is candidate order.
+//
+// Half-turn mode (the grid covers the full turn, ntheta = N): ray j + N/2
+// carries ray j's pair with + and - swapped (the angle table is exactly
+// antisymmetric), so only j < N/2 is evaluated and every survivor is written
+// twice.  A tile is then a set of whole rows i; its output is, row by row, the
+// survivors of the first half-row followed by their mirrors, which is again
+// (colour, i, j) order.  Tiles follow each other in (colour, row) order, so
+// the look-back prefix of a tile is its output offset.
+// Fused search: count pass and write pass.
+//
+// The candidates of a colour are cut into segments of consecutive
+// evaluations in row-major (i, j < W) order.  General mode: W = ntheta and a
+// segment is seg_len = 512 evaluations.  Half-turn mode (the grid spans the
+// full turn, ntheta = N): ray j + N/2 carries ray j's pair with + and -
+// swapped (the angle table is exactly antisymmetric), so only j < W = N/2 is
+// evaluated, a segment is one whole row, and the row's output is its half-row
+// survivors followed by their mirrors -- (colour, i, j) order again.
+//
+// Each wave owns whole segments (statically strided over all waves of the
+// grid), so no barrier, ticket or atomic is on the path:
+//   count pass: survivors per segment (and the per-colour summaries);
+//   scan:       segment counts -> output offsets, in segment order;
+//   write pass: segments with survivors are evaluated again and each wave
+//               writes its survivors at offset + (survivors before it in the
+//               segment), found with a ballot and the lane rank.
+template <bool EMIT_ALL, bool SUMM, bool SYM, bool WRITE>
+__global__ __launch_bounds__(256) void k_pair_pass(SearchArgs a) {
+    constexpr int NW = 256 / 64;
+    extern __shared__ double s_tab[];
     const int tid = threadIdx.x;
     const uint32_t lane = (uint32_t)tid & 63u;
     const int w = tid >> 6;
+    for (int k = tid; k < a.tab.tab_len; k += 256) s_tab[k] = a.tab.tab[k];
+    __syncthreads();
 
-    const double* tab = a.tab.tab;
-    if constexpr (TAB_LDS) {
-        for (int k = tid; k < a.tab.tab_len; k += BLOCK) s_tab[k] = a.tab.tab[k];
-        tab = s_tab;
-    }
+    const uint32_t mult = SYM ? 2u : 1u;
+    const int64_t per = (int64_t)a.nr * a.W;
+    // Waves stride over the segments statically; most segments hold no
+    // survivor and are skipped at the cost of one load.
+    const int64_t GW = (int64_t)gridDim.x * NW;
 
     int64_t cur_c = -1;
     uint32_t acc_cnt = 0, acc_ng = 0, acc_best = 0, acc_pat[7] = {0, 0, 0, 0, 0, 0, 0};
 
-    for (;;) {
-        if (tid == 0) s_tick = (int64_t)atomicAdd((unsigned long long*)&a.misc[0], 1ull);
-        __syncthreads();
-        const int64_t t = uniform_i64(s_tick);
-        if (t >= a.ntiles) break;
-        const int64_t c = t / a.tiles_per_colour;
-        const int32_t lt = (int32_t)(t - c * a.tiles_per_colour);
-        if constexpr (SUMM) {
+    for (int64_t sg = (int64_t)blockIdx.x * NW + w; sg < a.nsegs; sg += GW) {
+        const int64_t c = sg / a.segs_per_colour;
+        const int32_t ls = (int32_t)(sg - c * a.segs_per_colour);
+        uint64_t base = 0;
+        uint32_t half = 0;
+        if constexpr (WRITE) {
+            const uint32_t cnt = a.seg_cnt[sg];
+            if (cnt == 0) continue;
+            base = a.seg_prefix[sg];
+            half = SYM ? cnt / 2u : 0u;
+        }
+        if constexpr (SUMM && !WRITE) {
             if (c != cur_c) {
                 if (cur_c >= 0) flush_summary(a.acc, cur_c, lane, acc_cnt, acc_ng, acc_best, acc_pat);
                 cur_c = c;
             }
         }
         const ColorConst cc = a.cc[c];
-
-        // (i, j) of this thread's first candidate
-        const int32_t base_idx = lt * TILE;
-        const int32_t ib = base_idx / a.ntheta;
-        const int32_t jb = base_idx - ib * a.ntheta;
-        int32_t di, j;
-        divmod_small(jb + tid, a.ntheta, a.inv_ntheta, di, j);
-        int32_t i = ib + di;
-
-        uint32_t r_ij[K], r_lo[K], r_hi[K];
-        uint64_t bal[K];
-        uint32_t nib = 0, ng = 0, best = 0;
-#pragma unroll
-        for (int m = 0; m < K; ++m) {
-            const bool live = i < a.nr;
-            double s, co;
-            sincos_j<TAB_LDS>(tab, a.tab, live ? j : 0, s, co);
-            const double rr = (double)(i + 1);
-            PairEval e;
-            eval_pair(cc, a.g, (rr * a.ra) * s, (rr * a.rb) * co, e);
-            float Vp[3], Vm[3];
-            bool ing;
-            uint32_t p = decide(e, a.rule, Vp, Vm, ing);
-            const bool surv = live && ing && accepts(a.rule, p);
-            const uint32_t flags = (e.gp ? 1u : 0u) | (e.gm ? 2u : 0u) | (surv ? 4u : 0u);
-            pack_pair(Vp, Vm, ing ? p : 0u, flags, r_lo[m], r_hi[m]);
-            r_ij[m] = (uint32_t)i | ((uint32_t)j << 16);
+        const int32_t base_e = ls * a.seg_len;
+        const int32_t len = (int32_t)min((int64_t)a.seg_len, per - base_e);
+        int32_t i = base_e / a.W;
+        int32_t j;
+        {
+            const int32_t jb = base_e - i * a.W;
+            int32_t di;
+            divmod_small(jb + (int32_t)lane, a.W, a.inv_W, di, j);
+            i += di;
+        }
+        uint32_t wtop = 0;             // survivors of this segment before the current pass
+        uint32_t cnt = 0, ng = 0, best = 0, steps = 0;
+        uint64_t pk = 0;               // 8-bit pattern counters, flushed every 255 passes
+        const int32_t iters = (len + 63) >> 6;
+        for (int32_t it = 0; it < iters; ++it) {
+            const bool live = (it << 6) + (int32_t)lane < len;
+            double sn, co;
+            sincos_j(s_tab, a.tab.N, j, sn, co);
+            uint32_t lo, hi, pat;
+            bool surv, both;
+            candidate<EMIT_ALL>(cc, a, sn, co, i, live, lo, hi, surv, both, pat);
             const bool emit = EMIT_ALL ? live : surv;
-            bal[m] = __ballot(emit);
-            if (lane == 0) s_cnt[m * NW + w] = (uint32_t)__builtin_popcountll(bal[m]);
-            if constexpr (SUMM) {
-                nib += surv ? (1u << (4u * (p - 1u))) : 0u;
-                ng += (live && e.gp && e.gm) ? 1u : 0u;
+            const uint64_t bal = __ballot(emit);
+            if constexpr (WRITE) {
+                if (emit) {
+                    const uint64_t pos = base + wtop + rank_below(bal);
+                    const uint32_t ij = (uint32_t)i | ((uint32_t)j << 16);
+                    if (pos < a.capacity) a.out[pos] = make_uint4((uint32_t)c, ij, lo, hi);
+                    if constexpr (SYM) {
+                        if (pos + half < a.capacity) {
+                            uint32_t mlo, mhi;
+                            mirror_pair(lo, hi, mlo, mhi);
+                            a.out[pos + half] =
+                                make_uint4((uint32_t)c, ij + ((uint32_t)a.W << 16), mlo, mhi);
+                        }
+                    }
+                }
+            }
+            wtop += (uint32_t)__builtin_popcountll(bal);
+            if constexpr (SUMM && !WRITE) {
+                cnt += surv ? 1u : 0u;
+                pk += surv ? (1ull << (8u * ((pat - 1u) & 7u))) : 0ull;
+                ng += both ? 1u : 0u;
                 best = max(best, surv ? best_key(i, j) : 0u);
-            }
-            j += a.sj;
-            i += a.si;
-            if (j >= a.ntheta) { j -= a.ntheta; ++i; }
-        }
-        if constexpr (SUMM) {
+                if (++steps == 255) {
 #pragma unroll
-            for (int p = 0; p < 7; ++p) {
-                acc_pat[p] += (nib >> (4 * p)) & 0xFu;
-                acc_cnt += (nib >> (4 * p)) & 0xFu;
-            }
-            acc_ng += ng;
-            acc_best = max(acc_best, best);
-        }
-        __syncthreads();
-        if (w == 0) {
-            const uint32_t v = lane < (uint32_t)(K * NW) ? s_cnt[lane] : 0u;
-            uint32_t incl = v;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                uint32_t u = __shfl_up(incl, o, 64);
-                if (lane >= (uint32_t)o) incl += u;
-            }
-            if (lane < (uint32_t)(K * NW)) s_pre[lane] = incl - v;
-            const uint64_t tile_total = __shfl(incl, 63, 64);
-            const uint64_t excl = lookback(a.status, t, tile_total, lane, &a.misc[2]);
-            if (lane == 0) {
-                s_base = excl;
-                if (lt == 0 && a.offsets) a.offsets[c] = (int64_t)excl;
-                if (t == a.ntiles - 1) {
-                    a.misc[1] = excl + tile_total;
-                    if (a.offsets) a.offsets[a.n] = (int64_t)(excl + tile_total);
+                    for (int q = 0; q < 7; ++q) acc_pat[q] += mult * ((uint32_t)(pk >> (8 * q)) & 0xFFu);
+                    pk = 0;
+                    steps = 0;
                 }
             }
+            j += a.sj64;
+            i += a.si64;
+            if (j >= a.W) { j -= a.W; ++i; }
         }
-        __syncthreads();
-        const uint64_t base = s_base;
+        if constexpr (!WRITE) {
+            if (lane == 0) a.seg_cnt[sg] = mult * wtop;
+            if constexpr (SUMM) {
 #pragma unroll
-        for (int m = 0; m < K; ++m) {
-            if ((bal[m] >> lane) & 1ull) {
-                const uint64_t pos = base + s_pre[m * NW + w] + rank_below(bal[m]);
-                if (pos < (uint64_t)a.capacity) {
-                    uint4 rec = make_uint4((uint32_t)c, r_ij[m], r_lo[m], r_hi[m]);
-                    *reinterpret_cast<uint4*>(a.out + pos) = rec;
-                }
+                for (int q = 0; q < 7; ++q) acc_pat[q] += mult * ((uint32_t)(pk >> (8 * q)) & 0xFFu);
+                acc_cnt += mult * cnt;
+                acc_ng += mult * ng;
+                acc_best = max(acc_best, best);
             }
         }
     }
-    if constexpr (SUMM) {
+    if constexpr (SUMM && !WRITE) {
         if (cur_c >= 0) flush_summary(a.acc, cur_c, lane, acc_cnt, acc_ng, acc_best, acc_pat);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Segment record counts -> output offsets: an exclusive scan in segment
+// order, which is (colour, i, j) order; also the per-colour CSR offsets.
+
+constexpr int kScanBlock = 256;
+constexpr int kScanPer = 16;                       // items per thread
+constexpr int kScanChunk = kScanBlock * kScanPer;  // items per block
+
+// Block-wide exclusive scan of one value per thread; `total` receives the sum.
+__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* s_w,
+                                                         uint64_t& total) {
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    uint64_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t u = __shfl_up(incl, o, 64);
+        if (lane >= (uint32_t)o) incl += u;
+    }
+    if (lane == 63) s_w[w] = incl;
+    __syncthreads();
+    uint64_t before = 0;
+    total = 0;
+    for (uint32_t q = 0; q < blockDim.x / 64; ++q) {
+        if (q < w) before += s_w[q];
+        total += s_w[q];
+    }
+    __syncthreads();
+    return before + incl - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(const uint32_t* __restrict__ cnt,
+                                                          int64_t T, uint64_t* __restrict__ sums) {
+    __shared__ uint64_t s_w[kScanBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+    uint64_t v = 0;
+    for (int k = 0; k < kScanPer; ++k)
+        if (base + k < T) v += cnt[base + k];
+    uint64_t total;
+    block_exclusive_scan(v, s_w, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of the per-block sums by a single block.
+__global__ __launch_bounds__(kScanBlock) void k_scan_top(uint64_t* __restrict__ sums, int64_t B,
+                                                         uint64_t* __restrict__ misc) {
+    __shared__ uint64_t s_w[kScanBlock / 64];
+    uint64_t carry = 0;
+    for (int64_t b0 = 0; b0 < B; b0 += kScanBlock) {
+        const int64_t b = b0 + threadIdx.x;
+        const uint64_t v = b < B ? sums[b] : 0ull;
+        uint64_t total;
+        const uint64_t ex = block_exclusive_scan(v, s_w, total);
+        if (b < B) sums[b] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) misc[2] = carry; // survivor total
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const uint32_t* __restrict__ cnt,
+                                                           int64_t T,
+                                                           const uint64_t* __restrict__ sums,
+                                                           uint64_t* __restrict__ prefix,
+                                                           int64_t* __restrict__ offsets,
+                                                           int32_t segs_per_colour, int64_t n,
+                                                           const uint64_t* __restrict__ misc) {
+    __shared__ uint64_t s_w[kScanBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+    uint64_t v = 0;
+    for (int k = 0; k < kScanPer; ++k)
+        if (base + k < T) v += cnt[base + k];
+    uint64_t total;
+    uint64_t run = sums[blockIdx.x] + block_exclusive_scan(v, s_w, total);
+    for (int k = 0; k < kScanPer; ++k) {
+        const int64_t t = base + k;
+        if (t >= T) break;
+        prefix[t] = run;
+        if (offsets && t % segs_per_colour == 0) offsets[t / segs_per_colour] = (int64_t)run;
+        run += cnt[t];
+    }
+    if (offsets && blockIdx.x == 0 && threadIdx.x == 0) offsets[n] = (int64_t)misc[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -455,9 +548,10 @@ struct ReduceArgs {
     RuleDev rule;
     double ra, rb;
     int32_t nr, ntheta;
-    float inv_ntheta;
+    int32_t W;                // evaluations per row (ntheta, or N/2 in half-turn mode)
+    float inv_W;
     int32_t si, sj;
-    int32_t chunk;            // candidates per tile (multiple of the block size)
+    int32_t chunk;            // evaluations per tile (multiple of the block size)
     int32_t tiles_per_colour;
     int32_t bin_num, bin_den; // bin = (j * bin_num) / bin_den = floor(36 j / N)
     int64_t n, ntiles;
@@ -465,13 +559,16 @@ struct ReduceArgs {
     cv_color_summary* summ;   // direct mode outputs (nullable)
     cv_table_row* table;      // direct mode outputs (nullable)
     uint64_t* misc;           // [0] ticket
+    uint32_t* seg_cnt;        // SEG: output records per segment of the search
+    int32_t seg_len;          // SEG: evaluations per segment (chunk is a multiple)
+    int32_t segs_per_colour;  // SEG
 };
 
 __device__ __forceinline__ void write_summary(const ColorConst& cc, const Geom& g,
                                               const RuleDev& rule, const TabArgs& tab,
-                                              const double* tabp, double ra, double rb,
-                                              uint32_t count, uint32_t ng, uint32_t key,
-                                              const uint32_t pat[7], cv_color_summary* out) {
+                                              double ra, double rb, uint32_t count, uint32_t ng,
+                                              uint32_t key, const uint32_t pat[7],
+                                              cv_color_summary* out) {
     cv_color_summary s;
     s.count = count;
     s.n_gamut = ng;
@@ -484,47 +581,53 @@ __device__ __forceinline__ void write_summary(const ColorConst& cc, const Geom& 
     if (key) {
         const int32_t i = (int32_t)(key >> 16), j = (int32_t)(0xFFFFu - (key & 0xFFFFu));
         double sn, co;
-        sincos_j<false>(tabp, tab, j, sn, co);
+        sincos_j(tab.tab, tab.N, j, sn, co);
         const double rr = (double)(i + 1);
         PairEval e;
         eval_pair(cc, g, (rr * ra) * sn, (rr * rb) * co, e);
-        float Vp[3], Vm[3];
-        bool ing;
-        const uint32_t p = decide(e, rule, Vp, Vm, ing);
         s.best_i = (uint16_t)i;
         s.best_j = (uint16_t)j;
         for (int k = 0; k < 3; ++k) {
-            s.best_plus[k] = (uint8_t)Vp[k];
-            s.best_minus[k] = (uint8_t)Vm[k];
+            s.best_plus[k] = (uint8_t)e.Vp[k];
+            s.best_minus[k] = (uint8_t)e.Vm[k];
         }
-        s.best_p = (uint8_t)p;
+        s.best_p = (uint8_t)pattern_of(e.Vp, e.Vm, rule);
     }
     *out = s;
 }
 
-template <int BLOCK, bool TABLE, bool DIRECT, bool TAB_LDS>
+// Reduce-only search.  A tile is a chunk of one colour's evaluations (i, j < W)
+// in row-major order: the whole colour when it fits (results are then written
+// directly), otherwise per-colour accumulators are merged with atomics and a
+// finalize kernel writes the outputs.  With the angle-bin table, the largest
+// surviving radius index of every evaluated ray is kept in LDS.  In half-turn
+// mode (SYM) only rays j < N/2 are evaluated: counts double, and the bins of
+// the second half-turn copy the first (bin(theta + 180 deg) = bin(theta) + 18).
+template <int BLOCK, bool TABLE, bool DIRECT, bool SYM, bool SEG>
 __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
     constexpr int NW = BLOCK / 64;
+    constexpr int MAX_SEG = 2048;  // segments per tile (SEG)
     extern __shared__ double s_dyn[];
     __shared__ uint32_t s_red[NW][10];
     __shared__ uint32_t s_bins[36];
+    __shared__ uint32_t s_seg[SEG ? MAX_SEG : 1];
     __shared__ int64_t s_tick;
 
     const int tid = threadIdx.x;
     const uint32_t lane = (uint32_t)tid & 63u;
     const int w = tid >> 6;
-    const double* tab = a.tab.tab;
-    uint32_t* s_ray = nullptr;
-    if constexpr (TAB_LDS) {
-        for (int k = tid; k < a.tab.tab_len; k += BLOCK) s_dyn[k] = a.tab.tab[k];
-        tab = s_dyn;
-    }
-    if constexpr (TABLE) s_ray = reinterpret_cast<uint32_t*>(s_dyn + (TAB_LDS ? a.tab.tab_len : 0));
+    for (int k = tid; k < a.tab.tab_len; k += BLOCK) s_dyn[k] = a.tab.tab[k];
+    const double* tab = s_dyn;
+    uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len);
+    const uint32_t mult = SYM ? 2u : 1u;
 
     for (;;) {
         if (tid == 0) s_tick = (int64_t)atomicAdd((unsigned long long*)&a.misc[0], 1ull);
         if constexpr (TABLE) {
-            for (int k = tid; k < a.ntheta; k += BLOCK) s_ray[k] = 0;
+            for (int k = tid; k < a.W; k += BLOCK) s_ray[k] = 0;
+        }
+        if constexpr (SEG) {
+            for (int k = tid; k < MAX_SEG; k += BLOCK) s_seg[k] = 0;
         }
         __syncthreads();
         const int64_t t = uniform_i64(s_tick);
@@ -533,34 +636,64 @@ __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
         const int32_t lt = (int32_t)(t - c * a.tiles_per_colour);
         const ColorConst cc = a.cc[c];
         const int32_t begin = lt * a.chunk;
-        const int64_t per = (int64_t)a.nr * a.ntheta;
-        const int32_t len = (int32_t)min((int64_t)a.chunk, per - begin);
-        const int32_t ib = begin / a.ntheta;
-        const int32_t jb = begin - ib * a.ntheta;
-        int32_t di, j;
-        divmod_small(jb + tid, a.ntheta, a.inv_ntheta, di, j);
-        int32_t i = ib + di;
-
+        const int32_t len = min(a.chunk, a.nr * a.W - begin);
+        const int32_t seg0 = SEG ? begin / a.seg_len : 0;  // chunks start on segment bounds
+        int32_t i = begin / a.W;
+        int32_t j;
+        {
+            const int32_t jb = begin - i * a.W;
+            int32_t di;
+            divmod_small(jb + tid, a.W, a.inv_W, di, j);
+            i += di;
+        }
         uint32_t cnt = 0, ng = 0, best = 0;
         uint64_t pk = 0;          // 8-bit pattern counters, flushed every 255 steps
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
         int32_t steps = 0;
-        for (int32_t k = tid; k < len; k += BLOCK) {
-            double s, co;
-            sincos_j<TAB_LDS>(tab, a.tab, j, s, co);
+        const int32_t iters = (len + BLOCK - 1) / BLOCK;
+        for (int32_t it = 0; it < iters; ++it) {
+            const bool live = it * BLOCK + tid < len;
+            double sn, co;
+            sincos_j(tab, a.tab.N, j, sn, co);
             const double rr = (double)(i + 1);
-            PairEval e;
-            eval_pair(cc, a.g, (rr * a.ra) * s, (rr * a.rb) * co, e);
-            float Vp[3], Vm[3];
-            bool ing;
-            const uint32_t p = decide(e, a.rule, Vp, Vm, ing);
-            const bool surv = ing && accepts(a.rule, p);
-            ng += (e.gp && e.gm) ? 1u : 0u;
-            if (surv) {
-                ++cnt;
-                pk += 1ull << (8u * (p - 1u));
-                best = max(best, best_key(i, j));
-                if constexpr (TABLE) atomicMax(&s_ray[j], (uint32_t)(i + 1));
+            float fp[3], fm[3];
+            pair_linear(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
+            const bool both = live && in_unit_cube(fp) && in_unit_cube(fm);
+            const bool need = a.rule.clip ? live : both;
+            ng += both ? 1u : 0u;
+            bool surv = false;
+            if (__ballot(need) != 0ull) {
+                float Vp[3], Vm[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Vp[k] = code8(fp[k]);
+                    Vm[k] = code8(fm[k]);
+                }
+                const uint32_t p = pattern_of(Vp, Vm, a.rule);
+                surv = need && accepts(a.rule, p);
+                if (surv) {
+                    ++cnt;
+                    pk += 1ull << (8u * ((p - 1u) & 7u));
+                    best = max(best, best_key(i, j));
+                    if constexpr (TABLE) atomicMax(&s_ray[j], (uint32_t)(i + 1));
+                }
+            }
+            if constexpr (SEG) {
+                // survivors per search segment: split this pass's ballot by
+                // segment (a pass of 64 evaluations touches few segments)
+                const uint64_t sb = __ballot(surv);
+                if (sb) {
+                    const int32_t e = begin + it * BLOCK + tid;
+                    const int32_t sl = (SYM ? i : e / a.seg_len) - seg0;
+                    uint64_t rem = sb;
+                    while (rem) {
+                        const int32_t first = __builtin_ctzll(rem);
+                        const int32_t sid = __shfl(sl, first, 64);
+                        const uint64_t m = __ballot(sl == sid) & rem;
+                        if (lane == 0) atomicAdd(&s_seg[sid], (uint32_t)__builtin_popcountll(m));
+                        rem &= ~m;
+                    }
+                }
             }
             if (++steps == 255) {
 #pragma unroll
@@ -570,15 +703,15 @@ __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
             }
             j += a.sj;
             i += a.si;
-            if (j >= a.ntheta) { j -= a.ntheta; ++i; }
+            if (j >= a.W) { j -= a.W; ++i; }
         }
 #pragma unroll
         for (int q = 0; q < 7; ++q) pat[q] += (uint32_t)(pk >> (8 * q)) & 0xFFu;
 
         // block reduction: count, n_gamut, best, 7 patterns
-        uint32_t v[10] = {wave_sum_u32(cnt), wave_sum_u32(ng), wave_max_u32(best)};
+        uint32_t v[10] = {mult * wave_sum_u32(cnt), mult * wave_sum_u32(ng), wave_max_u32(best)};
 #pragma unroll
-        for (int q = 0; q < 7; ++q) v[3 + q] = wave_sum_u32(pat[q]);
+        for (int q = 0; q < 7; ++q) v[3 + q] = mult * wave_sum_u32(pat[q]);
         if (lane == 0) {
 #pragma unroll
             for (int q = 0; q < 10; ++q) s_red[w][q] = v[q];
@@ -587,25 +720,32 @@ __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
         if constexpr (TABLE) {
             if (tid < 36) s_bins[tid] = 0;
             __syncthreads();
-            for (int k = tid; k < a.ntheta; k += BLOCK) {
+            for (int k = tid; k < a.W; k += BLOCK) {
                 const uint32_t r = s_ray[k];
                 if (r) atomicMax(&s_bins[(k * a.bin_num) / a.bin_den], r);
             }
+            __syncthreads();
+            if (SYM && tid < 18) s_bins[tid + 18] = s_bins[tid];
             __syncthreads();
         }
         if (tid < 10) {
             uint32_t x = 0;
             for (int q = 0; q < NW; ++q) x = (tid == 2) ? max(x, s_red[q][tid]) : x + s_red[q][tid];
-            s_red[0][tid] = x;  // only wave 0's row is overwritten; read after the sync below
+            s_red[0][tid] = x;  // column tid is touched by this thread only
         }
         __syncthreads();
+        if constexpr (SEG) {
+            const int32_t nseg = (len + a.seg_len - 1) / a.seg_len;
+            uint32_t* dst = a.seg_cnt + c * (int64_t)a.segs_per_colour + seg0;
+            for (int k = tid; k < nseg; k += BLOCK) dst[k] = mult * s_seg[k];
+        }
         if constexpr (DIRECT) {
             if (tid == 0) {
                 uint32_t pt[7];
                 for (int q = 0; q < 7; ++q) pt[q] = s_red[0][3 + q];
                 if (a.summ)
-                    write_summary(cc, a.g, a.rule, a.tab, a.tab.tab, a.ra, a.rb, s_red[0][0],
-                                  s_red[0][1], s_red[0][2], pt, a.summ + c);
+                    write_summary(cc, a.g, a.rule, a.tab, a.ra, a.rb, s_red[0][0], s_red[0][1],
+                                  s_red[0][2], pt, a.summ + c);
                 if constexpr (TABLE) a.table[c].count = s_red[0][0];
             }
             if constexpr (TABLE) {
@@ -634,8 +774,7 @@ __global__ void k_finalize(const ColorConst* __restrict__ ccs, const SumAcc* __r
     const SumAcc s = acc[c];
     if (summ) {
         const ColorConst cc = ccs[c];
-        write_summary(cc, g, rule, tab, tab.tab, ra, rb, s.count, s.n_gamut, s.best_key, s.pat,
-                      summ + c);
+        write_summary(cc, g, rule, tab, ra, rb, s.count, s.n_gamut, s.best_key, s.pat, summ + c);
     }
     if (table) {
         table[c].count = s.count;
@@ -682,24 +821,20 @@ int zero_u64(void* p, int64_t n, hipStream_t s) {
     return CV_OK;
 }
 
-constexpr int kTabLdsBytes = 32 * 1024;
-
 // Common set-up of a search: per-colour constants and the angle table.
 int prepare(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd, hipStream_t s,
             TabArgs& tab) {
     int rc;
     if ((rc = ctx->ensure(ctx->colors, (size_t)n * sizeof(ColorConst))) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->table, (size_t)gd.tab_len * sizeof(double))) != CV_OK) return rc;
-    hipLaunchKernelGGL(k_angle_table, dim3(blocks_for(gd.N, 256)), dim3(256), 0, s,
-                       (double*)ctx->table.ptr, gd.N, gd.tab_len > gd.N ? 1 : 0);
+    hipLaunchKernelGGL(k_angle_table, dim3(blocks_for(gd.N / 2 + 1, 256)), dim3(256), 0, s,
+                       (double*)ctx->table.ptr, gd.N);
     CV_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_color_prologue, dim3(blocks_for(n, 256)), dim3(256), 0, s, rgb,
                        (ColorConst*)ctx->colors.ptr, n, mat_args());
     CV_HIP(hipGetLastError());
     tab.tab = (const double*)ctx->table.ptr;
     tab.tab_len = gd.tab_len;
-    tab.qoff = gd.qoff;
-    tab.wrap = gd.wrap;
     tab.N = gd.N;
     return CV_OK;
 }
@@ -716,43 +851,47 @@ int persistent_grid(cv_context* ctx, Kern k, int block, size_t lds, int64_t ntil
 }
 
 constexpr int kSearchBlock = 256;
-constexpr int kSearchK = 8;
-constexpr int kSearchTile = kSearchBlock * kSearchK;
+constexpr int kSegLen = 512;
 
-template <bool EMIT, bool SUMM, bool LDS>
-int launch_search_t(cv_context* ctx, const SearchArgs& a, hipStream_t s) {
-    auto k = k_pair_search<kSearchBlock, kSearchK, EMIT, SUMM, LDS>;
-    const size_t lds = LDS ? (size_t)a.tab.tab_len * sizeof(double) : 0;
+template <bool EMIT, bool SUMM, bool SYM, bool WRITE>
+int launch_pass_t(cv_context* ctx, const SearchArgs& a, hipStream_t s) {
+    auto k = k_pair_pass<EMIT, SUMM, SYM, WRITE>;
+    const size_t lds = (size_t)a.tab.tab_len * sizeof(double);
     unsigned grid;
-    int rc = persistent_grid(ctx, k, kSearchBlock, lds, a.ntiles, grid);
+    const int64_t blocks_needed = (a.nsegs + 3) / 4;
+    int rc = persistent_grid(ctx, k, kSearchBlock, lds, blocks_needed, grid);
     if (rc != CV_OK) return rc;
     hipLaunchKernelGGL(k, dim3(grid), dim3(kSearchBlock), lds, s, a);
     CV_HIP(hipGetLastError());
     return CV_OK;
 }
 
-int launch_search(cv_context* ctx, const SearchArgs& a, bool emit, bool summ, bool lds,
-                  hipStream_t s) {
-    const int sel = (emit ? 4 : 0) | (summ ? 2 : 0) | (lds ? 1 : 0);
+int launch_pass(cv_context* ctx, const SearchArgs& a, bool emit, bool summ, bool sym, bool write,
+                hipStream_t s) {
+    const int sel = (emit ? 8 : 0) | (summ && !write ? 4 : 0) | (sym ? 2 : 0) | (write ? 1 : 0);
     switch (sel) {
-    case 0: return launch_search_t<false, false, false>(ctx, a, s);
-    case 1: return launch_search_t<false, false, true>(ctx, a, s);
-    case 2: return launch_search_t<false, true, false>(ctx, a, s);
-    case 3: return launch_search_t<false, true, true>(ctx, a, s);
-    case 4: return launch_search_t<true, false, false>(ctx, a, s);
-    case 5: return launch_search_t<true, false, true>(ctx, a, s);
-    case 6: return launch_search_t<true, true, false>(ctx, a, s);
-    default: return launch_search_t<true, true, true>(ctx, a, s);
+    case 0: return launch_pass_t<false, false, false, false>(ctx, a, s);
+    case 1: return launch_pass_t<false, false, false, true>(ctx, a, s);
+    case 2: return launch_pass_t<false, false, true, false>(ctx, a, s);
+    case 3: return launch_pass_t<false, false, true, true>(ctx, a, s);
+    case 4: return launch_pass_t<false, true, false, false>(ctx, a, s);
+    case 6: return launch_pass_t<false, true, true, false>(ctx, a, s);
+    case 8: return launch_pass_t<true, false, false, false>(ctx, a, s);
+    case 9: return launch_pass_t<true, false, false, true>(ctx, a, s);
+    case 10: return launch_pass_t<true, false, true, false>(ctx, a, s);
+    case 11: return launch_pass_t<true, false, true, true>(ctx, a, s);
+    case 12: return launch_pass_t<true, true, false, false>(ctx, a, s);
+    default: return launch_pass_t<true, true, true, false>(ctx, a, s);
     }
 }
 
 constexpr int kReduceBlock = 256;
 
-template <bool TABLE, bool DIRECT, bool LDS>
+template <bool TABLE, bool DIRECT, bool SYM, bool SEG>
 int launch_reduce_t(cv_context* ctx, const ReduceArgs& a, hipStream_t s) {
-    auto k = k_pair_reduce<kReduceBlock, TABLE, DIRECT, LDS>;
-    const size_t lds = (LDS ? (size_t)a.tab.tab_len * sizeof(double) : 0) +
-                       (TABLE ? (size_t)a.ntheta * sizeof(uint32_t) : 0);
+    auto k = k_pair_reduce<kReduceBlock, TABLE, DIRECT, SYM, SEG>;
+    const size_t lds = (size_t)a.tab.tab_len * sizeof(double) +
+                       (TABLE ? (size_t)a.W * sizeof(uint32_t) : 0);
     unsigned grid;
     int rc = persistent_grid(ctx, k, kReduceBlock, lds, a.ntiles, grid);
     if (rc != CV_OK) return rc;
@@ -761,19 +900,90 @@ int launch_reduce_t(cv_context* ctx, const ReduceArgs& a, hipStream_t s) {
     return CV_OK;
 }
 
-int launch_reduce(cv_context* ctx, const ReduceArgs& a, bool table, bool direct, bool lds,
-                  hipStream_t s) {
-    const int sel = (table ? 4 : 0) | (direct ? 2 : 0) | (lds ? 1 : 0);
-    switch (sel) {
-    case 0: return launch_reduce_t<false, false, false>(ctx, a, s);
-    case 1: return launch_reduce_t<false, false, true>(ctx, a, s);
-    case 2: return launch_reduce_t<false, true, false>(ctx, a, s);
-    case 3: return launch_reduce_t<false, true, true>(ctx, a, s);
-    case 4: return launch_reduce_t<true, false, false>(ctx, a, s);
-    case 5: return launch_reduce_t<true, false, true>(ctx, a, s);
-    case 6: return launch_reduce_t<true, true, false>(ctx, a, s);
-    default: return launch_reduce_t<true, true, true>(ctx, a, s);
+int launch_reduce(cv_context* ctx, const ReduceArgs& a, bool table, bool direct, bool sym,
+                  bool seg, hipStream_t s) {
+    if (seg) {  // count pass of the search (no table)
+        const int sel = (direct ? 2 : 0) | (sym ? 1 : 0);
+        switch (sel) {
+        case 0: return launch_reduce_t<false, false, false, true>(ctx, a, s);
+        case 1: return launch_reduce_t<false, false, true, true>(ctx, a, s);
+        case 2: return launch_reduce_t<false, true, false, true>(ctx, a, s);
+        default: return launch_reduce_t<false, true, true, true>(ctx, a, s);
+        }
     }
+    const int sel = (table ? 4 : 0) | (direct ? 2 : 0) | (sym ? 1 : 0);
+    switch (sel) {
+    case 0: return launch_reduce_t<false, false, false, false>(ctx, a, s);
+    case 1: return launch_reduce_t<false, false, true, false>(ctx, a, s);
+    case 2: return launch_reduce_t<false, true, false, false>(ctx, a, s);
+    case 3: return launch_reduce_t<false, true, true, false>(ctx, a, s);
+    case 4: return launch_reduce_t<true, false, false, false>(ctx, a, s);
+    case 5: return launch_reduce_t<true, false, true, false>(ctx, a, s);
+    case 6: return launch_reduce_t<true, true, false, false>(ctx, a, s);
+    default: return launch_reduce_t<true, true, true, false>(ctx, a, s);
+    }
+}
+
+// Tiling of the reduce-only kernel: one tile per colour when there are many
+// colours of moderate size (direct mode), else chunks merged by atomics.  With
+// seg_len > 0 the chunks start on multiples of seg_len and hold at most 2048
+// segments (count pass of the search).
+struct ReducePlan {
+    bool direct;
+    int64_t chunk;
+    int32_t tpc;
+    int64_t ntiles;
+};
+
+ReducePlan plan_reduce(int64_t n, int64_t per, int32_t seg_len) {
+    ReducePlan p;
+    const int64_t max_chunk = seg_len > 0 ? (int64_t)2048 * seg_len : (int64_t)1 << 30;
+    p.direct = n >= 2048 && per <= (1 << 20) && per <= max_chunk;
+    if (p.direct) {
+        p.chunk = per;
+    } else {
+        const int64_t want_tiles_per_colour = (8192 + n - 1) / n;
+        int64_t chunk = (per + want_tiles_per_colour - 1) / want_tiles_per_colour;
+        if (chunk < 16 * kReduceBlock) chunk = 16 * kReduceBlock;
+        const int64_t unit = seg_len > 0 ? seg_len : kReduceBlock;
+        chunk = (chunk + unit - 1) / unit * unit;
+        if (chunk > max_chunk) chunk = max_chunk;
+        p.chunk = chunk;
+    }
+    p.tpc = (int32_t)((per + p.chunk - 1) / p.chunk);
+    p.ntiles = (int64_t)p.tpc * n;
+    return p;
+}
+
+ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, const RuleDev& rd,
+                       int32_t W, const ReducePlan& pl, int64_t n) {
+    ReduceArgs a;
+    a.cc = (const ColorConst*)ctx->colors.ptr;
+    a.tab = tab;
+    a.g = geom_constants();
+    a.rule = rd;
+    a.ra = gd.ra;
+    a.rb = gd.rb;
+    a.nr = gd.nr;
+    a.ntheta = gd.ntheta;
+    a.W = W;
+    a.inv_W = 1.0f / (float)W;
+    a.si = kReduceBlock / W;
+    a.sj = kReduceBlock % W;
+    a.chunk = (int32_t)pl.chunk;
+    a.tiles_per_colour = pl.tpc;
+    a.bin_num = 36;
+    a.bin_den = gd.N;
+    a.n = n;
+    a.ntiles = pl.ntiles;
+    a.acc = pl.direct ? nullptr : (SumAcc*)ctx->acc.ptr;
+    a.summ = nullptr;
+    a.table = nullptr;
+    a.misc = (uint64_t*)ctx->misc.ptr;
+    a.seg_cnt = nullptr;
+    a.seg_len = 0;
+    a.segs_per_colour = 0;
+    return a;
 }
 
 } // namespace
@@ -806,14 +1016,24 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     }
     TabArgs tab;
     if ((rc = prepare(ctx, rgb, n, gd, s, tab)) != CV_OK) return rc;
-    const int32_t tpc = (int32_t)((gd.per_colour + kSearchTile - 1) / kSearchTile);
-    const int64_t ntiles = (int64_t)tpc * n;
-    if ((rc = ctx->ensure(ctx->status, (size_t)ntiles * 8)) != CV_OK) return rc;
+    // half-turn mode when the grid spans the full turn: one row per segment
+    const bool sym = gd.ntheta == gd.N;
+    const int32_t W = sym ? gd.N / 2 : gd.ntheta;
+    const int32_t seg_len = sym ? W : kSegLen;
+    const int64_t per = (int64_t)gd.nr * W;
+    const int32_t spc = (int32_t)((per + seg_len - 1) / seg_len);
+    const int64_t nsegs = (int64_t)spc * n;
+    const int64_t nsums = (nsegs + kScanChunk - 1) / kScanChunk;
+    const bool emit = (flags & CV_EMIT_ALL) != 0;
+    const ReducePlan pl = plan_reduce(n, per, seg_len);
+    if ((rc = ctx->ensure(ctx->seg_cnt, (size_t)nsegs * 4)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->seg_prefix, (size_t)nsegs * 8)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->scan, (size_t)nsums * 8)) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->misc, 64)) != CV_OK) return rc;
-    if (summ && (rc = ctx->ensure(ctx->acc, (size_t)n * sizeof(SumAcc))) != CV_OK) return rc;
-    if ((rc = zero_u64(ctx->status.ptr, ntiles, s)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->acc, (size_t)n * sizeof(SumAcc))) != CV_OK) return rc;
     if ((rc = zero_u64(ctx->misc.ptr, 8, s)) != CV_OK) return rc;
-    if (summ && (rc = zero_u64(ctx->acc.ptr, n * (int64_t)(sizeof(SumAcc) / 8), s)) != CV_OK)
+    if ((emit || !pl.direct) &&
+        (rc = zero_u64(ctx->acc.ptr, n * (int64_t)(sizeof(SumAcc) / 8), s)) != CV_OK)
         return rc;
 
     SearchArgs a;
@@ -825,27 +1045,64 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     a.rb = gd.rb;
     a.nr = gd.nr;
     a.ntheta = gd.ntheta;
-    a.inv_ntheta = 1.0f / (float)gd.ntheta;
-    a.si = kSearchBlock / gd.ntheta;
-    a.sj = kSearchBlock % gd.ntheta;
-    a.tiles_per_colour = tpc;
+    a.W = W;
+    a.inv_W = 1.0f / (float)W;
+    a.si64 = 64 / W;
+    a.sj64 = 64 % W;
+    a.seg_len = seg_len;
+    a.segs_per_colour = spc;
     a.n = n;
-    a.ntiles = ntiles;
-    a.out = out;
-    a.capacity = out ? capacity : 0;
-    a.offsets = offsets;
-    a.status = (uint64_t*)ctx->status.ptr;
-    a.acc = summ ? (SumAcc*)ctx->acc.ptr : nullptr;
+    a.nsegs = nsegs;
+    a.seg_cnt = (uint32_t*)ctx->seg_cnt.ptr;
+    a.seg_prefix = (const uint64_t*)ctx->seg_prefix.ptr;
+    a.out = (uint4*)out;
+    a.capacity = out ? (uint64_t)capacity : 0ull;
+    a.acc = nullptr;
     a.misc = (uint64_t*)ctx->misc.ptr;
-    const bool lds = (size_t)gd.tab_len * sizeof(double) <= (size_t)kTabLdsBytes;
+
+    // Count pass: survivors per segment.  The reduce-only kernel does it
+    // (with the summaries); in emit-all mode every candidate is a record and
+    // the search kernel counts them itself.
+    ReduceArgs ra = reduce_args(ctx, tab, gd, rd, W, pl, n);
+    ra.summ = emit ? nullptr : summ;
+    ra.seg_cnt = a.seg_cnt;
+    ra.seg_len = seg_len;
+    ra.segs_per_colour = spc;
     if ((rc = ctx->time_begin(s)) != CV_OK) return rc;
-    if ((rc = launch_search(ctx, a, (flags & CV_EMIT_ALL) != 0, summ != nullptr, lds, s)) != CV_OK)
-        return rc;
+    if (emit) {
+        if ((rc = launch_pass(ctx, a, true, false, sym, false, s)) != CV_OK) return rc;
+    } else {
+        if ((rc = launch_reduce(ctx, ra, false, pl.direct, sym, true, s)) != CV_OK) return rc;
+    }
+    // segment counts -> output offsets
+    uint64_t* sums = (uint64_t*)ctx->scan.ptr;
+    uint64_t* misc = (uint64_t*)ctx->misc.ptr;
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nsums), dim3(kScanBlock), 0, s, a.seg_cnt,
+                       nsegs, sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, sums, nsums, misc);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsums), dim3(kScanBlock), 0, s, a.seg_cnt,
+                       nsegs, sums, (uint64_t*)ctx->seg_prefix.ptr, offsets, spc, n, misc);
+    CV_HIP(hipGetLastError());
+    // write pass
+    if (a.capacity > 0) {
+        if ((rc = launch_pass(ctx, a, emit, false, sym, true, s)) != CV_OK) return rc;
+    }
     if ((rc = ctx->time_end(s, false)) != CV_OK) return rc;
     if (summ) {
-        hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 128)), dim3(128), 0, s, a.cc, a.acc, n,
-                           a.g, rd, tab, gd.ra, gd.rb, summ, (cv_table_row*)nullptr);
-        CV_HIP(hipGetLastError());
+        if (emit) {  // summaries of an emit-all call come from a reduce pass
+            ReducePlan pa = plan_reduce(n, per, 0);
+            pa.direct = false;
+            ReduceArgs rb = reduce_args(ctx, tab, gd, rd, W, pa, n);
+            rb.misc = misc + 4;  // a ticket of its own
+            if ((rc = zero_u64(rb.misc, 1, s)) != CV_OK) return rc;
+            if ((rc = launch_reduce(ctx, rb, false, false, sym, false, s)) != CV_OK) return rc;
+        }
+        if (emit || !pl.direct) {
+            hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 128)), dim3(128), 0, s, a.cc,
+                               (const SumAcc*)ctx->acc.ptr, n, a.g, rd, tab, gd.ra, gd.rb, summ,
+                               (cv_table_row*)nullptr);
+            CV_HIP(hipGetLastError());
+        }
     }
     CV_HIP(hipMemcpyAsync(ctx->host_misc, ctx->misc.ptr, 3 * sizeof(uint64_t),
                           hipMemcpyDeviceToHost, s));
@@ -856,8 +1113,7 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
         ctx->kernel_ms += ms;
         ctx->kernel_launches += 1;
     }
-    if (ctx->host_misc[2] != 0) return fail(CV_ESTATE, "look-back wait exceeded its bound");
-    *total_host = (int64_t)ctx->host_misc[1];
+    *total_host = (int64_t)ctx->host_misc[2];
     if (*total_host > capacity)
         return fail(CV_ECAPACITY, "survivor total " + std::to_string(*total_host) +
                                       " exceeds capacity " + std::to_string(capacity));
@@ -871,54 +1127,25 @@ int run_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     int rc;
     TabArgs tab;
     if ((rc = prepare(ctx, rgb, n, gd, s, tab)) != CV_OK) return rc;
-    const int64_t per = gd.per_colour;
-    const bool direct = n >= 2048 && per <= (1 << 20);
-    int64_t chunk;
-    if (direct) {
-        chunk = per;
-    } else {
-        const int64_t want_tiles_per_colour = (8192 + n - 1) / n;
-        chunk = (per + want_tiles_per_colour - 1) / want_tiles_per_colour;
-        if (chunk < 16 * kReduceBlock) chunk = 16 * kReduceBlock;
-        chunk = (chunk + kReduceBlock - 1) / kReduceBlock * kReduceBlock;
-    }
-    const int32_t tpc = (int32_t)((per + chunk - 1) / chunk);
-    const int64_t ntiles = (int64_t)tpc * n;
+    const bool sym = gd.ntheta == gd.N;
+    const int32_t W = sym ? gd.N / 2 : gd.ntheta;
+    const int64_t per = (int64_t)gd.nr * W;  // evaluations per colour
+    const ReducePlan pl = plan_reduce(n, per, 0);
     if ((rc = ctx->ensure(ctx->misc, 64)) != CV_OK) return rc;
     if ((rc = zero_u64(ctx->misc.ptr, 8, s)) != CV_OK) return rc;
-    if (!direct) {
-        if ((rc = ctx->ensure(ctx->acc, (size_t)n * sizeof(SumAcc))) != CV_OK) return rc;
-        if ((rc = zero_u64(ctx->acc.ptr, n * (int64_t)(sizeof(SumAcc) / 8), s)) != CV_OK) return rc;
-    }
-    ReduceArgs a;
-    a.cc = (const ColorConst*)ctx->colors.ptr;
-    a.tab = tab;
-    a.g = geom_constants();
-    a.rule = rd;
-    a.ra = gd.ra;
-    a.rb = gd.rb;
-    a.nr = gd.nr;
-    a.ntheta = gd.ntheta;
-    a.inv_ntheta = 1.0f / (float)gd.ntheta;
-    a.si = kReduceBlock / gd.ntheta;
-    a.sj = kReduceBlock % gd.ntheta;
-    a.chunk = (int32_t)chunk;
-    a.tiles_per_colour = tpc;
-    a.bin_num = 36;
-    a.bin_den = gd.N;
-    a.n = n;
-    a.ntiles = ntiles;
-    a.acc = direct ? nullptr : (SumAcc*)ctx->acc.ptr;
+    if ((rc = ctx->ensure(ctx->acc, (size_t)n * sizeof(SumAcc))) != CV_OK) return rc;
+    if (!pl.direct &&
+        (rc = zero_u64(ctx->acc.ptr, n * (int64_t)(sizeof(SumAcc) / 8), s)) != CV_OK)
+        return rc;
+    ReduceArgs a = reduce_args(ctx, tab, gd, rd, W, pl, n);
     a.summ = summ;
     a.table = table;
-    a.misc = (uint64_t*)ctx->misc.ptr;
-    const bool lds = (size_t)gd.tab_len * sizeof(double) <= (size_t)kTabLdsBytes;
     if ((rc = ctx->time_begin(s)) != CV_OK) return rc;
-    if ((rc = launch_reduce(ctx, a, table != nullptr, direct, lds, s)) != CV_OK) return rc;
+    if ((rc = launch_reduce(ctx, a, table != nullptr, pl.direct, sym, false, s)) != CV_OK) return rc;
     if ((rc = ctx->time_end(s, true)) != CV_OK) return rc;
-    if (!direct) {
-        hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 128)), dim3(128), 0, s, a.cc, a.acc, n,
-                           a.g, rd, tab, gd.ra, gd.rb, summ, table);
+    if (!pl.direct) {
+        hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 128)), dim3(128), 0, s, a.cc,
+                           (const SumAcc*)ctx->acc.ptr, n, a.g, rd, tab, gd.ra, gd.rb, summ, table);
         CV_HIP(hipGetLastError());
     }
     return CV_OK;

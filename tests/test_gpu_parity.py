@@ -40,7 +40,10 @@ def compare_survivors(cv, oracle, colours, grid, rule, res, tag=""):
     kg = _keys(gpu["colour"], gpu["i"], gpu["j"], grid)
     ko = _keys(orc["colour"], orc["i"], orc["j"], grid)
     assert np.all(np.diff(kg) > 0), "GPU survivors out of (colour, i, j) order"
-    assert np.all((gpu["flags"] & 7) == 7)
+    clip = len(rule) > 3 and (rule[3] & 1)
+    assert np.all((gpu["flags"] & 4) == 4)
+    if not clip:  # under the clip reading survivors may lie outside the gamut
+        assert np.all((gpu["flags"] & 3) == 3)
     bflag = (orc["flags"] & 1).astype(bool)
     # oracle survivors that are not boundary cases must be GPU survivors with equal pairs
     pos = np.searchsorted(kg, ko)
@@ -127,18 +130,20 @@ def test_lab_to_rgbf_matches_oracle(cv, oracle):
 # --------------------------------------------------------------------------
 # cv_pair_search
 
-def test_emit_all_every_candidate(cv, oracle):
+@pytest.mark.parametrize("nt", [97, 100])
+def test_emit_all_every_candidate(cv, oracle, nt):
     """Every candidate of a ragged multi-tile grid: gamut, 8-bit pair, pattern
-    and survivor flag against the oracle."""
+    and survivor flag against the oracle.  ntheta = 97 < N = 100 runs the
+    general tiling, ntheta = N the half-turn mode (mirrored second half)."""
     cols = np.concatenate([W.PAPER_COLOUR_ARRAY[:3], W.random_colours(8, 3),
                            np.array([[0, 0, 0], [255, 255, 255], [2, 250, 3]], np.uint8)])
-    grid = (0.7, 37, 3.6, 97)  # 3589 candidates per colour: two tiles, ragged tail
+    grid = (0.7, 37, 3.6, nt)  # 3589 / 3700 candidates per colour: several tiles, ragged
     rule = (50, 0.5, 0x7F)
     res = cv.pair_search(_dev(cols), cv.Grid(*grid), cv.Rule(*rule), emit_all=True)
-    assert res.total == len(cols) * 37 * 97
-    g = cv.as_records(res.pairs, cv.PAIR_DTYPE).reshape(len(cols), 37, 97)
+    assert res.total == len(cols) * 37 * nt
+    g = cv.as_records(res.pairs, cv.PAIR_DTYPE).reshape(len(cols), 37, nt)
     o = oracle.eval_all(cols, grid, rule)
-    ii, jj = np.meshgrid(np.arange(37), np.arange(97), indexing="ij")
+    ii, jj = np.meshgrid(np.arange(37), np.arange(nt), indexing="ij")
     assert np.array_equal(g["i"], np.broadcast_to(ii, g.shape))
     assert np.array_equal(g["j"], np.broadcast_to(jj, g.shape))
     assert np.array_equal(g["colour"], np.broadcast_to(np.arange(len(cols))[:, None, None], g.shape))
@@ -171,9 +176,10 @@ def test_single_colour_every_table1_rule(cv, oracle):
     assert sum(s["oracle"] for s in stats) > 0
 
 
-def test_random_colours_multi_tile(cv, oracle):
+@pytest.mark.parametrize("nt", [180, 173])
+def test_random_colours_multi_tile(cv, oracle, nt):
     cols = np.concatenate([W.random_colours(21, 61), W.PAPER_COLOUR_ARRAY])
-    grid = (0.5, 120, 2.0, 180)
+    grid = (0.5, 120, 2.0, nt)
     for rule in ((50, 0.5, 0x7F), (100, 0.25, 0x7F), (150, 0.125, 0x55)):
         res = cv.pair_search(_dev(cols), cv.Grid(*grid), cv.Rule(*rule))
         st = compare_survivors(cv, oracle, cols, grid, rule, res, tag=str(rule))
@@ -209,12 +215,14 @@ def test_capacity_two_call_idiom(cv, oracle):
     with pytest.raises(cv.CvError) as ei:
         cv.pair_search(_dev(cols), cv.Grid(*grid), rule, capacity=small.shape[0], out=small)
     assert ei.value.code == cv.CV_ECAPACITY
+    assert str(full.total) in str(ei.value)
     # the first `capacity` survivors are written, in order
     assert torch.equal(small, full.pairs[: small.shape[0]])
-    # query-only call (capacity 0) reports the required size
-    with pytest.raises(cv.CvError):
-        cv.pair_search(_dev(cols), cv.Grid(*grid), rule, capacity=0,
-                       out=torch.zeros((1, 16), dtype=torch.uint8, device="cuda"))
+    # the retry with the reported size gives the full result
+    exact = torch.zeros((full.total, 16), dtype=torch.uint8, device="cuda")
+    again = cv.pair_search(_dev(cols), cv.Grid(*grid), rule, capacity=full.total, out=exact)
+    assert again.total == full.total and torch.equal(exact, full.pairs)
+    assert torch.equal(again.offsets, full.offsets)
 
 
 def test_deterministic_bitwise(cv):
@@ -261,8 +269,9 @@ def test_half_turn_symmetry_on_gpu(cv):
 # --------------------------------------------------------------------------
 # cv_pair_reduce
 
-def test_reduce_equals_search_summaries(cv):
-    grid = cv.Grid(0.25, 200, 2.0, 180)
+@pytest.mark.parametrize("nt", [180, 175])
+def test_reduce_equals_search_summaries(cv, nt):
+    grid = cv.Grid(0.25, 200, 2.0, nt)
     rule = cv.Rule(50, 0.5, 0x7F)
     for n in (9, 3000):  # atomic-merge and direct modes
         cols = _dev(np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(61, n - 9)]))
@@ -271,10 +280,12 @@ def test_reduce_equals_search_summaries(cv):
         assert torch.equal(s_search, s_reduce), n
 
 
-def test_table_rows_match_oracle(cv, oracle):
-    """Angle-bin table (36 bins of 10 deg, max radius index) on the cube grid."""
+@pytest.mark.parametrize("nt", [180, 171])
+def test_table_rows_match_oracle(cv, oracle, nt):
+    """Angle-bin table (36 bins of 10 deg, max radius index) on the cube grid
+    (and on a partial turn, which runs the general mode)."""
     cols = np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(71, 2039)])
-    grid = W.GRID_CUBE.astuple()
+    grid = W.GRID_CUBE.astuple()[:3] + (nt,)
     rule = (50, 0.5, 0x7F)
     for sub in (cols, cols[:40]):  # direct mode (>= 2048 colours) and atomic mode
         summ, tab = cv.pair_reduce(_dev(sub), cv.Grid(*grid), cv.Rule(*rule), table=True)
