@@ -4,11 +4,12 @@ Workload: the nine Table 1 colours, r = 0.01 .. 100 in steps of 0.01 (10,000
 radii) x theta = 0 .. 359.9 deg in steps of 0.1 deg (3,600 angles), rule
 V_th = 50, R_novib = 0.5, any pattern: 36 M candidate pairs per colour,
 324 M per step.  A step is one cv_pair_search call: per-colour prologue
-(RGB -> L*a*b*), the fused generate -> convert -> predicate -> compact kernel,
-and the per-colour summaries; inputs are resident in HBM before timing starts.
+(RGB -> L*a*b*), the evaluation (count) pass over every candidate with the
+per-colour summaries, the scan of segment counts and the write pass of the
+survivor list; inputs are resident in HBM before timing starts.
 
-Prints one JSON line (see the README of the measurement contract in the
-design notes).  `--gpus` above 1 is refused: this build measures one GPU.
+Prints one JSON line.  `--gpus` above 1 is refused: this build measures one
+GPU.
 """
 from __future__ import annotations
 
@@ -26,15 +27,19 @@ CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
 VALU_FMA_PEAK = CUS * SIMDS_PER_CU * LANES_PER_SIMD * 2 * CLOCK_HZ  # 78.6e12 flop/s
 HBM_PEAK = 8e12
 
-# Algorithmic floating-point work per candidate pair (FMA = 2 flops,
-# transcendental = 1; compares, selects, conversions and rounding not counted):
+# Algorithmic floating-point work of the evaluation kernel (FMA = 2 flops,
+# transcendental = 1; compares, selects, conversions and rounding not counted).
+# Per evaluated pair (when theta spans the full turn only rays j < N/2 are
+# evaluated: ray j + N/2 is the same pair with + and - swapped):
 #   displacement (i+1)*dr/500*sin, (i+1)*dr/200*cos ........ 4 mul      =  4
 #   f(X), f(Z) of both colours ............................. 4 add      =  4
 #   inverse companding, cube branch x4 ..................... 8 mul      =  8
 #   XYZ -> linear RGB, Y column hoisted, 2 colours x 3 ..... 12 fma     = 24
+# and, only for pairs with both colours in gamut (the others are decided):
 #   sRGB encode x6: log2, mul, exp2, fma ................... 6 x 5      = 30
 #   channel differences .................................... 3 sub      =  3
-FLOPS_PER_PAIR = 73
+FLOPS_GEOM = 40
+FLOPS_CODE = 33
 
 
 def parse():
@@ -99,25 +104,35 @@ def main():
     for _ in range(args.warmup):
         cv.pair_search(cols, grid, rule, out=out, ctx=ctx)
     ctx.set_timing(True)
-    ctx.kernel_time(reset=True)
+    for ph in (cv.CV_TIME_EVAL, cv.CV_TIME_WRITE, cv.CV_TIME_CALL):
+        ctx.kernel_time(ph, reset=True)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     t_wall = time.perf_counter()
     start.record()
-    total = 0
+    res = None
     for _ in range(args.steps):
-        total = cv.pair_search(cols, grid, rule, out=out, ctx=ctx).total
+        res = cv.pair_search(cols, grid, rule, out=out, ctx=ctx)
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
     ms = start.elapsed_time(stop)
-    k_ms, k_n = ctx.kernel_time(reset=True)
+    t_eval, n_eval = ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
+    t_write, n_write = ctx.kernel_time(cv.CV_TIME_WRITE, reset=True)
+    t_call, n_call = ctx.kernel_time(cv.CV_TIME_CALL, reset=True)
     ctx.set_timing(False)
+    total = res.total
+    summ = cv.as_records(res.summaries, cv.SUMMARY_DTYPE)
     ms_per_step = ms / args.steps
     value = pairs_per_step / (ms_per_step * 1e-3)
-    k_avg = k_ms / max(k_n, 1)
-    achieved = FLOPS_PER_PAIR * pairs_per_step / (k_avg * 1e-3)
+    half_turn = g.ntheta * g.dtheta_deg == 360.0
+    evals = pairs_per_step // 2 if half_turn else pairs_per_step
+    gamut_evals = int(summ["n_gamut"].sum()) // (2 if half_turn else 1)
+    flops = FLOPS_GEOM * evals + FLOPS_CODE * gamut_evals
+    k_eval = t_eval / max(n_eval, 1)
+    k_write = t_write / max(n_write, 1)
+    achieved = flops / (k_eval * 1e-3)
 
     res = {
         "metric": "candidate pairs evaluated/s + target colors resolved/s (exact vs surrogate)",
@@ -141,18 +156,23 @@ def main():
         },
         "colours_per_s_exact": len(W.PAPER_COLOUR_ARRAY) / (ms_per_step * 1e-3),
         "wall_s": wall,
+        "phases_ms": {"eval": k_eval, "write": k_write, "call": t_call / max(n_call, 1)},
         "roofline": {
             "bound": "alu",
-            "kernel": "k_pair_search",
+            "kernel": "k_pair_reduce (evaluation / count pass)",
             "achieved": achieved / 1e12,
             "peak": VALU_FMA_PEAK / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / VALU_FMA_PEAK,
             "traffic": None,
-            "kernel_ms": k_avg,
-            "flops_per_pair": FLOPS_PER_PAIR,
-            "survivor_write_GBps": 16.0 * total / (k_avg * 1e-3) / 1e9,
+            "kernel_ms": k_eval,
+            "flops_per_launch": flops,
+            "evaluated_pairs": evals,
+            "in_gamut_evaluations": gamut_evals,
         },
+        "write_pass": {"kernel": "k_pair_pass (write)", "ms": k_write,
+                       "GBps": 16.0 * total / (k_write * 1e-3) / 1e9 if k_write > 0 else None,
+                       "hbm_frac": 16.0 * total / (k_write * 1e-3) / HBM_PEAK if k_write > 0 else None},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -186,16 +186,25 @@ int cv_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
                    void* stream);
 
 /*
- * Kernel timing for measurement.  When enabled, the library brackets the
- * dominant kernel of cv_pair_search / cv_pair_reduce (the fused search or the
- * reduce-only search) with HIP events on the caller's stream and accumulates
- * their elapsed time.  cv_pair_reduce then synchronises its stream.
- * cv_context_kernel_time returns the accumulated milliseconds and launch
- * count (host pointers) and clears them when reset != 0.
- * Errors: CV_EINVAL (null ctx / outputs), CV_EHIP.
+ * Kernel timing for measurement.  When enabled, the library brackets its
+ * kernels with HIP events on the caller's stream and accumulates the elapsed
+ * time per phase:
+ *   CV_TIME_EVAL  - the evaluation kernel over every candidate (the reduce-only
+ *                   kernel; in cv_pair_search its count pass),
+ *   CV_TIME_WRITE - the write pass of cv_pair_search,
+ *   CV_TIME_CALL  - everything a cv_pair_search / cv_pair_reduce call enqueues
+ *                   after its set-up (evaluation, scan, write).
+ * While timing is on, cv_pair_reduce synchronises its stream.
+ * cv_context_kernel_time returns the accumulated milliseconds and the number
+ * of timed calls for one phase (host pointers) and clears that phase when
+ * reset != 0.  Errors: CV_EINVAL (null ctx / outputs, bad phase), CV_EHIP.
  */
+#define CV_TIME_EVAL 0
+#define CV_TIME_WRITE 1
+#define CV_TIME_CALL 2
 int cv_context_set_timing(cv_context* ctx, int on);
-int cv_context_kernel_time(cv_context* ctx, double* ms_host, int64_t* launches_host, int reset);
+int cv_context_kernel_time(cv_context* ctx, int phase, double* ms_host, int64_t* calls_host,
+                           int reset);
 
 #ifdef __cplusplus
 }

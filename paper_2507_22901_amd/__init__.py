@@ -28,6 +28,7 @@ CV_OK, CV_EINVAL, CV_ECAPACITY, CV_EHIP, CV_ENOMEM, CV_ESTATE = 0, -1, -2, -3, -
 CV_RGB8_TO_LAB, CV_LAB_TO_RGBF = 0, 1
 CV_EMIT_ALL = 0x1
 CV_RULE_CLIP = 0x1
+CV_TIME_EVAL, CV_TIME_WRITE, CV_TIME_CALL = 0, 1, 2
 
 _ERRNAMES = {CV_EINVAL: "CV_EINVAL", CV_ECAPACITY: "CV_ECAPACITY", CV_EHIP: "CV_EHIP",
              CV_ENOMEM: "CV_ENOMEM", CV_ESTATE: "CV_ESTATE"}
@@ -80,7 +81,8 @@ def lib() -> C.CDLL:
                                      P, P, C.POINTER(I64), C.c_uint32, P]
         L.cv_pair_reduce.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P]
         L.cv_context_set_timing.argtypes = [P, C.c_int]
-        L.cv_context_kernel_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(I64), C.c_int]
+        L.cv_context_kernel_time.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.POINTER(I64),
+                                             C.c_int]
         for name in EXPORTS:
             if name != "cv_last_error":
                 getattr(L, name).restype = C.c_int
@@ -136,10 +138,12 @@ class Context:
         """Bracket the dominant search kernel with HIP events on the call's stream."""
         _check(lib().cv_context_set_timing(self.handle, int(bool(on))))
 
-    def kernel_time(self, reset: bool = False):
-        """(accumulated kernel milliseconds, number of timed launches)."""
+    def kernel_time(self, phase: int = 0, reset: bool = False):
+        """(accumulated milliseconds, number of timed calls) of a phase:
+        CV_TIME_EVAL (0), CV_TIME_WRITE (1) or CV_TIME_CALL (2)."""
         ms, n = C.c_double(0.0), C.c_int64(0)
-        _check(lib().cv_context_kernel_time(self.handle, C.byref(ms), C.byref(n), int(reset)))
+        _check(lib().cv_context_kernel_time(self.handle, int(phase), C.byref(ms), C.byref(n),
+                                            int(reset)))
         return ms.value, n.value
 
     def close(self):

@@ -147,23 +147,22 @@ int cv_context::ensure(cvib::Buffer& b, size_t bytes) {
     return CV_OK;
 }
 
-int cv_context::time_begin(hipStream_t s) {
+int cv_context::mark(int phase, int end, hipStream_t s) {
     if (!timing) return CV_OK;
-    CV_HIP(hipEventRecord(ev0, s));
+    CV_HIP(hipEventRecord(ev[phase][end], s));
+    if (end) armed[phase] = true;
     return CV_OK;
 }
 
-// Records the end event; with sync, waits for it and accumulates the time
-// (otherwise the caller accumulates after its own synchronisation).
-int cv_context::time_end(hipStream_t s, bool sync) {
-    if (!timing) return CV_OK;
-    CV_HIP(hipEventRecord(ev1, s));
-    if (sync) {
-        CV_HIP(hipEventSynchronize(ev1));
+int cv_context::collect() {
+    for (int p = 0; p < 3; ++p) {
+        if (!armed[p]) continue;
         float ms = 0.0f;
-        CV_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-        kernel_ms += ms;
-        kernel_launches += 1;
+        CV_HIP(hipEventSynchronize(ev[p][1]));
+        CV_HIP(hipEventElapsedTime(&ms, ev[p][0], ev[p][1]));
+        kernel_ms[p] += ms;
+        kernel_calls[p] += 1;
+        armed[p] = false;
     }
     return CV_OK;
 }
@@ -236,8 +235,9 @@ int cv_context_destroy(cv_context* ctx) {
     for (cvib::Buffer* b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->host_misc) (void)hipHostFree(ctx->host_misc);
-    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
-    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    for (auto& pr : ctx->ev)
+        for (hipEvent_t e : pr)
+            if (e) (void)hipEventDestroy(e);
     delete ctx;
     return CV_OK;
     CV_GUARD_END
@@ -301,23 +301,25 @@ int cv_context_set_timing(cv_context* ctx, int on) {
     CV_GUARD_BEGIN
     if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
     DeviceGuard dg(ctx->device);
-    if (on && !ctx->ev0) {
-        CV_HIP(hipEventCreate(&ctx->ev0));
-        CV_HIP(hipEventCreate(&ctx->ev1));
+    if (on && !ctx->ev[0][0]) {
+        for (auto& pr : ctx->ev)
+            for (hipEvent_t& e : pr) CV_HIP(hipEventCreate(&e));
     }
     ctx->timing = on != 0;
     return CV_OK;
     CV_GUARD_END
 }
 
-int cv_context_kernel_time(cv_context* ctx, double* ms_host, int64_t* launches_host, int reset) {
+int cv_context_kernel_time(cv_context* ctx, int phase, double* ms_host, int64_t* calls_host,
+                           int reset) {
     CV_GUARD_BEGIN
-    if (!ctx || !ms_host || !launches_host) return fail(CV_EINVAL, "null argument");
-    *ms_host = ctx->kernel_ms;
-    *launches_host = ctx->kernel_launches;
+    if (!ctx || !ms_host || !calls_host) return fail(CV_EINVAL, "null argument");
+    if (phase < 0 || phase > 2) return fail(CV_EINVAL, "unknown timing phase");
+    *ms_host = ctx->kernel_ms[phase];
+    *calls_host = ctx->kernel_calls[phase];
     if (reset) {
-        ctx->kernel_ms = 0.0;
-        ctx->kernel_launches = 0;
+        ctx->kernel_ms[phase] = 0.0;
+        ctx->kernel_calls[phase] = 0;
     }
     return CV_OK;
     CV_GUARD_END

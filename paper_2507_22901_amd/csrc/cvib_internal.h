@@ -55,6 +55,9 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
 int run_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
                     const RuleDev& rd, cv_color_summary* summ, cv_table_row* table,
                     hipStream_t s);
+int run_scan_counts(cv_context* ctx, const uint32_t* cnt, int64_t T, uint64_t* prefix,
+                    int64_t* offsets, int32_t spc, int64_t n, uint64_t* total, hipStream_t s);
+Geom geom_constants();
 
 } // namespace cvib
 
@@ -69,12 +72,13 @@ struct cv_context {
     cvib::Buffer acc;         // per-colour accumulators
     cvib::Buffer misc;        // ticket, -, survivor total
     uint64_t* host_misc = nullptr; // pinned mirror of misc for the total
-    // kernel timing (cv_context_set_timing)
+    // kernel timing (cv_context_set_timing): event pairs and totals per phase
     bool timing = false;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    double kernel_ms = 0.0;
-    int64_t kernel_launches = 0;
+    hipEvent_t ev[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+    bool armed[3] = {false, false, false};
+    double kernel_ms[3] = {0.0, 0.0, 0.0};
+    int64_t kernel_calls[3] = {0, 0, 0};
     int ensure(cvib::Buffer& b, size_t bytes);
-    int time_begin(hipStream_t s);
-    int time_end(hipStream_t s, bool sync);
+    int mark(int phase, int end, hipStream_t s);  // record a phase's start / end event
+    int collect();                                // after a sync: add armed phases
 };

@@ -1,0 +1,195 @@
+// Device helpers shared by the library's kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "../../include/cvib.h"
+#include "cvib_device.h"
+
+namespace cvib {
+
+// ---------------------------------------------------------------------------
+// Small wave-level helpers (wave64).
+
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// A value known to be equal in every lane, moved to a scalar register.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// sRGB decode and L* companding in FP64 (per colour, not on the hot loop).
+
+__device__ __forceinline__ double decode_srgb(double c) {
+    return c <= 0.04045 ? c / 12.92 : pow((c + 0.055) / 1.055, 2.4);
+}
+
+__device__ __forceinline__ double lab_f(double t) {
+    const double d3 = kDelta * kDelta * kDelta;
+    return t > d3 ? cbrt(t) : t / kLinSlope + 4.0 / 29.0;
+}
+
+struct MatArgs {
+    double M[9];    // linear RGB -> XYZ
+    double Minv[9]; // XYZ -> linear RGB
+    double W[3];    // white point
+};
+
+__device__ __forceinline__ void rgb8_lab(const MatArgs& m, const uint8_t* p, double lab[3]) {
+    double lin[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lin[k] = decode_srgb((double)p[k] / 255.0);
+    double f[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        double x = m.M[3 * r] * lin[0] + m.M[3 * r + 1] * lin[1] + m.M[3 * r + 2] * lin[2];
+        f[r] = lab_f(x / m.W[r]);
+    }
+    lab[0] = 116.0 * f[1] - 16.0;
+    lab[1] = 500.0 * (f[0] - f[1]);
+    lab[2] = 200.0 * (f[1] - f[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Angle table.  theta_j = 360 j / N degrees.  sin(2 pi m / N) is evaluated
+// after folding m with exact integer steps: the half-turn fold makes
+// tab[j + N/2] = -tab[j] bitwise (so the + and - colours of ray j are the -
+// and + colours of ray j + N/2), the pi - x fold keeps the argument within a
+// quarter turn, and when 8 | N the octant fold keeps it within 45 degrees.
+
+__device__ inline double sin_turn(int64_t m, int64_t N) {
+    m %= N;
+    if (m < 0) m += N;
+    double sgn = 1.0;
+    if (2 * m >= N) { m -= N / 2; sgn = -1.0; }
+    if (4 * m > N) m = N / 2 - m;
+    if (N % 8 == 0 && 8 * m > N) return sgn * cos((double)(N / 4 - m) * (2.0 * M_PI / (double)N));
+    return sgn * sin((double)m * (2.0 * M_PI / (double)N));
+}
+
+__device__ inline double cos_turn(int64_t m, int64_t N) {
+    m %= N;
+    if (m < 0) m += N;
+    double sgn = 1.0;
+    if (2 * m >= N) { m -= N / 2; sgn = -sgn; }
+    if (4 * m > N) { m = N / 2 - m; sgn = -sgn; }
+    if (N % 8 == 0 && 8 * m > N) return sgn * sin((double)(N / 4 - m) * (2.0 * M_PI / (double)N));
+    return sgn * cos((double)m * (2.0 * M_PI / (double)N));
+}
+
+// ---------------------------------------------------------------------------
+// Shared pieces of the search kernels.
+
+struct SumAcc {            // per-colour accumulators (zeroed before a launch)
+    uint32_t count, n_gamut, best_key, _pad;
+    uint32_t pat[7], _pad2;
+    uint32_t bins[36];
+};
+static_assert(sizeof(SumAcc) == 192, "SumAcc layout");
+
+struct TabArgs {
+    const double* tab;
+    int32_t tab_len;  // doubles in the table
+    int32_t N;        // angles per full turn
+};
+
+// sin and cos of theta_j = 2 pi j / N (0 <= j < N) from the folded table.
+// The folds are exact integer steps, so ray j + N/2 reads the negated values
+// of ray j bit for bit.
+__device__ __forceinline__ void sincos_j(const double* tab, int32_t N, int32_t j, double& s,
+                                         double& c) {
+    const int32_t H = N >> 1;
+    const bool back = j >= H;          // second half-turn: negate both
+    const int32_t jj = back ? j - H : j;
+    if ((N & 3) == 0) {
+        const int32_t Q = N >> 2;
+        const bool lo = jj <= Q;
+        const double a = tab[lo ? jj : H - jj];  // sin(jj) = sin(pi - jj)
+        const double b = tab[lo ? Q - jj : jj - Q];
+        s = back ? -a : a;
+        const double cc = lo ? b : -b;            // cos(jj) = -sin(jj - pi/2)
+        c = back ? -cc : cc;
+    } else {
+        const double a = tab[jj], b = tab[H + 1 + jj];
+        s = back ? -a : a;
+        c = back ? -b : b;
+    }
+}
+
+// Key of the maximum-amplitude pair: larger i wins, then smaller j.  0 = none.
+__device__ __forceinline__ uint32_t best_key(int32_t i, int32_t j) {
+    return ((uint32_t)i << 16) | (0xFFFFu - (uint32_t)j);
+}
+
+// Split x (< 2^24) by d using an FP32 reciprocal and one correction step.
+__device__ __forceinline__ void divmod_small(int32_t x, int32_t d, float inv_d, int32_t& q,
+                                             int32_t& r) {
+    q = (int32_t)((float)x * inv_d);
+    r = x - q * d;
+    if (r < 0) { --q; r += d; }
+    if (r >= d) { ++q; r -= d; }
+}
+
+__device__ __forceinline__ void write_summary(const ColorConst& cc, const Geom& g,
+                                              const RuleDev& rule, const TabArgs& tab,
+                                              double ra, double rb, uint32_t count, uint32_t ng,
+                                              uint32_t key, const uint32_t pat[7],
+                                              cv_color_summary* out) {
+    cv_color_summary s;
+    s.count = count;
+    s.n_gamut = ng;
+    s.best_i = 0xFFFF;
+    s.best_j = 0;
+    for (int k = 0; k < 3; ++k) s.best_plus[k] = s.best_minus[k] = 0;
+    s.best_p = 0;
+    s._pad = 0;
+    for (int p = 0; p < 7; ++p) s.per_pattern[p] = pat[p];
+    if (key) {
+        const int32_t i = (int32_t)(key >> 16), j = (int32_t)(0xFFFFu - (key & 0xFFFFu));
+        double sn, co;
+        sincos_j(tab.tab, tab.N, j, sn, co);
+        const double rr = (double)(i + 1);
+        PairEval e;
+        eval_pair(cc, g, (rr * ra) * sn, (rr * rb) * co, e);
+        s.best_i = (uint16_t)i;
+        s.best_j = (uint16_t)j;
+        for (int k = 0; k < 3; ++k) {
+            s.best_plus[k] = (uint8_t)e.Vp[k];
+            s.best_minus[k] = (uint8_t)e.Vm[k];
+        }
+        s.best_p = (uint8_t)pattern_of(e.Vp, e.Vm, rule);
+    }
+    *out = s;
+}
+
+} // namespace cvib

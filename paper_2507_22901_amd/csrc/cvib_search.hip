@@ -11,79 +11,9 @@
 #include <stdint.h>
 
 #include "cvib_internal.h"
+#include "cvib_kernels.h"
 
 namespace cvib {
-
-// ---------------------------------------------------------------------------
-// Small wave-level helpers (wave64).
-
-__device__ __forceinline__ uint32_t lane_id() {
-    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-}
-
-// A value known to be equal in every lane, moved to a scalar register.
-__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// Number of set bits of `mask` below this lane.
-__device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// ---------------------------------------------------------------------------
-// sRGB decode and L* companding in FP64 (per colour, not on the hot loop).
-
-__device__ __forceinline__ double decode_srgb(double c) {
-    return c <= 0.04045 ? c / 12.92 : pow((c + 0.055) / 1.055, 2.4);
-}
-
-__device__ __forceinline__ double lab_f(double t) {
-    const double d3 = kDelta * kDelta * kDelta;
-    return t > d3 ? cbrt(t) : t / kLinSlope + 4.0 / 29.0;
-}
-
-struct MatArgs {
-    double M[9];    // linear RGB -> XYZ
-    double Minv[9]; // XYZ -> linear RGB
-    double W[3];    // white point
-};
-
-__device__ __forceinline__ void rgb8_lab(const MatArgs& m, const uint8_t* p, double lab[3]) {
-    double lin[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) lin[k] = decode_srgb((double)p[k] / 255.0);
-    double f[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        double x = m.M[3 * r] * lin[0] + m.M[3 * r + 1] * lin[1] + m.M[3 * r + 2] * lin[2];
-        f[r] = lab_f(x / m.W[r]);
-    }
-    lab[0] = 116.0 * f[1] - 16.0;
-    lab[1] = 500.0 * (f[0] - f[1]);
-    lab[2] = 200.0 * (f[1] - f[2]);
-}
 
 // CV_RGB8_TO_LAB
 __global__ void k_rgb8_to_lab(const uint8_t* __restrict__ rgb, float* __restrict__ lab, int64_t n,
@@ -140,33 +70,6 @@ __global__ void k_color_prologue(const uint8_t* __restrict__ rgb, ColorConst* __
     cc[k] = c;
 }
 
-// ---------------------------------------------------------------------------
-// Angle table.  theta_j = 360 j / N degrees.  sin(2 pi m / N) is evaluated
-// after folding m with exact integer steps: the half-turn fold makes
-// tab[j + N/2] = -tab[j] bitwise (so the + and - colours of ray j are the -
-// and + colours of ray j + N/2), the pi - x fold keeps the argument within a
-// quarter turn, and when 8 | N the octant fold keeps it within 45 degrees.
-
-__device__ double sin_turn(int64_t m, int64_t N) {
-    m %= N;
-    if (m < 0) m += N;
-    double sgn = 1.0;
-    if (2 * m >= N) { m -= N / 2; sgn = -1.0; }
-    if (4 * m > N) m = N / 2 - m;
-    if (N % 8 == 0 && 8 * m > N) return sgn * cos((double)(N / 4 - m) * (2.0 * M_PI / (double)N));
-    return sgn * sin((double)m * (2.0 * M_PI / (double)N));
-}
-
-__device__ double cos_turn(int64_t m, int64_t N) {
-    m %= N;
-    if (m < 0) m += N;
-    double sgn = 1.0;
-    if (2 * m >= N) { m -= N / 2; sgn = -sgn; }
-    if (4 * m > N) { m = N / 2 - m; sgn = -sgn; }
-    if (N % 8 == 0 && 8 * m > N) return sgn * sin((double)(N / 4 - m) * (2.0 * M_PI / (double)N));
-    return sgn * cos((double)m * (2.0 * M_PI / (double)N));
-}
-
 // Table layout.  N % 4 == 0: tab[k] = sin(2 pi k / N) for 0 <= k <= N/4 (a
 // quarter turn).  N % 4 == 2: tab[k] = sin, tab[H + 1 + k] = cos of
 // 2 pi k / N for 0 <= k <= H = N/2 (a half turn).
@@ -181,59 +84,6 @@ __global__ void k_angle_table(double* __restrict__ tab, int32_t N) {
             tab[H + 1 + k] = cos_turn(k, N);
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// Shared pieces of the search kernels.
-
-struct SumAcc {            // per-colour accumulators (zeroed before a launch)
-    uint32_t count, n_gamut, best_key, _pad;
-    uint32_t pat[7], _pad2;
-    uint32_t bins[36];
-};
-static_assert(sizeof(SumAcc) == 192, "SumAcc layout");
-
-struct TabArgs {
-    const double* tab;
-    int32_t tab_len;  // doubles in the table
-    int32_t N;        // angles per full turn
-};
-
-// sin and cos of theta_j = 2 pi j / N (0 <= j < N) from the folded table.
-// The folds are exact integer steps, so ray j + N/2 reads the negated values
-// of ray j bit for bit.
-__device__ __forceinline__ void sincos_j(const double* tab, int32_t N, int32_t j, double& s,
-                                         double& c) {
-    const int32_t H = N >> 1;
-    const bool back = j >= H;          // second half-turn: negate both
-    const int32_t jj = back ? j - H : j;
-    if ((N & 3) == 0) {
-        const int32_t Q = N >> 2;
-        const bool lo = jj <= Q;
-        const double a = tab[lo ? jj : H - jj];  // sin(jj) = sin(pi - jj)
-        const double b = tab[lo ? Q - jj : jj - Q];
-        s = back ? -a : a;
-        const double cc = lo ? b : -b;            // cos(jj) = -sin(jj - pi/2)
-        c = back ? -cc : cc;
-    } else {
-        const double a = tab[jj], b = tab[H + 1 + jj];
-        s = back ? -a : a;
-        c = back ? -b : b;
-    }
-}
-
-// Key of the maximum-amplitude pair: larger i wins, then smaller j.  0 = none.
-__device__ __forceinline__ uint32_t best_key(int32_t i, int32_t j) {
-    return ((uint32_t)i << 16) | (0xFFFFu - (uint32_t)j);
-}
-
-// Split x (< 2^24) by d using an FP32 reciprocal and one correction step.
-__device__ __forceinline__ void divmod_small(int32_t x, int32_t d, float inv_d, int32_t& q,
-                                             int32_t& r) {
-    q = (int32_t)((float)x * inv_d);
-    r = x - q * d;
-    if (r < 0) { --q; r += d; }
-    if (r >= d) { ++q; r -= d; }
 }
 
 struct SearchArgs {
@@ -496,7 +346,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_sums(const uint32_t* __rest
 
 // Exclusive scan of the per-block sums by a single block.
 __global__ __launch_bounds__(kScanBlock) void k_scan_top(uint64_t* __restrict__ sums, int64_t B,
-                                                         uint64_t* __restrict__ misc) {
+                                                         uint64_t* __restrict__ total_out) {
     __shared__ uint64_t s_w[kScanBlock / 64];
     uint64_t carry = 0;
     for (int64_t b0 = 0; b0 < B; b0 += kScanBlock) {
@@ -507,7 +357,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(uint64_t* __restrict__ 
         if (b < B) sums[b] = carry + ex;
         carry += total;
     }
-    if (threadIdx.x == 0) misc[2] = carry; // survivor total
+    if (threadIdx.x == 0) *total_out = carry;
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const uint32_t* __restrict__ cnt,
@@ -516,7 +366,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const uint32_t* __res
                                                            uint64_t* __restrict__ prefix,
                                                            int64_t* __restrict__ offsets,
                                                            int32_t segs_per_colour, int64_t n,
-                                                           const uint64_t* __restrict__ misc) {
+                                                           const uint64_t* __restrict__ grand) {
     __shared__ uint64_t s_w[kScanBlock / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
     uint64_t v = 0;
@@ -531,7 +381,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const uint32_t* __res
         if (offsets && t % segs_per_colour == 0) offsets[t / segs_per_colour] = (int64_t)run;
         run += cnt[t];
     }
-    if (offsets && blockIdx.x == 0 && threadIdx.x == 0) offsets[n] = (int64_t)misc[2];
+    if (offsets && blockIdx.x == 0 && threadIdx.x == 0) offsets[n] = (int64_t)*grand;
 }
 
 // ---------------------------------------------------------------------------
@@ -563,38 +413,6 @@ struct ReduceArgs {
     int32_t seg_len;          // SEG: evaluations per segment (chunk is a multiple)
     int32_t segs_per_colour;  // SEG
 };
-
-__device__ __forceinline__ void write_summary(const ColorConst& cc, const Geom& g,
-                                              const RuleDev& rule, const TabArgs& tab,
-                                              double ra, double rb, uint32_t count, uint32_t ng,
-                                              uint32_t key, const uint32_t pat[7],
-                                              cv_color_summary* out) {
-    cv_color_summary s;
-    s.count = count;
-    s.n_gamut = ng;
-    s.best_i = 0xFFFF;
-    s.best_j = 0;
-    for (int k = 0; k < 3; ++k) s.best_plus[k] = s.best_minus[k] = 0;
-    s.best_p = 0;
-    s._pad = 0;
-    for (int p = 0; p < 7; ++p) s.per_pattern[p] = pat[p];
-    if (key) {
-        const int32_t i = (int32_t)(key >> 16), j = (int32_t)(0xFFFFu - (key & 0xFFFFu));
-        double sn, co;
-        sincos_j(tab.tab, tab.N, j, sn, co);
-        const double rr = (double)(i + 1);
-        PairEval e;
-        eval_pair(cc, g, (rr * ra) * sn, (rr * rb) * co, e);
-        s.best_i = (uint16_t)i;
-        s.best_j = (uint16_t)j;
-        for (int k = 0; k < 3; ++k) {
-            s.best_plus[k] = (uint8_t)e.Vp[k];
-            s.best_minus[k] = (uint8_t)e.Vm[k];
-        }
-        s.best_p = (uint8_t)pattern_of(e.Vp, e.Vm, rule);
-    }
-    *out = s;
-}
 
 // Reduce-only search.  A tile is a chunk of one colour's evaluations (i, j < W)
 // in row-major order: the whole colour when it fits (results are then written
@@ -988,6 +806,25 @@ ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, c
 
 } // namespace
 
+// Exclusive scan of per-unit counts into 64-bit offsets (unit order); the
+// total goes to *total (device) and, if offsets is given, every spc-th unit's
+// offset to offsets[unit / spc] and the total to offsets[n].
+int run_scan_counts(cv_context* ctx, const uint32_t* cnt, int64_t T, uint64_t* prefix,
+                    int64_t* offsets, int32_t spc, int64_t n, uint64_t* total, hipStream_t s) {
+    const int64_t nsums = (T + kScanChunk - 1) / kScanChunk;
+    int rc;
+    if ((rc = ctx->ensure(ctx->scan, (size_t)(nsums > 0 ? nsums : 1) * 8)) != CV_OK) return rc;
+    uint64_t* sums = (uint64_t*)ctx->scan.ptr;
+    if (nsums > 0)
+        hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nsums), dim3(kScanBlock), 0, s, cnt, T, sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, sums, nsums, total);
+    if (nsums > 0)
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsums), dim3(kScanBlock), 0, s, cnt, T, sums,
+                           prefix, offsets, spc, n, (const uint64_t*)total);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
 int run_lab_convert(cv_context* ctx, const void* in, void* out, int64_t n, int dir,
                     hipStream_t s) {
     (void)ctx;
@@ -1023,12 +860,10 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     const int64_t per = (int64_t)gd.nr * W;
     const int32_t spc = (int32_t)((per + seg_len - 1) / seg_len);
     const int64_t nsegs = (int64_t)spc * n;
-    const int64_t nsums = (nsegs + kScanChunk - 1) / kScanChunk;
     const bool emit = (flags & CV_EMIT_ALL) != 0;
     const ReducePlan pl = plan_reduce(n, per, seg_len);
     if ((rc = ctx->ensure(ctx->seg_cnt, (size_t)nsegs * 4)) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->seg_prefix, (size_t)nsegs * 8)) != CV_OK) return rc;
-    if ((rc = ctx->ensure(ctx->scan, (size_t)nsums * 8)) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->misc, 64)) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->acc, (size_t)n * sizeof(SumAcc))) != CV_OK) return rc;
     if ((rc = zero_u64(ctx->misc.ptr, 8, s)) != CV_OK) return rc;
@@ -1068,26 +903,26 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     ra.seg_cnt = a.seg_cnt;
     ra.seg_len = seg_len;
     ra.segs_per_colour = spc;
-    if ((rc = ctx->time_begin(s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
     if (emit) {
         if ((rc = launch_pass(ctx, a, true, false, sym, false, s)) != CV_OK) return rc;
     } else {
         if ((rc = launch_reduce(ctx, ra, false, pl.direct, sym, true, s)) != CV_OK) return rc;
     }
+    if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
     // segment counts -> output offsets
-    uint64_t* sums = (uint64_t*)ctx->scan.ptr;
     uint64_t* misc = (uint64_t*)ctx->misc.ptr;
-    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nsums), dim3(kScanBlock), 0, s, a.seg_cnt,
-                       nsegs, sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, sums, nsums, misc);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsums), dim3(kScanBlock), 0, s, a.seg_cnt,
-                       nsegs, sums, (uint64_t*)ctx->seg_prefix.ptr, offsets, spc, n, misc);
-    CV_HIP(hipGetLastError());
+    if ((rc = run_scan_counts(ctx, a.seg_cnt, nsegs, (uint64_t*)ctx->seg_prefix.ptr, offsets, spc,
+                              n, misc + 2, s)) != CV_OK)
+        return rc;
     // write pass
     if (a.capacity > 0) {
+        if ((rc = ctx->mark(CV_TIME_WRITE, 0, s)) != CV_OK) return rc;
         if ((rc = launch_pass(ctx, a, emit, false, sym, true, s)) != CV_OK) return rc;
+        if ((rc = ctx->mark(CV_TIME_WRITE, 1, s)) != CV_OK) return rc;
     }
-    if ((rc = ctx->time_end(s, false)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
     if (summ) {
         if (emit) {  // summaries of an emit-all call come from a reduce pass
             ReducePlan pa = plan_reduce(n, per, 0);
@@ -1107,12 +942,7 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     CV_HIP(hipMemcpyAsync(ctx->host_misc, ctx->misc.ptr, 3 * sizeof(uint64_t),
                           hipMemcpyDeviceToHost, s));
     CV_HIP(hipStreamSynchronize(s));
-    if (ctx->timing) {
-        float ms = 0.0f;
-        CV_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-        ctx->kernel_ms += ms;
-        ctx->kernel_launches += 1;
-    }
+    if ((rc = ctx->collect()) != CV_OK) return rc;
     *total_host = (int64_t)ctx->host_misc[2];
     if (*total_host > capacity)
         return fail(CV_ECAPACITY, "survivor total " + std::to_string(*total_host) +
@@ -1140,14 +970,17 @@ int run_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     ReduceArgs a = reduce_args(ctx, tab, gd, rd, W, pl, n);
     a.summ = summ;
     a.table = table;
-    if ((rc = ctx->time_begin(s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
     if ((rc = launch_reduce(ctx, a, table != nullptr, pl.direct, sym, false, s)) != CV_OK) return rc;
-    if ((rc = ctx->time_end(s, true)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
     if (!pl.direct) {
         hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 128)), dim3(128), 0, s, a.cc,
                            (const SumAcc*)ctx->acc.ptr, n, a.g, rd, tab, gd.ra, gd.rb, summ, table);
         CV_HIP(hipGetLastError());
     }
+    if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
+    if (ctx->timing && (rc = ctx->collect()) != CV_OK) return rc;
     return CV_OK;
 }
 
