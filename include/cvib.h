@@ -130,6 +130,23 @@ typedef struct {
     uint8_t bin_ridx[36];
 } cv_table_row;
 
+/*
+ * Best pair of one information pattern for one colour, 12 bytes: the
+ * maximum-amplitude survivor (largest i, then smallest j) whose pattern is
+ * p.  flags bit0 = a pair exists (all other fields zero otherwise).
+ */
+typedef struct {
+    uint16_t i, j;
+    uint8_t plus[3], minus[3];
+    uint8_t pattern;
+    uint8_t flags;
+} cv_pattern_pair;
+
+/* ---- cv_frames_resolve flags ----------------------------------------- */
+#define CV_GRAPH 0x2u     /* capture the whole call once as a hipGraph (on a */
+                          /* stream of the context) and replay it; the graph */
+                          /* is rebuilt when any argument changes            */
+
 typedef struct cv_context cv_context;
 
 /* Create a context on HIP device `device`.  *out receives the handle.
@@ -184,6 +201,40 @@ int cv_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
 int cv_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,
                    const cv_rule* rule, cv_color_summary* summ, cv_table_row* table,
                    void* stream);
+
+/*
+ * Batched frames (all device arrays).  The colours of npix pixels (uint8
+ * [npix][3], e.g. several frames back to back) are de-duplicated: `colours`
+ * receives the distinct colours in ascending R<<16|G<<8|B order (uint8
+ * [colour_cap][3]), *ncolours (a DEVICE int64) their number and pixel_index
+ * (uint32 [npix]) each pixel's position in that list.  Every distinct colour
+ * is then searched on `grid` under `rule` in one persistent launch whose
+ * colour count stays on the device: summ (cv_color_summary [colour_cap],
+ * nullable), pbest (cv_pattern_pair [colour_cap][7]: the best pair of every
+ * information pattern) and rays (uint16 [colour_cap][ntheta], nullable: per
+ * ray the largest surviving radius index + 1, 0 = none).  If frame_a and
+ * frame_b are given (uint8 [npix][3] each), they receive the two colours
+ * that alternate on the display (Fig. 1a): for pixel k the pair of pattern
+ * info[k] (1..7) of its colour, or, with info NULL or info[k] = 0, the
+ * colour's maximum-amplitude pair (info[k] > 7 selects none); a pixel
+ * without such a pair keeps its colour in both frames.  *resolved (DEVICE
+ * int64, nullable; needs the frames) counts the pixels that received a pair.
+ * Nothing is copied to the host: the call is asynchronous, and with CV_GRAPH
+ * it is one graph launch (captured again when an argument changes or a
+ * context workspace had to grow).  The caller owns every array; the context
+ * owns a 2^24-bit colour bitmap and its scan (about 8 MiB).
+ * Requirements: colour_cap >= min(npix, 2^24); the angle table (8 * (N/4 + 1)
+ * bytes when N % 4 == 0, else 16 * (N/2 + 1)) plus, with rays, 4 bytes per
+ * evaluated ray (ntheta, or N/2 when theta spans the full turn) must fit in
+ * one block's LDS.
+ * Errors: CV_EINVAL, CV_EHIP, CV_ENOMEM.
+ */
+int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, const uint8_t* info,
+                      const cv_grid* grid, const cv_rule* rule, uint8_t* colours,
+                      int64_t colour_cap, int64_t* ncolours, uint32_t* pixel_index,
+                      cv_color_summary* summ, cv_pattern_pair* pbest, uint16_t* rays,
+                      uint8_t* frame_a, uint8_t* frame_b, int64_t* resolved, uint32_t flags,
+                      void* stream);
 
 /*
  * Kernel timing for measurement.  When enabled, the library brackets its

@@ -27,6 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libcvib.so")
 CV_OK, CV_EINVAL, CV_ECAPACITY, CV_EHIP, CV_ENOMEM, CV_ESTATE = 0, -1, -2, -3, -4, -5
 CV_RGB8_TO_LAB, CV_LAB_TO_RGBF = 0, 1
 CV_EMIT_ALL = 0x1
+CV_GRAPH = 0x2
 CV_RULE_CLIP = 0x1
 CV_TIME_EVAL, CV_TIME_WRITE, CV_TIME_CALL = 0, 1, 2
 
@@ -56,11 +57,15 @@ SUMMARY_DTYPE = np.dtype([("count", "<u4"), ("n_gamut", "<u4"), ("best_i", "<u2"
                           ("best_j", "<u2"), ("best_plus", "u1", 3), ("best_minus", "u1", 3),
                           ("best_p", "u1"), ("_pad", "u1"), ("per_pattern", "<u4", 7)])
 TABLE_DTYPE = np.dtype([("count", "<u4"), ("bin_ridx", "u1", 36)])
+PATTERN_PAIR_DTYPE = np.dtype([("i", "<u2"), ("j", "<u2"), ("plus", "u1", 3), ("minus", "u1", 3),
+                               ("pattern", "u1"), ("flags", "u1")])
 assert PAIR_DTYPE.itemsize == 16 and SUMMARY_DTYPE.itemsize == 48 and TABLE_DTYPE.itemsize == 40
+assert PATTERN_PAIR_DTYPE.itemsize == 12
 
 # Exported symbols (every one is declared in include/cvib.h).
 EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_convert",
-           "cv_pair_search", "cv_pair_reduce", "cv_context_set_timing", "cv_context_kernel_time")
+           "cv_pair_search", "cv_pair_reduce", "cv_frames_resolve", "cv_context_set_timing",
+           "cv_context_kernel_time")
 
 _lib = None
 
@@ -80,6 +85,8 @@ def lib() -> C.CDLL:
         L.cv_pair_search.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, I64,
                                      P, P, C.POINTER(I64), C.c_uint32, P]
         L.cv_pair_reduce.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P]
+        L.cv_frames_resolve.argtypes = [P, P, I64, P, C.POINTER(cv_grid), C.POINTER(cv_rule), P,
+                                        I64, P, P, P, P, P, P, P, P, C.c_uint32, P]
         L.cv_context_set_timing.argtypes = [P, C.c_int]
         L.cv_context_kernel_time.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.POINTER(I64),
                                              C.c_int]
@@ -266,3 +273,55 @@ def as_records(t: torch.Tensor, dtype: np.dtype) -> np.ndarray:
     """Copy a uint8 [k, itemsize] device tensor into a numpy structured array."""
     a = t.detach().cpu().contiguous().numpy()
     return a.reshape(-1).view(dtype) if a.size else np.zeros(0, dtype=dtype)
+
+
+@dataclass
+class FramesResult:
+    colours: torch.Tensor       # uint8 [colour_cap, 3]; the first ncolours are valid
+    ncolours: torch.Tensor      # int64 [1] on the GPU
+    pixel_index: torch.Tensor   # uint32 (as int32) [npix]
+    summaries: torch.Tensor | None   # uint8 [colour_cap, 48]
+    pbest: torch.Tensor         # uint8 [colour_cap, 7, 12] (PATTERN_PAIR_DTYPE)
+    rays: torch.Tensor | None   # int16 bits of uint16 [colour_cap, ntheta]
+    frame_a: torch.Tensor | None
+    frame_b: torch.Tensor | None
+    resolved: torch.Tensor | None   # int64 [1] on the GPU
+
+
+def frames_resolve(pixels: torch.Tensor, grid: Grid, rule: Rule, info: torch.Tensor | None = None,
+                   summaries: bool = True, rays: bool = False, frames: bool = True,
+                   graph: bool = False, out: FramesResult | None = None,
+                   ctx: Context | None = None) -> FramesResult:
+    """De-duplicate the colours of `pixels` (uint8 [..., 3] on the GPU), search
+    every distinct colour, and render the two alternating frames.  Pass the
+    previous result as `out` to reuse its buffers (needed for graph replays)."""
+    if pixels.dtype != torch.uint8 or pixels.shape[-1] != 3 or not pixels.is_cuda:
+        raise ValueError("pixels must be a uint8 CUDA tensor of shape [..., 3]")
+    px = pixels.contiguous().reshape(-1, 3)
+    npix = px.shape[0]
+    ctx = ctx or context(px.device.index)
+    dev = px.device
+    if info is not None:
+        if info.dtype != torch.uint8 or info.numel() != npix or not info.is_cuda:
+            raise ValueError("info must be a uint8 CUDA tensor with one entry per pixel")
+        info = info.contiguous().reshape(-1)
+    cap = min(npix, 1 << 24)
+    if out is None:
+        out = FramesResult(
+            colours=torch.empty((cap, 3), dtype=torch.uint8, device=dev),
+            ncolours=torch.zeros(1, dtype=torch.int64, device=dev),
+            pixel_index=torch.empty(npix, dtype=torch.int32, device=dev),
+            summaries=torch.empty((cap, 48), dtype=torch.uint8, device=dev) if summaries else None,
+            pbest=torch.empty((cap, 7, 12), dtype=torch.uint8, device=dev),
+            rays=torch.empty((cap, grid.ntheta), dtype=torch.int16, device=dev) if rays else None,
+            frame_a=torch.empty((npix, 3), dtype=torch.uint8, device=dev) if frames else None,
+            frame_b=torch.empty((npix, 3), dtype=torch.uint8, device=dev) if frames else None,
+            resolved=torch.zeros(1, dtype=torch.int64, device=dev) if frames else None)
+    g, r = grid.c(), rule.c()
+    _check(lib().cv_frames_resolve(ctx.handle, _dptr(px), npix, _dptr(info), C.byref(g),
+                                   C.byref(r), _dptr(out.colours), out.colours.shape[0],
+                                   _dptr(out.ncolours), _dptr(out.pixel_index),
+                                   _dptr(out.summaries), _dptr(out.pbest), _dptr(out.rays),
+                                   _dptr(out.frame_a), _dptr(out.frame_b), _dptr(out.resolved),
+                                   CV_GRAPH if graph else 0, _stream()))
+    return out

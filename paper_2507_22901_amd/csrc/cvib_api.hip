@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <cstring>
 #include <exception>
 #include <string>
 
@@ -230,8 +231,11 @@ int cv_context_destroy(cv_context* ctx) {
     if (!ctx) return CV_OK;
     DeviceGuard dg(ctx->device);
     (void)hipDeviceSynchronize();
+    if (ctx->fgraph_exec) (void)hipGraphExecDestroy(ctx->fgraph_exec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     cvib::Buffer* bufs[] = {&ctx->colors, &ctx->table, &ctx->seg_cnt, &ctx->seg_prefix,
-                            &ctx->scan,   &ctx->acc,   &ctx->misc};
+                            &ctx->scan,   &ctx->acc,   &ctx->misc,    &ctx->fbits,
+                            &ctx->fcnt,   &ctx->fprefix, &ctx->fmisc};
     for (cvib::Buffer* b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->host_misc) (void)hipHostFree(ctx->host_misc);
@@ -294,6 +298,46 @@ int cv_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
         return fail(CV_EINVAL, "table rows need 8 * table + 4 * ntheta <= 48 KiB of LDS");
     DeviceGuard dg(ctx->device);
     return cvib::run_pair_reduce(ctx, rgb, n, gd, rd, summ, table, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
+int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, const uint8_t* info,
+                      const cv_grid* grid, const cv_rule* rule, uint8_t* colours,
+                      int64_t colour_cap, int64_t* ncolours, uint32_t* pixel_index,
+                      cv_color_summary* summ, cv_pattern_pair* pbest, uint16_t* rays,
+                      uint8_t* frame_a, uint8_t* frame_b, int64_t* resolved, uint32_t flags,
+                      void* stream) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    if (npix < 1) return fail(CV_EINVAL, "npix must be >= 1");
+    if (!pixels || !colours || !ncolours || !pixel_index || !pbest)
+        return fail(CV_EINVAL, "null array");
+    if ((frame_a == nullptr) != (frame_b == nullptr))
+        return fail(CV_EINVAL, "frame_a and frame_b go together");
+    if (resolved && !frame_a) return fail(CV_EINVAL, "resolved needs the frames");
+    const int64_t need = npix < ((int64_t)1 << 24) ? npix : ((int64_t)1 << 24);
+    if (colour_cap < need) return fail(CV_EINVAL, "colour_cap < min(npix, 2^24)");
+    if (flags & ~(uint32_t)CV_GRAPH) return fail(CV_EINVAL, "unknown flags");
+    cvib::FramesCall call;
+    std::memset(&call, 0, sizeof call);  // bytewise comparison for the graph cache
+    int rc;
+    if ((rc = cvib::make_grid(grid, &call.gd)) != CV_OK) return rc;
+    if ((rc = cvib::make_rule(rule, &call.rd)) != CV_OK) return rc;
+    call.pixels = pixels;
+    call.npix = npix;
+    call.info = info;
+    call.colours = colours;
+    call.colour_cap = colour_cap;
+    call.ncolours = ncolours;
+    call.pixel_index = pixel_index;
+    call.summ = summ;
+    call.pbest = pbest;
+    call.rays = rays;
+    call.frame_a = frame_a;
+    call.frame_b = frame_b;
+    call.resolved = resolved;
+    DeviceGuard dg(ctx->device);
+    return cvib::run_frames_resolve(ctx, call, (flags & CV_GRAPH) != 0, (hipStream_t)stream);
     CV_GUARD_END
 }
 

@@ -1,0 +1,461 @@
+// Batched frames: de-duplicate the colours of many frames, search every
+// distinct colour in one persistent launch (the colour count stays on the
+// device), and render the two alternating frames that carry the per-pixel
+// information (Fig. 1a of the paper: the display alternates the two colours
+// of a pair; a device reads the per-channel change, people see the target).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstring>
+#include <string>
+
+#include "cvib_internal.h"
+#include "cvib_kernels.h"
+
+namespace cvib {
+
+constexpr int64_t kCube = (int64_t)1 << 24;     // distinct 8-bit colours
+constexpr int64_t kCubeWords = kCube / 32;      // bitmap words
+
+// ---------------------------------------------------------------------------
+// De-duplication through a 2^24-bit bitmap of colour ids R<<16 | G<<8 | B.
+
+__global__ void k_bitmap_mark(const uint8_t* __restrict__ px, int64_t npix,
+                              uint32_t* __restrict__ bits) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
+        const uint32_t id = ((uint32_t)px[3 * p] << 16) | ((uint32_t)px[3 * p + 1] << 8) | px[3 * p + 2];
+        const uint32_t bit = 1u << (id & 31u);
+        uint32_t* word = bits + (id >> 5);
+        // most pixels repeat a colour already marked: read first, then set
+        if ((__builtin_nontemporal_load(word) & bit) == 0u) atomicOr(word, bit);
+    }
+}
+
+__global__ void k_bitmap_popc(const uint32_t* __restrict__ bits, uint32_t* __restrict__ cnt) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < kCubeWords) cnt[w] = (uint32_t)__builtin_popcount(bits[w]);
+}
+
+// Sorted distinct colours: word w's colours start at prefix[w].
+__global__ void k_bitmap_compact(const uint32_t* __restrict__ bits,
+                                 const uint64_t* __restrict__ prefix,
+                                 uint8_t* __restrict__ colours) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= kCubeWords) return;
+    uint32_t m = bits[w];
+    uint64_t k = prefix[w];
+    while (m) {
+        const uint32_t b = (uint32_t)__builtin_ctz(m);
+        m &= m - 1u;
+        const uint32_t id = ((uint32_t)w << 5) | b;
+        colours[3 * k] = (uint8_t)(id >> 16);
+        colours[3 * k + 1] = (uint8_t)(id >> 8);
+        colours[3 * k + 2] = (uint8_t)id;
+        ++k;
+    }
+}
+
+// Index of each pixel's colour in the sorted list.
+__global__ void k_pixel_index(const uint8_t* __restrict__ px, int64_t npix,
+                              const uint32_t* __restrict__ bits,
+                              const uint64_t* __restrict__ prefix, uint32_t* __restrict__ index) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
+        const uint32_t id = ((uint32_t)px[3 * p] << 16) | ((uint32_t)px[3 * p + 1] << 8) | px[3 * p + 2];
+        const uint32_t w = id >> 5, b = id & 31u;
+        index[p] = (uint32_t)prefix[w] + (uint32_t)__builtin_popcount(bits[w] & ((1u << b) - 1u));
+    }
+}
+
+// Per-colour constants for a device-resident colour count.
+__global__ void k_prologue_dev(const uint8_t* __restrict__ rgb, const uint64_t* __restrict__ n_dev,
+                               ColorConst* __restrict__ cc, MatArgs m) {
+    const int64_t n = (int64_t)*n_dev;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        double lab[3];
+        rgb8_lab(m, rgb + 3 * k, lab);
+        const double fy = (lab[0] + 16.0) / 116.0;
+        const double Y = finv(fy) * m.W[1];
+        ColorConst c;
+        c.fx0 = fy + lab[1] / 500.0;
+        c.fz0 = fy - lab[2] / 200.0;
+        c.B[0] = m.Minv[1] * Y;
+        c.B[1] = m.Minv[4] * Y;
+        c.B[2] = m.Minv[7] * Y;
+        c.L = (float)lab[0];
+        c.a = (float)lab[1];
+        c.b = (float)lab[2];
+        c._pad = 0;
+        cc[k] = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-colour resolve: one block searches one colour completely (colours are
+// strided over the persistent grid; the count is read from the device).  It
+// produces the summary, the best pair of every information pattern and,
+// optionally, the largest surviving radius of every ray.
+
+struct ResolveArgs {
+    const ColorConst* cc;
+    const uint64_t* n_dev;
+    TabArgs tab;
+    Geom g;
+    RuleDev rule;
+    double ra, rb;
+    int32_t nr, ntheta, W;
+    float inv_W;
+    int32_t si, sj;
+    cv_color_summary* summ;   // nullable
+    cv_pattern_pair* pbest;   // [n][7]
+    uint16_t* rays;           // nullable, [n][ntheta]
+};
+
+template <bool SYM, bool RAYS>
+__global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
+    constexpr int BLOCK = 256, NW = BLOCK / 64;
+    extern __shared__ double s_dyn[];
+    __shared__ uint32_t s_red[NW][10];
+    __shared__ uint32_t s_pb[7];
+    const int tid = threadIdx.x;
+    const uint32_t lane = (uint32_t)tid & 63u;
+    const int w = tid >> 6;
+    for (int k = tid; k < a.tab.tab_len; k += BLOCK) s_dyn[k] = a.tab.tab[k];
+    const double* tab = s_dyn;
+    uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len);
+    const uint32_t mult = SYM ? 2u : 1u;
+    const int64_t n = (int64_t)*a.n_dev;
+    const int32_t per = a.nr * a.W;
+
+    for (int64_t c = blockIdx.x; c < n; c += gridDim.x) {
+        if (RAYS)
+            for (int k = tid; k < a.W; k += BLOCK) s_ray[k] = 0;
+        if (tid < 7) s_pb[tid] = 0;
+        __syncthreads();
+        const ColorConst cc = a.cc[c];
+        int32_t i, j;
+        divmod_small(tid, a.W, a.inv_W, i, j);
+        uint32_t cnt = 0, ng = 0, best = 0, steps = 0;
+        uint64_t pk = 0;
+        uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
+        const int32_t iters = (per + BLOCK - 1) / BLOCK;
+        for (int32_t it = 0; it < iters; ++it) {
+            const bool live = it * BLOCK + tid < per;
+            double sn, co;
+            sincos_j(tab, a.tab.N, j, sn, co);
+            const double rr = (double)(i + 1);
+            float fp[3], fm[3];
+            pair_linear(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
+            const bool both = live && in_unit_cube(fp) && in_unit_cube(fm);
+            const bool need = a.rule.clip ? live : both;
+            ng += both ? 1u : 0u;
+            if (__ballot(need) != 0ull) {
+                float Vp[3], Vm[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Vp[k] = code8(fp[k]);
+                    Vm[k] = code8(fm[k]);
+                }
+                const uint32_t p = pattern_of(Vp, Vm, a.rule);
+                if (need && accepts(a.rule, p)) {
+                    const uint32_t key = best_key(i, j);
+                    ++cnt;
+                    pk += 1ull << (8u * ((p - 1u) & 7u));
+                    best = max(best, key);
+                    atomicMax(&s_pb[p - 1u], key);
+                    if (RAYS) atomicMax(&s_ray[j], (uint32_t)(i + 1));
+                }
+            }
+            if (++steps == 255) {
+#pragma unroll
+                for (int q = 0; q < 7; ++q) pat[q] += (uint32_t)(pk >> (8 * q)) & 0xFFu;
+                pk = 0;
+                steps = 0;
+            }
+            j += a.sj;
+            i += a.si;
+            if (j >= a.W) { j -= a.W; ++i; }
+        }
+#pragma unroll
+        for (int q = 0; q < 7; ++q) pat[q] += (uint32_t)(pk >> (8 * q)) & 0xFFu;
+        uint32_t v[10] = {mult * wave_sum_u32(cnt), mult * wave_sum_u32(ng), wave_max_u32(best)};
+#pragma unroll
+        for (int q = 0; q < 7; ++q) v[3 + q] = mult * wave_sum_u32(pat[q]);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 10; ++q) s_red[w][q] = v[q];
+        }
+        __syncthreads();
+        if (tid < 10) {
+            uint32_t x = 0;
+            for (int q = 0; q < NW; ++q) x = (tid == 2) ? max(x, s_red[q][tid]) : x + s_red[q][tid];
+            s_red[0][tid] = x;  // column tid is touched by this thread only
+        }
+        __syncthreads();
+        if (tid == 0 && a.summ) {
+            uint32_t pt[7];
+            for (int q = 0; q < 7; ++q) pt[q] = s_red[0][3 + q];
+            write_summary(cc, a.g, a.rule, a.tab, a.ra, a.rb, s_red[0][0], s_red[0][1], s_red[0][2],
+                          pt, a.summ + c);
+        }
+        if (tid < 7) {
+            cv_pattern_pair r = {};
+            const uint32_t key = s_pb[tid];
+            if (key) {
+                const int32_t bi = (int32_t)(key >> 16), bj = (int32_t)(0xFFFFu - (key & 0xFFFFu));
+                double sn, co;
+                sincos_j(tab, a.tab.N, bj, sn, co);
+                const double rr = (double)(bi + 1);
+                PairEval e;
+                eval_pair(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, e);
+                r.i = (uint16_t)bi;
+                r.j = (uint16_t)bj;
+                for (int k = 0; k < 3; ++k) {
+                    r.plus[k] = (uint8_t)e.Vp[k];
+                    r.minus[k] = (uint8_t)e.Vm[k];
+                }
+                r.pattern = (uint8_t)(tid + 1);
+                r.flags = 1;
+            }
+            a.pbest[c * 7 + tid] = r;
+        }
+        if (RAYS) {
+            uint16_t* dst = a.rays + c * (int64_t)a.ntheta;
+            for (int k = tid; k < a.W; k += BLOCK) {
+                const uint16_t r = (uint16_t)s_ray[k];
+                dst[k] = r;
+                if (SYM) dst[k + a.W] = r;  // ray j + N/2 holds the same pairs
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rendering: frame A shows the + colour and frame B the - colour of the pair
+// chosen for each pixel (the best pair of the pixel's information pattern, or
+// of any pattern when no map is given); pixels without a pair keep their
+// colour in both frames.
+
+__global__ void k_render(const uint8_t* __restrict__ px, int64_t npix,
+                         const uint32_t* __restrict__ index, const uint8_t* __restrict__ info,
+                         const cv_pattern_pair* __restrict__ pbest,
+                         const cv_color_summary* __restrict__ summ, uint8_t* __restrict__ fa,
+                         uint8_t* __restrict__ fb, unsigned long long* __restrict__ resolved) {
+    uint32_t got = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
+        const uint32_t k = index[p];
+        const uint32_t q = info ? info[p] : 0u;
+        uint8_t A[3] = {px[3 * p], px[3 * p + 1], px[3 * p + 2]};
+        uint8_t B[3] = {A[0], A[1], A[2]};
+        bool ok = false;
+        if (q >= 1u && q <= 7u) {
+            const cv_pattern_pair& r = pbest[(int64_t)k * 7 + (q - 1u)];
+            if (r.flags & 1u) {
+                for (int c = 0; c < 3; ++c) {
+                    A[c] = r.plus[c];
+                    B[c] = r.minus[c];
+                }
+                ok = true;
+            }
+        } else if (q == 0u && summ && summ[k].best_i != 0xFFFFu) {
+            for (int c = 0; c < 3; ++c) {
+                A[c] = summ[k].best_plus[c];
+                B[c] = summ[k].best_minus[c];
+            }
+            ok = true;
+        }
+        for (int c = 0; c < 3; ++c) {
+            fa[3 * p + c] = A[c];
+            fb[3 * p + c] = B[c];
+        }
+        got += ok ? 1u : 0u;
+    }
+    const uint32_t s = wave_sum_u32(got);
+    if ((threadIdx.x & 63u) == 0 && s && resolved) atomicAdd(resolved, (unsigned long long)s);
+}
+
+__global__ void k_zero_words(uint64_t* __restrict__ p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = 0;
+}
+
+__global__ void k_copy_count(const uint64_t* __restrict__ src, int64_t* __restrict__ dst) {
+    *dst = (int64_t)*src;
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+namespace {
+
+MatArgs frame_mat_args() {
+    const ColorSpace& cs = color_space();
+    MatArgs m;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            m.M[3 * r + c] = cs.M[r][c];
+            m.Minv[3 * r + c] = cs.Minv[r][c];
+        }
+    for (int k = 0; k < 3; ++k) m.W[k] = cs.W[k];
+    return m;
+}
+
+unsigned grid_for(int64_t items, int per_block, unsigned cap) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    return (unsigned)(g > cap ? cap : g);
+}
+
+template <bool SYM, bool RAYS>
+int launch_resolve_t(cv_context* ctx, const ResolveArgs& a, hipStream_t s) {
+    auto k = k_colour_resolve<SYM, RAYS>;
+    const size_t lds = (size_t)a.tab.tab_len * 8 + (RAYS ? (size_t)a.W * 4 : 0);
+    int lds_max = 0;
+    CV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    if (lds + 256 > (size_t)lds_max)
+        return fail(CV_EINVAL, "angle table and per-ray maxima need " + std::to_string(lds) +
+                                   " bytes of LDS; this device has " + std::to_string(lds_max));
+    int per_cu = 0;
+    CV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds));
+    if (per_cu < 1) per_cu = 1;
+    hipLaunchKernelGGL(k, dim3((unsigned)(per_cu * ctx->num_cu)), dim3(256), lds, s, a);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
+} // namespace
+
+// Everything the call enqueues, in order, on stream s (also used for capture).
+int FramesCall::enqueue(cv_context* ctx, hipStream_t s) const {
+    int rc;
+    uint32_t* bits = (uint32_t*)ctx->fbits.ptr;
+    uint32_t* cnt = (uint32_t*)ctx->fcnt.ptr;
+    uint64_t* prefix = (uint64_t*)ctx->fprefix.ptr;
+    uint64_t* misc = (uint64_t*)ctx->fmisc.ptr;  // [0] colour count
+    hipLaunchKernelGGL(k_zero_words, dim3(1024), dim3(256), 0, s, (uint64_t*)bits, kCubeWords / 2);
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, misc, (int64_t)8);
+    hipLaunchKernelGGL(k_bitmap_mark, dim3(grid_for(npix, 256, 8192)), dim3(256), 0, s, pixels,
+                       npix, bits);
+    hipLaunchKernelGGL(k_bitmap_popc, dim3((unsigned)(kCubeWords / 256)), dim3(256), 0, s, bits, cnt);
+    CV_HIP(hipGetLastError());
+    if ((rc = run_scan_counts(ctx, cnt, kCubeWords, prefix, nullptr, 1, 0, misc, s)) != CV_OK)
+        return rc;
+    hipLaunchKernelGGL(k_bitmap_compact, dim3((unsigned)(kCubeWords / 256)), dim3(256), 0, s, bits,
+                       prefix, colours);
+    hipLaunchKernelGGL(k_pixel_index, dim3(grid_for(npix, 256, 8192)), dim3(256), 0, s, pixels, npix,
+                       bits, prefix, pixel_index);
+    hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, misc, ncolours);
+    // the search of every distinct colour
+    if ((rc = launch_angle_table((double*)ctx->table.ptr, gd.N, s)) != CV_OK) return rc;
+    hipLaunchKernelGGL(k_prologue_dev, dim3(grid_for(colour_cap, 256, 8192)), dim3(256), 0, s,
+                       colours, misc, (ColorConst*)ctx->colors.ptr, frame_mat_args());
+    CV_HIP(hipGetLastError());
+    ResolveArgs a;
+    a.cc = (const ColorConst*)ctx->colors.ptr;
+    a.n_dev = misc;
+    a.tab.tab = (const double*)ctx->table.ptr;
+    a.tab.tab_len = gd.tab_len;
+    a.tab.N = gd.N;
+    a.g = geom_constants();
+    a.rule = rd;
+    a.ra = gd.ra;
+    a.rb = gd.rb;
+    a.nr = gd.nr;
+    a.ntheta = gd.ntheta;
+    const bool sym = gd.ntheta == gd.N;
+    a.W = sym ? gd.N / 2 : gd.ntheta;
+    a.inv_W = 1.0f / (float)a.W;
+    a.si = 256 / a.W;
+    a.sj = 256 % a.W;
+    a.summ = summ;
+    a.pbest = pbest;
+    a.rays = rays;
+    if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
+    if (sym) {
+        rc = rays ? launch_resolve_t<true, true>(ctx, a, s) : launch_resolve_t<true, false>(ctx, a, s);
+    } else {
+        rc = rays ? launch_resolve_t<false, true>(ctx, a, s) : launch_resolve_t<false, false>(ctx, a, s);
+    }
+    if (rc != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
+    if (frame_a) {
+        if (resolved)
+            hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, (uint64_t*)resolved, (int64_t)1);
+        hipLaunchKernelGGL(k_render, dim3(grid_for(npix, 256, 8192)), dim3(256), 0, s, pixels, npix,
+                           pixel_index, info, pbest, summ, frame_a, frame_b,
+                           (unsigned long long*)resolved);
+    }
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
+bool FramesCall::same(const FramesCall& o) const {
+    return std::memcmp(this, &o, sizeof(FramesCall)) == 0;
+}
+
+int run_frames_resolve(cv_context* ctx, const FramesCall& call_in, bool graph, hipStream_t s) {
+    int rc;
+    FramesCall call = call_in;
+    // every allocation happens before any capture
+    if ((rc = ctx->ensure(ctx->fbits, (size_t)kCubeWords * 4)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->fcnt, (size_t)kCubeWords * 4)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->fprefix, (size_t)kCubeWords * 8)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->fmisc, 64)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->scan, (size_t)((kCubeWords + 4095) / 4096) * 8)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->colors, (size_t)call.colour_cap * sizeof(ColorConst))) != CV_OK)
+        return rc;
+    if ((rc = ctx->ensure(ctx->table, (size_t)call.gd.tab_len * 8)) != CV_OK) return rc;
+    const cvib::Buffer* ws[7] = {&ctx->fbits, &ctx->fcnt, &ctx->fprefix, &ctx->fmisc,
+                                 &ctx->scan,  &ctx->colors, &ctx->table};
+    for (int k = 0; k < 7; ++k) call.ws[k] = ws[k]->ptr;
+    if (!graph) {
+        if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
+        if ((rc = call.enqueue(ctx, s)) != CV_OK) return rc;
+        if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
+        if (ctx->timing) {
+            CV_HIP(hipStreamSynchronize(s));
+            if ((rc = ctx->collect()) != CV_OK) return rc;
+        }
+        return CV_OK;
+    }
+    if (!ctx->fgraph_exec || !ctx->fgraph_call.same(call)) {
+        if (ctx->fgraph_exec) {
+            CV_HIP(hipGraphExecDestroy(ctx->fgraph_exec));
+            ctx->fgraph_exec = nullptr;
+        }
+        if (!ctx->cap_stream) CV_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        const bool timing = ctx->timing;
+        ctx->timing = false;  // no timing events inside a captured graph
+        hipGraph_t g = nullptr;
+        CV_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        rc = call.enqueue(ctx, ctx->cap_stream);
+        hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+        ctx->timing = timing;
+        if (rc != CV_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&ctx->fgraph_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            ctx->fgraph_exec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        ctx->fgraph_call = call;
+    }
+    if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
+    CV_HIP(hipGraphLaunch(ctx->fgraph_exec, s));
+    if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
+    if (ctx->timing) {
+        CV_HIP(hipStreamSynchronize(s));
+        if ((rc = ctx->collect()) != CV_OK) return rc;
+    }
+    return CV_OK;
+}
+
+} // namespace cvib

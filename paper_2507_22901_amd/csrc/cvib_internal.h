@@ -58,6 +58,30 @@ int run_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
 int run_scan_counts(cv_context* ctx, const uint32_t* cnt, int64_t T, uint64_t* prefix,
                     int64_t* offsets, int32_t spc, int64_t n, uint64_t* total, hipStream_t s);
 Geom geom_constants();
+int launch_angle_table(double* tab, int32_t N, hipStream_t s);
+
+// One cv_frames_resolve call (compared bytewise to reuse a captured graph).
+struct FramesCall {
+    const uint8_t* pixels;
+    int64_t npix;
+    const uint8_t* info;
+    GridDev gd;
+    RuleDev rd;
+    uint8_t* colours;
+    int64_t colour_cap;
+    int64_t* ncolours;
+    uint32_t* pixel_index;
+    cv_color_summary* summ;
+    cv_pattern_pair* pbest;
+    uint16_t* rays;
+    uint8_t* frame_a;
+    uint8_t* frame_b;
+    int64_t* resolved;
+    const void* ws[7];  // context workspaces the call uses (a regrown one voids a cached graph)
+    int enqueue(cv_context* ctx, hipStream_t s) const;
+    bool same(const FramesCall& o) const;
+};
+int run_frames_resolve(cv_context* ctx, const FramesCall& call, bool graph, hipStream_t s);
 
 } // namespace cvib
 
@@ -71,6 +95,13 @@ struct cv_context {
     cvib::Buffer scan;        // per-block partial sums of the segment scan
     cvib::Buffer acc;         // per-colour accumulators
     cvib::Buffer misc;        // ticket, -, survivor total
+    cvib::Buffer fbits;       // frames: 2^24-bit colour bitmap
+    cvib::Buffer fcnt;        // frames: colours per bitmap word
+    cvib::Buffer fprefix;     // frames: first colour index per bitmap word
+    cvib::Buffer fmisc;       // frames: [0] colour count
+    hipStream_t cap_stream = nullptr;        // stream used for graph capture
+    hipGraphExec_t fgraph_exec = nullptr;    // captured cv_frames_resolve
+    cvib::FramesCall fgraph_call{};          // the call it was captured for
     uint64_t* host_misc = nullptr; // pinned mirror of misc for the total
     // kernel timing (cv_context_set_timing): event pairs and totals per phase
     bool timing = false;

@@ -806,6 +806,12 @@ ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, c
 
 } // namespace
 
+int launch_angle_table(double* tab, int32_t N, hipStream_t s) {
+    hipLaunchKernelGGL(k_angle_table, dim3(blocks_for(N / 2 + 1, 256)), dim3(256), 0, s, tab, N);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
 // Exclusive scan of per-unit counts into 64-bit offsets (unit order); the
 // total goes to *total (device) and, if offsets is given, every spc-th unit's
 // offset to offsets[unit / spc] and the total to offsets[n].

@@ -47,10 +47,10 @@ def test_every_declared_symbol_is_exported(cv):
 def test_struct_layouts_match_header(cv, tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "cvib.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cv_pair),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cv_pair),'
                    ' sizeof(cv_color_summary), sizeof(cv_table_row), sizeof(cv_grid),'
                    ' sizeof(cv_rule), offsetof(cv_color_summary, per_pattern),'
-                   ' offsetof(cv_pair, flags));return 0;}\n')
+                   ' offsetof(cv_pair, flags), sizeof(cv_pattern_pair));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), "-o", str(exe), str(src)], check=True)
     vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
@@ -60,6 +60,7 @@ def test_struct_layouts_match_header(cv, tmp_path):
     assert vals[3] == C.sizeof(cv.cv_grid) and vals[4] == C.sizeof(cv.cv_rule)
     assert vals[5] == cv.SUMMARY_DTYPE.fields["per_pattern"][1]
     assert vals[6] == cv.PAIR_DTYPE.fields["flags"][1]
+    assert vals[7] == cv.PATTERN_PAIR_DTYPE.itemsize == 12
 
 
 def test_null_context_is_rejected(cv):
@@ -72,6 +73,8 @@ def test_null_context_is_rejected(cv):
     assert L.cv_pair_search(None, None, 0, C.byref(g), C.byref(r), None, 0, None, None,
                             C.byref(tot), 0, None) == cv.CV_EINVAL
     assert L.cv_pair_reduce(None, None, 0, C.byref(g), C.byref(r), None, None, None) == cv.CV_EINVAL
+    assert L.cv_frames_resolve(None, None, 1, None, C.byref(g), C.byref(r), None, 1, None, None,
+                               None, None, None, None, None, None, 0, None) == cv.CV_EINVAL
     assert L.cv_context_destroy(None) == cv.CV_OK
     assert L.cv_context_create(0, None) == cv.CV_EINVAL
     assert L.cv_context_set_timing(None, 1) == cv.CV_EINVAL
@@ -138,6 +141,25 @@ def test_argument_validation(cv):
     gbig = cv.Grid(0.1, 300, 1.0, 360).c()
     assert L.cv_pair_reduce(dummy, None, 0, C.byref(gbig), C.byref(r), None,
                             C.cast(dummy, C.c_void_p), None) == cv.CV_EINVAL  # table needs nr<=255
+
+
+def test_frames_argument_validation(cv):
+    L = cv.lib()
+    d = C.cast((C.c_uint8 * 4096)(), C.c_void_p)
+    g = cv.Grid(0.1, 10, 1.0, 360).c()
+    r = cv.Rule().c()
+
+    def call(npix=4, colour_cap=4, fa=d, fb=d, res=None, flags=0, pixels=d, pbest=d):
+        return L.cv_frames_resolve(d, pixels, npix, None, C.byref(g), C.byref(r), d, colour_cap, d,
+                                   d, None, pbest, None, fa, fb, res, flags, None)
+    assert call(npix=0) == cv.CV_EINVAL                # no pixels
+    assert call(pixels=None) == cv.CV_EINVAL           # null input
+    assert call(pbest=None) == cv.CV_EINVAL            # pbest is required
+    assert call(colour_cap=3) == cv.CV_EINVAL          # fewer slots than possible colours
+    assert b"colour_cap" in L.cv_last_error()
+    assert call(fb=None) == cv.CV_EINVAL               # the two frames go together
+    assert call(fa=None, fb=None, res=d) == cv.CV_EINVAL
+    assert call(flags=0x10) == cv.CV_EINVAL            # unknown flag
 
 
 def test_binding_refuses_host_tensors(cv):

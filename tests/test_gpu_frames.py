@@ -1,0 +1,147 @@
+"""Batched frames on the GPU: de-duplication, per-colour resolve (summaries,
+best pair per information pattern, per-ray maxima), rendering of the two
+alternating frames, and hipGraph replays -- against the FP64 oracle and
+plain host definitions."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cv():
+    import paper_2507_22901_amd as cv
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cv.lib()
+    return cv
+
+
+def _frames():
+    # two small synthetic frames (gradients + Voronoi cells + noise) and a few
+    # Table 1 colours painted in, so that colours repeat across frames
+    f = W.frames([3, 4], height=72, width=128)
+    f[0, :8, :9] = W.PAPER_COLOUR_ARRAY[None, :, :]
+    f[1, -4:, :9] = W.PAPER_COLOUR_ARRAY[None, :, :]
+    return f
+
+
+def _oracle_best_per_pattern(oracle, colours, grid, rule):
+    """Best pair (max i, then min j) of each pattern, per colour, from the
+    oracle's survivor list; also per-ray maxima."""
+    recs, offs, _ = oracle.search(colours, grid, rule)
+    n = len(colours)
+    best = {}
+    rays = np.zeros((n, grid[3]), dtype=np.int64)
+    for k in range(n):
+        seg = recs[offs[k]:offs[k + 1]]
+        for p in range(1, 8):
+            sp = seg[seg["pattern"] == p]
+            if len(sp):
+                order = np.lexsort((sp["j"], -sp["i"].astype(np.int64)))
+                best[(k, p)] = sp[order[0]]
+        if len(seg):
+            np.maximum.at(rays[k], seg["j"].astype(np.int64), seg["i"].astype(np.int64) + 1)
+    return best, rays
+
+
+@pytest.mark.parametrize("nt", [180, 172])
+def test_frames_resolve_matches_oracle(cv, oracle, nt):
+    f = _frames()
+    npix = f.shape[0] * f.shape[1] * f.shape[2]
+    rng = np.random.default_rng(0)
+    info = rng.integers(0, 8, npix).astype(np.uint8)
+    grid = (0.5, 70, 2.0, nt)
+    rule = (50, 0.5, 0x7F)
+    px = torch.from_numpy(f).cuda()
+    res = cv.frames_resolve(px, cv.Grid(*grid), cv.Rule(*rule), info=torch.from_numpy(info).cuda(),
+                            rays=True)
+    torch.cuda.synchronize()
+    ids = oracle.distinct_colours(f)
+    n = int(res.ncolours.item())
+    assert n == len(ids)
+    cols = res.colours[:n].cpu().numpy()
+    assert np.array_equal(cols, W.cube_colours(ids))
+    pix = f.reshape(-1, 3)
+    idx = res.pixel_index.cpu().numpy().astype(np.int64)
+    assert np.array_equal(cols[idx], pix)
+    # per-colour results on a sample of colours (the oracle is slow)
+    sample = np.unique(np.concatenate([rng.choice(n, 60, replace=False),
+                                       idx[:9]]))  # includes painted paper colours
+    sc = cols[sample]
+    s_o = oracle.reduce(sc, grid, rule)
+    s_g = cv.as_records(res.summaries, cv.SUMMARY_DTYPE)[sample]
+    ex = s_o["n_ambiguous"] == 0
+    assert ex.mean() > 0.3
+    assert np.array_equal(s_g["count"][ex], s_o["count"][ex])
+    assert np.array_equal(s_g["per_pattern"][ex], s_o["per_pattern"][ex])
+    assert np.array_equal(s_g["best_i"][ex], s_o["best_i"][ex])
+    pb = cv.as_records(res.pbest.reshape(-1, 12), cv.PATTERN_PAIR_DTYPE).reshape(-1, 7)[sample]
+    best, rays_o = _oracle_best_per_pattern(oracle, sc, grid, rule)
+    rays_g = res.rays.cpu().numpy().view(np.uint16)[sample]
+    for k in np.nonzero(ex)[0]:
+        for p in range(1, 8):
+            b = best.get((k, p))
+            g = pb[k, p - 1]
+            if b is None:
+                assert g["flags"] == 0
+            else:
+                assert g["flags"] == 1 and g["pattern"] == p
+                assert (g["i"], g["j"]) == (b["i"], b["j"])
+                if not b["flags"] & 1:  # codes of a band candidate may round the other way
+                    assert np.array_equal(g["plus"], b["plus"])
+                    assert np.array_equal(g["minus"], b["minus"])
+        assert np.array_equal(rays_g[k].astype(np.int64), rays_o[k])
+    # rendering, against a host composition of the GPU's own per-colour pairs
+    pball = cv.as_records(res.pbest.reshape(-1, 12), cv.PATTERN_PAIR_DTYPE).reshape(-1, 7)
+    sall = cv.as_records(res.summaries, cv.SUMMARY_DTYPE)
+    A = pix.copy()
+    B = pix.copy()
+    got = 0
+    for p_ in range(npix):
+        k, q = idx[p_], int(info[p_])
+        if q:
+            r = pball[k, q - 1]
+            if r["flags"]:
+                A[p_], B[p_] = r["plus"], r["minus"]
+                got += 1
+        elif sall["best_i"][k] != 0xFFFF:
+            A[p_], B[p_] = sall["best_plus"][k], sall["best_minus"][k]
+            got += 1
+    assert np.array_equal(res.frame_a.cpu().numpy(), A)
+    assert np.array_equal(res.frame_b.cpu().numpy(), B)
+    assert int(res.resolved.item()) == got
+
+
+def test_frames_graph_replay_matches_eager(cv):
+    """The captured graph, replayed several times with eager work and
+    synchronisations in between, reproduces the eager result each time."""
+    f = torch.from_numpy(_frames()).cuda()
+    grid = cv.Grid(0.5, 60, 2.0, 180)
+    rule = cv.Rule(50, 0.5, 0x7F)
+    eager = cv.frames_resolve(f, grid, rule, rays=True)
+    torch.cuda.synchronize()
+    ref = {k: getattr(eager, k).clone() for k in ("colours", "ncolours", "pixel_index", "summaries",
+                                                    "pbest", "rays", "frame_a", "frame_b", "resolved")}
+    out = cv.frames_resolve(f, grid, rule, rays=True, graph=True)
+    for rep in range(4):
+        # eager work in between replays
+        other = cv.frames_resolve(f[:, :32], cv.Grid(0.5, 40, 2.0, 180), rule)
+        torch.cuda.synchronize()
+        for k in ref:
+            getattr(out, k).zero_()
+        torch.cuda.synchronize()
+        cv.frames_resolve(f, grid, rule, rays=True, graph=True, out=out)
+        torch.cuda.synchronize()
+        n = int(ref["ncolours"].item())
+        for k, v in ref.items():
+            g = getattr(out, k)
+            if k in ("colours", "summaries", "pbest", "rays"):
+                assert torch.equal(g[:n], v[:n]), (rep, k)
+            else:
+                assert torch.equal(g, v), (rep, k)
+        assert int(other.ncolours.item()) > 0
