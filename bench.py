@@ -49,7 +49,94 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--only", choices=("all", "nine", "frames", "cube"), default="all",
+                    help="run one workload only (the JSON line then carries just that part)")
     return ap.parse_args()
+
+
+def _alu_roofline(kernel, ms, evals, gamut_evals):
+    flops = FLOPS_GEOM * evals + FLOPS_CODE * gamut_evals
+    achieved = flops / (ms * 1e-3)
+    return {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12,
+            "peak": VALU_FMA_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / VALU_FMA_PEAK,
+            "traffic": None, "kernel_ms": ms, "flops_per_launch": flops,
+            "evaluated_pairs": evals, "in_gamut_evaluations": gamut_evals}
+
+
+def bench_frames(cv, W, torch, steps):
+    """Eight synthetic 3840 x 2160 frames (seeds 0..7): de-duplicate, resolve
+    every distinct colour on the 500 x 360 grid (best pair per information
+    pattern, per-ray maxima, summaries) and render the two frames; one
+    hipGraph launch per step, frames resident in HBM."""
+    import numpy as np
+    f = W.frames(range(8))
+    info = np.tile(W.info_map(0).reshape(-1), len(f))
+    g = W.GRID_FRAMES
+    grid, rule = cv.Grid(*g.astuple()), cv.Rule(*W.DEFAULT_RULE)
+    px = torch.from_numpy(f).cuda()
+    inf = torch.from_numpy(info).cuda()
+    ctx = cv.context(0)
+    # one eager call with kernel timing (the resolve kernel's own duration)
+    ctx.set_timing(True)
+    ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
+    out = cv.frames_resolve(px, grid, rule, info=inf, rays=True, ctx=ctx)
+    torch.cuda.synchronize()
+    t_res, _ = ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
+    ctx.set_timing(False)
+    cv.frames_resolve(px, grid, rule, info=inf, rays=True, graph=True, out=out, ctx=ctx)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        cv.frames_resolve(px, grid, rule, info=inf, rays=True, graph=True, out=out, ctx=ctx)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    n = int(out.ncolours.item())
+    summ = cv.as_records(out.summaries[:n], cv.SUMMARY_DTYPE)
+    half = g.ntheta * g.dtheta_deg == 360.0
+    evals = n * g.nr * (g.ntheta // 2 if half else g.ntheta)
+    gamut = int(summ["n_gamut"].astype(np.int64).sum()) // (2 if half else 1)
+    npix = px.shape[0] * px.shape[1] * px.shape[2]
+    return {
+        "workload": "8 synthetic 3840x2160 frames (seeds 0..7), 16x16-pixel information map; "
+                    "r = 0.1..50 step 0.1 (500) x theta = 0..359 deg step 1 (360)",
+        "colours_per_s_exact": n / (ms * 1e-3), "distinct_colours": n, "pixels": npix,
+        "pixels_per_s": npix / (ms * 1e-3), "pairs_per_s": n * g.per_colour / (ms * 1e-3),
+        "ms_per_call": ms, "calls": steps, "resolved_pixels": int(out.resolved.item()),
+        "resolve_kernel_ms": t_res,
+        "roofline": _alu_roofline("k_colour_resolve", t_res, evals, gamut),
+    }
+
+
+def bench_cube(cv, W, torch, steps):
+    """The whole RGB cube (2^24 colours) on the 200 x 180 grid: per-colour
+    count and 36-bin maximum radius table."""
+    import numpy as np
+    g = W.GRID_CUBE
+    grid, rule = cv.Grid(*g.astuple()), cv.Rule(*W.DEFAULT_RULE)
+    ids = torch.arange(1 << 24, dtype=torch.int32, device="cuda")
+    cols = torch.stack([(ids >> 16) & 255, (ids >> 8) & 255, ids & 255], dim=1).to(torch.uint8)
+    del ids
+    ctx = cv.context(0)
+    summ, tab = cv.pair_reduce(cols, grid, rule, table=True, ctx=ctx)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        cv.pair_reduce(cols, grid, rule, table=True, ctx=ctx)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    ng = int(summ[:, 4:8].contiguous().view(torch.int32).to(torch.int64).sum())
+    evals = (1 << 24) * g.nr * (g.ntheta // 2)
+    return {
+        "workload": "all 2^24 colours; r = 0.25..50 step 0.25 (200) x theta = 0..358 deg step 2 (180)",
+        "colours_per_s": (1 << 24) / (ms * 1e-3), "pairs_per_s": (1 << 24) * g.per_colour / (ms * 1e-3),
+        "ms_per_call": ms, "calls": steps,
+        "feasible_colours": int((tab[:, :4].contiguous().view(torch.int32) > 0).sum()),
+        "roofline_whole_call": _alu_roofline("k_pair_reduce<TABLE> (whole call)", ms, evals, ng // 2),
+    }
 
 
 def cpu_baseline(target_s: float):
@@ -174,6 +261,10 @@ def main():
                        "GBps": 16.0 * total / (k_write * 1e-3) / 1e9 if k_write > 0 else None,
                        "hbm_frac": 16.0 * total / (k_write * 1e-3) / HBM_PEAK if k_write > 0 else None},
     }
+    if args.only in ("all", "frames"):
+        res["frames_exact"] = bench_frames(cv, W, torch, 3)
+    if args.only in ("all", "cube"):
+        res["cube_table"] = bench_cube(cv, W, torch, 2)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(res))

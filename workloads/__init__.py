@@ -3,7 +3,7 @@
 Holds input data and input generators only (no part of the search's
 arithmetic): the paper's colours, information patterns and thresholds
 (Table 1), the search grids of the benchmark configurations, seeded colour
-samples and the synthetic 4K frame generator.
+samples, the synthetic 4K frame generator and per-pixel information maps.
 """
 from __future__ import annotations
 
@@ -100,6 +100,20 @@ def frame(seed: int, height: int = 2160, width: int = 3840, sites: int = 64,
     return out
 
 
-def frames(seeds, height: int = 2160, width: int = 3840) -> np.ndarray:
-    """Stack of frames [len(seeds), height, width, 3]."""
-    return np.stack([frame(s, height, width) for s in seeds])
+def frames(seeds, height: int = 2160, width: int = 3840, workers: int = 8) -> np.ndarray:
+    """Stack of frames [len(seeds), height, width, 3] (each frame from its own
+    seed, generated on a few host threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+    seeds = list(seeds)
+    with ThreadPoolExecutor(max_workers=max(1, min(workers, len(seeds)))) as ex:
+        return np.stack(list(ex.map(lambda s: frame(s, height, width), seeds)))
+
+
+def info_map(seed: int, height: int = 2160, width: int = 3840, block: int = 16) -> np.ndarray:
+    """Per-pixel 3-bit information map [height, width] uint8: square blocks of
+    `block` pixels, each carrying a pattern drawn uniformly from 1..7 (the
+    seven patterns of Table 1), from a Philox stream keyed by `seed`."""
+    rng = np.random.Generator(np.random.Philox(key=seed))
+    bh, bw = -(-height // block), -(-width // block)
+    cells = rng.integers(1, 8, size=(bh, bw), dtype=np.uint8)
+    return np.repeat(np.repeat(cells, block, axis=0), block, axis=1)[:height, :width].copy()
