@@ -257,6 +257,81 @@ int cv_context_set_timing(cv_context* ctx, int on);
 int cv_context_kernel_time(cv_context* ctx, int phase, double* ms_host, int64_t* calls_host,
                            int reset);
 
+/* ---- Surrogate network ------------------------------------------------
+ *
+ * A multilayer perceptron dims[0] -> dims[1] -> ... -> dims[nlayers] with
+ * ReLU after every layer but the last.  The surrogate of the exact search is
+ * 3 -> 256 -> 256 -> 256 -> 37: input RGB / 255 - 1/2, outputs the largest
+ * valid radius of each of the 36 angle bins divided by 50 (the table of
+ * cv_pair_reduce) and a feasibility logit.  The paper describes no learned
+ * part; the network only proposes pairs that the exact predicate re-checks
+ * (cv_surrogate_infer), and its targets come from the exact search.
+ *
+ * Arithmetic: the input layer in FP32; every other layer multiplies BF16
+ * activations by BF16 copies of the weights with FP32 accumulation, adds the
+ * FP32 bias, and rounds hidden activations to BF16 after the ReLU.  The
+ * network owns FP32 master weights, their gradients and the Adam moments.
+ * Parameters are one flat FP32 array, layer by layer: W_l row-major
+ * [dims[l+1]][dims[l]], then b_l [dims[l+1]].  All array arguments are
+ * device pointers owned by the caller unless noted.
+ * Limits: 2 <= nlayers <= 8, dims[0] = 3, hidden widths multiples of 32 in
+ * [32, 1024], output width in [2, 256].
+ */
+typedef struct cv_mlp cv_mlp;
+
+#define CV_MLP_KEEP 0x1u  /* keep the activations for cv_mlp_backward        */
+#define CV_MLP_RGB8 0x2u  /* x is uint8 RGB [B][3] instead of float [B][3]   */
+
+/* Create / destroy.  Weights start at zero: set them with cv_mlp_set_params
+ * or cv_mlp_load.  Errors: CV_EINVAL, CV_EHIP. */
+int cv_mlp_create(cv_context* ctx, const int32_t* dims_host, int32_t nlayers, cv_mlp** out);
+int cv_mlp_destroy(cv_mlp* m);
+int cv_mlp_num_params(const cv_mlp* m, int64_t* n_host);
+
+/* Copy the flat FP32 parameters in (this also clears the Adam moments) or
+ * out, and the gradients of the last cv_mlp_backward out (either output may
+ * be NULL, not both).  Asynchronous on `stream`. */
+int cv_mlp_set_params(cv_mlp* m, const float* params, void* stream);
+int cv_mlp_get_params(const cv_mlp* m, float* params, float* grads, void* stream);
+
+/* Forward pass of B rows: x float [B][3] (or uint8 [B][3] with CV_MLP_RGB8)
+ * -> out float [B][dims[nlayers]].  With CV_MLP_KEEP (B <= 2^24) the hidden
+ * activations stay in the network for the next cv_mlp_backward; without it
+ * rows go through in chunks of 2^20 (B <= 2^30). */
+int cv_mlp_forward(cv_mlp* m, const void* x, int64_t B, float* out, uint32_t flags, void* stream);
+
+/* Training loss of B rows and its gradient with respect to the outputs.
+ * out [B][D] (D = dims[nlayers]); t_r [B][D-1] radius targets (a bin with
+ * t_r <= 0 carries no radius loss); t_f [B] feasibility targets in {0, 1}.
+ *   loss = (1/B) sum_s [ (1/(D-1)) sum_k [t_r > 0] huber_delta(out_k - t_r,k)
+ *                        + log(1 + e^z) - z t_f ],   z = out_{D-1}
+ * *loss: device float [1].  gout [B][D] (nullable) receives dloss/dout. */
+int cv_mlp_loss(cv_mlp* m, const float* out, const float* t_r, const float* t_f, int64_t B,
+                float huber_delta, float* loss, float* gout, void* stream);
+
+/* Gradients of sum(gout * out) with respect to all parameters, for the batch
+ * of the last kept forward pass (same x and B; CV_ESTATE otherwise).  The
+ * gradients stay in the network (cv_mlp_get_params reads them). */
+int cv_mlp_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, void* stream);
+
+/* One Adam step (Kingma & Ba 2015) with bias correction for step t >= 1 on
+ * the gradients of the last backward pass. */
+int cv_adam_step(cv_mlp* m, float lr, float beta1, float beta2, float eps, int64_t t, void* stream);
+
+/* Training rows from a whole-cube table (cv_table_row [2^24], indexed by
+ * colour id R<<16 | G<<8 | B, made on a grid of radius step dr): for each of
+ * the B colour ids, x = RGB / 255 - 1/2, t_r[k] = bin_ridx[k] * dr / 50,
+ * t_f = (count > 0).  Needs a 3 -> ... -> 37 network. */
+int cv_mlp_table_batch(cv_mlp* m, const int32_t* ids, const cv_table_row* table, int64_t B,
+                       double dr, float* x, float* t_r, float* t_f, void* stream);
+
+/* Parameters to / from a file (host path): magic "CVMLP01", int32 nlayers,
+ * int32 dims[nlayers+1], int64 count, float params[count], little-endian.
+ * Loading requires the same shape and clears the Adam moments.  Both
+ * synchronise the device. */
+int cv_mlp_save(const cv_mlp* m, const char* path);
+int cv_mlp_load(cv_mlp* m, const char* path);
+
 #ifdef __cplusplus
 }
 #endif

@@ -305,3 +305,15 @@ def distinct_colours(frames_u8: np.ndarray) -> np.ndarray:
     f = np.asarray(frames_u8).reshape(-1, 3).astype(np.uint32)
     ids = (f[:, 0] << 16) | (f[:, 1] << 8) | f[:, 2]
     return np.unique(ids)
+
+
+def adam_step(p, g, m, v, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8):
+    """One Adam step (Kingma & Ba 2015, Algorithm 1) in FP64: returns the new
+    (p, m, v).  m and v are the first and second moment estimates, t >= 1."""
+    p, g, m, v = (np.asarray(a, dtype=np.float64) for a in (p, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v

@@ -65,7 +65,12 @@ assert PATTERN_PAIR_DTYPE.itemsize == 12
 # Exported symbols (every one is declared in include/cvib.h).
 EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_convert",
            "cv_pair_search", "cv_pair_reduce", "cv_frames_resolve", "cv_context_set_timing",
-           "cv_context_kernel_time")
+           "cv_context_kernel_time", "cv_mlp_create", "cv_mlp_destroy", "cv_mlp_num_params",
+           "cv_mlp_set_params", "cv_mlp_get_params", "cv_mlp_forward", "cv_mlp_loss",
+           "cv_mlp_backward", "cv_adam_step", "cv_mlp_table_batch", "cv_mlp_save", "cv_mlp_load")
+CV_MLP_KEEP = 0x1
+CV_MLP_RGB8 = 0x2
+SURROGATE_DIMS = (3, 256, 256, 256, 37)
 
 _lib = None
 
@@ -90,6 +95,18 @@ def lib() -> C.CDLL:
         L.cv_context_set_timing.argtypes = [P, C.c_int]
         L.cv_context_kernel_time.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.POINTER(I64),
                                              C.c_int]
+        L.cv_mlp_create.argtypes = [P, P, C.c_int32, C.POINTER(C.c_void_p)]
+        L.cv_mlp_destroy.argtypes = [P]
+        L.cv_mlp_num_params.argtypes = [P, C.POINTER(I64)]
+        L.cv_mlp_set_params.argtypes = [P, P, P]
+        L.cv_mlp_get_params.argtypes = [P, P, P, P]
+        L.cv_mlp_forward.argtypes = [P, P, I64, P, C.c_uint32, P]
+        L.cv_mlp_loss.argtypes = [P, P, P, P, I64, C.c_float, P, P, P]
+        L.cv_mlp_backward.argtypes = [P, P, P, I64, P]
+        L.cv_adam_step.argtypes = [P, C.c_float, C.c_float, C.c_float, C.c_float, I64, P]
+        L.cv_mlp_table_batch.argtypes = [P, P, P, I64, C.c_double, P, P, P, P]
+        L.cv_mlp_save.argtypes = [P, C.c_char_p]
+        L.cv_mlp_load.argtypes = [P, C.c_char_p]
         for name in EXPORTS:
             if name != "cv_last_error":
                 getattr(L, name).restype = C.c_int
@@ -325,3 +342,124 @@ def frames_resolve(pixels: torch.Tensor, grid: Grid, rule: Rule, info: torch.Ten
                                    _dptr(out.frame_a), _dptr(out.frame_b), _dptr(out.resolved),
                                    CV_GRAPH if graph else 0, _stream()))
     return out
+
+
+# --------------------------------------------------------------------------
+# Surrogate network
+
+
+def init_params(dims, seed: int) -> np.ndarray:
+    """He-normal weights (std sqrt(2 / fan_in)) and zero biases, flat FP32 in
+    the library's layout (per layer W_l [d_{l+1}][d_l], then b_l), drawn from a
+    Philox stream keyed by `seed`."""
+    rng = np.random.Generator(np.random.Philox(key=seed))
+    parts = []
+    for l in range(len(dims) - 1):
+        parts.append(rng.normal(0.0, np.sqrt(2.0 / dims[l]), (dims[l + 1], dims[l])).ravel())
+        parts.append(np.zeros(dims[l + 1]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def split_params(flat, dims):
+    """Flat parameters -> ([W_l], [b_l]) views."""
+    flat = np.asarray(flat)
+    Ws, bs, o = [], [], 0
+    for l in range(len(dims) - 1):
+        n = dims[l + 1] * dims[l]
+        Ws.append(flat[o:o + n].reshape(dims[l + 1], dims[l]))
+        o += n
+        bs.append(flat[o:o + dims[l + 1]])
+        o += dims[l + 1]
+    return Ws, bs
+
+
+class MLP:
+    """A cv_mlp: FP32 master weights, gradients and Adam moments on one GPU."""
+
+    def __init__(self, dims=SURROGATE_DIMS, ctx: Context | None = None):
+        self.ctx = ctx or context()
+        self.dims = tuple(int(d) for d in dims)
+        d = (C.c_int32 * len(self.dims))(*self.dims)
+        h = C.c_void_p()
+        _check(lib().cv_mlp_create(self.ctx.handle, d, len(self.dims) - 1, C.byref(h)))
+        self.handle = h
+        n = C.c_int64(0)
+        _check(lib().cv_mlp_num_params(h, C.byref(n)))
+        self.nparams = n.value
+        self.device = torch.device("cuda", self.ctx.device)
+
+    def set_params(self, flat):
+        t = torch.as_tensor(np.asarray(flat, dtype=np.float32) if not torch.is_tensor(flat) else flat)
+        t = t.to(self.device, torch.float32).contiguous()
+        if t.numel() != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {t.numel()}")
+        _check(lib().cv_mlp_set_params(self.handle, _dptr(t), _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    def params(self) -> torch.Tensor:
+        t = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        _check(lib().cv_mlp_get_params(self.handle, _dptr(t), None, _stream()))
+        return t
+
+    def grads(self) -> torch.Tensor:
+        t = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        _check(lib().cv_mlp_get_params(self.handle, None, _dptr(t), _stream()))
+        return t
+
+    def forward(self, x: torch.Tensor, keep: bool = False, out: torch.Tensor | None = None):
+        """x: float32 [B, 3] or uint8 RGB [B, 3] on the GPU -> float32 [B, dims[-1]]."""
+        if not x.is_cuda or x.dim() != 2 or x.shape[1] != 3 or x.dtype not in (torch.float32, torch.uint8):
+            raise ValueError("x must be a float32 or uint8 CUDA tensor of shape [B, 3]")
+        x = x.contiguous()
+        B = x.shape[0]
+        if out is None:
+            out = torch.empty((B, self.dims[-1]), dtype=torch.float32, device=self.device)
+        flags = (CV_MLP_KEEP if keep else 0) | (CV_MLP_RGB8 if x.dtype == torch.uint8 else 0)
+        _check(lib().cv_mlp_forward(self.handle, _dptr(x), B, _dptr(out), flags, _stream()))
+        return out
+
+    def loss(self, out, t_r, t_f, delta: float, want_grad: bool = True):
+        B = out.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        gout = torch.empty_like(out) if want_grad else None
+        _check(lib().cv_mlp_loss(self.handle, _dptr(out.contiguous()), _dptr(t_r.contiguous()),
+                                 _dptr(t_f.contiguous()), B, float(delta), _dptr(loss), _dptr(gout),
+                                 _stream()))
+        return loss, gout
+
+    def backward(self, x, gout):
+        _check(lib().cv_mlp_backward(self.handle, _dptr(x.contiguous()), _dptr(gout.contiguous()),
+                                     x.shape[0], _stream()))
+
+    def adam_step(self, lr: float, t: int, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        _check(lib().cv_adam_step(self.handle, lr, beta1, beta2, eps, int(t), _stream()))
+
+    def table_batch(self, ids: torch.Tensor, table: torch.Tensor, dr: float):
+        """Training rows for colour ids (int32 [B]) from a whole-cube table
+        (uint8 [2^24, 40]): (x [B, 3], t_r [B, 36], t_f [B])."""
+        if table.shape[0] != 1 << 24 or ids.dtype != torch.int32:
+            raise ValueError("table must hold all 2^24 rows and ids must be int32")
+        B = ids.shape[0]
+        x = torch.empty((B, 3), dtype=torch.float32, device=self.device)
+        tr = torch.empty((B, 36), dtype=torch.float32, device=self.device)
+        tf = torch.empty(B, dtype=torch.float32, device=self.device)
+        _check(lib().cv_mlp_table_batch(self.handle, _dptr(ids.contiguous()), _dptr(table), B,
+                                        float(dr), _dptr(x), _dptr(tr), _dptr(tf), _stream()))
+        return x, tr, tf
+
+    def save(self, path: str):
+        _check(lib().cv_mlp_save(self.handle, os.fsencode(path)))
+
+    def load(self, path: str):
+        _check(lib().cv_mlp_load(self.handle, os.fsencode(path)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().cv_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

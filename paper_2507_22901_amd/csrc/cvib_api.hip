@@ -170,29 +170,7 @@ int cv_context::collect() {
 
 using cvib::fail;
 
-#define CV_GUARD_BEGIN try {
-#define CV_GUARD_END                                                     \
-    }                                                                    \
-    catch (const std::exception& ex) {                                   \
-        return fail(CV_ESTATE, std::string("internal error: ") + ex.what()); \
-    }                                                                    \
-    catch (...) {                                                        \
-        return fail(CV_ESTATE, "internal error");                        \
-    }
-
-namespace {
-// Make the context's device current for the duration of a call.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-} // namespace
+using cvib::DeviceGuard;
 
 extern "C" {
 

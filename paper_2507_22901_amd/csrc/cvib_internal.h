@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <exception>
 #include <string>
 
 #include "../../include/cvib.h"
@@ -28,6 +29,29 @@ int hip_fail(hipError_t e, const char* what);
         hipError_t _e = (call);                             \
         if (_e != hipSuccess) return ::cvib::hip_fail(_e, #call); \
     } while (0)
+
+// Every C entry point runs inside this guard: no exception crosses the ABI.
+#define CV_GUARD_BEGIN try {
+#define CV_GUARD_END                                                                 \
+    }                                                                                \
+    catch (const std::exception& ex) {                                               \
+        return ::cvib::fail(CV_ESTATE, std::string("internal error: ") + ex.what()); \
+    }                                                                                \
+    catch (...) {                                                                    \
+        return ::cvib::fail(CV_ESTATE, "internal error");                            \
+    }
+
+// Make a device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
 
 // Validated, device-ready form of a grid.
 struct GridDev {

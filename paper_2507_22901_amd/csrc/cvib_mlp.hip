@@ -1,0 +1,803 @@
+// Surrogate network: a multilayer perceptron (ReLU hidden layers, linear
+// output) that maps a target colour to the largest valid radius of each
+// angle bin plus a feasibility logit.  It is trained and evaluated by the
+// kernels in this file:
+//   - the input layer (3 inputs) is a per-element FP32 kernel on the vector
+//     ALUs: a 3-long reduction has nothing to give to a matrix core;
+//   - every other layer is a BF16 matrix product on the matrix cores
+//     (v_mfma_f32_16x16x32_bf16, FP32 accumulation) with the bias, ReLU or
+//     ReLU-derivative mask fused into the epilogue;
+//   - weight gradients reduce over the batch with a fixed split and a
+//     fixed-order sum of the partials, so training is bitwise repeatable;
+//   - FP32 master weights with Adam; BF16 copies feed the matrix cores.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "cvib_internal.h"
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace cvib {
+namespace {
+
+constexpr int kMaxLayers = 8;
+constexpr int kMaxIn = 4;          // input width handled by the vector-ALU layer
+constexpr int kMaxHidden = 1024;
+constexpr int kMaxOut = 256;
+constexpr int64_t kSplitRows = 512;   // batch rows per split of a weight-gradient reduction
+constexpr int64_t kInferChunk = 1 << 20;  // rows per forward chunk when nothing is kept
+
+int32_t pad32(int32_t d) { return (d + 31) / 32 * 32; }
+
+// ---------------------------------------------------------------------------
+// Matrix-core product.  C[M][N] = sum_k A(m, k) B(n, k) over one split of k.
+// A_KC: A is stored [m][k] (k contiguous), else [k][m].  B_KC: B is stored
+// [n][k], else [k][n].  Tiles of 64 x 64 outputs, 32-deep k steps, 4 waves of
+// 32 x 32 (2 x 2 MFMA tiles of 16 x 16).  LDS keeps both tiles k-contiguous
+// (row pitch 40 elements = 80 bytes) so that each lane's fragment (8
+// consecutive k) is one 16-byte LDS read.
+//
+// MFMA 16x16x32 BF16 operand layout (lane l = 0..63): A row l % 16, k
+// 8 (l / 16) .. + 7; B column l % 16, same k; result rows 4 (l / 16) .. + 3,
+// column l % 16.
+enum { EPI_RELU_BF16 = 0, EPI_BIAS_F32 = 1, EPI_MASK_BF16 = 2, EPI_PARTIAL_F32 = 3 };
+
+struct GemmArgs {
+    const bf16* A;
+    int64_t lda;
+    const bf16* B;
+    int64_t ldb;
+    int32_t M, N, K, kchunk;   // kchunk: reduction length per blockIdx.z (multiple of 32)
+    const float* bias;         // [N]
+    bf16* cb;                  // bf16 result
+    float* cf;                 // fp32 result / partials
+    int64_t ldc;
+    int64_t zstride;           // partials: elements between splits
+    const bf16* mask;          // ReLU-derivative mask source (post-ReLU activations)
+    int64_t ldm;
+    int32_t nstore;            // result columns written (<= N)
+};
+
+constexpr int kTile = 64, kDepth = 32, kPitch = 40;
+
+template <bool KC>
+__device__ __forceinline__ void load_tile(const bf16* __restrict__ P, int64_t ld, int32_t r0,
+                                          int32_t R, int32_t k0, int32_t ke, bf16* s, int tid) {
+    if constexpr (KC) {
+        // 64 rows x 32 k: thread -> (row tid / 4, 8 k at 8 (tid % 4))
+        const int r = tid >> 2, c = (tid & 3) * 8;
+        bf16x8 v = {};
+        if (r0 + r < R && k0 + c < ke) v = *reinterpret_cast<const bf16x8*>(P + (int64_t)(r0 + r) * ld + k0 + c);
+        *reinterpret_cast<bf16x8*>(s + r * kPitch + c) = v;
+    } else {
+        // 32 k x 64 rows stored k-major: thread -> (k tid / 8, 8 rows at 8 (tid % 8))
+        const int kr = tid >> 3, c = (tid & 7) * 8;
+        bf16x8 v = {};
+        if (k0 + kr < ke && r0 + c < R) v = *reinterpret_cast<const bf16x8*>(P + (int64_t)(k0 + kr) * ld + r0 + c);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[(c + e) * kPitch + kr] = v[e];
+    }
+}
+
+template <bool A_KC, bool B_KC, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+    __shared__ __attribute__((aligned(16))) bf16 sA[kTile * kPitch];
+    __shared__ __attribute__((aligned(16))) bf16 sB[kTile * kPitch];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int32_t m0 = (int32_t)blockIdx.x * kTile, n0 = (int32_t)blockIdx.y * kTile;
+    const int32_t kb = (int32_t)blockIdx.z * a.kchunk;
+    const int32_t ke = min(a.K, kb + a.kchunk);
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    for (int32_t k0 = kb; k0 < ke; k0 += kDepth) {
+        load_tile<A_KC>(a.A, a.lda, m0, a.M, k0, ke, sA, tid);
+        load_tile<B_KC>(a.B, a.ldb, n0, a.N, k0, ke, sB, tid);
+        __syncthreads();
+        bf16x8 fa[2], fb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            fa[i] = *reinterpret_cast<const bf16x8*>(sA + (32 * wm + 16 * i + fr) * kPitch + fk);
+            fb[i] = *reinterpret_cast<const bf16x8*>(sB + (32 * wn + 16 * i + fr) * kPitch + fk);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int32_t m = m0 + 32 * wm + 16 * i + (lane >> 4) * 4 + e;
+                const int32_t n = n0 + 32 * wn + 16 * j + fr;
+                if (m >= a.M || n >= a.nstore) continue;
+                const float v = acc[i][j][e];
+                if constexpr (EPI == EPI_RELU_BF16) {
+                    a.cb[(int64_t)m * a.ldc + n] = (bf16)fmaxf(v + a.bias[n], 0.0f);
+                } else if constexpr (EPI == EPI_BIAS_F32) {
+                    a.cf[(int64_t)m * a.ldc + n] = v + a.bias[n];
+                } else if constexpr (EPI == EPI_MASK_BF16) {
+                    const float h = (float)a.mask[(int64_t)m * a.ldm + n];
+                    a.cb[(int64_t)m * a.ldc + n] = (bf16)(h > 0.0f ? v : 0.0f);
+                } else {
+                    a.cf[(int64_t)blockIdx.z * a.zstride + (int64_t)m * a.ldc + n] = v;
+                }
+            }
+}
+
+template <bool A_KC, bool B_KC, int EPI>
+int gemm(const GemmArgs& a, int32_t splits, hipStream_t s) {
+    // vector loads need 8-element alignment along every contiguous dimension
+    const bool ok = (a.lda % 8 == 0) && (a.ldb % 8 == 0) && (A_KC ? a.K % 8 == 0 : a.M % 8 == 0) &&
+                    (B_KC ? a.K % 8 == 0 : a.N % 8 == 0) && a.kchunk % kDepth == 0 && a.M > 0 &&
+                    a.N > 0 && a.K > 0 && splits >= 1 && (int64_t)splits * a.kchunk >= a.K;
+    if (!ok) return fail(CV_ESTATE, "internal: matrix product shape");
+    const dim3 grid((unsigned)((a.M + kTile - 1) / kTile), (unsigned)((a.N + kTile - 1) / kTile),
+                    (unsigned)splits);
+    hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI>), grid, dim3(256), 0, s, a);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Input layer on the vector ALUs: H1[s][o] = relu(b0[o] + sum_c W0[o][c] x_c)
+// with x either FP32 [B][d0] or 8-bit RGB (x = v / 255 - 1/2).
+template <bool RGB8>
+__global__ void k_input_layer(const void* __restrict__ xin, int64_t B, int32_t d0, int32_t d1,
+                              const float* __restrict__ W0, const float* __restrict__ b0,
+                              bf16* __restrict__ H1) {
+    const int64_t total = B * d1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const int64_t s = t / d1;
+        const int32_t o = (int32_t)(t - s * d1);
+        float acc = b0[o];
+        for (int32_t c = 0; c < d0; ++c) {
+            float x;
+            if constexpr (RGB8) x = (float)static_cast<const uint8_t*>(xin)[s * 3 + c] * (1.0f / 255.0f) - 0.5f;
+            else x = static_cast<const float*>(xin)[s * d0 + c];
+            acc = fmaf(W0[o * d0 + c], x, acc);
+        }
+        H1[t] = (bf16)fmaxf(acc, 0.0f);
+    }
+}
+
+// Input-layer gradients: partial sums over one split of the batch, per output
+// unit o: [z][o][c] = sum_s G1[s][o] x_c (c < d0) and [z][o][d0] = sum_s G1[s][o].
+__global__ void k_input_grad(const bf16* __restrict__ G1, int64_t ldg, const float* __restrict__ x,
+                             int64_t B, int32_t d0, int32_t d1, float* __restrict__ part) {
+    const int32_t o = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (o >= d1) return;
+    const int64_t s0 = (int64_t)blockIdx.y * kSplitRows, s1 = min(B, s0 + kSplitRows);
+    float acc[kMaxIn + 1] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int64_t s = s0; s < s1; ++s) {
+        const float g = (float)G1[s * ldg + o];
+        for (int32_t c = 0; c < d0; ++c) acc[c] = fmaf(g, x[s * d0 + c], acc[c]);
+        acc[kMaxIn] += g;
+    }
+    float* dst = part + ((int64_t)blockIdx.y * d1 + o) * (d0 + 1);
+    for (int32_t c = 0; c < d0; ++c) dst[c] = acc[c];
+    dst[d0] = acc[kMaxIn];
+}
+
+__global__ void k_input_grad_sum(const float* __restrict__ part, int32_t splits, int32_t d0,
+                                 int32_t d1, float* __restrict__ gW0, float* __restrict__ gb0) {
+    const int32_t t = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int32_t per = d0 + 1;
+    if (t >= d1 * per) return;
+    float acc = 0.0f;
+    for (int32_t z = 0; z < splits; ++z) acc += part[(int64_t)z * d1 * per + t];
+    const int32_t o = t / per, c = t - o * per;
+    if (c < d0) gW0[o * d0 + c] = acc;
+    else gb0[o] = acc;
+}
+
+// Column sums of G over one split of the batch (bias gradients).
+__global__ void k_colsum(const bf16* __restrict__ G, int64_t ldg, int64_t B, int32_t ncols,
+                         float* __restrict__ part) {
+    const int32_t c = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (c >= ncols) return;
+    const int64_t s0 = (int64_t)blockIdx.y * kSplitRows, s1 = min(B, s0 + kSplitRows);
+    float acc = 0.0f;
+    for (int64_t s = s0; s < s1; ++s) acc += (float)G[s * ldg + c];
+    part[(int64_t)blockIdx.y * ncols + c] = acc;
+}
+
+// Fixed-order sum of split partials [z][rows][ldp] into out[r][c] (r < rows, c < cols).
+__global__ void k_sum_splits(const float* __restrict__ part, int32_t splits, int64_t zstride,
+                             int32_t rows, int32_t cols, int64_t ldp, float* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rows * cols) return;
+    const int32_t r = (int32_t)(t / cols), c = (int32_t)(t - (int64_t)r * cols);
+    float acc = 0.0f;
+    for (int32_t z = 0; z < splits; ++z) acc += part[z * zstride + (int64_t)r * ldp + c];
+    out[t] = acc;
+}
+
+// FP32 output gradient -> BF16, zero-padded to the padded output width.
+__global__ void k_grad_to_bf16(const float* __restrict__ g, int64_t B, int32_t d, int32_t dp,
+                               bf16* __restrict__ G) {
+    const int64_t total = B * dp;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const int64_t s = t / dp;
+        const int32_t c = (int32_t)(t - s * dp);
+        G[t] = (bf16)(c < d ? g[s * d + c] : 0.0f);
+    }
+}
+
+// FP32 master weights -> BF16 copy [dp][din], rows d..dp-1 zero.
+__global__ void k_weights_bf16(const float* __restrict__ W, int32_t d, int32_t dp, int32_t din,
+                               bf16* __restrict__ Wb) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)dp * din) return;
+    const int32_t o = (int32_t)(t / din);
+    Wb[t] = (bf16)(o < d ? W[t] : 0.0f);
+}
+
+// Loss of a batch and its gradient with respect to the outputs.  Per sample s
+// with outputs z[0..D-1] (D-1 radii and the feasibility logit):
+//   l_s = (1/(D-1)) sum_k [t_k > 0] huber(z_k - t_k) + softplus(z) - z f
+// gradient dl/dz / B.  Per-block partial sums, then a fixed-order total.
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ out, const float* __restrict__ tr,
+                                              const float* __restrict__ tf, int64_t B, int32_t D,
+                                              float delta, float* __restrict__ gout,
+                                              float* __restrict__ part) {
+    __shared__ float s_sum[256];
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float ls = 0.0f;
+    if (s < B) {
+        const int32_t R = D - 1;
+        const float invR = 1.0f / (float)R, invB = 1.0f / (float)B;
+        for (int32_t k = 0; k < R; ++k) {
+            const float t = tr[s * R + k];
+            float g = 0.0f;
+            if (t > 0.0f) {
+                const float e = out[s * D + k] - t, ae = fabsf(e);
+                ls += (ae <= delta ? 0.5f * e * e : delta * (ae - 0.5f * delta)) * invR;
+                g = (ae <= delta ? e : copysignf(delta, e)) * invR;
+            }
+            if (gout) gout[s * D + k] = g * invB;
+        }
+        const float z = out[s * D + R], f = tf[s];
+        ls += fmaxf(z, 0.0f) - z * f + log1pf(expf(-fabsf(z)));
+        if (gout) gout[s * D + R] = (1.0f / (1.0f + expf(-z)) - f) * invB;
+    }
+    s_sum[threadIdx.x] = ls;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s_sum[threadIdx.x] += s_sum[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s_sum[0];
+}
+
+__global__ void k_loss_total(const float* __restrict__ part, int32_t nparts, int64_t B,
+                             float* __restrict__ loss) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = 0.0;
+    for (int32_t k = 0; k < nparts; ++k) acc += part[k];
+    *loss = (float)(acc / (double)B);
+}
+
+// Adam: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+// p -= lr (m c1) / (sqrt(v c2) + eps) with c1 = 1/(1-b1^t), c2 = 1/(1-b2^t).
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// Training rows from a table of the whole cube: x = RGB / 255 - 1/2 of colour
+// id, radius targets ridx * dr / 50 per bin (0 = no valid radius), feasibility
+// = count > 0.
+__global__ void k_table_batch(const int32_t* __restrict__ ids, const cv_table_row* __restrict__ table,
+                              int64_t B, float rscale, float* __restrict__ x, float* __restrict__ tr,
+                              float* __restrict__ tf) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B) return;
+    const uint32_t id = (uint32_t)ids[s] & 0xFFFFFFu;
+    x[s * 3 + 0] = (float)(id >> 16) * (1.0f / 255.0f) - 0.5f;
+    x[s * 3 + 1] = (float)((id >> 8) & 255u) * (1.0f / 255.0f) - 0.5f;
+    x[s * 3 + 2] = (float)(id & 255u) * (1.0f / 255.0f) - 0.5f;
+    const cv_table_row& r = table[id];
+    for (int k = 0; k < 36; ++k) tr[s * 36 + k] = (float)r.bin_ridx[k] * rscale;
+    tf[s] = r.count > 0 ? 1.0f : 0.0f;
+}
+
+unsigned blocks(int64_t n, int per) {
+    int64_t b = (n + per - 1) / per;
+    if (b < 1) b = 1;
+    if (b > (1 << 20)) b = 1 << 20;
+    return (unsigned)b;
+}
+
+} // namespace
+} // namespace cvib
+
+
+// ---------------------------------------------------------------------------
+// The network object.
+
+struct cv_mlp {
+    cv_context* ctx = nullptr;
+    int device = 0;
+    int32_t L = 0;                      // layers
+    int32_t dims[cvib::kMaxLayers + 1] = {};
+    int32_t dpad[cvib::kMaxLayers + 1] = {};  // d_l rounded up to 32 (l >= 1)
+    int64_t woff[cvib::kMaxLayers] = {}, boff[cvib::kMaxLayers] = {};
+    int64_t nparam = 0;
+    float* params = nullptr;  // FP32 master weights, per layer W_l [d_{l+1}][d_l] then b_l
+    float* grads = nullptr;
+    float* adam_m = nullptr;
+    float* adam_v = nullptr;
+    bf16* wb[cvib::kMaxLayers] = {};    // BF16 W_l, l >= 1, [dpad_{l+1}][d_l]
+    int64_t bcap = 0;                   // rows of the activation buffers
+    bf16* h[cvib::kMaxLayers] = {};     // post-ReLU H_l, l = 1..L-1, [bcap][d_l]
+    bf16* g[2] = {nullptr, nullptr};    // back-propagated gradients [bcap][gw]
+    int32_t gw = 0;                     // widest padded layer
+    float* part = nullptr;              // split partials
+    size_t part_bytes = 0;
+    float* lpart = nullptr;             // loss partials
+    int64_t lpart_n = 0;
+    int64_t fwd_rows = -1;              // batch of the last kept forward
+};
+
+namespace cvib {
+namespace {
+
+int grow(void** p, size_t* have, size_t want) {
+    if (*have >= want) return CV_OK;
+    if (*p) CV_HIP(hipFree(*p));
+    *p = nullptr;
+    *have = 0;
+    hipError_t e = hipMalloc(p, want);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(e, "hipMalloc(network workspace)");
+    }
+    *have = want;
+    return CV_OK;
+}
+
+// Activation and gradient buffers for `rows` rows.
+int ensure_rows(cv_mlp* m, int64_t rows) {
+    if (rows <= m->bcap) return CV_OK;
+    CV_HIP(hipDeviceSynchronize());
+    for (int l = 1; l < m->L; ++l) {
+        if (m->h[l]) CV_HIP(hipFree(m->h[l]));
+        m->h[l] = nullptr;
+    }
+    for (bf16*& q : m->g) {
+        if (q) CV_HIP(hipFree(q));
+        q = nullptr;
+    }
+    m->bcap = 0;
+    for (int l = 1; l < m->L; ++l)
+        CV_HIP(hipMalloc((void**)&m->h[l], (size_t)rows * m->dims[l] * sizeof(bf16)));
+    for (bf16*& q : m->g) CV_HIP(hipMalloc((void**)&q, (size_t)rows * m->gw * sizeof(bf16)));
+    m->bcap = rows;
+    return CV_OK;
+}
+
+int ensure_part(cv_mlp* m, size_t bytes) {
+    return grow((void**)&m->part, &m->part_bytes, bytes);
+}
+
+int refresh_bf16(cv_mlp* m, hipStream_t s) {
+    for (int l = 1; l < m->L; ++l) {
+        const int64_t n = (int64_t)m->dpad[l + 1] * m->dims[l];
+        hipLaunchKernelGGL(k_weights_bf16, dim3(blocks(n, 256)), dim3(256), 0, s,
+                           m->params + m->woff[l], m->dims[l + 1], m->dpad[l + 1], m->dims[l], m->wb[l]);
+    }
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
+// Hidden layers and the output layer for rows already in H_1.
+int forward_tail(cv_mlp* m, bf16* const* H, int64_t rows, float* out, hipStream_t s) {
+    int rc;
+    for (int l = 1; l < m->L; ++l) {
+        GemmArgs a = {};
+        a.A = H[l];
+        a.lda = m->dims[l];
+        a.B = m->wb[l];
+        a.ldb = m->dims[l];
+        a.M = (int32_t)rows;
+        a.N = m->dpad[l + 1];
+        a.K = m->dims[l];
+        a.kchunk = pad32(a.K);
+        a.bias = m->params + m->boff[l];
+        a.nstore = m->dims[l + 1];
+        if (l + 1 < m->L) {
+            a.cb = H[l + 1];
+            a.ldc = m->dims[l + 1];
+            rc = gemm<true, true, EPI_RELU_BF16>(a, 1, s);
+        } else {
+            a.cf = out;
+            a.ldc = m->dims[m->L];
+            rc = gemm<true, true, EPI_BIAS_F32>(a, 1, s);
+        }
+        if (rc != CV_OK) return rc;
+    }
+    return CV_OK;
+}
+
+// Forward pass.  keep: the activations of all rows stay for a backward pass;
+// otherwise rows go through in chunks that reuse the buffers.
+int run_forward(cv_mlp* m, const void* x, bool rgb8, int64_t rows, float* out, bool keep,
+                hipStream_t s) {
+    int rc;
+    const int64_t chunk = keep ? rows : std::min(rows, kInferChunk);
+    if ((rc = ensure_rows(m, chunk)) != CV_OK) return rc;
+    for (int64_t r0 = 0; r0 < rows; r0 += chunk) {
+        const int64_t nr = std::min(chunk, rows - r0);
+        const void* xs = rgb8 ? (const void*)((const uint8_t*)x + r0 * 3)
+                              : (const void*)((const float*)x + r0 * m->dims[0]);
+        if (rgb8)
+            hipLaunchKernelGGL(k_input_layer<true>, dim3(blocks(nr * m->dims[1], 256)), dim3(256), 0, s,
+                               xs, nr, m->dims[0], m->dims[1], m->params + m->woff[0],
+                               m->params + m->boff[0], m->h[1]);
+        else
+            hipLaunchKernelGGL(k_input_layer<false>, dim3(blocks(nr * m->dims[1], 256)), dim3(256), 0, s,
+                               xs, nr, m->dims[0], m->dims[1], m->params + m->woff[0],
+                               m->params + m->boff[0], m->h[1]);
+        CV_HIP(hipGetLastError());
+        if ((rc = forward_tail(m, m->h, nr, out + r0 * m->dims[m->L], s)) != CV_OK) return rc;
+    }
+    m->fwd_rows = keep ? rows : -1;
+    return CV_OK;
+}
+
+int run_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, hipStream_t s) {
+    int rc;
+    const int32_t L = m->L;
+    const int32_t splits = (int32_t)((B + kSplitRows - 1) / kSplitRows);
+    // partials: the widest weight gradient, or the input layer's, or a column sum
+    size_t need = 0;
+    for (int l = 0; l < L; ++l) {
+        const size_t w = (size_t)splits * m->dpad[l + 1] * (l == 0 ? (m->dims[0] + 1) : m->dims[l]);
+        need = std::max(need, w);
+    }
+    if ((rc = ensure_part(m, need * sizeof(float))) != CV_OK) return rc;
+    bf16* Gc = m->g[0];  // gradient w.r.t. the pre-activations of layer l's output
+    bf16* Gn = m->g[1];
+    hipLaunchKernelGGL(k_grad_to_bf16, dim3(blocks(B * m->dpad[L], 256)), dim3(256), 0, s, gout, B,
+                       m->dims[L], m->dpad[L], Gc);
+    CV_HIP(hipGetLastError());
+    int32_t ldg = m->dpad[L];
+    for (int l = L - 1; l >= 1; --l) {
+        const int32_t dout = m->dims[l + 1], dop = m->dpad[l + 1], din = m->dims[l];
+        // weight gradient: dW_l[o][i] = sum_s G[s][o] H_l[s][i]
+        GemmArgs a = {};
+        a.A = Gc;
+        a.lda = ldg;
+        a.B = m->h[l];
+        a.ldb = din;
+        a.M = dop;
+        a.N = din;
+        a.K = (int32_t)B;
+        a.kchunk = (int32_t)kSplitRows;
+        a.cf = m->part;
+        a.ldc = din;
+        a.zstride = (int64_t)dop * din;
+        a.nstore = din;
+        if ((rc = gemm<false, false, EPI_PARTIAL_F32>(a, splits, s)) != CV_OK) return rc;
+        hipLaunchKernelGGL(k_sum_splits, dim3(blocks((int64_t)dout * din, 256)), dim3(256), 0, s,
+                           m->part, splits, (int64_t)dop * din, dout, din, (int64_t)din,
+                           m->grads + m->woff[l]);
+        CV_HIP(hipGetLastError());
+        // bias gradient; its partials follow the weight partials' use (same stream)
+        hipLaunchKernelGGL(k_colsum, dim3((unsigned)((dout + 255) / 256), (unsigned)splits), dim3(256),
+                           0, s, Gc, (int64_t)ldg, B, dout, m->part);
+        hipLaunchKernelGGL(k_sum_splits, dim3(blocks(dout, 256)), dim3(256), 0, s, m->part, splits,
+                           (int64_t)dout, 1, dout, (int64_t)dout, m->grads + m->boff[l]);
+        CV_HIP(hipGetLastError());
+        // input gradient through W_l and the ReLU of H_l
+        GemmArgs d = {};
+        d.A = Gc;
+        d.lda = ldg;
+        d.B = m->wb[l];
+        d.ldb = din;
+        d.M = (int32_t)B;
+        d.N = din;
+        d.K = dop;
+        d.kchunk = dop;
+        d.cb = Gn;
+        d.ldc = din;
+        d.mask = m->h[l];
+        d.ldm = din;
+        d.nstore = din;
+        if ((rc = gemm<true, false, EPI_MASK_BF16>(d, 1, s)) != CV_OK) return rc;
+        std::swap(Gc, Gn);
+        ldg = din;
+    }
+    // input layer
+    const int32_t d0 = m->dims[0], d1 = m->dims[1];
+    hipLaunchKernelGGL(k_input_grad, dim3((unsigned)((d1 + 255) / 256), (unsigned)splits), dim3(256), 0,
+                       s, Gc, (int64_t)ldg, x, B, d0, d1, m->part);
+    hipLaunchKernelGGL(k_input_grad_sum, dim3(blocks((int64_t)d1 * (d0 + 1), 256)), dim3(256), 0, s,
+                       m->part, splits, d0, d1, m->grads + m->woff[0], m->grads + m->boff[0]);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
+void free_mlp(cv_mlp* m) {
+    void* ps[] = {m->params, m->grads, m->adam_m, m->adam_v, m->g[0], m->g[1], m->part, m->lpart};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    for (int l = 0; l < kMaxLayers; ++l) {
+        if (m->wb[l]) (void)hipFree(m->wb[l]);
+        if (m->h[l]) (void)hipFree(m->h[l]);
+    }
+    delete m;
+}
+
+const char kMagic[8] = {'C', 'V', 'M', 'L', 'P', '0', '1', '\0'};
+
+} // namespace
+} // namespace cvib
+
+using cvib::DeviceGuard;
+using cvib::fail;
+
+extern "C" {
+
+int cv_mlp_create(cv_context* ctx, const int32_t* dims, int32_t nlayers, cv_mlp** out) {
+    CV_GUARD_BEGIN
+    if (!ctx || !dims || !out) return fail(CV_EINVAL, "null argument");
+    *out = nullptr;
+    if (nlayers < 2 || nlayers > cvib::kMaxLayers)
+        return fail(CV_EINVAL, "nlayers must be in [2, " + std::to_string(cvib::kMaxLayers) + "]");
+    if (dims[0] < 1 || dims[0] > cvib::kMaxIn) return fail(CV_EINVAL, "dims[0] must be in [1, 4]");
+    if (dims[0] != 3) return fail(CV_EINVAL, "dims[0] must be 3 (an RGB colour)");
+    for (int l = 1; l < nlayers; ++l)
+        if (dims[l] < 32 || dims[l] > cvib::kMaxHidden || dims[l] % 32 != 0)
+            return fail(CV_EINVAL, "hidden widths must be multiples of 32 in [32, 1024]");
+    if (dims[nlayers] < 2 || dims[nlayers] > cvib::kMaxOut)
+        return fail(CV_EINVAL, "output width must be in [2, 256]");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(CV_EHIP, "hipSetDevice failed");
+    cv_mlp* m = new cv_mlp();
+    m->ctx = ctx;
+    m->device = ctx->device;
+    m->L = nlayers;
+    int64_t off = 0;
+    for (int l = 0; l <= nlayers; ++l) {
+        m->dims[l] = dims[l];
+        m->dpad[l] = l == 0 ? dims[0] : cvib::pad32(dims[l]);
+        m->gw = std::max(m->gw, m->dpad[l]);
+    }
+    for (int l = 0; l < nlayers; ++l) {
+        m->woff[l] = off;
+        off += (int64_t)dims[l + 1] * dims[l];
+        m->boff[l] = off;
+        off += dims[l + 1];
+    }
+    m->nparam = off;
+    const size_t pb = (size_t)off * sizeof(float);
+    hipError_t e = hipSuccess;
+    float** arrs[] = {&m->params, &m->grads, &m->adam_m, &m->adam_v};
+    for (float** a : arrs)
+        if (e == hipSuccess) e = hipMalloc((void**)a, pb);
+    for (int l = 1; l < nlayers && e == hipSuccess; ++l)
+        e = hipMalloc((void**)&m->wb[l], (size_t)m->dpad[l + 1] * dims[l] * sizeof(bf16));
+    for (float** a : arrs)
+        if (e == hipSuccess) e = hipMemset(*a, 0, pb);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        cvib::free_mlp(m);
+        return cvib::hip_fail(e, "network allocation");
+    }
+    int rc = cvib::refresh_bf16(m, nullptr);
+    if (rc == CV_OK) rc = (hipDeviceSynchronize() == hipSuccess) ? CV_OK : fail(CV_EHIP, "sync");
+    if (rc != CV_OK) {
+        cvib::free_mlp(m);
+        return rc;
+    }
+    *out = m;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_mlp_destroy(cv_mlp* m) {
+    CV_GUARD_BEGIN
+    if (!m) return CV_OK;
+    DeviceGuard dg(m->device);
+    (void)hipDeviceSynchronize();
+    cvib::free_mlp(m);
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_mlp_num_params(const cv_mlp* m, int64_t* n_host) {
+    CV_GUARD_BEGIN
+    if (!m || !n_host) return fail(CV_EINVAL, "null argument");
+    *n_host = m->nparam;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_mlp_set_params(cv_mlp* m, const float* params, void* stream) {
+    CV_GUARD_BEGIN
+    if (!m || !params) return fail(CV_EINVAL, "null argument");
+    DeviceGuard dg(m->device);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t pb = (size_t)m->nparam * sizeof(float);
+    CV_HIP(hipMemcpyAsync(m->params, params, pb, hipMemcpyDeviceToDevice, s));
+    CV_HIP(hipMemsetAsync(m->adam_m, 0, pb, s));
+    CV_HIP(hipMemsetAsync(m->adam_v, 0, pb, s));
+    return cvib::refresh_bf16(m, s);
+    CV_GUARD_END
+}
+
+int cv_mlp_get_params(const cv_mlp* m, float* params, float* grads, void* stream) {
+    CV_GUARD_BEGIN
+    if (!m || (!params && !grads)) return fail(CV_EINVAL, "null argument");
+    DeviceGuard dg(m->device);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t pb = (size_t)m->nparam * sizeof(float);
+    if (params) CV_HIP(hipMemcpyAsync(params, m->params, pb, hipMemcpyDeviceToDevice, s));
+    if (grads) CV_HIP(hipMemcpyAsync(grads, m->grads, pb, hipMemcpyDeviceToDevice, s));
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_mlp_forward(cv_mlp* m, const void* x, int64_t B, float* out, uint32_t flags, void* stream) {
+    CV_GUARD_BEGIN
+    if (!m) return fail(CV_EINVAL, "network is NULL");
+    if (B < 0) return fail(CV_EINVAL, "B < 0");
+    if (flags & ~(uint32_t)(CV_MLP_KEEP | CV_MLP_RGB8)) return fail(CV_EINVAL, "unknown flags");
+    if (B == 0) return CV_OK;
+    if (!x || !out) return fail(CV_EINVAL, "null array");
+    if (B > ((int64_t)1 << 30)) return fail(CV_EINVAL, "B > 2^30");
+    if ((flags & CV_MLP_KEEP) && B > ((int64_t)1 << 24)) return fail(CV_EINVAL, "kept batch > 2^24 rows");
+    DeviceGuard dg(m->device);
+    return cvib::run_forward(m, x, (flags & CV_MLP_RGB8) != 0, B, out, (flags & CV_MLP_KEEP) != 0,
+                             (hipStream_t)stream);
+    CV_GUARD_END
+}
+
+int cv_mlp_loss(cv_mlp* m, const float* out, const float* t_r, const float* t_f, int64_t B,
+                float huber_delta, float* loss, float* gout, void* stream) {
+    CV_GUARD_BEGIN
+    if (!m) return fail(CV_EINVAL, "network is NULL");
+    if (B < 1) return fail(CV_EINVAL, "B < 1");
+    if (!out || !t_r || !t_f || !loss) return fail(CV_EINVAL, "null array");
+    if (!(huber_delta > 0.0f)) return fail(CV_EINVAL, "huber_delta must be > 0");
+    DeviceGuard dg(m->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nb = (B + 255) / 256;
+    int rc;
+    size_t have = (size_t)m->lpart_n * sizeof(float);
+    if ((rc = cvib::grow((void**)&m->lpart, &have, (size_t)nb * sizeof(float))) != CV_OK) return rc;
+    m->lpart_n = (int64_t)(have / sizeof(float));
+    hipLaunchKernelGGL(cvib::k_loss, dim3((unsigned)nb), dim3(256), 0, s, out, t_r, t_f, B,
+                       m->dims[m->L], huber_delta, gout, m->lpart);
+    hipLaunchKernelGGL(cvib::k_loss_total, dim3(1), dim3(64), 0, s, m->lpart, (int32_t)nb, B, loss);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_mlp_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, void* stream) {
+    CV_GUARD_BEGIN
+    if (!m) return fail(CV_EINVAL, "network is NULL");
+    if (!x || !gout) return fail(CV_EINVAL, "null array");
+    if (B < 1 || B != m->fwd_rows)
+        return fail(CV_ESTATE, "backward needs a kept forward pass of the same batch");
+    DeviceGuard dg(m->device);
+    return cvib::run_backward(m, x, gout, B, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
+int cv_adam_step(cv_mlp* m, float lr, float beta1, float beta2, float eps, int64_t t, void* stream) {
+    CV_GUARD_BEGIN
+    if (!m) return fail(CV_EINVAL, "network is NULL");
+    if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps > 0.0f) || t < 1)
+        return fail(CV_EINVAL, "Adam needs lr >= 0, betas in [0, 1), eps > 0, step >= 1");
+    DeviceGuard dg(m->device);
+    hipStream_t s = (hipStream_t)stream;
+    const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)t)));
+    const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)t)));
+    hipLaunchKernelGGL(cvib::k_adam, dim3(cvib::blocks(m->nparam, 256)), dim3(256), 0, s, m->params,
+                       m->grads, m->adam_m, m->adam_v, m->nparam, lr, beta1, beta2, eps, c1, c2);
+    CV_HIP(hipGetLastError());
+    return cvib::refresh_bf16(m, s);
+    CV_GUARD_END
+}
+
+int cv_mlp_table_batch(cv_mlp* m, const int32_t* ids, const cv_table_row* table, int64_t B,
+                       double dr, float* x, float* t_r, float* t_f, void* stream) {
+    CV_GUARD_BEGIN
+    if (!m) return fail(CV_EINVAL, "network is NULL");
+    if (B < 0) return fail(CV_EINVAL, "B < 0");
+    if (B == 0) return CV_OK;
+    if (!ids || !table || !x || !t_r || !t_f) return fail(CV_EINVAL, "null array");
+    if (!(dr > 0.0)) return fail(CV_EINVAL, "dr must be > 0");
+    if (m->dims[0] != 3 || m->dims[m->L] != 37) return fail(CV_EINVAL, "network is not 3 -> ... -> 37");
+    DeviceGuard dg(m->device);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(cvib::k_table_batch, dim3(cvib::blocks(B, 256)), dim3(256), 0, s, ids, table, B,
+                       (float)(dr / 50.0), x, t_r, t_f);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_mlp_save(const cv_mlp* m, const char* path) {
+    CV_GUARD_BEGIN
+    if (!m || !path) return fail(CV_EINVAL, "null argument");
+    DeviceGuard dg(m->device);
+    std::string buf((size_t)m->nparam * sizeof(float), '\0');
+    CV_HIP(hipDeviceSynchronize());
+    CV_HIP(hipMemcpy(&buf[0], m->params, buf.size(), hipMemcpyDeviceToHost));
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(CV_EINVAL, std::string("cannot open ") + path);
+    const int32_t L = m->L;
+    const int64_t n = m->nparam;
+    bool ok = fwrite(cvib::kMagic, 1, 8, f) == 8 && fwrite(&L, 4, 1, f) == 1 &&
+              fwrite(m->dims, 4, (size_t)L + 1, f) == (size_t)L + 1 && fwrite(&n, 8, 1, f) == 1 &&
+              fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+    ok = (fclose(f) == 0) && ok;
+    return ok ? CV_OK : fail(CV_EINVAL, std::string("write failed: ") + path);
+    CV_GUARD_END
+}
+
+int cv_mlp_load(cv_mlp* m, const char* path) {
+    CV_GUARD_BEGIN
+    if (!m || !path) return fail(CV_EINVAL, "null argument");
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(CV_EINVAL, std::string("cannot open ") + path);
+    char magic[8];
+    int32_t L = 0, dims[cvib::kMaxLayers + 1];
+    int64_t n = 0;
+    bool ok = fread(magic, 1, 8, f) == 8 && std::memcmp(magic, cvib::kMagic, 8) == 0 &&
+              fread(&L, 4, 1, f) == 1 && L == m->L && fread(dims, 4, (size_t)L + 1, f) == (size_t)L + 1 &&
+              std::memcmp(dims, m->dims, sizeof(int32_t) * ((size_t)L + 1)) == 0 &&
+              fread(&n, 8, 1, f) == 1 && n == m->nparam;
+    std::string buf;
+    if (ok) {
+        buf.resize((size_t)n * sizeof(float));
+        ok = fread(&buf[0], 1, buf.size(), f) == buf.size();
+    }
+    fclose(f);
+    if (!ok) return fail(CV_EINVAL, std::string("not a network file of this shape: ") + path);
+    DeviceGuard dg(m->device);
+    CV_HIP(hipDeviceSynchronize());
+    CV_HIP(hipMemcpy(m->params, buf.data(), buf.size(), hipMemcpyHostToDevice));
+    CV_HIP(hipMemset(m->adam_m, 0, buf.size()));
+    CV_HIP(hipMemset(m->adam_v, 0, buf.size()));
+    int rc = cvib::refresh_bf16(m, nullptr);
+    if (rc != CV_OK) return rc;
+    CV_HIP(hipDeviceSynchronize());
+    return CV_OK;
+    CV_GUARD_END
+}
+
+} // extern "C"

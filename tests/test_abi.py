@@ -168,3 +168,38 @@ def test_binding_refuses_host_tensors(cv):
         cv.pair_search(torch.zeros((2, 3), dtype=torch.uint8), cv.Grid(0.1, 10, 1.0, 360), cv.Rule())
     with pytest.raises(ValueError):
         cv.rgb8_to_lab(torch.zeros((2, 4), dtype=torch.uint8))
+
+
+def test_mlp_argument_validation(cv):
+    L = cv.lib()
+    d = C.cast((C.c_uint8 * 4096)(), C.c_void_p)
+    h = C.c_void_p()
+
+    def create(dims):
+        arr = (C.c_int32 * len(dims))(*dims)
+        return L.cv_mlp_create(d, arr, len(dims) - 1, C.byref(h))
+    arr = (C.c_int32 * 5)(3, 256, 256, 256, 37)
+    assert L.cv_mlp_create(None, arr, 4, C.byref(h)) == cv.CV_EINVAL
+    assert create([3, 37]) == cv.CV_EINVAL                 # one layer
+    assert create([4, 64, 37]) == cv.CV_EINVAL             # not an RGB input
+    assert create([3, 48, 37]) == cv.CV_EINVAL             # width not a multiple of 32
+    assert create([3, 2048, 37]) == cv.CV_EINVAL           # too wide
+    assert create([3, 64, 300]) == cv.CV_EINVAL            # output too wide
+    assert create([3] + [32] * 9 + [37]) == cv.CV_EINVAL   # too deep
+    assert L.cv_mlp_destroy(None) == cv.CV_OK
+    assert L.cv_mlp_forward(None, None, 0, None, 0, None) == cv.CV_EINVAL
+    assert L.cv_mlp_loss(None, None, None, None, 1, 0.1, None, None, None) == cv.CV_EINVAL
+    assert L.cv_mlp_backward(None, None, None, 1, None) == cv.CV_EINVAL
+    assert L.cv_adam_step(None, 1e-3, 0.9, 0.999, 1e-8, 1, None) == cv.CV_EINVAL
+    assert L.cv_mlp_save(None, b"/tmp/x") == cv.CV_EINVAL
+    assert L.cv_mlp_load(None, b"/tmp/x") == cv.CV_EINVAL
+
+
+def test_init_params_layout(cv):
+    dims = cv.SURROGATE_DIMS
+    flat = cv.init_params(dims, 0)
+    assert flat.dtype == np.float32 and flat.size == 142117
+    Ws, bs = cv.split_params(flat, dims)
+    assert [w.shape for w in Ws] == [(256, 3), (256, 256), (256, 256), (37, 256)]
+    assert all(np.all(b == 0) for b in bs)
+    assert abs(Ws[1].std() - np.sqrt(2 / 256)) < 0.01

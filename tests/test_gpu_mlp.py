@@ -1,0 +1,213 @@
+"""Surrogate network kernels on the GPU: forward, loss, backward, Adam,
+save / load and a short training run.
+
+Two references: the FP64 oracle, given the same BF16-rounded weights, and a
+plain PyTorch FP32 CPU emulation that rounds at the same points as the
+kernels (hidden activations and back-propagated gradients to BF16).
+
+Bars (norm-wise relative error):
+- forward: 2e-2 against the oracle, 2e-3 against the emulation;
+- gradients: 5e-2 against the oracle, 2e-3 against the emulation.
+The gradient bar against FP64 is the floor that BF16 rounding itself sets:
+three back-propagation stages with a relative error of 2^-9 per element,
+amplified by cancellation in sums over the batch; the emulation, which has no
+kernel in it, is 3.5e-2 from FP64 for the first layer at B = 64 and 1.7e-2 at
+B = 1100."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (3, 256, 256, 256, 37)
+
+
+@pytest.fixture(scope="module")
+def cv():
+    import paper_2507_22901_amd as cv
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cv.lib()
+    return cv
+
+
+def bf(a):
+    """Round to BF16 (nearest even) and back to FP32."""
+    return torch.as_tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float32)
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def oracle_weights(cv, flat, dims):
+    """Weights as the kernels see them: BF16 for every matrix-core layer."""
+    Ws, bs = cv.split_params(flat, dims)
+    Ws = [Ws[0].astype(np.float64)] + [bf(w).double().numpy() for w in Ws[1:]]
+    return Ws, [b.astype(np.float64) for b in bs]
+
+
+def emulate(cv, flat, dims, x, gout=None):
+    """FP32 forward (and backward) rounding where the kernels round."""
+    Ws, bs = cv.split_params(torch.from_numpy(flat), dims)
+    L = len(dims) - 1
+    x = torch.as_tensor(x, dtype=torch.float32)
+    H = [None, bf(torch.relu(x @ Ws[0].T + bs[0]))]
+    for l in range(1, L - 1):
+        H.append(bf(torch.relu(H[l] @ bf(Ws[l]).T + bs[l])))
+    out = H[L - 1] @ bf(Ws[L - 1]).T + bs[L - 1]
+    if gout is None:
+        return out, None
+    G = bf(torch.as_tensor(gout, dtype=torch.float32))
+    gW, gb = [None] * L, [None] * L
+    for l in range(L - 1, 0, -1):
+        gW[l] = G.T @ H[l]
+        gb[l] = G.sum(0)
+        G = bf((G @ bf(Ws[l])) * (H[l] > 0))
+    gW[0] = G.T @ x
+    gb[0] = G.sum(0)
+    return out, (gW, gb)
+
+
+def _net(cv, dims=DIMS, seed=0):
+    m = cv.MLP(dims)
+    flat = cv.init_params(dims, seed)
+    # non-zero biases so that the bias paths are exercised
+    Ws, bs = cv.split_params(flat, dims)
+    rng = np.random.default_rng(seed + 100)
+    for b in bs:
+        b[:] = rng.normal(0, 0.05, b.shape)
+    m.set_params(flat)
+    return m, flat
+
+
+def _batch(B, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-0.5, 0.5, (B, 3)).astype(np.float32)
+    tr = np.where(rng.random((B, 36)) < 0.6, rng.uniform(0.02, 1.0, (B, 36)), 0.0).astype(np.float32)
+    tf = (rng.random(B) < 0.7).astype(np.float32)
+    return x, tr, tf
+
+
+@pytest.mark.parametrize("B", [1, 300, 1100])
+def test_forward_matches_references(cv, oracle, B):
+    m, flat = _net(cv)
+    x, _, _ = _batch(B, 1)
+    out = m.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    Ws, bs = oracle_weights(cv, flat, DIMS)
+    ref = oracle.mlp_forward(list(DIMS), Ws, bs, x.astype(np.float64))
+    assert rel(out, ref) < 2e-2
+    emu, _ = emulate(cv, flat, DIMS, x)
+    assert rel(out, emu.numpy()) < 2e-3
+    # kept and chunked forward agree bitwise
+    out2 = m.forward(torch.from_numpy(x).cuda(), keep=True).cpu().numpy()
+    assert np.array_equal(out, out2)
+
+
+def test_forward_rgb8_input(cv):
+    m, flat = _net(cv, seed=3)
+    rgb = W.random_colours(8, 777)
+    a = m.forward(torch.from_numpy(rgb).cuda())
+    # the kernel's own conversion: v * fl(1/255) - 1/2 in FP32
+    x = torch.from_numpy(rgb.astype(np.float32) * np.float32(1.0 / 255.0) - np.float32(0.5)).cuda()
+    b = m.forward(x)
+    assert torch.equal(a, b)
+
+
+def test_loss_matches_oracle(cv, oracle):
+    m, _ = _net(cv)
+    B = 1000
+    rng = np.random.default_rng(4)
+    out = rng.normal(0.3, 0.4, (B, 37)).astype(np.float32)
+    out[:, 36] = rng.normal(0, 3, B)
+    _, tr, tf = _batch(B, 4)
+    loss, gout = m.loss(torch.from_numpy(out).cuda(), torch.from_numpy(tr).cuda(),
+                        torch.from_numpy(tf).cuda(), 0.1)
+    val, g = oracle.mlp_loss(out.astype(np.float64), tr, tf, 0.1)
+    assert abs(float(loss.item()) - val) <= 1e-5 * abs(val)
+    assert np.max(np.abs(gout.cpu().numpy() - g)) <= 1e-6 * np.max(np.abs(g))
+
+
+@pytest.mark.parametrize("B", [64, 300, 1100])
+def test_backward_matches_references(cv, oracle, B):
+    m, flat = _net(cv, seed=B)
+    x, tr, tf = _batch(B, B + 1)
+    xd = torch.from_numpy(x).cuda()
+    out = m.forward(xd, keep=True)
+    loss, gout = m.loss(out, torch.from_numpy(tr).cuda(), torch.from_numpy(tf).cuda(), 0.1)
+    m.backward(xd, gout)
+    grads = m.grads().cpu().numpy()
+    gWs, gbs = cv.split_params(grads, DIMS)
+    Ws, bs = oracle_weights(cv, flat, DIMS)
+    o_gW, o_gb = oracle.mlp_backward(list(DIMS), Ws, bs, x.astype(np.float64),
+                                     gout.cpu().numpy().astype(np.float64))
+    _, (e_gW, e_gb) = emulate(cv, flat, DIMS, x, gout.cpu())
+    for l in range(len(DIMS) - 1):
+        assert rel(gWs[l], e_gW[l].numpy()) < 2e-3, ("W emu", l)
+        assert rel(gbs[l], e_gb[l].numpy()) < 2e-3, ("b emu", l)
+        assert rel(gWs[l], o_gW[l]) < 5e-2, ("W", l)
+        assert rel(gbs[l], o_gb[l]) < 5e-2, ("b", l)
+
+
+def test_small_network_and_repeatability(cv, oracle):
+    dims = (3, 32, 64, 37)
+    m, flat = _net(cv, dims, seed=7)
+    x, tr, tf = _batch(257, 8)
+    xd = torch.from_numpy(x).cuda()
+    runs = []
+    for _ in range(2):
+        out = m.forward(xd, keep=True)
+        _, gout = m.loss(out, torch.from_numpy(tr).cuda(), torch.from_numpy(tf).cuda(), 0.1)
+        m.backward(xd, gout)
+        runs.append(m.grads().cpu().numpy())
+    assert np.array_equal(runs[0], runs[1])   # fixed-order reductions
+    Ws, bs = oracle_weights(cv, flat, dims)
+    o_gW, _ = oracle.mlp_backward(list(dims), Ws, bs, x.astype(np.float64),
+                                  gout.cpu().numpy().astype(np.float64))
+    gWs, _ = cv.split_params(runs[0], dims)
+    for l in range(len(dims) - 1):
+        assert rel(gWs[l], o_gW[l]) < 5e-2
+
+
+def test_adam_matches_oracle(cv, oracle):
+    m, flat = _net(cv, seed=11)
+    x, tr, tf = _batch(512, 12)
+    xd = torch.from_numpy(x).cuda()
+    p, mo, vo = flat.astype(np.float64), np.zeros(len(flat)), np.zeros(len(flat))
+    for t in (1, 2, 3):
+        out = m.forward(xd, keep=True)
+        _, gout = m.loss(out, torch.from_numpy(tr).cuda(), torch.from_numpy(tf).cuda(), 0.1)
+        m.backward(xd, gout)
+        g = m.grads().cpu().numpy().astype(np.float64)
+        m.adam_step(1e-3, t)
+        p, mo, vo = oracle.adam_step(p, g, mo, vo, t, 1e-3)
+        got = m.params().cpu().numpy()
+        assert np.max(np.abs(got - p)) < 1e-6 * t, t
+        p = got.astype(np.float64)  # keep the two in step
+
+
+def test_save_load_roundtrip(cv, tmp_path):
+    m, flat = _net(cv, seed=5)
+    path = str(tmp_path / "net.cvmlp")
+    m.save(path)
+    m2 = cv.MLP(DIMS)
+    m2.load(path)
+    assert torch.equal(m.params(), m2.params())
+    x = torch.from_numpy(_batch(100, 6)[0]).cuda()
+    assert torch.equal(m.forward(x), m2.forward(x))
+    m3 = cv.MLP((3, 32, 37))
+    with pytest.raises(cv.CvError):
+        m3.load(path)
+
+
+def test_backward_needs_kept_forward(cv):
+    m, _ = _net(cv)
+    x = torch.from_numpy(_batch(64, 1)[0]).cuda()
+    g = torch.zeros((64, 37), device="cuda")
+    m.forward(x)  # not kept
+    with pytest.raises(cv.CvError):
+        m.backward(x, g)

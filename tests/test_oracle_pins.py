@@ -450,3 +450,40 @@ def test_mlp_forward_matches_matrix_products(oracle):
         if l < 2:
             h = np.maximum(h, 0)
     assert np.allclose(oracle.mlp_forward(dims, Ws, bs, x), h, atol=1e-12)
+
+
+def test_mlp_loss_closed_forms(oracle):
+    """Huber and logistic terms at hand-computable points: an output equal to
+    its target costs nothing; an error of 3 deltas costs delta^2 (3 - 1/2);
+    z = 0 gives log 2 whatever the label; masked bins cost nothing."""
+    delta = 0.1
+    out = np.zeros((2, 37))
+    tr = np.zeros((2, 36))
+    tf = np.array([0.0, 1.0])
+    tr[0, 0] = 0.5
+    out[0, 0] = 0.5            # exact: 0
+    tr[1, 3] = 0.2
+    out[1, 3] = 0.2 + 3 * delta  # linear branch
+    out[1, 4] = 7.0            # masked bin (target 0)
+    val, g = oracle.mlp_loss(out, tr, tf, delta)
+    expect = (0.0 + np.log(2.0) + delta * delta * 2.5 / 36 + np.log(2.0)) / 2
+    assert abs(val - expect) < 1e-15
+    assert g[1, 3] == delta / 36 / 2 and g[1, 4] == 0.0 and g[0, 0] == 0.0
+    assert abs(g[0, 36] - 0.5 / 2) < 1e-15 and abs(g[1, 36] + 0.5 / 2) < 1e-15
+
+
+def test_adam_closed_forms(oracle):
+    """Adam's first step moves every parameter by lr * sign(g) (bias-corrected
+    moments equal g and g^2); with a constant gradient every later step does
+    the same; a zero gradient leaves the parameter."""
+    rng = np.random.default_rng(2)
+    p0 = rng.normal(0, 1, 50)
+    g = rng.normal(0, 1, 50)
+    g[0] = 0.0
+    lr = 1e-3
+    p, m, v = oracle.adam_step(p0, g, np.zeros(50), np.zeros(50), 1, lr, eps=0.0 + 1e-300)
+    assert np.allclose(p[1:], p0[1:] - lr * np.sign(g[1:]), rtol=0, atol=1e-15)
+    assert p[0] == p0[0]
+    for t in range(2, 6):
+        p, m, v = oracle.adam_step(p, g, m, v, t, lr, eps=1e-300)
+    assert np.allclose(p[1:], p0[1:] - 5 * lr * np.sign(g[1:]), rtol=0, atol=1e-13)
