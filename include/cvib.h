@@ -245,6 +245,9 @@ int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, cons
  *   CV_TIME_WRITE - the write pass of cv_pair_search,
  *   CV_TIME_CALL  - everything a cv_pair_search / cv_pair_reduce call enqueues
  *                   after its set-up (evaluation, scan, write).
+ * In cv_frames_resolve, CV_TIME_EVAL is the per-colour resolve kernel; in the
+ * surrogate calls it is the exact fallback, CV_TIME_MLP the network and
+ * CV_TIME_VERIFY the proposal check.
  * While timing is on, cv_pair_reduce synchronises its stream.
  * cv_context_kernel_time returns the accumulated milliseconds and the number
  * of timed calls for one phase (host pointers) and clears that phase when
@@ -253,6 +256,8 @@ int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, cons
 #define CV_TIME_EVAL 0
 #define CV_TIME_WRITE 1
 #define CV_TIME_CALL 2
+#define CV_TIME_MLP 3     /* surrogate: the network's forward pass            */
+#define CV_TIME_VERIFY 4  /* surrogate: proposals through the exact predicate */
 int cv_context_set_timing(cv_context* ctx, int on);
 int cv_context_kernel_time(cv_context* ctx, int phase, double* ms_host, int64_t* calls_host,
                            int reset);
@@ -331,6 +336,59 @@ int cv_mlp_table_batch(cv_mlp* m, const int32_t* ids, const cv_table_row* table,
  * synchronise the device. */
 int cv_mlp_save(const cv_mlp* m, const char* path);
 int cv_mlp_load(cv_mlp* m, const char* path);
+
+/* ---- Surrogate resolve -------------------------------------------------
+ *
+ * One verified pair per target colour, proposed by a 3 -> ... -> 37 network
+ * (radii of the 36 angle bins / 50 and a feasibility logit, as trained on
+ * the table of cv_pair_reduce) and checked by the exact predicate.
+ *
+ * For a colour whose logit is >= tau, the network's kbins bins of largest
+ * predicted radius r (1 <= kbins <= 36) each propose every ray j of the bin
+ * (floor(36 j / N) = bin, j < ntheta) at the radius indices
+ * round(r / dr) - t, t = 0..5.  Every proposal runs through the same
+ * arithmetic as the exact search, so a verified pair is one of its
+ * survivors; the verified proposal of largest i (then smallest j) is kept.
+ * Colours with a lower logit or with no verified proposal go to the exact
+ * search (its maximum-amplitude pair), unless CV_NO_FALLBACK is set.
+ */
+#define CV_NO_FALLBACK 0x4u
+
+/* cv_pattern_pair.flags of a resolved pair */
+#define CV_PAIR_FOUND 0x1u      /* the pair exists                          */
+#define CV_PAIR_SURROGATE 0x2u  /* proposed by the network and verified     */
+#define CV_PAIR_FALLBACK 0x4u   /* found by the exact search                */
+
+/* per-colour status */
+#define CV_RESOLVED_SURROGATE 0  /* verified proposal                       */
+#define CV_RESOLVED_EXACT 1      /* exact fallback found a pair             */
+#define CV_RESOLVED_NONE 2       /* no pair (infeasible, or no fallback)    */
+
+/* A list of n colours (uint8 [n][3]).  pairs: cv_pattern_pair [n]; status:
+ * uint8 [n]; pred: float [n][37] (nullable) receives the network outputs;
+ * *nfallback (DEVICE int64, nullable): colours sent to the exact search.
+ * Asynchronous.  Errors: CV_EINVAL, CV_EHIP, CV_ENOMEM. */
+int cv_surrogate_infer(cv_context* ctx, cv_mlp* mlp, const uint8_t* rgb, int64_t n,
+                       const cv_grid* grid, const cv_rule* rule, float tau, int32_t kbins,
+                       float* pred, cv_pattern_pair* pairs, uint8_t* status, int64_t* nfallback,
+                       uint32_t flags, void* stream);
+
+/* Batched frames through the surrogate: the de-duplication of
+ * cv_frames_resolve (colours, *ncolours, pixel_index as there), one
+ * surrogate-resolved pair per distinct colour (pairs, status [colour_cap]),
+ * and frames A / B (uint8 [npix][3] each, nullable together) showing the +
+ * and - colour of the pixel's pair (a pixel without one keeps its colour);
+ * *resolved (DEVICE int64, nullable) counts pixels with a pair and
+ * *nfallback (DEVICE int64, nullable) the colours sent to the exact search.
+ * Reads the colour count back to the host once (the network runs on exactly
+ * that many rows), so the call synchronises its stream.
+ * Errors: CV_EINVAL, CV_EHIP, CV_ENOMEM. */
+int cv_frames_surrogate(cv_context* ctx, cv_mlp* mlp, const uint8_t* pixels, int64_t npix,
+                        const cv_grid* grid, const cv_rule* rule, float tau, int32_t kbins,
+                        uint8_t* colours, int64_t colour_cap, int64_t* ncolours,
+                        uint32_t* pixel_index, cv_pattern_pair* pairs, uint8_t* status,
+                        uint8_t* frame_a, uint8_t* frame_b, int64_t* resolved, int64_t* nfallback,
+                        uint32_t flags, void* stream);
 
 #ifdef __cplusplus
 }

@@ -67,7 +67,12 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_pair_search", "cv_pair_reduce", "cv_frames_resolve", "cv_context_set_timing",
            "cv_context_kernel_time", "cv_mlp_create", "cv_mlp_destroy", "cv_mlp_num_params",
            "cv_mlp_set_params", "cv_mlp_get_params", "cv_mlp_forward", "cv_mlp_loss",
-           "cv_mlp_backward", "cv_adam_step", "cv_mlp_table_batch", "cv_mlp_save", "cv_mlp_load")
+           "cv_mlp_backward", "cv_adam_step", "cv_mlp_table_batch", "cv_mlp_save", "cv_mlp_load",
+           "cv_surrogate_infer", "cv_frames_surrogate")
+CV_NO_FALLBACK = 0x4
+CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
+CV_RESOLVED_SURROGATE, CV_RESOLVED_EXACT, CV_RESOLVED_NONE = 0, 1, 2
+CV_TIME_MLP, CV_TIME_VERIFY = 3, 4
 CV_MLP_KEEP = 0x1
 CV_MLP_RGB8 = 0x2
 SURROGATE_DIMS = (3, 256, 256, 256, 37)
@@ -107,6 +112,11 @@ def lib() -> C.CDLL:
         L.cv_mlp_table_batch.argtypes = [P, P, P, I64, C.c_double, P, P, P, P]
         L.cv_mlp_save.argtypes = [P, C.c_char_p]
         L.cv_mlp_load.argtypes = [P, C.c_char_p]
+        L.cv_surrogate_infer.argtypes = [P, P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule),
+                                         C.c_float, C.c_int32, P, P, P, P, C.c_uint32, P]
+        L.cv_frames_surrogate.argtypes = [P, P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule),
+                                          C.c_float, C.c_int32, P, I64, P, P, P, P, P, P, P, P,
+                                          C.c_uint32, P]
         for name in EXPORTS:
             if name != "cv_last_error":
                 getattr(L, name).restype = C.c_int
@@ -463,3 +473,82 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------
+# Surrogate resolve
+
+
+@dataclass
+class SurrogateResult:
+    pairs: torch.Tensor        # uint8 [n, 12] (PATTERN_PAIR_DTYPE)
+    status: torch.Tensor       # uint8 [n]: CV_RESOLVED_*
+    nfallback: torch.Tensor    # int64 [1] on the GPU
+    pred: torch.Tensor | None  # float32 [n, 37]
+
+
+def surrogate_infer(colors: torch.Tensor, mlp: MLP, grid: Grid, rule: Rule, tau: float = 0.0,
+                    kbins: int = 4, fallback: bool = True, want_pred: bool = False,
+                    ctx: Context | None = None) -> SurrogateResult:
+    """One verified pair per colour (uint8 [n, 3] on the GPU)."""
+    colors = _colours(colors)
+    ctx = ctx or mlp.ctx
+    n = colors.shape[0]
+    dev = colors.device
+    pairs = torch.empty((n, 12), dtype=torch.uint8, device=dev)
+    status = torch.empty(n, dtype=torch.uint8, device=dev)
+    nfb = torch.zeros(1, dtype=torch.int64, device=dev)
+    pred = torch.empty((n, 37), dtype=torch.float32, device=dev) if want_pred else None
+    g, r = grid.c(), rule.c()
+    _check(lib().cv_surrogate_infer(ctx.handle, mlp.handle, _dptr(colors), n, C.byref(g), C.byref(r),
+                                    float(tau), int(kbins), _dptr(pred), _dptr(pairs), _dptr(status),
+                                    _dptr(nfb), 0 if fallback else CV_NO_FALLBACK, _stream()))
+    return SurrogateResult(pairs, status, nfb, pred)
+
+
+@dataclass
+class FramesSurrogateResult:
+    colours: torch.Tensor
+    ncolours: torch.Tensor
+    pixel_index: torch.Tensor
+    pairs: torch.Tensor
+    status: torch.Tensor
+    frame_a: torch.Tensor | None
+    frame_b: torch.Tensor | None
+    resolved: torch.Tensor | None
+    nfallback: torch.Tensor
+
+
+def frames_surrogate(pixels: torch.Tensor, mlp: MLP, grid: Grid, rule: Rule, tau: float = 0.0,
+                     kbins: int = 4, fallback: bool = True, frames: bool = True,
+                     out: FramesSurrogateResult | None = None,
+                     ctx: Context | None = None) -> FramesSurrogateResult:
+    """De-duplicate the colours of `pixels` (uint8 [..., 3]), resolve each
+    through the surrogate (verified) with the exact search as fallback, and
+    render the two frames."""
+    if pixels.dtype != torch.uint8 or pixels.shape[-1] != 3 or not pixels.is_cuda:
+        raise ValueError("pixels must be a uint8 CUDA tensor of shape [..., 3]")
+    px = pixels.contiguous().reshape(-1, 3)
+    npix = px.shape[0]
+    ctx = ctx or mlp.ctx
+    dev = px.device
+    cap = min(npix, 1 << 24)
+    if out is None:
+        out = FramesSurrogateResult(
+            colours=torch.empty((cap, 3), dtype=torch.uint8, device=dev),
+            ncolours=torch.zeros(1, dtype=torch.int64, device=dev),
+            pixel_index=torch.empty(npix, dtype=torch.int32, device=dev),
+            pairs=torch.empty((cap, 12), dtype=torch.uint8, device=dev),
+            status=torch.empty(cap, dtype=torch.uint8, device=dev),
+            frame_a=torch.empty((npix, 3), dtype=torch.uint8, device=dev) if frames else None,
+            frame_b=torch.empty((npix, 3), dtype=torch.uint8, device=dev) if frames else None,
+            resolved=torch.zeros(1, dtype=torch.int64, device=dev) if frames else None,
+            nfallback=torch.zeros(1, dtype=torch.int64, device=dev))
+    g, r = grid.c(), rule.c()
+    _check(lib().cv_frames_surrogate(ctx.handle, mlp.handle, _dptr(px), npix, C.byref(g), C.byref(r),
+                                     float(tau), int(kbins), _dptr(out.colours), out.colours.shape[0],
+                                     _dptr(out.ncolours), _dptr(out.pixel_index), _dptr(out.pairs),
+                                     _dptr(out.status), _dptr(out.frame_a), _dptr(out.frame_b),
+                                     _dptr(out.resolved), _dptr(out.nfallback),
+                                     0 if fallback else CV_NO_FALLBACK, _stream()))
+    return out

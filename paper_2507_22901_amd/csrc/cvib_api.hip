@@ -156,7 +156,7 @@ int cv_context::mark(int phase, int end, hipStream_t s) {
 }
 
 int cv_context::collect() {
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < kPhases; ++p) {
         if (!armed[p]) continue;
         float ms = 0.0f;
         CV_HIP(hipEventSynchronize(ev[p][1]));
@@ -213,7 +213,8 @@ int cv_context_destroy(cv_context* ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     cvib::Buffer* bufs[] = {&ctx->colors, &ctx->table, &ctx->seg_cnt, &ctx->seg_prefix,
                             &ctx->scan,   &ctx->acc,   &ctx->misc,    &ctx->fbits,
-                            &ctx->fcnt,   &ctx->fprefix, &ctx->fmisc};
+                            &ctx->fcnt,   &ctx->fprefix, &ctx->fmisc, &ctx->spred,
+                            &ctx->sneed,  &ctx->sprefix, &ctx->slist, &ctx->ssumm, &ctx->smisc};
     for (cvib::Buffer* b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->host_misc) (void)hipHostFree(ctx->host_misc);
@@ -319,6 +320,76 @@ int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, cons
     CV_GUARD_END
 }
 
+namespace {
+int surrogate_call(cv_context* ctx, cv_mlp* mlp, const cv_grid* grid, const cv_rule* rule, float tau,
+                   int32_t kbins, uint32_t flags, cvib::SurrogateCall* c) {
+    if (!ctx || !mlp) return fail(CV_EINVAL, "ctx or network is NULL");
+    if (cvib::mlp_in_width(mlp) != 3 || cvib::mlp_out_width(mlp) != 37)
+        return fail(CV_EINVAL, "the surrogate network must map 3 inputs to 37 outputs");
+    if (cvib::mlp_device(mlp) != ctx->device) return fail(CV_EINVAL, "network and context on different devices");
+    if (kbins < 1 || kbins > 36) return fail(CV_EINVAL, "kbins must be in [1, 36]");
+    if (!(tau == tau)) return fail(CV_EINVAL, "tau is NaN");
+    if (flags & ~(uint32_t)CV_NO_FALLBACK) return fail(CV_EINVAL, "unknown flags");
+    std::memset(c, 0, sizeof *c);
+    int rc;
+    if ((rc = cvib::make_grid(grid, &c->gd)) != CV_OK) return rc;
+    if ((rc = cvib::make_rule(rule, &c->rd)) != CV_OK) return rc;
+    c->mlp = mlp;
+    c->tau = tau;
+    c->kbins = kbins;
+    c->fallback = (flags & CV_NO_FALLBACK) == 0;
+    return CV_OK;
+}
+} // namespace
+
+int cv_surrogate_infer(cv_context* ctx, cv_mlp* mlp, const uint8_t* rgb, int64_t n,
+                       const cv_grid* grid, const cv_rule* rule, float tau, int32_t kbins,
+                       float* pred, cv_pattern_pair* pairs, uint8_t* status, int64_t* nfallback,
+                       uint32_t flags, void* stream) {
+    CV_GUARD_BEGIN
+    cvib::SurrogateCall c;
+    int rc;
+    if ((rc = surrogate_call(ctx, mlp, grid, rule, tau, kbins, flags, &c)) != CV_OK) return rc;
+    if (n < 0 || n > ((int64_t)1 << 30)) return fail(CV_EINVAL, "n must be in [0, 2^30]");
+    if (n > 0 && (!rgb || !pairs || !status)) return fail(CV_EINVAL, "null array");
+    c.rgb = rgb;
+    c.n = n;
+    c.pred = pred;
+    c.pairs = pairs;
+    c.status = status;
+    c.nfallback = nfallback;
+    DeviceGuard dg(ctx->device);
+    return cvib::run_surrogate(ctx, c, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
+int cv_frames_surrogate(cv_context* ctx, cv_mlp* mlp, const uint8_t* pixels, int64_t npix,
+                        const cv_grid* grid, const cv_rule* rule, float tau, int32_t kbins,
+                        uint8_t* colours, int64_t colour_cap, int64_t* ncolours,
+                        uint32_t* pixel_index, cv_pattern_pair* pairs, uint8_t* status,
+                        uint8_t* frame_a, uint8_t* frame_b, int64_t* resolved, int64_t* nfallback,
+                        uint32_t flags, void* stream) {
+    CV_GUARD_BEGIN
+    cvib::SurrogateCall c;
+    int rc;
+    if ((rc = surrogate_call(ctx, mlp, grid, rule, tau, kbins, flags, &c)) != CV_OK) return rc;
+    if (npix < 1) return fail(CV_EINVAL, "npix must be >= 1");
+    if (!pixels || !colours || !ncolours || !pixel_index || !pairs || !status)
+        return fail(CV_EINVAL, "null array");
+    if ((frame_a == nullptr) != (frame_b == nullptr))
+        return fail(CV_EINVAL, "frame_a and frame_b go together");
+    if (resolved && !frame_a) return fail(CV_EINVAL, "resolved needs the frames");
+    const int64_t need = npix < ((int64_t)1 << 24) ? npix : ((int64_t)1 << 24);
+    if (colour_cap < need) return fail(CV_EINVAL, "colour_cap < min(npix, 2^24)");
+    c.pairs = pairs;
+    c.status = status;
+    c.nfallback = nfallback;
+    DeviceGuard dg(ctx->device);
+    return cvib::run_frames_surrogate(ctx, c, pixels, npix, colours, colour_cap, ncolours, pixel_index,
+                                      frame_a, frame_b, resolved, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
 int cv_context_set_timing(cv_context* ctx, int on) {
     CV_GUARD_BEGIN
     if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
@@ -336,7 +407,7 @@ int cv_context_kernel_time(cv_context* ctx, int phase, double* ms_host, int64_t*
                            int reset) {
     CV_GUARD_BEGIN
     if (!ctx || !ms_host || !calls_host) return fail(CV_EINVAL, "null argument");
-    if (phase < 0 || phase > 2) return fail(CV_EINVAL, "unknown timing phase");
+    if (phase < 0 || phase >= cv_context::kPhases) return fail(CV_EINVAL, "unknown timing phase");
     *ms_host = ctx->kernel_ms[phase];
     *calls_host = ctx->kernel_calls[phase];
     if (reset) {

@@ -108,8 +108,9 @@ struct ResolveArgs {
     int32_t nr, ntheta, W;
     float inv_W;
     int32_t si, sj;
+    const uint32_t* list;     // nullable: the k-th colour searched is list[k]
     cv_color_summary* summ;   // nullable
-    cv_pattern_pair* pbest;   // [n][7]
+    cv_pattern_pair* pbest;   // nullable, [n][7]
     uint16_t* rays;           // nullable, [n][ntheta]
 };
 
@@ -129,7 +130,8 @@ __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
     const int64_t n = (int64_t)*a.n_dev;
     const int32_t per = a.nr * a.W;
 
-    for (int64_t c = blockIdx.x; c < n; c += gridDim.x) {
+    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+        const int64_t c = a.list ? (int64_t)a.list[k] : k;
         if (RAYS)
             for (int k = tid; k < a.W; k += BLOCK) s_ray[k] = 0;
         if (tid < 7) s_pb[tid] = 0;
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
             write_summary(cc, a.g, a.rule, a.tab, a.ra, a.rb, s_red[0][0], s_red[0][1], s_red[0][2],
                           pt, a.summ + c);
         }
-        if (tid < 7) {
+        if (tid < 7 && a.pbest) {
             cv_pattern_pair r = {};
             const uint32_t key = s_pb[tid];
             if (key) {
@@ -288,6 +290,178 @@ __global__ void k_copy_count(const uint64_t* __restrict__ src, int64_t* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Surrogate resolve.  The network's outputs for colour c are 36 predicted
+// maximum radii (divided by 50) and a feasibility logit.  A colour whose
+// logit reaches tau gets proposals: in each of its kbins bins of largest
+// predicted radius, every ray of the bin at radius indices i0 + 1, i0, ...,
+// i0 - (kDeltas - 2), i0 being the grid index of the predicted radius.  Each
+// proposal runs through the exact predicate of the search (the same device
+// functions and the same arithmetic), so a verified pair is a survivor of
+// the exact search; the verified pair of largest i (then smallest j) is kept.
+// Colours with a low logit or without a verified proposal go to the exact
+// fallback.  One wave per colour.
+
+constexpr int kBins = 36;
+constexpr int kDeltas = 6;
+
+struct ProposeArgs {
+    const ColorConst* cc;
+    const uint64_t* n_dev;
+    const float* pred;         // [n][37]
+    TabArgs tab;
+    Geom g;
+    RuleDev rule;
+    double ra, rb;
+    float dr;
+    int32_t nr, ntheta;
+    float tau;
+    int32_t kbins;
+    cv_pattern_pair* pairs;    // [n]
+    uint8_t* status;           // [n]
+    uint32_t* need;            // [n]: 1 = exact fallback
+};
+
+__global__ __launch_bounds__(256) void k_propose_verify(ProposeArgs a) {
+    extern __shared__ double s_tab[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    for (int k = tid; k < a.tab.tab_len; k += 256) s_tab[k] = a.tab.tab[k];
+    __syncthreads();
+    const int64_t n = (int64_t)*a.n_dev;
+    const int64_t GW = (int64_t)gridDim.x * 4;
+    for (int64_t c = (int64_t)blockIdx.x * 4 + (tid >> 6); c < n; c += GW) {
+        const float* p = a.pred + c * (kBins + 1);
+        const float rk = lane < kBins ? p[lane] * 50.0f : -INFINITY;
+        const float logit = p[kBins];
+        const ColorConst cc = a.cc[c];
+        uint32_t best = 0;
+        if (logit >= a.tau) {
+            // rank of every bin by predicted radius (ties: lower bin first)
+            int rank = 0;
+            for (int q = 0; q < kBins; ++q) {
+                const float rq = __shfl(rk, q);
+                rank += (rq > rk || (rq == rk && q < lane)) ? 1 : 0;
+            }
+            for (int b = 0; b < a.kbins; ++b) {
+                const uint64_t sel = __ballot(lane < kBins && rank == b);
+                const int bin = (int)__builtin_ctzll(sel);
+                const float rh = __shfl(rk, bin);
+                // rays of the bin: floor(36 j / N) = bin
+                const int32_t j_lo = (bin * a.tab.N + kBins - 1) / kBins;
+                const int32_t j_hi = min(((bin + 1) * a.tab.N + kBins - 1) / kBins, a.ntheta);
+                const int32_t nrays = j_hi - j_lo;
+                if (nrays <= 0) continue;
+                const int32_t i_top = (int32_t)rintf(fminf(fmaxf(rh / a.dr, 0.0f), 65536.0f));  // i0 + 1
+                const int32_t ncand = nrays * kDeltas;
+                for (int32_t u0 = 0; u0 < ncand; u0 += 64) {
+                    const int32_t u = u0 + lane;
+                    const int32_t t = u / nrays, q = u - t * nrays;
+                    const int32_t i = i_top - t;
+                    const int32_t j = j_lo + (u < ncand ? q : 0);
+                    const bool live = u < ncand && i >= 0 && i < a.nr;
+                    double sn, co;
+                    sincos_j(s_tab, a.tab.N, j, sn, co);
+                    const double rr = (double)(i + 1);
+                    float fp[3], fm[3];
+                    pair_linear(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
+                    const bool both = live && in_unit_cube(fp) && in_unit_cube(fm);
+                    const bool need = a.rule.clip ? live : both;
+                    bool ok = false;
+                    if (__ballot(need) != 0ull) {
+                        float Vp[3], Vm[3];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            Vp[k] = code8(fp[k]);
+                            Vm[k] = code8(fm[k]);
+                        }
+                        ok = need && accepts(a.rule, pattern_of(Vp, Vm, a.rule));
+                    }
+                    best = max(best, wave_max_u32(ok ? best_key(i, j) : 0u));
+                }
+            }
+        }
+        if (lane == 0) {
+            cv_pattern_pair r = {};
+            if (best) {
+                const int32_t bi = (int32_t)(best >> 16), bj = (int32_t)(0xFFFFu - (best & 0xFFFFu));
+                double sn, co;
+                sincos_j(s_tab, a.tab.N, bj, sn, co);
+                const double rr = (double)(bi + 1);
+                PairEval e;
+                eval_pair(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, e);
+                r.i = (uint16_t)bi;
+                r.j = (uint16_t)bj;
+                for (int k = 0; k < 3; ++k) {
+                    r.plus[k] = (uint8_t)e.Vp[k];
+                    r.minus[k] = (uint8_t)e.Vm[k];
+                }
+                r.pattern = (uint8_t)pattern_of(e.Vp, e.Vm, a.rule);
+                r.flags = CV_PAIR_FOUND | CV_PAIR_SURROGATE;
+            }
+            a.pairs[c] = r;
+            a.status[c] = best ? (uint8_t)CV_RESOLVED_SURROGATE : (uint8_t)CV_RESOLVED_NONE;
+            a.need[c] = best ? 0u : 1u;
+        }
+    }
+}
+
+// Fallback list: colours with need = 1, in colour order.
+__global__ void k_make_list(const uint32_t* __restrict__ need, const uint64_t* __restrict__ prefix,
+                            const uint64_t* __restrict__ n_dev, uint32_t* __restrict__ list) {
+    const int64_t n = (int64_t)*n_dev;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride)
+        if (need[c]) list[prefix[c]] = (uint32_t)c;
+}
+
+// The exact search's maximum-amplitude pair for every fallback colour.
+__global__ void k_fallback_finish(const uint32_t* __restrict__ list, const uint64_t* __restrict__ nlist,
+                                  const cv_color_summary* __restrict__ summ,
+                                  cv_pattern_pair* __restrict__ pairs, uint8_t* __restrict__ status) {
+    const int64_t n = (int64_t)*nlist;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const uint32_t c = list[k];
+        const cv_color_summary& sm = summ[c];
+        cv_pattern_pair r = {};
+        if (sm.best_i != 0xFFFFu) {
+            r.i = sm.best_i;
+            r.j = sm.best_j;
+            for (int q = 0; q < 3; ++q) {
+                r.plus[q] = sm.best_plus[q];
+                r.minus[q] = sm.best_minus[q];
+            }
+            r.pattern = sm.best_p;
+            r.flags = CV_PAIR_FOUND | CV_PAIR_FALLBACK;
+        }
+        pairs[c] = r;
+        status[c] = sm.best_i != 0xFFFFu ? (uint8_t)CV_RESOLVED_EXACT : (uint8_t)CV_RESOLVED_NONE;
+    }
+}
+
+// Two frames from one pair per colour.
+__global__ void k_render_pairs(const uint8_t* __restrict__ px, int64_t npix,
+                               const uint32_t* __restrict__ index,
+                               const cv_pattern_pair* __restrict__ pairs, uint8_t* __restrict__ fa,
+                               uint8_t* __restrict__ fb, unsigned long long* __restrict__ resolved) {
+    uint32_t got = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
+        const cv_pattern_pair& r = pairs[index[p]];
+        const bool ok = (r.flags & CV_PAIR_FOUND) != 0;
+        for (int c = 0; c < 3; ++c) {
+            fa[3 * p + c] = ok ? r.plus[c] : px[3 * p + c];
+            fb[3 * p + c] = ok ? r.minus[c] : px[3 * p + c];
+        }
+        got += ok ? 1u : 0u;
+    }
+    const uint32_t s = wave_sum_u32(got);
+    if ((threadIdx.x & 63u) == 0 && s && resolved) atomicAdd(resolved, (unsigned long long)s);
+}
+
+__global__ void k_set_u64(uint64_t* __restrict__ p, uint64_t v) { *p = v; }
+
+// ---------------------------------------------------------------------------
 // Host side.
 
 namespace {
@@ -327,10 +501,10 @@ int launch_resolve_t(cv_context* ctx, const ResolveArgs& a, hipStream_t s) {
     return CV_OK;
 }
 
-} // namespace
-
-// Everything the call enqueues, in order, on stream s (also used for capture).
-int FramesCall::enqueue(cv_context* ctx, hipStream_t s) const {
+// De-duplication: sorted distinct colours, their number (device, also in
+// ctx->fmisc[0]) and each pixel's index.
+int enqueue_dedupe(cv_context* ctx, const uint8_t* pixels, int64_t npix, uint8_t* colours,
+                   uint32_t* pixel_index, int64_t* ncolours, hipStream_t s) {
     int rc;
     uint32_t* bits = (uint32_t*)ctx->fbits.ptr;
     uint32_t* cnt = (uint32_t*)ctx->fcnt.ptr;
@@ -349,14 +523,25 @@ int FramesCall::enqueue(cv_context* ctx, hipStream_t s) const {
     hipLaunchKernelGGL(k_pixel_index, dim3(grid_for(npix, 256, 8192)), dim3(256), 0, s, pixels, npix,
                        bits, prefix, pixel_index);
     hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, misc, ncolours);
-    // the search of every distinct colour
-    if ((rc = launch_angle_table((double*)ctx->table.ptr, gd.N, s)) != CV_OK) return rc;
-    hipLaunchKernelGGL(k_prologue_dev, dim3(grid_for(colour_cap, 256, 8192)), dim3(256), 0, s,
-                       colours, misc, (ColorConst*)ctx->colors.ptr, frame_mat_args());
     CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
+// Angle table and per-colour constants of n_dev colours (at most cap).
+int enqueue_prologue(cv_context* ctx, const GridDev& gd, const uint8_t* colours, int64_t cap,
+                     const uint64_t* n_dev, hipStream_t s) {
+    int rc;
+    if ((rc = launch_angle_table((double*)ctx->table.ptr, gd.N, s)) != CV_OK) return rc;
+    hipLaunchKernelGGL(k_prologue_dev, dim3(grid_for(cap, 256, 8192)), dim3(256), 0, s, colours, n_dev,
+                       (ColorConst*)ctx->colors.ptr, frame_mat_args());
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
+ResolveArgs resolve_args(cv_context* ctx, const GridDev& gd, const RuleDev& rd, const uint64_t* n_dev) {
     ResolveArgs a;
     a.cc = (const ColorConst*)ctx->colors.ptr;
-    a.n_dev = misc;
+    a.n_dev = n_dev;
     a.tab.tab = (const double*)ctx->table.ptr;
     a.tab.tab_len = gd.tab_len;
     a.tab.N = gd.N;
@@ -371,16 +556,34 @@ int FramesCall::enqueue(cv_context* ctx, hipStream_t s) const {
     a.inv_W = 1.0f / (float)a.W;
     a.si = 256 / a.W;
     a.sj = 256 % a.W;
+    a.list = nullptr;
+    a.summ = nullptr;
+    a.pbest = nullptr;
+    a.rays = nullptr;
+    return a;
+}
+
+int launch_resolve(cv_context* ctx, const ResolveArgs& a, bool sym, hipStream_t s) {
+    if (sym) return a.rays ? launch_resolve_t<true, true>(ctx, a, s) : launch_resolve_t<true, false>(ctx, a, s);
+    return a.rays ? launch_resolve_t<false, true>(ctx, a, s) : launch_resolve_t<false, false>(ctx, a, s);
+}
+
+} // namespace
+
+// Everything the call enqueues, in order, on stream s (also used for capture).
+int FramesCall::enqueue(cv_context* ctx, hipStream_t s) const {
+    int rc;
+    uint64_t* misc = (uint64_t*)ctx->fmisc.ptr;  // [0] colour count
+    if ((rc = enqueue_dedupe(ctx, pixels, npix, colours, pixel_index, ncolours, s)) != CV_OK) return rc;
+    // the search of every distinct colour
+    if ((rc = enqueue_prologue(ctx, gd, colours, colour_cap, misc, s)) != CV_OK) return rc;
+    ResolveArgs a = resolve_args(ctx, gd, rd, misc);
+    const bool sym = gd.ntheta == gd.N;
     a.summ = summ;
     a.pbest = pbest;
     a.rays = rays;
     if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
-    if (sym) {
-        rc = rays ? launch_resolve_t<true, true>(ctx, a, s) : launch_resolve_t<true, false>(ctx, a, s);
-    } else {
-        rc = rays ? launch_resolve_t<false, true>(ctx, a, s) : launch_resolve_t<false, false>(ctx, a, s);
-    }
-    if (rc != CV_OK) return rc;
+    if ((rc = launch_resolve(ctx, a, sym, s)) != CV_OK) return rc;
     if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
     if (frame_a) {
         if (resolved)
@@ -450,6 +653,148 @@ int run_frames_resolve(cv_context* ctx, const FramesCall& call_in, bool graph, h
     }
     if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
     CV_HIP(hipGraphLaunch(ctx->fgraph_exec, s));
+    if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
+    if (ctx->timing) {
+        CV_HIP(hipStreamSynchronize(s));
+        if ((rc = ctx->collect()) != CV_OK) return rc;
+    }
+    return CV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Surrogate resolve, host side.
+
+namespace {
+
+int ensure_surrogate(cv_context* ctx, const SurrogateCall& c, int64_t n) {
+    int rc;
+    const int64_t m = n > 0 ? n : 1;
+    if ((rc = ctx->ensure(ctx->colors, (size_t)m * sizeof(ColorConst))) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->table, (size_t)c.gd.tab_len * 8)) != CV_OK) return rc;
+    if (!c.pred && (rc = ctx->ensure(ctx->spred, (size_t)m * 37 * sizeof(float))) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->sneed, (size_t)m * 4)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->sprefix, (size_t)m * 8)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->slist, (size_t)m * 4)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->ssumm, (size_t)m * sizeof(cv_color_summary))) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->smisc, 64)) != CV_OK) return rc;
+    return CV_OK;
+}
+
+// The surrogate resolve of n colours whose count is also at n_dev.
+int enqueue_surrogate(cv_context* ctx, const SurrogateCall& c, const uint8_t* rgb, int64_t n,
+                      const uint64_t* n_dev, hipStream_t s) {
+    int rc;
+    uint64_t* smisc = (uint64_t*)ctx->smisc.ptr;  // [1] fallback count
+    float* pred = c.pred ? c.pred : (float*)ctx->spred.ptr;
+    if ((rc = enqueue_prologue(ctx, c.gd, rgb, n, n_dev, s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_MLP, 0, s)) != CV_OK) return rc;
+    if ((rc = mlp_forward_rgb8(c.mlp, rgb, n, pred, s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_MLP, 1, s)) != CV_OK) return rc;
+    ProposeArgs p;
+    p.cc = (const ColorConst*)ctx->colors.ptr;
+    p.n_dev = n_dev;
+    p.pred = pred;
+    p.tab.tab = (const double*)ctx->table.ptr;
+    p.tab.tab_len = c.gd.tab_len;
+    p.tab.N = c.gd.N;
+    p.g = geom_constants();
+    p.rule = c.rd;
+    p.ra = c.gd.ra;
+    p.rb = c.gd.rb;
+    p.dr = (float)c.gd.dr;
+    p.nr = c.gd.nr;
+    p.ntheta = c.gd.ntheta;
+    p.tau = c.tau;
+    p.kbins = c.kbins;
+    p.pairs = c.pairs;
+    p.status = c.status;
+    p.need = (uint32_t*)ctx->sneed.ptr;
+    if ((rc = ctx->mark(CV_TIME_VERIFY, 0, s)) != CV_OK) return rc;
+    int lds_max = 0;
+    CV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    if ((size_t)c.gd.tab_len * 8 > (size_t)lds_max) return fail(CV_EINVAL, "angle table exceeds LDS");
+    hipLaunchKernelGGL(k_propose_verify, dim3(grid_for(n, 4, 65536)), dim3(256),
+                       (size_t)c.gd.tab_len * 8, s, p);
+    CV_HIP(hipGetLastError());
+    if ((rc = ctx->mark(CV_TIME_VERIFY, 1, s)) != CV_OK) return rc;
+    // colours without a verified proposal, counted (and listed) in colour order
+    uint64_t* prefix = (uint64_t*)ctx->sprefix.ptr;
+    uint32_t* list = (uint32_t*)ctx->slist.ptr;
+    if ((rc = run_scan_counts(ctx, (const uint32_t*)ctx->sneed.ptr, n, prefix, nullptr, 1, 0, smisc + 1,
+                              s)) != CV_OK)
+        return rc;
+    if (c.fallback) {
+        hipLaunchKernelGGL(k_make_list, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s,
+                           (const uint32_t*)ctx->sneed.ptr, prefix, n_dev, list);
+        CV_HIP(hipGetLastError());
+        ResolveArgs a = resolve_args(ctx, c.gd, c.rd, smisc + 1);
+        a.list = list;
+        a.summ = (cv_color_summary*)ctx->ssumm.ptr;
+        if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
+        if ((rc = launch_resolve(ctx, a, c.gd.ntheta == c.gd.N, s)) != CV_OK) return rc;
+        if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
+        hipLaunchKernelGGL(k_fallback_finish, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, list,
+                           smisc + 1, (const cv_color_summary*)ctx->ssumm.ptr, c.pairs, c.status);
+        CV_HIP(hipGetLastError());
+    }
+    if (c.nfallback) hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, smisc + 1, c.nfallback);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
+} // namespace
+
+int run_surrogate(cv_context* ctx, const SurrogateCall& c, hipStream_t s) {
+    int rc;
+    if (c.n == 0) {
+        if (c.nfallback) {
+            if ((rc = ctx->ensure(ctx->smisc, 64)) != CV_OK) return rc;
+            hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, (uint64_t*)c.nfallback, (int64_t)1);
+            CV_HIP(hipGetLastError());
+        }
+        return CV_OK;
+    }
+    if ((rc = ensure_surrogate(ctx, c, c.n)) != CV_OK) return rc;
+    uint64_t* smisc = (uint64_t*)ctx->smisc.ptr;
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, smisc, (uint64_t)c.n);
+    CV_HIP(hipGetLastError());
+    if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
+    if ((rc = enqueue_surrogate(ctx, c, c.rgb, c.n, smisc, s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
+    if (ctx->timing) {
+        CV_HIP(hipStreamSynchronize(s));
+        if ((rc = ctx->collect()) != CV_OK) return rc;
+    }
+    return CV_OK;
+}
+
+int run_frames_surrogate(cv_context* ctx, const SurrogateCall& c, const uint8_t* pixels, int64_t npix,
+                         uint8_t* colours, int64_t colour_cap, int64_t* ncolours,
+                         uint32_t* pixel_index, uint8_t* frame_a, uint8_t* frame_b,
+                         int64_t* resolved, hipStream_t s) {
+    int rc;
+    if ((rc = ctx->ensure(ctx->fbits, (size_t)kCubeWords * 4)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->fcnt, (size_t)kCubeWords * 4)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->fprefix, (size_t)kCubeWords * 8)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->fmisc, 64)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
+    if ((rc = enqueue_dedupe(ctx, pixels, npix, colours, pixel_index, ncolours, s)) != CV_OK) return rc;
+    // the network runs on exactly the distinct colours: read their number
+    CV_HIP(hipMemcpyAsync(ctx->host_misc, ctx->fmisc.ptr, 8, hipMemcpyDeviceToHost, s));
+    CV_HIP(hipStreamSynchronize(s));
+    const int64_t n = (int64_t)ctx->host_misc[0];
+    if (n < 1 || n > colour_cap) return fail(CV_ESTATE, "internal: distinct colour count");
+    if ((rc = ensure_surrogate(ctx, c, n)) != CV_OK) return rc;
+    if ((rc = enqueue_surrogate(ctx, c, colours, n, (const uint64_t*)ctx->fmisc.ptr, s)) != CV_OK)
+        return rc;
+    if (frame_a) {
+        if (resolved)
+            hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, (uint64_t*)resolved, (int64_t)1);
+        hipLaunchKernelGGL(k_render_pairs, dim3(grid_for(npix, 256, 8192)), dim3(256), 0, s, pixels, npix,
+                           pixel_index, (const cv_pattern_pair*)c.pairs, frame_a, frame_b,
+                           (unsigned long long*)resolved);
+        CV_HIP(hipGetLastError());
+    }
     if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
     if (ctx->timing) {
         CV_HIP(hipStreamSynchronize(s));

@@ -107,6 +107,33 @@ struct FramesCall {
 };
 int run_frames_resolve(cv_context* ctx, const FramesCall& call, bool graph, hipStream_t s);
 
+// Surrogate resolve of n colours (n_dev: the same count on the device).
+struct SurrogateCall {
+    cv_mlp* mlp;
+    const uint8_t* rgb;
+    int64_t n;
+    GridDev gd;
+    RuleDev rd;
+    float tau;
+    int32_t kbins;
+    bool fallback;
+    float* pred;              // nullable: a context workspace is used
+    cv_pattern_pair* pairs;
+    uint8_t* status;
+    int64_t* nfallback;       // nullable
+};
+int run_surrogate(cv_context* ctx, const SurrogateCall& call, hipStream_t s);
+int run_frames_surrogate(cv_context* ctx, const SurrogateCall& call, const uint8_t* pixels,
+                         int64_t npix, uint8_t* colours, int64_t colour_cap, int64_t* ncolours,
+                         uint32_t* pixel_index, uint8_t* frame_a, uint8_t* frame_b,
+                         int64_t* resolved, hipStream_t s);
+
+// Network pieces used by the surrogate resolve (defined with the network).
+int mlp_forward_rgb8(cv_mlp* m, const uint8_t* rgb, int64_t n, float* out, hipStream_t s);
+int mlp_out_width(const cv_mlp* m);
+int mlp_in_width(const cv_mlp* m);
+int mlp_device(const cv_mlp* m);
+
 } // namespace cvib
 
 struct cv_context {
@@ -123,16 +150,23 @@ struct cv_context {
     cvib::Buffer fcnt;        // frames: colours per bitmap word
     cvib::Buffer fprefix;     // frames: first colour index per bitmap word
     cvib::Buffer fmisc;       // frames: [0] colour count
+    cvib::Buffer spred;       // surrogate: network outputs [n][37]
+    cvib::Buffer sneed;       // surrogate: 1 = exact fallback, per colour
+    cvib::Buffer sprefix;     // surrogate: fallback list positions
+    cvib::Buffer slist;       // surrogate: fallback colour indices
+    cvib::Buffer ssumm;       // surrogate: exact summaries of fallback colours
+    cvib::Buffer smisc;       // surrogate: [0] colour count, [1] fallback count
     hipStream_t cap_stream = nullptr;        // stream used for graph capture
     hipGraphExec_t fgraph_exec = nullptr;    // captured cv_frames_resolve
     cvib::FramesCall fgraph_call{};          // the call it was captured for
     uint64_t* host_misc = nullptr; // pinned mirror of misc for the total
     // kernel timing (cv_context_set_timing): event pairs and totals per phase
     bool timing = false;
-    hipEvent_t ev[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
-    bool armed[3] = {false, false, false};
-    double kernel_ms[3] = {0.0, 0.0, 0.0};
-    int64_t kernel_calls[3] = {0, 0, 0};
+    static constexpr int kPhases = 5;
+    hipEvent_t ev[kPhases][2] = {};
+    bool armed[kPhases] = {};
+    double kernel_ms[kPhases] = {};
+    int64_t kernel_calls[kPhases] = {};
     int ensure(cvib::Buffer& b, size_t bytes);
     int mark(int phase, int end, hipStream_t s);  // record a phase's start / end event
     int collect();                                // after a sync: add armed phases

@@ -560,6 +560,14 @@ void free_mlp(cv_mlp* m) {
 const char kMagic[8] = {'C', 'V', 'M', 'L', 'P', '0', '1', '\0'};
 
 } // namespace
+
+int mlp_forward_rgb8(cv_mlp* m, const uint8_t* rgb, int64_t n, float* out, hipStream_t s) {
+    return run_forward(m, rgb, true, n, out, false, s);
+}
+int mlp_out_width(const cv_mlp* m) { return m->dims[m->L]; }
+int mlp_in_width(const cv_mlp* m) { return m->dims[0]; }
+int mlp_device(const cv_mlp* m) { return m->device; }
+
 } // namespace cvib
 
 using cvib::DeviceGuard;

@@ -1,0 +1,158 @@
+"""Surrogate resolve on the GPU: a network trained by the library's kernels on
+the exact search's whole-cube table proposes pairs; every emitted pair must
+be a survivor of the exact search (checked against the FP64 oracle), the
+fallback must reproduce the exact search, and the trained network must do
+better than an untrained one."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cv():
+    import paper_2507_22901_amd as cv
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cv.lib()
+    return cv
+
+
+@pytest.fixture(scope="module")
+def trained(cv):
+    from paper_2507_22901_amd import surrogate as S
+    g = W.GRID_CUBE
+    table = S.cube_table(cv.Grid(*g.astuple()), cv.Rule(*W.DEFAULT_RULE))
+    test_mask = torch.from_numpy(W.cube_split(0))
+    ids = torch.arange(1 << 24, dtype=torch.int32)
+    train_ids = ids[~test_mask].cuda()
+    m = cv.MLP()
+    m.set_params(cv.init_params(cv.SURROGATE_DIMS, 0))
+    steps, log, secs = S.train(m, table, train_ids, g.dr, epochs=1.0, log_every=100)
+    return {"mlp": m, "table": table, "log": log, "test_ids": ids[test_mask].cuda(), "S": S}
+
+
+def _colours():
+    return np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(21, 2991)])
+
+
+def test_training_reduces_loss(cv, trained):
+    log = trained["log"]
+    first, last = log[0][1], np.mean([l for _, l in log[-3:]])
+    assert np.isfinite(last) and last < 0.5 * first, log
+    ev = trained["S"].evaluate(trained["mlp"], trained["table"], trained["test_ids"][:200000],
+                               W.GRID_CUBE.dr)
+    print("after one epoch:", ev)
+    assert ev["radius_mae"] < 5.0 and ev["feasible_recall"] > 0.8
+
+
+def test_emitted_pairs_are_exact_survivors(cv, oracle, trained):
+    cols = _colours()
+    grid = W.GRID_FRAMES.astuple()
+    rule = W.DEFAULT_RULE
+    res = cv.surrogate_infer(torch.from_numpy(cols).cuda(), trained["mlp"], cv.Grid(*grid),
+                             cv.Rule(*rule), tau=0.0, kbins=4)
+    pairs = cv.as_records(res.pairs, cv.PATTERN_PAIR_DTYPE)
+    status = res.status.cpu().numpy()
+    sur = (pairs["flags"] & cv.CV_PAIR_SURROGATE) != 0
+    fb = (pairs["flags"] & cv.CV_PAIR_FALLBACK) != 0
+    assert np.all(sur == (status == cv.CV_RESOLVED_SURROGATE))
+    assert np.all(fb == (status == cv.CV_RESOLVED_EXACT))
+    assert sur.mean() > 0.3
+    # every surrogate pair is a survivor of the exact search (oracle, FP64)
+    k = np.nonzero(sur)[0]
+    cand = oracle.eval_list(cols, np.stack([k, pairs["i"][k], pairs["j"][k]], 1), grid, rule)
+    clear = cand["boundary"] == 0
+    assert np.all(cand["valid"][clear] == 1)
+    assert np.array_equal(cand["Vp"][clear], pairs["plus"][k][clear])
+    assert np.array_equal(cand["Vm"][clear], pairs["minus"][k][clear])
+    assert np.array_equal(cand["pattern"][clear], pairs["pattern"][k][clear])
+    # the exact search's best pair bounds every verified radius from above,
+    # and the fallback pairs are the exact search's best pairs
+    summ, _ = cv.pair_reduce(torch.from_numpy(cols).cuda(), cv.Grid(*grid), cv.Rule(*rule))
+    s = cv.as_records(summ, cv.SUMMARY_DTYPE)
+    assert np.all(s["count"][sur] > 0) and np.all(pairs["i"][sur] <= s["best_i"][sur])
+    assert np.array_equal(pairs["i"][fb], s["best_i"][fb]) and np.array_equal(pairs["j"][fb], s["best_j"][fb])
+    assert np.array_equal(pairs["plus"][fb], s["best_plus"][fb])
+    none = status == cv.CV_RESOLVED_NONE
+    assert np.all(s["count"][none] == 0)
+    assert int(res.nfallback.item()) == int((~sur).sum())
+    gap = (s["best_i"][sur].astype(np.int64) - pairs["i"][sur]) * W.GRID_FRAMES.dr
+    print(f"surrogate {sur.sum()} / fallback {fb.sum()} / none {none.sum()}; "
+          f"radius below the exact best: mean {gap.mean():.2f}, max {gap.max():.2f}")
+
+
+def test_fallback_only_equals_exact(cv, trained):
+    cols = torch.from_numpy(_colours()[:800]).cuda()
+    grid, rule = cv.Grid(*W.GRID_FRAMES.astuple()), cv.Rule(*W.DEFAULT_RULE)
+    res = cv.surrogate_infer(cols, trained["mlp"], grid, rule, tau=float("inf"))
+    pairs = cv.as_records(res.pairs, cv.PATTERN_PAIR_DTYPE)
+    summ, _ = cv.pair_reduce(cols, grid, rule)
+    s = cv.as_records(summ, cv.SUMMARY_DTYPE)
+    has = s["count"] > 0
+    assert int(res.nfallback.item()) == len(s)
+    assert np.array_equal((pairs["flags"] & cv.CV_PAIR_FOUND) != 0, has)
+    for f in ("i", "j"):
+        assert np.array_equal(pairs[f][has], s["best_" + f][has])
+    assert np.array_equal(pairs["plus"][has], s["best_plus"][has])
+    assert np.array_equal(pairs["minus"][has], s["best_minus"][has])
+    assert np.array_equal(pairs["pattern"][has], s["best_p"][has])
+
+
+def test_no_fallback_mode(cv, trained):
+    cols = torch.from_numpy(_colours()).cuda()
+    grid, rule = cv.Grid(*W.GRID_FRAMES.astuple()), cv.Rule(*W.DEFAULT_RULE)
+    a = cv.surrogate_infer(cols, trained["mlp"], grid, rule, tau=0.0, want_pred=True)
+    b = cv.surrogate_infer(cols, trained["mlp"], grid, rule, tau=0.0, fallback=False)
+    sa, sb = a.status.cpu().numpy(), b.status.cpu().numpy()
+    sur = sa == cv.CV_RESOLVED_SURROGATE
+    assert np.array_equal(sb == cv.CV_RESOLVED_SURROGATE, sur)
+    assert np.all(sb[~sur] == cv.CV_RESOLVED_NONE)
+    assert torch.equal(a.pairs[torch.from_numpy(sur).cuda()], b.pairs[torch.from_numpy(sur).cuda()])
+    assert int(b.nfallback.item()) == int((~sur).sum())
+    # the network outputs are the forward pass's
+    assert torch.equal(a.pred, trained["mlp"].forward(cols))
+
+
+def test_frames_surrogate_matches_pieces(cv, trained):
+    f = W.frames([11, 12], height=96, width=160)
+    px = torch.from_numpy(f).cuda()
+    grid, rule = cv.Grid(*W.GRID_FRAMES.astuple()), cv.Rule(*W.DEFAULT_RULE)
+    res = cv.frames_surrogate(px, trained["mlp"], grid, rule, tau=0.0)
+    ex = cv.frames_resolve(px, grid, rule)
+    n = int(res.ncolours.item())
+    assert n == int(ex.ncolours.item())
+    assert torch.equal(res.colours[:n], ex.colours[:n])
+    assert torch.equal(res.pixel_index, ex.pixel_index)
+    one = cv.surrogate_infer(res.colours[:n], trained["mlp"], grid, rule, tau=0.0)
+    assert torch.equal(one.pairs, res.pairs[:n]) and torch.equal(one.status, res.status[:n])
+    assert int(one.nfallback.item()) == int(res.nfallback.item())
+    idx = res.pixel_index.long()
+    pb = res.pairs[idx]
+    has = (pb[:, 11] & 1).bool()
+    flat = px.reshape(-1, 3)
+    assert torch.equal(res.frame_a, torch.where(has[:, None], pb[:, 4:7], flat))
+    assert torch.equal(res.frame_b, torch.where(has[:, None], pb[:, 7:10], flat))
+    assert int(res.resolved.item()) == int(has.sum())
+
+
+def test_trained_network_gains(cv, trained):
+    """What training buys: fewer colours left to the exact search, at a
+    larger verified radius, than the same resolve with the untrained
+    network."""
+    cols = torch.from_numpy(_colours()).cuda()
+    grid, rule = cv.Grid(*W.GRID_FRAMES.astuple()), cv.Rule(*W.DEFAULT_RULE)
+    raw = cv.MLP()
+    raw.set_params(cv.init_params(cv.SURROGATE_DIMS, 0))
+    out = {}
+    for name, m in (("trained", trained["mlp"]), ("untrained", raw)):
+        r = cv.surrogate_infer(cols, m, grid, rule, tau=0.0, fallback=False)
+        p = cv.as_records(r.pairs, cv.PATTERN_PAIR_DTYPE)
+        ok = (p["flags"] & cv.CV_PAIR_SURROGATE) != 0
+        out[name] = (ok.mean(), float(p["i"][ok].mean()) if ok.any() else 0.0)
+    print("verified fraction, mean verified radius index:", out)
+    assert out["trained"][0] > out["untrained"][0] + 0.2

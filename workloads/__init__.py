@@ -117,3 +117,11 @@ def info_map(seed: int, height: int = 2160, width: int = 3840, block: int = 16) 
     bh, bw = -(-height // block), -(-width // block)
     cells = rng.integers(1, 8, size=(bh, bw), dtype=np.uint8)
     return np.repeat(np.repeat(cells, block, axis=0), block, axis=1)[:height, :width].copy()
+
+
+def cube_split(seed: int = 0, test_fraction: float = 0.1) -> np.ndarray:
+    """Held-out mask over all 2^24 colour ids: colour id k is a test colour
+    when the k-th uniform draw of a Philox stream keyed by `seed` is below
+    `test_fraction` (about 10%, fixed per seed)."""
+    rng = np.random.Generator(np.random.Philox(key=seed))
+    return rng.random(1 << 24) < test_fraction
