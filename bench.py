@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--only", choices=("all", "nine", "frames", "cube"), default="all",
+    ap.add_argument("--epochs", type=float, default=4.0, help="surrogate training epochs")
+    ap.add_argument("--only", choices=("all", "nine", "frames", "cube", "surrogate"), default="all",
                     help="run one workload only (the JSON line then carries just that part)")
     return ap.parse_args()
 
@@ -106,6 +107,97 @@ def bench_frames(cv, W, torch, steps):
         "ms_per_call": ms, "calls": steps, "resolved_pixels": int(out.resolved.item()),
         "resolve_kernel_ms": t_res,
         "roofline": _alu_roofline("k_colour_resolve", t_res, evals, gamut),
+    }
+
+
+MLP_FWD_FLOPS = 2 * (3 * 256 + 256 * 256 * 2 + 256 * 37)   # 282,624 per sample
+MLP_TRAIN_FLOPS = 3 * MLP_FWD_FLOPS                          # forward + two backward products
+MFMA_BF16_PEAK = 2.5e15
+
+
+def bench_surrogate(cv, W, torch, epochs, steps):
+    """Train the surrogate on the exact search's whole-cube table (90/10
+    split), then resolve 16 synthetic 4K frames (seeds 100..115) both ways:
+    the exact batched search and the surrogate with verify and fallback."""
+    import numpy as np
+    from paper_2507_22901_amd import surrogate as S
+    gc = W.GRID_CUBE
+    t0 = time.perf_counter()
+    table = S.cube_table(cv.Grid(*gc.astuple()), cv.Rule(*W.DEFAULT_RULE))
+    torch.cuda.synchronize()
+    t_table = time.perf_counter() - t0
+    mask = torch.from_numpy(W.cube_split(0))
+    ids = torch.arange(1 << 24, dtype=torch.int32)
+    tr_ids, te_ids = ids[~mask].cuda(), ids[mask].cuda()
+    m = cv.MLP()
+    m.set_params(cv.init_params(cv.SURROGATE_DIMS, 0))
+    nsteps, log, t_train = S.train(m, table, tr_ids, gc.dr, epochs=epochs, log_every=500)
+    rows = nsteps * 8192
+    ev = S.evaluate(m, table, te_ids, gc.dr)
+    # frames
+    f = W.frames(range(100, 116))
+    px = torch.from_numpy(f).cuda()
+    del f
+    g = W.GRID_FRAMES
+    grid, rule = cv.Grid(*g.astuple()), cv.Rule(*W.DEFAULT_RULE)
+    ctx = m.ctx
+    ev_start, ev_stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        ev_start.record()
+        for _ in range(n):
+            fn()
+        ev_stop.record()
+        torch.cuda.synchronize()
+        return ev_start.elapsed_time(ev_stop) / n
+
+    ex = cv.frames_resolve(px, grid, rule, ctx=ctx)
+    ms_exact = timed(lambda: cv.frames_resolve(px, grid, rule, out=ex, ctx=ctx), max(1, steps - 1))
+    sr = cv.frames_surrogate(px, m, grid, rule, tau=0.0, kbins=3, ctx=ctx)
+    ms_sur = timed(lambda: cv.frames_surrogate(px, m, grid, rule, tau=0.0, kbins=3, out=sr, ctx=ctx), steps)
+    # phase times of one surrogate call
+    ctx.set_timing(True)
+    for ph in (cv.CV_TIME_MLP, cv.CV_TIME_VERIFY, cv.CV_TIME_EVAL, cv.CV_TIME_CALL):
+        ctx.kernel_time(ph, reset=True)
+    cv.frames_surrogate(px, m, grid, rule, tau=0.0, kbins=3, out=sr, ctx=ctx)
+    ph = {k: ctx.kernel_time(v, reset=True)[0] for k, v in
+          (("mlp", cv.CV_TIME_MLP), ("verify", cv.CV_TIME_VERIFY), ("fallback", cv.CV_TIME_EVAL),
+           ("call", cv.CV_TIME_CALL))}
+    ctx.set_timing(False)
+    n = int(sr.ncolours.item())
+    st = sr.status[:n].cpu().numpy()
+    pairs = cv.as_records(sr.pairs[:n], cv.PATTERN_PAIR_DTYPE)
+    summ = cv.as_records(ex.summaries[:n], cv.SUMMARY_DTYPE)
+    sur = st == cv.CV_RESOLVED_SURROGATE
+    gap = (summ["best_i"][sur].astype(np.int64) - pairs["i"][sur]) * g.dr
+    exact_found = int((summ["count"] > 0).sum())
+    found = int((st != cv.CV_RESOLVED_NONE).sum())
+    mlp_ms = ph["mlp"]
+    return {
+        "workload": "surrogate 3-256-256-256-37 trained on the 2^24-colour table (r step 0.25, "
+                    "theta step 2 deg; 90/10 split, seed 0); 16 synthetic 3840x2160 frames "
+                    "(seeds 100..115) on r = 0.1..50 step 0.1 x theta step 1 deg",
+        "table_s": t_table,
+        "train": {"epochs": epochs, "steps": nsteps, "batch": 8192, "seconds": t_train,
+                  "samples_per_s": rows / t_train,
+                  "tflops": rows * MLP_TRAIN_FLOPS / t_train / 1e12,
+                  "mfma_frac": rows * MLP_TRAIN_FLOPS / t_train / MFMA_BF16_PEAK,
+                  "loss_first": log[0][1], "loss_last": log[-1][1]},
+        "heldout": ev,
+        "distinct_colours": n,
+        "exact": {"ms_per_call": ms_exact, "colours_per_s": n / (ms_exact * 1e-3),
+                  "colours_with_pair": exact_found},
+        "surrogate": {"ms_per_call": ms_sur, "colours_per_s": n / (ms_sur * 1e-3),
+                      "resolved_by_network": int(sur.sum()), "fallback": int(sr.nfallback.item()),
+                      "fallback_frac": int(sr.nfallback.item()) / n,
+                      "colours_with_pair": found,
+                      "radius_gap_mean": float(gap.mean()) if len(gap) else None,
+                      "radius_gap_p95": float(np.percentile(gap, 95)) if len(gap) else None,
+                      "phases_ms": ph,
+                      "mlp_tflops": n * MLP_FWD_FLOPS / (mlp_ms * 1e-3) / 1e12 if mlp_ms > 0 else None},
+        "speedup": ms_exact / ms_sur,
     }
 
 
@@ -265,6 +357,8 @@ def main():
         res["frames_exact"] = bench_frames(cv, W, torch, 3)
     if args.only in ("all", "cube"):
         res["cube_table"] = bench_cube(cv, W, torch, 2)
+    if args.only in ("all", "surrogate"):
+        res["surrogate_frames"] = bench_surrogate(cv, W, torch, args.epochs, 3)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(res))

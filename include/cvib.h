@@ -345,10 +345,13 @@ int cv_mlp_load(cv_mlp* m, const char* path);
  *
  * For a colour whose logit is >= tau, the network's kbins bins of largest
  * predicted radius r (1 <= kbins <= 36) each propose every ray j of the bin
- * (floor(36 j / N) = bin, j < ntheta) at the radius indices
- * round(r / dr) - t, t = 0..5.  Every proposal runs through the same
- * arithmetic as the exact search, so a verified pair is one of its
- * survivors; the verified proposal of largest i (then smallest j) is kept.
+ * (floor(36 j / N) = bin, j < ntheta) at the grid radii nearest to r + o,
+ * o in {+1, 0, -1, -2.5, -5, -10} (Delta E 1976 units).  When theta spans
+ * the full turn only the 18 bins of the first half-turn are ranked (by the
+ * mean prediction of bin b and its mirror b + 18) and proposed.  Every
+ * proposal runs through the same arithmetic as the exact search, so a
+ * verified pair is one of its survivors; the verified proposal of largest i
+ * (then smallest j) is kept.
  * Colours with a lower logit or with no verified proposal go to the exact
  * search (its maximum-amplitude pair), unless CV_NO_FALLBACK is set.
  */

@@ -293,16 +293,21 @@ __global__ void k_copy_count(const uint64_t* __restrict__ src, int64_t* __restri
 // Surrogate resolve.  The network's outputs for colour c are 36 predicted
 // maximum radii (divided by 50) and a feasibility logit.  A colour whose
 // logit reaches tau gets proposals: in each of its kbins bins of largest
-// predicted radius, every ray of the bin at radius indices i0 + 1, i0, ...,
-// i0 - (kDeltas - 2), i0 being the grid index of the predicted radius.  Each
-// proposal runs through the exact predicate of the search (the same device
-// functions and the same arithmetic), so a verified pair is a survivor of
-// the exact search; the verified pair of largest i (then smallest j) is kept.
-// Colours with a low logit or without a verified proposal go to the exact
-// fallback.  One wave per colour.
+// predicted radius r, every ray of the bin at the radii r + o for o on a
+// fixed ladder (Delta E units: +1, 0, -1, -2.5, -5, -10), snapped to the grid.
+// When theta spans the full turn, bin b + 18 holds the mirror images of bin
+// b's pairs, so the 18 bins of the first half-turn are ranked by the mean of
+// the two predictions and only they are proposed (the mirror image of a pair
+// has the same validity and a larger j).  Each proposal runs through the
+// exact predicate of the search (the same device functions and the same
+// arithmetic), so a verified pair is a survivor of the exact search; the
+// verified pair of largest i (then smallest j) is kept.  Colours with a low
+// logit or without a verified proposal go to the exact fallback.  One wave
+// per colour.
 
 constexpr int kBins = 36;
 constexpr int kDeltas = 6;
+__constant__ float kLadder[kDeltas] = {1.0f, 0.0f, -1.0f, -2.5f, -5.0f, -10.0f};
 
 struct ProposeArgs {
     const ColorConst* cc;
@@ -331,19 +336,23 @@ __global__ __launch_bounds__(256) void k_propose_verify(ProposeArgs a) {
     const int64_t GW = (int64_t)gridDim.x * 4;
     for (int64_t c = (int64_t)blockIdx.x * 4 + (tid >> 6); c < n; c += GW) {
         const float* p = a.pred + c * (kBins + 1);
-        const float rk = lane < kBins ? p[lane] * 50.0f : -INFINITY;
+        const bool half = a.ntheta == a.tab.N;  // rank the first half-turn only
+        const int nb = half ? kBins / 2 : kBins;
+        float rk = -INFINITY;
+        if (lane < nb) rk = half ? 25.0f * (p[lane] + p[lane + kBins / 2]) : 50.0f * p[lane];
         const float logit = p[kBins];
         const ColorConst cc = a.cc[c];
         uint32_t best = 0;
         if (logit >= a.tau) {
             // rank of every bin by predicted radius (ties: lower bin first)
             int rank = 0;
-            for (int q = 0; q < kBins; ++q) {
+            for (int q = 0; q < nb; ++q) {
                 const float rq = __shfl(rk, q);
                 rank += (rq > rk || (rq == rk && q < lane)) ? 1 : 0;
             }
-            for (int b = 0; b < a.kbins; ++b) {
-                const uint64_t sel = __ballot(lane < kBins && rank == b);
+            const int kb = min(a.kbins, nb);
+            for (int b = 0; b < kb; ++b) {
+                const uint64_t sel = __ballot(lane < nb && rank == b);
                 const int bin = (int)__builtin_ctzll(sel);
                 const float rh = __shfl(rk, bin);
                 // rays of the bin: floor(36 j / N) = bin
@@ -351,12 +360,13 @@ __global__ __launch_bounds__(256) void k_propose_verify(ProposeArgs a) {
                 const int32_t j_hi = min(((bin + 1) * a.tab.N + kBins - 1) / kBins, a.ntheta);
                 const int32_t nrays = j_hi - j_lo;
                 if (nrays <= 0) continue;
-                const int32_t i_top = (int32_t)rintf(fminf(fmaxf(rh / a.dr, 0.0f), 65536.0f));  // i0 + 1
                 const int32_t ncand = nrays * kDeltas;
                 for (int32_t u0 = 0; u0 < ncand; u0 += 64) {
                     const int32_t u = u0 + lane;
-                    const int32_t t = u / nrays, q = u - t * nrays;
-                    const int32_t i = i_top - t;
+                    const int32_t t = min(u / nrays, kDeltas - 1), q = u - (u / nrays) * nrays;
+                    // radius r_i = (i + 1) dr nearest to the ladder point
+                    const float rr_t = fminf(fmaxf((rh + kLadder[t]) / a.dr, 0.0f), 65536.0f);
+                    const int32_t i = (int32_t)rintf(rr_t) - 1;
                     const int32_t j = j_lo + (u < ncand ? q : 0);
                     const bool live = u < ncand && i >= 0 && i < a.nr;
                     double sn, co;
