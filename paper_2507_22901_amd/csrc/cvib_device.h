@@ -47,14 +47,21 @@ __device__ __forceinline__ double finv(double u) {
     return u > kDelta ? cube : lin;
 }
 
+constexpr float kEncodeKnee = 0.0031308f;  // linear segment at or below
+
+// Power segment of the sRGB encode in code units: 255 (1.055 l^(1/2.4) - 0.055).
+__device__ __forceinline__ float encode255_pow(float l) {
+    float lg = __builtin_amdgcn_logf(l);                 // log2 (v_log_f32)
+    float p = __builtin_amdgcn_exp2f(lg * (1.0f / 2.4f)); // 2^(log2(l)/2.4)
+    return __builtin_fmaf(255.0f * 1.055f, p, -255.0f * 0.055f);
+}
+
 // sRGB encode of an FP32 linear value, in 0..255 code units (unrounded).
 // Outside [0,1] the two branches extend the curve monotonically.
 __device__ __forceinline__ float encode255(float l) {
-    float lg = __builtin_amdgcn_logf(l);                 // log2 (v_log_f32)
-    float p = __builtin_amdgcn_exp2f(lg * (1.0f / 2.4f)); // 2^(log2(l)/2.4)
-    float g = __builtin_fmaf(255.0f * 1.055f, p, -255.0f * 0.055f);
+    float g = encode255_pow(l);
     float s = l * (255.0f * 12.92f);
-    return l <= 0.0031308f ? s : g;
+    return l <= kEncodeKnee ? s : g;
 }
 
 // One colour of a candidate pair: displaced (fx, fz) -> linear RGB (FP64).
@@ -81,6 +88,31 @@ __device__ __forceinline__ void pair_linear(const ColorConst& cc, const Geom& g,
     }
 }
 
+// pair_linear for a whole wave, with the cube branch of finv taken without a
+// select when no lane of the wave needs the linear branch (same results).
+__device__ __forceinline__ void pair_linear_w(const ColorConst& cc, const Geom& g, double dx,
+                                             double dz, float fp[3], float fm[3]) {
+    const double xp = cc.fx0 + dx, zp = cc.fz0 - dz, xm = cc.fx0 - dx, zm = cc.fz0 + dz;
+    double gxp, gzp, gxm, gzm;
+    const double lo = fmin(fmin(xp, zp), fmin(xm, zm));
+    if (__ballot(lo <= kDelta) == 0ull) {
+        gxp = xp * xp * xp;
+        gzp = zp * zp * zp;
+        gxm = xm * xm * xm;
+        gzm = zm * zm * zm;
+    } else {
+        gxp = finv(xp);
+        gzp = finv(zp);
+        gxm = finv(xm);
+        gzm = finv(zm);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        fp[k] = (float)__builtin_fma(g.A[k], gxp, __builtin_fma(g.C[k], gzp, cc.B[k]));
+        fm[k] = (float)__builtin_fma(g.A[k], gxm, __builtin_fma(g.C[k], gzm, cc.B[k]));
+    }
+}
+
 // All three linear channels in [0, 1]: the IEEE bit patterns of non-negative
 // floats order like the values, and every negative float (sign bit set)
 // compares above 1.0f's pattern as an unsigned integer.
@@ -94,6 +126,29 @@ __device__ __forceinline__ bool in_unit_cube(const float l[3]) {
 // reading it is the reading itself.
 __device__ __forceinline__ float code8(float l) {
     return __builtin_rintf(__builtin_amdgcn_fmed3f(encode255(l), 0.0f, 255.0f));
+}
+
+// 8-bit codes of both colours of a wave's candidates; lanes with need = false
+// get unspecified codes.  Without the clip reading every needed lane is in
+// gamut, so its codes lie in [0, 255] and the clamp is idle; when no needed
+// lane has a channel on the linear segment either, the power segment alone
+// gives the same codes as code8.
+__device__ __forceinline__ void codes_w(const float fp[3], const float fm[3], bool need, bool clip,
+                                        float Vp[3], float Vm[3]) {
+    const float lo = fminf(fminf(fminf(fp[0], fp[1]), fp[2]), fminf(fminf(fm[0], fm[1]), fm[2]));
+    if (!clip && __ballot(need && lo <= kEncodeKnee) == 0ull) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            Vp[k] = __builtin_rintf(encode255_pow(fp[k]));
+            Vm[k] = __builtin_rintf(encode255_pow(fm[k]));
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            Vp[k] = code8(fp[k]);
+            Vm[k] = code8(fm[k]);
+        }
+    }
 }
 
 // Integer form of a rule (Section 3): high = d > v_th, low = d <= lo_max where

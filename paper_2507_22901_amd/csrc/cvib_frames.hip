@@ -123,9 +123,9 @@ __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
     const int tid = threadIdx.x;
     const uint32_t lane = (uint32_t)tid & 63u;
     const int w = tid >> 6;
-    for (int k = tid; k < a.tab.tab_len; k += BLOCK) s_dyn[k] = a.tab.tab[k];
-    const double* tab = s_dyn;
-    uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len);
+    const Angles ang = load_angles(a.tab, s_dyn);
+    uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW);
+    const bool clip = a.rule.clip != 0u;
     const uint32_t mult = SYM ? 2u : 1u;
     const int64_t n = (int64_t)*a.n_dev;
     const int32_t per = a.nr * a.W;
@@ -139,52 +139,47 @@ __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
         const ColorConst cc = a.cc[c];
         int32_t i, j;
         divmod_small(tid, a.W, a.inv_W, i, j);
-        uint32_t cnt = 0, ng = 0, best = 0, steps = 0;
-        uint64_t pk = 0;
+        // wave totals (the same value in every lane) and the lane's best key
+        uint32_t cnt = 0, ng = 0, best = 0;
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
         const int32_t iters = (per + BLOCK - 1) / BLOCK;
         for (int32_t it = 0; it < iters; ++it) {
             const bool live = it * BLOCK + tid < per;
             double sn, co;
-            sincos_j(tab, a.tab.N, j, sn, co);
+            ang.get(j, sn, co);
             const double rr = (double)(i + 1);
             float fp[3], fm[3];
-            pair_linear(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
-            const bool both = live && in_unit_cube(fp) && in_unit_cube(fm);
-            const bool need = a.rule.clip ? live : both;
-            ng += both ? 1u : 0u;
-            if (__ballot(need) != 0ull) {
+            pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
+            const uint64_t live_m = __ballot(live);
+            const uint64_t both_m = __ballot(in_unit_cube(fp) && in_unit_cube(fm)) & live_m;
+            const uint64_t need_m = clip ? live_m : both_m;
+            ng += (uint32_t)__builtin_popcountll(both_m);
+            if (need_m != 0ull) {
                 float Vp[3], Vm[3];
+                codes_w(fp, fm, (need_m >> lane) & 1ull, clip, Vp, Vm);
+                const PatMasks pm = pattern_masks(Vp, Vm, a.rule);
+                const uint64_t surv_m = accepted_lanes(pm, a.rule.mask) & need_m;
+                if (surv_m != 0ull) {
+                    cnt += (uint32_t)__builtin_popcountll(surv_m);
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    Vp[k] = code8(fp[k]);
-                    Vm[k] = code8(fm[k]);
+                    for (uint32_t p = 1; p <= 7; ++p)
+                        if ((a.rule.mask >> (p - 1u)) & 1u)
+                            pat[p - 1] += (uint32_t)__builtin_popcountll(pattern_lanes(pm, p) & need_m);
+                    if ((surv_m >> lane) & 1ull) {
+                        const uint32_t key = best_key(i, j);
+                        best = max(best, key);
+                        atomicMax(&s_pb[pattern_of(Vp, Vm, a.rule) - 1u], key);
+                        if (RAYS) atomicMax(&s_ray[j], (uint32_t)(i + 1));
+                    }
                 }
-                const uint32_t p = pattern_of(Vp, Vm, a.rule);
-                if (need && accepts(a.rule, p)) {
-                    const uint32_t key = best_key(i, j);
-                    ++cnt;
-                    pk += 1ull << (8u * ((p - 1u) & 7u));
-                    best = max(best, key);
-                    atomicMax(&s_pb[p - 1u], key);
-                    if (RAYS) atomicMax(&s_ray[j], (uint32_t)(i + 1));
-                }
-            }
-            if (++steps == 255) {
-#pragma unroll
-                for (int q = 0; q < 7; ++q) pat[q] += (uint32_t)(pk >> (8 * q)) & 0xFFu;
-                pk = 0;
-                steps = 0;
             }
             j += a.sj;
             i += a.si;
             if (j >= a.W) { j -= a.W; ++i; }
         }
+        uint32_t v[10] = {mult * cnt, mult * ng, wave_max_u32(best)};
 #pragma unroll
-        for (int q = 0; q < 7; ++q) pat[q] += (uint32_t)(pk >> (8 * q)) & 0xFFu;
-        uint32_t v[10] = {mult * wave_sum_u32(cnt), mult * wave_sum_u32(ng), wave_max_u32(best)};
-#pragma unroll
-        for (int q = 0; q < 7; ++q) v[3 + q] = mult * wave_sum_u32(pat[q]);
+        for (int q = 0; q < 7; ++q) v[3 + q] = mult * pat[q];
         if (lane == 0) {
 #pragma unroll
             for (int q = 0; q < 10; ++q) s_red[w][q] = v[q];
@@ -208,7 +203,7 @@ __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
             if (key) {
                 const int32_t bi = (int32_t)(key >> 16), bj = (int32_t)(0xFFFFu - (key & 0xFFFFu));
                 double sn, co;
-                sincos_j(tab, a.tab.N, bj, sn, co);
+                ang.get(bj, sn, co);
                 const double rr = (double)(bi + 1);
                 PairEval e;
                 eval_pair(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, e);
@@ -330,8 +325,7 @@ __global__ __launch_bounds__(256) void k_propose_verify(ProposeArgs a) {
     extern __shared__ double s_tab[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    for (int k = tid; k < a.tab.tab_len; k += 256) s_tab[k] = a.tab.tab[k];
-    __syncthreads();
+    const Angles ang = load_angles(a.tab, s_tab);
     const int64_t n = (int64_t)*a.n_dev;
     const int64_t GW = (int64_t)gridDim.x * 4;
     for (int64_t c = (int64_t)blockIdx.x * 4 + (tid >> 6); c < n; c += GW) {
@@ -370,10 +364,10 @@ __global__ __launch_bounds__(256) void k_propose_verify(ProposeArgs a) {
                     const int32_t j = j_lo + (u < ncand ? q : 0);
                     const bool live = u < ncand && i >= 0 && i < a.nr;
                     double sn, co;
-                    sincos_j(s_tab, a.tab.N, j, sn, co);
+                    ang.get(j, sn, co);
                     const double rr = (double)(i + 1);
                     float fp[3], fm[3];
-                    pair_linear(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
+                    pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
                     const bool both = live && in_unit_cube(fp) && in_unit_cube(fm);
                     const bool need = a.rule.clip ? live : both;
                     bool ok = false;
@@ -395,7 +389,7 @@ __global__ __launch_bounds__(256) void k_propose_verify(ProposeArgs a) {
             if (best) {
                 const int32_t bi = (int32_t)(best >> 16), bj = (int32_t)(0xFFFFu - (best & 0xFFFFu));
                 double sn, co;
-                sincos_j(s_tab, a.tab.N, bj, sn, co);
+                ang.get(bj, sn, co);
                 const double rr = (double)(bi + 1);
                 PairEval e;
                 eval_pair(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, e);
@@ -497,7 +491,7 @@ unsigned grid_for(int64_t items, int per_block, unsigned cap) {
 template <bool SYM, bool RAYS>
 int launch_resolve_t(cv_context* ctx, const ResolveArgs& a, hipStream_t s) {
     auto k = k_colour_resolve<SYM, RAYS>;
-    const size_t lds = (size_t)a.tab.tab_len * 8 + (RAYS ? (size_t)a.W * 4 : 0);
+    const size_t lds = angle_lds_bytes(a.tab) + (RAYS ? (size_t)a.W * 4 : 0);
     int lds_max = 0;
     CV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
     if (lds + 256 > (size_t)lds_max)
@@ -555,6 +549,8 @@ ResolveArgs resolve_args(cv_context* ctx, const GridDev& gd, const RuleDev& rd, 
     a.tab.tab = (const double*)ctx->table.ptr;
     a.tab.tab_len = gd.tab_len;
     a.tab.N = gd.N;
+    a.tab.dW = direct_rays(gd.ntheta, gd.N, gd.tab_len, (size_t)gd.ntheta * 4);
+    a.tab._pad = 0;
     a.g = geom_constants();
     a.rule = rd;
     a.ra = gd.ra;
@@ -707,6 +703,8 @@ int enqueue_surrogate(cv_context* ctx, const SurrogateCall& c, const uint8_t* rg
     p.tab.tab = (const double*)ctx->table.ptr;
     p.tab.tab_len = c.gd.tab_len;
     p.tab.N = c.gd.N;
+    p.tab.dW = direct_rays(c.gd.ntheta, c.gd.N, c.gd.tab_len, 0);
+    p.tab._pad = 0;
     p.g = geom_constants();
     p.rule = c.rd;
     p.ra = c.gd.ra;
@@ -722,9 +720,9 @@ int enqueue_surrogate(cv_context* ctx, const SurrogateCall& c, const uint8_t* rg
     if ((rc = ctx->mark(CV_TIME_VERIFY, 0, s)) != CV_OK) return rc;
     int lds_max = 0;
     CV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-    if ((size_t)c.gd.tab_len * 8 > (size_t)lds_max) return fail(CV_EINVAL, "angle table exceeds LDS");
+    if (angle_lds_bytes(p.tab) > (size_t)lds_max) return fail(CV_EINVAL, "angle table exceeds LDS");
     hipLaunchKernelGGL(k_propose_verify, dim3(grid_for(n, 4, 65536)), dim3(256),
-                       (size_t)c.gd.tab_len * 8, s, p);
+                       angle_lds_bytes(p.tab), s, p);
     CV_HIP(hipGetLastError());
     if ((rc = ctx->mark(CV_TIME_VERIFY, 1, s)) != CV_OK) return rc;
     // colours without a verified proposal, counted (and listed) in colour order

@@ -121,7 +121,28 @@ struct TabArgs {
     const double* tab;
     int32_t tab_len;  // doubles in the table
     int32_t N;        // angles per full turn
+    int32_t dW;       // rays 0..dW-1 get their own sin / cos entries in LDS (0 = none)
+    int32_t _pad;
 };
+
+// Rays given their own LDS entries at most (16 bytes each).
+constexpr int32_t kDirectRays = 3072;
+
+// Direct rays for a kernel over rays j < (ntheta, or N/2 when theta spans the
+// full turn) that keeps `extra` more bytes of dynamic LDS: all of them when
+// the tables fit in 56 KiB together, else none.
+inline int32_t direct_rays(int32_t ntheta, int32_t N, int32_t tab_len, size_t extra) {
+    const int32_t W = ntheta == N ? N / 2 : ntheta;
+    if (W > kDirectRays) return 0;
+    if (8 * (size_t)tab_len + 16 * (size_t)W + extra > 56 * 1024) return 0;
+    return W;
+}
+
+// Dynamic LDS of the angle tables: the folded table, then sin and cos of the
+// direct rays.
+__host__ __device__ inline size_t angle_lds_bytes(const TabArgs& t) {
+    return 8 * (size_t)t.tab_len + 16 * (size_t)t.dW;
+}
 
 // sin and cos of theta_j = 2 pi j / N (0 <= j < N) from the folded table.
 // The folds are exact integer steps, so ray j + N/2 reads the negated values
@@ -144,6 +165,82 @@ __device__ __forceinline__ void sincos_j(const double* tab, int32_t N, int32_t j
         s = back ? -a : a;
         c = back ? -b : b;
     }
+}
+
+// Angle lookup for the hot loops: two LDS reads for a direct ray, else the
+// folding of sincos_j.  Both give the same bits.
+struct Angles {
+    const double* fold;
+    const double* sn;
+    const double* cs;
+    int32_t N;
+    bool direct;
+    __device__ __forceinline__ void get(int32_t j, double& s, double& c) const {
+        if (direct) {
+            s = sn[j];
+            c = cs[j];
+        } else {
+            sincos_j(fold, N, j, s, c);
+        }
+    }
+};
+
+// Copy the folded table to LDS (s_dyn) and expand the direct rays from it.
+// Every thread of the block must call it; it ends with a barrier.
+__device__ inline Angles load_angles(const TabArgs& t, double* s_dyn) {
+    const int nt = (int)blockDim.x;
+    for (int k = (int)threadIdx.x; k < t.tab_len; k += nt) s_dyn[k] = t.tab[k];
+    __syncthreads();
+    Angles a;
+    a.fold = s_dyn;
+    a.sn = s_dyn + t.tab_len;
+    a.cs = a.sn + t.dW;
+    a.N = t.N;
+    a.direct = t.dW > 0;
+    if (a.direct) {
+        for (int k = (int)threadIdx.x; k < t.dW; k += nt) {
+            double sv, cv;
+            sincos_j(s_dyn, t.N, k, sv, cv);
+            s_dyn[t.tab_len + k] = sv;
+            s_dyn[t.tab_len + t.dW + k] = cv;
+        }
+        __syncthreads();
+    }
+    return a;
+}
+
+// Lane masks of the per-channel classification of a wave's candidates:
+// H[k] = change above v_th (high), L[k] = change at most lo_max (low).  A
+// lane carries pattern p = 4 R + 2 G + B exactly when, per channel, it is in
+// H (bit set) or L (bit clear); high and low never overlap (lo_max < v_th).
+struct PatMasks {
+    uint64_t H[3], L[3];
+};
+
+__device__ __forceinline__ PatMasks pattern_masks(const float Vp[3], const float Vm[3],
+                                                  const RuleDev& r) {
+    PatMasks m;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float d = fabsf(Vp[k] - Vm[k]);
+        m.H[k] = __ballot(d > r.v_th);
+        m.L[k] = __ballot(d <= r.lo_max);
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint64_t pattern_lanes(const PatMasks& m, uint32_t p) {
+    return ((p & 4u) ? m.H[0] : m.L[0]) & ((p & 2u) ? m.H[1] : m.L[1]) & ((p & 1u) ? m.H[2] : m.L[2]);
+}
+
+// Lanes whose pattern the rule accepts.
+__device__ __forceinline__ uint64_t accepted_lanes(const PatMasks& m, uint32_t mask) {
+    if ((mask & 0x7Fu) == 0x7Fu)
+        return (m.H[0] | m.L[0]) & (m.H[1] | m.L[1]) & (m.H[2] | m.L[2]) & (m.H[0] | m.H[1] | m.H[2]);
+    uint64_t s = 0;
+    for (uint32_t p = 1; p <= 7; ++p)
+        if ((mask >> (p - 1u)) & 1u) s |= pattern_lanes(m, p);
+    return s;
 }
 
 // Key of the maximum-amplitude pair: larger i wins, then smaller j.  0 = none.

@@ -139,7 +139,7 @@ __device__ __forceinline__ void candidate(const ColorConst& cc, const SearchArgs
                                           uint32_t& hi, bool& surv, bool& both, uint32_t& pat) {
     const double rr = (double)(i + 1);
     float fp[3], fm[3];
-    pair_linear(cc, a.g, (rr * a.ra) * s, (rr * a.rb) * co, fp, fm);
+    pair_linear_w(cc, a.g, (rr * a.ra) * s, (rr * a.rb) * co, fp, fm);
     const bool gp = in_unit_cube(fp), gm = in_unit_cube(fm);
     both = live && gp && gm;
     const bool need = a.rule.clip ? live : both;
@@ -147,12 +147,9 @@ __device__ __forceinline__ void candidate(const ColorConst& cc, const SearchArgs
     pat = 0;
     lo = hi = 0;
     if (EMIT_ALL || __ballot(need) != 0ull) {
+        // every emitted candidate carries its clamped codes: the full encode
         float Vp[3], Vm[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            Vp[k] = code8(fp[k]);
-            Vm[k] = code8(fm[k]);
-        }
+        codes_w(fp, fm, need, EMIT_ALL || a.rule.clip, Vp, Vm);
         const uint32_t p = pattern_of(Vp, Vm, a.rule);
         surv = need && accepts(a.rule, p);
         pat = (need || EMIT_ALL) && (a.rule.clip || (gp && gm)) ? p : 0u;
@@ -201,8 +198,7 @@ __global__ __launch_bounds__(256) void k_pair_pass(SearchArgs a) {
     const int tid = threadIdx.x;
     const uint32_t lane = (uint32_t)tid & 63u;
     const int w = tid >> 6;
-    for (int k = tid; k < a.tab.tab_len; k += 256) s_tab[k] = a.tab.tab[k];
-    __syncthreads();
+    const Angles ang = load_angles(a.tab, s_tab);
 
     const uint32_t mult = SYM ? 2u : 1u;
     const int64_t per = (int64_t)a.nr * a.W;
@@ -248,7 +244,7 @@ __global__ __launch_bounds__(256) void k_pair_pass(SearchArgs a) {
         for (int32_t it = 0; it < iters; ++it) {
             const bool live = (it << 6) + (int32_t)lane < len;
             double sn, co;
-            sincos_j(s_tab, a.tab.N, j, sn, co);
+            ang.get(j, sn, co);
             uint32_t lo, hi, pat;
             bool surv, both;
             candidate<EMIT_ALL>(cc, a, sn, co, i, live, lo, hi, surv, both, pat);
@@ -434,10 +430,10 @@ __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
     const int tid = threadIdx.x;
     const uint32_t lane = (uint32_t)tid & 63u;
     const int w = tid >> 6;
-    for (int k = tid; k < a.tab.tab_len; k += BLOCK) s_dyn[k] = a.tab.tab[k];
-    const double* tab = s_dyn;
-    uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len);
+    const Angles ang = load_angles(a.tab, s_dyn);
+    uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW);
     const uint32_t mult = SYM ? 2u : 1u;
+    const bool clip = a.rule.clip != 0u;
 
     for (;;) {
         if (tid == 0) s_tick = (int64_t)atomicAdd((unsigned long long*)&a.misc[0], 1ull);
@@ -464,46 +460,46 @@ __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
             divmod_small(jb + tid, a.W, a.inv_W, di, j);
             i += di;
         }
+        // wave totals (the same value in every lane) and the lane's best key
         uint32_t cnt = 0, ng = 0, best = 0;
-        uint64_t pk = 0;          // 8-bit pattern counters, flushed every 255 steps
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
-        int32_t steps = 0;
         const int32_t iters = (len + BLOCK - 1) / BLOCK;
         for (int32_t it = 0; it < iters; ++it) {
             const bool live = it * BLOCK + tid < len;
             double sn, co;
-            sincos_j(tab, a.tab.N, j, sn, co);
+            ang.get(j, sn, co);
             const double rr = (double)(i + 1);
             float fp[3], fm[3];
-            pair_linear(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
-            const bool both = live && in_unit_cube(fp) && in_unit_cube(fm);
-            const bool need = a.rule.clip ? live : both;
-            ng += both ? 1u : 0u;
-            bool surv = false;
-            if (__ballot(need) != 0ull) {
+            pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
+            const uint64_t live_m = __ballot(live);
+            const uint64_t both_m = __ballot(in_unit_cube(fp) && in_unit_cube(fm)) & live_m;
+            const uint64_t need_m = clip ? live_m : both_m;
+            ng += (uint32_t)__builtin_popcountll(both_m);
+            uint64_t surv_m = 0;
+            if (need_m != 0ull) {
                 float Vp[3], Vm[3];
+                codes_w(fp, fm, (need_m >> lane) & 1ull, clip, Vp, Vm);
+                const PatMasks pm = pattern_masks(Vp, Vm, a.rule);
+                surv_m = accepted_lanes(pm, a.rule.mask) & need_m;
+                if (surv_m != 0ull) {
+                    cnt += (uint32_t)__builtin_popcountll(surv_m);
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    Vp[k] = code8(fp[k]);
-                    Vm[k] = code8(fm[k]);
-                }
-                const uint32_t p = pattern_of(Vp, Vm, a.rule);
-                surv = need && accepts(a.rule, p);
-                if (surv) {
-                    ++cnt;
-                    pk += 1ull << (8u * ((p - 1u) & 7u));
-                    best = max(best, best_key(i, j));
-                    if constexpr (TABLE) atomicMax(&s_ray[j], (uint32_t)(i + 1));
+                    for (uint32_t p = 1; p <= 7; ++p)
+                        if ((a.rule.mask >> (p - 1u)) & 1u)
+                            pat[p - 1] += (uint32_t)__builtin_popcountll(pattern_lanes(pm, p) & need_m);
+                    if ((surv_m >> lane) & 1ull) {
+                        best = max(best, best_key(i, j));
+                        if constexpr (TABLE) atomicMax(&s_ray[j], (uint32_t)(i + 1));
+                    }
                 }
             }
             if constexpr (SEG) {
                 // survivors per search segment: split this pass's ballot by
                 // segment (a pass of 64 evaluations touches few segments)
-                const uint64_t sb = __ballot(surv);
-                if (sb) {
+                if (surv_m != 0ull) {
                     const int32_t e = begin + it * BLOCK + tid;
                     const int32_t sl = (SYM ? i : e / a.seg_len) - seg0;
-                    uint64_t rem = sb;
+                    uint64_t rem = surv_m;
                     while (rem) {
                         const int32_t first = __builtin_ctzll(rem);
                         const int32_t sid = __shfl(sl, first, 64);
@@ -513,23 +509,15 @@ __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
                     }
                 }
             }
-            if (++steps == 255) {
-#pragma unroll
-                for (int q = 0; q < 7; ++q) pat[q] += (uint32_t)(pk >> (8 * q)) & 0xFFu;
-                pk = 0;
-                steps = 0;
-            }
             j += a.sj;
             i += a.si;
             if (j >= a.W) { j -= a.W; ++i; }
         }
-#pragma unroll
-        for (int q = 0; q < 7; ++q) pat[q] += (uint32_t)(pk >> (8 * q)) & 0xFFu;
 
         // block reduction: count, n_gamut, best, 7 patterns
-        uint32_t v[10] = {mult * wave_sum_u32(cnt), mult * wave_sum_u32(ng), wave_max_u32(best)};
+        uint32_t v[10] = {mult * cnt, mult * ng, wave_max_u32(best)};
 #pragma unroll
-        for (int q = 0; q < 7; ++q) v[3 + q] = mult * wave_sum_u32(pat[q]);
+        for (int q = 0; q < 7; ++q) v[3 + q] = mult * pat[q];
         if (lane == 0) {
 #pragma unroll
             for (int q = 0; q < 10; ++q) s_red[w][q] = v[q];
@@ -654,6 +642,9 @@ int prepare(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd, h
     tab.tab = (const double*)ctx->table.ptr;
     tab.tab_len = gd.tab_len;
     tab.N = gd.N;
+    // room for the per-ray maxima of the angle-bin table as well
+    tab.dW = direct_rays(gd.ntheta, gd.N, gd.tab_len, (size_t)gd.ntheta * 4);
+    tab._pad = 0;
     return CV_OK;
 }
 
@@ -674,7 +665,7 @@ constexpr int kSegLen = 512;
 template <bool EMIT, bool SUMM, bool SYM, bool WRITE>
 int launch_pass_t(cv_context* ctx, const SearchArgs& a, hipStream_t s) {
     auto k = k_pair_pass<EMIT, SUMM, SYM, WRITE>;
-    const size_t lds = (size_t)a.tab.tab_len * sizeof(double);
+    const size_t lds = angle_lds_bytes(a.tab);
     unsigned grid;
     const int64_t blocks_needed = (a.nsegs + 3) / 4;
     int rc = persistent_grid(ctx, k, kSearchBlock, lds, blocks_needed, grid);
@@ -708,8 +699,7 @@ constexpr int kReduceBlock = 256;
 template <bool TABLE, bool DIRECT, bool SYM, bool SEG>
 int launch_reduce_t(cv_context* ctx, const ReduceArgs& a, hipStream_t s) {
     auto k = k_pair_reduce<kReduceBlock, TABLE, DIRECT, SYM, SEG>;
-    const size_t lds = (size_t)a.tab.tab_len * sizeof(double) +
-                       (TABLE ? (size_t)a.W * sizeof(uint32_t) : 0);
+    const size_t lds = angle_lds_bytes(a.tab) + (TABLE ? (size_t)a.W * sizeof(uint32_t) : 0);
     unsigned grid;
     int rc = persistent_grid(ctx, k, kReduceBlock, lds, a.ntiles, grid);
     if (rc != CV_OK) return rc;
