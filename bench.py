@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--epochs", type=float, default=4.0, help="surrogate training epochs")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="only copy 256 MiB on the device three times (the known-size kernel "
+                         "that scales FETCH_SIZE / WRITE_SIZE counters to bytes)")
     ap.add_argument("--only", choices=("all", "nine", "frames", "cube", "surrogate"), default="all",
                     help="run one workload only (the JSON line then carries just that part)")
     return ap.parse_args()
@@ -265,6 +268,15 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_reference:
+        a = torch.ones(64 << 20, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copied_bytes_per_copy": 4 * a.numel(), "copies": 3}))
+        return
 
     import paper_2507_22901_amd as cv
     import workloads as W

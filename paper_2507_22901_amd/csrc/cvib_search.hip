@@ -133,6 +133,10 @@ __device__ __forceinline__ void flush_summary(SumAcc* acc, int64_t col, uint32_t
 // the wave has both colours in gamut, or every candidate is to be emitted)
 // the FP32 transfer, rounding and the predicate.  Returns the packed record
 // bytes and the decision.
+// Threads per block of the search kernels: eight waves share one copy of the
+// angle tables in LDS.
+constexpr int kPassBlock = 512;
+
 template <bool EMIT_ALL>
 __device__ __forceinline__ void candidate(const ColorConst& cc, const SearchArgs& a, double s,
                                           double co, int32_t i, bool live, uint32_t& lo,
@@ -192,8 +196,8 @@ __device__ __forceinline__ void candidate(const ColorConst& cc, const SearchArgs
 //               writes its survivors at offset + (survivors before it in the
 //               segment), found with a ballot and the lane rank.
 template <bool EMIT_ALL, bool SUMM, bool SYM, bool WRITE>
-__global__ __launch_bounds__(256) void k_pair_pass(SearchArgs a) {
-    constexpr int NW = 256 / 64;
+__global__ __launch_bounds__(kPassBlock) void k_pair_pass(SearchArgs a) {
+    constexpr int NW = kPassBlock / 64;
     extern __shared__ double s_tab[];
     const int tid = threadIdx.x;
     const uint32_t lane = (uint32_t)tid & 63u;
@@ -396,7 +400,8 @@ struct ReduceArgs {
     int32_t nr, ntheta;
     int32_t W;                // evaluations per row (ntheta, or N/2 in half-turn mode)
     float inv_W;
-    int32_t si, sj;
+    int32_t si, sj;           // a step of one block = si rows + sj rays
+    int32_t block;            // threads per block that si, sj were made for
     int32_t chunk;            // evaluations per tile (multiple of the block size)
     int32_t tiles_per_colour;
     int32_t bin_num, bin_den; // bin = (j * bin_num) / bin_den = floor(36 j / N)
@@ -659,7 +664,7 @@ int persistent_grid(cv_context* ctx, Kern k, int block, size_t lds, int64_t ntil
     return CV_OK;
 }
 
-constexpr int kSearchBlock = 256;
+constexpr int kSearchBlock = kPassBlock;
 constexpr int kSegLen = 512;
 
 template <bool EMIT, bool SUMM, bool SYM, bool WRITE>
@@ -667,7 +672,7 @@ int launch_pass_t(cv_context* ctx, const SearchArgs& a, hipStream_t s) {
     auto k = k_pair_pass<EMIT, SUMM, SYM, WRITE>;
     const size_t lds = angle_lds_bytes(a.tab);
     unsigned grid;
-    const int64_t blocks_needed = (a.nsegs + 3) / 4;
+    const int64_t blocks_needed = (a.nsegs + kPassBlock / 64 - 1) / (kPassBlock / 64);
     int rc = persistent_grid(ctx, k, kSearchBlock, lds, blocks_needed, grid);
     if (rc != CV_OK) return rc;
     hipLaunchKernelGGL(k, dim3(grid), dim3(kSearchBlock), lds, s, a);
@@ -694,16 +699,23 @@ int launch_pass(cv_context* ctx, const SearchArgs& a, bool emit, bool summ, bool
     }
 }
 
-constexpr int kReduceBlock = 256;
+// Threads per block of the reduce kernel: a tile that is one whole colour
+// (direct mode, usually small) keeps 4 waves so that more tiles run per CU;
+// large chunks take 8 waves to share one copy of the angle tables.
+constexpr int kReduceBlock = 512;
+constexpr int kReduceBlockDirect = 256;
+constexpr int reduce_block(bool direct) { return direct ? kReduceBlockDirect : kReduceBlock; }
 
 template <bool TABLE, bool DIRECT, bool SYM, bool SEG>
 int launch_reduce_t(cv_context* ctx, const ReduceArgs& a, hipStream_t s) {
-    auto k = k_pair_reduce<kReduceBlock, TABLE, DIRECT, SYM, SEG>;
+    constexpr int B = reduce_block(DIRECT);
+    if (a.block != B) return fail(CV_ESTATE, "internal: reduce block size");
+    auto k = k_pair_reduce<B, TABLE, DIRECT, SYM, SEG>;
     const size_t lds = angle_lds_bytes(a.tab) + (TABLE ? (size_t)a.W * sizeof(uint32_t) : 0);
     unsigned grid;
-    int rc = persistent_grid(ctx, k, kReduceBlock, lds, a.ntiles, grid);
+    int rc = persistent_grid(ctx, k, B, lds, a.ntiles, grid);
     if (rc != CV_OK) return rc;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(kReduceBlock), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(B), lds, s, a);
     CV_HIP(hipGetLastError());
     return CV_OK;
 }
@@ -776,8 +788,10 @@ ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, c
     a.ntheta = gd.ntheta;
     a.W = W;
     a.inv_W = 1.0f / (float)W;
-    a.si = kReduceBlock / W;
-    a.sj = kReduceBlock % W;
+    const int B = reduce_block(pl.direct);
+    a.si = B / W;
+    a.sj = B % W;
+    a.block = B;
     a.chunk = (int32_t)pl.chunk;
     a.tiles_per_colour = pl.tpc;
     a.bin_num = 36;
