@@ -323,6 +323,18 @@ int cv_mlp_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, voi
  * the gradients of the last backward pass. */
 int cv_adam_step(cv_mlp* m, float lr, float beta1, float beta2, float eps, int64_t t, void* stream);
 
+/* A run of training steps in one call: rows ids[0..n) (colour ids, already
+ * shuffled; device int32) are taken batch by batch from the whole-cube table
+ * (as cv_mlp_table_batch), and each batch does forward, loss (huber_delta),
+ * backward and an Adam step (beta 0.9, 0.999; eps 1e-8) whose learning rate
+ * decays by a cosine from lr_max at step 0 to lr_min at step total_steps - 1
+ * (steps counted from step0 across calls; Adam's t = step + 1).  The last
+ * batch may be short.  loss_log (device float [ceil(n / batch)], nullable)
+ * receives each step's loss.  Asynchronous. */
+int cv_mlp_train_steps(cv_mlp* m, const int32_t* ids, int64_t n, const cv_table_row* table, double dr,
+                       int64_t batch, float huber_delta, float lr_max, float lr_min, int64_t step0,
+                       int64_t total_steps, float* loss_log, void* stream);
+
 /* Training rows from a whole-cube table (cv_table_row [2^24], indexed by
  * colour id R<<16 | G<<8 | B, made on a grid of radius step dr): for each of
  * the B colour ids, x = RGB / 255 - 1/2, t_r[k] = bin_ridx[k] * dr / 50,

@@ -67,7 +67,8 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_pair_search", "cv_pair_reduce", "cv_frames_resolve", "cv_context_set_timing",
            "cv_context_kernel_time", "cv_mlp_create", "cv_mlp_destroy", "cv_mlp_num_params",
            "cv_mlp_set_params", "cv_mlp_get_params", "cv_mlp_forward", "cv_mlp_loss",
-           "cv_mlp_backward", "cv_adam_step", "cv_mlp_table_batch", "cv_mlp_save", "cv_mlp_load",
+           "cv_mlp_backward", "cv_adam_step", "cv_mlp_train_steps", "cv_mlp_table_batch", "cv_mlp_save",
+           "cv_mlp_load",
            "cv_surrogate_infer", "cv_frames_surrogate")
 CV_NO_FALLBACK = 0x4
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
@@ -110,6 +111,8 @@ def lib() -> C.CDLL:
         L.cv_mlp_backward.argtypes = [P, P, P, I64, P]
         L.cv_adam_step.argtypes = [P, C.c_float, C.c_float, C.c_float, C.c_float, I64, P]
         L.cv_mlp_table_batch.argtypes = [P, P, P, I64, C.c_double, P, P, P, P]
+        L.cv_mlp_train_steps.argtypes = [P, P, I64, P, C.c_double, I64, C.c_float, C.c_float,
+                                         C.c_float, I64, I64, P, P]
         L.cv_mlp_save.argtypes = [P, C.c_char_p]
         L.cv_mlp_load.argtypes = [P, C.c_char_p]
         L.cv_surrogate_infer.argtypes = [P, P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule),
@@ -456,6 +459,21 @@ class MLP:
         _check(lib().cv_mlp_table_batch(self.handle, _dptr(ids.contiguous()), _dptr(table), B,
                                         float(dr), _dptr(x), _dptr(tr), _dptr(tf), _stream()))
         return x, tr, tf
+
+    def train_steps(self, ids: torch.Tensor, table: torch.Tensor, dr: float, batch: int,
+                    delta: float, lr_max: float, lr_min: float, step0: int, total_steps: int,
+                    log: bool = True):
+        """Steps over ids (int32, shuffled) in batches; returns the per-step
+        losses (float32 tensor on the GPU) when log is set."""
+        if table.shape[0] != 1 << 24 or ids.dtype != torch.int32 or not ids.is_cuda:
+            raise ValueError("table must hold all 2^24 rows and ids must be int32 on the GPU")
+        n = ids.shape[0]
+        steps = -(-n // batch)
+        losses = torch.empty(steps, dtype=torch.float32, device=self.device) if log else None
+        _check(lib().cv_mlp_train_steps(self.handle, _dptr(ids.contiguous()), n, _dptr(table), float(dr),
+                                        int(batch), float(delta), float(lr_max), float(lr_min),
+                                        int(step0), int(total_steps), _dptr(losses), _stream()))
+        return losses
 
     def save(self, path: str):
         _check(lib().cv_mlp_save(self.handle, os.fsencode(path)))

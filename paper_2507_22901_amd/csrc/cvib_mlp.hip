@@ -179,22 +179,37 @@ __global__ void k_input_layer(const void* __restrict__ xin, int64_t B, int32_t d
     }
 }
 
-// Input-layer gradients: partial sums over one split of the batch, per output
-// unit o: [z][o][c] = sum_s G1[s][o] x_c (c < d0) and [z][o][d0] = sum_s G1[s][o].
-__global__ void k_input_grad(const bf16* __restrict__ G1, int64_t ldg, const float* __restrict__ x,
-                             int64_t B, int32_t d0, int32_t d1, float* __restrict__ part) {
-    const int32_t o = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (o >= d1) return;
-    const int64_t s0 = (int64_t)blockIdx.y * kSplitRows, s1 = min(B, s0 + kSplitRows);
+// Column reductions for the bias gradients and the input layer's weight
+// gradients.  Block (x, y) covers columns 64x .. 64x+63 and rows
+// kColRows y .. + kColRows-1: thread (c, g) sums every fourth row of the tile
+// for column c, the four row groups are added in LDS in a fixed order, and
+// part[y][o][k] receives, for column o, sum_s G[s][o] x[s][k] (k < d0) and
+// sum_s G[s][o] (k = d0).  With d0 = 0 only the column sums are formed.
+constexpr int kColRows = 256;
+
+__global__ __launch_bounds__(256) void k_colgrad(const bf16* __restrict__ G, int64_t ldg,
+                                                 const float* __restrict__ x, int32_t d0, int64_t B,
+                                                 int32_t ncols, float* __restrict__ part) {
+    __shared__ float s_acc[4][64][kMaxIn + 1];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int32_t o = (int32_t)blockIdx.x * 64 + c;
+    const int64_t s0 = (int64_t)blockIdx.y * kColRows, s1 = min(B, s0 + kColRows);
     float acc[kMaxIn + 1] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int64_t s = s0; s < s1; ++s) {
-        const float g = (float)G1[s * ldg + o];
-        for (int32_t c = 0; c < d0; ++c) acc[c] = fmaf(g, x[s * d0 + c], acc[c]);
-        acc[kMaxIn] += g;
+    if (o < ncols) {
+        for (int64_t sr = s0 + g; sr < s1; sr += 4) {
+            const float v = (float)G[sr * ldg + o];
+            for (int32_t k = 0; k < d0; ++k) acc[k] = fmaf(v, x[sr * d0 + k], acc[k]);
+            acc[kMaxIn] += v;
+        }
     }
-    float* dst = part + ((int64_t)blockIdx.y * d1 + o) * (d0 + 1);
-    for (int32_t c = 0; c < d0; ++c) dst[c] = acc[c];
-    dst[d0] = acc[kMaxIn];
+    for (int k = 0; k <= kMaxIn; ++k) s_acc[g][c][k] = acc[k];
+    __syncthreads();
+    if (g == 0 && o < ncols) {
+        float* dst = part + ((int64_t)blockIdx.y * ncols + o) * (d0 + 1);
+        for (int32_t k = 0; k < d0; ++k)
+            dst[k] = ((s_acc[0][c][k] + s_acc[1][c][k]) + s_acc[2][c][k]) + s_acc[3][c][k];
+        dst[d0] = ((s_acc[0][c][kMaxIn] + s_acc[1][c][kMaxIn]) + s_acc[2][c][kMaxIn]) + s_acc[3][c][kMaxIn];
+    }
 }
 
 __global__ void k_input_grad_sum(const float* __restrict__ part, int32_t splits, int32_t d0,
@@ -207,17 +222,6 @@ __global__ void k_input_grad_sum(const float* __restrict__ part, int32_t splits,
     const int32_t o = t / per, c = t - o * per;
     if (c < d0) gW0[o * d0 + c] = acc;
     else gb0[o] = acc;
-}
-
-// Column sums of G over one split of the batch (bias gradients).
-__global__ void k_colsum(const bf16* __restrict__ G, int64_t ldg, int64_t B, int32_t ncols,
-                         float* __restrict__ part) {
-    const int32_t c = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (c >= ncols) return;
-    const int64_t s0 = (int64_t)blockIdx.y * kSplitRows, s1 = min(B, s0 + kSplitRows);
-    float acc = 0.0f;
-    for (int64_t s = s0; s < s1; ++s) acc += (float)G[s * ldg + c];
-    part[(int64_t)blockIdx.y * ncols + c] = acc;
 }
 
 // Fixed-order sum of split partials [z][rows][ldp] into out[r][c] (r < rows, c < cols).
@@ -365,6 +369,14 @@ struct cv_mlp {
     float* lpart = nullptr;             // loss partials
     int64_t lpart_n = 0;
     int64_t fwd_rows = -1;              // batch of the last kept forward
+    // training-step buffers (cv_mlp_train_steps)
+    int64_t tcap = 0;
+    float* tx = nullptr;    // [tcap][3]
+    float* ttr = nullptr;   // [tcap][36]
+    float* ttf = nullptr;   // [tcap]
+    float* tout = nullptr;  // [tcap][37]
+    float* tgout = nullptr; // [tcap][37]
+    float* tloss = nullptr; // [1]: loss of a step that is not logged
 };
 
 namespace cvib {
@@ -477,11 +489,13 @@ int run_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, hipStr
     int rc;
     const int32_t L = m->L;
     const int32_t splits = (int32_t)((B + kSplitRows - 1) / kSplitRows);
-    // partials: the widest weight gradient, or the input layer's, or a column sum
+    const int32_t csplits = (int32_t)((B + kColRows - 1) / kColRows);  // column reductions
+    // partials: the widest weight gradient, or a column reduction
     size_t need = 0;
     for (int l = 0; l < L; ++l) {
-        const size_t w = (size_t)splits * m->dpad[l + 1] * (l == 0 ? (m->dims[0] + 1) : m->dims[l]);
-        need = std::max(need, w);
+        const size_t w = (size_t)splits * m->dpad[l + 1] * (l == 0 ? 0 : m->dims[l]);
+        const size_t c = (size_t)csplits * m->dpad[l + 1] * (l == 0 ? (m->dims[0] + 1) : 1);
+        need = std::max(need, std::max(w, c));
     }
     if ((rc = ensure_part(m, need * sizeof(float))) != CV_OK) return rc;
     bf16* Gc = m->g[0];  // gradient w.r.t. the pre-activations of layer l's output
@@ -512,9 +526,9 @@ int run_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, hipStr
                            m->grads + m->woff[l]);
         CV_HIP(hipGetLastError());
         // bias gradient; its partials follow the weight partials' use (same stream)
-        hipLaunchKernelGGL(k_colsum, dim3((unsigned)((dout + 255) / 256), (unsigned)splits), dim3(256),
-                           0, s, Gc, (int64_t)ldg, B, dout, m->part);
-        hipLaunchKernelGGL(k_sum_splits, dim3(blocks(dout, 256)), dim3(256), 0, s, m->part, splits,
+        hipLaunchKernelGGL(k_colgrad, dim3((unsigned)((dout + 63) / 64), (unsigned)csplits), dim3(256), 0,
+                           s, Gc, (int64_t)ldg, (const float*)nullptr, 0, B, dout, m->part);
+        hipLaunchKernelGGL(k_sum_splits, dim3(blocks(dout, 256)), dim3(256), 0, s, m->part, csplits,
                            (int64_t)dout, 1, dout, (int64_t)dout, m->grads + m->boff[l]);
         CV_HIP(hipGetLastError());
         // input gradient through W_l and the ReLU of H_l
@@ -538,16 +552,59 @@ int run_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, hipStr
     }
     // input layer
     const int32_t d0 = m->dims[0], d1 = m->dims[1];
-    hipLaunchKernelGGL(k_input_grad, dim3((unsigned)((d1 + 255) / 256), (unsigned)splits), dim3(256), 0,
-                       s, Gc, (int64_t)ldg, x, B, d0, d1, m->part);
+    hipLaunchKernelGGL(k_colgrad, dim3((unsigned)((d1 + 63) / 64), (unsigned)csplits), dim3(256), 0, s,
+                       Gc, (int64_t)ldg, x, d0, B, d1, m->part);
     hipLaunchKernelGGL(k_input_grad_sum, dim3(blocks((int64_t)d1 * (d0 + 1), 256)), dim3(256), 0, s,
-                       m->part, splits, d0, d1, m->grads + m->woff[0], m->grads + m->boff[0]);
+                       m->part, csplits, d0, d1, m->grads + m->woff[0], m->grads + m->boff[0]);
     CV_HIP(hipGetLastError());
     return CV_OK;
 }
 
+int run_loss(cv_mlp* m, const float* out, const float* tr, const float* tf, int64_t B, float delta,
+             float* loss, float* gout, hipStream_t s) {
+    const int64_t nb = (B + 255) / 256;
+    int rc;
+    size_t have = (size_t)m->lpart_n * sizeof(float);
+    if ((rc = grow((void**)&m->lpart, &have, (size_t)nb * sizeof(float))) != CV_OK) return rc;
+    m->lpart_n = (int64_t)(have / sizeof(float));
+    hipLaunchKernelGGL(k_loss, dim3((unsigned)nb), dim3(256), 0, s, out, tr, tf, B, m->dims[m->L], delta,
+                       gout, m->lpart);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, s, m->lpart, (int32_t)nb, B, loss);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
+int run_adam(cv_mlp* m, float lr, float b1, float b2, float eps, int64_t t, hipStream_t s) {
+    const float c1 = (float)(1.0 / (1.0 - pow((double)b1, (double)t)));
+    const float c2 = (float)(1.0 / (1.0 - pow((double)b2, (double)t)));
+    hipLaunchKernelGGL(k_adam, dim3(blocks(m->nparam, 256)), dim3(256), 0, s, m->params, m->grads,
+                       m->adam_m, m->adam_v, m->nparam, lr, b1, b2, eps, c1, c2);
+    CV_HIP(hipGetLastError());
+    return refresh_bf16(m, s);
+}
+
+int ensure_train(cv_mlp* m, int64_t B) {
+    if (B <= m->tcap) return CV_OK;
+    CV_HIP(hipDeviceSynchronize());
+    float** bufs[] = {&m->tx, &m->ttr, &m->ttf, &m->tout, &m->tgout};
+    for (float** b : bufs) {
+        if (*b) CV_HIP(hipFree(*b));
+        *b = nullptr;
+    }
+    m->tcap = 0;
+    CV_HIP(hipMalloc((void**)&m->tx, (size_t)B * 3 * sizeof(float)));
+    CV_HIP(hipMalloc((void**)&m->ttr, (size_t)B * 36 * sizeof(float)));
+    CV_HIP(hipMalloc((void**)&m->ttf, (size_t)B * sizeof(float)));
+    CV_HIP(hipMalloc((void**)&m->tout, (size_t)B * 37 * sizeof(float)));
+    CV_HIP(hipMalloc((void**)&m->tgout, (size_t)B * 37 * sizeof(float)));
+    if (!m->tloss) CV_HIP(hipMalloc((void**)&m->tloss, sizeof(float)));
+    m->tcap = B;
+    return CV_OK;
+}
+
 void free_mlp(cv_mlp* m) {
-    void* ps[] = {m->params, m->grads, m->adam_m, m->adam_v, m->g[0], m->g[1], m->part, m->lpart};
+    void* ps[] = {m->params, m->grads, m->adam_m, m->adam_v, m->g[0], m->g[1], m->part, m->lpart,
+                  m->tx, m->ttr, m->ttf, m->tout, m->tgout, m->tloss};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     for (int l = 0; l < kMaxLayers; ++l) {
@@ -698,17 +755,7 @@ int cv_mlp_loss(cv_mlp* m, const float* out, const float* t_r, const float* t_f,
     if (!out || !t_r || !t_f || !loss) return fail(CV_EINVAL, "null array");
     if (!(huber_delta > 0.0f)) return fail(CV_EINVAL, "huber_delta must be > 0");
     DeviceGuard dg(m->device);
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t nb = (B + 255) / 256;
-    int rc;
-    size_t have = (size_t)m->lpart_n * sizeof(float);
-    if ((rc = cvib::grow((void**)&m->lpart, &have, (size_t)nb * sizeof(float))) != CV_OK) return rc;
-    m->lpart_n = (int64_t)(have / sizeof(float));
-    hipLaunchKernelGGL(cvib::k_loss, dim3((unsigned)nb), dim3(256), 0, s, out, t_r, t_f, B,
-                       m->dims[m->L], huber_delta, gout, m->lpart);
-    hipLaunchKernelGGL(cvib::k_loss_total, dim3(1), dim3(64), 0, s, m->lpart, (int32_t)nb, B, loss);
-    CV_HIP(hipGetLastError());
-    return CV_OK;
+    return cvib::run_loss(m, out, t_r, t_f, B, huber_delta, loss, gout, (hipStream_t)stream);
     CV_GUARD_END
 }
 
@@ -730,13 +777,45 @@ int cv_adam_step(cv_mlp* m, float lr, float beta1, float beta2, float eps, int64
         !(eps > 0.0f) || t < 1)
         return fail(CV_EINVAL, "Adam needs lr >= 0, betas in [0, 1), eps > 0, step >= 1");
     DeviceGuard dg(m->device);
+    return cvib::run_adam(m, lr, beta1, beta2, eps, t, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
+int cv_mlp_train_steps(cv_mlp* m, const int32_t* ids, int64_t n, const cv_table_row* table, double dr,
+                       int64_t batch, float huber_delta, float lr_max, float lr_min, int64_t step0,
+                       int64_t total_steps, float* loss_log, void* stream) {
+    CV_GUARD_BEGIN
+    if (!m) return fail(CV_EINVAL, "network is NULL");
+    if (n < 1 || !ids || !table) return fail(CV_EINVAL, "no training rows");
+    if (batch < 1 || batch > ((int64_t)1 << 20)) return fail(CV_EINVAL, "batch must be in [1, 2^20]");
+    if (!(dr > 0.0) || !(huber_delta > 0.0f)) return fail(CV_EINVAL, "dr and huber_delta must be > 0");
+    if (!(lr_max >= 0.0f) || !(lr_min >= 0.0f)) return fail(CV_EINVAL, "learning rates must be >= 0");
+    if (step0 < 0 || total_steps < 1) return fail(CV_EINVAL, "step0 >= 0 and total_steps >= 1");
+    if (m->dims[0] != 3 || m->dims[m->L] != 37) return fail(CV_EINVAL, "network is not 3 -> ... -> 37");
+    DeviceGuard dg(m->device);
     hipStream_t s = (hipStream_t)stream;
-    const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)t)));
-    const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)t)));
-    hipLaunchKernelGGL(cvib::k_adam, dim3(cvib::blocks(m->nparam, 256)), dim3(256), 0, s, m->params,
-                       m->grads, m->adam_m, m->adam_v, m->nparam, lr, beta1, beta2, eps, c1, c2);
-    CV_HIP(hipGetLastError());
-    return cvib::refresh_bf16(m, s);
+    const int64_t B = std::min(batch, n);
+    int rc;
+    if ((rc = cvib::ensure_train(m, B)) != CV_OK) return rc;
+    if ((rc = cvib::ensure_rows(m, B)) != CV_OK) return rc;
+    const int64_t steps = (n + batch - 1) / batch;
+    for (int64_t k = 0; k < steps; ++k) {
+        const int64_t r0 = k * batch, nb = std::min(batch, n - r0);
+        hipLaunchKernelGGL(cvib::k_table_batch, dim3(cvib::blocks(nb, 256)), dim3(256), 0, s, ids + r0,
+                           table, nb, (float)(dr / 50.0), m->tx, m->ttr, m->ttf);
+        CV_HIP(hipGetLastError());
+        if ((rc = cvib::run_forward(m, m->tx, false, nb, m->tout, true, s)) != CV_OK) return rc;
+        float* lp = loss_log ? loss_log + k : m->tloss;
+        if ((rc = cvib::run_loss(m, m->tout, m->ttr, m->ttf, nb, huber_delta, lp, m->tgout, s)) != CV_OK)
+            return rc;
+        if ((rc = cvib::run_backward(m, m->tx, m->tgout, nb, s)) != CV_OK) return rc;
+        // cosine decay from lr_max to lr_min over total_steps
+        const int64_t t = step0 + k;
+        const double frac = total_steps > 1 ? (double)std::min(t, total_steps - 1) / (double)(total_steps - 1) : 0.0;
+        const float lr = (float)(lr_min + 0.5 * (lr_max - lr_min) * (1.0 + cos(M_PI * frac)));
+        if ((rc = cvib::run_adam(m, lr, 0.9f, 0.999f, 1e-8f, t + 1, s)) != CV_OK) return rc;
+    }
+    return CV_OK;
     CV_GUARD_END
 }
 

@@ -29,31 +29,28 @@ def train(mlp: MLP, table: torch.Tensor, train_ids: torch.Tensor, dr: float, epo
           seed: int = 0, log_every: int = 200, step0: int = 0):
     """Adam with cosine decay from lr to lr_min over the run; rows are the
     training colour ids (int32 on the GPU) shuffled per epoch by a Philox
-    stream keyed by `seed`.  Returns (steps, [(step, loss)], seconds)."""
+    stream keyed by `seed`; each epoch is one call of the library's training
+    loop.  Returns (steps, [(step, loss)], seconds)."""
     n = train_ids.shape[0]
     per_epoch = math.ceil(n / batch)
     total = max(1, int(round(epochs * per_epoch)))
     rng = np.random.Generator(np.random.Philox(key=seed))
     log = []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     step = 0
-    perm_ids = None
     while step < total:
-        k = step % per_epoch
-        if k == 0:
-            perm = torch.from_numpy(rng.permutation(n).astype(np.int64)).to(train_ids.device)
-            perm_ids = train_ids[perm]
-        ids = perm_ids[k * batch:(k + 1) * batch]
-        x, tr, tf = mlp.table_batch(ids, table, dr)
-        out = mlp.forward(x, keep=True)
-        loss, gout = mlp.loss(out, tr, tf, delta)
-        mlp.backward(x, gout)
-        frac = step / max(1, total - 1)
-        lr_t = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * frac))
-        mlp.adam_step(lr_t, step0 + step + 1)
-        if log_every and (step % log_every == 0 or step == total - 1):
-            log.append((step, float(loss.item())))
-        step += 1
+        take = min(per_epoch, total - step)
+        perm = torch.from_numpy(rng.permutation(n).astype(np.int64)).to(train_ids.device)
+        ids = train_ids[perm[:min(n, take * batch)]].contiguous()
+        losses = mlp.train_steps(ids, table, dr, batch, delta, lr, lr_min, step0 + step, total,
+                                 log=bool(log_every))
+        if log_every:
+            lv = losses.cpu().numpy()
+            for k in range(0, take, log_every):
+                log.append((step + k, float(lv[k])))
+            log.append((step + take - 1, float(lv[-1])))
+        step += take
     torch.cuda.synchronize()
     return total, log, time.perf_counter() - t0
 

@@ -211,3 +211,34 @@ def test_backward_needs_kept_forward(cv):
     m.forward(x)  # not kept
     with pytest.raises(cv.CvError):
         m.backward(x, g)
+
+
+def test_train_steps_equals_single_calls(cv):
+    """The library's training loop does what the single calls do: table batch,
+    kept forward, loss, backward, Adam with the cosine rate.  Losses agree bit
+    for bit; parameters within a few units in the last place, since the host's
+    cos in the rate schedule may round differently from Python's."""
+    import math
+    g = torch.Generator(device="cuda").manual_seed(3)
+    table = torch.randint(0, 256, (1 << 24, 40), dtype=torch.uint8, device="cuda", generator=g)
+    ids = torch.randint(0, 1 << 24, (5000,), dtype=torch.int32, device="cuda", generator=g)
+    a, flat = _net(cv, seed=21)
+    b = cv.MLP(DIMS)
+    b.set_params(flat)
+    batch, total, dr, delta, lr0, lr1 = 1024, 5, 0.25, 0.05, 2e-3, 2e-5
+    losses = a.train_steps(ids, table, dr, batch, delta, lr0, lr1, 0, total)
+    manual = []
+    for k in range(total):
+        x, tr, tf = b.table_batch(ids[k * batch:(k + 1) * batch], table, dr)
+        out = b.forward(x, keep=True)
+        loss, gout = b.loss(out, tr, tf, delta)
+        b.backward(x, gout)
+        # the loop's schedule: double arithmetic on the FP32 rates it was given
+        frac = k / (total - 1)
+        f0, f1 = float(np.float32(lr0)), float(np.float32(lr1))
+        lr = f1 + 0.5 * (f0 - f1) * (1.0 + math.cos(math.pi * frac))
+        b.adam_step(float(np.float32(lr)), k + 1)
+        manual.append(loss)
+    assert torch.equal(losses, torch.cat(manual))
+    pa, pb = a.params(), b.params()
+    assert torch.max(torch.abs(pa - pb)).item() <= 4 * np.finfo(np.float32).eps * torch.max(torch.abs(pb)).item()
