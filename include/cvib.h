@@ -253,6 +253,24 @@ int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, cons
  * of timed calls for one phase (host pointers) and clears that phase when
  * reset != 0.  Errors: CV_EINVAL (null ctx / outputs, bad phase), CV_EHIP.
  */
+/*
+ * Kernel choice for the per-colour resolve (cv_frames_resolve and the exact
+ * fallback of the surrogate calls): variant 0 gives one colour to a block of
+ * four waves, 1 one colour to each wave with four waves per block, 2 the
+ * same with eight waves per block.  All give identical results.  With
+ * autotuning on, the first cv_frames_resolve call of a grid shape (nr,
+ * ntheta, N, per-ray output or not) runs once eagerly, then times every
+ * variant that fits in LDS on up to 8192 of its colours and keeps the
+ * fastest for that shape in the context.  A forced variant (0..2) overrides
+ * the tuning; -1 returns to it.  cv_context_resolve_variant reports the
+ * variant a call of that shape would use and (tuned_host, nullable) whether it
+ * came from tuning.  Errors: CV_EINVAL.
+ */
+int cv_context_set_autotune(cv_context* ctx, int on);
+int cv_context_set_resolve_variant(cv_context* ctx, int variant);
+int cv_context_resolve_variant(cv_context* ctx, const cv_grid* grid, int rays, int* variant_host,
+                               int* tuned_host);
+
 #define CV_TIME_EVAL 0
 #define CV_TIME_WRITE 1
 #define CV_TIME_CALL 2

@@ -69,7 +69,8 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_mlp_set_params", "cv_mlp_get_params", "cv_mlp_forward", "cv_mlp_loss",
            "cv_mlp_backward", "cv_adam_step", "cv_mlp_train_steps", "cv_mlp_table_batch", "cv_mlp_save",
            "cv_mlp_load",
-           "cv_surrogate_infer", "cv_frames_surrogate")
+           "cv_surrogate_infer", "cv_frames_surrogate", "cv_context_set_autotune",
+           "cv_context_set_resolve_variant", "cv_context_resolve_variant")
 CV_NO_FALLBACK = 0x4
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
 CV_RESOLVED_SURROGATE, CV_RESOLVED_EXACT, CV_RESOLVED_NONE = 0, 1, 2
@@ -120,6 +121,10 @@ def lib() -> C.CDLL:
         L.cv_frames_surrogate.argtypes = [P, P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule),
                                           C.c_float, C.c_int32, P, I64, P, P, P, P, P, P, P, P,
                                           C.c_uint32, P]
+        L.cv_context_set_autotune.argtypes = [P, C.c_int]
+        L.cv_context_set_resolve_variant.argtypes = [P, C.c_int]
+        L.cv_context_resolve_variant.argtypes = [P, C.POINTER(cv_grid), C.c_int, C.POINTER(C.c_int),
+                                                 C.POINTER(C.c_int)]
         for name in EXPORTS:
             if name != "cv_last_error":
                 getattr(L, name).restype = C.c_int
@@ -182,6 +187,22 @@ class Context:
         _check(lib().cv_context_kernel_time(self.handle, int(phase), C.byref(ms), C.byref(n),
                                             int(reset)))
         return ms.value, n.value
+
+    def set_autotune(self, on: bool = True):
+        """Time the per-colour resolve variants on the first call of each grid shape."""
+        _check(lib().cv_context_set_autotune(self.handle, int(bool(on))))
+
+    def set_resolve_variant(self, variant: int = -1):
+        """Force a per-colour resolve variant (0, 1, 2) or return to tuning (-1)."""
+        _check(lib().cv_context_set_resolve_variant(self.handle, int(variant)))
+
+    def resolve_variant(self, grid: "Grid", rays: bool = False):
+        """(variant a call of this grid shape would use, whether it was tuned)."""
+        v, t = C.c_int(0), C.c_int(0)
+        g = grid.c()
+        _check(lib().cv_context_resolve_variant(self.handle, C.byref(g), int(bool(rays)), C.byref(v),
+                                                C.byref(t)))
+        return v.value, bool(t.value)
 
     def close(self):
         if self.handle:

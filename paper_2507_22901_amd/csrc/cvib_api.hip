@@ -390,6 +390,37 @@ int cv_frames_surrogate(cv_context* ctx, cv_mlp* mlp, const uint8_t* pixels, int
     CV_GUARD_END
 }
 
+int cv_context_set_autotune(cv_context* ctx, int on) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    ctx->autotune = on != 0;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_context_set_resolve_variant(cv_context* ctx, int variant) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    if (variant < -1 || variant >= cvib::kResolveVariants) return fail(CV_EINVAL, "unknown resolve variant");
+    ctx->resolve_forced = variant;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_context_resolve_variant(cv_context* ctx, const cv_grid* grid, int rays, int* variant_host,
+                               int* tuned_host) {
+    CV_GUARD_BEGIN
+    if (!ctx || !variant_host) return fail(CV_EINVAL, "null argument");
+    cvib::GridDev gd;
+    int rc;
+    if ((rc = cvib::make_grid(grid, &gd)) != CV_OK) return rc;
+    *variant_host = cvib::resolve_variant(ctx, gd, rays != 0);
+    if (tuned_host)
+        *tuned_host = ctx->resolve_forced < 0 && ctx->resolve_tuned.count(cvib::resolve_key(gd, rays != 0)) ? 1 : 0;
+    return CV_OK;
+    CV_GUARD_END
+}
+
 int cv_context_set_timing(cv_context* ctx, int on) {
     CV_GUARD_BEGIN
     if (!ctx) return fail(CV_EINVAL, "ctx is NULL");

@@ -107,13 +107,91 @@ struct ResolveArgs {
     double ra, rb;
     int32_t nr, ntheta, W;
     float inv_W;
-    int32_t si, sj;
+    int32_t si, sj;           // a step of 256 evaluations = si rows + sj rays
+    int32_t si64, sj64;       // a step of 64 evaluations
     const uint32_t* list;     // nullable: the k-th colour searched is list[k]
     cv_color_summary* summ;   // nullable
     cv_pattern_pair* pbest;   // nullable, [n][7]
     uint16_t* rays;           // nullable, [n][ntheta]
 };
 
+// All candidates of one colour, split over a group of g_size threads (a block
+// or one wave): thread g_tid takes evaluations g_tid, g_tid + g_size, ... in
+// row-major (i, j < W) order; a step of g_size evaluations is si rows + sj
+// rays.  Wave totals accumulate in cnt, ng and pat (the same value in every
+// lane), the lane's best key in best; survivors raise the pattern's best key
+// in s_pb and, with RAYS, the ray's largest radius in s_ray.
+template <bool RAYS>
+__device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angles& ang,
+                                               const ColorConst& cc, int32_t g_tid, int32_t g_size,
+                                               int32_t si, int32_t sj, uint32_t lane, uint32_t* s_pb,
+                                               uint32_t* s_ray, uint32_t& cnt, uint32_t& ng,
+                                               uint32_t& best, uint32_t pat[7]) {
+    const bool clip = a.rule.clip != 0u;
+    const int32_t per = a.nr * a.W;
+    int32_t i, j;
+    divmod_small(g_tid, a.W, a.inv_W, i, j);
+    const int32_t iters = (per + g_size - 1) / g_size;
+    for (int32_t it = 0; it < iters; ++it) {
+        const bool live = it * g_size + g_tid < per;
+        double sn, co;
+        ang.get(j, sn, co);
+        const double rr = (double)(i + 1);
+        float fp[3], fm[3];
+        pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
+        const uint64_t live_m = __ballot(live);
+        const uint64_t both_m = __ballot(in_unit_cube(fp) && in_unit_cube(fm)) & live_m;
+        const uint64_t need_m = clip ? live_m : both_m;
+        ng += (uint32_t)__builtin_popcountll(both_m);
+        if (need_m != 0ull) {
+            float Vp[3], Vm[3];
+            codes_w(fp, fm, (need_m >> lane) & 1ull, clip, Vp, Vm);
+            const PatMasks pm = pattern_masks(Vp, Vm, a.rule);
+            const uint64_t surv_m = accepted_lanes(pm, a.rule.mask) & need_m;
+            if (surv_m != 0ull) {
+                cnt += (uint32_t)__builtin_popcountll(surv_m);
+#pragma unroll
+                for (uint32_t p = 1; p <= 7; ++p)
+                    if ((a.rule.mask >> (p - 1u)) & 1u)
+                        pat[p - 1] += (uint32_t)__builtin_popcountll(pattern_lanes(pm, p) & need_m);
+                if ((surv_m >> lane) & 1ull) {
+                    const uint32_t key = best_key(i, j);
+                    best = max(best, key);
+                    atomicMax(&s_pb[pattern_of(Vp, Vm, a.rule) - 1u], key);
+                    if (RAYS) atomicMax(&s_ray[j], (uint32_t)(i + 1));
+                }
+            }
+        }
+        j += sj;
+        i += si;
+        if (j >= a.W) { j -= a.W; ++i; }
+    }
+}
+
+// The best pair of pattern q + 1 from its key (0 = none), codes evaluated again.
+__device__ __forceinline__ cv_pattern_pair pattern_pair(const ResolveArgs& a, const Angles& ang,
+                                                        const ColorConst& cc, uint32_t key, int q) {
+    cv_pattern_pair r = {};
+    if (key) {
+        const int32_t bi = (int32_t)(key >> 16), bj = (int32_t)(0xFFFFu - (key & 0xFFFFu));
+        double sn, co;
+        ang.get(bj, sn, co);
+        const double rr = (double)(bi + 1);
+        PairEval e;
+        eval_pair(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, e);
+        r.i = (uint16_t)bi;
+        r.j = (uint16_t)bj;
+        for (int k = 0; k < 3; ++k) {
+            r.plus[k] = (uint8_t)e.Vp[k];
+            r.minus[k] = (uint8_t)e.Vm[k];
+        }
+        r.pattern = (uint8_t)(q + 1);
+        r.flags = 1;
+    }
+    return r;
+}
+
+// One colour per block of four waves.
 template <bool SYM, bool RAYS>
 __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
     constexpr int BLOCK = 256, NW = BLOCK / 64;
@@ -125,58 +203,19 @@ __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
     const int w = tid >> 6;
     const Angles ang = load_angles(a.tab, s_dyn);
     uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW);
-    const bool clip = a.rule.clip != 0u;
     const uint32_t mult = SYM ? 2u : 1u;
     const int64_t n = (int64_t)*a.n_dev;
-    const int32_t per = a.nr * a.W;
 
     for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
         const int64_t c = a.list ? (int64_t)a.list[k] : k;
         if (RAYS)
-            for (int k = tid; k < a.W; k += BLOCK) s_ray[k] = 0;
+            for (int q = tid; q < a.W; q += BLOCK) s_ray[q] = 0;
         if (tid < 7) s_pb[tid] = 0;
         __syncthreads();
         const ColorConst cc = a.cc[c];
-        int32_t i, j;
-        divmod_small(tid, a.W, a.inv_W, i, j);
-        // wave totals (the same value in every lane) and the lane's best key
         uint32_t cnt = 0, ng = 0, best = 0;
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
-        const int32_t iters = (per + BLOCK - 1) / BLOCK;
-        for (int32_t it = 0; it < iters; ++it) {
-            const bool live = it * BLOCK + tid < per;
-            double sn, co;
-            ang.get(j, sn, co);
-            const double rr = (double)(i + 1);
-            float fp[3], fm[3];
-            pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
-            const uint64_t live_m = __ballot(live);
-            const uint64_t both_m = __ballot(in_unit_cube(fp) && in_unit_cube(fm)) & live_m;
-            const uint64_t need_m = clip ? live_m : both_m;
-            ng += (uint32_t)__builtin_popcountll(both_m);
-            if (need_m != 0ull) {
-                float Vp[3], Vm[3];
-                codes_w(fp, fm, (need_m >> lane) & 1ull, clip, Vp, Vm);
-                const PatMasks pm = pattern_masks(Vp, Vm, a.rule);
-                const uint64_t surv_m = accepted_lanes(pm, a.rule.mask) & need_m;
-                if (surv_m != 0ull) {
-                    cnt += (uint32_t)__builtin_popcountll(surv_m);
-#pragma unroll
-                    for (uint32_t p = 1; p <= 7; ++p)
-                        if ((a.rule.mask >> (p - 1u)) & 1u)
-                            pat[p - 1] += (uint32_t)__builtin_popcountll(pattern_lanes(pm, p) & need_m);
-                    if ((surv_m >> lane) & 1ull) {
-                        const uint32_t key = best_key(i, j);
-                        best = max(best, key);
-                        atomicMax(&s_pb[pattern_of(Vp, Vm, a.rule) - 1u], key);
-                        if (RAYS) atomicMax(&s_ray[j], (uint32_t)(i + 1));
-                    }
-                }
-            }
-            j += a.sj;
-            i += a.si;
-            if (j >= a.W) { j -= a.W; ++i; }
-        }
+        resolve_colour<RAYS>(a, ang, cc, tid, BLOCK, a.si, a.sj, lane, s_pb, s_ray, cnt, ng, best, pat);
         uint32_t v[10] = {mult * cnt, mult * ng, wave_max_u32(best)};
 #pragma unroll
         for (int q = 0; q < 7; ++q) v[3 + q] = mult * pat[q];
@@ -197,36 +236,72 @@ __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
             write_summary(cc, a.g, a.rule, a.tab, a.ra, a.rb, s_red[0][0], s_red[0][1], s_red[0][2],
                           pt, a.summ + c);
         }
-        if (tid < 7 && a.pbest) {
-            cv_pattern_pair r = {};
-            const uint32_t key = s_pb[tid];
-            if (key) {
-                const int32_t bi = (int32_t)(key >> 16), bj = (int32_t)(0xFFFFu - (key & 0xFFFFu));
-                double sn, co;
-                ang.get(bj, sn, co);
-                const double rr = (double)(bi + 1);
-                PairEval e;
-                eval_pair(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, e);
-                r.i = (uint16_t)bi;
-                r.j = (uint16_t)bj;
-                for (int k = 0; k < 3; ++k) {
-                    r.plus[k] = (uint8_t)e.Vp[k];
-                    r.minus[k] = (uint8_t)e.Vm[k];
-                }
-                r.pattern = (uint8_t)(tid + 1);
-                r.flags = 1;
-            }
-            a.pbest[c * 7 + tid] = r;
-        }
+        if (tid < 7 && a.pbest) a.pbest[c * 7 + tid] = pattern_pair(a, ang, cc, s_pb[tid], tid);
         if (RAYS) {
             uint16_t* dst = a.rays + c * (int64_t)a.ntheta;
-            for (int k = tid; k < a.W; k += BLOCK) {
-                const uint16_t r = (uint16_t)s_ray[k];
-                dst[k] = r;
-                if (SYM) dst[k + a.W] = r;  // ray j + N/2 holds the same pairs
+            for (int q = tid; q < a.W; q += BLOCK) {
+                const uint16_t r = (uint16_t)s_ray[q];
+                dst[q] = r;
+                if (SYM) dst[q + a.W] = r;  // ray j + N/2 holds the same pairs
             }
         }
         __syncthreads();
+    }
+}
+
+// LDS written by some lanes of a wave visible to its other lanes: a wave's
+// LDS operations complete in order; this keeps the compiler from moving
+// accesses across the point and waits for the outstanding ones.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One colour per wave, BLOCK / 64 colours per block: no block barrier after
+// the start, each wave with its own pattern keys and per-ray maxima in LDS.
+template <bool SYM, bool RAYS, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_colour_resolve_w(ResolveArgs a) {
+    constexpr int NW = BLOCK / 64;
+    extern __shared__ double s_dyn[];
+    __shared__ uint32_t s_pbw[NW][8];
+    const int tid = threadIdx.x;
+    const uint32_t lane = (uint32_t)tid & 63u;
+    const int w = tid >> 6;
+    const Angles ang = load_angles(a.tab, s_dyn);
+    uint32_t* s_ray =
+        reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW) + (RAYS ? w * a.W : 0);
+    uint32_t* s_pb = s_pbw[w];
+    const uint32_t mult = SYM ? 2u : 1u;
+    const int64_t n = (int64_t)*a.n_dev;
+
+    for (int64_t k = (int64_t)blockIdx.x * NW + w; k < n; k += (int64_t)gridDim.x * NW) {
+        const int64_t c = a.list ? (int64_t)a.list[k] : k;
+        if (RAYS)
+            for (int q = (int)lane; q < a.W; q += 64) s_ray[q] = 0;
+        if (lane < 7) s_pb[lane] = 0;
+        wave_lds_sync();
+        const ColorConst cc = a.cc[c];
+        uint32_t cnt = 0, ng = 0, best = 0;
+        uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
+        resolve_colour<RAYS>(a, ang, cc, (int32_t)lane, 64, a.si64, a.sj64, lane, s_pb, s_ray, cnt, ng,
+                             best, pat);
+        best = wave_max_u32(best);
+        wave_lds_sync();
+        if (lane == 0 && a.summ) {
+            uint32_t pt[7];
+            for (int q = 0; q < 7; ++q) pt[q] = mult * pat[q];
+            write_summary(cc, a.g, a.rule, a.tab, a.ra, a.rb, mult * cnt, mult * ng, best, pt, a.summ + c);
+        }
+        if (lane < 7 && a.pbest) a.pbest[c * 7 + lane] = pattern_pair(a, ang, cc, s_pb[lane], (int)lane);
+        if (RAYS) {
+            uint16_t* dst = a.rays + c * (int64_t)a.ntheta;
+            for (int q = (int)lane; q < a.W; q += 64) {
+                const uint16_t r = (uint16_t)s_ray[q];
+                dst[q] = r;
+                if (SYM) dst[q + a.W] = r;
+            }
+        }
+        wave_lds_sync();
     }
 }
 
@@ -488,21 +563,37 @@ unsigned grid_for(int64_t items, int per_block, unsigned cap) {
     return (unsigned)(g > cap ? cap : g);
 }
 
-template <bool SYM, bool RAYS>
-int launch_resolve_t(cv_context* ctx, const ResolveArgs& a, hipStream_t s) {
-    auto k = k_colour_resolve<SYM, RAYS>;
-    const size_t lds = angle_lds_bytes(a.tab) + (RAYS ? (size_t)a.W * 4 : 0);
+template <typename Kern>
+int launch_resolve_k(cv_context* ctx, Kern k, int block, size_t lds, const ResolveArgs& a, hipStream_t s) {
     int lds_max = 0;
     CV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-    if (lds + 256 > (size_t)lds_max)
+    if (lds + 512 > (size_t)lds_max)
         return fail(CV_EINVAL, "angle table and per-ray maxima need " + std::to_string(lds) +
                                    " bytes of LDS; this device has " + std::to_string(lds_max));
     int per_cu = 0;
-    CV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds));
+    CV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, lds));
     if (per_cu < 1) per_cu = 1;
-    hipLaunchKernelGGL(k, dim3((unsigned)(per_cu * ctx->num_cu)), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k, dim3((unsigned)(per_cu * ctx->num_cu)), dim3(block), lds, s, a);
     CV_HIP(hipGetLastError());
     return CV_OK;
+}
+
+// LDS of a resolve variant: the angle tables and, with per-ray maxima, one
+// array of W words per colour in flight in the block.
+size_t resolve_lds(const ResolveArgs& a, bool rays, int variant) {
+    const size_t per_colour = rays ? (size_t)a.W * 4 : 0;
+    const int colours = variant == 0 ? 1 : (variant == 1 ? 4 : 8);
+    return angle_lds_bytes(a.tab) + per_colour * colours;
+}
+
+template <bool SYM, bool RAYS>
+int launch_resolve_t(cv_context* ctx, const ResolveArgs& a, int variant, hipStream_t s) {
+    const size_t lds = resolve_lds(a, RAYS, variant);
+    switch (variant) {
+    case 1: return launch_resolve_k(ctx, k_colour_resolve_w<SYM, RAYS, 256>, 256, lds, a, s);
+    case 2: return launch_resolve_k(ctx, k_colour_resolve_w<SYM, RAYS, 512>, 512, lds, a, s);
+    default: return launch_resolve_k(ctx, k_colour_resolve<SYM, RAYS>, 256, lds, a, s);
+    }
 }
 
 // De-duplication: sorted distinct colours, their number (device, also in
@@ -562,6 +653,8 @@ ResolveArgs resolve_args(cv_context* ctx, const GridDev& gd, const RuleDev& rd, 
     a.inv_W = 1.0f / (float)a.W;
     a.si = 256 / a.W;
     a.sj = 256 % a.W;
+    a.si64 = 64 / a.W;
+    a.sj64 = 64 % a.W;
     a.list = nullptr;
     a.summ = nullptr;
     a.pbest = nullptr;
@@ -569,9 +662,12 @@ ResolveArgs resolve_args(cv_context* ctx, const GridDev& gd, const RuleDev& rd, 
     return a;
 }
 
-int launch_resolve(cv_context* ctx, const ResolveArgs& a, bool sym, hipStream_t s) {
-    if (sym) return a.rays ? launch_resolve_t<true, true>(ctx, a, s) : launch_resolve_t<true, false>(ctx, a, s);
-    return a.rays ? launch_resolve_t<false, true>(ctx, a, s) : launch_resolve_t<false, false>(ctx, a, s);
+int launch_resolve(cv_context* ctx, const ResolveArgs& a, bool sym, int variant, hipStream_t s) {
+    if (sym)
+        return a.rays ? launch_resolve_t<true, true>(ctx, a, variant, s)
+                      : launch_resolve_t<true, false>(ctx, a, variant, s);
+    return a.rays ? launch_resolve_t<false, true>(ctx, a, variant, s)
+                  : launch_resolve_t<false, false>(ctx, a, variant, s);
 }
 
 } // namespace
@@ -589,7 +685,7 @@ int FramesCall::enqueue(cv_context* ctx, hipStream_t s) const {
     a.pbest = pbest;
     a.rays = rays;
     if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
-    if ((rc = launch_resolve(ctx, a, sym, s)) != CV_OK) return rc;
+    if ((rc = launch_resolve(ctx, a, sym, variant, s)) != CV_OK) return rc;
     if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
     if (frame_a) {
         if (resolved)
@@ -606,6 +702,72 @@ bool FramesCall::same(const FramesCall& o) const {
     return std::memcmp(this, &o, sizeof(FramesCall)) == 0;
 }
 
+uint64_t resolve_key(const GridDev& gd, bool rays) {
+    return (uint64_t)(uint32_t)gd.nr | ((uint64_t)(uint32_t)gd.ntheta << 16) | ((uint64_t)(uint32_t)gd.N << 32) |
+           ((uint64_t)(rays ? 1 : 0) << 48);
+}
+
+int resolve_variant(cv_context* ctx, const GridDev& gd, bool rays) {
+    if (ctx->resolve_forced >= 0) return ctx->resolve_forced;
+    const auto it = ctx->resolve_tuned.find(resolve_key(gd, rays));
+    return it == ctx->resolve_tuned.end() ? 0 : it->second;
+}
+
+namespace {
+
+// Time every resolve variant that fits in LDS on up to kTuneColours of the
+// call's colours (their constants are in place after an eager call) and keep
+// the fastest for this grid shape.  The runs rewrite the first outputs with
+// the same values.
+constexpr int64_t kTuneColours = 8192;
+
+int tune_resolve(cv_context* ctx, const FramesCall& call, hipStream_t s) {
+    CV_HIP(hipMemcpyAsync(ctx->host_misc, ctx->fmisc.ptr, 8, hipMemcpyDeviceToHost, s));
+    CV_HIP(hipStreamSynchronize(s));
+    const int64_t n = (int64_t)ctx->host_misc[0];
+    const bool rays = call.rays != nullptr;
+    const uint64_t key = resolve_key(call.gd, rays);
+    if (n < 1) return CV_OK;  // nothing to time: keep the default, tune on a later call
+    uint64_t* cnt = (uint64_t*)ctx->fmisc.ptr + 1;
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, cnt, (uint64_t)std::min(n, kTuneColours));
+    CV_HIP(hipGetLastError());
+    ResolveArgs a = resolve_args(ctx, call.gd, call.rd, cnt);
+    a.summ = call.summ;
+    a.pbest = call.pbest;
+    a.rays = call.rays;
+    const bool sym = call.gd.ntheta == call.gd.N;
+    int lds_max = 0;
+    CV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CV_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    int rc = CV_OK, best_v = 0;
+    float best_ms = 0.0f;
+    for (int v = 0; v < kResolveVariants && rc == CV_OK; ++v) {
+        if (resolve_lds(a, rays, v) + 512 > (size_t)lds_max) continue;
+        if ((rc = launch_resolve(ctx, a, sym, v, s)) != CV_OK) break;  // warm-up
+        float ms = 0.0f;
+        if ((he = hipEventRecord(e0, s)) == hipSuccess && (rc = launch_resolve(ctx, a, sym, v, s)) == CV_OK &&
+            (he = hipEventRecord(e1, s)) == hipSuccess && (he = hipEventSynchronize(e1)) == hipSuccess)
+            he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) rc = hip_fail(he, "timing a resolve variant");
+        if (rc == CV_OK && (v == 0 || ms < best_ms)) {
+            best_ms = ms;
+            best_v = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == CV_OK) ctx->resolve_tuned[key] = best_v;
+    return rc;
+}
+
+} // namespace
+
 int run_frames_resolve(cv_context* ctx, const FramesCall& call_in, bool graph, hipStream_t s) {
     int rc;
     FramesCall call = call_in;
@@ -621,6 +783,18 @@ int run_frames_resolve(cv_context* ctx, const FramesCall& call_in, bool graph, h
     const cvib::Buffer* ws[7] = {&ctx->fbits, &ctx->fcnt, &ctx->fprefix, &ctx->fmisc,
                                  &ctx->scan,  &ctx->colors, &ctx->table};
     for (int k = 0; k < 7; ++k) call.ws[k] = ws[k]->ptr;
+    const bool rays = call.rays != nullptr;
+    if (ctx->autotune && ctx->resolve_forced < 0 && !ctx->resolve_tuned.count(resolve_key(call.gd, rays))) {
+        // one eager call (its outputs stand), then the variants are timed on it
+        const bool timing = ctx->timing;
+        ctx->timing = false;
+        call.variant = 0;
+        rc = call.enqueue(ctx, s);
+        if (rc == CV_OK) rc = tune_resolve(ctx, call, s);
+        ctx->timing = timing;
+        if (rc != CV_OK) return rc;
+    }
+    call.variant = resolve_variant(ctx, call.gd, rays);
     if (!graph) {
         if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
         if ((rc = call.enqueue(ctx, s)) != CV_OK) return rc;
@@ -739,7 +913,9 @@ int enqueue_surrogate(cv_context* ctx, const SurrogateCall& c, const uint8_t* rg
         a.list = list;
         a.summ = (cv_color_summary*)ctx->ssumm.ptr;
         if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
-        if ((rc = launch_resolve(ctx, a, c.gd.ntheta == c.gd.N, s)) != CV_OK) return rc;
+        if ((rc = launch_resolve(ctx, a, c.gd.ntheta == c.gd.N, resolve_variant(ctx, c.gd, false), s)) !=
+            CV_OK)
+            return rc;
         if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
         hipLaunchKernelGGL(k_fallback_finish, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, list,
                            smisc + 1, (const cv_color_summary*)ctx->ssumm.ptr, c.pairs, c.status);

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <exception>
+#include <map>
 #include <string>
 
 #include "../../include/cvib.h"
@@ -102,10 +103,18 @@ struct FramesCall {
     uint8_t* frame_b;
     int64_t* resolved;
     const void* ws[7];  // context workspaces the call uses (a regrown one voids a cached graph)
+    int32_t variant;    // per-colour resolve kernel (see resolve_variant)
+    int32_t _pad;
     int enqueue(cv_context* ctx, hipStream_t s) const;
     bool same(const FramesCall& o) const;
 };
 int run_frames_resolve(cv_context* ctx, const FramesCall& call, bool graph, hipStream_t s);
+
+// Per-colour resolve kernels: 0 = one colour per block of 4 waves, 1 = one
+// colour per wave with 4 waves per block, 2 = the same with 8 waves per block.
+constexpr int kResolveVariants = 3;
+uint64_t resolve_key(const GridDev& gd, bool rays);
+int resolve_variant(cv_context* ctx, const GridDev& gd, bool rays);
 
 // Surrogate resolve of n colours (n_dev: the same count on the device).
 struct SurrogateCall {
@@ -156,6 +165,10 @@ struct cv_context {
     cvib::Buffer slist;       // surrogate: fallback colour indices
     cvib::Buffer ssumm;       // surrogate: exact summaries of fallback colours
     cvib::Buffer smisc;       // surrogate: [0] colour count, [1] fallback count
+    // per-colour resolve kernel choice: forced (-1 = none), or tuned per grid shape
+    bool autotune = false;
+    int resolve_forced = -1;
+    std::map<uint64_t, int> resolve_tuned;
     hipStream_t cap_stream = nullptr;        // stream used for graph capture
     hipGraphExec_t fgraph_exec = nullptr;    // captured cv_frames_resolve
     cvib::FramesCall fgraph_call{};          // the call it was captured for

@@ -203,3 +203,14 @@ def test_init_params_layout(cv):
     assert [w.shape for w in Ws] == [(256, 3), (256, 256), (256, 256), (37, 256)]
     assert all(np.all(b == 0) for b in bs)
     assert abs(Ws[1].std() - np.sqrt(2 / 256)) < 0.01
+
+
+def test_resolve_variant_validation(cv):
+    L = cv.lib()
+    d = C.cast((C.c_uint8 * 4096)(), C.c_void_p)
+    assert L.cv_context_set_autotune(None, 1) == cv.CV_EINVAL
+    assert L.cv_context_set_resolve_variant(None, 0) == cv.CV_EINVAL
+    assert L.cv_context_set_resolve_variant(d, 3) == cv.CV_EINVAL
+    assert L.cv_context_set_resolve_variant(d, -2) == cv.CV_EINVAL
+    v = C.c_int(0)
+    assert L.cv_context_resolve_variant(None, None, 0, C.byref(v), None) == cv.CV_EINVAL

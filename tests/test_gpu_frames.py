@@ -145,3 +145,34 @@ def test_frames_graph_replay_matches_eager(cv):
             else:
                 assert torch.equal(g, v), (rep, k)
         assert int(other.ncolours.item()) > 0
+
+
+@pytest.mark.parametrize("nt", [180, 172])
+def test_resolve_variants_and_autotune_agree(cv, nt):
+    """Every per-colour resolve kernel (one colour per 4-wave block, one per
+    wave with 4 or 8 waves per block) and the tuned choice give the same
+    bytes."""
+    f = torch.from_numpy(_frames()).cuda()
+    grid = cv.Grid(0.5, 60, 2.0, nt)
+    rule = cv.Rule(50, 0.5, 0x7F)
+    info = torch.from_numpy(np.random.default_rng(2).integers(0, 8, f.numel() // 3).astype(np.uint8)).cuda()
+    ctx = cv.Context(0)
+    outs = []
+    for v in (0, 1, 2):
+        ctx.set_resolve_variant(v)
+        assert ctx.resolve_variant(grid, rays=True) == (v, False)
+        outs.append(cv.frames_resolve(f, grid, rule, info=info, rays=True, ctx=ctx))
+    ctx.set_resolve_variant(-1)
+    ctx.set_autotune(True)
+    outs.append(cv.frames_resolve(f, grid, rule, info=info, rays=True, ctx=ctx))
+    v, tuned = ctx.resolve_variant(grid, rays=True)
+    assert tuned and v in (0, 1, 2)
+    outs.append(cv.frames_resolve(f, grid, rule, info=info, rays=True, graph=True, ctx=ctx))
+    torch.cuda.synchronize()
+    n = int(outs[0].ncolours.item())
+    for o in outs[1:]:
+        for k in ("summaries", "pbest", "rays"):
+            assert torch.equal(getattr(o, k)[:n], getattr(outs[0], k)[:n]), k
+        for k in ("frame_a", "frame_b", "resolved", "pixel_index"):
+            assert torch.equal(getattr(o, k), getattr(outs[0], k)), k
+    print("tuned variant", v)
