@@ -226,6 +226,37 @@ def bench_surrogate(cv, W, torch, epochs, steps):
     }
 
 
+def bench_table2(cv, W, torch, steps):
+    """Table 2: the nine colours under the twelve Table 1 settings on the
+    nine-colour grid, in one multi-rule pass and as twelve reductions."""
+    cols = torch.from_numpy(W.PAPER_COLOUR_ARRAY.copy()).cuda()
+    grid = cv.Grid(*W.GRID_NINE.astuple())
+    rules = [cv.Rule(v, r) for v, r in W.TABLE1_RULES]
+    counts = cv.pair_reduce_rules(cols, grid, rules)
+    for r in rules:
+        cv.pair_reduce(cols, grid, r)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(steps):
+        cv.pair_reduce_rules(cols, grid, rules)
+    e.record()
+    torch.cuda.synchronize()
+    one = s.elapsed_time(e) / steps
+    s.record()
+    for _ in range(steps):
+        for r in rules:
+            cv.pair_reduce(cols, grid, r)
+    e.record()
+    torch.cuda.synchronize()
+    twelve = s.elapsed_time(e) / steps
+    pres = (counts > 0).any(dim=1).cpu().numpy()
+    return {"workload": "nine Table 1 colours x twelve Table 1 settings, 324 M candidates each",
+            "ms_one_pass": one, "ms_twelve_reductions": twelve, "speedup": twelve / one,
+            "candidate_rule_pairs_per_s": 12 * 324e6 / (one * 1e-3),
+            "presence_cells": int(pres.sum())}
+
+
 def bench_cube(cv, W, torch, steps):
     """The whole RGB cube (2^24 colours) on the 200 x 180 grid: per-colour
     count and 36-bin maximum radius table."""
@@ -387,6 +418,8 @@ def main():
                        "GBps": 16.0 * total / (k_write * 1e-3) / 1e9 if k_write > 0 else None,
                        "hbm_frac": 16.0 * total / (k_write * 1e-3) / HBM_PEAK if k_write > 0 else None},
     }
+    if args.only in ("all", "nine"):
+        res["table2"] = bench_table2(cv, W, torch, 5)
     if args.only in ("all", "frames"):
         res["frames_exact"] = bench_frames(cv, W, torch, 3)
     if args.only in ("all", "cube"):

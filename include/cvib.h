@@ -203,6 +203,19 @@ int cv_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
                    void* stream);
 
 /*
+ * Several rules in one pass (Table 1's twelve settings give Table 2): for
+ * each colour and rule, the survivors of each pattern.  rules: host array of
+ * nrules (1..16) cv_rule with the same flags (one gamut reading); together
+ * their thresholds (v_th and ceil(v_th * r_novib) - 1 of each) may take at
+ * most 12 distinct values.  rgb: uint8 [n][3] device (n <= 65536).  counts:
+ * uint32 [n][nrules][7] device; [c][r][p-1] counts colour c's survivors of
+ * pattern p under rule r (0 where the rule's mask leaves p out).
+ * Asynchronous.  Errors: CV_EINVAL, CV_EHIP, CV_ENOMEM.
+ */
+int cv_pair_reduce_rules(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,
+                         const cv_rule* rules, int32_t nrules, uint32_t* counts, void* stream);
+
+/*
  * Batched frames (all device arrays).  The colours of npix pixels (uint8
  * [npix][3], e.g. several frames back to back) are de-duplicated: `colours`
  * receives the distinct colours in ascending R<<16|G<<8|B order (uint8

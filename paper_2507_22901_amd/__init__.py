@@ -70,7 +70,7 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_mlp_backward", "cv_adam_step", "cv_mlp_train_steps", "cv_mlp_table_batch", "cv_mlp_save",
            "cv_mlp_load",
            "cv_surrogate_infer", "cv_frames_surrogate", "cv_context_set_autotune",
-           "cv_context_set_resolve_variant", "cv_context_resolve_variant")
+           "cv_context_set_resolve_variant", "cv_context_resolve_variant", "cv_pair_reduce_rules")
 CV_NO_FALLBACK = 0x4
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
 CV_RESOLVED_SURROGATE, CV_RESOLVED_EXACT, CV_RESOLVED_NONE = 0, 1, 2
@@ -125,6 +125,7 @@ def lib() -> C.CDLL:
         L.cv_context_set_resolve_variant.argtypes = [P, C.c_int]
         L.cv_context_resolve_variant.argtypes = [P, C.POINTER(cv_grid), C.c_int, C.POINTER(C.c_int),
                                                  C.POINTER(C.c_int)]
+        L.cv_pair_reduce_rules.argtypes = [P, P, I64, C.POINTER(cv_grid), P, C.c_int32, P, P]
         for name in EXPORTS:
             if name != "cv_last_error":
                 getattr(L, name).restype = C.c_int
@@ -318,6 +319,21 @@ def pair_reduce(colors: torch.Tensor, grid: Grid, rule: Rule, summaries: bool = 
     _check(lib().cv_pair_reduce(ctx.handle, _dptr(colors), n, C.byref(g), C.byref(r), _dptr(summ),
                                 _dptr(tab), _stream()))
     return summ, tab
+
+
+def pair_reduce_rules(colors: torch.Tensor, grid: Grid, rules, ctx: Context | None = None) -> torch.Tensor:
+    """Survivor counts of every pattern under every rule in one pass:
+    int32 view of uint32 [n, len(rules), 7] (rules: Rule objects sharing one
+    gamut reading)."""
+    colors = _colours(colors)
+    ctx = ctx or context(colors.device.index)
+    n = colors.shape[0]
+    arr = (cv_rule * len(rules))(*[r.c() for r in rules])
+    counts = torch.empty((n, len(rules), 7), dtype=torch.int32, device=colors.device)
+    g = grid.c()
+    _check(lib().cv_pair_reduce_rules(ctx.handle, _dptr(colors), n, C.byref(g), C.cast(arr, C.c_void_p),
+                                      len(rules), _dptr(counts), _stream()))
+    return counts
 
 
 def as_records(t: torch.Tensor, dtype: np.dtype) -> np.ndarray:

@@ -214,7 +214,8 @@ int cv_context_destroy(cv_context* ctx) {
     cvib::Buffer* bufs[] = {&ctx->colors, &ctx->table, &ctx->seg_cnt, &ctx->seg_prefix,
                             &ctx->scan,   &ctx->acc,   &ctx->misc,    &ctx->fbits,
                             &ctx->fcnt,   &ctx->fprefix, &ctx->fmisc, &ctx->spred,
-                            &ctx->sneed,  &ctx->sprefix, &ctx->slist, &ctx->ssumm, &ctx->smisc};
+                            &ctx->sneed,  &ctx->sprefix, &ctx->slist, &ctx->ssumm, &ctx->smisc,
+                            &ctx->rtab,   &ctx->rhist};
     for (cvib::Buffer* b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->host_misc) (void)hipHostFree(ctx->host_misc);
@@ -387,6 +388,24 @@ int cv_frames_surrogate(cv_context* ctx, cv_mlp* mlp, const uint8_t* pixels, int
     DeviceGuard dg(ctx->device);
     return cvib::run_frames_surrogate(ctx, c, pixels, npix, colours, colour_cap, ncolours, pixel_index,
                                       frame_a, frame_b, resolved, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
+int cv_pair_reduce_rules(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,
+                         const cv_rule* rules, int32_t nrules, uint32_t* counts, void* stream) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(CV_EINVAL, "n < 0");
+    if (!rules || nrules < 1 || nrules > 16) return fail(CV_EINVAL, "rules: 1..16 of them");
+    if (n > 0 && (!rgb || !counts)) return fail(CV_EINVAL, "null array");
+    cvib::GridDev gd;
+    int rc;
+    if ((rc = cvib::make_grid(grid, &gd)) != CV_OK) return rc;
+    cvib::RuleDev rd[16];
+    for (int r = 0; r < nrules; ++r)
+        if ((rc = cvib::make_rule(&rules[r], &rd[r])) != CV_OK) return rc;
+    DeviceGuard dg(ctx->device);
+    return cvib::run_pair_reduce_rules(ctx, rgb, n, gd, rd, nrules, counts, (hipStream_t)stream);
     CV_GUARD_END
 }
 

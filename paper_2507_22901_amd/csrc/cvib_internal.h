@@ -110,6 +110,9 @@ struct FramesCall {
 };
 int run_frames_resolve(cv_context* ctx, const FramesCall& call, bool graph, hipStream_t s);
 
+int run_pair_reduce_rules(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
+                          const RuleDev* rules, int32_t nrules, uint32_t* counts, hipStream_t s);
+
 // Per-colour resolve kernels: 0 = one colour per block of 4 waves, 1 = one
 // colour per wave with 4 waves per block, 2 = the same with 8 waves per block.
 constexpr int kResolveVariants = 3;
@@ -165,6 +168,8 @@ struct cv_context {
     cvib::Buffer slist;       // surrogate: fallback colour indices
     cvib::Buffer ssumm;       // surrogate: exact summaries of fallback colours
     cvib::Buffer smisc;       // surrogate: [0] colour count, [1] fallback count
+    cvib::Buffer rtab;        // multi-rule: interval table, classes, masks
+    cvib::Buffer rhist;       // multi-rule: interval-triple histogram per colour
     // per-colour resolve kernel choice: forced (-1 = none), or tuned per grid shape
     bool autotune = false;
     int resolve_forced = -1;

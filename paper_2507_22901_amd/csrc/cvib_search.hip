@@ -633,26 +633,6 @@ int zero_u64(void* p, int64_t n, hipStream_t s) {
 }
 
 // Common set-up of a search: per-colour constants and the angle table.
-int prepare(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd, hipStream_t s,
-            TabArgs& tab) {
-    int rc;
-    if ((rc = ctx->ensure(ctx->colors, (size_t)n * sizeof(ColorConst))) != CV_OK) return rc;
-    if ((rc = ctx->ensure(ctx->table, (size_t)gd.tab_len * sizeof(double))) != CV_OK) return rc;
-    hipLaunchKernelGGL(k_angle_table, dim3(blocks_for(gd.N / 2 + 1, 256)), dim3(256), 0, s,
-                       (double*)ctx->table.ptr, gd.N);
-    CV_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_color_prologue, dim3(blocks_for(n, 256)), dim3(256), 0, s, rgb,
-                       (ColorConst*)ctx->colors.ptr, n, mat_args());
-    CV_HIP(hipGetLastError());
-    tab.tab = (const double*)ctx->table.ptr;
-    tab.tab_len = gd.tab_len;
-    tab.N = gd.N;
-    // room for the per-ray maxima of the angle-bin table as well
-    tab.dW = direct_rays(gd.ntheta, gd.N, gd.tab_len, (size_t)gd.ntheta * 4);
-    tab._pad = 0;
-    return CV_OK;
-}
-
 template <typename Kern>
 int persistent_grid(cv_context* ctx, Kern k, int block, size_t lds, int64_t ntiles, unsigned& grid) {
     int per_cu = 0;
@@ -810,6 +790,28 @@ ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, c
 
 } // namespace
 
+// Per-colour constants and the angle table of a call (shared with the
+// multi-rule pass).
+int prepare_colours(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd, hipStream_t s,
+            TabArgs& tab) {
+    int rc;
+    if ((rc = ctx->ensure(ctx->colors, (size_t)n * sizeof(ColorConst))) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->table, (size_t)gd.tab_len * sizeof(double))) != CV_OK) return rc;
+    hipLaunchKernelGGL(k_angle_table, dim3(blocks_for(gd.N / 2 + 1, 256)), dim3(256), 0, s,
+                       (double*)ctx->table.ptr, gd.N);
+    CV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_color_prologue, dim3(blocks_for(n, 256)), dim3(256), 0, s, rgb,
+                       (ColorConst*)ctx->colors.ptr, n, mat_args());
+    CV_HIP(hipGetLastError());
+    tab.tab = (const double*)ctx->table.ptr;
+    tab.tab_len = gd.tab_len;
+    tab.N = gd.N;
+    // room for the per-ray maxima of the angle-bin table as well
+    tab.dW = direct_rays(gd.ntheta, gd.N, gd.tab_len, (size_t)gd.ntheta * 4);
+    tab._pad = 0;
+    return CV_OK;
+}
+
 int launch_angle_table(double* tab, int32_t N, hipStream_t s) {
     hipLaunchKernelGGL(k_angle_table, dim3(blocks_for(N / 2 + 1, 256)), dim3(256), 0, s, tab, N);
     CV_HIP(hipGetLastError());
@@ -862,7 +864,7 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
         return CV_OK;
     }
     TabArgs tab;
-    if ((rc = prepare(ctx, rgb, n, gd, s, tab)) != CV_OK) return rc;
+    if ((rc = prepare_colours(ctx, rgb, n, gd, s, tab)) != CV_OK) return rc;
     // half-turn mode when the grid spans the full turn: one row per segment
     const bool sym = gd.ntheta == gd.N;
     const int32_t W = sym ? gd.N / 2 : gd.ntheta;
@@ -966,7 +968,7 @@ int run_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     if (n == 0) return CV_OK;
     int rc;
     TabArgs tab;
-    if ((rc = prepare(ctx, rgb, n, gd, s, tab)) != CV_OK) return rc;
+    if ((rc = prepare_colours(ctx, rgb, n, gd, s, tab)) != CV_OK) return rc;
     const bool sym = gd.ntheta == gd.N;
     const int32_t W = sym ? gd.N / 2 : gd.ntheta;
     const int64_t per = (int64_t)gd.nr * W;  // evaluations per colour

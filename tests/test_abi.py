@@ -214,3 +214,15 @@ def test_resolve_variant_validation(cv):
     assert L.cv_context_set_resolve_variant(d, -2) == cv.CV_EINVAL
     v = C.c_int(0)
     assert L.cv_context_resolve_variant(None, None, 0, C.byref(v), None) == cv.CV_EINVAL
+
+
+def test_rules_validation(cv):
+    L = cv.lib()
+    d = C.cast((C.c_uint8 * 4096)(), C.c_void_p)
+    g = cv.Grid(0.1, 10, 1.0, 360).c()
+    rules = (cv.cv_rule * 17)(*[cv.Rule().c() for _ in range(17)])
+    assert L.cv_pair_reduce_rules(None, d, 1, C.byref(g), C.cast(rules, C.c_void_p), 1, d, None) == cv.CV_EINVAL
+    assert L.cv_pair_reduce_rules(d, d, 1, C.byref(g), C.cast(rules, C.c_void_p), 0, d, None) == cv.CV_EINVAL
+    assert L.cv_pair_reduce_rules(d, d, 1, C.byref(g), C.cast(rules, C.c_void_p), 17, d, None) == cv.CV_EINVAL
+    assert L.cv_pair_reduce_rules(d, d, 1, C.byref(g), None, 3, d, None) == cv.CV_EINVAL
+    assert L.cv_pair_reduce_rules(d, None, 1, C.byref(g), C.cast(rules, C.c_void_p), 3, d, None) == cv.CV_EINVAL
