@@ -66,67 +66,101 @@ struct GemmArgs {
     int32_t nstore;            // result columns written (<= N)
 };
 
-constexpr int kTile = 64, kDepth = 32, kPitch = 40;
+constexpr int kDepth = 32, kPitch = 40;
 
-template <bool KC>
-__device__ __forceinline__ void load_tile(const bf16* __restrict__ P, int64_t ld, int32_t r0,
-                                          int32_t R, int32_t k0, int32_t ke, bf16* s, int tid) {
-    if constexpr (KC) {
-        // 64 rows x 32 k: thread -> (row tid / 4, 8 k at 8 (tid % 4))
-        const int r = tid >> 2, c = (tid & 3) * 8;
-        bf16x8 v = {};
-        if (r0 + r < R && k0 + c < ke) v = *reinterpret_cast<const bf16x8*>(P + (int64_t)(r0 + r) * ld + k0 + c);
-        *reinterpret_cast<bf16x8*>(s + r * kPitch + c) = v;
-    } else {
-        // 32 k x 64 rows stored k-major: thread -> (k tid / 8, 8 rows at 8 (tid % 8))
-        const int kr = tid >> 3, c = (tid & 7) * 8;
-        bf16x8 v = {};
-        if (k0 + kr < ke && r0 + c < R) v = *reinterpret_cast<const bf16x8*>(P + (int64_t)(k0 + kr) * ld + r0 + c);
+// A tile of R rows x 32 k of one operand, global -> registers: PER 8-element
+// chunks per thread (R * 4 / 256 of them).  KC: stored [row][k]; else [k][row].
+template <bool KC, int R>
+struct TileLoad {
+    static constexpr int PER = R * 4 / 256;
+    bf16x8 v[PER];
+    __device__ __forceinline__ void load(const bf16* __restrict__ P, int64_t ld, int32_t r0, int32_t rows,
+                                         int32_t k0, int32_t ke, int tid) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) s[(c + e) * kPitch + kr] = v[e];
+        for (int q = 0; q < PER; ++q) {
+            const int u = tid + 256 * q;
+            v[q] = bf16x8{};
+            if constexpr (KC) {
+                const int r = u >> 2, c = (u & 3) * 8;
+                if (r0 + r < rows && k0 + c < ke)
+                    v[q] = *reinterpret_cast<const bf16x8*>(P + (int64_t)(r0 + r) * ld + k0 + c);
+            } else {
+                const int kr = u / (R / 8), c = (u % (R / 8)) * 8;
+                if (k0 + kr < ke && r0 + c < rows)
+                    v[q] = *reinterpret_cast<const bf16x8*>(P + (int64_t)(k0 + kr) * ld + r0 + c);
+            }
+        }
     }
-}
+    // registers -> LDS tile [row][k] (k contiguous, pitch kPitch)
+    __device__ __forceinline__ void store(bf16* s, int tid) const {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int u = tid + 256 * q;
+            if constexpr (KC) {
+                const int r = u >> 2, c = (u & 3) * 8;
+                *reinterpret_cast<bf16x8*>(s + r * kPitch + c) = v[q];
+            } else {
+                const int kr = u / (R / 8), c = (u % (R / 8)) * 8;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) s[(c + e) * kPitch + kr] = v[q][e];
+            }
+        }
+    }
+};
 
-template <bool A_KC, bool B_KC, int EPI>
+// BM x BN outputs per block of 4 waves (2 x 2), each wave (BM/2) x (BN/2) as
+// MFMA tiles of 16 x 16; the next 32-deep slice of both operands is fetched
+// into registers while the current one is multiplied from LDS.
+template <bool A_KC, bool B_KC, int EPI, int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
-    __shared__ __attribute__((aligned(16))) bf16 sA[kTile * kPitch];
-    __shared__ __attribute__((aligned(16))) bf16 sB[kTile * kPitch];
+    constexpr int TM = BM / 32, TN = BN / 32;  // MFMA tiles per wave
+    __shared__ __attribute__((aligned(16))) bf16 sA[BM * kPitch];
+    __shared__ __attribute__((aligned(16))) bf16 sB[BN * kPitch];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
-    const int32_t m0 = (int32_t)blockIdx.x * kTile, n0 = (int32_t)blockIdx.y * kTile;
+    const int32_t m0 = (int32_t)blockIdx.x * BM, n0 = (int32_t)blockIdx.y * BN;
     const int32_t kb = (int32_t)blockIdx.z * a.kchunk;
     const int32_t ke = min(a.K, kb + a.kchunk);
-    f32x4 acc[2][2];
+    f32x4 acc[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int fr = lane & 15, fk = (lane >> 4) * 8;
+    TileLoad<A_KC, BM> la;
+    TileLoad<B_KC, BN> lb;
+    la.load(a.A, a.lda, m0, a.M, kb, ke, tid);
+    lb.load(a.B, a.ldb, n0, a.N, kb, ke, tid);
     for (int32_t k0 = kb; k0 < ke; k0 += kDepth) {
-        load_tile<A_KC>(a.A, a.lda, m0, a.M, k0, ke, sA, tid);
-        load_tile<B_KC>(a.B, a.ldb, n0, a.N, k0, ke, sB, tid);
+        la.store(sA, tid);
+        lb.store(sB, tid);
         __syncthreads();
-        bf16x8 fa[2], fb[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            fa[i] = *reinterpret_cast<const bf16x8*>(sA + (32 * wm + 16 * i + fr) * kPitch + fk);
-            fb[i] = *reinterpret_cast<const bf16x8*>(sB + (32 * wn + 16 * i + fr) * kPitch + fk);
+        if (k0 + kDepth < ke) {  // next slice in flight during the products
+            la.load(a.A, a.lda, m0, a.M, k0 + kDepth, ke, tid);
+            lb.load(a.B, a.ldb, n0, a.N, k0 + kDepth, ke, tid);
         }
+        bf16x8 fa[TM], fb[TN];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < TM; ++i)
+            fa[i] = *reinterpret_cast<const bf16x8*>(sA + ((BM / 2) * wm + 16 * i + fr) * kPitch + fk);
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TN; ++j)
+            fb[j] = *reinterpret_cast<const bf16x8*>(sB + ((BN / 2) * wn + 16 * j + fr) * kPitch + fk);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int32_t m = m0 + 32 * wm + 16 * i + (lane >> 4) * 4 + e;
-                const int32_t n = n0 + 32 * wn + 16 * j + fr;
+                const int32_t m = m0 + (BM / 2) * wm + 16 * i + (lane >> 4) * 4 + e;
+                const int32_t n = n0 + (BN / 2) * wn + 16 * j + fr;
                 if (m >= a.M || n >= a.nstore) continue;
                 const float v = acc[i][j][e];
                 if constexpr (EPI == EPI_RELU_BF16) {
@@ -142,6 +176,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
             }
 }
 
+// Rows from which the larger tiles pay (enough blocks to fill the chip).
+constexpr int32_t kBigTileRows = 32768;
+
 template <bool A_KC, bool B_KC, int EPI>
 int gemm(const GemmArgs& a, int32_t splits, hipStream_t s) {
     // vector loads need 8-element alignment along every contiguous dimension
@@ -149,33 +186,54 @@ int gemm(const GemmArgs& a, int32_t splits, hipStream_t s) {
                     (B_KC ? a.K % 8 == 0 : a.N % 8 == 0) && a.kchunk % kDepth == 0 && a.M > 0 &&
                     a.N > 0 && a.K > 0 && splits >= 1 && (int64_t)splits * a.kchunk >= a.K;
     if (!ok) return fail(CV_ESTATE, "internal: matrix product shape");
-    const dim3 grid((unsigned)((a.M + kTile - 1) / kTile), (unsigned)((a.N + kTile - 1) / kTile),
-                    (unsigned)splits);
-    hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI>), grid, dim3(256), 0, s, a);
+    if (a.M >= kBigTileRows && splits == 1) {
+        const dim3 grid((unsigned)((a.M + 127) / 128), (unsigned)((a.N + 127) / 128), 1);
+        hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI, 128, 128>), grid, dim3(256), 0, s, a);
+    } else {
+        const dim3 grid((unsigned)((a.M + 63) / 64), (unsigned)((a.N + 63) / 64), (unsigned)splits);
+        hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI, 64, 64>), grid, dim3(256), 0, s, a);
+    }
     CV_HIP(hipGetLastError());
     return CV_OK;
 }
 
 // ---------------------------------------------------------------------------
 // Input layer on the vector ALUs: H1[s][o] = relu(b0[o] + sum_c W0[o][c] x_c)
-// with x either FP32 [B][d0] or 8-bit RGB (x = v / 255 - 1/2).
+// with x either FP32 [B][d0] or 8-bit RGB (x = v / 255 - 1/2).  Eight threads
+// per row, each 32 consecutive outputs written as four 16-byte stores; the
+// weights sit in LDS.  d1 must be a multiple of 32 and at most 1024.
 template <bool RGB8>
-__global__ void k_input_layer(const void* __restrict__ xin, int64_t B, int32_t d0, int32_t d1,
-                              const float* __restrict__ W0, const float* __restrict__ b0,
-                              bf16* __restrict__ H1) {
-    const int64_t total = B * d1;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-        const int64_t s = t / d1;
-        const int32_t o = (int32_t)(t - s * d1);
-        float acc = b0[o];
+__global__ __launch_bounds__(256) void k_input_layer(const void* __restrict__ xin, int64_t B, int32_t d0,
+                                                     int32_t d1, const float* __restrict__ W0,
+                                                     const float* __restrict__ b0, bf16* __restrict__ H1) {
+    __shared__ float s_w[kMaxHidden * (kMaxIn + 1)];
+    for (int k = threadIdx.x; k < d1 * d0; k += 256) s_w[k] = W0[k];
+    for (int k = threadIdx.x; k < d1; k += 256) s_w[d1 * d0 + k] = b0[k];
+    __syncthreads();
+    const int32_t groups = d1 / 32;                      // threads per row
+    const int64_t total = B * groups;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += stride) {
+        const int64_t s = t / groups;
+        const int32_t o0 = (int32_t)(t - s * groups) * 32;
+        float x[kMaxIn] = {0.f, 0.f, 0.f, 0.f};
         for (int32_t c = 0; c < d0; ++c) {
-            float x;
-            if constexpr (RGB8) x = (float)static_cast<const uint8_t*>(xin)[s * 3 + c] * (1.0f / 255.0f) - 0.5f;
-            else x = static_cast<const float*>(xin)[s * d0 + c];
-            acc = fmaf(W0[o * d0 + c], x, acc);
+            if constexpr (RGB8) x[c] = (float)static_cast<const uint8_t*>(xin)[s * 3 + c] * (1.0f / 255.0f) - 0.5f;
+            else x[c] = static_cast<const float*>(xin)[s * d0 + c];
         }
-        H1[t] = (bf16)fmaxf(acc, 0.0f);
+        bf16* dst = H1 + s * d1 + o0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bf16x8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int32_t o = o0 + 8 * q + e;
+                float acc = s_w[d1 * d0 + o];
+                for (int32_t c = 0; c < d0; ++c) acc = fmaf(s_w[o * d0 + c], x[c], acc);
+                v[e] = (bf16)fmaxf(acc, 0.0f);
+            }
+            *reinterpret_cast<bf16x8*>(dst + 8 * q) = v;
+        }
     }
 }
 
@@ -470,14 +528,13 @@ int run_forward(cv_mlp* m, const void* x, bool rgb8, int64_t rows, float* out, b
         const int64_t nr = std::min(chunk, rows - r0);
         const void* xs = rgb8 ? (const void*)((const uint8_t*)x + r0 * 3)
                               : (const void*)((const float*)x + r0 * m->dims[0]);
+        const unsigned ib = blocks(nr * (m->dims[1] / 32), 256);
         if (rgb8)
-            hipLaunchKernelGGL(k_input_layer<true>, dim3(blocks(nr * m->dims[1], 256)), dim3(256), 0, s,
-                               xs, nr, m->dims[0], m->dims[1], m->params + m->woff[0],
-                               m->params + m->boff[0], m->h[1]);
+            hipLaunchKernelGGL(k_input_layer<true>, dim3(ib), dim3(256), 0, s, xs, nr, m->dims[0],
+                               m->dims[1], m->params + m->woff[0], m->params + m->boff[0], m->h[1]);
         else
-            hipLaunchKernelGGL(k_input_layer<false>, dim3(blocks(nr * m->dims[1], 256)), dim3(256), 0, s,
-                               xs, nr, m->dims[0], m->dims[1], m->params + m->woff[0],
-                               m->params + m->boff[0], m->h[1]);
+            hipLaunchKernelGGL(k_input_layer<false>, dim3(ib), dim3(256), 0, s, xs, nr, m->dims[0],
+                               m->dims[1], m->params + m->woff[0], m->params + m->boff[0], m->h[1]);
         CV_HIP(hipGetLastError());
         if ((rc = forward_tail(m, m->h, nr, out + r0 * m->dims[m->L], s)) != CV_OK) return rc;
     }
