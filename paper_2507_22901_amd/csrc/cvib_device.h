@@ -90,12 +90,13 @@ __device__ __forceinline__ void pair_linear(const ColorConst& cc, const Geom& g,
 
 // pair_linear for a whole wave, with the cube branch of finv taken without a
 // select when no lane of the wave needs the linear branch (same results).
+// cube_known: the caller has shown that every f of the call exceeds delta.
 __device__ __forceinline__ void pair_linear_w(const ColorConst& cc, const Geom& g, double dx,
-                                             double dz, float fp[3], float fm[3]) {
+                                             double dz, float fp[3], float fm[3],
+                                             bool cube_known = false) {
     const double xp = cc.fx0 + dx, zp = cc.fz0 - dz, xm = cc.fx0 - dx, zm = cc.fz0 + dz;
     double gxp, gzp, gxm, gzm;
-    const double lo = fmin(fmin(xp, zp), fmin(xm, zm));
-    if (__ballot(lo <= kDelta) == 0ull) {
+    if (cube_known || __ballot(fmin(fmin(xp, zp), fmin(xm, zm)) <= kDelta) == 0ull) {
         gxp = xp * xp * xp;
         gzp = zp * zp * zp;
         gxm = xm * xm * xm;
@@ -111,6 +112,15 @@ __device__ __forceinline__ void pair_linear_w(const ColorConst& cc, const Geom& 
         fp[k] = (float)__builtin_fma(g.A[k], gxp, __builtin_fma(g.C[k], gzp, cc.B[k]));
         fm[k] = (float)__builtin_fma(g.A[k], gxm, __builtin_fma(g.C[k], gzm, cc.B[k]));
     }
+}
+
+// Whether every f = f0 +- r sin / 500 (X) and f0 -+ r cos / 200 (Z) of radii
+// up to (imax + 1) dr lies above delta, so that finv takes its cube branch:
+// |sin|, |cos| <= 1, with a margin far above the rounding of the products.
+__device__ __forceinline__ bool cube_branch_only(const ColorConst& cc, int32_t imax, double ra,
+                                                 double rb) {
+    const double r = (double)(imax + 1);
+    return cc.fx0 - r * ra > kDelta + 1e-9 && cc.fz0 - r * rb > kDelta + 1e-9;
 }
 
 // All three linear channels in [0, 1]: the IEEE bit patterns of non-negative

@@ -132,13 +132,14 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
     int32_t i, j;
     divmod_small(g_tid, a.W, a.inv_W, i, j);
     const int32_t iters = (per + g_size - 1) / g_size;
+    const bool cube = cube_branch_only(cc, a.nr - 1, a.ra, a.rb);
     for (int32_t it = 0; it < iters; ++it) {
         const bool live = it * g_size + g_tid < per;
         double sn, co;
         ang.get(j, sn, co);
         const double rr = (double)(i + 1);
         float fp[3], fm[3];
-        pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
+        pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm, cube);
         const uint64_t live_m = __ballot(live);
         const uint64_t both_m = __ballot(in_unit_cube(fp) && in_unit_cube(fm)) & live_m;
         const uint64_t need_m = clip ? live_m : both_m;

@@ -139,11 +139,11 @@ constexpr int kPassBlock = 512;
 
 template <bool EMIT_ALL>
 __device__ __forceinline__ void candidate(const ColorConst& cc, const SearchArgs& a, double s,
-                                          double co, int32_t i, bool live, uint32_t& lo,
+                                          double co, int32_t i, bool live, bool cube, uint32_t& lo,
                                           uint32_t& hi, bool& surv, bool& both, uint32_t& pat) {
     const double rr = (double)(i + 1);
     float fp[3], fm[3];
-    pair_linear_w(cc, a.g, (rr * a.ra) * s, (rr * a.rb) * co, fp, fm);
+    pair_linear_w(cc, a.g, (rr * a.ra) * s, (rr * a.rb) * co, fp, fm, cube);
     const bool gp = in_unit_cube(fp), gm = in_unit_cube(fm);
     both = live && gp && gm;
     const bool need = a.rule.clip ? live : both;
@@ -241,6 +241,7 @@ __global__ __launch_bounds__(kPassBlock) void k_pair_pass(SearchArgs a) {
             divmod_small(jb + (int32_t)lane, a.W, a.inv_W, di, j);
             i += di;
         }
+        const bool cube = cube_branch_only(cc, (base_e + len - 1) / a.W, a.ra, a.rb);
         uint32_t wtop = 0;             // survivors of this segment before the current pass
         uint32_t cnt = 0, ng = 0, best = 0, steps = 0;
         uint64_t pk = 0;               // 8-bit pattern counters, flushed every 255 passes
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(kPassBlock) void k_pair_pass(SearchArgs a) {
             ang.get(j, sn, co);
             uint32_t lo, hi, pat;
             bool surv, both;
-            candidate<EMIT_ALL>(cc, a, sn, co, i, live, lo, hi, surv, both, pat);
+            candidate<EMIT_ALL>(cc, a, sn, co, i, live, cube, lo, hi, surv, both, pat);
             const bool emit = EMIT_ALL ? live : surv;
             const uint64_t bal = __ballot(emit);
             if constexpr (WRITE) {
@@ -469,13 +470,14 @@ __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
         uint32_t cnt = 0, ng = 0, best = 0;
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
         const int32_t iters = (len + BLOCK - 1) / BLOCK;
+        const bool cube = cube_branch_only(cc, (begin + len - 1) / a.W, a.ra, a.rb);
         for (int32_t it = 0; it < iters; ++it) {
             const bool live = it * BLOCK + tid < len;
             double sn, co;
             ang.get(j, sn, co);
             const double rr = (double)(i + 1);
             float fp[3], fm[3];
-            pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
+            pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm, cube);
             const uint64_t live_m = __ballot(live);
             const uint64_t both_m = __ballot(in_unit_cube(fp) && in_unit_cube(fm)) & live_m;
             const uint64_t need_m = clip ? live_m : both_m;
