@@ -60,6 +60,8 @@ extern "C" {
 /* ---- cv_pair_search flags --------------------------------------------- */
 #define CV_EMIT_ALL 0x1u  /* testing: emit every candidate; cv_pair.flags   */
                           /* then tells gamut / validity                     */
+#define CV_PER_RAY 0x8u   /* only the survivor of largest i of every ray    */
+                          /* (colour, j), in (colour, j) order               */
 
 /* ---- rule flags -------------------------------------------------------- */
 #define CV_RULE_CLIP 0x1u /* alternative gamut reading: clamp each encoded  */
@@ -185,6 +187,10 @@ int cv_lab_convert(cv_context* ctx, const void* in, void* out, int64_t n, int di
  * is a pure count.  The context's workspace grows with the number of
  * segments (one per row of radius when theta covers the full turn, else one
  * per 512 candidates): 12 bytes each.
+ * With CV_PER_RAY (not with CV_EMIT_ALL) the records are, for every colour
+ * and every ray j < ntheta that has a survivor, the survivor of largest
+ * radius index i, in (colour, j) order; offsets and the two-call idiom work
+ * as above, and the workspace holds 16 bytes per ray of every colour.
  * Errors: CV_EINVAL, CV_ECAPACITY, CV_EHIP, CV_ENOMEM, CV_ESTATE.
  */
 int cv_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,
@@ -201,6 +207,16 @@ int cv_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
 int cv_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,
                    const cv_rule* rule, cv_color_summary* summ, cv_table_row* table,
                    void* stream);
+
+/*
+ * Summaries of a survivor list (the output of cv_pair_search, either mode):
+ * recs (cv_pair, device) with CSR offsets (int64 [n + 1], device) -> summ
+ * (cv_color_summary [n], device): count, per-pattern counts and the
+ * maximum-amplitude record of each colour's range.  A list carries no gamut
+ * count: n_gamut is 0.  Asynchronous.  Errors: CV_EINVAL, CV_EHIP.
+ */
+int cv_pair_reduce_csr(cv_context* ctx, const cv_pair* recs, const int64_t* offsets, int64_t n,
+                       cv_color_summary* summ, void* stream);
 
 /*
  * Several rules in one pass (Table 1's twelve settings give Table 2): for

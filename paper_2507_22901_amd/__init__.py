@@ -27,6 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libcvib.so")
 CV_OK, CV_EINVAL, CV_ECAPACITY, CV_EHIP, CV_ENOMEM, CV_ESTATE = 0, -1, -2, -3, -4, -5
 CV_RGB8_TO_LAB, CV_LAB_TO_RGBF = 0, 1
 CV_EMIT_ALL = 0x1
+CV_PER_RAY = 0x8
 CV_GRAPH = 0x2
 CV_RULE_CLIP = 0x1
 CV_TIME_EVAL, CV_TIME_WRITE, CV_TIME_CALL = 0, 1, 2
@@ -70,7 +71,8 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_mlp_backward", "cv_adam_step", "cv_mlp_train_steps", "cv_mlp_table_batch", "cv_mlp_save",
            "cv_mlp_load",
            "cv_surrogate_infer", "cv_frames_surrogate", "cv_context_set_autotune",
-           "cv_context_set_resolve_variant", "cv_context_resolve_variant", "cv_pair_reduce_rules")
+           "cv_context_set_resolve_variant", "cv_context_resolve_variant", "cv_pair_reduce_rules",
+           "cv_pair_reduce_csr")
 CV_NO_FALLBACK = 0x4
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
 CV_RESOLVED_SURROGATE, CV_RESOLVED_EXACT, CV_RESOLVED_NONE = 0, 1, 2
@@ -126,6 +128,7 @@ def lib() -> C.CDLL:
         L.cv_context_resolve_variant.argtypes = [P, C.POINTER(cv_grid), C.c_int, C.POINTER(C.c_int),
                                                  C.POINTER(C.c_int)]
         L.cv_pair_reduce_rules.argtypes = [P, P, I64, C.POINTER(cv_grid), P, C.c_int32, P, P]
+        L.cv_pair_reduce_csr.argtypes = [P, P, P, I64, P, P]
         for name in EXPORTS:
             if name != "cv_last_error":
                 getattr(L, name).restype = C.c_int
@@ -274,9 +277,10 @@ class SearchResult:
 
 
 def pair_search(colors: torch.Tensor, grid: Grid, rule: Rule, capacity: int | None = None,
-                summaries: bool = True, emit_all: bool = False,
+                summaries: bool = True, emit_all: bool = False, per_ray: bool = False,
                 out: torch.Tensor | None = None, ctx: Context | None = None) -> SearchResult:
-    """Full search with stream compaction; survivors in (colour, i, j) order.
+    """Full search with stream compaction; survivors in (colour, i, j) order
+    (per_ray: the largest-radius survivor of each ray, in (colour, j) order).
 
     With capacity None the output grows to fit (one extra search if the first
     guess is too small)."""
@@ -286,11 +290,14 @@ def pair_search(colors: torch.Tensor, grid: Grid, rule: Rule, capacity: int | No
     dev = colors.device
     offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
     summ = torch.empty((n, 48), dtype=torch.uint8, device=dev) if summaries else None
-    flags = CV_EMIT_ALL if emit_all else 0
+    flags = (CV_EMIT_ALL if emit_all else 0) | (CV_PER_RAY if per_ray else 0)
     if out is None:
         if capacity is None:
             full = n * grid.per_colour
-            capacity = full if emit_all else min(full, max(1 << 20, full // 4))
+            if per_ray:
+                capacity = n * grid.ntheta
+            else:
+                capacity = full if emit_all else min(full, max(1 << 20, full // 4))
         out = torch.empty((max(capacity, 1), 16), dtype=torch.uint8, device=dev)
     cap = out.shape[0] if capacity is None else min(capacity, out.shape[0])
     total = C.c_int64(0)
@@ -319,6 +326,20 @@ def pair_reduce(colors: torch.Tensor, grid: Grid, rule: Rule, summaries: bool = 
     _check(lib().cv_pair_reduce(ctx.handle, _dptr(colors), n, C.byref(g), C.byref(r), _dptr(summ),
                                 _dptr(tab), _stream()))
     return summ, tab
+
+
+def pair_reduce_csr(records: torch.Tensor, offsets: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:
+    """Per-colour summaries (uint8 [n, 48]) of a survivor list (uint8 [total, 16])
+    with its CSR offsets (int64 [n + 1]); n_gamut is 0."""
+    if not records.is_cuda or not offsets.is_cuda or offsets.dtype != torch.int64:
+        raise ValueError("records and offsets must be CUDA tensors, offsets int64")
+    ctx = ctx or context(offsets.device.index)
+    n = offsets.numel() - 1
+    summ = torch.empty((n, 48), dtype=torch.uint8, device=offsets.device)
+    recs = records.contiguous() if records.numel() else torch.empty((1, 16), dtype=torch.uint8, device=offsets.device)
+    _check(lib().cv_pair_reduce_csr(ctx.handle, _dptr(recs), _dptr(offsets.contiguous()), n, _dptr(summ),
+                                    _stream()))
+    return summ
 
 
 def pair_reduce_rules(colors: torch.Tensor, grid: Grid, rules, ctx: Context | None = None) -> torch.Tensor:

@@ -215,7 +215,7 @@ int cv_context_destroy(cv_context* ctx) {
                             &ctx->scan,   &ctx->acc,   &ctx->misc,    &ctx->fbits,
                             &ctx->fcnt,   &ctx->fprefix, &ctx->fmisc, &ctx->spred,
                             &ctx->sneed,  &ctx->sprefix, &ctx->slist, &ctx->ssumm, &ctx->smisc,
-                            &ctx->rtab,   &ctx->rhist};
+                            &ctx->rtab,   &ctx->rhist,   &ctx->rays};
     for (cvib::Buffer* b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->host_misc) (void)hipHostFree(ctx->host_misc);
@@ -248,7 +248,9 @@ int cv_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
     if (capacity < 0) return fail(CV_EINVAL, "capacity < 0");
     if (capacity > 0 && !out) return fail(CV_EINVAL, "out is NULL with capacity > 0");
     if (n > 0 && !rgb) return fail(CV_EINVAL, "rgb is NULL");
-    if (flags & ~(uint32_t)CV_EMIT_ALL) return fail(CV_EINVAL, "unknown flags");
+    if (flags & ~(uint32_t)(CV_EMIT_ALL | CV_PER_RAY)) return fail(CV_EINVAL, "unknown flags");
+    if ((flags & CV_EMIT_ALL) && (flags & CV_PER_RAY))
+        return fail(CV_EINVAL, "CV_EMIT_ALL and CV_PER_RAY exclude each other");
     cvib::GridDev gd;
     cvib::RuleDev rd;
     int rc;
@@ -388,6 +390,17 @@ int cv_frames_surrogate(cv_context* ctx, cv_mlp* mlp, const uint8_t* pixels, int
     DeviceGuard dg(ctx->device);
     return cvib::run_frames_surrogate(ctx, c, pixels, npix, colours, colour_cap, ncolours, pixel_index,
                                       frame_a, frame_b, resolved, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
+int cv_pair_reduce_csr(cv_context* ctx, const cv_pair* recs, const int64_t* offsets, int64_t n,
+                       cv_color_summary* summ, void* stream) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(CV_EINVAL, "n < 0");
+    if (n > 0 && (!offsets || !summ)) return fail(CV_EINVAL, "null array");
+    DeviceGuard dg(ctx->device);
+    return cvib::run_pair_csr_summary(ctx, recs, offsets, n, summ, (hipStream_t)stream);
     CV_GUARD_END
 }
 

@@ -77,6 +77,8 @@ int run_lab_convert(cv_context* ctx, const void* in, void* out, int64_t n, int d
 int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
                     const RuleDev& rd, cv_pair* out, int64_t capacity, int64_t* offsets,
                     cv_color_summary* summ, int64_t* total_host, uint32_t flags, hipStream_t s);
+int run_pair_csr_summary(cv_context* ctx, const cv_pair* recs, const int64_t* offsets, int64_t n,
+                         cv_color_summary* summ, hipStream_t s);
 int run_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
                     const RuleDev& rd, cv_color_summary* summ, cv_table_row* table,
                     hipStream_t s);
@@ -168,6 +170,7 @@ struct cv_context {
     cvib::Buffer slist;       // surrogate: fallback colour indices
     cvib::Buffer ssumm;       // surrogate: exact summaries of fallback colours
     cvib::Buffer smisc;       // surrogate: [0] colour count, [1] fallback count
+    cvib::Buffer rays;        // per-ray search: largest i + 1 per evaluated ray
     cvib::Buffer rtab;        // multi-rule: interval table, classes, masks
     cvib::Buffer rhist;       // multi-rule: interval-triple histogram per colour
     // per-colour resolve kernel choice: forced (-1 = none), or tuned per grid shape

@@ -304,6 +304,116 @@ __global__ __launch_bounds__(kPassBlock) void k_pair_pass(SearchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Per-ray survivors: for every ray of the grid the survivor of largest i, in
+// (colour, j) order.  rays[c][jj] holds that i + 1 for the evaluated rays;
+// ray j reads jj = j, or j - W (its mirror) in half-turn mode.
+
+__global__ void k_ray_flags(const uint32_t* __restrict__ rays, int64_t n, int32_t W, int32_t ntheta,
+                            uint32_t* __restrict__ flags) {
+    const int64_t total = n * ntheta;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const int64_t c = t / ntheta;
+        const int32_t j = (int32_t)(t - c * ntheta);
+        const int32_t jj = j < W ? j : j - W;
+        flags[t] = rays[c * W + jj] ? 1u : 0u;
+    }
+}
+
+__global__ void k_ray_records(const uint32_t* __restrict__ rays, const uint64_t* __restrict__ prefix,
+                              int64_t n, int32_t W, int32_t ntheta, const ColorConst* __restrict__ ccs,
+                              Geom g, RuleDev rule, TabArgs tab, double ra, double rb,
+                              uint4* __restrict__ out, uint64_t capacity) {
+    const int64_t total = n * ntheta;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const int64_t c = t / ntheta;
+        const int32_t j = (int32_t)(t - c * ntheta);
+        const int32_t jj = j < W ? j : j - W;
+        const uint32_t r = rays[c * W + jj];
+        const uint64_t pos = prefix[t];
+        if (!r || pos >= capacity) continue;
+        const int32_t i = (int32_t)r - 1;
+        double sn, co;
+        sincos_j(tab.tab, tab.N, jj, sn, co);
+        const double rr = (double)(i + 1);
+        PairEval e;
+        eval_pair(ccs[c], g, (rr * ra) * sn, (rr * rb) * co, e);
+        const uint32_t p = pattern_of(e.Vp, e.Vm, rule);
+        const uint32_t fl = (e.gp ? 1u : 0u) | (e.gm ? 2u : 0u) | 4u;
+        uint32_t lo, hi;
+        pack_pair(e.Vp, e.Vm, p, fl, lo, hi);
+        if (j >= W) {  // the mirror: + and - swap
+            uint32_t mlo, mhi;
+            mirror_pair(lo, hi, mlo, mhi);
+            lo = mlo;
+            hi = mhi;
+        }
+        out[pos] = make_uint4((uint32_t)c, (uint32_t)i | ((uint32_t)j << 16), lo, hi);
+    }
+}
+
+// Summaries of a survivor list: block per colour over its CSR range.  The
+// list holds no gamut count (n_gamut = 0).
+__global__ __launch_bounds__(256) void k_csr_summary(const uint4* __restrict__ recs,
+                                                     const int64_t* __restrict__ offsets, int64_t n,
+                                                     cv_color_summary* __restrict__ summ) {
+    __shared__ uint32_t s_cnt[8];
+    __shared__ uint32_t s_best;
+    for (int64_t c = blockIdx.x; c < n; c += gridDim.x) {
+        if (threadIdx.x < 8) s_cnt[threadIdx.x] = 0;
+        if (threadIdx.x == 0) s_best = 0;
+        __syncthreads();
+        const int64_t b = offsets[c], e = offsets[c + 1];
+        uint32_t best = 0, cnt = 0;
+        for (int64_t k = b + threadIdx.x; k < e; k += blockDim.x) {
+            const uint4 r = recs[k];
+            const uint32_t i = r.y & 0xFFFFu, j = r.y >> 16, p = (r.w >> 16) & 0xFFu;
+            best = max(best, (i << 16) | (0xFFFFu - j));
+            ++cnt;
+            if (p >= 1u && p <= 7u) atomicAdd(&s_cnt[p], 1u);
+        }
+        best = wave_max_u32(best);
+        cnt = wave_sum_u32(cnt);
+        if ((threadIdx.x & 63u) == 0) {
+            atomicMax(&s_best, best);
+            atomicAdd(&s_cnt[0], cnt);
+        }
+        __syncthreads();
+        const uint32_t key = s_best;
+        if (threadIdx.x == 0) {
+            cv_color_summary o = {};
+            o.count = s_cnt[0];
+            o.n_gamut = 0;
+            o.best_i = 0xFFFFu;
+            for (int q = 0; q < 7; ++q) o.per_pattern[q] = s_cnt[q + 1];
+            if (!key) summ[c] = o;
+        }
+        if (key) {
+            for (int64_t k = b + threadIdx.x; k < e; k += blockDim.x) {
+                const uint4 r = recs[k];
+                const uint32_t i = r.y & 0xFFFFu, j = r.y >> 16;
+                if (((i << 16) | (0xFFFFu - j)) != key) continue;
+                cv_color_summary o = {};
+                o.count = s_cnt[0];
+                o.n_gamut = 0;
+                o.best_i = (uint16_t)i;
+                o.best_j = (uint16_t)j;
+                const uint8_t* by = reinterpret_cast<const uint8_t*>(&r) + 8;  // plus[3], minus[3], p
+                for (int q = 0; q < 3; ++q) {
+                    o.best_plus[q] = by[q];
+                    o.best_minus[q] = by[3 + q];
+                }
+                o.best_p = by[6];
+                for (int q = 0; q < 7; ++q) o.per_pattern[q] = s_cnt[q + 1];
+                summ[c] = o;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Segment record counts -> output offsets: an exclusive scan in segment
 // order, which is (colour, i, j) order; also the per-colour CSR offsets.
 
@@ -411,6 +521,7 @@ struct ReduceArgs {
     cv_color_summary* summ;   // direct mode outputs (nullable)
     cv_table_row* table;      // direct mode outputs (nullable)
     uint64_t* misc;           // [0] ticket
+    uint32_t* rays_out;       // TABLE: per-ray largest i + 1, [n][W], merged by atomicMax (nullable)
     uint32_t* seg_cnt;        // SEG: output records per segment of the search
     int32_t seg_len;          // SEG: evaluations per segment (chunk is a multiple)
     int32_t segs_per_colour;  // SEG
@@ -531,6 +642,11 @@ __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
         }
         __syncthreads();
         if constexpr (TABLE) {
+            if (a.rays_out) {
+                uint32_t* dst = a.rays_out + c * (int64_t)a.W;
+                for (int k = tid; k < a.W; k += BLOCK)
+                    if (s_ray[k]) atomicMax(&dst[k], s_ray[k]);
+            }
             if (tid < 36) s_bins[tid] = 0;
             __syncthreads();
             for (int k = tid; k < a.W; k += BLOCK) {
@@ -559,10 +675,12 @@ __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
                 if (a.summ)
                     write_summary(cc, a.g, a.rule, a.tab, a.ra, a.rb, s_red[0][0], s_red[0][1],
                                   s_red[0][2], pt, a.summ + c);
-                if constexpr (TABLE) a.table[c].count = s_red[0][0];
+                if constexpr (TABLE) {
+                    if (a.table) a.table[c].count = s_red[0][0];
+                }
             }
             if constexpr (TABLE) {
-                if (tid < 36) a.table[c].bin_ridx[tid] = (uint8_t)min(s_bins[tid], 255u);
+                if (tid < 36 && a.table) a.table[c].bin_ridx[tid] = (uint8_t)min(s_bins[tid], 255u);
             }
         } else {
             SumAcc* acc = a.acc + c;
@@ -784,6 +902,7 @@ ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, c
     a.summ = nullptr;
     a.table = nullptr;
     a.misc = (uint64_t*)ctx->misc.ptr;
+    a.rays_out = nullptr;
     a.seg_cnt = nullptr;
     a.seg_len = 0;
     a.segs_per_colour = 0;
@@ -854,11 +973,88 @@ int run_lab_convert(cv_context* ctx, const void* in, void* out, int64_t n, int d
     return CV_OK;
 }
 
+namespace {
+
+// The search with CV_PER_RAY: per-ray maxima from the reduce kernel (its
+// angle-bin path keeps them in LDS and merges them per colour), then flags in
+// (colour, ray) order, a scan, and the records of the flagged rays evaluated
+// again.
+int run_pair_search_per_ray(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
+                            const RuleDev& rd, cv_pair* out, int64_t capacity, int64_t* offsets,
+                            cv_color_summary* summ, int64_t* total_host, hipStream_t s) {
+    int rc;
+    TabArgs tab;
+    if ((rc = prepare_colours(ctx, rgb, n, gd, s, tab)) != CV_OK) return rc;
+    const bool sym = gd.ntheta == gd.N;
+    const int32_t W = sym ? gd.N / 2 : gd.ntheta;
+    const int64_t per = (int64_t)gd.nr * W;
+    const ReducePlan pl = plan_reduce(n, per, 0);
+    const int64_t nrays = n * (int64_t)gd.ntheta;
+    if ((rc = ctx->ensure(ctx->misc, 64)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->acc, (size_t)n * sizeof(SumAcc))) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->rays, (size_t)(n * W + 1) * 4)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->seg_cnt, (size_t)nrays * 4)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->seg_prefix, (size_t)nrays * 8)) != CV_OK) return rc;
+    if ((rc = zero_u64(ctx->misc.ptr, 8, s)) != CV_OK) return rc;
+    if ((rc = zero_u64(ctx->rays.ptr, (n * W + 1) / 2, s)) != CV_OK) return rc;
+    if (!pl.direct && (rc = zero_u64(ctx->acc.ptr, n * (int64_t)(sizeof(SumAcc) / 8), s)) != CV_OK) return rc;
+    ReduceArgs a = reduce_args(ctx, tab, gd, rd, W, pl, n);
+    a.summ = summ;
+    a.table = nullptr;
+    a.rays_out = (uint32_t*)ctx->rays.ptr;
+    if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
+    if ((rc = launch_reduce(ctx, a, true, pl.direct, sym, false, s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
+    if (!pl.direct && summ) {
+        hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 128)), dim3(128), 0, s, a.cc,
+                           (const SumAcc*)ctx->acc.ptr, n, a.g, rd, tab, gd.ra, gd.rb, summ,
+                           (cv_table_row*)nullptr);
+    }
+    hipLaunchKernelGGL(k_ray_flags, dim3(blocks_for(nrays, 256)), dim3(256), 0, s,
+                       (const uint32_t*)ctx->rays.ptr, n, W, gd.ntheta, (uint32_t*)ctx->seg_cnt.ptr);
+    CV_HIP(hipGetLastError());
+    uint64_t* misc = (uint64_t*)ctx->misc.ptr;
+    if ((rc = run_scan_counts(ctx, (const uint32_t*)ctx->seg_cnt.ptr, nrays, (uint64_t*)ctx->seg_prefix.ptr,
+                              offsets, gd.ntheta, n, misc + 2, s)) != CV_OK)
+        return rc;
+    if (out && capacity > 0) {
+        hipLaunchKernelGGL(k_ray_records, dim3(blocks_for(nrays, 256)), dim3(256), 0, s,
+                           (const uint32_t*)ctx->rays.ptr, (const uint64_t*)ctx->seg_prefix.ptr, n, W,
+                           gd.ntheta, (const ColorConst*)ctx->colors.ptr, a.g, rd, tab, gd.ra, gd.rb,
+                           (uint4*)out, (uint64_t)capacity);
+        CV_HIP(hipGetLastError());
+    }
+    if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
+    CV_HIP(hipMemcpyAsync(ctx->host_misc, ctx->misc.ptr, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    CV_HIP(hipStreamSynchronize(s));
+    if ((rc = ctx->collect()) != CV_OK) return rc;
+    *total_host = (int64_t)ctx->host_misc[2];
+    if (*total_host > capacity)
+        return fail(CV_ECAPACITY, "per-ray total " + std::to_string(*total_host) + " exceeds capacity " +
+                                      std::to_string(capacity));
+    return CV_OK;
+}
+
+} // namespace
+
+int run_pair_csr_summary(cv_context* ctx, const cv_pair* recs, const int64_t* offsets, int64_t n,
+                         cv_color_summary* summ, hipStream_t s) {
+    (void)ctx;
+    if (n == 0) return CV_OK;
+    hipLaunchKernelGGL(k_csr_summary, dim3((unsigned)std::min<int64_t>(n, 65536)), dim3(256), 0, s,
+                       (const uint4*)recs, offsets, n, summ);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
 int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
                     const RuleDev& rd, cv_pair* out, int64_t capacity, int64_t* offsets,
                     cv_color_summary* summ, int64_t* total_host, uint32_t flags,
                     hipStream_t s) {
     int rc;
+    if (n > 0 && (flags & CV_PER_RAY))
+        return run_pair_search_per_ray(ctx, rgb, n, gd, rd, out, capacity, offsets, summ, total_host, s);
     if (n == 0) {
         if (offsets) hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, offsets, (int64_t)0);
         CV_HIP(hipGetLastError());

@@ -226,3 +226,17 @@ def test_rules_validation(cv):
     assert L.cv_pair_reduce_rules(d, d, 1, C.byref(g), C.cast(rules, C.c_void_p), 17, d, None) == cv.CV_EINVAL
     assert L.cv_pair_reduce_rules(d, d, 1, C.byref(g), None, 3, d, None) == cv.CV_EINVAL
     assert L.cv_pair_reduce_rules(d, None, 1, C.byref(g), C.cast(rules, C.c_void_p), 3, d, None) == cv.CV_EINVAL
+
+
+def test_per_ray_and_list_validation(cv):
+    L = cv.lib()
+    d = C.cast((C.c_uint8 * 4096)(), C.c_void_p)
+    g = cv.Grid(0.1, 10, 1.0, 360).c()
+    r = cv.Rule().c()
+    tot = C.c_int64(0)
+    both = cv.CV_EMIT_ALL | cv.CV_PER_RAY
+    assert L.cv_pair_search(d, d, 1, C.byref(g), C.byref(r), None, 0, None, None, C.byref(tot), both,
+                            None) == cv.CV_EINVAL
+    assert L.cv_pair_reduce_csr(None, d, d, 1, d, None) == cv.CV_EINVAL
+    assert L.cv_pair_reduce_csr(d, d, None, 1, d, None) == cv.CV_EINVAL
+    assert L.cv_pair_reduce_csr(d, d, d, -1, d, None) == cv.CV_EINVAL

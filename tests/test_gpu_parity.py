@@ -310,3 +310,77 @@ def test_nine_colours_full_grid(cv, oracle):
     st = compare_survivors(cv, oracle, cols, grid, rule, res, tag="nine")
     print("nine colours, full grid:", st)
     compare_summaries(cv, oracle, cols, grid, rule, res.summaries)
+
+
+# --------------------------------------------------------------------------
+# Per-ray mode and list summaries
+
+def _oracle_per_ray(recs, offs, n, nt):
+    """(colour, j) -> best survivor record (largest i) from an oracle list."""
+    best = {}
+    for c in range(n):
+        for r in recs[offs[c]:offs[c + 1]]:
+            k = (c, int(r["j"]))
+            if k not in best or r["i"] > best[k]["i"]:
+                best[k] = r
+    return best
+
+
+@pytest.mark.parametrize("nt", [180, 166])
+def test_per_ray_search_matches_oracle(cv, oracle, nt):
+    cols = np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(81, 40)])
+    grid = (0.5, 90, 2.0, nt)
+    rule = (50, 0.5, 0x7F)
+    res = cv.pair_search(_dev(cols), cv.Grid(*grid), cv.Rule(*rule), per_ray=True)
+    g = cv.as_records(res.pairs, cv.PAIR_DTYPE)
+    offs = res.offsets.cpu().numpy()
+    recs, o_offs, _ = oracle.search(cols, grid, rule)
+    s_o = oracle.reduce(cols, grid, rule)
+    best = _oracle_per_ray(recs, o_offs, len(cols), nt)
+    # order: (colour, j) strictly increasing; offsets consistent
+    key = g["colour"].astype(np.int64) * nt + g["j"]
+    assert np.all(np.diff(key) > 0)
+    assert offs[-1] == len(g) and np.all(np.diff(offs) >= 0)
+    ok = s_o["n_ambiguous"] == 0
+    checked = 0
+    for c in np.nonzero(ok)[0]:
+        mine = g[offs[c]:offs[c + 1]]
+        want = sorted((k[1], v) for k, v in best.items() if k[0] == c)
+        assert len(mine) == len(want), c
+        for rec, (j, b) in zip(mine, want):
+            assert rec["j"] == j and rec["i"] == b["i"], (c, j)
+            if not b["flags"] & 1:
+                assert np.array_equal(rec["plus"], b["plus"]) and np.array_equal(rec["minus"], b["minus"])
+                assert rec["pattern"] == b["pattern"]
+            checked += 1
+    assert checked > 100
+    # the summaries of the per-ray call are the full search's
+    full = cv.pair_search(_dev(cols), cv.Grid(*grid), cv.Rule(*rule))
+    assert torch.equal(res.summaries, full.summaries)
+
+
+def test_per_ray_capacity_two_call(cv):
+    cols = _dev(W.random_colours(82, 30))
+    grid, rule = cv.Grid(0.5, 90, 2.0, 180), cv.Rule(50, 0.5, 0x7F)
+    ref = cv.pair_search(cols, grid, rule, per_ray=True)
+    small = torch.empty((7, 16), dtype=torch.uint8, device="cuda")
+    with pytest.raises(cv.CvError) as e:
+        cv.pair_search(cols, grid, rule, capacity=7, per_ray=True, out=small)
+    assert e.value.code == cv.CV_ECAPACITY
+    assert torch.equal(small, ref.pairs[:7])
+
+
+def test_list_summaries_equal_search_summaries(cv):
+    cols = _dev(np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(83, 50)]))
+    grid, rule = cv.Grid(0.5, 100, 2.0, 180), cv.Rule(100, 0.25, 0x7F)
+    full = cv.pair_search(cols, grid, rule)
+    a = cv.as_records(cv.pair_reduce_csr(full.pairs, full.offsets), cv.SUMMARY_DTYPE)
+    b = cv.as_records(full.summaries, cv.SUMMARY_DTYPE)
+    for k in ("count", "best_i", "best_j", "best_plus", "best_minus", "best_p", "per_pattern"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.all(a["n_gamut"] == 0)
+    # the best pair is also the best of the per-ray list
+    pr = cv.pair_search(cols, grid, rule, per_ray=True)
+    c = cv.as_records(cv.pair_reduce_csr(pr.pairs, pr.offsets), cv.SUMMARY_DTYPE)
+    for k in ("best_i", "best_j", "best_plus", "best_minus", "best_p"):
+        assert np.array_equal(c[k], b[k]), k
