@@ -41,11 +41,13 @@ HBM_PEAK = 8e12
 FLOPS_GEOM = 40
 FLOPS_CODE = 33
 
-# HBM traffic of the count pass on this workload, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch) scaled by the same counters on a 256 MiB device
-# copy; valid only for the kernel sources it was measured on (their digest).
-MEASURED_TRAFFIC = {"sources_sha256": "3b7a7f977b42624ea5f949c9ad272a325fd5d7b56f73996129689d301168b4de",
-                    "bytes": 1331598}  # profiles/search_nine_colours.md
+# Counter figures of the count pass on this workload, from rocprofv3 runs of
+# `bench.py --only nine` (profiles/search_nine_colours.md): HBM traffic =
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the same counters on
+# a 256 MiB device copy; VALU issue = SQ_INSTS_VALU x 4 cycles over 1024 SIMDs
+# x GRBM_GUI_ACTIVE cycles.  Valid only for the kernel sources they were
+# measured on (their digest).
+MEASURED_COUNTERS = {"sources_sha256": None, "traffic_bytes": None, "valu_issue": None}
 KERNEL_SOURCES = ("cvib_search.hip", "cvib_device.h", "cvib_kernels.h")
 
 
@@ -58,9 +60,9 @@ def kernel_sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic():
-    if MEASURED_TRAFFIC["sources_sha256"] == kernel_sources_digest():
-        return MEASURED_TRAFFIC["bytes"]
+def measured_counter(name):
+    if MEASURED_COUNTERS["sources_sha256"] == kernel_sources_digest():
+        return MEASURED_COUNTERS[name]
     return None
 
 
@@ -308,10 +310,17 @@ def cpu_baseline(target_s: float):
     oracle.reduce(cols, (g.dr, rows, g.dtheta_deg, g.ntheta), W.DEFAULT_RULE, nthreads=threads)
     dt = time.perf_counter() - t0
     pairs = len(cols) * rows * g.ntheta
+    # one core, on a sample of about a tenth of the time
+    rows1 = max(2, int(rows * 0.1 / max(threads, 1)))
+    t0 = time.perf_counter()
+    oracle.reduce(cols, (g.dr, rows1, g.dtheta_deg, g.ntheta), W.DEFAULT_RULE, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"nine colours x first {rows} of {g.nr} radii x {g.ntheta} angles "
                       f"({pairs} pairs, {dt:.1f} s)",
-            "seconds": dt}
+            "seconds": dt,
+            "single_core": {"value": len(cols) * rows1 * g.ntheta / dt1, "unit": "pairs/s", "cores": 1,
+                            "sample": f"nine colours x first {rows1} radii ({dt1:.2f} s)"}}
 
 
 def main():
@@ -408,7 +417,8 @@ def main():
             "peak": VALU_FMA_PEAK / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / VALU_FMA_PEAK,
-            "traffic": measured_traffic(),
+            "traffic": measured_counter("traffic_bytes"),
+            "valu_issue_profiled": measured_counter("valu_issue"),
             "kernel_ms": k_eval,
             "flops_per_launch": flops,
             "evaluated_pairs": evals,
