@@ -240,6 +240,13 @@ int run_pair_reduce_rules(cv_context* ctx, const uint8_t* rgb, int64_t n, const 
     a.mult = sym ? 2u : 1u;
     auto k = sym ? k_rule_hist<true> : k_rule_hist<false>;
     const size_t lds = angle_lds_bytes(tab);
+    hipFuncAttributes fa;
+    CV_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k)));
+    int lds_max = 0;
+    CV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    if (lds + fa.sharedSizeBytes > (size_t)lds_max)
+        return fail(CV_EINVAL, "this grid needs " + std::to_string(lds + fa.sharedSizeBytes) +
+                                   " bytes of LDS per block; the device has " + std::to_string(lds_max));
     int per_cu = 0;
     CV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kRulesBlock, lds));
     if (per_cu < 1) per_cu = 1;

@@ -755,6 +755,14 @@ int zero_u64(void* p, int64_t n, hipStream_t s) {
 // Common set-up of a search: per-colour constants and the angle table.
 template <typename Kern>
 int persistent_grid(cv_context* ctx, Kern k, int block, size_t lds, int64_t ntiles, unsigned& grid) {
+    // the angle tables (and per-ray maxima) of large grids may not fit
+    hipFuncAttributes fa;
+    CV_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k)));
+    int lds_max = 0;
+    CV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    if (lds + fa.sharedSizeBytes > (size_t)lds_max)
+        return fail(CV_EINVAL, "this grid needs " + std::to_string(lds + fa.sharedSizeBytes) +
+                                   " bytes of LDS per block; the device has " + std::to_string(lds_max));
     int per_cu = 0;
     CV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, lds));
     if (per_cu < 1) per_cu = 1;

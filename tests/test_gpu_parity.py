@@ -384,3 +384,30 @@ def test_list_summaries_equal_search_summaries(cv):
     c = cv.as_records(cv.pair_reduce_csr(pr.pairs, pr.offsets), cv.SUMMARY_DTYPE)
     for k in ("best_i", "best_j", "best_plus", "best_minus", "best_p"):
         assert np.array_equal(c[k], b[k]), k
+
+
+# --------------------------------------------------------------------------
+# Large angle grids: more rays than the direct per-ray LDS tables hold, so the
+# hot loops read the folded table (a quarter turn when N % 4 == 0, a half turn
+# of sin and cos when N % 4 == 2).
+
+@pytest.mark.parametrize("N,nt", [(8192, 8192), (6146, 6146), (8192, 5000)])
+def test_large_angle_grids(cv, oracle, N, nt):
+    cols = np.concatenate([W.PAPER_COLOUR_ARRAY[:4], W.random_colours(91, 4)])
+    grid = (0.75, 14, 360.0 / N, nt)
+    rule = (50, 0.5, 0x7F)
+    res = cv.pair_search(_dev(cols), cv.Grid(*grid), cv.Rule(*rule))
+    compare_survivors(cv, oracle, cols, grid, rule, res, tag=f"N={N}")
+    summ, _ = cv.pair_reduce(_dev(cols), cv.Grid(*grid), cv.Rule(*rule))
+    assert torch.equal(summ, res.summaries)
+    counts = cv.pair_reduce_rules(_dev(cols), cv.Grid(*grid), [cv.Rule(*rule)])
+    s = cv.as_records(summ, cv.SUMMARY_DTYPE)
+    assert np.array_equal(counts[:, 0].cpu().numpy(), s["per_pattern"].astype(np.int64))
+    # the per-colour resolve of the frames path on the same colours
+    px = _dev(np.repeat(cols[None, :, :], 3, axis=0))
+    fr = cv.frames_resolve(px, cv.Grid(*grid), cv.Rule(*rule))
+    n = int(fr.ncolours.item())
+    order = np.argsort((cols.astype(np.int64) << [16, 8, 0]).sum(1))
+    fs = cv.as_records(fr.summaries[:n], cv.SUMMARY_DTYPE)
+    for k in ("count", "n_gamut", "best_i", "best_j", "per_pattern"):
+        assert np.array_equal(fs[k], s[k][order]), k
