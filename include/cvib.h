@@ -410,7 +410,13 @@ int cv_mlp_load(cv_mlp* m, const char* path);
  * mean prediction of bin b and its mirror b + 18) and proposed.  Every
  * proposal runs through the same arithmetic as the exact search, so a
  * verified pair is one of its survivors; the verified proposal of largest i
- * (then smallest j) is kept.
+ * (then smallest j) is kept.  A local search through the same predicate then
+ * raises it: its ray is climbed (the radii above it, 64 at a time, up to 256,
+ * stopping at a block of 64 with no survivor), every ray of every proposed
+ * bin is tried at the few radii above the kept one (64 / rays of the bin),
+ * and the 16 rays around the kept ray (-8..+7) at the 4 radii above it, up
+ * to 4 times; a survivor of larger i replaces the kept pair and its ray is
+ * climbed.  The result is never above the exact search's best pair.
  * Colours with a lower logit or with no verified proposal go to the exact
  * search (its maximum-amplitude pair), unless CV_NO_FALLBACK is set.
  */

@@ -372,13 +372,68 @@ __global__ void k_copy_count(const uint64_t* __restrict__ src, int64_t* __restri
 // has the same validity and a larger j).  Each proposal runs through the
 // exact predicate of the search (the same device functions and the same
 // arithmetic), so a verified pair is a survivor of the exact search; the
-// verified pair of largest i (then smallest j) is kept.  Colours with a low
-// logit or without a verified proposal go to the exact fallback.  One wave
-// per colour.
+// verified pair of largest i (then smallest j) is kept.  A local search then
+// raises it:
+// - climb: the radii of one ray from a start index upward, 64 at a time,
+//   through the same predicate; the largest that passes is a candidate; the
+//   climb stops at the first block of 64 with no survivor or after
+//   kClimbBlocks blocks;
+// - the kept pair's ray is climbed;
+// - bin sweep: every ray of every proposed bin at the few radii above the
+//   kept one (64 / rays of the bin, at least one); the survivor of largest
+//   key replaces the kept pair and its ray is climbed;
+// - sweep: the 16 rays around the kept pair's ray (-8..+7) at the 4 radii
+//   above it; a survivor replaces the kept pair and its ray is climbed;
+//   repeated up to kSweeps times while it finds one.
+// Colours with a low logit or without a verified proposal go to the exact
+// fallback.  One wave per colour.
 
 constexpr int kBins = 36;
 constexpr int kDeltas = 6;
+constexpr int kClimbBlocks = 4;
+constexpr int kSweeps = 4;
 __constant__ float kLadder[kDeltas] = {1.0f, 0.0f, -1.0f, -2.5f, -5.0f, -10.0f};
+
+// Exact predicate of candidate (i, j) for one lane; false when not live.
+__device__ __forceinline__ bool verify_candidate(const ColorConst& cc, const Angles& ang, const Geom& g,
+                                                 const RuleDev& rule, double ra, double rb, int32_t i,
+                                                 int32_t j, bool live) {
+    double sn, co;
+    ang.get(j, sn, co);
+    const double rr = (double)(i + 1);
+    float fp[3], fm[3];
+    pair_linear_w(cc, g, (rr * ra) * sn, (rr * rb) * co, fp, fm);
+    const bool both = live && in_unit_cube(fp) && in_unit_cube(fm);
+    const bool need = rule.clip ? live : both;
+    bool ok = false;
+    if (__ballot(need) != 0ull) {
+        float Vp[3], Vm[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            Vp[k] = code8(fp[k]);
+            Vm[k] = code8(fm[k]);
+        }
+        ok = need && accepts(rule, pattern_of(Vp, Vm, rule));
+    }
+    return ok;
+}
+
+// Largest verified key on ray j over radii i_start, i_start + 1, ... (at most
+// kClimbBlocks blocks of 64, stopping at an empty block), merged into best.
+// Wave-uniform arguments and result.
+__device__ __forceinline__ uint32_t climb_ray(const ColorConst& cc, const Angles& ang, const Geom& g,
+                                              const RuleDev& rule, double ra, double rb, int32_t nr,
+                                              int32_t j, int32_t i_start, uint32_t best) {
+    const int lane = threadIdx.x & 63;
+    for (int32_t blk = 0, i0 = i_start; blk < kClimbBlocks && i0 < nr; ++blk, i0 += 64) {
+        const int32_t i = i0 + lane;
+        const bool ok = verify_candidate(cc, ang, g, rule, ra, rb, min(i, nr - 1), j, i < nr);
+        const uint32_t top = wave_max_u32(ok ? best_key(i, j) : 0u);
+        if (top == 0u) break;
+        best = max(best, top);
+    }
+    return best;
+}
 
 struct ProposeArgs {
     const ColorConst* cc;
@@ -431,6 +486,7 @@ __global__ __launch_bounds__(256) void k_propose_verify(ProposeArgs a) {
                 const int32_t nrays = j_hi - j_lo;
                 if (nrays <= 0) continue;
                 const int32_t ncand = nrays * kDeltas;
+                uint32_t bb = 0;
                 for (int32_t u0 = 0; u0 < ncand; u0 += 64) {
                     const int32_t u = u0 + lane;
                     const int32_t t = min(u / nrays, kDeltas - 1), q = u - (u / nrays) * nrays;
@@ -439,24 +495,48 @@ __global__ __launch_bounds__(256) void k_propose_verify(ProposeArgs a) {
                     const int32_t i = (int32_t)rintf(rr_t) - 1;
                     const int32_t j = j_lo + (u < ncand ? q : 0);
                     const bool live = u < ncand && i >= 0 && i < a.nr;
-                    double sn, co;
-                    ang.get(j, sn, co);
-                    const double rr = (double)(i + 1);
-                    float fp[3], fm[3];
-                    pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm);
-                    const bool both = live && in_unit_cube(fp) && in_unit_cube(fm);
-                    const bool need = a.rule.clip ? live : both;
-                    bool ok = false;
-                    if (__ballot(need) != 0ull) {
-                        float Vp[3], Vm[3];
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            Vp[k] = code8(fp[k]);
-                            Vm[k] = code8(fm[k]);
-                        }
-                        ok = need && accepts(a.rule, pattern_of(Vp, Vm, a.rule));
+                    const bool ok = verify_candidate(cc, ang, a.g, a.rule, a.ra, a.rb, i, j, live);
+                    bb = max(bb, wave_max_u32(ok ? best_key(i, j) : 0u));
+                }
+                best = max(best, bb);
+            }
+            if (best) {
+                best = climb_ray(cc, ang, a.g, a.rule, a.ra, a.rb, a.nr, (int32_t)(0xFFFFu - (best & 0xFFFFu)),
+                                 (int32_t)(best >> 16) + 1, best);
+                for (int b = 0; b < kb; ++b) {
+                    const uint64_t sel = __ballot(lane < nb && rank == b);
+                    const int bin = (int)__builtin_ctzll(sel);
+                    const int32_t j_lo = (bin * a.tab.N + kBins - 1) / kBins;
+                    const int32_t j_hi = min(((bin + 1) * a.tab.N + kBins - 1) / kBins, a.ntheta);
+                    const int32_t nrays = j_hi - j_lo;
+                    if (nrays <= 0) continue;
+                    const int32_t per = max(1, 64 / nrays), span = min(nrays, 64);
+                    for (int32_t q0 = 0; q0 < nrays; q0 += span) {
+                        const int32_t bi = (int32_t)(best >> 16);
+                        const int32_t q = q0 + lane % span, i = bi + 1 + lane / span;
+                        const bool live = lane < span * per && q < nrays && i < a.nr;
+                        const int32_t j = j_lo + min(q, nrays - 1);
+                        const bool ok = verify_candidate(cc, ang, a.g, a.rule, a.ra, a.rb, min(i, a.nr - 1), j,
+                                                         live);
+                        const uint32_t top = wave_max_u32(ok ? best_key(i, j) : 0u);
+                        if (top == 0u) continue;
+                        best = climb_ray(cc, ang, a.g, a.rule, a.ra, a.rb, a.nr,
+                                         (int32_t)(0xFFFFu - (top & 0xFFFFu)), (int32_t)(top >> 16) + 1,
+                                         max(best, top));
                     }
-                    best = max(best, wave_max_u32(ok ? best_key(i, j) : 0u));
+                }
+                // mirrors of the second half-turn never win the tie on j
+                const int32_t jend = half ? a.tab.N / 2 : a.ntheta;
+                for (int sw = 0; sw < kSweeps; ++sw) {
+                    const int32_t bi = (int32_t)(best >> 16), bj = (int32_t)(0xFFFFu - (best & 0xFFFFu));
+                    const int32_t j = bj + (lane & 15) - 8, i = bi + 1 + (lane >> 4);
+                    const bool live = j >= 0 && j < jend && j != bj && i < a.nr;
+                    const bool ok = verify_candidate(cc, ang, a.g, a.rule, a.ra, a.rb, min(i, a.nr - 1),
+                                                     live ? j : bj, live);
+                    const uint32_t top = wave_max_u32(ok ? best_key(i, j) : 0u);
+                    if (top == 0u) break;
+                    best = climb_ray(cc, ang, a.g, a.rule, a.ra, a.rb, a.nr, (int32_t)(0xFFFFu - (top & 0xFFFFu)),
+                                     (int32_t)(top >> 16) + 1, max(best, top));
                 }
             }
         }
