@@ -374,13 +374,17 @@ def main():
     t_eval, n_eval = ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
     t_write, n_write = ctx.kernel_time(cv.CV_TIME_WRITE, reset=True)
     t_call, n_call = ctx.kernel_time(cv.CV_TIME_CALL, reset=True)
+    skipped = ctx.skipped(reset=True) // max(n_eval, 1)
     ctx.set_timing(False)
     total = res.total
     summ = cv.as_records(res.summaries, cv.SUMMARY_DTYPE)
     ms_per_step = ms / args.steps
     value = pairs_per_step / (ms_per_step * 1e-3)
     half_turn = g.ntheta * g.dtheta_deg == 360.0
-    evals = pairs_per_step // 2 if half_turn else pairs_per_step
+    # candidates the count pass decides: the evaluated ones and those in
+    # gamut cells proven out of gamut (skipped); only evaluated work counts
+    decided = pairs_per_step // 2 if half_turn else pairs_per_step
+    evals = decided - skipped
     gamut_evals = int(summ["n_gamut"].sum()) // (2 if half_turn else 1)
     flops = FLOPS_GEOM * evals + FLOPS_CODE * gamut_evals
     k_eval = t_eval / max(n_eval, 1)
@@ -421,7 +425,9 @@ def main():
             "valu_issue_profiled": measured_counter("valu_issue"),
             "kernel_ms": k_eval,
             "flops_per_launch": flops,
+            "decided_pairs": decided,
             "evaluated_pairs": evals,
+            "skipped_by_gamut_cells": skipped,
             "in_gamut_evaluations": gamut_evals,
         },
         "write_pass": {"kernel": "k_pair_pass (write)", "ms": k_write,

@@ -283,6 +283,23 @@ int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, cons
  * reset != 0.  Errors: CV_EINVAL (null ctx / outputs, bad phase), CV_EHIP.
  */
 /*
+ * Gamut cells.  The reduce-only kernel (cv_pair_reduce, and the count pass of
+ * cv_pair_search) first splits each of its tiles into cells of 16 radii by 16
+ * rays and proves, by interval arithmetic over the cell in FP64 with a margin
+ * of 1e-6 on the linear channels, which cells hold no pair with both colours
+ * in gamut; a wave step whose candidates all lie in such cells is not
+ * evaluated.  Without the gamut requirement (CV_RULE_CLIP) there are no
+ * cells.  Results are identical with the cells on (the default) or off.
+ * cv_context_set_gamut_cells turns them on or off for later calls.
+ * cv_context_skipped returns (host pointer) the number of candidates the
+ * cells skipped in the calls made while timing was on, since context creation
+ * or the last reset (reset != 0 clears it after reading); it synchronises the
+ * device.  Errors: CV_EINVAL (null ctx / output), CV_EHIP.
+ */
+int cv_context_set_gamut_cells(cv_context* ctx, int on);
+int cv_context_skipped(cv_context* ctx, int64_t* skipped_host, int reset);
+
+/*
  * Kernel choice for the per-colour resolve (cv_frames_resolve and the exact
  * fallback of the surrogate calls): variant 0 gives one colour to a block of
  * four waves, 1 one colour to each wave with four waves per block, 2 the

@@ -72,7 +72,7 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_mlp_load",
            "cv_surrogate_infer", "cv_frames_surrogate", "cv_context_set_autotune",
            "cv_context_set_resolve_variant", "cv_context_resolve_variant", "cv_pair_reduce_rules",
-           "cv_pair_reduce_csr")
+           "cv_pair_reduce_csr", "cv_context_set_gamut_cells", "cv_context_skipped")
 CV_NO_FALLBACK = 0x4
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
 CV_RESOLVED_SURROGATE, CV_RESOLVED_EXACT, CV_RESOLVED_NONE = 0, 1, 2
@@ -129,6 +129,8 @@ def lib() -> C.CDLL:
                                                  C.POINTER(C.c_int)]
         L.cv_pair_reduce_rules.argtypes = [P, P, I64, C.POINTER(cv_grid), P, C.c_int32, P, P]
         L.cv_pair_reduce_csr.argtypes = [P, P, P, I64, P, P]
+        L.cv_context_set_gamut_cells.argtypes = [P, C.c_int]
+        L.cv_context_skipped.argtypes = [P, C.POINTER(I64), C.c_int]
         for name in EXPORTS:
             if name != "cv_last_error":
                 getattr(L, name).restype = C.c_int
@@ -191,6 +193,16 @@ class Context:
         _check(lib().cv_context_kernel_time(self.handle, int(phase), C.byref(ms), C.byref(n),
                                             int(reset)))
         return ms.value, n.value
+
+    def set_gamut_cells(self, on: bool = True):
+        """Skip wave steps of the reduce kernels that lie in cells proven out of gamut."""
+        _check(lib().cv_context_set_gamut_cells(self.handle, int(bool(on))))
+
+    def skipped(self, reset: bool = False) -> int:
+        """Candidates skipped by the gamut cells in calls made while timing was on."""
+        v = C.c_int64(0)
+        _check(lib().cv_context_skipped(self.handle, C.byref(v), int(bool(reset))))
+        return v.value
 
     def set_autotune(self, on: bool = True):
         """Time the per-colour resolve variants on the first call of each grid shape."""

@@ -215,7 +215,7 @@ int cv_context_destroy(cv_context* ctx) {
                             &ctx->scan,   &ctx->acc,   &ctx->misc,    &ctx->fbits,
                             &ctx->fcnt,   &ctx->fprefix, &ctx->fmisc, &ctx->spred,
                             &ctx->sneed,  &ctx->sprefix, &ctx->slist, &ctx->ssumm, &ctx->smisc,
-                            &ctx->rtab,   &ctx->rhist,   &ctx->rays};
+                            &ctx->rtab,   &ctx->rhist,   &ctx->rays,    &ctx->stats};
     for (cvib::Buffer* b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->host_misc) (void)hipHostFree(ctx->host_misc);
@@ -461,7 +461,38 @@ int cv_context_set_timing(cv_context* ctx, int on) {
         for (auto& pr : ctx->ev)
             for (hipEvent_t& e : pr) CV_HIP(hipEventCreate(&e));
     }
+    if (on && !ctx->stats.ptr) {
+        int rc = ctx->ensure(ctx->stats, 64);
+        if (rc != CV_OK) return rc;
+        CV_HIP(hipMemset(ctx->stats.ptr, 0, 64));
+        ctx->stats_base = 0;
+    }
     ctx->timing = on != 0;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_context_set_gamut_cells(cv_context* ctx, int on) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    ctx->gamut_cells = on != 0;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_context_skipped(cv_context* ctx, int64_t* skipped_host, int reset) {
+    CV_GUARD_BEGIN
+    if (!ctx || !skipped_host) return fail(CV_EINVAL, "null argument");
+    DeviceGuard dg(ctx->device);
+    uint64_t v = 0;
+    if (ctx->stats.ptr) {
+        uint64_t w[8];
+        CV_HIP(hipDeviceSynchronize());
+        CV_HIP(hipMemcpy(w, ctx->stats.ptr, sizeof(w), hipMemcpyDeviceToHost));
+        for (uint64_t x : w) v += x;
+    }
+    *skipped_host = (int64_t)(v - ctx->stats_base);
+    if (reset) ctx->stats_base = v;
     return CV_OK;
     CV_GUARD_END
 }

@@ -173,6 +173,11 @@ struct cv_context {
     cvib::Buffer rays;        // per-ray search: largest i + 1 per evaluated ray
     cvib::Buffer rtab;        // multi-rule: interval table, classes, masks
     cvib::Buffer rhist;       // multi-rule: interval-triple histogram per colour
+    // gamut cells in the reduce kernels (cv_context_set_gamut_cells), and the
+    // device counter of the candidates they skipped (counted while timing)
+    bool gamut_cells = true;
+    cvib::Buffer stats;
+    uint64_t stats_base = 0;
     // per-colour resolve kernel choice: forced (-1 = none), or tuned per grid shape
     bool autotune = false;
     int resolve_forced = -1;

@@ -23,6 +23,12 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Number of set bits of `mask` below this lane.
 __device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -209,6 +215,57 @@ __device__ inline Angles load_angles(const TabArgs& t, double* s_dyn) {
     return a;
 }
 
+// Gamut cells.  A cell is a block of candidates: rows i0..i1 by rays j0..j1
+// (the reduce kernel makes one of each wave step's evaluations).
+// cell_out_of_gamut proves, by interval arithmetic, that in every pair of the
+// cell one colour has a linear channel outside [0, 1], so that no candidate
+// of the cell is in gamut:
+// - sin and cos of the cell's rays lie between their values at j0 and j1,
+//   widened to +-1 where the rays pass 90, 180 or 270 degrees (between those
+//   angles both are monotone);
+// - the displacements (i + 1) ra sin and (i + 1) rb cos are bilinear in the
+//   radius and the sine (cosine) with a positive radius, so their ranges are
+//   spanned by the four corners;
+// - finv is increasing, so f -> finv(f) maps the ranges of f to the ranges
+//   of the companded values;
+// - a linear channel A finv(fx) + C finv(fz) + B is bounded term by term.
+// The verdict needs a channel beyond the unit interval by kCellMargin, far
+// above the rounding of the bounds and of the kernels' own FP64 arithmetic,
+// and the FP32 rounding of the channel cannot bring such a value back.
+constexpr double kCellMargin = 1e-6;
+
+__device__ inline bool colour_out(const Geom& g, const ColorConst& cc, double xlo, double xhi, double zlo,
+                                  double zhi) {
+    const double gx0 = finv(xlo), gx1 = finv(xhi), gz0 = finv(zlo), gz1 = finv(zhi);
+    bool out = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double ax0 = g.A[k] * gx0, ax1 = g.A[k] * gx1, cz0 = g.C[k] * gz0, cz1 = g.C[k] * gz1;
+        const double lo = cc.B[k] + fmin(ax0, ax1) + fmin(cz0, cz1);
+        const double hi = cc.B[k] + fmax(ax0, ax1) + fmax(cz0, cz1);
+        out = out || hi < -kCellMargin || lo > 1.0 + kCellMargin;
+    }
+    return out;
+}
+
+__device__ inline bool cell_out_of_gamut(const ColorConst& cc, const Geom& g, const Angles& ang, double ra,
+                                         double rb, int32_t i0, int32_t i1, int32_t j0, int32_t j1) {
+    double s0, c0, s1, c1;
+    ang.get(j0, s0, c0);
+    ang.get(j1, s1, c1);
+    double slo = fmin(s0, s1), shi = fmax(s0, s1), clo = fmin(c0, c1), chi = fmax(c0, c1);
+    const int64_t N = ang.N, J0 = 4 * (int64_t)j0, J1 = 4 * (int64_t)j1;
+    if (J0 <= N && N <= J1) shi = 1.0;
+    if (J0 <= 2 * N && 2 * N <= J1) clo = -1.0;
+    if (J0 <= 3 * N && 3 * N <= J1) slo = -1.0;
+    const double r0 = (double)(i0 + 1), r1 = (double)(i1 + 1);
+    const double dxlo = fmin((r0 * ra) * slo, (r1 * ra) * slo), dxhi = fmax((r0 * ra) * shi, (r1 * ra) * shi);
+    const double dzlo = fmin((r0 * rb) * clo, (r1 * rb) * clo), dzhi = fmax((r0 * rb) * chi, (r1 * rb) * chi);
+    // + colour: (fx0 + dx, fz0 - dz); - colour: (fx0 - dx, fz0 + dz)
+    return colour_out(g, cc, cc.fx0 + dxlo, cc.fx0 + dxhi, cc.fz0 - dzhi, cc.fz0 - dzlo) ||
+           colour_out(g, cc, cc.fx0 - dxhi, cc.fx0 - dxlo, cc.fz0 + dzlo, cc.fz0 + dzhi);
+}
+
 // Lane masks of the per-channel classification of a wave's candidates:
 // H[k] = change above v_th (high), L[k] = change at most lo_max (low).  A
 // lane carries pattern p = 4 R + 2 G + B exactly when, per channel, it is in
@@ -255,6 +312,29 @@ __device__ __forceinline__ void divmod_small(int32_t x, int32_t d, float inv_d, 
     r = x - q * d;
     if (r < 0) { --q; r += d; }
     if (r >= d) { ++q; r -= d; }
+}
+
+// Whether a wave step may hold a pair with both colours in gamut.  The step
+// covers evaluations e0..e1 (e1 - e0 < 64) counted in row-major order from
+// ray jb0 of row row0 (jb0 + e1 < 2^24): one row, the end of one row and the
+// start of the next, or (W < 64) every ray of several rows.  `any` says
+// whether the step exists; e0 and e1 must be valid either way.  Every lane of
+// the wave calls it (the test of a second row runs when any lane needs it).
+__device__ inline bool step_open(const ColorConst& cc, const Geom& g, const Angles& ang, double ra, double rb,
+                                 int32_t W, float inv_W, int32_t row0, int32_t jb0, int32_t e0, int32_t e1,
+                                 bool any) {
+    int32_t ia, ja, ib, jb;
+    divmod_small(jb0 + e0, W, inv_W, ia, ja);
+    divmod_small(jb0 + e1, W, inv_W, ib, jb);
+    ia += row0;
+    ib += row0;
+    const bool two = ib == ia + 1, many = ib > ia + 1;
+    bool open = !cell_out_of_gamut(cc, g, ang, ra, rb, ia, many ? ib : ia, many ? 0 : ja, ib > ia ? W - 1 : jb);
+    if (__ballot(any && two) != 0ull) {
+        const bool o2 = !cell_out_of_gamut(cc, g, ang, ra, rb, ib, ib, 0, jb);
+        open = open || (two && o2);
+    }
+    return open && any;
 }
 
 __device__ __forceinline__ void write_summary(const ColorConst& cc, const Geom& g,

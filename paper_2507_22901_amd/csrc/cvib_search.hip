@@ -95,7 +95,6 @@ struct SearchArgs {
     int32_t nr, ntheta;
     int32_t W;                 // evaluations per row: ntheta, or N/2 in half-turn mode
     float inv_W;
-    int32_t si64, sj64;        // a pass of 64 evaluations = si64 rows + sj64 rays
     int32_t seg_len;           // evaluations per segment (one row in half-turn mode)
     int32_t segs_per_colour;
     int64_t n, nsegs;
@@ -105,6 +104,7 @@ struct SearchArgs {
     uint64_t capacity;         // records
     SumAcc* acc;               // nullable
     uint64_t* misc;            // [0] count-pass ticket, [2] survivor total
+    int32_t cells, _pad;       // skip wave steps proven out of gamut (not with EMIT_ALL)
 };
 
 // Per-wave flush of a thread's running summary into the colour accumulator.
@@ -233,21 +233,29 @@ __global__ __launch_bounds__(kPassBlock) void k_pair_pass(SearchArgs a) {
         const ColorConst cc = a.cc[c];
         const int32_t base_e = ls * a.seg_len;
         const int32_t len = (int32_t)min((int64_t)a.seg_len, per - base_e);
-        int32_t i = base_e / a.W;
-        int32_t j;
-        {
-            const int32_t jb = base_e - i * a.W;
-            int32_t di;
-            divmod_small(jb + (int32_t)lane, a.W, a.inv_W, di, j);
-            i += di;
-        }
+        int32_t i, j;
         const bool cube = cube_branch_only(cc, (base_e + len - 1) / a.W, a.ra, a.rb);
         uint32_t wtop = 0;             // survivors of this segment before the current pass
         uint32_t cnt = 0, ng = 0, best = 0, steps = 0;
         uint64_t pk = 0;               // 8-bit pattern counters, flushed every 255 passes
-        const int32_t iters = (len + 63) >> 6;
-        for (int32_t it = 0; it < iters; ++it) {
+        const int32_t iters = (len + 63) >> 6;  // at most 64: a segment is 512 evaluations or a row
+        const int32_t i_seg = base_e / a.W, j_seg = base_e - i_seg * a.W;
+        uint64_t open_m;
+        if (!EMIT_ALL && a.cells) {
+            // lane l decides pass l; passes proven out of gamut hold no survivor
+            const int32_t e0 = (int32_t)lane << 6;
+            open_m = uniform_u64(__ballot(step_open(cc, a.g, ang, a.ra, a.rb, a.W, a.inv_W, i_seg, j_seg,
+                                                    min(e0, len - 1), min(e0 + 63, len - 1),
+                                                    (int32_t)lane < iters)));
+        } else {
+            open_m = iters >= 64 ? ~0ull : (1ull << iters) - 1ull;
+        }
+        while (open_m) {
+            const int32_t it = (int32_t)__builtin_ctzll(open_m);
+            open_m &= open_m - 1ull;
             const bool live = (it << 6) + (int32_t)lane < len;
+            divmod_small(j_seg + min((it << 6) + (int32_t)lane, len - 1), a.W, a.inv_W, i, j);
+            i += i_seg;
             double sn, co;
             ang.get(j, sn, co);
             uint32_t lo, hi, pat;
@@ -283,9 +291,6 @@ __global__ __launch_bounds__(kPassBlock) void k_pair_pass(SearchArgs a) {
                     steps = 0;
                 }
             }
-            j += a.sj64;
-            i += a.si64;
-            if (j >= a.W) { j -= a.W; ++i; }
         }
         if constexpr (!WRITE) {
             if (lane == 0) a.seg_cnt[sg] = mult * wtop;
@@ -525,6 +530,10 @@ struct ReduceArgs {
     uint32_t* seg_cnt;        // SEG: output records per segment of the search
     int32_t seg_len;          // SEG: evaluations per segment (chunk is a multiple)
     int32_t segs_per_colour;  // SEG
+    // gamut cells: one per wave step, decided per tile into cell_words
+    // 64-bit masks per wave (0 = off)
+    int32_t cell_words, _pad;
+    uint64_t* stats;          // [0..7]: candidates skipped by the cells, summed (nullable)
 };
 
 // Reduce-only search.  A tile is a chunk of one colour's evaluations (i, j < W)
@@ -534,8 +543,14 @@ struct ReduceArgs {
 // surviving radius index of every evaluated ray is kept in LDS.  In half-turn
 // mode (SYM) only rays j < N/2 are evaluated: counts double, and the bins of
 // the second half-turn copy the first (bin(theta + 180 deg) = bin(theta) + 18).
+// With gamut cells, each tile first decides, for every wave step, whether its
+// 64 evaluations are proven out of gamut; such steps are not evaluated (their
+// candidates could neither survive nor count as in gamut), and each wave walks
+// only the open steps of its mask, deriving (i, j) from the step index.
+// Large-chunk blocks of eight waves hold the register budget of six waves per
+// SIMD, so that three blocks share a CU.
 template <int BLOCK, bool TABLE, bool DIRECT, bool SYM, bool SEG>
-__global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
+__global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceArgs a) {
     constexpr int NW = BLOCK / 64;
     constexpr int MAX_SEG = 2048;  // segments per tile (SEG)
     extern __shared__ double s_dyn[];
@@ -549,8 +564,12 @@ __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
     const int w = tid >> 6;
     const Angles ang = load_angles(a.tab, s_dyn);
     uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW);
+    uint64_t* s_open =
+        reinterpret_cast<uint64_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW + (TABLE ? (a.W + 1) / 2 : 0));
     const uint32_t mult = SYM ? 2u : 1u;
     const bool clip = a.rule.clip != 0u;
+    const bool cells = a.cell_words > 0;
+    uint64_t skipped = 0;  // lane's share over the block's tiles
 
     for (;;) {
         if (tid == 0) s_tick = (int64_t)atomicAdd((unsigned long long*)&a.misc[0], 1ull);
@@ -569,67 +588,91 @@ __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
         const int32_t begin = lt * a.chunk;
         const int32_t len = min(a.chunk, a.nr * a.W - begin);
         const int32_t seg0 = SEG ? begin / a.seg_len : 0;  // chunks start on segment bounds
-        int32_t i = begin / a.W;
-        int32_t j;
-        {
-            const int32_t jb = begin - i * a.W;
-            int32_t di;
-            divmod_small(jb + tid, a.W, a.inv_W, di, j);
-            i += di;
+        const int32_t row0 = begin / a.W;
+        const int32_t jb0 = begin - row0 * a.W;  // ray of the tile's first evaluation
+        const int32_t iters = (len + BLOCK - 1) / BLOCK;
+        const int32_t nwords = (iters + 63) >> 6;
+        if (cells) {
+            // Which wave steps hold a candidate that may be in gamut: lane l of
+            // a task decides step it = 64 word + l of wave wv, whose 64
+            // evaluations (one or two rows, several when W < 64) form the cell.
+            for (int32_t task = w; task < NW * nwords; task += NW) {
+                const int32_t word = task / NW, wv = task - word * NW;
+                const int32_t it = word * 64 + (int32_t)lane;
+                const int32_t e0 = it * BLOCK + wv * 64;
+                const bool any = it < iters && e0 < len;
+                const int32_t e1 = min(e0 + 63, len - 1);
+                const bool open = step_open(cc, a.g, ang, a.ra, a.rb, a.W, a.inv_W, row0, jb0, min(e0, len - 1),
+                                            e1, any);
+                if (any && !open) skipped += (uint64_t)(e1 - e0 + 1);
+                const uint64_t m = __ballot(open);
+                if (lane == 0) s_open[wv * a.cell_words + word] = m;
+            }
+            __syncthreads();
         }
         // wave totals (the same value in every lane) and the lane's best key
         uint32_t cnt = 0, ng = 0, best = 0;
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
-        const int32_t iters = (len + BLOCK - 1) / BLOCK;
         const bool cube = cube_branch_only(cc, (begin + len - 1) / a.W, a.ra, a.rb);
-        for (int32_t it = 0; it < iters; ++it) {
-            const bool live = it * BLOCK + tid < len;
-            double sn, co;
-            ang.get(j, sn, co);
-            const double rr = (double)(i + 1);
-            float fp[3], fm[3];
-            pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm, cube);
-            const uint64_t live_m = __ballot(live);
-            const uint64_t both_m = __ballot(in_unit_cube(fp) && in_unit_cube(fm)) & live_m;
-            const uint64_t need_m = clip ? live_m : both_m;
-            ng += (uint32_t)__builtin_popcountll(both_m);
-            uint64_t surv_m = 0;
-            if (need_m != 0ull) {
-                float Vp[3], Vm[3];
-                codes_w(fp, fm, (need_m >> lane) & 1ull, clip, Vp, Vm);
-                const PatMasks pm = pattern_masks(Vp, Vm, a.rule);
-                surv_m = accepted_lanes(pm, a.rule.mask) & need_m;
-                if (surv_m != 0ull) {
-                    cnt += (uint32_t)__builtin_popcountll(surv_m);
+        for (int32_t word = 0; word < nwords; ++word) {
+            uint64_t steps;
+            if (cells) {
+                steps = uniform_u64(s_open[w * a.cell_words + word]);
+            } else {
+                const int32_t rem = iters - word * 64;
+                steps = rem >= 64 ? ~0ull : (1ull << rem) - 1ull;
+            }
+            while (steps) {
+                const int32_t it = word * 64 + (int32_t)__builtin_ctzll(steps);
+                steps &= steps - 1ull;
+                const int32_t e = it * BLOCK + tid;  // evaluation within the tile
+                const bool live = e < len;
+                int32_t i, j;
+                divmod_small(jb0 + min(e, len - 1), a.W, a.inv_W, i, j);
+                i += row0;
+                double sn, co;
+                ang.get(j, sn, co);
+                const double rr = (double)(i + 1);
+                float fp[3], fm[3];
+                pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm, cube);
+                const uint64_t live_m = __ballot(live);
+                const uint64_t both_m = __ballot(in_unit_cube(fp) && in_unit_cube(fm)) & live_m;
+                const uint64_t need_m = clip ? live_m : both_m;
+                ng += (uint32_t)__builtin_popcountll(both_m);
+                uint64_t surv_m = 0;
+                if (need_m != 0ull) {
+                    float Vp[3], Vm[3];
+                    codes_w(fp, fm, (need_m >> lane) & 1ull, clip, Vp, Vm);
+                    const PatMasks pm = pattern_masks(Vp, Vm, a.rule);
+                    surv_m = accepted_lanes(pm, a.rule.mask) & need_m;
+                    if (surv_m != 0ull) {
+                        cnt += (uint32_t)__builtin_popcountll(surv_m);
 #pragma unroll
-                    for (uint32_t p = 1; p <= 7; ++p)
-                        if ((a.rule.mask >> (p - 1u)) & 1u)
-                            pat[p - 1] += (uint32_t)__builtin_popcountll(pattern_lanes(pm, p) & need_m);
-                    if ((surv_m >> lane) & 1ull) {
-                        best = max(best, best_key(i, j));
-                        if constexpr (TABLE) atomicMax(&s_ray[j], (uint32_t)(i + 1));
+                        for (uint32_t p = 1; p <= 7; ++p)
+                            if ((a.rule.mask >> (p - 1u)) & 1u)
+                                pat[p - 1] += (uint32_t)__builtin_popcountll(pattern_lanes(pm, p) & need_m);
+                        if ((surv_m >> lane) & 1ull) {
+                            best = max(best, best_key(i, j));
+                            if constexpr (TABLE) atomicMax(&s_ray[j], (uint32_t)(i + 1));
+                        }
+                    }
+                }
+                if constexpr (SEG) {
+                    // survivors per search segment: split this pass's ballot by
+                    // segment (a pass of 64 evaluations touches few segments)
+                    if (surv_m != 0ull) {
+                        const int32_t sl = (SYM ? i : (begin + e) / a.seg_len) - seg0;
+                        uint64_t rem = surv_m;
+                        while (rem) {
+                            const int32_t first = __builtin_ctzll(rem);
+                            const int32_t sid = __shfl(sl, first, 64);
+                            const uint64_t m = __ballot(sl == sid) & rem;
+                            if (lane == 0) atomicAdd(&s_seg[sid], (uint32_t)__builtin_popcountll(m));
+                            rem &= ~m;
+                        }
                     }
                 }
             }
-            if constexpr (SEG) {
-                // survivors per search segment: split this pass's ballot by
-                // segment (a pass of 64 evaluations touches few segments)
-                if (surv_m != 0ull) {
-                    const int32_t e = begin + it * BLOCK + tid;
-                    const int32_t sl = (SYM ? i : e / a.seg_len) - seg0;
-                    uint64_t rem = surv_m;
-                    while (rem) {
-                        const int32_t first = __builtin_ctzll(rem);
-                        const int32_t sid = __shfl(sl, first, 64);
-                        const uint64_t m = __ballot(sl == sid) & rem;
-                        if (lane == 0) atomicAdd(&s_seg[sid], (uint32_t)__builtin_popcountll(m));
-                        rem &= ~m;
-                    }
-                }
-            }
-            j += a.sj;
-            i += a.si;
-            if (j >= a.W) { j -= a.W; ++i; }
         }
 
         // block reduction: count, n_gamut, best, 7 patterns
@@ -693,6 +736,18 @@ __global__ __launch_bounds__(BLOCK) void k_pair_reduce(ReduceArgs a) {
             }
         }
         __syncthreads();
+    }
+    // every thread left the loop at the same ticket, after a barrier
+    if (a.stats) {
+        __shared__ uint64_t s_skip[NW];
+        for (int o = 32; o > 0; o >>= 1) skipped += (uint64_t)__shfl_xor((unsigned long long)skipped, o, 64);
+        if (lane == 0) s_skip[w] = skipped;
+        __syncthreads();
+        if (tid == 0) {
+            uint64_t sum = 0;
+            for (int q = 0; q < NW; ++q) sum += s_skip[q];
+            if (sum) atomicAdd((unsigned long long*)&a.stats[blockIdx.x & 7u], (unsigned long long)sum);
+        }
     }
 }
 
@@ -812,6 +867,8 @@ int launch_pass(cv_context* ctx, const SearchArgs& a, bool emit, bool summ, bool
 // large chunks take 8 waves to share one copy of the angle tables.
 constexpr int kReduceBlock = 512;
 constexpr int kReduceBlockDirect = 256;
+// LDS bytes of a tile's open-step masks.
+size_t cell_bytes(const ReduceArgs& a) { return (size_t)(a.block / 64) * a.cell_words * sizeof(uint64_t); }
 constexpr int reduce_block(bool direct) { return direct ? kReduceBlockDirect : kReduceBlock; }
 
 template <bool TABLE, bool DIRECT, bool SYM, bool SEG>
@@ -819,7 +876,7 @@ int launch_reduce_t(cv_context* ctx, const ReduceArgs& a, hipStream_t s) {
     constexpr int B = reduce_block(DIRECT);
     if (a.block != B) return fail(CV_ESTATE, "internal: reduce block size");
     auto k = k_pair_reduce<B, TABLE, DIRECT, SYM, SEG>;
-    const size_t lds = angle_lds_bytes(a.tab) + (TABLE ? (size_t)a.W * sizeof(uint32_t) : 0);
+    const size_t lds = angle_lds_bytes(a.tab) + (TABLE ? (size_t)(a.W + 1) / 2 * sizeof(double) : 0) + cell_bytes(a);
     unsigned grid;
     int rc = persistent_grid(ctx, k, B, lds, a.ntiles, grid);
     if (rc != CV_OK) return rc;
@@ -870,7 +927,7 @@ ReducePlan plan_reduce(int64_t n, int64_t per, int32_t seg_len) {
     if (p.direct) {
         p.chunk = per;
     } else {
-        const int64_t want_tiles_per_colour = (8192 + n - 1) / n;
+        const int64_t want_tiles_per_colour = (4096 + n - 1) / n;
         int64_t chunk = (per + want_tiles_per_colour - 1) / want_tiles_per_colour;
         if (chunk < 16 * kReduceBlock) chunk = 16 * kReduceBlock;
         const int64_t unit = seg_len > 0 ? seg_len : kReduceBlock;
@@ -914,6 +971,11 @@ ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, c
     a.seg_cnt = nullptr;
     a.seg_len = 0;
     a.segs_per_colour = 0;
+    // one open-step bit per wave step of a tile; under the clip reading every
+    // candidate counts, so there are no cells
+    a.cell_words = ctx->gamut_cells && !rd.clip ? (int32_t)(((pl.chunk + B - 1) / B + 63) / 64) : 0;
+    a._pad = 0;
+    a.stats = ctx->timing ? (uint64_t*)ctx->stats.ptr : nullptr;
     return a;
 }
 
@@ -1100,8 +1162,6 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     a.ntheta = gd.ntheta;
     a.W = W;
     a.inv_W = 1.0f / (float)W;
-    a.si64 = 64 / W;
-    a.sj64 = 64 % W;
     a.seg_len = seg_len;
     a.segs_per_colour = spc;
     a.n = n;
@@ -1112,6 +1172,8 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     a.capacity = out ? (uint64_t)capacity : 0ull;
     a.acc = nullptr;
     a.misc = (uint64_t*)ctx->misc.ptr;
+    a.cells = ctx->gamut_cells && !rd.clip && !emit ? 1 : 0;
+    a._pad = 0;
 
     // Count pass: survivors per segment.  The reduce-only kernel does it
     // (with the summaries); in emit-all mode every candidate is a record and

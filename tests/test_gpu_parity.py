@@ -411,3 +411,42 @@ def test_large_angle_grids(cv, oracle, N, nt):
     fs = cv.as_records(fr.summaries[:n], cv.SUMMARY_DTYPE)
     for k in ("count", "n_gamut", "best_i", "best_j", "per_pattern"):
         assert np.array_equal(fs[k], s[k][order]), k
+
+
+# --------------------------------------------------------------------------
+# Gamut cells: skipping cells proven out of gamut changes no result.
+
+@pytest.mark.parametrize("case", ["nine", "frames", "cube", "partial", "large", "clip"])
+def test_gamut_cells_change_nothing(cv, case):
+    grids = {
+        "nine": ((0.05, 2000, 0.2, 1800), W.PAPER_COLOUR_ARRAY),
+        "frames": (W.GRID_FRAMES.astuple(), W.random_colours(5, 3000)),
+        "cube": (W.GRID_CUBE.astuple(), W.random_colours(6, 5000)),
+        "partial": ((0.25, 160, 0.5, 500), W.random_colours(7, 40)),
+        "large": ((0.75, 14, 360.0 / 8192, 8192), W.random_colours(8, 12)),
+        "clip": ((0.25, 160, 1.0, 360), W.random_colours(9, 40)),
+    }
+    g, cols = grids[case]
+    rule = cv.Rule(50, 0.5, 0x7F, cv.CV_RULE_CLIP if case == "clip" else 0)
+    grid = cv.Grid(*g)
+    x = _dev(cols)
+    ctx = cv.Context(0)
+    ctx.set_timing(True)
+    ctx.set_gamut_cells(True)
+    tab = g[1] <= 255 and g[3] <= 3600  # table rows: radius indices below 256, tables in LDS
+    on = cv.pair_reduce(x, grid, rule, table=tab, ctx=ctx)
+    s_on = cv.pair_search(x, grid, rule, ctx=ctx)
+    skipped = ctx.skipped(reset=True)
+    ctx.set_gamut_cells(False)
+    off = cv.pair_reduce(x, grid, rule, table=tab, ctx=ctx)
+    s_off = cv.pair_search(x, grid, rule, ctx=ctx)
+    assert ctx.skipped() == 0
+    assert torch.equal(on[0], off[0]) and (not tab or torch.equal(on[1], off[1]))
+    assert s_on.total == s_off.total and torch.equal(s_on.summaries, s_off.summaries)
+    assert torch.equal(s_on.pairs[:s_on.total], s_off.pairs[:s_off.total])
+    per = g[1] * (g[3] // 2 if g[3] * g[2] == 360.0 else g[3])
+    print(f"{case}: skipped {skipped} of {2 * len(cols) * per} evaluations")
+    if case == "clip":
+        assert skipped == 0
+    else:
+        assert 0 < skipped < 2 * len(cols) * per
