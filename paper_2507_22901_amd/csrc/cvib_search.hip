@@ -549,7 +549,7 @@ struct ReduceArgs {
 // only the open steps of its mask, deriving (i, j) from the step index.
 // Large-chunk blocks of eight waves hold the register budget of six waves per
 // SIMD, so that three blocks share a CU.
-template <int BLOCK, bool TABLE, bool DIRECT, bool SYM, bool SEG>
+template <int BLOCK, bool TABLE, bool DIRECT, bool SYM, bool SEG, bool CELLS>
 __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceArgs a) {
     constexpr int NW = BLOCK / 64;
     constexpr int MAX_SEG = 2048;  // segments per tile (SEG)
@@ -568,7 +568,6 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
         reinterpret_cast<uint64_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW + (TABLE ? (a.W + 1) / 2 : 0));
     const uint32_t mult = SYM ? 2u : 1u;
     const bool clip = a.rule.clip != 0u;
-    const bool cells = a.cell_words > 0;
     uint64_t skipped = 0;  // lane's share over the block's tiles
 
     for (;;) {
@@ -592,7 +591,7 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
         const int32_t jb0 = begin - row0 * a.W;  // ray of the tile's first evaluation
         const int32_t iters = (len + BLOCK - 1) / BLOCK;
         const int32_t nwords = (iters + 63) >> 6;
-        if (cells) {
+        if constexpr (CELLS) {
             // Which wave steps hold a candidate that may be in gamut: lane l of
             // a task decides step it = 64 word + l of wave wv, whose 64
             // evaluations (one or two rows, several when W < 64) form the cell.
@@ -614,64 +613,75 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
         uint32_t cnt = 0, ng = 0, best = 0;
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
         const bool cube = cube_branch_only(cc, (begin + len - 1) / a.W, a.ra, a.rb);
-        for (int32_t word = 0; word < nwords; ++word) {
-            uint64_t steps;
-            if (cells) {
-                steps = uniform_u64(s_open[w * a.cell_words + word]);
-            } else {
-                const int32_t rem = iters - word * 64;
-                steps = rem >= 64 ? ~0ull : (1ull << rem) - 1ull;
-            }
-            while (steps) {
-                const int32_t it = word * 64 + (int32_t)__builtin_ctzll(steps);
-                steps &= steps - 1ull;
-                const int32_t e = it * BLOCK + tid;  // evaluation within the tile
-                const bool live = e < len;
-                int32_t i, j;
-                divmod_small(jb0 + min(e, len - 1), a.W, a.inv_W, i, j);
-                i += row0;
-                double sn, co;
-                ang.get(j, sn, co);
-                const double rr = (double)(i + 1);
-                float fp[3], fm[3];
-                pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm, cube);
-                const uint64_t live_m = __ballot(live);
-                const uint64_t both_m = __ballot(in_unit_cube(fp) && in_unit_cube(fm)) & live_m;
-                const uint64_t need_m = clip ? live_m : both_m;
-                ng += (uint32_t)__builtin_popcountll(both_m);
-                uint64_t surv_m = 0;
-                if (need_m != 0ull) {
-                    float Vp[3], Vm[3];
-                    codes_w(fp, fm, (need_m >> lane) & 1ull, clip, Vp, Vm);
-                    const PatMasks pm = pattern_masks(Vp, Vm, a.rule);
-                    surv_m = accepted_lanes(pm, a.rule.mask) & need_m;
-                    if (surv_m != 0ull) {
-                        cnt += (uint32_t)__builtin_popcountll(surv_m);
+        // one wave step: evaluation e of the tile is candidate (i, j)
+        auto step = [&](int32_t i, int32_t j, int32_t e, bool live) {
+            double sn, co;
+            ang.get(j, sn, co);
+            const double rr = (double)(i + 1);
+            float fp[3], fm[3];
+            pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm, cube);
+            const uint64_t live_m = __ballot(live);
+            const uint64_t both_m = __ballot(in_unit_cube(fp) && in_unit_cube(fm)) & live_m;
+            const uint64_t need_m = clip ? live_m : both_m;
+            ng += (uint32_t)__builtin_popcountll(both_m);
+            uint64_t surv_m = 0;
+            if (need_m != 0ull) {
+                float Vp[3], Vm[3];
+                codes_w(fp, fm, (need_m >> lane) & 1ull, clip, Vp, Vm);
+                const PatMasks pm = pattern_masks(Vp, Vm, a.rule);
+                surv_m = accepted_lanes(pm, a.rule.mask) & need_m;
+                if (surv_m != 0ull) {
+                    cnt += (uint32_t)__builtin_popcountll(surv_m);
 #pragma unroll
-                        for (uint32_t p = 1; p <= 7; ++p)
-                            if ((a.rule.mask >> (p - 1u)) & 1u)
-                                pat[p - 1] += (uint32_t)__builtin_popcountll(pattern_lanes(pm, p) & need_m);
-                        if ((surv_m >> lane) & 1ull) {
-                            best = max(best, best_key(i, j));
-                            if constexpr (TABLE) atomicMax(&s_ray[j], (uint32_t)(i + 1));
-                        }
+                    for (uint32_t p = 1; p <= 7; ++p)
+                        if ((a.rule.mask >> (p - 1u)) & 1u)
+                            pat[p - 1] += (uint32_t)__builtin_popcountll(pattern_lanes(pm, p) & need_m);
+                    if ((surv_m >> lane) & 1ull) {
+                        best = max(best, best_key(i, j));
+                        if constexpr (TABLE) atomicMax(&s_ray[j], (uint32_t)(i + 1));
                     }
                 }
-                if constexpr (SEG) {
-                    // survivors per search segment: split this pass's ballot by
-                    // segment (a pass of 64 evaluations touches few segments)
-                    if (surv_m != 0ull) {
-                        const int32_t sl = (SYM ? i : (begin + e) / a.seg_len) - seg0;
-                        uint64_t rem = surv_m;
-                        while (rem) {
-                            const int32_t first = __builtin_ctzll(rem);
-                            const int32_t sid = __shfl(sl, first, 64);
-                            const uint64_t m = __ballot(sl == sid) & rem;
-                            if (lane == 0) atomicAdd(&s_seg[sid], (uint32_t)__builtin_popcountll(m));
-                            rem &= ~m;
-                        }
+            }
+            if constexpr (SEG) {
+                // survivors per search segment: split this pass's ballot by
+                // segment (a pass of 64 evaluations touches few segments)
+                if (surv_m != 0ull) {
+                    const int32_t sl = (SYM ? i : (begin + e) / a.seg_len) - seg0;
+                    uint64_t rem = surv_m;
+                    while (rem) {
+                        const int32_t first = __builtin_ctzll(rem);
+                        const int32_t sid = __shfl(sl, first, 64);
+                        const uint64_t m = __ballot(sl == sid) & rem;
+                        if (lane == 0) atomicAdd(&s_seg[sid], (uint32_t)__builtin_popcountll(m));
+                        rem &= ~m;
                     }
                 }
+            }
+        };
+        if constexpr (CELLS) {
+            // the open steps of this wave, (i, j) from the step index
+            for (int32_t word = 0; word < nwords; ++word) {
+                uint64_t steps = uniform_u64(s_open[w * a.cell_words + word]);
+                while (steps) {
+                    const int32_t it = word * 64 + (int32_t)__builtin_ctzll(steps);
+                    steps &= steps - 1ull;
+                    const int32_t e = it * BLOCK + tid;
+                    int32_t i, j;
+                    divmod_small(jb0 + min(e, len - 1), a.W, a.inv_W, i, j);
+                    step(i + row0, j, e, e < len);
+                }
+            }
+        } else {
+            // every step, (i, j) advanced by one block of evaluations per step
+            int32_t i, j;
+            divmod_small(jb0 + tid, a.W, a.inv_W, i, j);
+            i += row0;
+            for (int32_t it = 0; it < iters; ++it) {
+                const int32_t e = it * BLOCK + tid;
+                step(i, j, e, e < len);
+                j += a.sj;
+                i += a.si;
+                if (j >= a.W) { j -= a.W; ++i; }
             }
         }
 
@@ -867,6 +877,8 @@ int launch_pass(cv_context* ctx, const SearchArgs& a, bool emit, bool summ, bool
 // large chunks take 8 waves to share one copy of the angle tables.
 constexpr int kReduceBlock = 512;
 constexpr int kReduceBlockDirect = 256;
+constexpr int32_t kCellMinRays = 128;
+
 // LDS bytes of a tile's open-step masks.
 size_t cell_bytes(const ReduceArgs& a) { return (size_t)(a.block / 64) * a.cell_words * sizeof(uint64_t); }
 constexpr int reduce_block(bool direct) { return direct ? kReduceBlockDirect : kReduceBlock; }
@@ -875,7 +887,8 @@ template <bool TABLE, bool DIRECT, bool SYM, bool SEG>
 int launch_reduce_t(cv_context* ctx, const ReduceArgs& a, hipStream_t s) {
     constexpr int B = reduce_block(DIRECT);
     if (a.block != B) return fail(CV_ESTATE, "internal: reduce block size");
-    auto k = k_pair_reduce<B, TABLE, DIRECT, SYM, SEG>;
+    auto k = a.cell_words > 0 ? k_pair_reduce<B, TABLE, DIRECT, SYM, SEG, true>
+                              : k_pair_reduce<B, TABLE, DIRECT, SYM, SEG, false>;
     const size_t lds = angle_lds_bytes(a.tab) + (TABLE ? (size_t)(a.W + 1) / 2 * sizeof(double) : 0) + cell_bytes(a);
     unsigned grid;
     int rc = persistent_grid(ctx, k, B, lds, a.ntiles, grid);
@@ -971,9 +984,13 @@ ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, c
     a.seg_cnt = nullptr;
     a.seg_len = 0;
     a.segs_per_colour = 0;
-    // one open-step bit per wave step of a tile; under the clip reading every
-    // candidate counts, so there are no cells
-    a.cell_words = ctx->gamut_cells && !rd.clip ? (int32_t)(((pl.chunk + B - 1) / B + 63) / 64) : 0;
+    // one open-step bit per wave step of a tile.  Under the clip reading every
+    // candidate counts, so there are no cells; with fewer than 128 evaluated
+    // rays per row a step spans more than half of them and the proof rarely
+    // holds (measured: the 90-ray whole-cube table loses 6% with cells)
+    a.cell_words = ctx->gamut_cells && !rd.clip && W >= kCellMinRays
+                       ? (int32_t)(((pl.chunk + B - 1) / B + 63) / 64)
+                       : 0;
     a._pad = 0;
     a.stats = ctx->timing ? (uint64_t*)ctx->stats.ptr : nullptr;
     return a;
