@@ -113,6 +113,7 @@ struct ResolveArgs {
     cv_color_summary* summ;   // nullable
     cv_pattern_pair* pbest;   // nullable, [n][7]
     uint16_t* rays;           // nullable, [n][ntheta]
+    int32_t cells, _pad;      // skip wave steps proven out of gamut (CELLS kernels)
 };
 
 // All candidates of one colour, split over a group of g_size threads (a block
@@ -120,8 +121,12 @@ struct ResolveArgs {
 // row-major (i, j < W) order; a step of g_size evaluations is si rows + sj
 // rays.  Wave totals accumulate in cnt, ng and pat (the same value in every
 // lane), the lane's best key in best; survivors raise the pattern's best key
-// in s_pb and, with RAYS, the ray's largest radius in s_ray.
-template <bool RAYS>
+// in s_pb and, with RAYS, the ray's largest radius in s_ray.  With CELLS
+// ((nr + 3) W < 2^24) the candidates are taken in the band order (bands of
+// four rows, ray by ray; every result here is a count or a maximum, so the
+// order is free) and each wave first decides 64 of its steps at a time, one
+// per lane, evaluating only those that may hold a pair in gamut.
+template <bool RAYS, bool CELLS>
 __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angles& ang,
                                                const ColorConst& cc, int32_t g_tid, int32_t g_size,
                                                int32_t si, int32_t sj, uint32_t lane, uint32_t* s_pb,
@@ -129,12 +134,9 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
                                                uint32_t& best, uint32_t pat[7]) {
     const bool clip = a.rule.clip != 0u;
     const int32_t per = a.nr * a.W;
-    int32_t i, j;
-    divmod_small(g_tid, a.W, a.inv_W, i, j);
     const int32_t iters = (per + g_size - 1) / g_size;
     const bool cube = cube_branch_only(cc, a.nr - 1, a.ra, a.rb);
-    for (int32_t it = 0; it < iters; ++it) {
-        const bool live = it * g_size + g_tid < per;
+    auto step = [&](int32_t i, int32_t j, bool live) {
         double sn, co;
         ang.get(j, sn, co);
         const double rr = (double)(i + 1);
@@ -163,9 +165,35 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
                 }
             }
         }
-        j += sj;
-        i += si;
-        if (j >= a.W) { j -= a.W; ++i; }
+    };
+    if constexpr (CELLS) {
+        const int32_t per4 = ((a.nr + 3) >> 2) * 4 * a.W;  // whole bands
+        const int32_t iters4 = (per4 + g_size - 1) / g_size;
+        const float inv_W4 = 0.25f * a.inv_W;
+        const int32_t wb = g_tid - (int32_t)lane;  // the wave's first evaluation of a step
+        for (int32_t word = 0; word < (iters4 + 63) >> 6; ++word) {
+            const int32_t itl = word * 64 + (int32_t)lane, e0 = itl * g_size + wb;
+            const bool any = itl < iters4 && e0 < per4;
+            uint64_t m = uniform_u64(__ballot(band_step_open(cc, a.g, ang, a.ra, a.rb, a.W, inv_W4,
+                                                             min(e0, per4 - 1), min(e0 + 63, per4 - 1), any)));
+            while (m) {
+                const int32_t e = (word * 64 + (int32_t)__builtin_ctzll(m)) * g_size + g_tid;
+                m &= m - 1ull;
+                int32_t band, q;
+                divmod_small(min(e, per4 - 1), 4 * a.W, inv_W4, band, q);
+                const int32_t i = 4 * band + (q & 3);
+                step(min(i, a.nr - 1), q >> 2, e < per4 && i < a.nr);
+            }
+        }
+    } else {
+        int32_t i, j;
+        divmod_small(g_tid, a.W, a.inv_W, i, j);
+        for (int32_t it = 0; it < iters; ++it) {
+            step(i, j, it * g_size + g_tid < per);
+            j += sj;
+            i += si;
+            if (j >= a.W) { j -= a.W; ++i; }
+        }
     }
 }
 
@@ -193,7 +221,7 @@ __device__ __forceinline__ cv_pattern_pair pattern_pair(const ResolveArgs& a, co
 }
 
 // One colour per block of four waves.
-template <bool SYM, bool RAYS>
+template <bool SYM, bool RAYS, bool CELLS>
 __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
     constexpr int BLOCK = 256, NW = BLOCK / 64;
     extern __shared__ double s_dyn[];
@@ -216,7 +244,7 @@ __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
         const ColorConst cc = a.cc[c];
         uint32_t cnt = 0, ng = 0, best = 0;
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
-        resolve_colour<RAYS>(a, ang, cc, tid, BLOCK, a.si, a.sj, lane, s_pb, s_ray, cnt, ng, best, pat);
+        resolve_colour<RAYS, CELLS>(a, ang, cc, tid, BLOCK, a.si, a.sj, lane, s_pb, s_ray, cnt, ng, best, pat);
         uint32_t v[10] = {mult * cnt, mult * ng, wave_max_u32(best)};
 #pragma unroll
         for (int q = 0; q < 7; ++q) v[3 + q] = mult * pat[q];
@@ -260,7 +288,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // One colour per wave, BLOCK / 64 colours per block: no block barrier after
 // the start, each wave with its own pattern keys and per-ray maxima in LDS.
-template <bool SYM, bool RAYS, int BLOCK>
+template <bool SYM, bool RAYS, int BLOCK, bool CELLS>
 __global__ __launch_bounds__(BLOCK) void k_colour_resolve_w(ResolveArgs a) {
     constexpr int NW = BLOCK / 64;
     extern __shared__ double s_dyn[];
@@ -284,8 +312,8 @@ __global__ __launch_bounds__(BLOCK) void k_colour_resolve_w(ResolveArgs a) {
         const ColorConst cc = a.cc[c];
         uint32_t cnt = 0, ng = 0, best = 0;
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
-        resolve_colour<RAYS>(a, ang, cc, (int32_t)lane, 64, a.si64, a.sj64, lane, s_pb, s_ray, cnt, ng,
-                             best, pat);
+        resolve_colour<RAYS, CELLS>(a, ang, cc, (int32_t)lane, 64, a.si64, a.sj64, lane, s_pb, s_ray, cnt,
+                                    ng, best, pat);
         best = wave_max_u32(best);
         wave_lds_sync();
         if (lane == 0 && a.summ) {
@@ -667,14 +695,20 @@ size_t resolve_lds(const ResolveArgs& a, bool rays, int variant) {
     return angle_lds_bytes(a.tab) + per_colour * colours;
 }
 
-template <bool SYM, bool RAYS>
-int launch_resolve_t(cv_context* ctx, const ResolveArgs& a, int variant, hipStream_t s) {
+template <bool SYM, bool RAYS, bool CELLS>
+int launch_resolve_c(cv_context* ctx, const ResolveArgs& a, int variant, hipStream_t s) {
     const size_t lds = resolve_lds(a, RAYS, variant);
     switch (variant) {
-    case 1: return launch_resolve_k(ctx, k_colour_resolve_w<SYM, RAYS, 256>, 256, lds, a, s);
-    case 2: return launch_resolve_k(ctx, k_colour_resolve_w<SYM, RAYS, 512>, 512, lds, a, s);
-    default: return launch_resolve_k(ctx, k_colour_resolve<SYM, RAYS>, 256, lds, a, s);
+    case 1: return launch_resolve_k(ctx, k_colour_resolve_w<SYM, RAYS, 256, CELLS>, 256, lds, a, s);
+    case 2: return launch_resolve_k(ctx, k_colour_resolve_w<SYM, RAYS, 512, CELLS>, 512, lds, a, s);
+    default: return launch_resolve_k(ctx, k_colour_resolve<SYM, RAYS, CELLS>, 256, lds, a, s);
     }
+}
+
+template <bool SYM, bool RAYS>
+int launch_resolve_t(cv_context* ctx, const ResolveArgs& a, int variant, hipStream_t s) {
+    return a.cells ? launch_resolve_c<SYM, RAYS, true>(ctx, a, variant, s)
+                   : launch_resolve_c<SYM, RAYS, false>(ctx, a, variant, s);
 }
 
 // De-duplication: sorted distinct colours, their number (device, also in
@@ -740,6 +774,9 @@ ResolveArgs resolve_args(cv_context* ctx, const GridDev& gd, const RuleDev& rd, 
     a.summ = nullptr;
     a.pbest = nullptr;
     a.rays = nullptr;
+    // gamut cells as in the reduce kernel, with exact FP32 index splits
+    a.cells = ctx->gamut_cells && !rd.clip && a.W >= kCellMinRays && (int64_t)(a.nr + 3) * a.W < (1 << 24) ? 1 : 0;
+    a._pad = 0;
     return a;
 }
 
@@ -876,6 +913,7 @@ int run_frames_resolve(cv_context* ctx, const FramesCall& call_in, bool graph, h
         if (rc != CV_OK) return rc;
     }
     call.variant = resolve_variant(ctx, call.gd, rays);
+    call.cells = ctx->gamut_cells ? 1 : 0;
     if (!graph) {
         if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
         if ((rc = call.enqueue(ctx, s)) != CV_OK) return rc;

@@ -106,7 +106,7 @@ struct FramesCall {
     int64_t* resolved;
     const void* ws[7];  // context workspaces the call uses (a regrown one voids a cached graph)
     int32_t variant;    // per-colour resolve kernel (see resolve_variant)
-    int32_t _pad;
+    int32_t cells;      // gamut cells on in the context when captured
     int enqueue(cv_context* ctx, hipStream_t s) const;
     bool same(const FramesCall& o) const;
 };

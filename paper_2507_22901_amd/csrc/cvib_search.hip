@@ -877,8 +877,6 @@ int launch_pass(cv_context* ctx, const SearchArgs& a, bool emit, bool summ, bool
 // large chunks take 8 waves to share one copy of the angle tables.
 constexpr int kReduceBlock = 512;
 constexpr int kReduceBlockDirect = 256;
-constexpr int32_t kCellMinRays = 128;
-
 // LDS bytes of a tile's open-step masks.
 size_t cell_bytes(const ReduceArgs& a) { return (size_t)(a.block / 64) * a.cell_words * sizeof(uint64_t); }
 constexpr int reduce_block(bool direct) { return direct ? kReduceBlockDirect : kReduceBlock; }

@@ -176,3 +176,32 @@ def test_resolve_variants_and_autotune_agree(cv, nt):
         for k in ("frame_a", "frame_b", "resolved", "pixel_index"):
             assert torch.equal(getattr(o, k), getattr(outs[0], k)), k
     print("tuned variant", v)
+
+
+@pytest.mark.parametrize("nt", [360, 300])
+def test_gamut_cells_change_no_frame_output(cv, nt):
+    """Grids of at least 128 evaluated rays per row skip wave steps proven out
+    of gamut in the per-colour resolve; every kernel variant, eager and
+    captured, gives the bytes of the resolve without them."""
+    f = torch.from_numpy(_frames()).cuda()
+    grid = cv.Grid(0.25, 200, 1.0, nt)
+    rule = cv.Rule(50, 0.5, 0x7F)
+    info = torch.from_numpy(np.random.default_rng(3).integers(0, 8, f.numel() // 3).astype(np.uint8)).cuda()
+    ctx = cv.Context(0)
+    ctx.set_gamut_cells(False)
+    ref = cv.frames_resolve(f, grid, rule, info=info, rays=True, ctx=ctx)
+    outs = []
+    ctx.set_gamut_cells(True)
+    for v in (0, 1, 2):
+        ctx.set_resolve_variant(v)
+        outs.append(cv.frames_resolve(f, grid, rule, info=info, rays=True, ctx=ctx))
+    outs.append(cv.frames_resolve(f, grid, rule, info=info, rays=True, graph=True, ctx=ctx))
+    ctx.set_gamut_cells(False)  # a captured call of the other setting is not replayed
+    outs.append(cv.frames_resolve(f, grid, rule, info=info, rays=True, graph=True, ctx=ctx))
+    torch.cuda.synchronize()
+    n = int(ref.ncolours.item())
+    for o in outs:
+        for k in ("summaries", "pbest", "rays"):
+            assert torch.equal(getattr(o, k)[:n], getattr(ref, k)[:n]), k
+        for k in ("frame_a", "frame_b", "resolved", "pixel_index"):
+            assert torch.equal(getattr(o, k), getattr(ref, k)), k
