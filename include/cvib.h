@@ -283,16 +283,20 @@ int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, cons
  * reset != 0.  Errors: CV_EINVAL (null ctx / outputs, bad phase), CV_EHIP.
  */
 /*
- * Gamut cells.  The reduce-only kernel (cv_pair_reduce, and the count pass of
- * cv_pair_search) first splits each of its tiles into cells of 16 radii by 16
- * rays and proves, by interval arithmetic over the cell in FP64 with a margin
- * of 1e-6 on the linear channels, which cells hold no pair with both colours
- * in gamut; a wave step whose candidates all lie in such cells is not
- * evaluated.  Without the gamut requirement (CV_RULE_CLIP) there are no
- * cells.  Results are identical with the cells on (the default) or off.
+ * Gamut cells.  Before evaluating, the search kernels prove by interval
+ * arithmetic (FP64, with a margin of 1e-6 on the linear channels) which wave
+ * steps of 64 candidates hold no pair with both colours in gamut, and skip
+ * them: the reduce-only kernel (cv_pair_reduce, the count pass of
+ * cv_pair_search), the write pass of cv_pair_search (not with CV_EMIT_ALL),
+ * the multi-rule pass (cv_pair_reduce_rules) and the per-colour resolve (cv_frames_resolve, the exact fallback of the
+ * surrogate calls), which takes its candidates in bands of four rows so that
+ * a step covers 16 rays.  Cells are used when the rule requires the gamut
+ * (not CV_RULE_CLIP) and a row holds at least 128 evaluated rays.  Results
+ * are identical with the cells on (the default) or off.
  * cv_context_set_gamut_cells turns them on or off for later calls.
  * cv_context_skipped returns (host pointer) the number of candidates the
- * cells skipped in the calls made while timing was on, since context creation
+ * cells skipped in the reduce-only kernel (the count pass) in the calls made
+ * while timing was on, since context creation
  * or the last reset (reset != 0 clears it after reading); it synchronises the
  * device.  Errors: CV_EINVAL (null ctx / output), CV_EHIP.
  */

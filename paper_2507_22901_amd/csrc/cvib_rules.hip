@@ -53,7 +53,10 @@ struct RulesArgs {
     uint32_t mult;             // 2 when only half a turn is evaluated
 };
 
-template <bool SYM>
+// With CELLS each wave first decides 64 of its steps at a time (one per lane)
+// and evaluates only those that may hold a pair in gamut; the histogram holds
+// in-gamut candidates only, so skipped steps add nothing to it.
+template <bool SYM, bool CELLS>
 __global__ __launch_bounds__(kRulesBlock) void k_rule_hist(RulesArgs a) {
     extern __shared__ double s_dyn[];
     __shared__ uint32_t s_hist[kMaxBins];
@@ -76,15 +79,9 @@ __global__ __launch_bounds__(kRulesBlock) void k_rule_hist(RulesArgs a) {
         const ColorConst cc = a.cc[c];
         const int32_t begin = lt * a.chunk;
         const int32_t len = min(a.chunk, a.nr * a.W - begin);
-        int32_t i = begin / a.W, j;
-        {
-            int32_t di;
-            divmod_small(begin - i * a.W + tid, a.W, a.inv_W, di, j);
-            i += di;
-        }
+        const int32_t row0 = begin / a.W, jb0 = begin - row0 * a.W;
         const int32_t iters = (len + kRulesBlock - 1) / kRulesBlock;
-        for (int32_t it = 0; it < iters; ++it) {
-            const bool live = it * kRulesBlock + tid < len;
+        auto step = [&](int32_t i, int32_t j, bool live) {
             double sn, co;
             ang.get(j, sn, co);
             const double rr = (double)(i + 1);
@@ -112,9 +109,32 @@ __global__ __launch_bounds__(kRulesBlock) void k_rule_hist(RulesArgs a) {
                     rem &= ~same;
                 }
             }
-            j += a.sj;
-            i += a.si;
-            if (j >= a.W) { j -= a.W; ++i; }
+        };
+        if constexpr (CELLS) {
+            const int32_t wb = tid - (int32_t)lane;  // the wave's first evaluation of a step
+            for (int32_t word = 0; word < (iters + 63) >> 6; ++word) {
+                const int32_t itl = word * 64 + (int32_t)lane, e0 = itl * kRulesBlock + wb;
+                const bool any = itl < iters && e0 < len;
+                uint64_t m = uniform_u64(__ballot(step_open(cc, a.g, ang, a.ra, a.rb, a.W, a.inv_W, row0, jb0,
+                                                            min(e0, len - 1), min(e0 + 63, len - 1), any)));
+                while (m) {
+                    const int32_t e = (word * 64 + (int32_t)__builtin_ctzll(m)) * kRulesBlock + tid;
+                    m &= m - 1ull;
+                    int32_t i, j;
+                    divmod_small(jb0 + min(e, len - 1), a.W, a.inv_W, i, j);
+                    step(i + row0, j, e < len);
+                }
+            }
+        } else {
+            int32_t i, j;
+            divmod_small(jb0 + tid, a.W, a.inv_W, i, j);
+            i += row0;
+            for (int32_t it = 0; it < iters; ++it) {
+                step(i, j, it * kRulesBlock + tid < len);
+                j += a.sj;
+                i += a.si;
+                if (j >= a.W) { j -= a.W; ++i; }
+            }
         }
         __syncthreads();
         uint32_t* dst = a.hist + c * (int64_t)nbins;
@@ -238,7 +258,9 @@ int run_pair_reduce_rules(cv_context* ctx, const uint8_t* rgb, int64_t n, const 
     a.lut = (const uint8_t*)ctx->rtab.ptr;
     a.hist = (uint32_t*)ctx->rhist.ptr;
     a.mult = sym ? 2u : 1u;
-    auto k = sym ? k_rule_hist<true> : k_rule_hist<false>;
+    const bool cells = ctx->gamut_cells && !a.clip && W >= kCellMinRays;
+    auto k = sym ? (cells ? k_rule_hist<true, true> : k_rule_hist<true, false>)
+                 : (cells ? k_rule_hist<false, true> : k_rule_hist<false, false>);
     const size_t lds = angle_lds_bytes(tab);
     hipFuncAttributes fa;
     CV_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k)));

@@ -96,3 +96,14 @@ def test_table2_full_grid_one_pass_equals_twelve(cv):
         summ, _ = cv.pair_reduce(cols, grid, rule)
         s = cv.as_records(summ, cv.SUMMARY_DTYPE)
         assert np.array_equal(counts[:, r], s["per_pattern"].astype(np.int64)), r
+
+
+@pytest.mark.parametrize("grid", [PRESENCE_GRID, (0.5, 120, 1.0, 200)])
+def test_gamut_cells_change_no_rule_count(cv, grid):
+    cols = torch.from_numpy(np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(36, 55)])).cuda()
+    ctx = cv.Context(0)
+    out = []
+    for on in (True, False):
+        ctx.set_gamut_cells(on)
+        out.append(cv.pair_reduce_rules(cols, cv.Grid(*grid), _rules(cv), ctx=ctx))
+    assert torch.equal(out[0], out[1])
