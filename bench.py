@@ -351,14 +351,19 @@ def main():
     ctx = cv.context(0)
     pairs_per_step = len(W.PAPER_COLOUR_ARRAY) * g.per_colour
 
-    # size the survivor buffer once (outside the timed region)
+    # size the survivor buffer once (outside the timed region); every step is
+    # a whole cv_pair_search call (the same output, offset and summary buffers
+    # each time); the captured-graph replay of the call is timed beside it
     first = cv.pair_search(cols, grid, rule, ctx=ctx)
     out = torch.empty((first.total + 1024, 16), dtype=torch.uint8, device="cuda")
+    off = torch.empty(cols.shape[0] + 1, dtype=torch.int64, device="cuda")
+    summ_buf = torch.empty((cols.shape[0], 48), dtype=torch.uint8, device="cuda")
+
+    def step(graph=False):
+        return cv.pair_search(cols, grid, rule, out=out, ctx=ctx, graph=graph, offsets=off, summ_out=summ_buf)
+
     for _ in range(args.warmup):
-        cv.pair_search(cols, grid, rule, out=out, ctx=ctx)
-    ctx.set_timing(True)
-    for ph in (cv.CV_TIME_EVAL, cv.CV_TIME_WRITE, cv.CV_TIME_CALL):
-        ctx.kernel_time(ph, reset=True)
+        step()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -366,11 +371,27 @@ def main():
     start.record()
     res = None
     for _ in range(args.steps):
-        res = cv.pair_search(cols, grid, rule, out=out, ctx=ctx)
+        res = step()
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
     ms = start.elapsed_time(stop)
+    # the same calls replayed from a captured graph, for comparison
+    n_graph = max(3, min(args.steps, 20))
+    step(graph=True)
+    start.record()
+    for _ in range(n_graph):
+        step(graph=True)
+    stop.record()
+    torch.cuda.synchronize()
+    ms_graph = start.elapsed_time(stop) / n_graph
+    # kernel phases from eager calls with the library's HIP events
+    ctx.set_timing(True)
+    for ph in (cv.CV_TIME_EVAL, cv.CV_TIME_WRITE, cv.CV_TIME_CALL):
+        ctx.kernel_time(ph, reset=True)
+    ctx.skipped(reset=True)
+    for _ in range(max(3, min(args.steps, 20))):
+        step(graph=False)
     t_eval, n_eval = ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
     t_write, n_write = ctx.kernel_time(cv.CV_TIME_WRITE, reset=True)
     t_call, n_call = ctx.kernel_time(cv.CV_TIME_CALL, reset=True)
@@ -413,6 +434,7 @@ def main():
         },
         "colours_per_s_exact": len(W.PAPER_COLOUR_ARRAY) / (ms_per_step * 1e-3),
         "wall_s": wall,
+        "ms_per_step_graph": ms_graph,
         "phases_ms": {"eval": k_eval, "write": k_write, "call": t_call / max(n_call, 1)},
         "roofline": {
             "bound": "alu",

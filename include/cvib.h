@@ -144,7 +144,7 @@ typedef struct {
     uint8_t flags;
 } cv_pattern_pair;
 
-/* ---- cv_frames_resolve flags ----------------------------------------- */
+/* ---- cv_frames_resolve and cv_pair_search flags ----------------------- */
 #define CV_GRAPH 0x2u     /* capture the whole call once as a hipGraph (on a */
                           /* stream of the context) and replay it; the graph */
                           /* is rebuilt when any argument changes            */
@@ -187,6 +187,12 @@ int cv_lab_convert(cv_context* ctx, const void* in, void* out, int64_t n, int di
  * is a pure count.  The context's workspace grows with the number of
  * segments (one per row of radius when theta covers the full turn, else one
  * per 512 candidates): 12 bytes each.
+ * With CV_GRAPH everything the call enqueues before the total is read back
+ * is captured once as a hipGraph (on a stream of the context) and replayed by
+ * later calls with the same arguments (pointers, sizes, grid, rule, flags)
+ * and the same context workspaces; anything else captures again.  Results
+ * are those of the eager call; no timing events are recorded inside the
+ * graph.  CV_GRAPH is ignored with CV_PER_RAY.
  * With CV_PER_RAY (not with CV_EMIT_ALL) the records are, for every colour
  * and every ray j < ntheta that has a survivor, the survivor of largest
  * radius index i, in (colour, j) order; offsets and the two-call idiom work

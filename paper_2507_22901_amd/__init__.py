@@ -290,19 +290,29 @@ class SearchResult:
 
 def pair_search(colors: torch.Tensor, grid: Grid, rule: Rule, capacity: int | None = None,
                 summaries: bool = True, emit_all: bool = False, per_ray: bool = False,
-                out: torch.Tensor | None = None, ctx: Context | None = None) -> SearchResult:
+                out: torch.Tensor | None = None, ctx: Context | None = None, graph: bool = False,
+                offsets: torch.Tensor | None = None, summ_out: torch.Tensor | None = None) -> SearchResult:
     """Full search with stream compaction; survivors in (colour, i, j) order
     (per_ray: the largest-radius survivor of each ray, in (colour, j) order).
 
     With capacity None the output grows to fit (one extra search if the first
-    guess is too small)."""
+    guess is too small).  graph: capture the call once as a hipGraph and
+    replay it while the arguments (pointers included: pass out, offsets and
+    summ_out to reuse them) stay the same."""
     colors = _colours(colors)
     ctx = ctx or context(colors.device.index)
     n = colors.shape[0]
     dev = colors.device
-    offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
-    summ = torch.empty((n, 48), dtype=torch.uint8, device=dev) if summaries else None
-    flags = (CV_EMIT_ALL if emit_all else 0) | (CV_PER_RAY if per_ray else 0)
+    if offsets is None:
+        offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    elif offsets.dtype != torch.int64 or offsets.numel() < n + 1 or not offsets.is_cuda:
+        raise ValueError("offsets must be an int64 CUDA tensor of at least n + 1 elements")
+    summ = None
+    if summaries:
+        summ = summ_out if summ_out is not None else torch.empty((n, 48), dtype=torch.uint8, device=dev)
+        if summ.dtype != torch.uint8 or summ.numel() < n * 48 or not summ.is_cuda:
+            raise ValueError("summ_out must be a uint8 CUDA tensor of at least n x 48 bytes")
+    flags = (CV_EMIT_ALL if emit_all else 0) | (CV_PER_RAY if per_ray else 0) | (CV_GRAPH if graph else 0)
     if out is None:
         if capacity is None:
             full = n * grid.per_colour

@@ -210,6 +210,7 @@ int cv_context_destroy(cv_context* ctx) {
     DeviceGuard dg(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->fgraph_exec) (void)hipGraphExecDestroy(ctx->fgraph_exec);
+    if (ctx->sgraph_exec) (void)hipGraphExecDestroy(ctx->sgraph_exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     cvib::Buffer* bufs[] = {&ctx->colors, &ctx->table, &ctx->seg_cnt, &ctx->seg_prefix,
                             &ctx->scan,   &ctx->acc,   &ctx->misc,    &ctx->fbits,
@@ -248,7 +249,7 @@ int cv_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
     if (capacity < 0) return fail(CV_EINVAL, "capacity < 0");
     if (capacity > 0 && !out) return fail(CV_EINVAL, "out is NULL with capacity > 0");
     if (n > 0 && !rgb) return fail(CV_EINVAL, "rgb is NULL");
-    if (flags & ~(uint32_t)(CV_EMIT_ALL | CV_PER_RAY)) return fail(CV_EINVAL, "unknown flags");
+    if (flags & ~(uint32_t)(CV_EMIT_ALL | CV_PER_RAY | CV_GRAPH)) return fail(CV_EINVAL, "unknown flags");
     if ((flags & CV_EMIT_ALL) && (flags & CV_PER_RAY))
         return fail(CV_EINVAL, "CV_EMIT_ALL and CV_PER_RAY exclude each other");
     cvib::GridDev gd;

@@ -112,6 +112,23 @@ struct FramesCall {
 };
 int run_frames_resolve(cv_context* ctx, const FramesCall& call, bool graph, hipStream_t s);
 
+// Everything a cv_pair_search call (not per-ray) depends on: compared
+// bytewise to reuse a captured graph.
+struct SearchCall {
+    const uint8_t* rgb;
+    int64_t n;
+    GridDev gd;
+    RuleDev rd;
+    cv_pair* out;
+    int64_t capacity;
+    int64_t* offsets;
+    cv_color_summary* summ;
+    const void* ws[8];  // context workspaces the call uses
+    uint32_t flags;
+    int32_t cells;
+    bool same(const SearchCall& o) const;
+};
+
 int run_pair_reduce_rules(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
                           const RuleDev* rules, int32_t nrules, uint32_t* counts, hipStream_t s);
 
@@ -184,6 +201,8 @@ struct cv_context {
     std::map<uint64_t, int> resolve_tuned;
     hipStream_t cap_stream = nullptr;        // stream used for graph capture
     hipGraphExec_t fgraph_exec = nullptr;    // captured cv_frames_resolve
+    hipGraphExec_t sgraph_exec = nullptr;    // captured cv_pair_search
+    cvib::SearchCall sgraph_call{};          // the call it was captured for
     cvib::FramesCall fgraph_call{};          // the call it was captured for
     uint64_t* host_misc = nullptr; // pinned mirror of misc for the total
     // kernel timing (cv_context_set_timing): event pairs and totals per phase

@@ -6,6 +6,7 @@
 // with L* fixed; the pairs meeting both conditions are picked out of the
 // candidate array) and Section 3 / Table 1 (a channel bit is 1 when its
 // change is above V_th and 0 when it is under V_th * R_novib).
+#include <cstring>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -1133,34 +1134,65 @@ int run_pair_csr_summary(cv_context* ctx, const cv_pair* recs, const int64_t* of
     return CV_OK;
 }
 
-int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
-                    const RuleDev& rd, cv_pair* out, int64_t capacity, int64_t* offsets,
-                    cv_color_summary* summ, int64_t* total_host, uint32_t flags,
-                    hipStream_t s) {
+namespace {
+
+// Segments of a search: one per row in half-turn mode, else 512 evaluations.
+struct SearchShape {
+    bool sym;
+    int32_t W, seg_len, spc;
+    int64_t per, nsegs;
+};
+
+SearchShape search_shape(int64_t n, const GridDev& gd) {
+    SearchShape h;
+    h.sym = gd.ntheta == gd.N;
+    h.W = h.sym ? gd.N / 2 : gd.ntheta;
+    h.seg_len = h.sym ? h.W : kSegLen;
+    h.per = (int64_t)gd.nr * h.W;
+    h.spc = (int32_t)((h.per + h.seg_len - 1) / h.seg_len);
+    h.nsegs = (int64_t)h.spc * n;
+    return h;
+}
+
+// Every workspace a search call uses, at its full size, before anything is
+// enqueued (so that nothing allocates under graph capture).
+int size_search(cv_context* ctx, int64_t n, const GridDev& gd) {
+    const SearchShape h = search_shape(n, gd);
+    const int64_t nsums = (h.nsegs + kScanChunk - 1) / kScanChunk;
     int rc;
-    if (n > 0 && (flags & CV_PER_RAY))
-        return run_pair_search_per_ray(ctx, rgb, n, gd, rd, out, capacity, offsets, summ, total_host, s);
-    if (n == 0) {
-        if (offsets) hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, offsets, (int64_t)0);
-        CV_HIP(hipGetLastError());
-        *total_host = 0;
-        return CV_OK;
-    }
+    if ((rc = ctx->ensure(ctx->colors, (size_t)n * sizeof(ColorConst))) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->table, (size_t)gd.tab_len * sizeof(double))) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->seg_cnt, (size_t)h.nsegs * 4)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->seg_prefix, (size_t)h.nsegs * 8)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->misc, 64)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->acc, (size_t)n * sizeof(SumAcc))) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->scan, (size_t)(nsums > 0 ? nsums : 1) * 8)) != CV_OK) return rc;
+    return CV_OK;
+}
+
+// The kernels of a search call, in order, on stream s: colour constants and
+// angle table, count pass, scan, write pass, summaries.  The survivor total
+// ends in misc[2].
+int enqueue_search(cv_context* ctx, const SearchCall& c, hipStream_t s) {
+    const uint8_t* rgb = c.rgb;
+    const int64_t n = c.n;
+    const GridDev& gd = c.gd;
+    const RuleDev& rd = c.rd;
+    cv_pair* out = c.out;
+    const int64_t capacity = c.capacity;
+    int64_t* offsets = c.offsets;
+    cv_color_summary* summ = c.summ;
+    const uint32_t flags = c.flags;
+    int rc;
     TabArgs tab;
     if ((rc = prepare_colours(ctx, rgb, n, gd, s, tab)) != CV_OK) return rc;
     // half-turn mode when the grid spans the full turn: one row per segment
-    const bool sym = gd.ntheta == gd.N;
-    const int32_t W = sym ? gd.N / 2 : gd.ntheta;
-    const int32_t seg_len = sym ? W : kSegLen;
-    const int64_t per = (int64_t)gd.nr * W;
-    const int32_t spc = (int32_t)((per + seg_len - 1) / seg_len);
-    const int64_t nsegs = (int64_t)spc * n;
+    const SearchShape h = search_shape(n, gd);
+    const bool sym = h.sym;
+    const int32_t W = h.W, seg_len = h.seg_len, spc = h.spc;
+    const int64_t per = h.per, nsegs = h.nsegs;
     const bool emit = (flags & CV_EMIT_ALL) != 0;
     const ReducePlan pl = plan_reduce(n, per, seg_len);
-    if ((rc = ctx->ensure(ctx->seg_cnt, (size_t)nsegs * 4)) != CV_OK) return rc;
-    if ((rc = ctx->ensure(ctx->seg_prefix, (size_t)nsegs * 8)) != CV_OK) return rc;
-    if ((rc = ctx->ensure(ctx->misc, 64)) != CV_OK) return rc;
-    if ((rc = ctx->ensure(ctx->acc, (size_t)n * sizeof(SumAcc))) != CV_OK) return rc;
     if ((rc = zero_u64(ctx->misc.ptr, 8, s)) != CV_OK) return rc;
     if ((emit || !pl.direct) &&
         (rc = zero_u64(ctx->acc.ptr, n * (int64_t)(sizeof(SumAcc) / 8), s)) != CV_OK)
@@ -1233,6 +1265,75 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
                                (cv_table_row*)nullptr);
             CV_HIP(hipGetLastError());
         }
+    }
+    return CV_OK;
+}
+
+} // namespace
+
+bool SearchCall::same(const SearchCall& o) const { return std::memcmp(this, &o, sizeof(SearchCall)) == 0; }
+
+int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
+                    const RuleDev& rd, cv_pair* out, int64_t capacity, int64_t* offsets,
+                    cv_color_summary* summ, int64_t* total_host, uint32_t flags,
+                    hipStream_t s) {
+    int rc;
+    if (n > 0 && (flags & CV_PER_RAY))
+        return run_pair_search_per_ray(ctx, rgb, n, gd, rd, out, capacity, offsets, summ, total_host, s);
+    if (n == 0) {
+        if (offsets) hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, offsets, (int64_t)0);
+        CV_HIP(hipGetLastError());
+        *total_host = 0;
+        return CV_OK;
+    }
+    if ((rc = size_search(ctx, n, gd)) != CV_OK) return rc;
+    SearchCall call;
+    std::memset(&call, 0, sizeof call);  // bytewise comparison for the graph cache
+    call.rgb = rgb;
+    call.n = n;
+    call.gd = gd;
+    call.rd = rd;
+    call.out = out;
+    call.capacity = capacity;
+    call.offsets = offsets;
+    call.summ = summ;
+    const cvib::Buffer* ws[8] = {&ctx->colors,     &ctx->table, &ctx->seg_cnt, &ctx->seg_prefix,
+                                 &ctx->misc,       &ctx->acc,   &ctx->scan,    &ctx->stats};
+    for (int k = 0; k < 8; ++k) call.ws[k] = ws[k]->ptr;
+    call.flags = flags & (uint32_t)CV_EMIT_ALL;
+    call.cells = ctx->gamut_cells ? 1 : 0;
+    if (!(flags & CV_GRAPH)) {
+        if ((rc = enqueue_search(ctx, call, s)) != CV_OK) return rc;
+    } else {
+        if (!ctx->sgraph_exec || !ctx->sgraph_call.same(call)) {
+            if (ctx->sgraph_exec) {
+                CV_HIP(hipGraphExecDestroy(ctx->sgraph_exec));
+                ctx->sgraph_exec = nullptr;
+            }
+            if (!ctx->cap_stream) CV_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+            const bool timing = ctx->timing;
+            ctx->timing = false;  // no timing events inside a captured graph
+            hipGraph_t g = nullptr;
+            CV_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            rc = enqueue_search(ctx, call, ctx->cap_stream);
+            hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+            ctx->timing = timing;
+            if (rc != CV_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&ctx->sgraph_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                ctx->sgraph_exec = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            ctx->sgraph_call = call;
+        }
+        if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
+        CV_HIP(hipGraphLaunch(ctx->sgraph_exec, s));
+        if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
     }
     CV_HIP(hipMemcpyAsync(ctx->host_misc, ctx->misc.ptr, 3 * sizeof(uint64_t),
                           hipMemcpyDeviceToHost, s));

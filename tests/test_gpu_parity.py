@@ -451,3 +451,35 @@ def test_gamut_cells_change_nothing(cv, case):
         assert skipped == 0
     else:
         assert 0 < skipped < 2 * len(cols) * per
+
+
+# --------------------------------------------------------------------------
+# Captured search: replays equal the eager call; a changed argument captures
+# again; per-ray mode runs eagerly.
+
+def test_search_graph_replays_equal_eager(cv):
+    cols = np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(77, 23)])
+    x = _dev(cols)
+    grid = cv.Grid(0.05, 400, 0.5, 720)
+    ctx = cv.Context(0)
+    n = len(cols)
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    summ = torch.empty((n, 48), dtype=torch.uint8, device="cuda")
+    for rule in (cv.Rule(50, 0.5), cv.Rule(40, 0.25, 0x15)):
+        ref = cv.pair_search(x, grid, rule, ctx=ctx)
+        out = torch.empty((ref.total + 7, 16), dtype=torch.uint8, device="cuda")
+        for rep in range(3):
+            g = cv.pair_search(x, grid, rule, out=out, ctx=ctx, graph=True, offsets=off, summ_out=summ)
+            torch.cuda.synchronize()
+            assert g.total == ref.total, rep
+            assert torch.equal(g.pairs, ref.pairs) and torch.equal(off, ref.offsets), rep
+            assert torch.equal(summ, ref.summaries), rep
+            # eager work between replays
+            cv.pair_search(x[:3], grid, rule, ctx=ctx)
+    # too small an output: the two-call idiom through the graph path
+    small = torch.empty((5, 16), dtype=torch.uint8, device="cuda")
+    with pytest.raises(cv.CvError):
+        cv.pair_search(x, grid, cv.Rule(50, 0.5), capacity=5, out=small, ctx=ctx, graph=True)
+    pr = cv.pair_search(x, grid, cv.Rule(50, 0.5), per_ray=True, ctx=ctx, graph=True)
+    pe = cv.pair_search(x, grid, cv.Rule(50, 0.5), per_ray=True, ctx=ctx)
+    assert pr.total == pe.total and torch.equal(pr.pairs, pe.pairs)
