@@ -238,6 +238,9 @@ constexpr double kCellMargin = 1e-6;
 // a wave step of 64 rays that spans more than half of them rarely lies wholly
 // out of gamut (measured: the 90-ray whole-cube table loses 6% with cells).
 constexpr int32_t kCellMinRays = 128;
+// Band-order steps (16 rays by 4 rows) need 4 W > 64 and pay from about 32
+// rays per row.
+constexpr int32_t kBandMinRays = 32;
 
 __device__ inline bool colour_out(const Geom& g, const ColorConst& cc, double xlo, double xhi, double zlo,
                                   double zhi) {

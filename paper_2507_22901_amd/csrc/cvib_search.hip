@@ -592,7 +592,7 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
         const int32_t jb0 = begin - row0 * a.W;  // ray of the tile's first evaluation
         const int32_t iters = (len + BLOCK - 1) / BLOCK;
         const int32_t nwords = (iters + 63) >> 6;
-        if constexpr (CELLS) {
+        if constexpr (CELLS && !(DIRECT && !SEG)) {
             // Which wave steps hold a candidate that may be in gamut: lane l of
             // a task decides step it = 64 word + l of wave wv, whose 64
             // evaluations (one or two rows, several when W < 64) form the cell.
@@ -659,7 +659,34 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                 }
             }
         };
-        if constexpr (CELLS) {
+        if constexpr (CELLS && DIRECT && !SEG) {
+            // One whole colour, counts and maxima only: the band order (four
+            // rows, ray by ray) gives steps of 16 rays by 4 rows, decided 64
+            // at a time per wave, one per lane.  Skipped = the colour's
+            // candidates less the evaluated ones (unsigned sums cancel).
+            const int32_t per4 = ((a.nr + 3) >> 2) * 4 * a.W;
+            const int32_t iters4 = (per4 + BLOCK - 1) / BLOCK;
+            const float inv_W4 = 0.25f * a.inv_W;
+            const int32_t wb = tid - (int32_t)lane;
+            uint64_t evald = 0;
+            for (int32_t word = 0; word < (iters4 + 63) >> 6; ++word) {
+                const int32_t itl = word * 64 + (int32_t)lane, e0 = itl * BLOCK + wb;
+                const bool any = itl < iters4 && e0 < per4;
+                uint64_t steps = uniform_u64(__ballot(band_step_open(
+                    cc, a.g, ang, a.ra, a.rb, a.W, inv_W4, min(e0, per4 - 1), min(e0 + 63, per4 - 1), any)));
+                while (steps) {
+                    const int32_t e = (word * 64 + (int32_t)__builtin_ctzll(steps)) * BLOCK + tid;
+                    steps &= steps - 1ull;
+                    int32_t band, q;
+                    divmod_small(min(e, per4 - 1), 4 * a.W, inv_W4, band, q);
+                    const int32_t i = 4 * band + (q & 3);
+                    const bool live = e < per4 && i < a.nr;
+                    evald += (uint64_t)__builtin_popcountll(__ballot(live));
+                    step(min(i, a.nr - 1), q >> 2, e, live);
+                }
+            }
+            if (lane == 0) skipped += (w == 0 ? (uint64_t)len : 0ull) - evald;
+        } else if constexpr (CELLS) {
             // the open steps of this wave, (i, j) from the step index
             for (int32_t word = 0; word < nwords; ++word) {
                 uint64_t steps = uniform_u64(s_open[w * a.cell_words + word]);
@@ -883,9 +910,15 @@ size_t cell_bytes(const ReduceArgs& a) { return (size_t)(a.block / 64) * a.cell_
 constexpr int reduce_block(bool direct) { return direct ? kReduceBlockDirect : kReduceBlock; }
 
 template <bool TABLE, bool DIRECT, bool SYM, bool SEG>
-int launch_reduce_t(cv_context* ctx, const ReduceArgs& a, hipStream_t s) {
+int launch_reduce_t(cv_context* ctx, const ReduceArgs& a_in, hipStream_t s) {
     constexpr int B = reduce_block(DIRECT);
-    if (a.block != B) return fail(CV_ESTATE, "internal: reduce block size");
+    if (a_in.block != B) return fail(CV_ESTATE, "internal: reduce block size");
+    ReduceArgs a = a_in;
+    // one-colour tiles without segments take the band order, whose steps
+    // cover 16 rays of 4 rows: worth cells from 32 rays per row
+    if (DIRECT && !SEG && ctx->gamut_cells && !a.rule.clip && a.W >= kBandMinRays &&
+        (int64_t)(a.nr + 3) * a.W < (1 << 24))
+        a.cell_words = 1;
     auto k = a.cell_words > 0 ? k_pair_reduce<B, TABLE, DIRECT, SYM, SEG, true>
                               : k_pair_reduce<B, TABLE, DIRECT, SYM, SEG, false>;
     const size_t lds = angle_lds_bytes(a.tab) + (TABLE ? (size_t)(a.W + 1) / 2 * sizeof(double) : 0) + cell_bytes(a);
