@@ -216,7 +216,8 @@ int cv_context_destroy(cv_context* ctx) {
                             &ctx->scan,   &ctx->acc,   &ctx->misc,    &ctx->fbits,
                             &ctx->fcnt,   &ctx->fprefix, &ctx->fmisc, &ctx->spred,
                             &ctx->sneed,  &ctx->sprefix, &ctx->slist, &ctx->ssumm, &ctx->smisc,
-                            &ctx->rtab,   &ctx->rhist,   &ctx->rays,    &ctx->stats};
+                            &ctx->rtab,   &ctx->rhist,   &ctx->rays,    &ctx->stats,
+                            &ctx->seg_mask};
     for (cvib::Buffer* b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->host_misc) (void)hipHostFree(ctx->host_misc);

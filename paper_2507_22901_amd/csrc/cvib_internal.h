@@ -123,7 +123,7 @@ struct SearchCall {
     int64_t capacity;
     int64_t* offsets;
     cv_color_summary* summ;
-    const void* ws[8];  // context workspaces the call uses
+    const void* ws[9];  // context workspaces the call uses
     uint32_t flags;
     int32_t cells;
     bool same(const SearchCall& o) const;
@@ -174,6 +174,7 @@ struct cv_context {
     cvib::Buffer table;   // angle table
     cvib::Buffer seg_cnt;     // records per search segment
     cvib::Buffer seg_prefix;  // output offset per search segment
+    cvib::Buffer seg_mask;    // passes holding survivors per search segment
     cvib::Buffer scan;        // per-block partial sums of the segment scan
     cvib::Buffer acc;         // per-colour accumulators
     cvib::Buffer misc;        // ticket, -, survivor total

@@ -106,6 +106,7 @@ struct SearchArgs {
     SumAcc* acc;               // nullable
     uint64_t* misc;            // [0] count-pass ticket, [2] survivor total
     int32_t cells, _pad;       // skip wave steps proven out of gamut (not with EMIT_ALL)
+    const uint64_t* seg_mask;  // write pass: the passes of a segment holding survivors (nullable)
 };
 
 // Per-wave flush of a thread's running summary into the colour accumulator.
@@ -242,7 +243,9 @@ __global__ __launch_bounds__(kPassBlock) void k_pair_pass(SearchArgs a) {
         const int32_t iters = (len + 63) >> 6;  // at most 64: a segment is 512 evaluations or a row
         const int32_t i_seg = base_e / a.W, j_seg = base_e - i_seg * a.W;
         uint64_t open_m;
-        if (!EMIT_ALL && a.cells) {
+        if (WRITE && !EMIT_ALL && a.seg_mask) {
+            open_m = uniform_u64(a.seg_mask[sg]);  // the passes holding survivors
+        } else if (!EMIT_ALL && a.cells) {
             // lane l decides pass l; passes proven out of gamut hold no survivor
             const int32_t e0 = (int32_t)lane << 6;
             open_m = uniform_u64(__ballot(step_open(cc, a.g, ang, a.ra, a.rb, a.W, a.inv_W, i_seg, j_seg,
@@ -535,6 +538,10 @@ struct ReduceArgs {
     // 64-bit masks per wave (0 = off)
     int32_t cell_words, _pad;
     uint64_t* stats;          // [0..7]: candidates skipped by the cells, summed (nullable)
+    // SEG: per segment, bit k = survivors among its evaluations 64k..64k+63
+    // (the write pass's k-th pass); mask_slots = segments per tile (nullable)
+    uint64_t* seg_mask;
+    int32_t mask_slots, _pad2;
 };
 
 // Reduce-only search.  A tile is a chunk of one colour's evaluations (i, j < W)
@@ -567,6 +574,7 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
     uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW);
     uint64_t* s_open =
         reinterpret_cast<uint64_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW + (TABLE ? (a.W + 1) / 2 : 0));
+    uint64_t* s_mask = s_open + NW * a.cell_words;  // SEG with seg_mask
     const uint32_t mult = SYM ? 2u : 1u;
     const bool clip = a.rule.clip != 0u;
     uint64_t skipped = 0;  // lane's share over the block's tiles
@@ -578,6 +586,8 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
         }
         if constexpr (SEG) {
             for (int k = tid; k < MAX_SEG; k += BLOCK) s_seg[k] = 0;
+            if (a.seg_mask)
+                for (int k = tid; k < a.mask_slots; k += BLOCK) s_mask[k] = 0;
         }
         __syncthreads();
         const int64_t t = uniform_i64(s_tick);
@@ -647,12 +657,22 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                 // survivors per search segment: split this pass's ballot by
                 // segment (a pass of 64 evaluations touches few segments)
                 if (surv_m != 0ull) {
-                    const int32_t sl = (SYM ? i : (begin + e) / a.seg_len) - seg0;
+                    const int32_t sa = SYM ? i : (begin + e) / a.seg_len;  // segment of the colour
+                    const int32_t sl = sa - seg0;
+                    // the write pass's pass of this evaluation within its segment
+                    const int32_t kb = SYM ? (j >> 6) : ((begin + e - sa * a.seg_len) >> 6);
                     uint64_t rem = surv_m;
                     while (rem) {
                         const int32_t first = __builtin_ctzll(rem);
                         const int32_t sid = __shfl(sl, first, 64);
                         const uint64_t m = __ballot(sl == sid) & rem;
+                        if (a.seg_mask) {
+                            // 64 consecutive evaluations meet at most two passes of a segment,
+                            // and the lanes' passes rise with the lane
+                            const int32_t k0 = __shfl(kb, first, 64), k1 = __shfl(kb, 63 - __builtin_clzll(m), 64);
+                            if (lane == 0)
+                                atomicOr((unsigned long long*)&s_mask[sid], (1ull << k0) | (1ull << k1));
+                        }
                         if (lane == 0) atomicAdd(&s_seg[sid], (uint32_t)__builtin_popcountll(m));
                         rem &= ~m;
                     }
@@ -748,6 +768,10 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
             const int32_t nseg = (len + a.seg_len - 1) / a.seg_len;
             uint32_t* dst = a.seg_cnt + c * (int64_t)a.segs_per_colour + seg0;
             for (int k = tid; k < nseg; k += BLOCK) dst[k] = mult * s_seg[k];
+            if (a.seg_mask) {
+                uint64_t* mdst = a.seg_mask + c * (int64_t)a.segs_per_colour + seg0;
+                for (int k = tid; k < nseg; k += BLOCK) mdst[k] = s_mask[k];
+            }
         }
         if constexpr (DIRECT) {
             if (tid == 0) {
@@ -921,7 +945,8 @@ int launch_reduce_t(cv_context* ctx, const ReduceArgs& a_in, hipStream_t s) {
         a.cell_words = 1;
     auto k = a.cell_words > 0 ? k_pair_reduce<B, TABLE, DIRECT, SYM, SEG, true>
                               : k_pair_reduce<B, TABLE, DIRECT, SYM, SEG, false>;
-    const size_t lds = angle_lds_bytes(a.tab) + (TABLE ? (size_t)(a.W + 1) / 2 * sizeof(double) : 0) + cell_bytes(a);
+    const size_t lds = angle_lds_bytes(a.tab) + (TABLE ? (size_t)(a.W + 1) / 2 * sizeof(double) : 0) + cell_bytes(a) +
+                       (SEG && a.seg_mask ? (size_t)a.mask_slots * sizeof(uint64_t) : 0);
     unsigned grid;
     int rc = persistent_grid(ctx, k, B, lds, a.ntiles, grid);
     if (rc != CV_OK) return rc;
@@ -1025,6 +1050,9 @@ ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, c
                        : 0;
     a._pad = 0;
     a.stats = ctx->timing ? (uint64_t*)ctx->stats.ptr : nullptr;
+    a.seg_mask = nullptr;
+    a.mask_slots = 0;
+    a._pad2 = 0;
     return a;
 }
 
@@ -1197,6 +1225,7 @@ int size_search(cv_context* ctx, int64_t n, const GridDev& gd) {
     if ((rc = ctx->ensure(ctx->table, (size_t)gd.tab_len * sizeof(double))) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->seg_cnt, (size_t)h.nsegs * 4)) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->seg_prefix, (size_t)h.nsegs * 8)) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->seg_mask, (size_t)h.nsegs * 8)) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->misc, 64)) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->acc, (size_t)n * sizeof(SumAcc))) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->scan, (size_t)(nsums > 0 ? nsums : 1) * 8)) != CV_OK) return rc;
@@ -1254,6 +1283,7 @@ int enqueue_search(cv_context* ctx, const SearchCall& c, hipStream_t s) {
     a.misc = (uint64_t*)ctx->misc.ptr;
     a.cells = ctx->gamut_cells && !rd.clip && !emit ? 1 : 0;
     a._pad = 0;
+    a.seg_mask = emit ? nullptr : (const uint64_t*)ctx->seg_mask.ptr;
 
     // Count pass: survivors per segment.  The reduce-only kernel does it
     // (with the summaries); in emit-all mode every candidate is a record and
@@ -1263,6 +1293,8 @@ int enqueue_search(cv_context* ctx, const SearchCall& c, hipStream_t s) {
     ra.seg_cnt = a.seg_cnt;
     ra.seg_len = seg_len;
     ra.segs_per_colour = spc;
+    ra.seg_mask = (uint64_t*)ctx->seg_mask.ptr;
+    ra.mask_slots = (int32_t)((pl.chunk + seg_len - 1) / seg_len);
     if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
     if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
     if (emit) {
@@ -1330,9 +1362,9 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     call.capacity = capacity;
     call.offsets = offsets;
     call.summ = summ;
-    const cvib::Buffer* ws[8] = {&ctx->colors,     &ctx->table, &ctx->seg_cnt, &ctx->seg_prefix,
-                                 &ctx->misc,       &ctx->acc,   &ctx->scan,    &ctx->stats};
-    for (int k = 0; k < 8; ++k) call.ws[k] = ws[k]->ptr;
+    const cvib::Buffer* ws[9] = {&ctx->colors, &ctx->table, &ctx->seg_cnt, &ctx->seg_prefix, &ctx->misc,
+                                 &ctx->acc,    &ctx->scan,  &ctx->stats,   &ctx->seg_mask};
+    for (int k = 0; k < 9; ++k) call.ws[k] = ws[k]->ptr;
     call.flags = flags & (uint32_t)CV_EMIT_ALL;
     call.cells = ctx->gamut_cells ? 1 : 0;
     if (!(flags & CV_GRAPH)) {
