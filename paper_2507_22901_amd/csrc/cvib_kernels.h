@@ -256,22 +256,30 @@ __device__ inline bool colour_out(const Geom& g, const ColorConst& cc, double xl
     return out;
 }
 
-__device__ inline bool cell_out_of_gamut(const ColorConst& cc, const Geom& g, const Angles& ang, double ra,
-                                         double rb, int32_t i0, int32_t i1, int32_t j0, int32_t j1) {
-    double s0, c0, s1, c1;
-    ang.get(j0, s0, c0);
-    ang.get(j1, s1, c1);
+// The same with the end rays' sin and cos given (j0 <= j1 < 2N).
+__device__ inline bool cell_out_of_gamut_ends(const ColorConst& cc, const Geom& g, int32_t N_, double ra,
+                                              double rb, int32_t i0, int32_t i1, int32_t j0, int32_t j1,
+                                              double s0, double c0, double s1, double c1) {
     double slo = fmin(s0, s1), shi = fmax(s0, s1), clo = fmin(c0, c1), chi = fmax(c0, c1);
-    const int64_t N = ang.N, J0 = 4 * (int64_t)j0, J1 = 4 * (int64_t)j1;
-    if (J0 <= N && N <= J1) shi = 1.0;
-    if (J0 <= 2 * N && 2 * N <= J1) clo = -1.0;
-    if (J0 <= 3 * N && 3 * N <= J1) slo = -1.0;
+    const int64_t N = N_, J0 = 4 * (int64_t)j0, J1 = 4 * (int64_t)j1;
+    if ((J0 <= N && N <= J1) || (J0 <= 5 * N && 5 * N <= J1)) shi = 1.0;   // 90, 450 deg
+    if (J0 <= 2 * N && 2 * N <= J1) clo = -1.0;                               // 180 deg
+    if (J0 <= 3 * N && 3 * N <= J1) slo = -1.0;                               // 270 deg
+    if (J0 <= 4 * N && 4 * N <= J1) chi = 1.0;                                // 360 deg
     const double r0 = (double)(i0 + 1), r1 = (double)(i1 + 1);
     const double dxlo = fmin((r0 * ra) * slo, (r1 * ra) * slo), dxhi = fmax((r0 * ra) * shi, (r1 * ra) * shi);
     const double dzlo = fmin((r0 * rb) * clo, (r1 * rb) * clo), dzhi = fmax((r0 * rb) * chi, (r1 * rb) * chi);
     // + colour: (fx0 + dx, fz0 - dz); - colour: (fx0 - dx, fz0 + dz)
     return colour_out(g, cc, cc.fx0 + dxlo, cc.fx0 + dxhi, cc.fz0 - dzhi, cc.fz0 - dzlo) ||
            colour_out(g, cc, cc.fx0 - dxhi, cc.fx0 - dxlo, cc.fz0 + dzlo, cc.fz0 + dzhi);
+}
+
+__device__ inline bool cell_out_of_gamut(const ColorConst& cc, const Geom& g, const Angles& ang, double ra,
+                                         double rb, int32_t i0, int32_t i1, int32_t j0, int32_t j1) {
+    double s0, c0, s1, c1;
+    ang.get(j0, s0, c0);
+    ang.get(j1, s1, c1);
+    return cell_out_of_gamut_ends(cc, g, ang.N, ra, rb, i0, i1, j0, j1, s0, c0, s1, c1);
 }
 
 // Lane masks of the per-channel classification of a wave's candidates:
@@ -328,15 +336,28 @@ __device__ __forceinline__ void divmod_small(int32_t x, int32_t d, float inv_d, 
 // start of the next, or (W < 64) every ray of several rows.  `any` says
 // whether the step exists; e0 and e1 must be valid either way.  Every lane of
 // the wave calls it (the test of a second row runs when any lane needs it).
+// In half-turn mode (sym: W = N/2) ray j of a row is the mirror of ray j + W,
+// so a step that runs into the next row covers, for both rows, the angles
+// from ray ja up to ray W + jb: one test.
 __device__ inline bool step_open(const ColorConst& cc, const Geom& g, const Angles& ang, double ra, double rb,
                                  int32_t W, float inv_W, int32_t row0, int32_t jb0, int32_t e0, int32_t e1,
-                                 bool any) {
+                                 bool any, bool sym = false) {
     int32_t ia, ja, ib, jb;
     divmod_small(jb0 + e0, W, inv_W, ia, ja);
     divmod_small(jb0 + e1, W, inv_W, ib, jb);
     ia += row0;
     ib += row0;
     const bool two = ib == ia + 1, many = ib > ia + 1;
+    if (sym && !many) {
+        double s0, c0, s1, c1;
+        ang.get(ja, s0, c0);
+        ang.get(jb, s1, c1);
+        if (two) {  // ray W + jb: the negated values of ray jb
+            s1 = -s1;
+            c1 = -c1;
+        }
+        return any && !cell_out_of_gamut_ends(cc, g, ang.N, ra, rb, ia, ib, ja, two ? W + jb : jb, s0, c0, s1, c1);
+    }
     bool open = !cell_out_of_gamut(cc, g, ang, ra, rb, ia, many ? ib : ia, many ? 0 : ja, ib > ia ? W - 1 : jb);
     if (__ballot(any && two) != 0ull) {
         const bool o2 = !cell_out_of_gamut(cc, g, ang, ra, rb, ib, ib, 0, jb);

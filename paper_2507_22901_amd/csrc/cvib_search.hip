@@ -589,6 +589,9 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
             if (a.seg_mask)
                 for (int k = tid; k < a.mask_slots; k += BLOCK) s_mask[k] = 0;
         }
+        if constexpr (CELLS && !(DIRECT && !SEG)) {
+            for (int k = tid; k < NW * a.cell_words; k += BLOCK) s_open[k] = 0;
+        }
         __syncthreads();
         const int64_t t = uniform_i64(s_tick);
         if (t >= a.ntiles) break;
@@ -603,20 +606,22 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
         const int32_t iters = (len + BLOCK - 1) / BLOCK;
         const int32_t nwords = (iters + 63) >> 6;
         if constexpr (CELLS && !(DIRECT && !SEG)) {
-            // Which wave steps hold a candidate that may be in gamut: lane l of
-            // a task decides step it = 64 word + l of wave wv, whose 64
-            // evaluations (one or two rows, several when W < 64) form the cell.
-            for (int32_t task = w; task < NW * nwords; task += NW) {
-                const int32_t word = task / NW, wv = task - word * NW;
-                const int32_t it = word * 64 + (int32_t)lane;
+            // Which wave steps hold a candidate that may be in gamut: the
+            // tile's steps (it, wv) are dealt out densely, one per lane; the
+            // 64 evaluations of a step (one or two rows, several when W < 64)
+            // form its cell, and an open step sets its bit in wave wv's mask
+            // (zeroed with the tile's other LDS).
+            for (int32_t s0 = w * 64; s0 < iters * NW; s0 += BLOCK) {
+                const int32_t sidx = s0 + (int32_t)lane;
+                const int32_t it = sidx / NW, wv = sidx - it * NW;
                 const int32_t e0 = it * BLOCK + wv * 64;
-                const bool any = it < iters && e0 < len;
+                const bool any = sidx < iters * NW && e0 < len;
                 const int32_t e1 = min(e0 + 63, len - 1);
                 const bool open = step_open(cc, a.g, ang, a.ra, a.rb, a.W, a.inv_W, row0, jb0, min(e0, len - 1),
-                                            e1, any);
+                                            e1, any, SYM);
                 if (any && !open) skipped += (uint64_t)(e1 - e0 + 1);
-                const uint64_t m = __ballot(open);
-                if (lane == 0) s_open[wv * a.cell_words + word] = m;
+                if (open)
+                    atomicOr((unsigned long long*)&s_open[wv * a.cell_words + (it >> 6)], 1ull << (it & 63));
             }
             __syncthreads();
         }
