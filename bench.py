@@ -107,9 +107,11 @@ def bench_frames(cv, W, torch, steps):
     # one eager call with kernel timing (the resolve kernel's own duration)
     ctx.set_timing(True)
     ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
+    ctx.skipped(reset=True)
     out = cv.frames_resolve(px, grid, rule, info=inf, rays=True, ctx=ctx)
     torch.cuda.synchronize()
     t_res, _ = ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
+    skipped = ctx.skipped(reset=True)
     ctx.set_timing(False)
     cv.frames_resolve(px, grid, rule, info=inf, rays=True, graph=True, out=out, ctx=ctx)
     torch.cuda.synchronize()
@@ -123,7 +125,8 @@ def bench_frames(cv, W, torch, steps):
     n = int(out.ncolours.item())
     summ = cv.as_records(out.summaries[:n], cv.SUMMARY_DTYPE)
     half = g.ntheta * g.dtheta_deg == 360.0
-    evals = n * g.nr * (g.ntheta // 2 if half else g.ntheta)
+    decided = n * g.nr * (g.ntheta // 2 if half else g.ntheta)
+    evals = decided - skipped  # the rest lie in steps proven out of gamut
     gamut = int(summ["n_gamut"].astype(np.int64).sum()) // (2 if half else 1)
     npix = px.shape[0] * px.shape[1] * px.shape[2]
     return {
@@ -133,7 +136,8 @@ def bench_frames(cv, W, torch, steps):
         "pixels_per_s": npix / (ms * 1e-3), "pairs_per_s": n * g.per_colour / (ms * 1e-3),
         "ms_per_call": ms, "calls": steps, "resolved_pixels": int(out.resolved.item()),
         "resolve_kernel_ms": t_res,
-        "roofline": _alu_roofline("k_colour_resolve", t_res, evals, gamut),
+        "roofline": dict(_alu_roofline("k_colour_resolve", t_res, evals, gamut), decided_pairs=decided,
+                         skipped_by_gamut_cells=skipped),
     }
 
 
@@ -269,8 +273,12 @@ def bench_cube(cv, W, torch, steps):
     cols = torch.stack([(ids >> 16) & 255, (ids >> 8) & 255, ids & 255], dim=1).to(torch.uint8)
     del ids
     ctx = cv.context(0)
+    ctx.set_timing(True)
+    ctx.skipped(reset=True)
     summ, tab = cv.pair_reduce(cols, grid, rule, table=True, ctx=ctx)
     torch.cuda.synchronize()
+    skipped = ctx.skipped(reset=True)
+    ctx.set_timing(False)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(steps):
@@ -279,13 +287,15 @@ def bench_cube(cv, W, torch, steps):
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
     ng = int(summ[:, 4:8].contiguous().view(torch.int32).to(torch.int64).sum())
-    evals = (1 << 24) * g.nr * (g.ntheta // 2)
+    decided = (1 << 24) * g.nr * (g.ntheta // 2)
+    evals = decided - skipped  # the rest lie in steps proven out of gamut
     return {
         "workload": "all 2^24 colours; r = 0.25..50 step 0.25 (200) x theta = 0..358 deg step 2 (180)",
         "colours_per_s": (1 << 24) / (ms * 1e-3), "pairs_per_s": (1 << 24) * g.per_colour / (ms * 1e-3),
         "ms_per_call": ms, "calls": steps,
         "feasible_colours": int((tab[:, :4].contiguous().view(torch.int32) > 0).sum()),
-        "roofline_whole_call": _alu_roofline("k_pair_reduce<TABLE> (whole call)", ms, evals, ng // 2),
+        "roofline_whole_call": dict(_alu_roofline("k_pair_reduce<TABLE> (whole call)", ms, evals, ng // 2),
+                                    decided_pairs=decided, skipped_by_gamut_cells=skipped),
     }
 
 

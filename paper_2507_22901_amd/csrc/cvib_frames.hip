@@ -114,7 +114,24 @@ struct ResolveArgs {
     cv_pattern_pair* pbest;   // nullable, [n][7]
     uint16_t* rays;           // nullable, [n][ntheta]
     int32_t cells, _pad;      // skip wave steps proven out of gamut (CELLS kernels)
+    uint64_t* stats;          // [0..7]: candidates skipped by the cells, summed (nullable)
 };
+
+// Per-block sum of the lanes' skipped counts into stats (every thread calls
+// it once, at the end).
+template <int NW>
+__device__ __forceinline__ void add_skipped(uint64_t* stats, uint64_t skipped) {
+    if (!stats) return;
+    __shared__ uint64_t s_skip[NW];
+    for (int o = 32; o > 0; o >>= 1) skipped += (uint64_t)__shfl_xor((unsigned long long)skipped, o, 64);
+    if ((threadIdx.x & 63u) == 0) s_skip[threadIdx.x >> 6] = skipped;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t sum = 0;
+        for (int q = 0; q < NW; ++q) sum += s_skip[q];
+        if (sum) atomicAdd((unsigned long long*)&stats[blockIdx.x & 7u], (unsigned long long)sum);
+    }
+}
 
 // All candidates of one colour, split over a group of g_size threads (a block
 // or one wave): thread g_tid takes evaluations g_tid, g_tid + g_size, ... in
@@ -131,7 +148,7 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
                                                const ColorConst& cc, int32_t g_tid, int32_t g_size,
                                                int32_t si, int32_t sj, uint32_t lane, uint32_t* s_pb,
                                                uint32_t* s_ray, uint32_t& cnt, uint32_t& ng,
-                                               uint32_t& best, uint32_t pat[7]) {
+                                               uint32_t& best, uint32_t pat[7], uint64_t& skipped) {
     const bool clip = a.rule.clip != 0u;
     const int32_t per = a.nr * a.W;
     const int32_t iters = (per + g_size - 1) / g_size;
@@ -171,6 +188,7 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
         const int32_t iters4 = (per4 + g_size - 1) / g_size;
         const float inv_W4 = 0.25f * a.inv_W;
         const int32_t wb = g_tid - (int32_t)lane;  // the wave's first evaluation of a step
+        uint64_t evald = 0;
         for (int32_t word = 0; word < (iters4 + 63) >> 6; ++word) {
             const int32_t itl = word * 64 + (int32_t)lane, e0 = itl * g_size + wb;
             const bool any = itl < iters4 && e0 < per4;
@@ -182,9 +200,13 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
                 int32_t band, q;
                 divmod_small(min(e, per4 - 1), 4 * a.W, inv_W4, band, q);
                 const int32_t i = 4 * band + (q & 3);
-                step(min(i, a.nr - 1), q >> 2, e < per4 && i < a.nr);
+                const bool live = e < per4 && i < a.nr;
+                evald += (uint64_t)__builtin_popcountll(__ballot(live));
+                step(min(i, a.nr - 1), q >> 2, live);
             }
         }
+        // the colour's candidates less those evaluated (unsigned sums cancel)
+        if (lane == 0) skipped += (wb == 0 ? (uint64_t)per : 0ull) - evald;
     } else {
         int32_t i, j;
         divmod_small(g_tid, a.W, a.inv_W, i, j);
@@ -234,6 +256,7 @@ __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
     uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW);
     const uint32_t mult = SYM ? 2u : 1u;
     const int64_t n = (int64_t)*a.n_dev;
+    uint64_t skipped = 0;
 
     for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
         const int64_t c = a.list ? (int64_t)a.list[k] : k;
@@ -244,7 +267,8 @@ __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
         const ColorConst cc = a.cc[c];
         uint32_t cnt = 0, ng = 0, best = 0;
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
-        resolve_colour<RAYS, CELLS>(a, ang, cc, tid, BLOCK, a.si, a.sj, lane, s_pb, s_ray, cnt, ng, best, pat);
+        resolve_colour<RAYS, CELLS>(a, ang, cc, tid, BLOCK, a.si, a.sj, lane, s_pb, s_ray, cnt, ng, best, pat,
+                                    skipped);
         uint32_t v[10] = {mult * cnt, mult * ng, wave_max_u32(best)};
 #pragma unroll
         for (int q = 0; q < 7; ++q) v[3 + q] = mult * pat[q];
@@ -276,6 +300,7 @@ __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
         }
         __syncthreads();
     }
+    add_skipped<NW>(a.stats, skipped);
 }
 
 // LDS written by some lanes of a wave visible to its other lanes: a wave's
@@ -302,6 +327,7 @@ __global__ __launch_bounds__(BLOCK) void k_colour_resolve_w(ResolveArgs a) {
     uint32_t* s_pb = s_pbw[w];
     const uint32_t mult = SYM ? 2u : 1u;
     const int64_t n = (int64_t)*a.n_dev;
+    uint64_t skipped = 0;
 
     for (int64_t k = (int64_t)blockIdx.x * NW + w; k < n; k += (int64_t)gridDim.x * NW) {
         const int64_t c = a.list ? (int64_t)a.list[k] : k;
@@ -313,7 +339,7 @@ __global__ __launch_bounds__(BLOCK) void k_colour_resolve_w(ResolveArgs a) {
         uint32_t cnt = 0, ng = 0, best = 0;
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
         resolve_colour<RAYS, CELLS>(a, ang, cc, (int32_t)lane, 64, a.si64, a.sj64, lane, s_pb, s_ray, cnt,
-                                    ng, best, pat);
+                                    ng, best, pat, skipped);
         best = wave_max_u32(best);
         wave_lds_sync();
         if (lane == 0 && a.summ) {
@@ -332,6 +358,7 @@ __global__ __launch_bounds__(BLOCK) void k_colour_resolve_w(ResolveArgs a) {
         }
         wave_lds_sync();
     }
+    add_skipped<NW>(a.stats, skipped);  // every wave reaches it once its colours are done
 }
 
 // ---------------------------------------------------------------------------
@@ -777,6 +804,7 @@ ResolveArgs resolve_args(cv_context* ctx, const GridDev& gd, const RuleDev& rd, 
     // gamut cells as in the reduce kernel, with exact FP32 index splits
     a.cells = ctx->gamut_cells && !rd.clip && a.W >= kCellMinRays && (int64_t)(a.nr + 3) * a.W < (1 << 24) ? 1 : 0;
     a._pad = 0;
+    a.stats = ctx->timing ? (uint64_t*)ctx->stats.ptr : nullptr;
     return a;
 }
 
