@@ -260,7 +260,13 @@ def bench_table2(cv, W, torch, steps):
     return {"workload": "nine Table 1 colours x twelve Table 1 settings, 324 M candidates each",
             "ms_one_pass": one, "ms_twelve_reductions": twelve, "speedup": twelve / one,
             "candidate_rule_pairs_per_s": 12 * 324e6 / (one * 1e-3),
-            "presence_cells": int(pres.sum())}
+            "presence_cells": int(pres.sum()),
+            # Section 3 of the paper: the same colour / pattern / threshold
+            # combinations searched on a laptop CPU; its r and theta grid is
+            # not given, so these are context, not a like-for-like target
+            "paper_context": {"array_method_s": 62.62, "previous_method_s": 3423.07,
+                              "hardware": "MacBook Pro 13-inch 2019, Intel Core i5-8279U",
+                              "grid": "not stated"}}
 
 
 def bench_cube(cv, W, torch, steps):
