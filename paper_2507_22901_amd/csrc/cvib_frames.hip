@@ -170,10 +170,7 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
             const uint64_t surv_m = accepted_lanes(pm, a.rule.mask) & need_m;
             if (surv_m != 0ull) {
                 cnt += (uint32_t)__builtin_popcountll(surv_m);
-#pragma unroll
-                for (uint32_t p = 1; p <= 7; ++p)
-                    if ((a.rule.mask >> (p - 1u)) & 1u)
-                        pat[p - 1] += (uint32_t)__builtin_popcountll(pattern_lanes(pm, p) & need_m);
+                count_patterns(pm, need_m, pat);
                 if ((surv_m >> lane) & 1ull) {
                     const uint32_t key = best_key(i, j);
                     best = max(best, key);
@@ -271,7 +268,7 @@ __global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
                                     skipped);
         uint32_t v[10] = {mult * cnt, mult * ng, wave_max_u32(best)};
 #pragma unroll
-        for (int q = 0; q < 7; ++q) v[3 + q] = mult * pat[q];
+        for (int q = 0; q < 7; ++q) v[3 + q] = mult * accepted_count(a.rule.mask, q, pat[q]);
         if (lane == 0) {
 #pragma unroll
             for (int q = 0; q < 10; ++q) s_red[w][q] = v[q];
@@ -344,7 +341,7 @@ __global__ __launch_bounds__(BLOCK) void k_colour_resolve_w(ResolveArgs a) {
         wave_lds_sync();
         if (lane == 0 && a.summ) {
             uint32_t pt[7];
-            for (int q = 0; q < 7; ++q) pt[q] = mult * pat[q];
+            for (int q = 0; q < 7; ++q) pt[q] = mult * accepted_count(a.rule.mask, q, pat[q]);
             write_summary(cc, a.g, a.rule, a.tab, a.ra, a.rb, mult * cnt, mult * ng, best, pt, a.summ + c);
         }
         if (lane < 7 && a.pbest) a.pbest[c * 7 + lane] = pattern_pair(a, ang, cc, s_pb[lane], (int)lane);

@@ -307,13 +307,28 @@ __device__ __forceinline__ uint64_t pattern_lanes(const PatMasks& m, uint32_t p)
 }
 
 // Lanes whose pattern the rule accepts.
+// Every lane with a pattern (all channels high or low, one high at least);
+// for a partial mask each lane looks its own pattern up in the mask, so that
+// no per-pattern flag stays live across a loop.
 __device__ __forceinline__ uint64_t accepted_lanes(const PatMasks& m, uint32_t mask) {
-    if ((mask & 0x7Fu) == 0x7Fu)
-        return (m.H[0] | m.L[0]) & (m.H[1] | m.L[1]) & (m.H[2] | m.L[2]) & (m.H[0] | m.H[1] | m.H[2]);
-    uint64_t s = 0;
-    for (uint32_t p = 1; p <= 7; ++p)
-        if ((mask >> (p - 1u)) & 1u) s |= pattern_lanes(m, p);
-    return s;
+    const uint64_t any = (m.H[0] | m.L[0]) & (m.H[1] | m.L[1]) & (m.H[2] | m.L[2]) & (m.H[0] | m.H[1] | m.H[2]);
+    if ((mask & 0x7Fu) == 0x7Fu) return any;
+    const uint32_t lane = lane_id();
+    const uint32_t p = (uint32_t)(((m.H[0] >> lane) & 1ull) << 2 | ((m.H[1] >> lane) & 1ull) << 1 |
+                                  ((m.H[2] >> lane) & 1ull));
+    return any & __ballot(((mask >> ((p - 1u) & 7u)) & 1u) != 0u);
+}
+
+// Lanes of each pattern among `lanes`, added to the wave's counts for every
+// pattern whether the rule accepts it or not: a caller keeps the counts of the
+// accepted patterns only (accepted_counts), outside its loop.
+__device__ __forceinline__ void count_patterns(const PatMasks& m, uint64_t lanes, uint32_t pat[7]) {
+#pragma unroll
+    for (uint32_t p = 1; p <= 7; ++p) pat[p - 1] += (uint32_t)__builtin_popcountll(pattern_lanes(m, p) & lanes);
+}
+
+__device__ __forceinline__ uint32_t accepted_count(uint32_t mask, int q, uint32_t count) {
+    return ((mask >> q) & 1u) ? count : 0u;
 }
 
 // Key of the maximum-amplitude pair: larger i wins, then smaller j.  0 = none.

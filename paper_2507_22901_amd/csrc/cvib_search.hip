@@ -648,10 +648,7 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                 surv_m = accepted_lanes(pm, a.rule.mask) & need_m;
                 if (surv_m != 0ull) {
                     cnt += (uint32_t)__builtin_popcountll(surv_m);
-#pragma unroll
-                    for (uint32_t p = 1; p <= 7; ++p)
-                        if ((a.rule.mask >> (p - 1u)) & 1u)
-                            pat[p - 1] += (uint32_t)__builtin_popcountll(pattern_lanes(pm, p) & need_m);
+                    count_patterns(pm, need_m, pat);
                     if ((surv_m >> lane) & 1ull) {
                         best = max(best, best_key(i, j));
                         if constexpr (TABLE) atomicMax(&s_ray[j], (uint32_t)(i + 1));
@@ -738,10 +735,10 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
             }
         }
 
-        // block reduction: count, n_gamut, best, 7 patterns
+        // block reduction: count, n_gamut, best, 7 patterns (the accepted ones)
         uint32_t v[10] = {mult * cnt, mult * ng, wave_max_u32(best)};
 #pragma unroll
-        for (int q = 0; q < 7; ++q) v[3 + q] = mult * pat[q];
+        for (int q = 0; q < 7; ++q) v[3 + q] = mult * accepted_count(a.rule.mask, q, pat[q]);
         if (lane == 0) {
 #pragma unroll
             for (int q = 0; q < 10; ++q) s_red[w][q] = v[q];
