@@ -240,8 +240,10 @@ __device__ __forceinline__ cv_pattern_pair pattern_pair(const ResolveArgs& a, co
 }
 
 // One colour per block of four waves.
+// Six waves per SIMD: the register budget of 80 keeps one more wave resident
+// than the unbounded allocation (84) would.
 template <bool SYM, bool RAYS, bool CELLS>
-__global__ __launch_bounds__(256) void k_colour_resolve(ResolveArgs a) {
+__global__ __launch_bounds__(256, 6) void k_colour_resolve(ResolveArgs a) {
     constexpr int BLOCK = 256, NW = BLOCK / 64;
     extern __shared__ double s_dyn[];
     __shared__ uint32_t s_red[NW][10];
@@ -504,7 +506,7 @@ struct ProposeArgs {
     uint32_t* need;            // [n]: 1 = exact fallback
 };
 
-__global__ __launch_bounds__(256) void k_propose_verify(ProposeArgs a) {
+__global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
     extern __shared__ double s_tab[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
