@@ -438,12 +438,16 @@ int cv_mlp_load(cv_mlp* m, const char* path);
  * proposal runs through the same arithmetic as the exact search, so a
  * verified pair is one of its survivors; the verified proposal of largest i
  * (then smallest j) is kept.  A local search through the same predicate then
- * raises it: its ray is climbed (the radii above it, 64 at a time, up to 256,
+ * raises it: its ray is climbed (the radii above it, 64 at a time, up to 512,
  * stopping at a block of 64 with no survivor), every ray of every proposed
  * bin is tried at the few radii above the kept one (64 / rays of the bin),
  * and the 16 rays around the kept ray (-8..+7) at the 4 radii above it, up
  * to 4 times; a survivor of larger i replaces the kept pair and its ray is
- * climbed.  The result is never above the exact search's best pair.
+ * climbed.  The bin sweep continues down the ranking through the bins whose
+ * predicted radius comes within 5 Delta E of the kept one.  The result is
+ * never above the exact search's best pair.  Low confidence: unless
+ * CV_NO_FALLBACK is set, a colour whose verified radius is more than 10
+ * Delta E below the largest predicted bin radius goes to the exact search.
  * Colours with a lower logit or with no verified proposal go to the exact
  * search (its maximum-amplitude pair), unless CV_NO_FALLBACK is set.
  */

@@ -435,17 +435,22 @@ __global__ void k_copy_count(const uint64_t* __restrict__ src, int64_t* __restri
 // - the kept pair's ray is climbed;
 // - bin sweep: every ray of every proposed bin at the few radii above the
 //   kept one (64 / rays of the bin, at least one); the survivor of largest
-//   key replaces the kept pair and its ray is climbed;
+//   key replaces the kept pair and its ray is climbed; the sweep goes on down
+//   the ranking through the bins whose predicted radius comes within
+//   kSweepMargin of the kept pair's;
 // - sweep: the 16 rays around the kept pair's ray (-8..+7) at the 4 radii
 //   above it; a survivor replaces the kept pair and its ray is climbed;
 //   repeated up to kSweeps times while it finds one.
-// Colours with a low logit or without a verified proposal go to the exact
-// fallback.  One wave per colour.
+// Colours with a low logit, without a verified proposal, or (with a fallback)
+// whose verified radius lies more than kShortfall below the largest predicted
+// bin radius go to the exact fallback.  One wave per colour.
 
 constexpr int kBins = 36;
 constexpr int kDeltas = 6;
-constexpr int kClimbBlocks = 4;
+constexpr int kClimbBlocks = 8;
 constexpr int kSweeps = 4;
+constexpr float kSweepMargin = 5.0f;  // Delta E
+constexpr float kShortfall = 10.0f;   // Delta E
 __constant__ float kLadder[kDeltas] = {1.0f, 0.0f, -1.0f, -2.5f, -5.0f, -10.0f};
 
 // Exact predicate of candidate (i, j) for one lane; false when not live.
@@ -501,6 +506,7 @@ struct ProposeArgs {
     int32_t nr, ntheta;
     float tau;
     int32_t kbins;
+    int32_t shortfall;         // 1: a verified radius far below the prediction goes to the fallback
     cv_pattern_pair* pairs;    // [n]
     uint8_t* status;           // [n]
     uint32_t* need;            // [n]: 1 = exact fallback
@@ -522,6 +528,7 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
         const float logit = p[kBins];
         const ColorConst cc = a.cc[c];
         uint32_t best = 0;
+        float top_pred = 0.0f;  // the largest predicted bin radius (Delta E)
         if (logit >= a.tau) {
             // rank of every bin by predicted radius (ties: lower bin first)
             int rank = 0;
@@ -530,6 +537,7 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
                 rank += (rq > rk || (rq == rk && q < lane)) ? 1 : 0;
             }
             const int kb = min(a.kbins, nb);
+            top_pred = __shfl(rk, (int)__builtin_ctzll(__ballot(lane < nb && rank == 0)));
             for (int b = 0; b < kb; ++b) {
                 const uint64_t sel = __ballot(lane < nb && rank == b);
                 const int bin = (int)__builtin_ctzll(sel);
@@ -557,9 +565,12 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
             if (best) {
                 best = climb_ray(cc, ang, a.g, a.rule, a.ra, a.rb, a.nr, (int32_t)(0xFFFFu - (best & 0xFFFFu)),
                                  (int32_t)(best >> 16) + 1, best);
-                for (int b = 0; b < kb; ++b) {
+                for (int b = 0; b < nb; ++b) {
                     const uint64_t sel = __ballot(lane < nb && rank == b);
                     const int bin = (int)__builtin_ctzll(sel);
+                    // past the proposed bins, only those whose predicted radius
+                    // comes within kSweepMargin of the kept one (ranks fall)
+                    if (b >= kb && __shfl(rk, bin) + kSweepMargin <= (float)((best >> 16) + 1) * a.dr) break;
                     const int32_t j_lo = (bin * a.tab.N + kBins - 1) / kBins;
                     const int32_t j_hi = min(((bin + 1) * a.tab.N + kBins - 1) / kBins, a.ntheta);
                     const int32_t nrays = j_hi - j_lo;
@@ -594,6 +605,10 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
                 }
             }
         }
+        // low confidence: with the exact search to fall back on, a verified
+        // radius more than kShortfall below the network's largest prediction
+        // is left to it (the network saw a better bin that was not found)
+        if (a.shortfall && best && (float)((best >> 16) + 1) * a.dr < top_pred - kShortfall) best = 0;
         if (lane == 0) {
             cv_pattern_pair r = {};
             if (best) {
@@ -1034,6 +1049,7 @@ int enqueue_surrogate(cv_context* ctx, const SurrogateCall& c, const uint8_t* rg
     p.ntheta = c.gd.ntheta;
     p.tau = c.tau;
     p.kbins = c.kbins;
+    p.shortfall = c.fallback ? 1 : 0;
     p.pairs = c.pairs;
     p.status = c.status;
     p.need = (uint32_t*)ctx->sneed.ptr;

@@ -68,6 +68,14 @@ struct GemmArgs {
 
 constexpr int kDepth = 32, kPitch = 40;
 
+// Network input of an 8-bit code: v * fl(1/255) - 1/2, the product and the
+// difference each rounded to FP32 (never contracted into one FMA), the same
+// in every kernel that converts colours.
+__device__ __forceinline__ float rgb_input(uint32_t v) {
+#pragma clang fp contract(off)
+    return (float)v * (1.0f / 255.0f) - 0.5f;
+}
+
 // A tile of R rows x 32 k of one operand, global -> registers: PER 8-element
 // chunks per thread (R * 4 / 256 of them).  KC: stored [row][k]; else [k][row].
 template <bool KC, int R>
@@ -218,7 +226,7 @@ __global__ __launch_bounds__(256) void k_input_layer(const void* __restrict__ xi
         const int32_t o0 = (int32_t)(t - s * groups) * 32;
         float x[kMaxIn] = {0.f, 0.f, 0.f, 0.f};
         for (int32_t c = 0; c < d0; ++c) {
-            if constexpr (RGB8) x[c] = (float)static_cast<const uint8_t*>(xin)[s * 3 + c] * (1.0f / 255.0f) - 0.5f;
+            if constexpr (RGB8) x[c] = rgb_input(static_cast<const uint8_t*>(xin)[s * 3 + c]);
             else x[c] = static_cast<const float*>(xin)[s * d0 + c];
         }
         bf16* dst = H1 + s * d1 + o0;
@@ -234,6 +242,123 @@ __global__ __launch_bounds__(256) void k_input_layer(const void* __restrict__ xi
             }
             *reinterpret_cast<bf16x8*>(dst + 8 * q) = v;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused inference of the surrogate's shape (inputs <= 4, three hidden layers
+// of 256, outputs <= 64) from 8-bit colours: a block of four waves takes 64
+// rows through every layer with the activations in LDS, so nothing but the
+// colours and the outputs touches HBM (the weights stay in L2).
+//   - input layer: per element on the vector ALUs, as k_input_layer<true>;
+//   - hidden layers: each wave computes 64 rows x 64 columns as 4 x 4 MFMA
+//     tiles, the A fragments from LDS, the B fragments (weights, [n][k]) from
+//     global memory one 32-deep slice ahead; then a barrier, and the
+//     bias + ReLU results overwrite the activations in LDS;
+//   - output layer: wave w computes columns 16w .. 16w + 15.
+// Same instruction, fragment layout, k order and epilogue arithmetic as
+// k_gemm, so the results equal the unfused pass bit for bit.
+constexpr int kFusedRows = 64, kFusedWidth = 256, kFusedPitch = kFusedWidth + 8;
+
+__global__ __launch_bounds__(256) void k_mlp_infer_fused(const uint8_t* __restrict__ rgb, int64_t B, int32_t d0,
+                                                         int32_t dout, const float* __restrict__ W0,
+                                                         const float* __restrict__ b0,
+                                                         const bf16* __restrict__ W1, const float* __restrict__ b1,
+                                                         const bf16* __restrict__ W2, const float* __restrict__ b2,
+                                                         const bf16* __restrict__ W3, const float* __restrict__ b3,
+                                                         float* __restrict__ out) {
+    __shared__ __attribute__((aligned(16))) bf16 sH[kFusedRows * kFusedPitch];
+    __shared__ float s_w0[kFusedWidth * (kMaxIn + 1)];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    for (int k = tid; k < kFusedWidth * d0; k += 256) s_w0[k] = W0[k];
+    for (int k = tid; k < kFusedWidth; k += 256) s_w0[kFusedWidth * d0 + k] = b0[k];
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * kFusedRows;
+    const int32_t rows = (int32_t)min((int64_t)kFusedRows, B - r0);
+    // input layer: thread t -> row t / 4, columns 64 (t % 4) .. + 63
+    {
+        const int row = tid >> 2, c0 = (tid & 3) * 64;
+        float x[kMaxIn] = {0.f, 0.f, 0.f, 0.f};
+        if (row < rows)
+            for (int32_t c = 0; c < d0; ++c) x[c] = rgb_input(rgb[(r0 + row) * 3 + c]);
+        for (int q = 0; q < 8; ++q) {
+            bf16x8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int o = c0 + 8 * q + e;
+                float acc = s_w0[kFusedWidth * d0 + o];
+                for (int32_t c = 0; c < d0; ++c) acc = fmaf(s_w0[o * d0 + c], x[c], acc);
+                v[e] = (bf16)fmaxf(acc, 0.0f);
+            }
+            *reinterpret_cast<bf16x8*>(sH + row * kFusedPitch + c0 + 8 * q) = v;
+        }
+    }
+    __syncthreads();
+    // hidden layers
+    for (int layer = 0; layer < 2; ++layer) {
+        const bf16* Wl = layer == 0 ? W1 : W2;
+        const float* bl = layer == 0 ? b1 : b2;
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        bf16x8 fb[4], fbn[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            fb[j] = *reinterpret_cast<const bf16x8*>(Wl + (int64_t)(64 * w + 16 * j + fr) * kFusedWidth + fk);
+        for (int k0 = 0; k0 < kFusedWidth; k0 += kDepth) {
+            if (k0 + kDepth < kFusedWidth) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    fbn[j] = *reinterpret_cast<const bf16x8*>(Wl + (int64_t)(64 * w + 16 * j + fr) * kFusedWidth +
+                                                              k0 + kDepth + fk);
+            }
+            bf16x8 fa[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                fa[i] = *reinterpret_cast<const bf16x8*>(sH + (16 * i + fr) * kFusedPitch + k0 + fk);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) fb[j] = fbn[j];
+        }
+        __syncthreads();  // every wave has read the layer's input
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int m = 16 * i + (lane >> 4) * 4 + e, n = 64 * w + 16 * j + fr;
+                    sH[m * kFusedPitch + n] = (bf16)fmaxf(acc[i][j][e] + bl[n], 0.0f);
+                }
+        __syncthreads();
+    }
+    // output layer: 64 columns (dout <= 64, rows of W3 padded with zeros)
+    {
+        f32x4 acc[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < kFusedWidth; k0 += kDepth) {
+            const bf16x8 fb = *reinterpret_cast<const bf16x8*>(W3 + (int64_t)(16 * w + fr) * kFusedWidth + k0 + fk);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bf16x8 fa = *reinterpret_cast<const bf16x8*>(sH + (16 * i + fr) * kFusedPitch + k0 + fk);
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = 16 * i + (lane >> 4) * 4 + e, n = 16 * w + fr;
+                if (m < rows && n < dout) out[(r0 + m) * dout + n] = acc[i][e] + b3[n];
+            }
     }
 }
 
@@ -383,9 +508,9 @@ __global__ void k_table_batch(const int32_t* __restrict__ ids, const cv_table_ro
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= B) return;
     const uint32_t id = (uint32_t)ids[s] & 0xFFFFFFu;
-    x[s * 3 + 0] = (float)(id >> 16) * (1.0f / 255.0f) - 0.5f;
-    x[s * 3 + 1] = (float)((id >> 8) & 255u) * (1.0f / 255.0f) - 0.5f;
-    x[s * 3 + 2] = (float)(id & 255u) * (1.0f / 255.0f) - 0.5f;
+    x[s * 3 + 0] = rgb_input(id >> 16);
+    x[s * 3 + 1] = rgb_input((id >> 8) & 255u);
+    x[s * 3 + 2] = rgb_input(id & 255u);
     const cv_table_row& r = table[id];
     for (int k = 0; k < 36; ++k) tr[s * 36 + k] = (float)r.bin_ridx[k] * rscale;
     tf[s] = r.count > 0 ? 1.0f : 0.0f;
@@ -517,11 +642,29 @@ int forward_tail(cv_mlp* m, bf16* const* H, int64_t rows, float* out, hipStream_
     return CV_OK;
 }
 
+// Whether the fused inference kernel takes this network.
+bool fused_shape(const cv_mlp* m) {
+    return m->L == 4 && m->dims[0] <= kMaxIn && m->dims[1] == kFusedWidth && m->dims[2] == kFusedWidth &&
+           m->dims[3] == kFusedWidth && m->dpad[4] == 64;  // 33 to 64 outputs
+}
+
 // Forward pass.  keep: the activations of all rows stay for a backward pass;
-// otherwise rows go through in chunks that reuse the buffers.
+// otherwise rows go through in chunks that reuse the buffers (or, for 8-bit
+// colours and the surrogate's shape, through the fused kernel).
 int run_forward(cv_mlp* m, const void* x, bool rgb8, int64_t rows, float* out, bool keep,
                 hipStream_t s) {
     int rc;
+    if (rgb8 && !keep && fused_shape(m)) {
+        if (rows == 0) return CV_OK;
+        const bf16* W3 = m->wb[3];  // 64 rows, zero beyond dims[4]
+        hipLaunchKernelGGL(k_mlp_infer_fused, dim3((unsigned)((rows + kFusedRows - 1) / kFusedRows)), dim3(256),
+                           0, s, (const uint8_t*)x, rows, m->dims[0], m->dims[4], m->params + m->woff[0],
+                           m->params + m->boff[0], m->wb[1], m->params + m->boff[1], m->wb[2],
+                           m->params + m->boff[2], W3, m->params + m->boff[3], out);
+        CV_HIP(hipGetLastError());
+        m->fwd_rows = -1;
+        return CV_OK;
+    }
     const int64_t chunk = keep ? rows : std::min(rows, kInferChunk);
     if ((rc = ensure_rows(m, chunk)) != CV_OK) return rc;
     for (int64_t r0 = 0; r0 < rows; r0 += chunk) {

@@ -242,3 +242,19 @@ def test_train_steps_equals_single_calls(cv):
     assert torch.equal(losses, torch.cat(manual))
     pa, pb = a.params(), b.params()
     assert torch.max(torch.abs(pa - pb)).item() <= 4 * np.finfo(np.float32).eps * torch.max(torch.abs(pb)).item()
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 70001])
+def test_fused_inference_equals_layer_by_layer(cv, n):
+    """8-bit colours through the surrogate's shape take the fused kernel
+    (activations in LDS); a kept forward and FP32 inputs take the
+    layer-by-layer kernels.  All round at the same points (the input
+    conversion v * fl(1/255) - 1/2 with two roundings, as numpy does it), so
+    the outputs are equal bit for bit."""
+    m, _ = _net(cv, dims=cv.SURROGATE_DIMS, seed=5)
+    rgb = W.random_colours(9, n)
+    a = m.forward(torch.from_numpy(rgb).cuda())
+    k = m.forward(torch.from_numpy(rgb).cuda(), keep=True)
+    x = torch.from_numpy(rgb.astype(np.float32) * np.float32(1.0 / 255.0) - np.float32(0.5)).cuda()
+    b = m.forward(x)
+    assert torch.equal(a, k) and torch.equal(k, b)
