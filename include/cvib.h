@@ -295,8 +295,8 @@ int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, cons
  * them: the reduce-only kernel (cv_pair_reduce, the count pass of
  * cv_pair_search), the write pass of cv_pair_search (not with CV_EMIT_ALL),
  * the multi-rule pass (cv_pair_reduce_rules) and the per-colour resolve (cv_frames_resolve, the exact fallback of the
- * surrogate calls), which takes its candidates in bands of four rows so that
- * a step covers 16 rays.  Cells are used when the rule requires the gamut
+ * surrogate calls), which takes its candidates in bands of 16 rows so that
+ * a step covers 4 rays.  Cells are used when the rule requires the gamut
  * (not CV_RULE_CLIP) and a row holds at least 128 evaluated rays.  Results
  * are identical with the cells on (the default) or off.
  * cv_context_set_gamut_cells turns them on or off for later calls.

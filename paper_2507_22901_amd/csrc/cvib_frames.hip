@@ -139,8 +139,8 @@ __device__ __forceinline__ void add_skipped(uint64_t* stats, uint64_t skipped) {
 // rays.  Wave totals accumulate in cnt, ng and pat (the same value in every
 // lane), the lane's best key in best; survivors raise the pattern's best key
 // in s_pb and, with RAYS, the ray's largest radius in s_ray.  With CELLS
-// ((nr + 3) W < 2^24) the candidates are taken in the band order (bands of
-// four rows, ray by ray; every result here is a count or a maximum, so the
+// ((nr + kBandRows - 1) W < 2^24) the candidates are taken in the band order
+// (bands of kBandRows rows, ray by ray; every result here is a count or a maximum, so the
 // order is free) and each wave first decides 64 of its steps at a time, one
 // per lane, evaluating only those that may hold a pair in gamut.
 template <bool RAYS, bool CELLS>
@@ -181,9 +181,9 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
         }
     };
     if constexpr (CELLS) {
-        const int32_t per4 = ((a.nr + 3) >> 2) * 4 * a.W;  // whole bands
+        const int32_t per4 = ((a.nr + kBandRows - 1) / kBandRows) * kBandRows * a.W;  // whole bands
         const int32_t iters4 = (per4 + g_size - 1) / g_size;
-        const float inv_W4 = 0.25f * a.inv_W;
+        const float inv_W4 = a.inv_W / (float)kBandRows;  // exact: a power of two
         const int32_t wb = g_tid - (int32_t)lane;  // the wave's first evaluation of a step
         uint64_t evald = 0;
         for (int32_t word = 0; word < (iters4 + 63) >> 6; ++word) {
@@ -194,12 +194,11 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
             while (m) {
                 const int32_t e = (word * 64 + (int32_t)__builtin_ctzll(m)) * g_size + g_tid;
                 m &= m - 1ull;
-                int32_t band, q;
-                divmod_small(min(e, per4 - 1), 4 * a.W, inv_W4, band, q);
-                const int32_t i = 4 * band + (q & 3);
+                const BandPos bp = band_pos(min(e, per4 - 1), a.W, inv_W4);
+                const int32_t i = bp.i;
                 const bool live = e < per4 && i < a.nr;
                 evald += (uint64_t)__builtin_popcountll(__ballot(live));
-                step(min(i, a.nr - 1), q >> 2, live);
+                step(min(i, a.nr - 1), bp.j, live);
             }
         }
         // the colour's candidates less those evaluated (unsigned sums cancel)
@@ -816,7 +815,7 @@ ResolveArgs resolve_args(cv_context* ctx, const GridDev& gd, const RuleDev& rd, 
     a.pbest = nullptr;
     a.rays = nullptr;
     // gamut cells as in the reduce kernel, with exact FP32 index splits
-    a.cells = ctx->gamut_cells && !rd.clip && a.W >= kCellMinRays && (int64_t)(a.nr + 3) * a.W < (1 << 24) ? 1 : 0;
+    a.cells = ctx->gamut_cells && !rd.clip && a.W >= kCellMinRays && (int64_t)(a.nr + kBandRows - 1) * a.W < (1 << 24) ? 1 : 0;
     a._pad = 0;
     a.stats = ctx->timing ? (uint64_t*)ctx->stats.ptr : nullptr;
     return a;

@@ -238,7 +238,7 @@ constexpr double kCellMargin = 1e-6;
 // a wave step of 64 rays that spans more than half of them rarely lies wholly
 // out of gamut (measured: the 90-ray whole-cube table loses 6% with cells).
 constexpr int32_t kCellMinRays = 128;
-// Band-order steps (16 rays by 4 rows) need 4 W > 64 and pay from about 32
+// Band-order steps (4 rays by 16 rows) need 16 W > 64 and pay from about 32
 // rays per row.
 constexpr int32_t kBandMinRays = 32;
 
@@ -382,20 +382,35 @@ __device__ inline bool step_open(const ColorConst& cc, const Geom& g, const Angl
 }
 
 // The same for a wave step of the band order: evaluations are numbered by
-// bands of four rows, each band ray by ray and, within a ray, row by row
-// (evaluation E is row 4 (E / 4W) + E % 4, ray (E % 4W) / 4), so that 64
-// consecutive evaluations cover 16 rays of 4 rows.  The step E0..E1 lies in
-// one band or runs into the next one (4W > 64).  Rows past nr are bounded too
+// bands of kBandRows rows, each band ray by ray and, within a ray, row by row
+// (evaluation E is row kBandRows (E / (kBandRows W)) + E % kBandRows, ray
+// (E % (kBandRows W)) / kBandRows), so that 64 consecutive evaluations cover
+// 64 / kBandRows rays of kBandRows rows.  The step E0..E1 lies in one band or
+// runs into the next one (kBandRows W > 64).  Rows past nr are bounded too
 // (they are not live).
+constexpr int32_t kBandRows = 16;
+
+struct BandPos {
+    int32_t i, j;
+};
+
+// Row and ray of band-order evaluation e (< 2^24); inv_WB = 1 / (kBandRows W).
+__device__ __forceinline__ BandPos band_pos(int32_t e, int32_t W, float inv_WB) {
+    int32_t band, q;
+    divmod_small(e, kBandRows * W, inv_WB, band, q);
+    return BandPos{kBandRows * band + (q & (kBandRows - 1)), q / kBandRows};
+}
+
 __device__ inline bool band_step_open(const ColorConst& cc, const Geom& g, const Angles& ang, double ra,
-                                      double rb, int32_t W, float inv_W4, int32_t E0, int32_t E1, bool any) {
+                                      double rb, int32_t W, float inv_WB, int32_t E0, int32_t E1, bool any) {
     int32_t ba, qa, bb, qb;
-    divmod_small(E0, 4 * W, inv_W4, ba, qa);
-    divmod_small(E1, 4 * W, inv_W4, bb, qb);
+    divmod_small(E0, kBandRows * W, inv_WB, ba, qa);
+    divmod_small(E1, kBandRows * W, inv_WB, bb, qb);
     const bool two = bb != ba;
-    bool open = !cell_out_of_gamut(cc, g, ang, ra, rb, 4 * ba, 4 * ba + 3, qa >> 2, two ? W - 1 : qb >> 2);
+    const int32_t R = kBandRows;
+    bool open = !cell_out_of_gamut(cc, g, ang, ra, rb, R * ba, R * ba + R - 1, qa / R, two ? W - 1 : qb / R);
     if (__ballot(any && two) != 0ull) {
-        const bool o2 = !cell_out_of_gamut(cc, g, ang, ra, rb, 4 * bb, 4 * bb + 3, 0, qb >> 2);
+        const bool o2 = !cell_out_of_gamut(cc, g, ang, ra, rb, R * bb, R * bb + R - 1, 0, qb / R);
         open = open || (two && o2);
     }
     return open && any;

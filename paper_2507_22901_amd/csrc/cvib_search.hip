@@ -682,13 +682,13 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
             }
         };
         if constexpr (CELLS && DIRECT && !SEG) {
-            // One whole colour, counts and maxima only: the band order (four
-            // rows, ray by ray) gives steps of 16 rays by 4 rows, decided 64
+            // One whole colour, counts and maxima only: the band order (16
+            // rows, ray by ray) gives steps of 4 rays by 16 rows, decided 64
             // at a time per wave, one per lane.  Skipped = the colour's
             // candidates less the evaluated ones (unsigned sums cancel).
-            const int32_t per4 = ((a.nr + 3) >> 2) * 4 * a.W;
+            const int32_t per4 = ((a.nr + kBandRows - 1) / kBandRows) * kBandRows * a.W;  // whole bands
             const int32_t iters4 = (per4 + BLOCK - 1) / BLOCK;
-            const float inv_W4 = 0.25f * a.inv_W;
+            const float inv_W4 = a.inv_W / (float)kBandRows;  // exact: a power of two
             const int32_t wb = tid - (int32_t)lane;
             uint64_t evald = 0;
             for (int32_t word = 0; word < (iters4 + 63) >> 6; ++word) {
@@ -699,12 +699,11 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                 while (steps) {
                     const int32_t e = (word * 64 + (int32_t)__builtin_ctzll(steps)) * BLOCK + tid;
                     steps &= steps - 1ull;
-                    int32_t band, q;
-                    divmod_small(min(e, per4 - 1), 4 * a.W, inv_W4, band, q);
-                    const int32_t i = 4 * band + (q & 3);
+                    const BandPos bp = band_pos(min(e, per4 - 1), a.W, inv_W4);
+                    const int32_t i = bp.i;
                     const bool live = e < per4 && i < a.nr;
                     evald += (uint64_t)__builtin_popcountll(__ballot(live));
-                    step(min(i, a.nr - 1), q >> 2, e, live);
+                    step(min(i, a.nr - 1), bp.j, e, live);
                 }
             }
             if (lane == 0) skipped += (w == 0 ? (uint64_t)len : 0ull) - evald;
@@ -941,9 +940,9 @@ int launch_reduce_t(cv_context* ctx, const ReduceArgs& a_in, hipStream_t s) {
     if (a_in.block != B) return fail(CV_ESTATE, "internal: reduce block size");
     ReduceArgs a = a_in;
     // one-colour tiles without segments take the band order, whose steps
-    // cover 16 rays of 4 rows: worth cells from 32 rays per row
+    // cover 4 rays of 16 rows: worth cells from 32 rays per row
     if (DIRECT && !SEG && ctx->gamut_cells && !a.rule.clip && a.W >= kBandMinRays &&
-        (int64_t)(a.nr + 3) * a.W < (1 << 24))
+        (int64_t)(a.nr + kBandRows - 1) * a.W < (1 << 24))
         a.cell_words = 1;
     auto k = a.cell_words > 0 ? k_pair_reduce<B, TABLE, DIRECT, SYM, SEG, true>
                               : k_pair_reduce<B, TABLE, DIRECT, SYM, SEG, false>;

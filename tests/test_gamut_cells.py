@@ -13,7 +13,7 @@ mathematical statement:
 - a linear channel A f^-1(fx) + C f^-1(fz) + B is bounded term by term.
 Three properties are checked on several hundred blocks of the shapes the
 kernels use (one or two rows of 64 rays, the mirrored range of a half-turn
-row crossing, 4 rows by 16 rays, several whole rows):
+row crossing, 16 rows by 4 rays, several whole rows):
 - containment: every linear channel of both colours of every candidate
   (FP64 oracle) lies inside the block's intervals -- any narrowing fails it,
   whatever the gamut's shape;
@@ -111,9 +111,9 @@ def _blocks(rng, nr, W_):
         cand = [(r, j) for r in (i, i + 1) for j in list(range(ja, W_)) + list(range(0, jb + 1))]
         out.append(("mirrored", (i, i + 1, ja, W_ + jb), cand))
     for _ in range(40):
-        b = int(rng.integers(0, nr // 4)); j0 = int(rng.integers(0, W_ - 16))
-        out.append(("band", (4 * b, 4 * b + 3, j0, j0 + 15),
-                    [(4 * b + q, j) for q in range(4) for j in range(j0, j0 + 16)]))
+        b = int(rng.integers(0, nr // 16)); j0 = int(rng.integers(0, W_ - 4))
+        out.append(("band", (16 * b, 16 * b + 15, j0, j0 + 3),
+                    [(16 * b + q, j) for q in range(16) for j in range(j0, j0 + 4)]))
     return out
 
 
