@@ -6,6 +6,7 @@
 // with L* fixed; the pairs meeting both conditions are picked out of the
 // candidate array) and Section 3 / Table 1 (a channel bit is 1 when its
 // change is above V_th and 0 when it is under V_th * R_novib).
+#include <algorithm>
 #include <cstring>
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -50,12 +51,9 @@ __global__ void k_lab_to_rgbf(const float* __restrict__ lab, float* __restrict__
 }
 
 // Per-target prologue: RGB8 -> L*a*b* -> the constants of ColorConst.
-__global__ void k_color_prologue(const uint8_t* __restrict__ rgb, ColorConst* __restrict__ cc,
-                                 int64_t n, MatArgs m) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+__device__ __forceinline__ ColorConst color_const(const MatArgs& m, const uint8_t* rgb) {
     double lab[3];
-    rgb8_lab(m, rgb + 3 * k, lab);
+    rgb8_lab(m, rgb, lab);
     double fy = (lab[0] + 16.0) / 116.0;
     double Y = finv(fy) * m.W[1];
     ColorConst c;
@@ -68,23 +66,45 @@ __global__ void k_color_prologue(const uint8_t* __restrict__ rgb, ColorConst* __
     c.a = (float)lab[1];
     c.b = (float)lab[2];
     c._pad = 0;
-    cc[k] = c;
+    return c;
+}
+
+__global__ void k_color_prologue(const uint8_t* __restrict__ rgb, ColorConst* __restrict__ cc,
+                                 int64_t n, MatArgs m) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    cc[k] = color_const(m, rgb + 3 * k);
 }
 
 // Table layout.  N % 4 == 0: tab[k] = sin(2 pi k / N) for 0 <= k <= N/4 (a
 // quarter turn).  N % 4 == 2: tab[k] = sin, tab[H + 1 + k] = cos of
 // 2 pi k / N for 0 <= k <= H = N/2 (a half turn).
-__global__ void k_angle_table(double* __restrict__ tab, int32_t N) {
-    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void angle_entry(double* __restrict__ tab, int32_t N, int64_t k) {
     if (N % 4 == 0) {
-        if (k <= N / 4) tab[k] = sin_turn(k, N);
+        if (k <= N / 4) tab[k] = sin_turn((int32_t)k, N);
     } else {
         const int32_t H = N / 2;
         if (k <= H) {
-            tab[k] = sin_turn(k, N);
-            tab[H + 1 + k] = cos_turn(k, N);
+            tab[k] = sin_turn((int32_t)k, N);
+            tab[H + 1 + k] = cos_turn((int32_t)k, N);
         }
     }
+}
+
+__global__ void k_angle_table(double* __restrict__ tab, int32_t N) {
+    angle_entry(tab, N, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// The search's set-up in one launch: colour constants, the angle table, and
+// zeroed words (the ticket and totals; the per-colour accumulators).
+__global__ void k_search_prologue(const uint8_t* __restrict__ rgb, ColorConst* __restrict__ cc, int64_t n,
+                                  MatArgs m, double* __restrict__ tab, int32_t N, uint64_t* __restrict__ za,
+                                  int64_t na, uint64_t* __restrict__ zb, int64_t nb) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) cc[k] = color_const(m, rgb + 3 * k);
+    angle_entry(tab, N, k);
+    if (k < na) za[k] = 0;
+    if (k < nb) zb[k] = 0;
 }
 
 struct SearchArgs {
@@ -1247,8 +1267,6 @@ int enqueue_search(cv_context* ctx, const SearchCall& c, hipStream_t s) {
     cv_color_summary* summ = c.summ;
     const uint32_t flags = c.flags;
     int rc;
-    TabArgs tab;
-    if ((rc = prepare_colours(ctx, rgb, n, gd, s, tab)) != CV_OK) return rc;
     // half-turn mode when the grid spans the full turn: one row per segment
     const SearchShape h = search_shape(n, gd);
     const bool sym = h.sym;
@@ -1256,10 +1274,21 @@ int enqueue_search(cv_context* ctx, const SearchCall& c, hipStream_t s) {
     const int64_t per = h.per, nsegs = h.nsegs;
     const bool emit = (flags & CV_EMIT_ALL) != 0;
     const ReducePlan pl = plan_reduce(n, per, seg_len);
-    if ((rc = zero_u64(ctx->misc.ptr, 8, s)) != CV_OK) return rc;
-    if ((emit || !pl.direct) &&
-        (rc = zero_u64(ctx->acc.ptr, n * (int64_t)(sizeof(SumAcc) / 8), s)) != CV_OK)
-        return rc;
+    // colour constants, angle table, ticket and totals, accumulators: one launch
+    TabArgs tab;
+    tab.tab = (const double*)ctx->table.ptr;
+    tab.tab_len = gd.tab_len;
+    tab.N = gd.N;
+    tab.dW = direct_rays(gd.ntheta, gd.N, gd.tab_len, (size_t)gd.ntheta * 4);
+    tab._pad = 0;
+    {
+        const int64_t nacc = (emit || !pl.direct) ? n * (int64_t)(sizeof(SumAcc) / 8) : 0;
+        const int64_t threads = std::max<int64_t>(std::max<int64_t>(n, gd.N / 2 + 1), std::max<int64_t>(8, nacc));
+        hipLaunchKernelGGL(k_search_prologue, dim3(blocks_for(threads, 256)), dim3(256), 0, s, rgb,
+                           (ColorConst*)ctx->colors.ptr, n, mat_args(), (double*)ctx->table.ptr, gd.N,
+                           (uint64_t*)ctx->misc.ptr, (int64_t)8, (uint64_t*)ctx->acc.ptr, nacc);
+        CV_HIP(hipGetLastError());
+    }
 
     SearchArgs a;
     a.cc = (const ColorConst*)ctx->colors.ptr;
