@@ -246,10 +246,10 @@ def num_threads() -> int:
 
 def _mlp_bind(L):
     P = C.c_void_p
-    L.orc_mlp_forward.argtypes = [P, C.c_int32, P, P, C.c_int64, P, P]
+    L.orc_mlp_forward.argtypes = [P, C.c_int32, P, P, C.c_int64, P, P, C.c_double]
     L.orc_mlp_loss.argtypes = [P, P, P, C.c_int64, C.c_int32, C.c_double, P]
     L.orc_mlp_loss.restype = C.c_double
-    L.orc_mlp_backward.argtypes = [P, C.c_int32, P, P, C.c_int64, P, P, P, P]
+    L.orc_mlp_backward.argtypes = [P, C.c_int32, P, P, C.c_int64, P, P, P, P, C.c_double]
 
 
 def _flat(dims, Ws, bs):
@@ -258,13 +258,15 @@ def _flat(dims, Ws, bs):
     return np.asarray(dims, dtype=np.int32), W, b
 
 
-def mlp_forward(dims, Ws, bs, x) -> np.ndarray:
+def mlp_forward(dims, Ws, bs, x, omega0: float = 0.0) -> np.ndarray:
     """dims = [d0..dL]; Ws[l] is [d_{l+1}, d_l]; bs[l] is [d_{l+1}]; x is [B, d0].
-    Returns the network output [B, dL] (ReLU hidden layers, linear output)."""
+    Returns the network output [B, dL] (ReLU hidden layers, or sin(omega0 z)
+    on the first when omega0 > 0; linear output)."""
     d, W, b = _flat(dims, Ws, bs)
     x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
     out = np.zeros((x.shape[0], int(d[-1])))
-    lib().orc_mlp_forward(_ptr(d), len(d) - 1, _ptr(W), _ptr(b), x.shape[0], _ptr(x), _ptr(out))
+    lib().orc_mlp_forward(_ptr(d), len(d) - 1, _ptr(W), _ptr(b), x.shape[0], _ptr(x), _ptr(out),
+                          float(omega0))
     return out
 
 
@@ -279,7 +281,7 @@ def mlp_loss(out, target_r, target_f, huber_delta: float):
     return val, g
 
 
-def mlp_backward(dims, Ws, bs, x, gout):
+def mlp_backward(dims, Ws, bs, x, gout, omega0: float = 0.0):
     """Gradients of sum(gout * out) w.r.t. every layer's weights and biases."""
     d, W, b = _flat(dims, Ws, bs)
     nl = len(d) - 1
@@ -288,7 +290,7 @@ def mlp_backward(dims, Ws, bs, x, gout):
     gW = np.zeros_like(W)
     gb = np.zeros_like(b)
     lib().orc_mlp_backward(_ptr(d), nl, _ptr(W), _ptr(b), x.shape[0], _ptr(x), _ptr(gout),
-                           _ptr(gW), _ptr(gb))
+                           _ptr(gW), _ptr(gb), float(omega0))
     gWs, gbs, ow, ob = [], [], 0, 0
     for l in range(nl):
         o, i = int(d[l + 1]), int(d[l])

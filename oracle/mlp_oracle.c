@@ -1,7 +1,11 @@
 /*
  * FP64 oracle for the surrogate network: a plain multilayer perceptron
- * (ReLU on every hidden layer, linear output), its training loss and its
- * gradients by ordinary back-propagation.
+ * (ReLU on every hidden layer, or a sine on the first one, linear output),
+ * its training loss and its gradients by ordinary back-propagation.
+ *
+ * First hidden layer: h = relu(z) when omega0 = 0, else h = sin(omega0 z)
+ * (a sinusoidal layer of fixed frequency omega0, whose derivative is
+ * omega0 cos(omega0 z)); z = W_0 x + b_0.  Every later hidden layer is ReLU.
  *
  * TEST INFRASTRUCTURE ONLY (see cvib_oracle.c).  Shares no code with the HIP
  * kernels.  Layer l maps d_l inputs to d_{l+1} outputs: y = W_l x + b_l with
@@ -31,7 +35,7 @@ static int64_t total_hidden(const int32_t* dims, int32_t nl) {
 /* Forward pass for one sample; h receives the post-ReLU hidden activations of
  * layers 1..nl-1 back to back (size total_hidden). */
 static void forward1(const int32_t* dims, int32_t nl, const double* W, const double* b,
-                     const double* x, double* h, double* out) {
+                     const double* x, double* h, double* out, double omega0) {
     const double* in = x;
     double* hp = h;
     int64_t ow = 0, ob = 0;
@@ -41,7 +45,9 @@ static void forward1(const int32_t* dims, int32_t nl, const double* W, const dou
         for (int32_t o = 0; o < dout; ++o) {
             double acc = b[ob + o];
             for (int32_t k = 0; k < di; ++k) acc += W[ow + (int64_t)o * di + k] * in[k];
-            dst[o] = (l == nl - 1) ? acc : (acc > 0.0 ? acc : 0.0);
+            if (l == nl - 1) dst[o] = acc;
+            else if (l == 0 && omega0 > 0.0) dst[o] = sin(omega0 * acc);
+            else dst[o] = acc > 0.0 ? acc : 0.0;
         }
         ow += (int64_t)dout * di;
         ob += dout;
@@ -53,11 +59,11 @@ static void forward1(const int32_t* dims, int32_t nl, const double* W, const dou
 }
 
 void orc_mlp_forward(const int32_t* dims, int32_t nl, const double* W, const double* b,
-                     int64_t B, const double* x, double* out) {
+                     int64_t B, const double* x, double* out, double omega0) {
     int64_t H = total_hidden(dims, nl);
     double* h = (double*)malloc(sizeof(double) * (size_t)(H > 0 ? H : 1));
     for (int64_t s = 0; s < B; ++s)
-        forward1(dims, nl, W, b, x + s * dims[0], h, out + s * dims[nl]);
+        forward1(dims, nl, W, b, x + s * dims[0], h, out + s * dims[nl], omega0);
     free(h);
 }
 
@@ -89,7 +95,8 @@ double orc_mlp_loss(const double* out, const double* tr, const double* tf, int64
 /* Gradients of sum_s sum_o gout[s][o] * out[s][o] with respect to W and b
  * (accumulated over the batch into gW, gb, which are overwritten). */
 void orc_mlp_backward(const int32_t* dims, int32_t nl, const double* W, const double* b,
-                      int64_t B, const double* x, const double* gout, double* gW, double* gb) {
+                      int64_t B, const double* x, const double* gout, double* gW, double* gb,
+                      double omega0) {
     int64_t nW = 0, nb = 0, H = total_hidden(dims, nl);
     int32_t dmax = 0;
     for (int l = 0; l < nl; ++l) {
@@ -119,7 +126,7 @@ void orc_mlp_backward(const int32_t* dims, int32_t nl, const double* W, const do
     }
     for (int64_t s = 0; s < B; ++s) {
         const double* xs = x + s * dims[0];
-        forward1(dims, nl, W, b, xs, h, out);
+        forward1(dims, nl, W, b, xs, h, out, omega0);
         for (int32_t o = 0; o < dims[nl]; ++o) delta[o] = gout[s * dims[nl] + o];
         for (int l = nl - 1; l >= 0; --l) {
             int32_t di = dims[l], dout = dims[l + 1];
@@ -134,8 +141,16 @@ void orc_mlp_backward(const int32_t* dims, int32_t nl, const double* W, const do
             for (int32_t k = 0; k < di; ++k) {
                 double acc = 0.0;
                 for (int32_t o = 0; o < dout; ++o) acc += W[offW[l] + (int64_t)o * di + k] * delta[o];
-                /* ReLU derivative at the input of this layer (output of l-1) */
-                prev[k] = in[k] > 0.0 ? acc : 0.0;
+                if (l == 1 && omega0 > 0.0) {
+                    /* sine derivative at the first hidden layer: omega0 cos(omega0 z),
+                     * z = W_0 x + b_0 recomputed */
+                    double z = b[k];
+                    for (int32_t c = 0; c < dims[0]; ++c) z += W[(int64_t)k * dims[0] + c] * xs[c];
+                    prev[k] = acc * omega0 * cos(omega0 * z);
+                } else {
+                    /* ReLU derivative at the input of this layer (output of l-1) */
+                    prev[k] = in[k] > 0.0 ? acc : 0.0;
+                }
             }
             memcpy(delta, prev, sizeof(double) * (size_t)di);
         }

@@ -390,11 +390,17 @@ def test_search_reduce_and_eval_agree(oracle):
 # --------------------------------------------------------------------------
 # MLP oracle: gradients by central finite differences (P12).
 
-def test_mlp_gradients_finite_differences(oracle):
+@pytest.mark.parametrize("omega0", [0.0, 30.0])
+def test_mlp_gradients_finite_differences(oracle, omega0):
+    """Back-propagation against central differences of the loss, with ReLU
+    hidden layers (omega0 = 0) and with a sinusoidal first layer."""
     rng = np.random.default_rng(5)
     dims = [3, 8, 8, 8, 37]
     Ws = [rng.normal(0, 0.6, (dims[l + 1], dims[l])) for l in range(4)]
     bs = [rng.normal(0, 0.1, dims[l + 1]) for l in range(4)]
+    if omega0:
+        Ws[0] = rng.uniform(-1 / 3, 1 / 3, Ws[0].shape)
+        bs[0] = rng.uniform(-0.5, 0.5, bs[0].shape)
     B = 5
     x = rng.uniform(-0.5, 0.5, (B, 3))
     tr = np.where(rng.random((B, 36)) < 0.6, rng.uniform(0.05, 1.0, (B, 36)), 0.0)
@@ -402,11 +408,11 @@ def test_mlp_gradients_finite_differences(oracle):
     delta = 0.1
 
     def loss(Ws_, bs_):
-        return oracle.mlp_loss(oracle.mlp_forward(dims, Ws_, bs_, x), tr, tf, delta)[0]
+        return oracle.mlp_loss(oracle.mlp_forward(dims, Ws_, bs_, x, omega0), tr, tf, delta)[0]
 
-    out = oracle.mlp_forward(dims, Ws, bs, x)
+    out = oracle.mlp_forward(dims, Ws, bs, x, omega0)
     val, gout = oracle.mlp_loss(out, tr, tf, delta)
-    gWs, gbs = oracle.mlp_backward(dims, Ws, bs, x, gout)
+    gWs, gbs = oracle.mlp_backward(dims, Ws, bs, x, gout, omega0)
     h = 1e-6
     checked = 0
     for l in range(4):
@@ -437,8 +443,10 @@ def test_mlp_gradients_finite_differences(oracle):
     assert checked == 48 and np.isfinite(val)
 
 
-def test_mlp_forward_matches_matrix_products(oracle):
-    """The forward pass equals relu(W x + b) layer by layer (numpy products)."""
+@pytest.mark.parametrize("omega0", [0.0, 30.0])
+def test_mlp_forward_matches_matrix_products(oracle, omega0):
+    """The forward pass equals relu(W x + b) layer by layer (numpy products),
+    the first layer sin(omega0 (W x + b)) when omega0 > 0."""
     rng = np.random.default_rng(9)
     dims = [3, 16, 16, 5]
     Ws = [rng.normal(0, 1, (dims[l + 1], dims[l])) for l in range(3)]
@@ -447,9 +455,11 @@ def test_mlp_forward_matches_matrix_products(oracle):
     h = x
     for l in range(3):
         h = h @ Ws[l].T + bs[l]
-        if l < 2:
+        if l == 0 and omega0:
+            h = np.sin(omega0 * h)
+        elif l < 2:
             h = np.maximum(h, 0)
-    assert np.allclose(oracle.mlp_forward(dims, Ws, bs, x), h, atol=1e-12)
+    assert np.allclose(oracle.mlp_forward(dims, Ws, bs, x, omega0), h, atol=1e-12)
 
 
 def test_mlp_loss_closed_forms(oracle):
