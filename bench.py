@@ -160,8 +160,7 @@ def bench_surrogate(cv, W, torch, epochs, steps):
     mask = torch.from_numpy(W.cube_split(0))
     ids = torch.arange(1 << 24, dtype=torch.int32)
     tr_ids, te_ids = ids[~mask].cuda(), ids[mask].cuda()
-    m = cv.MLP()
-    m.set_params(cv.init_params(cv.SURROGATE_DIMS, 0))
+    m = cv.surrogate_network(0)
     nsteps, log, t_train = S.train(m, table, tr_ids, gc.dr, epochs=epochs, log_every=500)
     rows = nsteps * 8192
     ev = S.evaluate(m, table, te_ids, gc.dr)

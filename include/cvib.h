@@ -339,8 +339,10 @@ int cv_context_kernel_time(cv_context* ctx, int phase, double* ms_host, int64_t*
 /* ---- Surrogate network ------------------------------------------------
  *
  * A multilayer perceptron dims[0] -> dims[1] -> ... -> dims[nlayers] with
- * ReLU after every layer but the last.  The surrogate of the exact search is
- * 3 -> 256 -> 256 -> 256 -> 37: input RGB / 255 - 1/2, outputs the largest
+ * ReLU after every layer but the last; the first hidden layer may instead be
+ * sinusoidal, sin(omega0 z) (cv_mlp_set_first_sine).  The surrogate of the
+ * exact search is 3 -> 256 -> 256 -> 256 -> 37 with a sinusoidal first layer
+ * (omega0 = 30): input RGB / 255 - 1/2, outputs the largest
  * valid radius of each of the 36 angle bins divided by 50 (the table of
  * cv_pair_reduce) and a feasibility logit.  The paper describes no learned
  * part; the network only proposes pairs that the exact predicate re-checks
@@ -348,7 +350,8 @@ int cv_context_kernel_time(cv_context* ctx, int phase, double* ms_host, int64_t*
  *
  * Arithmetic: the input layer in FP32; every other layer multiplies BF16
  * activations by BF16 copies of the weights with FP32 accumulation, adds the
- * FP32 bias, and rounds hidden activations to BF16 after the ReLU.  The
+ * FP32 bias, and rounds hidden activations to BF16 after the activation.  The
+ * backward pass of a sinusoidal first layer recomputes z in FP32 from x.  The
  * network owns FP32 master weights, their gradients and the Adam moments.
  * Parameters are one flat FP32 array, layer by layer: W_l row-major
  * [dims[l+1]][dims[l]], then b_l [dims[l+1]].  All array arguments are
@@ -366,6 +369,13 @@ typedef struct cv_mlp cv_mlp;
 int cv_mlp_create(cv_context* ctx, const int32_t* dims_host, int32_t nlayers, cv_mlp** out);
 int cv_mlp_destroy(cv_mlp* m);
 int cv_mlp_num_params(const cv_mlp* m, int64_t* n_host);
+
+/* First hidden layer h1 = sin(omega0 (W_0 x + b_0)) for omega0 > 0, ReLU for
+ * omega0 = 0 (the default).  Applies to every later forward and backward
+ * pass; the training step does not change it.  Errors: CV_EINVAL for a
+ * negative or non-finite omega0. */
+int cv_mlp_set_first_sine(cv_mlp* m, float omega0);
+int cv_mlp_first_sine(const cv_mlp* m, float* omega0_host);
 
 /* Copy the flat FP32 parameters in (this also clears the Adam moments) or
  * out, and the gradients of the last cv_mlp_backward out (either output may
@@ -416,10 +426,11 @@ int cv_mlp_train_steps(cv_mlp* m, const int32_t* ids, int64_t n, const cv_table_
 int cv_mlp_table_batch(cv_mlp* m, const int32_t* ids, const cv_table_row* table, int64_t B,
                        double dr, float* x, float* t_r, float* t_f, void* stream);
 
-/* Parameters to / from a file (host path): magic "CVMLP01", int32 nlayers,
- * int32 dims[nlayers+1], int64 count, float params[count], little-endian.
- * Loading requires the same shape and clears the Adam moments.  Both
- * synchronise the device. */
+/* Parameters to / from a file (host path): magic "CVMLP02", int32 nlayers,
+ * int32 dims[nlayers+1], int64 count, float omega0, float params[count],
+ * little-endian.  Loading requires the same shape, takes omega0 from the file
+ * (a "CVMLP01" file has no omega0 field and loads as omega0 = 0) and clears
+ * the Adam moments.  Both synchronise the device. */
 int cv_mlp_save(const cv_mlp* m, const char* path);
 int cv_mlp_load(cv_mlp* m, const char* path);
 

@@ -72,7 +72,8 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_mlp_load",
            "cv_surrogate_infer", "cv_frames_surrogate", "cv_context_set_autotune",
            "cv_context_set_resolve_variant", "cv_context_resolve_variant", "cv_pair_reduce_rules",
-           "cv_pair_reduce_csr", "cv_context_set_gamut_cells", "cv_context_skipped")
+           "cv_pair_reduce_csr", "cv_context_set_gamut_cells", "cv_context_skipped",
+           "cv_mlp_set_first_sine", "cv_mlp_first_sine")
 CV_NO_FALLBACK = 0x4
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
 CV_RESOLVED_SURROGATE, CV_RESOLVED_EXACT, CV_RESOLVED_NONE = 0, 1, 2
@@ -80,6 +81,7 @@ CV_TIME_MLP, CV_TIME_VERIFY = 3, 4
 CV_MLP_KEEP = 0x1
 CV_MLP_RGB8 = 0x2
 SURROGATE_DIMS = (3, 256, 256, 256, 37)
+SURROGATE_OMEGA0 = 30.0   # first hidden layer sin(30 z)
 
 _lib = None
 
@@ -107,6 +109,8 @@ def lib() -> C.CDLL:
         L.cv_mlp_create.argtypes = [P, P, C.c_int32, C.POINTER(C.c_void_p)]
         L.cv_mlp_destroy.argtypes = [P]
         L.cv_mlp_num_params.argtypes = [P, C.POINTER(I64)]
+        L.cv_mlp_set_first_sine.argtypes = [P, C.c_float]
+        L.cv_mlp_first_sine.argtypes = [P, C.POINTER(C.c_float)]
         L.cv_mlp_set_params.argtypes = [P, P, P]
         L.cv_mlp_get_params.argtypes = [P, P, P, P]
         L.cv_mlp_forward.argtypes = [P, P, I64, P, C.c_uint32, P]
@@ -441,13 +445,21 @@ def frames_resolve(pixels: torch.Tensor, grid: Grid, rule: Rule, info: torch.Ten
 # Surrogate network
 
 
-def init_params(dims, seed: int) -> np.ndarray:
+def init_params(dims, seed: int, first_sine: bool = False) -> np.ndarray:
     """He-normal weights (std sqrt(2 / fan_in)) and zero biases, flat FP32 in
     the library's layout (per layer W_l [d_{l+1}][d_l], then b_l), drawn from a
-    Philox stream keyed by `seed`."""
+    Philox stream keyed by `seed`.  With first_sine the first layer (a
+    sinusoidal one) starts uniform instead: W_0 in [-1/d_0, 1/d_0] and b_0 in
+    [-1/sqrt(d_0), 1/sqrt(d_0)], which spreads the phases omega0 z over
+    several periods across the input cube (the SIREN first-layer scheme of
+    Sitzmann et al. 2020)."""
     rng = np.random.Generator(np.random.Philox(key=seed))
     parts = []
     for l in range(len(dims) - 1):
+        if l == 0 and first_sine:
+            parts.append(rng.uniform(-1.0 / dims[0], 1.0 / dims[0], (dims[1], dims[0])).ravel())
+            parts.append(rng.uniform(-dims[0] ** -0.5, dims[0] ** -0.5, dims[1]))
+            continue
         parts.append(rng.normal(0.0, np.sqrt(2.0 / dims[l]), (dims[l + 1], dims[l])).ravel())
         parts.append(np.zeros(dims[l + 1]))
     return np.concatenate(parts).astype(np.float32)
@@ -480,6 +492,16 @@ class MLP:
         _check(lib().cv_mlp_num_params(h, C.byref(n)))
         self.nparams = n.value
         self.device = torch.device("cuda", self.ctx.device)
+
+    def set_first_sine(self, omega0: float):
+        """First hidden layer sin(omega0 z) (omega0 > 0) or ReLU (omega0 = 0)."""
+        _check(lib().cv_mlp_set_first_sine(self.handle, float(omega0)))
+
+    @property
+    def omega0(self) -> float:
+        v = C.c_float(0.0)
+        _check(lib().cv_mlp_first_sine(self.handle, C.byref(v)))
+        return v.value
 
     def set_params(self, flat):
         t = torch.as_tensor(np.asarray(flat, dtype=np.float32) if not torch.is_tensor(flat) else flat)
@@ -571,6 +593,15 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+def surrogate_network(seed: int = 0, ctx: Context | None = None) -> MLP:
+    """The untrained surrogate network: 3 -> 256 -> 256 -> 256 -> 37 with a
+    sinusoidal first layer (omega0 = 30), initialised from `seed`."""
+    m = MLP(SURROGATE_DIMS, ctx)
+    m.set_first_sine(SURROGATE_OMEGA0)
+    m.set_params(init_params(SURROGATE_DIMS, seed, first_sine=True))
+    return m
 
 
 # --------------------------------------------------------------------------

@@ -48,7 +48,7 @@ int32_t pad32(int32_t d) { return (d + 31) / 32 * 32; }
 // MFMA 16x16x32 BF16 operand layout (lane l = 0..63): A row l % 16, k
 // 8 (l / 16) .. + 7; B column l % 16, same k; result rows 4 (l / 16) .. + 3,
 // column l % 16.
-enum { EPI_RELU_BF16 = 0, EPI_BIAS_F32 = 1, EPI_MASK_BF16 = 2, EPI_PARTIAL_F32 = 3 };
+enum { EPI_RELU_BF16 = 0, EPI_BIAS_F32 = 1, EPI_MASK_BF16 = 2, EPI_PARTIAL_F32 = 3, EPI_SINE_BF16 = 4 };
 
 struct GemmArgs {
     const bf16* A;
@@ -64,6 +64,13 @@ struct GemmArgs {
     const bf16* mask;          // ReLU-derivative mask source (post-ReLU activations)
     int64_t ldm;
     int32_t nstore;            // result columns written (<= N)
+    // EPI_SINE_BF16: the derivative omega0 cos(omega0 z) of a sinusoidal first
+    // layer, z = b0 + W0 x recomputed from the FP32 inputs x [M][d0]
+    const float* x0;
+    const float* w0;
+    const float* b0;
+    int32_t d0;
+    float omega0;
 };
 
 constexpr int kDepth = 32, kPitch = 40;
@@ -74,6 +81,13 @@ constexpr int kDepth = 32, kPitch = 40;
 __device__ __forceinline__ float rgb_input(uint32_t v) {
 #pragma clang fp contract(off)
     return (float)v * (1.0f / 255.0f) - 0.5f;
+}
+
+// Activation of the first hidden layer: ReLU, or sin(omega0 z) when omega0 > 0
+// (a sinusoidal layer, which lets the network follow finer detail of its
+// three inputs).  Every later hidden layer is ReLU.
+__device__ __forceinline__ float first_act(float z, float omega0) {
+    return omega0 > 0.0f ? sinf(omega0 * z) : fmaxf(z, 0.0f);
 }
 
 // A tile of R rows x 32 k of one operand, global -> registers: PER 8-element
@@ -178,6 +192,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
                 } else if constexpr (EPI == EPI_MASK_BF16) {
                     const float h = (float)a.mask[(int64_t)m * a.ldm + n];
                     a.cb[(int64_t)m * a.ldc + n] = (bf16)(h > 0.0f ? v : 0.0f);
+                } else if constexpr (EPI == EPI_SINE_BF16) {
+                    float z = a.b0[n];
+                    for (int32_t c = 0; c < a.d0; ++c) z = fmaf(a.w0[n * a.d0 + c], a.x0[(int64_t)m * a.d0 + c], z);
+                    a.cb[(int64_t)m * a.ldc + n] = (bf16)(v * (a.omega0 * cosf(a.omega0 * z)));
                 } else {
                     a.cf[(int64_t)blockIdx.z * a.zstride + (int64_t)m * a.ldc + n] = v;
                 }
@@ -213,7 +231,8 @@ int gemm(const GemmArgs& a, int32_t splits, hipStream_t s) {
 template <bool RGB8>
 __global__ __launch_bounds__(256) void k_input_layer(const void* __restrict__ xin, int64_t B, int32_t d0,
                                                      int32_t d1, const float* __restrict__ W0,
-                                                     const float* __restrict__ b0, bf16* __restrict__ H1) {
+                                                     const float* __restrict__ b0, float omega0,
+                                                     bf16* __restrict__ H1) {
     __shared__ float s_w[kMaxHidden * (kMaxIn + 1)];
     for (int k = threadIdx.x; k < d1 * d0; k += 256) s_w[k] = W0[k];
     for (int k = threadIdx.x; k < d1; k += 256) s_w[d1 * d0 + k] = b0[k];
@@ -238,7 +257,7 @@ __global__ __launch_bounds__(256) void k_input_layer(const void* __restrict__ xi
                 const int32_t o = o0 + 8 * q + e;
                 float acc = s_w[d1 * d0 + o];
                 for (int32_t c = 0; c < d0; ++c) acc = fmaf(s_w[o * d0 + c], x[c], acc);
-                v[e] = (bf16)fmaxf(acc, 0.0f);
+                v[e] = (bf16)first_act(acc, omega0);
             }
             *reinterpret_cast<bf16x8*>(dst + 8 * q) = v;
         }
@@ -262,7 +281,7 @@ constexpr int kFusedRows = 64, kFusedWidth = 256, kFusedPitch = kFusedWidth + 8;
 
 __global__ __launch_bounds__(256) void k_mlp_infer_fused(const uint8_t* __restrict__ rgb, int64_t B, int32_t d0,
                                                          int32_t dout, const float* __restrict__ W0,
-                                                         const float* __restrict__ b0,
+                                                         const float* __restrict__ b0, float omega0,
                                                          const bf16* __restrict__ W1, const float* __restrict__ b1,
                                                          const bf16* __restrict__ W2, const float* __restrict__ b2,
                                                          const bf16* __restrict__ W3, const float* __restrict__ b3,
@@ -289,7 +308,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer_fused(const uint8_t* __restri
                 const int o = c0 + 8 * q + e;
                 float acc = s_w0[kFusedWidth * d0 + o];
                 for (int32_t c = 0; c < d0; ++c) acc = fmaf(s_w0[o * d0 + c], x[c], acc);
-                v[e] = (bf16)fmaxf(acc, 0.0f);
+                v[e] = (bf16)first_act(acc, omega0);
             }
             *reinterpret_cast<bf16x8*>(sH + row * kFusedPitch + c0 + 8 * q) = v;
         }
@@ -536,6 +555,7 @@ struct cv_mlp {
     int32_t L = 0;                      // layers
     int32_t dims[cvib::kMaxLayers + 1] = {};
     int32_t dpad[cvib::kMaxLayers + 1] = {};  // d_l rounded up to 32 (l >= 1)
+    float omega0 = 0.0f;                // > 0: first hidden layer sin(omega0 z), else ReLU
     int64_t woff[cvib::kMaxLayers] = {}, boff[cvib::kMaxLayers] = {};
     int64_t nparam = 0;
     float* params = nullptr;  // FP32 master weights, per layer W_l [d_{l+1}][d_l] then b_l
@@ -659,7 +679,7 @@ int run_forward(cv_mlp* m, const void* x, bool rgb8, int64_t rows, float* out, b
         const bf16* W3 = m->wb[3];  // 64 rows, zero beyond dims[4]
         hipLaunchKernelGGL(k_mlp_infer_fused, dim3((unsigned)((rows + kFusedRows - 1) / kFusedRows)), dim3(256),
                            0, s, (const uint8_t*)x, rows, m->dims[0], m->dims[4], m->params + m->woff[0],
-                           m->params + m->boff[0], m->wb[1], m->params + m->boff[1], m->wb[2],
+                           m->params + m->boff[0], m->omega0, m->wb[1], m->params + m->boff[1], m->wb[2],
                            m->params + m->boff[2], W3, m->params + m->boff[3], out);
         CV_HIP(hipGetLastError());
         m->fwd_rows = -1;
@@ -674,10 +694,10 @@ int run_forward(cv_mlp* m, const void* x, bool rgb8, int64_t rows, float* out, b
         const unsigned ib = blocks(nr * (m->dims[1] / 32), 256);
         if (rgb8)
             hipLaunchKernelGGL(k_input_layer<true>, dim3(ib), dim3(256), 0, s, xs, nr, m->dims[0],
-                               m->dims[1], m->params + m->woff[0], m->params + m->boff[0], m->h[1]);
+                               m->dims[1], m->params + m->woff[0], m->params + m->boff[0], m->omega0, m->h[1]);
         else
             hipLaunchKernelGGL(k_input_layer<false>, dim3(ib), dim3(256), 0, s, xs, nr, m->dims[0],
-                               m->dims[1], m->params + m->woff[0], m->params + m->boff[0], m->h[1]);
+                               m->dims[1], m->params + m->woff[0], m->params + m->boff[0], m->omega0, m->h[1]);
         CV_HIP(hipGetLastError());
         if ((rc = forward_tail(m, m->h, nr, out + r0 * m->dims[m->L], s)) != CV_OK) return rc;
     }
@@ -746,7 +766,17 @@ int run_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, hipStr
         d.mask = m->h[l];
         d.ldm = din;
         d.nstore = din;
-        if ((rc = gemm<true, false, EPI_MASK_BF16>(d, 1, s)) != CV_OK) return rc;
+        if (l == 1 && m->omega0 > 0.0f) {
+            d.x0 = x;
+            d.w0 = m->params + m->woff[0];
+            d.b0 = m->params + m->boff[0];
+            d.d0 = m->dims[0];
+            d.omega0 = m->omega0;
+            rc = gemm<true, false, EPI_SINE_BF16>(d, 1, s);
+        } else {
+            rc = gemm<true, false, EPI_MASK_BF16>(d, 1, s);
+        }
+        if (rc != CV_OK) return rc;
         std::swap(Gc, Gn);
         ldg = din;
     }
@@ -814,7 +844,10 @@ void free_mlp(cv_mlp* m) {
     delete m;
 }
 
-const char kMagic[8] = {'C', 'V', 'M', 'L', 'P', '0', '1', '\0'};
+// File tags: version 02 adds the first layer's omega0 (a float after the
+// parameter count); a version 01 file is a ReLU network (omega0 = 0).
+const char kMagic[8] = {'C', 'V', 'M', 'L', 'P', '0', '2', '\0'};
+const char kMagic01[8] = {'C', 'V', 'M', 'L', 'P', '0', '1', '\0'};
 
 } // namespace
 
@@ -895,6 +928,23 @@ int cv_mlp_destroy(cv_mlp* m) {
     DeviceGuard dg(m->device);
     (void)hipDeviceSynchronize();
     cvib::free_mlp(m);
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_mlp_set_first_sine(cv_mlp* m, float omega0) {
+    CV_GUARD_BEGIN
+    if (!m) return fail(CV_EINVAL, "null network");
+    if (!std::isfinite(omega0) || omega0 < 0.0f) return fail(CV_EINVAL, "omega0 must be finite and >= 0");
+    m->omega0 = omega0;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_mlp_first_sine(const cv_mlp* m, float* omega0_host) {
+    CV_GUARD_BEGIN
+    if (!m || !omega0_host) return fail(CV_EINVAL, "null argument");
+    *omega0_host = m->omega0;
     return CV_OK;
     CV_GUARD_END
 }
@@ -1050,7 +1100,7 @@ int cv_mlp_save(const cv_mlp* m, const char* path) {
     const int64_t n = m->nparam;
     bool ok = fwrite(cvib::kMagic, 1, 8, f) == 8 && fwrite(&L, 4, 1, f) == 1 &&
               fwrite(m->dims, 4, (size_t)L + 1, f) == (size_t)L + 1 && fwrite(&n, 8, 1, f) == 1 &&
-              fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+              fwrite(&m->omega0, 4, 1, f) == 1 && fwrite(buf.data(), 1, buf.size(), f) == buf.size();
     ok = (fclose(f) == 0) && ok;
     return ok ? CV_OK : fail(CV_EINVAL, std::string("write failed: ") + path);
     CV_GUARD_END
@@ -1064,10 +1114,13 @@ int cv_mlp_load(cv_mlp* m, const char* path) {
     char magic[8];
     int32_t L = 0, dims[cvib::kMaxLayers + 1];
     int64_t n = 0;
-    bool ok = fread(magic, 1, 8, f) == 8 && std::memcmp(magic, cvib::kMagic, 8) == 0 &&
-              fread(&L, 4, 1, f) == 1 && L == m->L && fread(dims, 4, (size_t)L + 1, f) == (size_t)L + 1 &&
-              std::memcmp(dims, m->dims, sizeof(int32_t) * ((size_t)L + 1)) == 0 &&
-              fread(&n, 8, 1, f) == 1 && n == m->nparam;
+    float omega0 = 0.0f;
+    bool ok = fread(magic, 1, 8, f) == 8;
+    const bool v02 = ok && std::memcmp(magic, cvib::kMagic, 8) == 0;
+    ok = ok && (v02 || std::memcmp(magic, cvib::kMagic01, 8) == 0) && fread(&L, 4, 1, f) == 1 &&
+         L == m->L && fread(dims, 4, (size_t)L + 1, f) == (size_t)L + 1 &&
+         std::memcmp(dims, m->dims, sizeof(int32_t) * ((size_t)L + 1)) == 0 && fread(&n, 8, 1, f) == 1 &&
+         n == m->nparam && (!v02 || fread(&omega0, 4, 1, f) == 1) && std::isfinite(omega0) && omega0 >= 0.0f;
     std::string buf;
     if (ok) {
         buf.resize((size_t)n * sizeof(float));
@@ -1080,6 +1133,7 @@ int cv_mlp_load(cv_mlp* m, const char* path) {
     CV_HIP(hipMemcpy(m->params, buf.data(), buf.size(), hipMemcpyHostToDevice));
     CV_HIP(hipMemset(m->adam_m, 0, buf.size()));
     CV_HIP(hipMemset(m->adam_v, 0, buf.size()));
+    m->omega0 = omega0;
     int rc = cvib::refresh_bf16(m, nullptr);
     if (rc != CV_OK) return rc;
     CV_HIP(hipDeviceSynchronize());

@@ -193,6 +193,8 @@ def test_mlp_argument_validation(cv):
     assert L.cv_adam_step(None, 1e-3, 0.9, 0.999, 1e-8, 1, None) == cv.CV_EINVAL
     assert L.cv_mlp_save(None, b"/tmp/x") == cv.CV_EINVAL
     assert L.cv_mlp_load(None, b"/tmp/x") == cv.CV_EINVAL
+    assert L.cv_mlp_set_first_sine(None, 30.0) == cv.CV_EINVAL
+    assert L.cv_mlp_first_sine(None, None) == cv.CV_EINVAL
 
 
 def test_init_params_layout(cv):
@@ -203,6 +205,12 @@ def test_init_params_layout(cv):
     assert [w.shape for w in Ws] == [(256, 3), (256, 256), (256, 256), (37, 256)]
     assert all(np.all(b == 0) for b in bs)
     assert abs(Ws[1].std() - np.sqrt(2 / 256)) < 0.01
+    # a sinusoidal first layer starts uniform; the other layers as before
+    fs = cv.init_params(dims, 0, first_sine=True)
+    Ws2, bs2 = cv.split_params(fs, dims)
+    assert np.all(np.abs(Ws2[0]) <= 1 / 3) and Ws2[0].std() > 0.15
+    assert np.all(np.abs(bs2[0]) <= 3 ** -0.5) and bs2[0].std() > 0.25
+    assert abs(Ws2[1].std() - np.sqrt(2 / 256)) < 0.01 and all(np.all(b == 0) for b in bs2[1:])
 
 
 def test_resolve_variant_validation(cv):

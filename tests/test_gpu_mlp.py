@@ -3,7 +3,8 @@ save / load and a short training run.
 
 Two references: the FP64 oracle, given the same BF16-rounded weights, and a
 plain PyTorch FP32 CPU emulation that rounds at the same points as the
-kernels (hidden activations and back-propagated gradients to BF16).
+kernels (hidden activations and back-propagated gradients to BF16).  Both
+the ReLU first layer and the sinusoidal one (omega0 = 30) are checked.
 
 Bars (norm-wise relative error):
 - forward: 2e-2 against the oracle, 2e-3 against the emulation;
@@ -51,12 +52,13 @@ def oracle_weights(cv, flat, dims):
     return Ws, [b.astype(np.float64) for b in bs]
 
 
-def emulate(cv, flat, dims, x, gout=None):
+def emulate(cv, flat, dims, x, gout=None, omega0=0.0):
     """FP32 forward (and backward) rounding where the kernels round."""
     Ws, bs = cv.split_params(torch.from_numpy(flat), dims)
     L = len(dims) - 1
     x = torch.as_tensor(x, dtype=torch.float32)
-    H = [None, bf(torch.relu(x @ Ws[0].T + bs[0]))]
+    z1 = x @ Ws[0].T + bs[0]
+    H = [None, bf(torch.sin(omega0 * z1) if omega0 > 0 else torch.relu(z1))]
     for l in range(1, L - 1):
         H.append(bf(torch.relu(H[l] @ bf(Ws[l]).T + bs[l])))
     out = H[L - 1] @ bf(Ws[L - 1]).T + bs[L - 1]
@@ -67,20 +69,24 @@ def emulate(cv, flat, dims, x, gout=None):
     for l in range(L - 1, 0, -1):
         gW[l] = G.T @ H[l]
         gb[l] = G.sum(0)
-        G = bf((G @ bf(Ws[l])) * (H[l] > 0))
+        deriv = omega0 * torch.cos(omega0 * z1) if (l == 1 and omega0 > 0) else (H[l] > 0)
+        G = bf((G @ bf(Ws[l])) * deriv)
     gW[0] = G.T @ x
     gb[0] = G.sum(0)
     return out, (gW, gb)
 
 
-def _net(cv, dims=DIMS, seed=0):
+def _net(cv, dims=DIMS, seed=0, omega0=0.0):
     m = cv.MLP(dims)
-    flat = cv.init_params(dims, seed)
-    # non-zero biases so that the bias paths are exercised
+    m.set_first_sine(omega0)
+    flat = cv.init_params(dims, seed, first_sine=omega0 > 0)
+    # non-zero biases so that the bias paths are exercised (a sinusoidal
+    # first layer already starts with them)
     Ws, bs = cv.split_params(flat, dims)
     rng = np.random.default_rng(seed + 100)
-    for b in bs:
-        b[:] = rng.normal(0, 0.05, b.shape)
+    for l, b in enumerate(bs):
+        if l > 0 or omega0 == 0:
+            b[:] = rng.normal(0, 0.05, b.shape)
     m.set_params(flat)
     return m, flat
 
@@ -93,15 +99,16 @@ def _batch(B, seed):
     return x, tr, tf
 
 
+@pytest.mark.parametrize("omega0", [0.0, 30.0])
 @pytest.mark.parametrize("B", [1, 300, 1100])
-def test_forward_matches_references(cv, oracle, B):
-    m, flat = _net(cv)
+def test_forward_matches_references(cv, oracle, B, omega0):
+    m, flat = _net(cv, omega0=omega0)
     x, _, _ = _batch(B, 1)
     out = m.forward(torch.from_numpy(x).cuda()).cpu().numpy()
     Ws, bs = oracle_weights(cv, flat, DIMS)
-    ref = oracle.mlp_forward(list(DIMS), Ws, bs, x.astype(np.float64))
+    ref = oracle.mlp_forward(list(DIMS), Ws, bs, x.astype(np.float64), omega0=omega0)
     assert rel(out, ref) < 2e-2
-    emu, _ = emulate(cv, flat, DIMS, x)
+    emu, _ = emulate(cv, flat, DIMS, x, omega0=omega0)
     assert rel(out, emu.numpy()) < 2e-3
     # kept and chunked forward agree bitwise
     out2 = m.forward(torch.from_numpy(x).cuda(), keep=True).cpu().numpy()
@@ -132,9 +139,10 @@ def test_loss_matches_oracle(cv, oracle):
     assert np.max(np.abs(gout.cpu().numpy() - g)) <= 1e-6 * np.max(np.abs(g))
 
 
+@pytest.mark.parametrize("omega0", [0.0, 30.0])
 @pytest.mark.parametrize("B", [64, 300, 1100])
-def test_backward_matches_references(cv, oracle, B):
-    m, flat = _net(cv, seed=B)
+def test_backward_matches_references(cv, oracle, B, omega0):
+    m, flat = _net(cv, seed=B, omega0=omega0)
     x, tr, tf = _batch(B, B + 1)
     xd = torch.from_numpy(x).cuda()
     out = m.forward(xd, keep=True)
@@ -144,8 +152,8 @@ def test_backward_matches_references(cv, oracle, B):
     gWs, gbs = cv.split_params(grads, DIMS)
     Ws, bs = oracle_weights(cv, flat, DIMS)
     o_gW, o_gb = oracle.mlp_backward(list(DIMS), Ws, bs, x.astype(np.float64),
-                                     gout.cpu().numpy().astype(np.float64))
-    _, (e_gW, e_gb) = emulate(cv, flat, DIMS, x, gout.cpu())
+                                     gout.cpu().numpy().astype(np.float64), omega0=omega0)
+    _, (e_gW, e_gb) = emulate(cv, flat, DIMS, x, gout.cpu(), omega0=omega0)
     for l in range(len(DIMS) - 1):
         assert rel(gWs[l], e_gW[l].numpy()) < 2e-3, ("W emu", l)
         assert rel(gbs[l], e_gb[l].numpy()) < 2e-3, ("b emu", l)
@@ -191,17 +199,34 @@ def test_adam_matches_oracle(cv, oracle):
 
 
 def test_save_load_roundtrip(cv, tmp_path):
-    m, flat = _net(cv, seed=5)
+    m, flat = _net(cv, seed=5, omega0=30.0)
     path = str(tmp_path / "net.cvmlp")
     m.save(path)
     m2 = cv.MLP(DIMS)
     m2.load(path)
+    assert m2.omega0 == 30.0
     assert torch.equal(m.params(), m2.params())
     x = torch.from_numpy(_batch(100, 6)[0]).cuda()
     assert torch.equal(m.forward(x), m2.forward(x))
     m3 = cv.MLP((3, 32, 37))
     with pytest.raises(cv.CvError):
         m3.load(path)
+    # a file in the earlier format (tag CVMLP01, no omega0 field) is a ReLU
+    # network
+    raw = open(path, "rb").read()
+    hdr = 8 + 4 + 4 * len(DIMS) + 8
+    assert raw[:8] == b"CVMLP02\0"
+    old = tmp_path / "net01.cvmlp"
+    old.write_bytes(b"CVMLP01\0" + raw[8:hdr] + raw[hdr + 4:])
+    m2.load(str(old))
+    assert m2.omega0 == 0.0
+    assert torch.equal(m.params(), m2.params())
+    m.set_first_sine(0.0)
+    assert torch.equal(m.forward(x), m2.forward(x))
+    with pytest.raises(cv.CvError):
+        m.set_first_sine(-1.0)
+    with pytest.raises(cv.CvError):
+        m.set_first_sine(float("nan"))
 
 
 def test_backward_needs_kept_forward(cv):
@@ -244,14 +269,15 @@ def test_train_steps_equals_single_calls(cv):
     assert torch.max(torch.abs(pa - pb)).item() <= 4 * np.finfo(np.float32).eps * torch.max(torch.abs(pb)).item()
 
 
+@pytest.mark.parametrize("omega0", [0.0, 30.0])
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 70001])
-def test_fused_inference_equals_layer_by_layer(cv, n):
+def test_fused_inference_equals_layer_by_layer(cv, n, omega0):
     """8-bit colours through the surrogate's shape take the fused kernel
     (activations in LDS); a kept forward and FP32 inputs take the
     layer-by-layer kernels.  All round at the same points (the input
     conversion v * fl(1/255) - 1/2 with two roundings, as numpy does it), so
     the outputs are equal bit for bit."""
-    m, _ = _net(cv, dims=cv.SURROGATE_DIMS, seed=5)
+    m, _ = _net(cv, dims=cv.SURROGATE_DIMS, seed=5, omega0=omega0)
     rgb = W.random_colours(9, n)
     a = m.forward(torch.from_numpy(rgb).cuda())
     k = m.forward(torch.from_numpy(rgb).cuda(), keep=True)

@@ -30,8 +30,7 @@ def trained(cv):
     test_mask = torch.from_numpy(W.cube_split(0))
     ids = torch.arange(1 << 24, dtype=torch.int32)
     train_ids = ids[~test_mask].cuda()
-    m = cv.MLP()
-    m.set_params(cv.init_params(cv.SURROGATE_DIMS, 0))
+    m = cv.surrogate_network(0)
     steps, log, secs = S.train(m, table, train_ids, g.dr, epochs=1.0, log_every=100)
     return {"mlp": m, "table": table, "log": log, "test_ids": ids[test_mask].cuda(), "S": S}
 
@@ -155,8 +154,7 @@ def test_trained_network_gains(cv, trained):
     network."""
     cols = torch.from_numpy(_colours()).cuda()
     grid, rule = cv.Grid(*W.GRID_FRAMES.astuple()), cv.Rule(*W.DEFAULT_RULE)
-    raw = cv.MLP()
-    raw.set_params(cv.init_params(cv.SURROGATE_DIMS, 0))
+    raw = cv.surrogate_network(0)
     out = {}
     for name, m in (("trained", trained["mlp"]), ("untrained", raw)):
         r = cv.surrogate_infer(cols, m, grid, rule, tau=0.0, fallback=False)
