@@ -426,6 +426,14 @@ int cv_mlp_train_steps(cv_mlp* m, const int32_t* ids, int64_t n, const cv_table_
 int cv_mlp_table_batch(cv_mlp* m, const int32_t* ids, const cv_table_row* table, int64_t B,
                        double dr, float* x, float* t_r, float* t_f, void* stream);
 
+/* Training order: out[i] = in[pi(i)] for a keyed pseudorandom permutation pi
+ * of [0, n) (a four-round Feistel network on the smallest even bit width
+ * that holds n, cycle-walked into [0, n); Black and Rogaway 2002).  The same
+ * key gives the same order on every device.  in and out are device int32
+ * arrays of n entries that must not overlap; n <= 2^31.  Asynchronous.
+ * Errors: CV_EINVAL. */
+int cv_permute_ids(cv_context* ctx, const int32_t* in, int64_t n, uint64_t key, int32_t* out, void* stream);
+
 /* Parameters to / from a file (host path): magic "CVMLP02", int32 nlayers,
  * int32 dims[nlayers+1], int64 count, float omega0, float params[count],
  * little-endian.  Loading requires the same shape, takes omega0 from the file

@@ -73,7 +73,7 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_surrogate_infer", "cv_frames_surrogate", "cv_context_set_autotune",
            "cv_context_set_resolve_variant", "cv_context_resolve_variant", "cv_pair_reduce_rules",
            "cv_pair_reduce_csr", "cv_context_set_gamut_cells", "cv_context_skipped",
-           "cv_mlp_set_first_sine", "cv_mlp_first_sine")
+           "cv_mlp_set_first_sine", "cv_mlp_first_sine", "cv_permute_ids")
 CV_NO_FALLBACK = 0x4
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
 CV_RESOLVED_SURROGATE, CV_RESOLVED_EXACT, CV_RESOLVED_NONE = 0, 1, 2
@@ -111,6 +111,7 @@ def lib() -> C.CDLL:
         L.cv_mlp_num_params.argtypes = [P, C.POINTER(I64)]
         L.cv_mlp_set_first_sine.argtypes = [P, C.c_float]
         L.cv_mlp_first_sine.argtypes = [P, C.POINTER(C.c_float)]
+        L.cv_permute_ids.argtypes = [P, P, I64, C.c_uint64, P, P]
         L.cv_mlp_set_params.argtypes = [P, P, P]
         L.cv_mlp_get_params.argtypes = [P, P, P, P]
         L.cv_mlp_forward.argtypes = [P, P, I64, P, C.c_uint32, P]
@@ -593,6 +594,20 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+def permute_ids(ids: torch.Tensor, key: int, out: torch.Tensor | None = None,
+                ctx: Context | None = None) -> torch.Tensor:
+    """ids (int32 on the GPU) in a keyed pseudorandom order (cv_permute_ids)."""
+    ctx = ctx or context()
+    if not ids.is_cuda or ids.dtype != torch.int32 or ids.dim() != 1:
+        raise ValueError("ids must be a 1-D int32 CUDA tensor")
+    ids = ids.contiguous()
+    if out is None:
+        out = torch.empty_like(ids)
+    _check(lib().cv_permute_ids(ctx.handle, _dptr(ids), ids.shape[0], int(key) & (2 ** 64 - 1), _dptr(out),
+                                _stream()))
+    return out
 
 
 def surrogate_network(seed: int = 0, ctx: Context | None = None) -> MLP:

@@ -32,7 +32,7 @@ constexpr int kMaxLayers = 8;
 constexpr int kMaxIn = 4;          // input width handled by the vector-ALU layer
 constexpr int kMaxHidden = 1024;
 constexpr int kMaxOut = 256;
-constexpr int64_t kSplitRows = 512;   // batch rows per split of a weight-gradient reduction
+constexpr int64_t kSplitRows = 256;   // batch rows per split of a weight-gradient reduction
 constexpr int64_t kInferChunk = 1 << 20;  // rows per forward chunk when nothing is kept
 
 int32_t pad32(int32_t d) { return (d + 31) / 32 * 32; }
@@ -224,10 +224,11 @@ int gemm(const GemmArgs& a, int32_t splits, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Input layer on the vector ALUs: H1[s][o] = relu(b0[o] + sum_c W0[o][c] x_c)
-// with x either FP32 [B][d0] or 8-bit RGB (x = v / 255 - 1/2).  Eight threads
-// per row, each 32 consecutive outputs written as four 16-byte stores; the
-// weights sit in LDS.  d1 must be a multiple of 32 and at most 1024.
+// Input layer on the vector ALUs: H1[s][o] = act(b0[o] + sum_c W0[o][c] x_c)
+// with act = first_act (ReLU or the sinusoid) and x either FP32 [B][d0] or
+// 8-bit RGB (x = v / 255 - 1/2).  Eight threads per row, each 32 consecutive
+// outputs written as four 16-byte stores; the weights sit in LDS.  d1 must be
+// a multiple of 32 and at most 1024.
 template <bool RGB8>
 __global__ __launch_bounds__(256) void k_input_layer(const void* __restrict__ xin, int64_t B, int32_t d0,
                                                      int32_t d1, const float* __restrict__ W0,
@@ -269,7 +270,8 @@ __global__ __launch_bounds__(256) void k_input_layer(const void* __restrict__ xi
 // of 256, outputs <= 64) from 8-bit colours: a block of four waves takes 64
 // rows through every layer with the activations in LDS, so nothing but the
 // colours and the outputs touches HBM (the weights stay in L2).
-//   - input layer: per element on the vector ALUs, as k_input_layer<true>;
+//   - input layer: per element on the vector ALUs, as k_input_layer<true>
+//     (ReLU or the sinusoid);
 //   - hidden layers: each wave computes 64 rows x 64 columns as 4 x 4 MFMA
 //     tiles, the A fragments from LDS, the B fragments (weights, [n][k]) from
 //     global memory one 32-deep slice ahead; then a barrier, and the
@@ -383,34 +385,54 @@ __global__ __launch_bounds__(256) void k_mlp_infer_fused(const uint8_t* __restri
 
 // Column reductions for the bias gradients and the input layer's weight
 // gradients.  Block (x, y) covers columns 64x .. 64x+63 and rows
-// kColRows y .. + kColRows-1: thread (c, g) sums every fourth row of the tile
-// for column c, the four row groups are added in LDS in a fixed order, and
-// part[y][o][k] receives, for column o, sum_s G[s][o] x[s][k] (k < d0) and
-// sum_s G[s][o] (k = d0).  With d0 = 0 only the column sums are formed.
-constexpr int kColRows = 256;
+// kColRows y .. + kColRows-1.  Thread (q, r) reads eight columns
+// 64x + 8q .. + 7 as one 16-byte load from rows r, r + 32, ... of the tile
+// and sums them in that order; the 32 row groups are then added in LDS in
+// their fixed order, and part[y][o][k] receives, for column o,
+// sum_s G[s][o] x[s][k] (k < d0) and sum_s G[s][o] (k = d0).  With d0 = 0
+// only the column sums are formed.  ldg must be a multiple of 8.
+constexpr int kColRows = 256, kColGroups = 32;
 
 __global__ __launch_bounds__(256) void k_colgrad(const bf16* __restrict__ G, int64_t ldg,
                                                  const float* __restrict__ x, int32_t d0, int64_t B,
                                                  int32_t ncols, float* __restrict__ part) {
-    __shared__ float s_acc[4][64][kMaxIn + 1];
-    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int32_t o = (int32_t)blockIdx.x * 64 + c;
+    __shared__ float s_acc[kColGroups][64][kMaxIn + 1];
+    const int q = threadIdx.x & 7, r = threadIdx.x >> 3;
+    const int32_t o0 = (int32_t)blockIdx.x * 64 + 8 * q;
     const int64_t s0 = (int64_t)blockIdx.y * kColRows, s1 = min(B, s0 + kColRows);
-    float acc[kMaxIn + 1] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    if (o < ncols) {
-        for (int64_t sr = s0 + g; sr < s1; sr += 4) {
-            const float v = (float)G[sr * ldg + o];
-            for (int32_t k = 0; k < d0; ++k) acc[k] = fmaf(v, x[sr * d0 + k], acc[k]);
-            acc[kMaxIn] += v;
+    float acc[8][kMaxIn + 1];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int k = 0; k <= kMaxIn; ++k) acc[e][k] = 0.0f;
+    if (o0 + 8 <= ldg) {
+        for (int64_t sr = s0 + r; sr < s1; sr += kColGroups) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8*>(G + sr * ldg + o0);
+            float xs[kMaxIn];
+#pragma unroll
+            for (int k = 0; k < kMaxIn; ++k) xs[k] = k < d0 ? x[sr * d0 + k] : 0.0f;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float ve = (float)v[e];
+#pragma unroll
+                for (int k = 0; k < kMaxIn; ++k)
+                    if (k < d0) acc[e][k] = fmaf(ve, xs[k], acc[e][k]);
+                acc[e][kMaxIn] += ve;
+            }
         }
     }
-    for (int k = 0; k <= kMaxIn; ++k) s_acc[g][c][k] = acc[k];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int k = 0; k <= kMaxIn; ++k) s_acc[r][8 * q + e][k] = acc[e][k];
     __syncthreads();
-    if (g == 0 && o < ncols) {
-        float* dst = part + ((int64_t)blockIdx.y * ncols + o) * (d0 + 1);
-        for (int32_t k = 0; k < d0; ++k)
-            dst[k] = ((s_acc[0][c][k] + s_acc[1][c][k]) + s_acc[2][c][k]) + s_acc[3][c][k];
-        dst[d0] = ((s_acc[0][c][kMaxIn] + s_acc[1][c][kMaxIn]) + s_acc[2][c][kMaxIn]) + s_acc[3][c][kMaxIn];
+    for (int t = threadIdx.x; t < 64 * (kMaxIn + 1); t += 256) {
+        const int c = t / (kMaxIn + 1), k = t - c * (kMaxIn + 1);
+        const int32_t o = (int32_t)blockIdx.x * 64 + c;
+        if (o >= ncols || (k < kMaxIn && k >= d0)) continue;
+        float sum = 0.0f;
+        for (int g = 0; g < kColGroups; ++g) sum += s_acc[g][c][k];
+        part[((int64_t)blockIdx.y * ncols + o) * (d0 + 1) + (k == kMaxIn ? d0 : k)] = sum;
     }
 }
 
@@ -426,15 +448,25 @@ __global__ void k_input_grad_sum(const float* __restrict__ part, int32_t splits,
     else gb0[o] = acc;
 }
 
-// Fixed-order sum of split partials [z][rows][ldp] into out[r][c] (r < rows, c < cols).
-__global__ void k_sum_splits(const float* __restrict__ part, int32_t splits, int64_t zstride,
-                             int32_t rows, int32_t cols, int64_t ldp, float* __restrict__ out) {
+// One launch for a layer's two fixed-order sums: the weight gradient from
+// its split partials pw [z][rows][ldp] (threads t < rows * cols), then the
+// bias gradient from the column partials pb [z][rows] (the next rows threads).
+__global__ void k_sum_grads(const float* __restrict__ pw, int32_t wsplits, int64_t zstride, int32_t rows,
+                            int32_t cols, int64_t ldp, float* __restrict__ gw, const float* __restrict__ pb,
+                            int32_t bsplits, float* __restrict__ gb) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)rows * cols) return;
-    const int32_t r = (int32_t)(t / cols), c = (int32_t)(t - (int64_t)r * cols);
-    float acc = 0.0f;
-    for (int32_t z = 0; z < splits; ++z) acc += part[z * zstride + (int64_t)r * ldp + c];
-    out[t] = acc;
+    const int64_t nw = (int64_t)rows * cols;
+    if (t < nw) {
+        const int32_t r = (int32_t)(t / cols), c = (int32_t)(t - (int64_t)r * cols);
+        float acc = 0.0f;
+        for (int32_t z = 0; z < wsplits; ++z) acc += pw[z * zstride + (int64_t)r * ldp + c];
+        gw[t] = acc;
+    } else if (t < nw + rows) {
+        const int32_t o = (int32_t)(t - nw);
+        float acc = 0.0f;
+        for (int32_t z = 0; z < bsplits; ++z) acc += pb[(int64_t)z * rows + o];
+        gb[o] = acc;
+    }
 }
 
 // FP32 output gradient -> BF16, zero-padded to the padded output width.
@@ -461,30 +493,45 @@ __global__ void k_weights_bf16(const float* __restrict__ W, int32_t d, int32_t d
 // Loss of a batch and its gradient with respect to the outputs.  Per sample s
 // with outputs z[0..D-1] (D-1 radii and the feasibility logit):
 //   l_s = (1/(D-1)) sum_k [t_k > 0] huber(z_k - t_k) + softplus(z) - z f
-// gradient dl/dz / B.  Per-block partial sums, then a fixed-order total.
+// gradient dl/dz / B, written as FP32 [B][D] (gout) and / or rounded to BF16
+// with zero padding [B][ldgb] (gb, ldgb >= D: the first operand of the
+// backward pass).  Block x takes rows 16x .. 16x+15, one wave per row and one
+// lane per output; its loss terms are summed by a fixed tree into part[x].
+constexpr int kLossRows = 16;
+
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ out, const float* __restrict__ tr,
                                               const float* __restrict__ tf, int64_t B, int32_t D,
-                                              float delta, float* __restrict__ gout,
-                                              float* __restrict__ part) {
+                                              float delta, float* __restrict__ gout, bf16* __restrict__ gb,
+                                              int32_t ldgb, float* __restrict__ part) {
     __shared__ float s_sum[256];
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t R = D - 1;
+    const int32_t width = gb ? max(D, ldgb) : D;
+    const float invR = 1.0f / (float)R, invB = 1.0f / (float)B;
     float ls = 0.0f;
-    if (s < B) {
-        const int32_t R = D - 1;
-        const float invR = 1.0f / (float)R, invB = 1.0f / (float)B;
-        for (int32_t k = 0; k < R; ++k) {
-            const float t = tr[s * R + k];
+    const int64_t s0 = (int64_t)blockIdx.x * kLossRows;
+#pragma unroll
+    for (int rr = w; rr < kLossRows; rr += 4) {
+        const int64_t s = s0 + rr;
+        if (s >= B) continue;
+        for (int32_t c = lane; c < width; c += 64) {
             float g = 0.0f;
-            if (t > 0.0f) {
-                const float e = out[s * D + k] - t, ae = fabsf(e);
-                ls += (ae <= delta ? 0.5f * e * e : delta * (ae - 0.5f * delta)) * invR;
-                g = (ae <= delta ? e : copysignf(delta, e)) * invR;
+            if (c < R) {
+                const float t = tr[s * R + c];
+                if (t > 0.0f) {
+                    const float e = out[s * D + c] - t, ae = fabsf(e);
+                    ls += (ae <= delta ? 0.5f * e * e : delta * (ae - 0.5f * delta)) * invR;
+                    g = (ae <= delta ? e : copysignf(delta, e)) * invR;
+                }
+            } else if (c == R) {
+                const float z = out[s * D + R], f = tf[s];
+                ls += fmaxf(z, 0.0f) - z * f + log1pf(expf(-fabsf(z)));
+                g = 1.0f / (1.0f + expf(-z)) - f;
             }
-            if (gout) gout[s * D + k] = g * invB;
+            g *= invB;
+            if (gout && c < D) gout[s * D + c] = g;
+            if (gb) gb[s * ldgb + c] = (bf16)g;
         }
-        const float z = out[s * D + R], f = tf[s];
-        ls += fmaxf(z, 0.0f) - z * f + log1pf(expf(-fabsf(z)));
-        if (gout) gout[s * D + R] = (1.0f / (1.0f + expf(-z)) - f) * invB;
     }
     s_sum[threadIdx.x] = ls;
     __syncthreads();
@@ -495,19 +542,36 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ out, con
     if (threadIdx.x == 0) part[blockIdx.x] = s_sum[0];
 }
 
-__global__ void k_loss_total(const float* __restrict__ part, int32_t nparts, int64_t B,
-                             float* __restrict__ loss) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Total of the per-block loss partials in FP64: thread t sums partials
+// t, t + 256, ... in order, then a fixed tree.
+__global__ __launch_bounds__(256) void k_loss_total(const float* __restrict__ part, int32_t nparts, int64_t B,
+                                                    float* __restrict__ loss) {
+    __shared__ double s_sum[256];
     double acc = 0.0;
-    for (int32_t k = 0; k < nparts; ++k) acc += part[k];
-    *loss = (float)(acc / (double)B);
+    for (int32_t k = (int32_t)threadIdx.x; k < nparts; k += 256) acc += part[k];
+    s_sum[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s_sum[threadIdx.x] += s_sum[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)(s_sum[0] / (double)B);
 }
 
 // Adam: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
 // p -= lr (m c1) / (sqrt(v c2) + eps) with c1 = 1/(1-b1^t), c2 = 1/(1-b2^t).
+// The new value of every matrix-core weight also goes to its BF16 copy
+// (the rows of W_l [d][din] are the first d rows of the copy [dpad][din]).
+struct BF16Copies {
+    int32_t n = 0;
+    int64_t off[kMaxLayers] = {};
+    int64_t cnt[kMaxLayers] = {};
+    bf16* dst[kMaxLayers] = {};
+};
+
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
-                       float c1, float c2) {
+                       float c1, float c2, BF16Copies cp) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
@@ -515,7 +579,10 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    const float pi = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    p[i] = pi;
+    for (int32_t l = 0; l < cp.n; ++l)
+        if (i >= cp.off[l] && i < cp.off[l] + cp.cnt[l]) cp.dst[l][i - cp.off[l]] = (bf16)pi;
 }
 
 // Training rows from a table of the whole cube: x = RGB / 255 - 1/2 of colour
@@ -533,6 +600,46 @@ __global__ void k_table_batch(const int32_t* __restrict__ ids, const cv_table_ro
     const cv_table_row& r = table[id];
     for (int k = 0; k < 36; ++k) tr[s * 36 + k] = (float)r.bin_ridx[k] * rscale;
     tf[s] = r.count > 0 ? 1.0f : 0.0f;
+}
+
+// A keyed pseudorandom permutation of [0, n): a balanced Feistel network of
+// four rounds on 2h-bit values (2^2h >= n, at most 4n), with cycle walking
+// back into [0, n) (Black and Rogaway 2002, "Ciphers with arbitrary finite
+// domains").  A Feistel network is a bijection whatever its round function,
+// so cycle walking ends at the latest when it comes back round to the start;
+// the expected number of steps is below 4.  Round r: (L, R) -> (R, L xor
+// (mix64(R + k_r) mod 2^h)), mix64 the SplitMix64 finaliser, k_r =
+// mix64(key + (r + 1) 0x9E3779B97F4A7C15).
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct FeistelKey {
+    uint64_t k[4];
+    uint32_t h;  // bits per half
+};
+
+__device__ __forceinline__ uint64_t feistel(uint64_t v, const FeistelKey& fk) {
+    const uint64_t mask = (1ull << fk.h) - 1ull;
+    uint64_t L = v >> fk.h, R = v & mask;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t t = L ^ (mix64(R + fk.k[r]) & mask);
+        L = R;
+        R = t;
+    }
+    return (L << fk.h) | R;
+}
+
+__global__ void k_permute_ids(const int32_t* __restrict__ in, int64_t n, FeistelKey fk,
+                              int32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t v = feistel((uint64_t)i, fk);
+    while (v >= (uint64_t)n) v = feistel(v, fk);
+    out[i] = in[v];
 }
 
 unsigned blocks(int64_t n, int per) {
@@ -578,7 +685,6 @@ struct cv_mlp {
     float* ttr = nullptr;   // [tcap][36]
     float* ttf = nullptr;   // [tcap]
     float* tout = nullptr;  // [tcap][37]
-    float* tgout = nullptr; // [tcap][37]
     float* tloss = nullptr; // [1]: loss of a step that is not logged
 };
 
@@ -705,24 +811,28 @@ int run_forward(cv_mlp* m, const void* x, bool rgb8, int64_t rows, float* out, b
     return CV_OK;
 }
 
+// gout: FP32 [B][dims_L]; or nullptr when run_loss has already put the BF16
+// gradient in g[0].
 int run_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, hipStream_t s) {
     int rc;
     const int32_t L = m->L;
     const int32_t splits = (int32_t)((B + kSplitRows - 1) / kSplitRows);
     const int32_t csplits = (int32_t)((B + kColRows - 1) / kColRows);  // column reductions
-    // partials: the widest weight gradient, or a column reduction
+    // partials: a layer's weight partials followed by its column partials
     size_t need = 0;
     for (int l = 0; l < L; ++l) {
         const size_t w = (size_t)splits * m->dpad[l + 1] * (l == 0 ? 0 : m->dims[l]);
         const size_t c = (size_t)csplits * m->dpad[l + 1] * (l == 0 ? (m->dims[0] + 1) : 1);
-        need = std::max(need, std::max(w, c));
+        need = std::max(need, w + c);
     }
     if ((rc = ensure_part(m, need * sizeof(float))) != CV_OK) return rc;
     bf16* Gc = m->g[0];  // gradient w.r.t. the pre-activations of layer l's output
     bf16* Gn = m->g[1];
-    hipLaunchKernelGGL(k_grad_to_bf16, dim3(blocks(B * m->dpad[L], 256)), dim3(256), 0, s, gout, B,
-                       m->dims[L], m->dpad[L], Gc);
-    CV_HIP(hipGetLastError());
+    if (gout) {
+        hipLaunchKernelGGL(k_grad_to_bf16, dim3(blocks(B * m->dpad[L], 256)), dim3(256), 0, s, gout, B,
+                           m->dims[L], m->dpad[L], Gc);
+        CV_HIP(hipGetLastError());
+    }
     int32_t ldg = m->dpad[L];
     for (int l = L - 1; l >= 1; --l) {
         const int32_t dout = m->dims[l + 1], dop = m->dpad[l + 1], din = m->dims[l];
@@ -741,15 +851,13 @@ int run_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, hipStr
         a.zstride = (int64_t)dop * din;
         a.nstore = din;
         if ((rc = gemm<false, false, EPI_PARTIAL_F32>(a, splits, s)) != CV_OK) return rc;
-        hipLaunchKernelGGL(k_sum_splits, dim3(blocks((int64_t)dout * din, 256)), dim3(256), 0, s,
-                           m->part, splits, (int64_t)dop * din, dout, din, (int64_t)din,
-                           m->grads + m->woff[l]);
-        CV_HIP(hipGetLastError());
-        // bias gradient; its partials follow the weight partials' use (same stream)
+        // bias gradient: column partials after the weight partials, then both sums in one launch
+        float* pb = m->part + (size_t)splits * dop * din;
         hipLaunchKernelGGL(k_colgrad, dim3((unsigned)((dout + 63) / 64), (unsigned)csplits), dim3(256), 0,
-                           s, Gc, (int64_t)ldg, (const float*)nullptr, 0, B, dout, m->part);
-        hipLaunchKernelGGL(k_sum_splits, dim3(blocks(dout, 256)), dim3(256), 0, s, m->part, csplits,
-                           (int64_t)dout, 1, dout, (int64_t)dout, m->grads + m->boff[l]);
+                           s, Gc, (int64_t)ldg, (const float*)nullptr, 0, B, dout, pb);
+        hipLaunchKernelGGL(k_sum_grads, dim3(blocks((int64_t)dout * din + dout, 256)), dim3(256), 0, s,
+                           m->part, splits, (int64_t)dop * din, dout, din, (int64_t)din, m->grads + m->woff[l],
+                           pb, csplits, m->grads + m->boff[l]);
         CV_HIP(hipGetLastError());
         // input gradient through W_l and the ReLU of H_l
         GemmArgs d = {};
@@ -790,16 +898,18 @@ int run_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, hipStr
     return CV_OK;
 }
 
+// gb (nullable): the BF16 output gradient [B][dpad_L] for run_backward's
+// first operand, written in the same pass.
 int run_loss(cv_mlp* m, const float* out, const float* tr, const float* tf, int64_t B, float delta,
-             float* loss, float* gout, hipStream_t s) {
-    const int64_t nb = (B + 255) / 256;
+             float* loss, float* gout, bf16* gb, hipStream_t s) {
+    const int64_t nb = (B + kLossRows - 1) / kLossRows;
     int rc;
     size_t have = (size_t)m->lpart_n * sizeof(float);
     if ((rc = grow((void**)&m->lpart, &have, (size_t)nb * sizeof(float))) != CV_OK) return rc;
     m->lpart_n = (int64_t)(have / sizeof(float));
     hipLaunchKernelGGL(k_loss, dim3((unsigned)nb), dim3(256), 0, s, out, tr, tf, B, m->dims[m->L], delta,
-                       gout, m->lpart);
-    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, s, m->lpart, (int32_t)nb, B, loss);
+                       gout, gb, m->dpad[m->L], m->lpart);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, m->lpart, (int32_t)nb, B, loss);
     CV_HIP(hipGetLastError());
     return CV_OK;
 }
@@ -807,16 +917,23 @@ int run_loss(cv_mlp* m, const float* out, const float* tr, const float* tf, int6
 int run_adam(cv_mlp* m, float lr, float b1, float b2, float eps, int64_t t, hipStream_t s) {
     const float c1 = (float)(1.0 / (1.0 - pow((double)b1, (double)t)));
     const float c2 = (float)(1.0 / (1.0 - pow((double)b2, (double)t)));
+    BF16Copies cp;
+    for (int l = 1; l < m->L; ++l) {
+        cp.off[cp.n] = m->woff[l];
+        cp.cnt[cp.n] = (int64_t)m->dims[l + 1] * m->dims[l];
+        cp.dst[cp.n] = m->wb[l];
+        ++cp.n;
+    }
     hipLaunchKernelGGL(k_adam, dim3(blocks(m->nparam, 256)), dim3(256), 0, s, m->params, m->grads,
-                       m->adam_m, m->adam_v, m->nparam, lr, b1, b2, eps, c1, c2);
+                       m->adam_m, m->adam_v, m->nparam, lr, b1, b2, eps, c1, c2, cp);
     CV_HIP(hipGetLastError());
-    return refresh_bf16(m, s);
+    return CV_OK;
 }
 
 int ensure_train(cv_mlp* m, int64_t B) {
     if (B <= m->tcap) return CV_OK;
     CV_HIP(hipDeviceSynchronize());
-    float** bufs[] = {&m->tx, &m->ttr, &m->ttf, &m->tout, &m->tgout};
+    float** bufs[] = {&m->tx, &m->ttr, &m->ttf, &m->tout};
     for (float** b : bufs) {
         if (*b) CV_HIP(hipFree(*b));
         *b = nullptr;
@@ -826,7 +943,6 @@ int ensure_train(cv_mlp* m, int64_t B) {
     CV_HIP(hipMalloc((void**)&m->ttr, (size_t)B * 36 * sizeof(float)));
     CV_HIP(hipMalloc((void**)&m->ttf, (size_t)B * sizeof(float)));
     CV_HIP(hipMalloc((void**)&m->tout, (size_t)B * 37 * sizeof(float)));
-    CV_HIP(hipMalloc((void**)&m->tgout, (size_t)B * 37 * sizeof(float)));
     if (!m->tloss) CV_HIP(hipMalloc((void**)&m->tloss, sizeof(float)));
     m->tcap = B;
     return CV_OK;
@@ -834,7 +950,7 @@ int ensure_train(cv_mlp* m, int64_t B) {
 
 void free_mlp(cv_mlp* m) {
     void* ps[] = {m->params, m->grads, m->adam_m, m->adam_v, m->g[0], m->g[1], m->part, m->lpart,
-                  m->tx, m->ttr, m->ttf, m->tout, m->tgout, m->tloss};
+                  m->tx, m->ttr, m->ttf, m->tout, m->tloss};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     for (int l = 0; l < kMaxLayers; ++l) {
@@ -1005,7 +1121,7 @@ int cv_mlp_loss(cv_mlp* m, const float* out, const float* t_r, const float* t_f,
     if (!out || !t_r || !t_f || !loss) return fail(CV_EINVAL, "null array");
     if (!(huber_delta > 0.0f)) return fail(CV_EINVAL, "huber_delta must be > 0");
     DeviceGuard dg(m->device);
-    return cvib::run_loss(m, out, t_r, t_f, B, huber_delta, loss, gout, (hipStream_t)stream);
+    return cvib::run_loss(m, out, t_r, t_f, B, huber_delta, loss, gout, nullptr, (hipStream_t)stream);
     CV_GUARD_END
 }
 
@@ -1056,9 +1172,10 @@ int cv_mlp_train_steps(cv_mlp* m, const int32_t* ids, int64_t n, const cv_table_
         CV_HIP(hipGetLastError());
         if ((rc = cvib::run_forward(m, m->tx, false, nb, m->tout, true, s)) != CV_OK) return rc;
         float* lp = loss_log ? loss_log + k : m->tloss;
-        if ((rc = cvib::run_loss(m, m->tout, m->ttr, m->ttf, nb, huber_delta, lp, m->tgout, s)) != CV_OK)
+        // the loss writes the BF16 output gradient straight into the backward pass's first operand
+        if ((rc = cvib::run_loss(m, m->tout, m->ttr, m->ttf, nb, huber_delta, lp, nullptr, m->g[0], s)) != CV_OK)
             return rc;
-        if ((rc = cvib::run_backward(m, m->tx, m->tgout, nb, s)) != CV_OK) return rc;
+        if ((rc = cvib::run_backward(m, m->tx, nullptr, nb, s)) != CV_OK) return rc;
         // cosine decay from lr_max to lr_min over total_steps
         const int64_t t = step0 + k;
         const double frac = total_steps > 1 ? (double)std::min(t, total_steps - 1) / (double)(total_steps - 1) : 0.0;
@@ -1082,6 +1199,25 @@ int cv_mlp_table_batch(cv_mlp* m, const int32_t* ids, const cv_table_row* table,
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(cvib::k_table_batch, dim3(cvib::blocks(B, 256)), dim3(256), 0, s, ids, table, B,
                        (float)(dr / 50.0), x, t_r, t_f);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_permute_ids(cv_context* ctx, const int32_t* in, int64_t n, uint64_t key, int32_t* out, void* stream) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "context is NULL");
+    if (n < 0 || n > ((int64_t)1 << 31)) return fail(CV_EINVAL, "n must be in [0, 2^31]");
+    if (n == 0) return CV_OK;
+    if (!in || !out) return fail(CV_EINVAL, "null array");
+    if (in == out) return fail(CV_EINVAL, "in and out must not overlap");
+    cvib::FeistelKey fk;
+    fk.h = 1;
+    while ((int64_t)1 << (2 * fk.h) < n) ++fk.h;
+    for (int r = 0; r < 4; ++r) fk.k[r] = cvib::mix64(key + (uint64_t)(r + 1) * 0x9E3779B97F4A7C15ull);
+    DeviceGuard dg(ctx->device);
+    hipLaunchKernelGGL(cvib::k_permute_ids, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       in, n, fk, out);
     CV_HIP(hipGetLastError());
     return CV_OK;
     CV_GUARD_END

@@ -7,10 +7,9 @@ from __future__ import annotations
 import math
 import time
 
-import numpy as np
 import torch
 
-from . import MLP, Grid, Rule, context, pair_reduce
+from . import MLP, Grid, Rule, context, pair_reduce, permute_ids
 
 
 def cube_colours_device(device="cuda") -> torch.Tensor:
@@ -25,26 +24,28 @@ def cube_table(grid: Grid, rule: Rule, ctx=None) -> torch.Tensor:
 
 
 def train(mlp: MLP, table: torch.Tensor, train_ids: torch.Tensor, dr: float, epochs: float = 4.0,
-          batch: int = 8192, lr: float = 2e-3, lr_min: float = 2e-5, delta: float = 0.05,
+          batch: int = 8192, lr: float = 4e-3, lr_min: float = 2e-5, delta: float = 0.05,
           seed: int = 0, log_every: int = 200, step0: int = 0):
     """Adam with cosine decay from lr to lr_min over the run; rows are the
-    training colour ids (int32 on the GPU) shuffled per epoch by a Philox
-    stream keyed by `seed`; each epoch is one call of the library's training
-    loop.  Returns (steps, [(step, loss)], seconds)."""
+    training colour ids (int32 on the GPU) in a new pseudorandom order every
+    epoch (the library's keyed permutation, key = (seed, epoch)); each epoch
+    is one call of the library's training loop.  Returns (steps,
+    [(step, loss)], seconds)."""
     n = train_ids.shape[0]
     per_epoch = math.ceil(n / batch)
     total = max(1, int(round(epochs * per_epoch)))
-    rng = np.random.Generator(np.random.Philox(key=seed))
     log = []
+    ids = torch.empty_like(train_ids)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     step = 0
+    epoch = 0
     while step < total:
         take = min(per_epoch, total - step)
-        perm = torch.from_numpy(rng.permutation(n).astype(np.int64)).to(train_ids.device)
-        ids = train_ids[perm[:min(n, take * batch)]].contiguous()
-        losses = mlp.train_steps(ids, table, dr, batch, delta, lr, lr_min, step0 + step, total,
-                                 log=bool(log_every))
+        permute_ids(train_ids, (seed << 32) + epoch, out=ids, ctx=mlp.ctx)
+        losses = mlp.train_steps(ids[:min(n, take * batch)], table, dr, batch, delta, lr, lr_min,
+                                 step0 + step, total, log=bool(log_every))
+        epoch += 1
         if log_every:
             lv = losses.cpu().numpy()
             for k in range(0, take, log_every):

@@ -195,6 +195,7 @@ def test_mlp_argument_validation(cv):
     assert L.cv_mlp_load(None, b"/tmp/x") == cv.CV_EINVAL
     assert L.cv_mlp_set_first_sine(None, 30.0) == cv.CV_EINVAL
     assert L.cv_mlp_first_sine(None, None) == cv.CV_EINVAL
+    assert L.cv_permute_ids(None, None, 1, 0, None, None) == cv.CV_EINVAL
 
 
 def test_init_params_layout(cv):

@@ -284,3 +284,61 @@ def test_fused_inference_equals_layer_by_layer(cv, n, omega0):
     x = torch.from_numpy(rgb.astype(np.float32) * np.float32(1.0 / 255.0) - np.float32(0.5)).cuda()
     b = m.forward(x)
     assert torch.equal(a, k) and torch.equal(k, b)
+
+
+def _mix64(z):
+    M = (1 << 64) - 1
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+    return z ^ (z >> 31)
+
+
+def _feistel_order(n, key):
+    """The training order from its definition: four Feistel rounds on 2h-bit
+    values, round r xor-ing mix64(R + k_r) mod 2^h into L, cycle-walked back
+    into [0, n)."""
+    M = (1 << 64) - 1
+    h = 1
+    while (1 << (2 * h)) < n:
+        h += 1
+    ks = [_mix64((key + (r + 1) * 0x9E3779B97F4A7C15) & M) for r in range(4)]
+    mask = (1 << h) - 1
+
+    def pi(v):
+        L, R = v >> h, v & mask
+        for k in ks:
+            L, R = R, L ^ (_mix64((R + k) & M) & mask)
+        return (L << h) | R
+
+    out = []
+    for i in range(n):
+        v = pi(i)
+        while v >= n:
+            v = pi(v)
+        out.append(v)
+    return out
+
+
+@pytest.mark.parametrize("n,key", [(1, 0), (2, 5), (7, 1), (1000, 3), (4097, (1 << 32) + 2)])
+def test_permute_ids_matches_definition(cv, n, key):
+    ids = torch.arange(10, 10 + n, dtype=torch.int32, device="cuda")
+    got = cv.permute_ids(ids, key).cpu().numpy()
+    want = 10 + np.array(_feistel_order(n, key))
+    assert np.array_equal(got, want)
+
+
+def test_permute_ids_is_a_shuffle(cv):
+    n = 15_101_294   # the training colours of the whole-cube 90/10 split
+    ids = torch.arange(n, dtype=torch.int32, device="cuda") * 3
+    a = cv.permute_ids(ids, 1)
+    b = cv.permute_ids(ids, 2)
+    assert torch.equal(torch.sort(a).values, ids)       # a permutation
+    assert torch.equal(cv.permute_ids(ids, 1), a)       # the same key, the same order
+    fixed = int((a == ids).sum())
+    assert fixed < 100                                  # about one expected
+    assert int((a == b).sum()) < 100
+    # neighbours in the output come from far apart in the input
+    d = torch.abs(a[1:].double() - a[:-1].double()) / 3
+    assert float(d.median()) > n / 8
+    with pytest.raises(cv.CvError):   # in place is refused
+        cv._check(cv.lib().cv_permute_ids(cv.context().handle, cv._dptr(ids), n, 1, cv._dptr(ids), None))
