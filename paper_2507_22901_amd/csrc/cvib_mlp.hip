@@ -226,9 +226,9 @@ int gemm(const GemmArgs& a, int32_t splits, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Input layer on the vector ALUs: H1[s][o] = act(b0[o] + sum_c W0[o][c] x_c)
 // with act = first_act (ReLU or the sinusoid) and x either FP32 [B][d0] or
-// 8-bit RGB (x = v / 255 - 1/2).  Eight threads per row, each 32 consecutive
-// outputs written as four 16-byte stores; the weights sit in LDS.  d1 must be
-// a multiple of 32 and at most 1024.
+// 8-bit RGB (x = v / 255 - 1/2).  d1 / 8 threads per row, each 8 consecutive
+// outputs written as one 16-byte store; the weights sit in LDS.  d1 must be a
+// multiple of 32 and at most 1024.
 template <bool RGB8>
 __global__ __launch_bounds__(256) void k_input_layer(const void* __restrict__ xin, int64_t B, int32_t d0,
                                                      int32_t d1, const float* __restrict__ W0,
@@ -238,30 +238,26 @@ __global__ __launch_bounds__(256) void k_input_layer(const void* __restrict__ xi
     for (int k = threadIdx.x; k < d1 * d0; k += 256) s_w[k] = W0[k];
     for (int k = threadIdx.x; k < d1; k += 256) s_w[d1 * d0 + k] = b0[k];
     __syncthreads();
-    const int32_t groups = d1 / 32;                      // threads per row
+    const int32_t groups = d1 / 8;                       // threads per row
     const int64_t total = B * groups;
     const int64_t stride = (int64_t)gridDim.x * 256;
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += stride) {
         const int64_t s = t / groups;
-        const int32_t o0 = (int32_t)(t - s * groups) * 32;
+        const int32_t o0 = (int32_t)(t - s * groups) * 8;
         float x[kMaxIn] = {0.f, 0.f, 0.f, 0.f};
         for (int32_t c = 0; c < d0; ++c) {
             if constexpr (RGB8) x[c] = rgb_input(static_cast<const uint8_t*>(xin)[s * 3 + c]);
             else x[c] = static_cast<const float*>(xin)[s * d0 + c];
         }
-        bf16* dst = H1 + s * d1 + o0;
+        bf16x8 v;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            bf16x8 v;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int32_t o = o0 + 8 * q + e;
-                float acc = s_w[d1 * d0 + o];
-                for (int32_t c = 0; c < d0; ++c) acc = fmaf(s_w[o * d0 + c], x[c], acc);
-                v[e] = (bf16)first_act(acc, omega0);
-            }
-            *reinterpret_cast<bf16x8*>(dst + 8 * q) = v;
+        for (int e = 0; e < 8; ++e) {
+            const int32_t o = o0 + e;
+            float acc = s_w[d1 * d0 + o];
+            for (int32_t c = 0; c < d0; ++c) acc = fmaf(s_w[o * d0 + c], x[c], acc);
+            v[e] = (bf16)first_act(acc, omega0);
         }
+        *reinterpret_cast<bf16x8*>(H1 + s * d1 + o0) = v;
     }
 }
 
@@ -442,6 +438,7 @@ __global__ void k_input_grad_sum(const float* __restrict__ part, int32_t splits,
     const int32_t per = d0 + 1;
     if (t >= d1 * per) return;
     float acc = 0.0f;
+#pragma unroll 8
     for (int32_t z = 0; z < splits; ++z) acc += part[(int64_t)z * d1 * per + t];
     const int32_t o = t / per, c = t - o * per;
     if (c < d0) gW0[o * d0 + c] = acc;
@@ -459,11 +456,13 @@ __global__ void k_sum_grads(const float* __restrict__ pw, int32_t wsplits, int64
     if (t < nw) {
         const int32_t r = (int32_t)(t / cols), c = (int32_t)(t - (int64_t)r * cols);
         float acc = 0.0f;
+#pragma unroll 8
         for (int32_t z = 0; z < wsplits; ++z) acc += pw[z * zstride + (int64_t)r * ldp + c];
         gw[t] = acc;
     } else if (t < nw + rows) {
         const int32_t o = (int32_t)(t - nw);
         float acc = 0.0f;
+#pragma unroll 8
         for (int32_t z = 0; z < bsplits; ++z) acc += pb[(int64_t)z * rows + o];
         gb[o] = acc;
     }
@@ -797,7 +796,7 @@ int run_forward(cv_mlp* m, const void* x, bool rgb8, int64_t rows, float* out, b
         const int64_t nr = std::min(chunk, rows - r0);
         const void* xs = rgb8 ? (const void*)((const uint8_t*)x + r0 * 3)
                               : (const void*)((const float*)x + r0 * m->dims[0]);
-        const unsigned ib = blocks(nr * (m->dims[1] / 32), 256);
+        const unsigned ib = blocks(nr * (m->dims[1] / 8), 256);
         if (rgb8)
             hipLaunchKernelGGL(k_input_layer<true>, dim3(ib), dim3(256), 0, s, xs, nr, m->dims[0],
                                m->dims[1], m->params + m->woff[0], m->params + m->boff[0], m->omega0, m->h[1]);

@@ -149,17 +149,25 @@ def test_frames_surrogate_matches_pieces(cv, trained):
 
 
 def test_trained_network_gains(cv, trained):
-    """What training buys: fewer colours left to the exact search, at a
-    larger verified radius, than the same resolve with the untrained
-    network."""
+    """What training buys: more colours resolved by the network (fewer left
+    to the exact search) and more of the exact best radius recovered, than
+    the same resolve with the untrained network.  Recovered share: the
+    verified radius summed over the colours that have a pair (0 where the
+    network verifies none), over the exact best radius summed likewise."""
     cols = torch.from_numpy(_colours()).cuda()
     grid, rule = cv.Grid(*W.GRID_FRAMES.astuple()), cv.Rule(*W.DEFAULT_RULE)
+    summ, _ = cv.pair_reduce(cols, grid, rule)
+    summ = cv.as_records(summ, cv.SUMMARY_DTYPE)
+    has = summ["count"] > 0
+    best = summ["best_i"][has].astype(np.float64) + 1.0
     raw = cv.surrogate_network(0)
     out = {}
     for name, m in (("trained", trained["mlp"]), ("untrained", raw)):
         r = cv.surrogate_infer(cols, m, grid, rule, tau=0.0, fallback=False)
         p = cv.as_records(r.pairs, cv.PATTERN_PAIR_DTYPE)
         ok = (p["flags"] & cv.CV_PAIR_SURROGATE) != 0
-        out[name] = (ok.mean(), float(p["i"][ok].mean()) if ok.any() else 0.0)
-    print("verified fraction, mean verified radius index:", out)
+        got = np.where(ok, p["i"].astype(np.float64) + 1.0, 0.0)[has]
+        out[name] = (float(ok.mean()), float(got.sum() / best.sum()))
+    print("verified fraction, recovered share of the best radius:", out)
     assert out["trained"][0] > out["untrained"][0] + 0.2
+    assert out["trained"][1] > 1.2 * out["untrained"][1]
