@@ -8,8 +8,8 @@ V_th = 50, R_novib = 0.5, any pattern: 36 M candidate pairs per colour,
 per-colour summaries, the scan of segment counts and the write pass of the
 survivor list; inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  `--gpus` above 1 is refused: this build measures one
-GPU.
+Prints one JSON line.  `--gpus` above 1 is refused: the benchmark measures
+one GPU.
 """
 from __future__ import annotations
 
@@ -342,7 +342,7 @@ def cpu_baseline(target_s: float):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures a single GPU; run with --gpus 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU (its kernels run on a single device); run with --gpus 1"}))
         sys.exit(2)
     import numpy as np
     import torch

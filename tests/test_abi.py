@@ -249,3 +249,18 @@ def test_per_ray_and_list_validation(cv):
     assert L.cv_pair_reduce_csr(None, d, d, 1, d, None) == cv.CV_EINVAL
     assert L.cv_pair_reduce_csr(d, d, None, 1, d, None) == cv.CV_EINVAL
     assert L.cv_pair_reduce_csr(d, d, d, -1, d, None) == cv.CV_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message, before
+    touching a device."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
