@@ -6,7 +6,10 @@ V_th = 50, R_novib = 0.5, any pattern: 36 M candidate pairs per colour,
 324 M per step.  A step is one cv_pair_search call: per-colour prologue
 (RGB -> L*a*b*), the evaluation (count) pass over every candidate with the
 per-colour summaries, the scan of segment counts and the write pass of the
-survivor list; inputs are resident in HBM before timing starts.
+survivor list; inputs are resident in HBM before timing starts.  The timed
+steps are enqueued back to back without reading anything back (the survivor
+total stays on the device in offsets[n], checked after the timed region); a
+run of calls that each wait for the total is timed beside it.
 
 Prints one JSON line.  `--gpus` above 1 is refused: the benchmark measures
 one GPU.
@@ -375,8 +378,9 @@ def main():
     off = torch.empty(cols.shape[0] + 1, dtype=torch.int64, device="cuda")
     summ_buf = torch.empty((cols.shape[0], 48), dtype=torch.uint8, device="cuda")
 
-    def step(graph=False):
-        return cv.pair_search(cols, grid, rule, out=out, ctx=ctx, graph=graph, offsets=off, summ_out=summ_buf)
+    def step(graph=False, sync=False):
+        return cv.pair_search(cols, grid, rule, out=out, ctx=ctx, graph=graph, offsets=off, summ_out=summ_buf,
+                              sync=sync)
 
     for _ in range(args.warmup):
         step()
@@ -385,13 +389,22 @@ def main():
     stop = torch.cuda.Event(enable_timing=True)
     t_wall = time.perf_counter()
     start.record()
-    res = None
     for _ in range(args.steps):
-        res = step()
+        step()
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
     ms = start.elapsed_time(stop)
+    if int(off[-1].item()) != first.total:
+        raise RuntimeError("survivor total changed between calls")
+    # calls that each read the total back (a host round trip per call)
+    n_sync = max(3, min(args.steps, 20))
+    start.record()
+    for _ in range(n_sync):
+        res = step(sync=True)
+    stop.record()
+    torch.cuda.synchronize()
+    ms_sync = start.elapsed_time(stop) / n_sync
     # the same calls replayed from a captured graph, for comparison
     n_graph = max(3, min(args.steps, 20))
     step(graph=True)
@@ -407,7 +420,7 @@ def main():
         ctx.kernel_time(ph, reset=True)
     ctx.skipped(reset=True)
     for _ in range(max(3, min(args.steps, 20))):
-        step(graph=False)
+        step(graph=False, sync=True)
     t_eval, n_eval = ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
     t_write, n_write = ctx.kernel_time(cv.CV_TIME_WRITE, reset=True)
     t_call, n_call = ctx.kernel_time(cv.CV_TIME_CALL, reset=True)
@@ -451,6 +464,7 @@ def main():
         "colours_per_s_exact": len(W.PAPER_COLOUR_ARRAY) / (ms_per_step * 1e-3),
         "wall_s": wall,
         "ms_per_step_graph": ms_graph,
+        "ms_per_call_with_readback": ms_sync,
         "phases_ms": {"eval": k_eval, "write": k_write, "call": t_call / max(n_call, 1)},
         "roofline": {
             "bound": "alu",

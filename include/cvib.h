@@ -184,7 +184,12 @@ int cv_lab_convert(cv_context* ctx, const void* in, void* out, int64_t n, int di
  * CV_ECAPACITY and *total_host still holds the required total; offsets and
  * summ are complete and out holds the first `capacity` survivors (two-call
  * idiom: call again with capacity >= total).  capacity = 0 with out = NULL
- * is a pure count.  The context's workspace grows with the number of
+ * is a pure count.  total_host may be NULL when offsets is not: the call
+ * then returns once its work is enqueued, without reading anything back
+ * (calls can follow each other on the stream with no host round trip);
+ * offsets[n] holds the total on the device, survivors past `capacity` are
+ * not written, and no CV_ECAPACITY is raised (compare offsets[n] with
+ * capacity once the stream has reached the call).  The context's workspace grows with the number of
  * segments (one per row of radius when theta covers the full turn, else one
  * per 512 candidates): 12 bytes each.
  * With CV_GRAPH everything the call enqueues before the total is read back

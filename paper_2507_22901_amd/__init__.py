@@ -287,23 +287,27 @@ def lab_to_rgbf(lab: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:
 
 @dataclass
 class SearchResult:
-    pairs: torch.Tensor        # uint8 [total, 16] (PAIR_DTYPE records) on the GPU
+    pairs: torch.Tensor        # uint8 [total, 16] (PAIR_DTYPE records) on the GPU (sync=False: the whole buffer)
     offsets: torch.Tensor      # int64 [n + 1]
     summaries: torch.Tensor | None  # uint8 [n, 48] (SUMMARY_DTYPE)
-    total: int
+    total: int | None          # None for sync=False: offsets[n] on the device
 
 
 def pair_search(colors: torch.Tensor, grid: Grid, rule: Rule, capacity: int | None = None,
                 summaries: bool = True, emit_all: bool = False, per_ray: bool = False,
                 out: torch.Tensor | None = None, ctx: Context | None = None, graph: bool = False,
-                offsets: torch.Tensor | None = None, summ_out: torch.Tensor | None = None) -> SearchResult:
+                offsets: torch.Tensor | None = None, summ_out: torch.Tensor | None = None,
+                sync: bool = True) -> SearchResult:
     """Full search with stream compaction; survivors in (colour, i, j) order
     (per_ray: the largest-radius survivor of each ray, in (colour, j) order).
 
     With capacity None the output grows to fit (one extra search if the first
     guess is too small).  graph: capture the call once as a hipGraph and
     replay it while the arguments (pointers included: pass out, offsets and
-    summ_out to reuse them) stay the same."""
+    summ_out to reuse them) stay the same.  sync=False: nothing is read back
+    (the call only enqueues work); the result's total is None, offsets[n]
+    holds it on the device, and records past the capacity of `out` (which
+    must then be given) are dropped."""
     colors = _colours(colors)
     ctx = ctx or context(colors.device.index)
     n = colors.shape[0]
@@ -318,6 +322,14 @@ def pair_search(colors: torch.Tensor, grid: Grid, rule: Rule, capacity: int | No
         if summ.dtype != torch.uint8 or summ.numel() < n * 48 or not summ.is_cuda:
             raise ValueError("summ_out must be a uint8 CUDA tensor of at least n x 48 bytes")
     flags = (CV_EMIT_ALL if emit_all else 0) | (CV_PER_RAY if per_ray else 0) | (CV_GRAPH if graph else 0)
+    if not sync:
+        if out is None:
+            raise ValueError("sync=False needs an output tensor")
+        cap = out.shape[0] if capacity is None else min(capacity, out.shape[0])
+        g, r = grid.c(), rule.c()
+        _check(lib().cv_pair_search(ctx.handle, _dptr(colors), n, C.byref(g), C.byref(r), _dptr(out), cap,
+                                    _dptr(offsets), _dptr(summ), None, flags, _stream()))
+        return SearchResult(out, offsets, summ, None)
     if out is None:
         if capacity is None:
             full = n * grid.per_colour

@@ -245,7 +245,7 @@ int cv_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
                    cv_color_summary* summ, int64_t* total_host, uint32_t flags, void* stream) {
     CV_GUARD_BEGIN
     if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
-    if (!total_host) return fail(CV_EINVAL, "total_host is NULL");
+    if (!total_host && !offsets) return fail(CV_EINVAL, "total_host and offsets are both NULL");
     if (n < 0 || n > 0xFFFFFFFFll) return fail(CV_EINVAL, "n out of range");
     if (capacity < 0) return fail(CV_EINVAL, "capacity < 0");
     if (capacity > 0 && !out) return fail(CV_EINVAL, "out is NULL with capacity > 0");

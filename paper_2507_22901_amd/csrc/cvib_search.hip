@@ -1194,6 +1194,7 @@ int run_pair_search_per_ray(cv_context* ctx, const uint8_t* rgb, int64_t n, cons
         CV_HIP(hipGetLastError());
     }
     if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
+    if (!total_host) return ctx->collect();  // no readback: offsets[n] holds the total
     CV_HIP(hipMemcpyAsync(ctx->host_misc, ctx->misc.ptr, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     CV_HIP(hipStreamSynchronize(s));
     if ((rc = ctx->collect()) != CV_OK) return rc;
@@ -1378,7 +1379,7 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     if (n == 0) {
         if (offsets) hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, offsets, (int64_t)0);
         CV_HIP(hipGetLastError());
-        *total_host = 0;
+        if (total_host) *total_host = 0;
         return CV_OK;
     }
     if ((rc = size_search(ctx, n, gd)) != CV_OK) return rc;
@@ -1430,6 +1431,7 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
         CV_HIP(hipGraphLaunch(ctx->sgraph_exec, s));
         if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
     }
+    if (!total_host) return ctx->collect();  // no readback: offsets[n] holds the total
     CV_HIP(hipMemcpyAsync(ctx->host_misc, ctx->misc.ptr, 3 * sizeof(uint64_t),
                           hipMemcpyDeviceToHost, s));
     CV_HIP(hipStreamSynchronize(s));

@@ -124,7 +124,7 @@ def test_argument_validation(cv):
     g = cv.Grid(0.1, 10, 1.0, 360).c()
     r = cv.Rule().c()
     tot = C.c_int64(0)
-    # negative capacity, capacity without an output array, missing total
+    # negative capacity, capacity without an output array, neither total nor offsets
     assert L.cv_pair_search(dummy, None, 0, C.byref(g), C.byref(r), None, -1, None, None,
                             C.byref(tot), 0, None) == cv.CV_EINVAL
     assert L.cv_pair_search(dummy, None, 0, C.byref(g), C.byref(r), None, 5, None, None,

@@ -482,3 +482,40 @@ def test_search_graph_replays_equal_eager(cv):
     pr = cv.pair_search(x, grid, cv.Rule(50, 0.5), per_ray=True, ctx=ctx, graph=True)
     pe = cv.pair_search(x, grid, cv.Rule(50, 0.5), per_ray=True, ctx=ctx)
     assert pr.total == pe.total and torch.equal(pr.pairs, pe.pairs)
+
+
+def test_search_without_readback(cv):
+    """total_host = NULL: calls only enqueue work.  Several calls back to
+    back on one stream, eager and as graph replays, give the synchronous
+    call's records, offsets (offsets[n] = total) and summaries; with too small
+    an output the records that fit are the first ones and offsets[n] still
+    holds the full total.  Per-ray mode as well."""
+    cols = np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(78, 23)])
+    x = _dev(cols)
+    grid = cv.Grid(0.05, 400, 0.5, 720)
+    ctx = cv.Context(0)
+    n = len(cols)
+    rule = cv.Rule(50, 0.5)
+    ref = cv.pair_search(x, grid, rule, ctx=ctx)
+    out = torch.empty((ref.total + 7, 16), dtype=torch.uint8, device="cuda")
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    summ = torch.empty((n, 48), dtype=torch.uint8, device="cuda")
+    for graph in (False, True):
+        for _ in range(3):
+            r = cv.pair_search(x, grid, rule, out=out, ctx=ctx, graph=graph, offsets=off, summ_out=summ,
+                               sync=False)
+            assert r.total is None
+        torch.cuda.synchronize()
+        assert int(off[n].item()) == ref.total
+        assert torch.equal(out[:ref.total], ref.pairs) and torch.equal(off, ref.offsets)
+        assert torch.equal(summ, ref.summaries)
+    small = torch.zeros((100, 16), dtype=torch.uint8, device="cuda")
+    cv.pair_search(x, grid, rule, out=small, ctx=ctx, offsets=off, summ_out=summ, sync=False)
+    torch.cuda.synchronize()
+    assert int(off[n].item()) == ref.total
+    assert torch.equal(small, ref.pairs[:100])
+    pe = cv.pair_search(x, grid, rule, per_ray=True, ctx=ctx)
+    pout = torch.empty((pe.total, 16), dtype=torch.uint8, device="cuda")
+    cv.pair_search(x, grid, rule, per_ray=True, out=pout, ctx=ctx, offsets=off, summ_out=summ, sync=False)
+    torch.cuda.synchronize()
+    assert int(off[n].item()) == pe.total and torch.equal(pout, pe.pairs)
