@@ -466,11 +466,7 @@ __device__ __forceinline__ bool verify_candidate(const ColorConst& cc, const Ang
     bool ok = false;
     if (__ballot(need) != 0ull) {
         float Vp[3], Vm[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            Vp[k] = code8(fp[k]);
-            Vm[k] = code8(fm[k]);
-        }
+        codes_w(fp, fm, need, rule.clip != 0u, Vp, Vm);
         ok = need && accepts(rule, pattern_of(Vp, Vm, rule));
     }
     return ok;
