@@ -99,12 +99,14 @@ __global__ void k_angle_table(double* __restrict__ tab, int32_t N) {
 // zeroed words (the ticket and totals; the per-colour accumulators).
 __global__ void k_search_prologue(const uint8_t* __restrict__ rgb, ColorConst* __restrict__ cc, int64_t n,
                                   MatArgs m, double* __restrict__ tab, int32_t N, uint64_t* __restrict__ za,
-                                  int64_t na, uint64_t* __restrict__ zb, int64_t nb) {
+                                  int64_t na, uint64_t* __restrict__ zb, int64_t nb, uint64_t* __restrict__ zc,
+                                  int64_t nc) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) cc[k] = color_const(m, rgb + 3 * k);
     angle_entry(tab, N, k);
     if (k < na) za[k] = 0;
     if (k < nb) zb[k] = 0;
+    if (k < nc) zc[k] = 0;
 }
 
 struct SearchArgs {
@@ -562,6 +564,9 @@ struct ReduceArgs {
     // (the write pass's k-th pass); mask_slots = segments per tile (nullable)
     uint64_t* seg_mask;
     int32_t mask_slots, _pad2;
+    // SEG: per-block sums of the scan (kScanChunk segments each), added to
+    // by every tile for its segments (zeroed beforehand; nullable)
+    uint64_t* scan_sums;
 };
 
 // Reduce-only search.  A tile is a chunk of one colour's evaluations (i, j < W)
@@ -793,6 +798,23 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                 uint64_t* mdst = a.seg_mask + c * (int64_t)a.segs_per_colour + seg0;
                 for (int k = tid; k < nseg; k += BLOCK) mdst[k] = s_mask[k];
             }
+            if (a.scan_sums) {
+                // the tile's segments meet at most two scan blocks (nseg <= 2048)
+                const int64_t g0 = c * (int64_t)a.segs_per_colour + seg0;
+                const int64_t q0 = g0 / kScanChunk;
+                uint64_t s0 = 0, s1 = 0;
+                for (int k = tid; k < nseg; k += BLOCK) {
+                    const uint64_t v = (uint64_t)mult * s_seg[k];
+                    if ((g0 + k) / kScanChunk == q0) s0 += v;
+                    else s1 += v;
+                }
+                s0 = wave_sum_u64(s0);
+                s1 = wave_sum_u64(s1);
+                if (lane == 0) {
+                    if (s0) atomicAdd((unsigned long long*)&a.scan_sums[q0], (unsigned long long)s0);
+                    if (s1) atomicAdd((unsigned long long*)&a.scan_sums[q0 + 1], (unsigned long long)s1);
+                }
+            }
         }
         if constexpr (DIRECT) {
             if (tid == 0) {
@@ -848,6 +870,48 @@ __global__ void k_finalize(const ColorConst* __restrict__ ccs, const SumAcc* __r
     if (table) {
         table[c].count = s.count;
         for (int k = 0; k < 36; ++k) table[c].bin_ridx[k] = (uint8_t)min(s.bins[k], 255u);
+    }
+}
+
+// The scan's second half in one launch when the per-block sums fit one block
+// (B <= kScanBlock): every block scans the sums itself and then writes the
+// prefixes and offsets of its chunk as k_scan_apply does; block 0 writes the
+// total; and, given acc and summ, the blocks share out the colours'
+// summaries as k_finalize does.  Launched with B blocks.
+__global__ __launch_bounds__(kScanBlock) void k_scan_finish(
+    const uint32_t* __restrict__ cnt, int64_t T, const uint64_t* __restrict__ sums, int64_t B,
+    uint64_t* __restrict__ prefix, int64_t* __restrict__ offsets, int32_t segs_per_colour, int64_t n,
+    uint64_t* __restrict__ total_out, const ColorConst* __restrict__ ccs, const SumAcc* __restrict__ acc,
+    Geom g, RuleDev rule, TabArgs tab, double ra, double rb, cv_color_summary* __restrict__ summ) {
+    __shared__ uint64_t s_w[kScanBlock / 64];
+    __shared__ uint64_t s_base;
+    const uint64_t sv = (int64_t)threadIdx.x < B ? sums[threadIdx.x] : 0ull;
+    uint64_t grand;
+    const uint64_t sex = block_exclusive_scan(sv, s_w, grand);
+    if (threadIdx.x == blockIdx.x) s_base = sex;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+    uint64_t v = 0;
+    for (int k = 0; k < kScanPer; ++k)
+        if (base + k < T) v += cnt[base + k];
+    uint64_t total;
+    uint64_t run = s_base + block_exclusive_scan(v, s_w, total);
+    for (int k = 0; k < kScanPer; ++k) {
+        const int64_t t = base + k;
+        if (t >= T) break;
+        prefix[t] = run;
+        if (offsets && t % segs_per_colour == 0) offsets[t / segs_per_colour] = (int64_t)run;
+        run += cnt[t];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (offsets) offsets[n] = (int64_t)grand;
+        *total_out = grand;
+    }
+    if (acc && summ) {
+        for (int64_t c = (int64_t)blockIdx.x * kScanBlock + threadIdx.x; c < n; c += (int64_t)gridDim.x * kScanBlock) {
+            const SumAcc sa = acc[c];
+            write_summary(ccs[c], g, rule, tab, ra, rb, sa.count, sa.n_gamut, sa.best_key, sa.pat, summ + c);
+        }
     }
 }
 
@@ -1074,6 +1138,7 @@ ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, c
     a.seg_mask = nullptr;
     a.mask_slots = 0;
     a._pad2 = 0;
+    a.scan_sums = nullptr;
     return a;
 }
 
@@ -1282,12 +1347,20 @@ int enqueue_search(cv_context* ctx, const SearchCall& c, hipStream_t s) {
     tab.N = gd.N;
     tab.dW = direct_rays(gd.ntheta, gd.N, gd.tab_len, (size_t)gd.ntheta * 4);
     tab._pad = 0;
+    // with few scan blocks, the count pass adds up the scan's block sums and
+    // one launch does the rest of the scan and the accumulators' summaries
+    const int64_t nsums = (nsegs + kScanChunk - 1) / kScanChunk;
+    const bool fin_acc = summ && !emit && !pl.direct;  // summaries from the accumulators
+    const bool fused = !emit && nsums >= 1 && nsums <= kScanBlock && (!fin_acc || n <= ((int64_t)1 << 16));
     {
         const int64_t nacc = (emit || !pl.direct) ? n * (int64_t)(sizeof(SumAcc) / 8) : 0;
-        const int64_t threads = std::max<int64_t>(std::max<int64_t>(n, gd.N / 2 + 1), std::max<int64_t>(8, nacc));
+        const int64_t nz = fused ? nsums : 0;
+        const int64_t threads =
+            std::max<int64_t>(std::max<int64_t>(n, gd.N / 2 + 1), std::max<int64_t>(std::max<int64_t>(8, nacc), nz));
         hipLaunchKernelGGL(k_search_prologue, dim3(blocks_for(threads, 256)), dim3(256), 0, s, rgb,
                            (ColorConst*)ctx->colors.ptr, n, mat_args(), (double*)ctx->table.ptr, gd.N,
-                           (uint64_t*)ctx->misc.ptr, (int64_t)8, (uint64_t*)ctx->acc.ptr, nacc);
+                           (uint64_t*)ctx->misc.ptr, (int64_t)8, (uint64_t*)ctx->acc.ptr, nacc,
+                           (uint64_t*)ctx->scan.ptr, nz);
         CV_HIP(hipGetLastError());
     }
 
@@ -1326,6 +1399,7 @@ int enqueue_search(cv_context* ctx, const SearchCall& c, hipStream_t s) {
     ra.segs_per_colour = spc;
     ra.seg_mask = (uint64_t*)ctx->seg_mask.ptr;
     ra.mask_slots = (int32_t)((pl.chunk + seg_len - 1) / seg_len);
+    ra.scan_sums = fused ? (uint64_t*)ctx->scan.ptr : nullptr;
     if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
     if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
     if (emit) {
@@ -1336,9 +1410,17 @@ int enqueue_search(cv_context* ctx, const SearchCall& c, hipStream_t s) {
     if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
     // segment counts -> output offsets
     uint64_t* misc = (uint64_t*)ctx->misc.ptr;
-    if ((rc = run_scan_counts(ctx, a.seg_cnt, nsegs, (uint64_t*)ctx->seg_prefix.ptr, offsets, spc,
-                              n, misc + 2, s)) != CV_OK)
+    if (fused) {
+        uint64_t* sums = (uint64_t*)ctx->scan.ptr;
+        hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)nsums), dim3(kScanBlock), 0, s, a.seg_cnt, nsegs,
+                           (const uint64_t*)sums, nsums, (uint64_t*)ctx->seg_prefix.ptr, offsets, spc, n, misc + 2,
+                           a.cc, fin_acc ? (const SumAcc*)ctx->acc.ptr : (const SumAcc*)nullptr, a.g, rd, tab,
+                           gd.ra, gd.rb, fin_acc ? summ : (cv_color_summary*)nullptr);
+        CV_HIP(hipGetLastError());
+    } else if ((rc = run_scan_counts(ctx, a.seg_cnt, nsegs, (uint64_t*)ctx->seg_prefix.ptr, offsets, spc,
+                                     n, misc + 2, s)) != CV_OK) {
         return rc;
+    }
     // write pass
     if (a.capacity > 0) {
         if ((rc = ctx->mark(CV_TIME_WRITE, 0, s)) != CV_OK) return rc;
@@ -1355,7 +1437,7 @@ int enqueue_search(cv_context* ctx, const SearchCall& c, hipStream_t s) {
             if ((rc = zero_u64(rb.misc, 1, s)) != CV_OK) return rc;
             if ((rc = launch_reduce(ctx, rb, false, false, sym, false, s)) != CV_OK) return rc;
         }
-        if (emit || !pl.direct) {
+        if ((emit || !pl.direct) && !(fused && fin_acc)) {
             hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 128)), dim3(128), 0, s, a.cc,
                                (const SumAcc*)ctx->acc.ptr, n, a.g, rd, tab, gd.ra, gd.rb, summ,
                                (cv_table_row*)nullptr);
