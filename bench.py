@@ -50,7 +50,7 @@ FLOPS_CODE = 33
 # a 256 MiB device copy; VALU issue = SQ_INSTS_VALU x 4 cycles over 1024 SIMDs
 # x GRBM_GUI_ACTIVE cycles.  Valid only for the kernel sources they were
 # measured on (their digest).
-MEASURED_COUNTERS = {"sources_sha256": "067a118a8e8739d7b589ba5ddb5e29bfd8bd848379e7c0e2d73152370502159b", "traffic_bytes": 28580275, "valu_issue": 0.610}
+MEASURED_COUNTERS = {"sources_sha256": "e244444c73c54b909e33307b4893c6ddbe62a6f3bdb23c4221b8844eb69f3d5f", "traffic_bytes": 25086878, "valu_issue": 0.595}
 KERNEL_SOURCES = ("cvib_search.hip", "cvib_device.h", "cvib_kernels.h")
 
 
