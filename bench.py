@@ -419,12 +419,14 @@ def main():
     for ph in (cv.CV_TIME_EVAL, cv.CV_TIME_WRITE, cv.CV_TIME_CALL):
         ctx.kernel_time(ph, reset=True)
     ctx.skipped(reset=True)
+    ctx.no_high(reset=True)
     for _ in range(max(3, min(args.steps, 20))):
         step(graph=False, sync=True)
     t_eval, n_eval = ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
     t_write, n_write = ctx.kernel_time(cv.CV_TIME_WRITE, reset=True)
     t_call, n_call = ctx.kernel_time(cv.CV_TIME_CALL, reset=True)
     skipped = ctx.skipped(reset=True) // max(n_eval, 1)
+    no_high = ctx.no_high(reset=True) // max(n_eval, 1)
     ctx.set_timing(False)
     total = res.total
     summ = cv.as_records(res.summaries, cv.SUMMARY_DTYPE)
@@ -436,7 +438,8 @@ def main():
     decided = pairs_per_step // 2 if half_turn else pairs_per_step
     evals = decided - skipped
     gamut_evals = int(summ["n_gamut"].sum()) // (2 if half_turn else 1)
-    flops = FLOPS_GEOM * evals + FLOPS_CODE * gamut_evals
+    # in-gamut pairs of steps proven to hold no high channel are not encoded
+    flops = FLOPS_GEOM * evals + FLOPS_CODE * (gamut_evals - no_high)
     k_eval = t_eval / max(n_eval, 1)
     k_write = t_write / max(n_write, 1)
     achieved = flops / (k_eval * 1e-3)
@@ -481,6 +484,7 @@ def main():
             "evaluated_pairs": evals,
             "skipped_by_gamut_cells": skipped,
             "in_gamut_evaluations": gamut_evals,
+            "in_gamut_not_encoded": no_high,
         },
         "write_pass": {"kernel": "k_pair_pass (write)", "ms": k_write,
                        "GBps": 16.0 * total / (k_write * 1e-3) / 1e9 if k_write > 0 else None,

@@ -310,9 +310,17 @@ int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, cons
  * while timing was on, since context creation
  * or the last reset (reset != 0 clears it after reading); it synchronises the
  * device.  Errors: CV_EINVAL (null ctx / output), CV_EHIP.
+ * With the cells on, the reduce-only kernel over chunks of rows (the count
+ * pass of cv_pair_search among them) also bounds the 8-bit codes of each
+ * open step: an accepted pattern needs a channel that changes by more than
+ * v_th codes, and where the bound shows that no channel can, the step's
+ * pairs are only counted for n_gamut, without the encode (Section 3's
+ * predicate cannot hold there).  cv_context_no_high returns, like
+ * cv_context_skipped, the number of in-gamut pairs counted that way.
  */
 int cv_context_set_gamut_cells(cv_context* ctx, int on);
 int cv_context_skipped(cv_context* ctx, int64_t* skipped_host, int reset);
+int cv_context_no_high(cv_context* ctx, int64_t* in_gamut_host, int reset);
 
 /*
  * Kernel choice for the per-colour resolve (cv_frames_resolve and the exact

@@ -73,7 +73,7 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_surrogate_infer", "cv_frames_surrogate", "cv_context_set_autotune",
            "cv_context_set_resolve_variant", "cv_context_resolve_variant", "cv_pair_reduce_rules",
            "cv_pair_reduce_csr", "cv_context_set_gamut_cells", "cv_context_skipped",
-           "cv_mlp_set_first_sine", "cv_mlp_first_sine", "cv_permute_ids")
+           "cv_mlp_set_first_sine", "cv_mlp_first_sine", "cv_permute_ids", "cv_context_no_high")
 CV_NO_FALLBACK = 0x4
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
 CV_RESOLVED_SURROGATE, CV_RESOLVED_EXACT, CV_RESOLVED_NONE = 0, 1, 2
@@ -136,6 +136,7 @@ def lib() -> C.CDLL:
         L.cv_pair_reduce_csr.argtypes = [P, P, P, I64, P, P]
         L.cv_context_set_gamut_cells.argtypes = [P, C.c_int]
         L.cv_context_skipped.argtypes = [P, C.POINTER(I64), C.c_int]
+        L.cv_context_no_high.argtypes = [P, C.POINTER(I64), C.c_int]
         for name in EXPORTS:
             if name != "cv_last_error":
                 getattr(L, name).restype = C.c_int
@@ -207,6 +208,13 @@ class Context:
         """Candidates skipped by the gamut cells in calls made while timing was on."""
         v = C.c_int64(0)
         _check(lib().cv_context_skipped(self.handle, C.byref(v), int(bool(reset))))
+        return v.value
+
+    def no_high(self, reset: bool = False) -> int:
+        """In-gamut pairs of steps proven to hold no high channel (counted,
+        not encoded) in calls made while timing was on."""
+        v = C.c_int64(0)
+        _check(lib().cv_context_no_high(self.handle, C.byref(v), int(bool(reset))))
         return v.value
 
     def set_autotune(self, on: bool = True):

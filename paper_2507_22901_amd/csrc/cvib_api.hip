@@ -464,10 +464,11 @@ int cv_context_set_timing(cv_context* ctx, int on) {
             for (hipEvent_t& e : pr) CV_HIP(hipEventCreate(&e));
     }
     if (on && !ctx->stats.ptr) {
-        int rc = ctx->ensure(ctx->stats, 64);
+        int rc = ctx->ensure(ctx->stats, 128);
         if (rc != CV_OK) return rc;
-        CV_HIP(hipMemset(ctx->stats.ptr, 0, 64));
+        CV_HIP(hipMemset(ctx->stats.ptr, 0, 128));
         ctx->stats_base = 0;
+        ctx->no_high_base = 0;
     }
     ctx->timing = on != 0;
     return CV_OK;
@@ -495,6 +496,23 @@ int cv_context_skipped(cv_context* ctx, int64_t* skipped_host, int reset) {
     }
     *skipped_host = (int64_t)(v - ctx->stats_base);
     if (reset) ctx->stats_base = v;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_context_no_high(cv_context* ctx, int64_t* in_gamut_host, int reset) {
+    CV_GUARD_BEGIN
+    if (!ctx || !in_gamut_host) return fail(CV_EINVAL, "null argument");
+    DeviceGuard dg(ctx->device);
+    uint64_t v = 0;
+    if (ctx->stats.ptr) {
+        uint64_t w[16];
+        CV_HIP(hipDeviceSynchronize());
+        CV_HIP(hipMemcpy(w, ctx->stats.ptr, sizeof(w), hipMemcpyDeviceToHost));
+        for (int k = 8; k < 16; ++k) v += w[k];
+    }
+    *in_gamut_host = (int64_t)(v - ctx->no_high_base);
+    if (reset) ctx->no_high_base = v;
     return CV_OK;
     CV_GUARD_END
 }

@@ -196,6 +196,7 @@ struct cv_context {
     bool gamut_cells = true;
     cvib::Buffer stats;
     uint64_t stats_base = 0;
+    uint64_t no_high_base = 0;
     // per-colour resolve kernel choice: forced (-1 = none), or tuned per grid shape
     bool autotune = false;
     int resolve_forced = -1;

@@ -242,24 +242,66 @@ constexpr int32_t kCellMinRays = 128;
 // rays per row.
 constexpr int32_t kBandMinRays = 32;
 
-__device__ inline bool colour_out(const Geom& g, const ColorConst& cc, double xlo, double xhi, double zlo,
-                                  double zhi) {
+// Ranges [lo[k], hi[k]] of the three linear channels of one colour over the
+// f-space box [xlo, xhi] x [zlo, zhi].
+__device__ inline void colour_bounds(const Geom& g, const ColorConst& cc, double xlo, double xhi, double zlo,
+                                     double zhi, double lo[3], double hi[3]) {
     const double gx0 = finv(xlo), gx1 = finv(xhi), gz0 = finv(zlo), gz1 = finv(zhi);
-    bool out = false;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double ax0 = g.A[k] * gx0, ax1 = g.A[k] * gx1, cz0 = g.C[k] * gz0, cz1 = g.C[k] * gz1;
-        const double lo = cc.B[k] + fmin(ax0, ax1) + fmin(cz0, cz1);
-        const double hi = cc.B[k] + fmax(ax0, ax1) + fmax(cz0, cz1);
-        out = out || hi < -kCellMargin || lo > 1.0 + kCellMargin;
+        lo[k] = cc.B[k] + fmin(ax0, ax1) + fmin(cz0, cz1);
+        hi[k] = cc.B[k] + fmax(ax0, ax1) + fmax(cz0, cz1);
     }
+}
+
+__device__ inline bool bounds_out(const double lo[3], const double hi[3]) {
+    bool out = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out = out || hi[k] < -kCellMargin || lo[k] > 1.0 + kCellMargin;
     return out;
 }
 
-// The same with the end rays' sin and cos given (j0 <= j1 < 2N).
+__device__ inline bool colour_out(const Geom& g, const ColorConst& cc, double xlo, double xhi, double zlo,
+                                  double zhi) {
+    double lo[3], hi[3];
+    colour_bounds(g, cc, xlo, xhi, zlo, zhi, lo, hi);
+    return bounds_out(lo, hi);
+}
+
+// Whether a cell may hold a pair with some channel changing by more than
+// v_th codes (a "high" channel, which every accepted pattern has), given the
+// ranges of both colours' linear channels.  Only pairs with both colours in
+// gamut can be accepted, so the ranges are cut to [0, 1] (widened by
+// kCellMargin first); the 8-bit code rint(encode(l)) is increasing in l, so
+// a channel's change is at most encode(hi of one colour) - encode(lo of the
+// other) + 1.  The test asks for at most v_th - 1.5 before that + 1, which
+// leaves half a code for the FP32 encode's own error.
+__device__ inline void cut_unit(const double lo[3], const double hi[3], float l[3], float h[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        l[k] = (float)fmin(fmax(lo[k] - kCellMargin, 0.0), 1.0);
+        h[k] = (float)fmin(fmax(hi[k] + kCellMargin, 0.0), 1.0);
+    }
+}
+
+__device__ inline bool bounds_high(const float pl[3], const float ph[3], const float ml[3], const float mh[3],
+                                   float v_th) {
+    bool high = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float d = fmaxf(encode255(ph[k]) - encode255(ml[k]), encode255(mh[k]) - encode255(pl[k]));
+        high = high || d > v_th - 1.5f;
+    }
+    return high;
+}
+
+// The gamut test of a cell with the end rays' sin and cos given (j0 <= j1 <
+// 2N); with `high` given, it also receives bounds_high of the cell.
 __device__ inline bool cell_out_of_gamut_ends(const ColorConst& cc, const Geom& g, int32_t N_, double ra,
                                               double rb, int32_t i0, int32_t i1, int32_t j0, int32_t j1,
-                                              double s0, double c0, double s1, double c1) {
+                                              double s0, double c0, double s1, double c1,
+                                              const RuleDev* rule = nullptr, bool* high = nullptr) {
     double slo = fmin(s0, s1), shi = fmax(s0, s1), clo = fmin(c0, c1), chi = fmax(c0, c1);
     const int64_t N = N_, J0 = 4 * (int64_t)j0, J1 = 4 * (int64_t)j1;
     if ((J0 <= N && N <= J1) || (J0 <= 5 * N && 5 * N <= J1)) shi = 1.0;   // 90, 450 deg
@@ -270,16 +312,25 @@ __device__ inline bool cell_out_of_gamut_ends(const ColorConst& cc, const Geom& 
     const double dxlo = fmin((r0 * ra) * slo, (r1 * ra) * slo), dxhi = fmax((r0 * ra) * shi, (r1 * ra) * shi);
     const double dzlo = fmin((r0 * rb) * clo, (r1 * rb) * clo), dzhi = fmax((r0 * rb) * chi, (r1 * rb) * chi);
     // + colour: (fx0 + dx, fz0 - dz); - colour: (fx0 - dx, fz0 + dz)
-    return colour_out(g, cc, cc.fx0 + dxlo, cc.fx0 + dxhi, cc.fz0 - dzhi, cc.fz0 - dzlo) ||
-           colour_out(g, cc, cc.fx0 - dxhi, cc.fx0 - dxlo, cc.fz0 + dzlo, cc.fz0 + dzhi);
+    double lo[3], hi[3];
+    float pl[3], ph[3], ml[3], mh[3];
+    colour_bounds(g, cc, cc.fx0 + dxlo, cc.fx0 + dxhi, cc.fz0 - dzhi, cc.fz0 - dzlo, lo, hi);
+    bool out = bounds_out(lo, hi);
+    cut_unit(lo, hi, pl, ph);
+    colour_bounds(g, cc, cc.fx0 - dxhi, cc.fx0 - dxlo, cc.fz0 + dzlo, cc.fz0 + dzhi, lo, hi);
+    out = out || bounds_out(lo, hi);
+    cut_unit(lo, hi, ml, mh);
+    if (high) *high = !out && bounds_high(pl, ph, ml, mh, rule->v_th);
+    return out;
 }
 
 __device__ inline bool cell_out_of_gamut(const ColorConst& cc, const Geom& g, const Angles& ang, double ra,
-                                         double rb, int32_t i0, int32_t i1, int32_t j0, int32_t j1) {
+                                         double rb, int32_t i0, int32_t i1, int32_t j0, int32_t j1,
+                                         const RuleDev* rule = nullptr, bool* high = nullptr) {
     double s0, c0, s1, c1;
     ang.get(j0, s0, c0);
     ang.get(j1, s1, c1);
-    return cell_out_of_gamut_ends(cc, g, ang.N, ra, rb, i0, i1, j0, j1, s0, c0, s1, c1);
+    return cell_out_of_gamut_ends(cc, g, ang.N, ra, rb, i0, i1, j0, j1, s0, c0, s1, c1, rule, high);
 }
 
 // Lane masks of the per-channel classification of a wave's candidates:
@@ -354,9 +405,12 @@ __device__ __forceinline__ void divmod_small(int32_t x, int32_t d, float inv_d, 
 // In half-turn mode (sym: W = N/2) ray j of a row is the mirror of ray j + W,
 // so a step that runs into the next row covers, for both rows, the angles
 // from ray ja up to ray W + jb: one test.
+// With `high` given (and the rule), *high receives whether an open step may
+// hold a pair with a high channel (bounds_high of its cells); a step that
+// may not holds no survivor, and only its gamut count is needed.
 __device__ inline bool step_open(const ColorConst& cc, const Geom& g, const Angles& ang, double ra, double rb,
                                  int32_t W, float inv_W, int32_t row0, int32_t jb0, int32_t e0, int32_t e1,
-                                 bool any, bool sym = false) {
+                                 bool any, bool sym = false, const RuleDev* rule = nullptr, bool* high = nullptr) {
     int32_t ia, ja, ib, jb;
     divmod_small(jb0 + e0, W, inv_W, ia, ja);
     divmod_small(jb0 + e1, W, inv_W, ib, jb);
@@ -371,13 +425,20 @@ __device__ inline bool step_open(const ColorConst& cc, const Geom& g, const Angl
             s1 = -s1;
             c1 = -c1;
         }
-        return any && !cell_out_of_gamut_ends(cc, g, ang.N, ra, rb, ia, ib, ja, two ? W + jb : jb, s0, c0, s1, c1);
+        return any && !cell_out_of_gamut_ends(cc, g, ang.N, ra, rb, ia, ib, ja, two ? W + jb : jb, s0, c0, s1, c1,
+                                              rule, high);
     }
-    bool open = !cell_out_of_gamut(cc, g, ang, ra, rb, ia, many ? ib : ia, many ? 0 : ja, ib > ia ? W - 1 : jb);
+    bool h1 = true;
+    bool open = !cell_out_of_gamut(cc, g, ang, ra, rb, ia, many ? ib : ia, many ? 0 : ja, ib > ia ? W - 1 : jb,
+                                   rule, high ? &h1 : nullptr);
+    bool hi = open && h1;
     if (__ballot(any && two) != 0ull) {
-        const bool o2 = !cell_out_of_gamut(cc, g, ang, ra, rb, ib, ib, 0, jb);
+        bool h2 = true;
+        const bool o2 = !cell_out_of_gamut(cc, g, ang, ra, rb, ib, ib, 0, jb, rule, high ? &h2 : nullptr);
         open = open || (two && o2);
+        hi = hi || (two && o2 && h2);
     }
+    if (high) *high = hi;
     return open && any;
 }
 

@@ -559,7 +559,8 @@ struct ReduceArgs {
     // gamut cells: one per wave step, decided per tile into cell_words
     // 64-bit masks per wave (0 = off)
     int32_t cell_words, _pad;
-    uint64_t* stats;          // [0..7]: candidates skipped by the cells, summed (nullable)
+    uint64_t* stats;          // [0..7]: candidates skipped by the cells; [8..15]: in-gamut pairs of steps
+                              // proven to hold no high channel (not encoded); summed (nullable)
     // SEG: per segment, bit k = survivors among its evaluations 64k..64k+63
     // (the write pass's k-th pass); mask_slots = segments per tile (nullable)
     uint64_t* seg_mask;
@@ -599,10 +600,13 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
     uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW);
     uint64_t* s_open =
         reinterpret_cast<uint64_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW + (TABLE ? (a.W + 1) / 2 : 0));
-    uint64_t* s_mask = s_open + NW * a.cell_words;  // SEG with seg_mask
+    // steps that may hold a high channel (the rest are only counted for n_gamut)
+    uint64_t* s_full = s_open + NW * a.cell_words;
+    uint64_t* s_mask = s_full + NW * a.cell_words;  // SEG with seg_mask
     const uint32_t mult = SYM ? 2u : 1u;
     const bool clip = a.rule.clip != 0u;
     uint64_t skipped = 0;  // lane's share over the block's tiles
+    uint64_t no_high = 0;  // in-gamut pairs of steps without a high channel (lane 0)
 
     for (;;) {
         if (tid == 0) s_tick = (int64_t)atomicAdd((unsigned long long*)&a.misc[0], 1ull);
@@ -615,7 +619,7 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                 for (int k = tid; k < a.mask_slots; k += BLOCK) s_mask[k] = 0;
         }
         if constexpr (CELLS && !(DIRECT && !SEG)) {
-            for (int k = tid; k < NW * a.cell_words; k += BLOCK) s_open[k] = 0;
+            for (int k = tid; k < 2 * NW * a.cell_words; k += BLOCK) s_open[k] = 0;
         }
         __syncthreads();
         const int64_t t = uniform_i64(s_tick);
@@ -642,11 +646,14 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                 const int32_t e0 = it * BLOCK + wv * 64;
                 const bool any = sidx < iters * NW && e0 < len;
                 const int32_t e1 = min(e0 + 63, len - 1);
+                bool high = true;
                 const bool open = step_open(cc, a.g, ang, a.ra, a.rb, a.W, a.inv_W, row0, jb0, min(e0, len - 1),
-                                            e1, any, SYM);
+                                            e1, any, SYM, &a.rule, &high);
                 if (any && !open) skipped += (uint64_t)(e1 - e0 + 1);
                 if (open)
                     atomicOr((unsigned long long*)&s_open[wv * a.cell_words + (it >> 6)], 1ull << (it & 63));
+                if (open && high)
+                    atomicOr((unsigned long long*)&s_full[wv * a.cell_words + (it >> 6)], 1ull << (it & 63));
             }
             __syncthreads();
         }
@@ -706,6 +713,19 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                 }
             }
         };
+        // a step proven to hold no high channel: only its in-gamut pairs are
+        // counted (n_gamut); none can survive, so nothing is encoded
+        [[maybe_unused]] auto gamut_step = [&](int32_t i, int32_t j, bool live) {
+            double sn, co;
+            ang.get(j, sn, co);
+            const double rr = (double)(i + 1);
+            float fp[3], fm[3];
+            pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm, cube);
+            const uint32_t nb =
+                (uint32_t)__builtin_popcountll(__ballot(live && in_unit_cube(fp) && in_unit_cube(fm)));
+            ng += nb;
+            if (lane == 0) no_high += nb;
+        };
         if constexpr (CELLS && DIRECT && !SEG) {
             // One whole colour, counts and maxima only: the band order (16
             // rows, ray by ray) gives steps of 4 rays by 16 rows, decided 64
@@ -736,13 +756,16 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
             // the open steps of this wave, (i, j) from the step index
             for (int32_t word = 0; word < nwords; ++word) {
                 uint64_t steps = uniform_u64(s_open[w * a.cell_words + word]);
+                const uint64_t full = uniform_u64(s_full[w * a.cell_words + word]);
                 while (steps) {
-                    const int32_t it = word * 64 + (int32_t)__builtin_ctzll(steps);
+                    const int32_t bit = (int32_t)__builtin_ctzll(steps);
+                    const int32_t it = word * 64 + bit;
                     steps &= steps - 1ull;
                     const int32_t e = it * BLOCK + tid;
                     int32_t i, j;
                     divmod_small(jb0 + min(e, len - 1), a.W, a.inv_W, i, j);
-                    step(i + row0, j, e, e < len);
+                    if ((full >> bit) & 1ull) step(i + row0, j, e, e < len);
+                    else gamut_step(i + row0, j, e < len);
                 }
             }
         } else {
@@ -844,14 +867,21 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
     }
     // every thread left the loop at the same ticket, after a barrier
     if (a.stats) {
-        __shared__ uint64_t s_skip[NW];
+        __shared__ uint64_t s_skip[NW], s_noh[NW];
         for (int o = 32; o > 0; o >>= 1) skipped += (uint64_t)__shfl_xor((unsigned long long)skipped, o, 64);
-        if (lane == 0) s_skip[w] = skipped;
+        if (lane == 0) {
+            s_skip[w] = skipped;
+            s_noh[w] = no_high;
+        }
         __syncthreads();
         if (tid == 0) {
-            uint64_t sum = 0;
-            for (int q = 0; q < NW; ++q) sum += s_skip[q];
+            uint64_t sum = 0, nh = 0;
+            for (int q = 0; q < NW; ++q) {
+                sum += s_skip[q];
+                nh += s_noh[q];
+            }
             if (sum) atomicAdd((unsigned long long*)&a.stats[blockIdx.x & 7u], (unsigned long long)sum);
+            if (nh) atomicAdd((unsigned long long*)&a.stats[8 + (blockIdx.x & 7u)], (unsigned long long)nh);
         }
     }
 }
@@ -1015,7 +1045,7 @@ int launch_pass(cv_context* ctx, const SearchArgs& a, bool emit, bool summ, bool
 constexpr int kReduceBlock = 512;
 constexpr int kReduceBlockDirect = 256;
 // LDS bytes of a tile's open-step masks.
-size_t cell_bytes(const ReduceArgs& a) { return (size_t)(a.block / 64) * a.cell_words * sizeof(uint64_t); }
+size_t cell_bytes(const ReduceArgs& a) { return 2 * (size_t)(a.block / 64) * a.cell_words * sizeof(uint64_t); }
 constexpr int reduce_block(bool direct) { return direct ? kReduceBlockDirect : kReduceBlock; }
 
 template <bool TABLE, bool DIRECT, bool SYM, bool SEG>

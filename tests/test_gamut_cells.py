@@ -194,3 +194,53 @@ def test_gamut_cell_intervals_contain_every_candidate(oracle):
                     for k in range(3):
                         lo, hi = iv[colour][k]
                         assert lo - 1e-12 <= vals[k] <= hi + 1e-12, (kind, blk[1], i, j, colour, k)
+
+
+def _encode255(l):
+    """sRGB encode in 0..255 code units (IEC 61966-2-1), FP64."""
+    l = np.asarray(l, np.float64)
+    return np.where(l <= 0.0031308, 255.0 * 12.92 * l, 255.0 * (1.055 * np.power(np.maximum(l, 0.0), 1 / 2.4) - 0.055))
+
+
+def _no_high(iv, v_th):
+    """The kernels' second test of an open cell: with both colours' channel
+    ranges cut to [0, 1] (after widening by the margin), whether every
+    channel's code change stays at most v_th - 1.5 + 1 below a high one."""
+    (p, m) = iv
+    for k in range(3):
+        pl = min(max(p[k][0] - MARGIN, 0.0), 1.0); ph = min(max(p[k][1] + MARGIN, 0.0), 1.0)
+        ml = min(max(m[k][0] - MARGIN, 0.0), 1.0); mh = min(max(m[k][1] + MARGIN, 0.0), 1.0)
+        d = max(_encode255(ph) - _encode255(ml), _encode255(mh) - _encode255(pl))
+        if d > v_th - 1.5:
+            return False
+    return True
+
+
+def test_high_channel_bound_is_sound_and_useful(oracle):
+    """Cells where no channel can change by more than v_th codes: no pair of
+    such a cell with both colours in gamut has a high channel (so none can
+    carry an accepted pattern), while most small-radius cells are proven."""
+    rng = np.random.default_rng(16)
+    cols = np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(17, 9)])
+    dr, nr, dth, nt = 0.25, 200, 1.0, 360
+    W_ = nt // 2
+    v_th = 50
+    proven = small_open = 0
+    for rgb in cols:
+        bd = _Bound(oracle, rgb[None, :], dr, dth)
+        for blk in _blocks(rng, nr, W_):
+            kind, cand = blk[0], blk[2]
+            if kind == "two rows" or bd.out(*blk[1]):
+                continue
+            idx = np.array([(0, i, j) for i, j in cand], np.int64)
+            ev = oracle.eval_list(rgb[None, :], idx, (dr, nr, dth, nt), (v_th, 0.5, 0x7F))
+            both = ev["gamut"] == 3
+            d = np.abs(ev["Vp"].astype(int) - ev["Vm"].astype(int)).max(axis=1)
+            small = blk[1][1] < 40
+            small_open += small
+            if _no_high(bd.intervals(*blk[1]), v_th):
+                proven += small
+                assert not (both & (d > v_th)).any(), (kind, blk[1])
+                assert not (ev["valid"] != 0).any(), (kind, blk[1])
+    assert small_open > 50
+    assert proven > 0.5 * small_open, (proven, small_open)
