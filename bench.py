@@ -43,6 +43,14 @@ HBM_PEAK = 8e12
 #   channel differences .................................... 3 sub      =  3
 FLOPS_GEOM = 40
 FLOPS_CODE = 33
+# and the interval proof of every wave step of 64 decided candidates (one
+# cell per step), the part that every test runs:
+#   displacement ranges: 2 radii x (ra, rb), x 4 sine/cosine ends .. 12 mul  = 12
+#   f(X), f(Z) ranges of both colours ........................... 8 add  =  8
+#   inverse companding of the 8 range ends, cube branch .......... 16 mul = 16
+#   channel bounds, 2 colours x 3 channels x (4 mul + 4 add) ...........   = 48
+# (the code bounds of the open steps, 12 encodes more, are not counted)
+FLOPS_CELL = 84
 
 # Counter figures of the count pass on this workload, from rocprofv3 runs of
 # `bench.py --only nine` (profiles/search_nine_colours.md): HBM traffic =
@@ -85,8 +93,8 @@ def parse():
     return ap.parse_args()
 
 
-def _alu_roofline(kernel, ms, evals, gamut_evals):
-    flops = FLOPS_GEOM * evals + FLOPS_CODE * gamut_evals
+def _alu_roofline(kernel, ms, evals, gamut_evals, cell_tests=0):
+    flops = FLOPS_GEOM * evals + FLOPS_CODE * gamut_evals + FLOPS_CELL * cell_tests
     achieved = flops / (ms * 1e-3)
     return {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12,
             "peak": VALU_FMA_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / VALU_FMA_PEAK,
@@ -139,8 +147,8 @@ def bench_frames(cv, W, torch, steps):
         "pixels_per_s": npix / (ms * 1e-3), "pairs_per_s": n * g.per_colour / (ms * 1e-3),
         "ms_per_call": ms, "calls": steps, "resolved_pixels": int(out.resolved.item()),
         "resolve_kernel_ms": t_res,
-        "roofline": dict(_alu_roofline("k_colour_resolve", t_res, evals, gamut), decided_pairs=decided,
-                         skipped_by_gamut_cells=skipped),
+        "roofline": dict(_alu_roofline("k_colour_resolve", t_res, evals, gamut, -(-decided // 64)),
+                         decided_pairs=decided, skipped_by_gamut_cells=skipped),
     }
 
 
@@ -283,28 +291,38 @@ def bench_cube(cv, W, torch, steps):
     del ids
     ctx = cv.context(0)
     ctx.set_timing(True)
+    # one call with summaries for the in-gamut count (n_gamut) and the
+    # in-gamut pairs of steps without a high channel (counted, not encoded)
     ctx.skipped(reset=True)
-    summ, tab = cv.pair_reduce(cols, grid, rule, table=True, ctx=ctx)
+    ctx.no_high(reset=True)
+    summ, _ = cv.pair_reduce(cols, grid, rule, table=True, ctx=ctx)
+    torch.cuda.synchronize()
+    no_high = ctx.no_high(reset=True)
+    # the table alone, as timed: steps without a high channel are skipped too
+    ctx.skipped(reset=True)
+    _, tab = cv.pair_reduce(cols, grid, rule, summaries=False, table=True, ctx=ctx)
     torch.cuda.synchronize()
     skipped = ctx.skipped(reset=True)
     ctx.set_timing(False)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(steps):
-        cv.pair_reduce(cols, grid, rule, table=True, ctx=ctx)
+        cv.pair_reduce(cols, grid, rule, summaries=False, table=True, ctx=ctx)
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
     ng = int(summ[:, 4:8].contiguous().view(torch.int32).to(torch.int64).sum())
     decided = (1 << 24) * g.nr * (g.ntheta // 2)
-    evals = decided - skipped  # the rest lie in steps proven out of gamut
+    evals = decided - skipped  # the rest lie in steps proven out of gamut or without a high channel
     return {
         "workload": "all 2^24 colours; r = 0.25..50 step 0.25 (200) x theta = 0..358 deg step 2 (180)",
         "colours_per_s": (1 << 24) / (ms * 1e-3), "pairs_per_s": (1 << 24) * g.per_colour / (ms * 1e-3),
         "ms_per_call": ms, "calls": steps,
         "feasible_colours": int((tab[:, :4].contiguous().view(torch.int32) > 0).sum()),
-        "roofline_whole_call": dict(_alu_roofline("k_pair_reduce<TABLE> (whole call)", ms, evals, ng // 2),
-                                    decided_pairs=decided, skipped_by_gamut_cells=skipped),
+        "roofline_whole_call": dict(_alu_roofline("k_pair_reduce<TABLE> (whole call)", ms, evals, ng // 2 - no_high,
+                                                  -(-decided // 64)),
+                                    decided_pairs=decided, skipped_by_gamut_cells=skipped,
+                                    in_gamut_without_high_channel=no_high),
     }
 
 
@@ -378,9 +396,9 @@ def main():
     off = torch.empty(cols.shape[0] + 1, dtype=torch.int64, device="cuda")
     summ_buf = torch.empty((cols.shape[0], 48), dtype=torch.uint8, device="cuda")
 
-    def step(graph=False, sync=False):
+    def step(graph=False, sync=False, ngamut=False):
         return cv.pair_search(cols, grid, rule, out=out, ctx=ctx, graph=graph, offsets=off, summ_out=summ_buf,
-                              sync=sync)
+                              sync=sync, ngamut=ngamut)
 
     for _ in range(args.warmup):
         step()
@@ -418,28 +436,36 @@ def main():
     ctx.set_timing(True)
     for ph in (cv.CV_TIME_EVAL, cv.CV_TIME_WRITE, cv.CV_TIME_CALL):
         ctx.kernel_time(ph, reset=True)
-    ctx.skipped(reset=True)
+    # one call with n_gamut: the in-gamut pairs of steps without a high
+    # channel, which the timed calls skip (they are not encoded either way)
     ctx.no_high(reset=True)
+    step(graph=False, sync=True, ngamut=True)
+    no_high = ctx.no_high(reset=True)
+    for ph in (cv.CV_TIME_EVAL, cv.CV_TIME_WRITE, cv.CV_TIME_CALL):
+        ctx.kernel_time(ph, reset=True)
+    ctx.skipped(reset=True)
     for _ in range(max(3, min(args.steps, 20))):
         step(graph=False, sync=True)
     t_eval, n_eval = ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
     t_write, n_write = ctx.kernel_time(cv.CV_TIME_WRITE, reset=True)
     t_call, n_call = ctx.kernel_time(cv.CV_TIME_CALL, reset=True)
     skipped = ctx.skipped(reset=True) // max(n_eval, 1)
-    no_high = ctx.no_high(reset=True) // max(n_eval, 1)
     ctx.set_timing(False)
     total = res.total
-    summ = cv.as_records(res.summaries, cv.SUMMARY_DTYPE)
+    summ = cv.as_records(first.summaries, cv.SUMMARY_DTYPE)  # with n_gamut
     ms_per_step = ms / args.steps
     value = pairs_per_step / (ms_per_step * 1e-3)
     half_turn = g.ntheta * g.dtheta_deg == 360.0
     # candidates the count pass decides: the evaluated ones and those in
-    # gamut cells proven out of gamut (skipped); only evaluated work counts
+    # cells proven out of gamut or without a high channel (skipped); only
+    # evaluated work counts
     decided = pairs_per_step // 2 if half_turn else pairs_per_step
     evals = decided - skipped
     gamut_evals = int(summ["n_gamut"].sum()) // (2 if half_turn else 1)
-    # in-gamut pairs of steps proven to hold no high channel are not encoded
-    flops = FLOPS_GEOM * evals + FLOPS_CODE * (gamut_evals - no_high)
+    # in-gamut pairs of steps proven to hold no high channel are not encoded;
+    # every step of 64 decided candidates is one cell test
+    cell_tests = -(-decided // 64)
+    flops = FLOPS_GEOM * evals + FLOPS_CODE * (gamut_evals - no_high) + FLOPS_CELL * cell_tests
     k_eval = t_eval / max(n_eval, 1)
     k_write = t_write / max(n_write, 1)
     achieved = flops / (k_eval * 1e-3)
@@ -459,7 +485,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "nine Table 1 colours; r = 0.01..100 step 0.01 (10,000) x theta = "
-                        "0..359.9 deg step 0.1 (3,600); rule V_th=50, R_novib=0.5, any pattern",
+                        "0..359.9 deg step 0.1 (3,600); rule V_th=50, R_novib=0.5, any pattern; "
+                        "survivor list with CSR offsets and per-colour summaries (count, best pair, "
+                        "per-pattern counts; n_gamut not asked for)",
             "colours": int(len(W.PAPER_COLOUR_ARRAY)),
             "pairs_per_step": pairs_per_step,
             "survivors_per_step": int(total),
@@ -485,6 +513,7 @@ def main():
             "skipped_by_gamut_cells": skipped,
             "in_gamut_evaluations": gamut_evals,
             "in_gamut_not_encoded": no_high,
+            "cell_tests": cell_tests,
         },
         "write_pass": {"kernel": "k_pair_pass (write)", "ms": k_write,
                        "GBps": 16.0 * total / (k_write * 1e-3) / 1e9 if k_write > 0 else None,

@@ -62,6 +62,8 @@ extern "C" {
                           /* then tells gamut / validity                     */
 #define CV_PER_RAY 0x8u   /* only the survivor of largest i of every ray    */
                           /* (colour, j), in (colour, j) order               */
+#define CV_NO_NGAMUT 0x10u /* summaries without n_gamut (left 0): steps    */
+                          /* that can hold no survivor are not evaluated    */
 
 /* ---- rule flags -------------------------------------------------------- */
 #define CV_RULE_CLIP 0x1u /* alternative gamut reading: clamp each encoded  */
@@ -198,6 +200,10 @@ int cv_lab_convert(cv_context* ctx, const void* in, void* out, int64_t n, int di
  * and the same context workspaces; anything else captures again.  Results
  * are those of the eager call; no timing events are recorded inside the
  * graph.  CV_GRAPH is ignored with CV_PER_RAY.
+ * With CV_NO_NGAMUT (not with CV_EMIT_ALL or CV_PER_RAY, where it is
+ * ignored) the summaries' n_gamut is left 0, and the count pass does not
+ * evaluate steps that its bounds show can hold no survivor; every other
+ * output is unchanged.
  * With CV_PER_RAY (not with CV_EMIT_ALL) the records are, for every colour
  * and every ray j < ntheta that has a survivor, the survivor of largest
  * radius index i, in (colour, j) order; offsets and the two-call idiom work

@@ -28,6 +28,7 @@ CV_OK, CV_EINVAL, CV_ECAPACITY, CV_EHIP, CV_ENOMEM, CV_ESTATE = 0, -1, -2, -3, -
 CV_RGB8_TO_LAB, CV_LAB_TO_RGBF = 0, 1
 CV_EMIT_ALL = 0x1
 CV_PER_RAY = 0x8
+CV_NO_NGAMUT = 0x10
 CV_GRAPH = 0x2
 CV_RULE_CLIP = 0x1
 CV_TIME_EVAL, CV_TIME_WRITE, CV_TIME_CALL = 0, 1, 2
@@ -305,7 +306,7 @@ def pair_search(colors: torch.Tensor, grid: Grid, rule: Rule, capacity: int | No
                 summaries: bool = True, emit_all: bool = False, per_ray: bool = False,
                 out: torch.Tensor | None = None, ctx: Context | None = None, graph: bool = False,
                 offsets: torch.Tensor | None = None, summ_out: torch.Tensor | None = None,
-                sync: bool = True) -> SearchResult:
+                sync: bool = True, ngamut: bool = True) -> SearchResult:
     """Full search with stream compaction; survivors in (colour, i, j) order
     (per_ray: the largest-radius survivor of each ray, in (colour, j) order).
 
@@ -315,7 +316,8 @@ def pair_search(colors: torch.Tensor, grid: Grid, rule: Rule, capacity: int | No
     summ_out to reuse them) stay the same.  sync=False: nothing is read back
     (the call only enqueues work); the result's total is None, offsets[n]
     holds it on the device, and records past the capacity of `out` (which
-    must then be given) are dropped."""
+    must then be given) are dropped.  ngamut=False: the summaries' n_gamut is
+    left 0 and steps that can hold no survivor are not evaluated."""
     colors = _colours(colors)
     ctx = ctx or context(colors.device.index)
     n = colors.shape[0]
@@ -330,6 +332,7 @@ def pair_search(colors: torch.Tensor, grid: Grid, rule: Rule, capacity: int | No
         if summ.dtype != torch.uint8 or summ.numel() < n * 48 or not summ.is_cuda:
             raise ValueError("summ_out must be a uint8 CUDA tensor of at least n x 48 bytes")
     flags = (CV_EMIT_ALL if emit_all else 0) | (CV_PER_RAY if per_ray else 0) | (CV_GRAPH if graph else 0)
+    flags |= 0 if ngamut else CV_NO_NGAMUT
     if not sync:
         if out is None:
             raise ValueError("sync=False needs an output tensor")

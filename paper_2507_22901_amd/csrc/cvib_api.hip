@@ -250,7 +250,7 @@ int cv_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
     if (capacity < 0) return fail(CV_EINVAL, "capacity < 0");
     if (capacity > 0 && !out) return fail(CV_EINVAL, "out is NULL with capacity > 0");
     if (n > 0 && !rgb) return fail(CV_EINVAL, "rgb is NULL");
-    if (flags & ~(uint32_t)(CV_EMIT_ALL | CV_PER_RAY | CV_GRAPH)) return fail(CV_EINVAL, "unknown flags");
+    if (flags & ~(uint32_t)(CV_EMIT_ALL | CV_PER_RAY | CV_GRAPH | CV_NO_NGAMUT)) return fail(CV_EINVAL, "unknown flags");
     if ((flags & CV_EMIT_ALL) && (flags & CV_PER_RAY))
         return fail(CV_EINVAL, "CV_EMIT_ALL and CV_PER_RAY exclude each other");
     cvib::GridDev gd;

@@ -463,17 +463,25 @@ __device__ __forceinline__ BandPos band_pos(int32_t e, int32_t W, float inv_WB) 
 }
 
 __device__ inline bool band_step_open(const ColorConst& cc, const Geom& g, const Angles& ang, double ra,
-                                      double rb, int32_t W, float inv_WB, int32_t E0, int32_t E1, bool any) {
+                                      double rb, int32_t W, float inv_WB, int32_t E0, int32_t E1, bool any,
+                                      const RuleDev* rule = nullptr, bool* high = nullptr) {
     int32_t ba, qa, bb, qb;
     divmod_small(E0, kBandRows * W, inv_WB, ba, qa);
     divmod_small(E1, kBandRows * W, inv_WB, bb, qb);
     const bool two = bb != ba;
     const int32_t R = kBandRows;
-    bool open = !cell_out_of_gamut(cc, g, ang, ra, rb, R * ba, R * ba + R - 1, qa / R, two ? W - 1 : qb / R);
+    bool h1 = true;
+    bool open = !cell_out_of_gamut(cc, g, ang, ra, rb, R * ba, R * ba + R - 1, qa / R, two ? W - 1 : qb / R, rule,
+                                   high ? &h1 : nullptr);
+    bool hi = open && h1;
     if (__ballot(any && two) != 0ull) {
-        const bool o2 = !cell_out_of_gamut(cc, g, ang, ra, rb, R * bb, R * bb + R - 1, 0, qb / R);
+        bool h2 = true;
+        const bool o2 = !cell_out_of_gamut(cc, g, ang, ra, rb, R * bb, R * bb + R - 1, 0, qb / R, rule,
+                                           high ? &h2 : nullptr);
         open = open || (two && o2);
+        hi = hi || (two && o2 && h2);
     }
+    if (high) *high = hi;
     return open && any;
 }
 

@@ -558,7 +558,10 @@ struct ReduceArgs {
     int32_t segs_per_colour;  // SEG
     // gamut cells: one per wave step, decided per tile into cell_words
     // 64-bit masks per wave (0 = off)
-    int32_t cell_words, _pad;
+    int32_t cell_words;
+    // 0: n_gamut is not asked for (left 0), so open steps proven to hold no
+    // high channel are skipped rather than counted
+    int32_t need_ng;
     uint64_t* stats;          // [0..7]: candidates skipped by the cells; [8..15]: in-gamut pairs of steps
                               // proven to hold no high channel (not encoded); summed (nullable)
     // SEG: per segment, bit k = survivors among its evaluations 64k..64k+63
@@ -649,8 +652,10 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                 bool high = true;
                 const bool open = step_open(cc, a.g, ang, a.ra, a.rb, a.W, a.inv_W, row0, jb0, min(e0, len - 1),
                                             e1, any, SYM, &a.rule, &high);
-                if (any && !open) skipped += (uint64_t)(e1 - e0 + 1);
-                if (open)
+                // without n_gamut, a step without a high channel needs nothing
+                const bool take = open && (high || a.need_ng != 0);
+                if (any && !take) skipped += (uint64_t)(e1 - e0 + 1);
+                if (take)
                     atomicOr((unsigned long long*)&s_open[wv * a.cell_words + (it >> 6)], 1ull << (it & 63));
                 if (open && high)
                     atomicOr((unsigned long long*)&s_full[wv * a.cell_words + (it >> 6)], 1ull << (it & 63));
@@ -671,7 +676,7 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
             const uint64_t live_m = __ballot(live);
             const uint64_t both_m = __ballot(in_unit_cube(fp) && in_unit_cube(fm)) & live_m;
             const uint64_t need_m = clip ? live_m : both_m;
-            ng += (uint32_t)__builtin_popcountll(both_m);
+            if (a.need_ng) ng += (uint32_t)__builtin_popcountll(both_m);
             uint64_t surv_m = 0;
             if (need_m != 0ull) {
                 float Vp[3], Vm[3];
@@ -736,19 +741,27 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
             const float inv_W4 = a.inv_W / (float)kBandRows;  // exact: a power of two
             const int32_t wb = tid - (int32_t)lane;
             uint64_t evald = 0;
+            // steps without a high channel hold no survivor: with summaries
+            // they are counted for n_gamut, without them not evaluated at all
+            const bool need_ng = a.summ != nullptr && a.need_ng != 0;
             for (int32_t word = 0; word < (iters4 + 63) >> 6; ++word) {
                 const int32_t itl = word * 64 + (int32_t)lane, e0 = itl * BLOCK + wb;
                 const bool any = itl < iters4 && e0 < per4;
-                uint64_t steps = uniform_u64(__ballot(band_step_open(
-                    cc, a.g, ang, a.ra, a.rb, a.W, inv_W4, min(e0, per4 - 1), min(e0 + 63, per4 - 1), any)));
+                bool high = true;
+                const bool open = band_step_open(cc, a.g, ang, a.ra, a.rb, a.W, inv_W4, min(e0, per4 - 1),
+                                                 min(e0 + 63, per4 - 1), any, &a.rule, &high);
+                const uint64_t full = uniform_u64(__ballot(open && high));
+                uint64_t steps = need_ng ? uniform_u64(__ballot(open)) : full;
                 while (steps) {
-                    const int32_t e = (word * 64 + (int32_t)__builtin_ctzll(steps)) * BLOCK + tid;
+                    const int32_t bit = (int32_t)__builtin_ctzll(steps);
+                    const int32_t e = (word * 64 + bit) * BLOCK + tid;
                     steps &= steps - 1ull;
                     const BandPos bp = band_pos(min(e, per4 - 1), a.W, inv_W4);
                     const int32_t i = bp.i;
                     const bool live = e < per4 && i < a.nr;
                     evald += (uint64_t)__builtin_popcountll(__ballot(live));
-                    step(min(i, a.nr - 1), bp.j, e, live);
+                    if ((full >> bit) & 1ull) step(min(i, a.nr - 1), bp.j, e, live);
+                    else gamut_step(min(i, a.nr - 1), bp.j, live);
                 }
             }
             if (lane == 0) skipped += (w == 0 ? (uint64_t)len : 0ull) - evald;
@@ -1163,7 +1176,7 @@ ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, c
     a.cell_words = ctx->gamut_cells && !rd.clip && W >= kCellMinRays
                        ? (int32_t)(((pl.chunk + B - 1) / B + 63) / 64)
                        : 0;
-    a._pad = 0;
+    a.need_ng = 1;
     a.stats = ctx->timing ? (uint64_t*)ctx->stats.ptr : nullptr;
     a.seg_mask = nullptr;
     a.mask_slots = 0;
@@ -1424,6 +1437,7 @@ int enqueue_search(cv_context* ctx, const SearchCall& c, hipStream_t s) {
     // the search kernel counts them itself.
     ReduceArgs ra = reduce_args(ctx, tab, gd, rd, W, pl, n);
     ra.summ = emit ? nullptr : summ;
+    ra.need_ng = (flags & CV_NO_NGAMUT) ? 0 : 1;
     ra.seg_cnt = a.seg_cnt;
     ra.seg_len = seg_len;
     ra.segs_per_colour = spc;
@@ -1508,7 +1522,7 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     const cvib::Buffer* ws[9] = {&ctx->colors, &ctx->table, &ctx->seg_cnt, &ctx->seg_prefix, &ctx->misc,
                                  &ctx->acc,    &ctx->scan,  &ctx->stats,   &ctx->seg_mask};
     for (int k = 0; k < 9; ++k) call.ws[k] = ws[k]->ptr;
-    call.flags = flags & (uint32_t)CV_EMIT_ALL;
+    call.flags = flags & (uint32_t)(CV_EMIT_ALL | CV_NO_NGAMUT);
     call.cells = ctx->gamut_cells ? 1 : 0;
     if (!(flags & CV_GRAPH)) {
         if ((rc = enqueue_search(ctx, call, s)) != CV_OK) return rc;

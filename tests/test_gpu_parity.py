@@ -519,3 +519,27 @@ def test_search_without_readback(cv):
     cv.pair_search(x, grid, rule, per_ray=True, out=pout, ctx=ctx, offsets=off, summ_out=summ, sync=False)
     torch.cuda.synchronize()
     assert int(off[n].item()) == pe.total and torch.equal(pout, pe.pairs)
+
+
+def test_search_without_ngamut(cv):
+    """CV_NO_NGAMUT: steps that can hold no survivor are not evaluated and
+    the summaries' n_gamut is 0; records, offsets and every other summary
+    field equal those of the full call (eager and graph; nine colours and a
+    grid of few colours in direct mode)."""
+    cases = [(np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(79, 23)]), cv.Grid(0.05, 400, 0.5, 720)),
+             (W.random_colours(80, 2100), cv.Grid(0.5, 60, 1.0, 360))]
+    for cols, grid in cases:
+        x = _dev(cols)
+        n = len(cols)
+        for rule in (cv.Rule(50, 0.5), cv.Rule(40, 0.25, 0x15)):
+            ref = cv.pair_search(x, grid, rule)
+            for graph in (False, True):
+                r = cv.pair_search(x, grid, rule, graph=graph, ngamut=False)
+                assert r.total == ref.total
+                assert torch.equal(r.pairs, ref.pairs) and torch.equal(r.offsets, ref.offsets)
+                s_ref = cv.as_records(ref.summaries, cv.SUMMARY_DTYPE)
+                s_new = cv.as_records(r.summaries, cv.SUMMARY_DTYPE)
+                assert np.all(s_new["n_gamut"] == 0)
+                for f in s_ref.dtype.names:
+                    if f != "n_gamut":
+                        assert np.array_equal(s_new[f], s_ref[f]), (n, f)
