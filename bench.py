@@ -105,8 +105,8 @@ def _alu_roofline(kernel, ms, evals, gamut_evals, cell_tests=0):
 def bench_frames(cv, W, torch, steps):
     """Eight synthetic 3840 x 2160 frames (seeds 0..7): de-duplicate, resolve
     every distinct colour on the 500 x 360 grid (best pair per information
-    pattern, per-ray maxima, summaries) and render the two frames; one
-    hipGraph launch per step, frames resident in HBM."""
+    pattern, per-ray maxima, summaries without n_gamut) and render the two
+    frames; one hipGraph launch per step, frames resident in HBM."""
     import numpy as np
     f = W.frames(range(8))
     info = np.tile(W.info_map(0).reshape(-1), len(f))
@@ -115,30 +115,36 @@ def bench_frames(cv, W, torch, steps):
     px = torch.from_numpy(f).cuda()
     inf = torch.from_numpy(info).cuda()
     ctx = cv.context(0)
-    # one eager call with kernel timing (the resolve kernel's own duration)
+    # one eager call with n_gamut: the in-gamut count and the in-gamut pairs of
+    # steps without a high channel (the timed calls skip those steps)
     ctx.set_timing(True)
+    ctx.no_high(reset=True)
+    out = cv.frames_resolve(px, grid, rule, info=inf, rays=True, ctx=ctx)
+    torch.cuda.synchronize()
+    no_high = ctx.no_high(reset=True)
+    n = int(out.ncolours.item())
+    half = g.ntheta * g.dtheta_deg == 360.0
+    gamut = int(cv.as_records(out.summaries[:n], cv.SUMMARY_DTYPE)["n_gamut"].astype(np.int64).sum()) // \
+        (2 if half else 1)
+    # one eager call as timed, with kernel timing (the resolve kernel's own duration)
     ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
     ctx.skipped(reset=True)
-    out = cv.frames_resolve(px, grid, rule, info=inf, rays=True, ctx=ctx)
+    cv.frames_resolve(px, grid, rule, info=inf, rays=True, out=out, ctx=ctx, ngamut=False)
     torch.cuda.synchronize()
     t_res, _ = ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
     skipped = ctx.skipped(reset=True)
     ctx.set_timing(False)
-    cv.frames_resolve(px, grid, rule, info=inf, rays=True, graph=True, out=out, ctx=ctx)
+    cv.frames_resolve(px, grid, rule, info=inf, rays=True, graph=True, out=out, ctx=ctx, ngamut=False)
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(steps):
-        cv.frames_resolve(px, grid, rule, info=inf, rays=True, graph=True, out=out, ctx=ctx)
+        cv.frames_resolve(px, grid, rule, info=inf, rays=True, graph=True, out=out, ctx=ctx, ngamut=False)
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
-    n = int(out.ncolours.item())
-    summ = cv.as_records(out.summaries[:n], cv.SUMMARY_DTYPE)
-    half = g.ntheta * g.dtheta_deg == 360.0
     decided = n * g.nr * (g.ntheta // 2 if half else g.ntheta)
-    evals = decided - skipped  # the rest lie in steps proven out of gamut
-    gamut = int(summ["n_gamut"].astype(np.int64).sum()) // (2 if half else 1)
+    evals = decided - skipped  # the rest lie in steps proven out of gamut or without a high channel
     npix = px.shape[0] * px.shape[1] * px.shape[2]
     return {
         "workload": "8 synthetic 3840x2160 frames (seeds 0..7), 16x16-pixel information map; "
@@ -147,8 +153,9 @@ def bench_frames(cv, W, torch, steps):
         "pixels_per_s": npix / (ms * 1e-3), "pairs_per_s": n * g.per_colour / (ms * 1e-3),
         "ms_per_call": ms, "calls": steps, "resolved_pixels": int(out.resolved.item()),
         "resolve_kernel_ms": t_res,
-        "roofline": dict(_alu_roofline("k_colour_resolve", t_res, evals, gamut, -(-decided // 64)),
-                         decided_pairs=decided, skipped_by_gamut_cells=skipped),
+        "roofline": dict(_alu_roofline("k_colour_resolve", t_res, evals, gamut - no_high, -(-decided // 64)),
+                         decided_pairs=decided, skipped_by_gamut_cells=skipped,
+                         in_gamut_without_high_channel=no_high),
     }
 
 
@@ -194,8 +201,8 @@ def bench_surrogate(cv, W, torch, epochs, steps):
         torch.cuda.synchronize()
         return ev_start.elapsed_time(ev_stop) / n
 
-    ex = cv.frames_resolve(px, grid, rule, ctx=ctx)
-    ms_exact = timed(lambda: cv.frames_resolve(px, grid, rule, out=ex, ctx=ctx), max(1, steps - 1))
+    ex = cv.frames_resolve(px, grid, rule, ctx=ctx, ngamut=False)
+    ms_exact = timed(lambda: cv.frames_resolve(px, grid, rule, out=ex, ctx=ctx, ngamut=False), max(1, steps - 1))
     sr = cv.frames_surrogate(px, m, grid, rule, tau=0.0, kbins=6, ctx=ctx)
     ms_sur = timed(lambda: cv.frames_surrogate(px, m, grid, rule, tau=0.0, kbins=6, out=sr, ctx=ctx), steps)
     # phase times of one surrogate call

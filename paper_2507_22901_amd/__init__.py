@@ -429,10 +429,11 @@ class FramesResult:
 def frames_resolve(pixels: torch.Tensor, grid: Grid, rule: Rule, info: torch.Tensor | None = None,
                    summaries: bool = True, rays: bool = False, frames: bool = True,
                    graph: bool = False, out: FramesResult | None = None,
-                   ctx: Context | None = None) -> FramesResult:
+                   ctx: Context | None = None, ngamut: bool = True) -> FramesResult:
     """De-duplicate the colours of `pixels` (uint8 [..., 3] on the GPU), search
     every distinct colour, and render the two alternating frames.  Pass the
-    previous result as `out` to reuse its buffers (needed for graph replays)."""
+    previous result as `out` to reuse its buffers (needed for graph replays).
+    ngamut=False: the summaries' n_gamut is left 0 (CV_NO_NGAMUT)."""
     if pixels.dtype != torch.uint8 or pixels.shape[-1] != 3 or not pixels.is_cuda:
         raise ValueError("pixels must be a uint8 CUDA tensor of shape [..., 3]")
     px = pixels.contiguous().reshape(-1, 3)
@@ -461,7 +462,7 @@ def frames_resolve(pixels: torch.Tensor, grid: Grid, rule: Rule, info: torch.Ten
                                    _dptr(out.ncolours), _dptr(out.pixel_index),
                                    _dptr(out.summaries), _dptr(out.pbest), _dptr(out.rays),
                                    _dptr(out.frame_a), _dptr(out.frame_b), _dptr(out.resolved),
-                                   CV_GRAPH if graph else 0, _stream()))
+                                   (CV_GRAPH if graph else 0) | (0 if ngamut else CV_NO_NGAMUT), _stream()))
     return out
 
 

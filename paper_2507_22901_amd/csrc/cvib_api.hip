@@ -301,9 +301,10 @@ int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, cons
     if (resolved && !frame_a) return fail(CV_EINVAL, "resolved needs the frames");
     const int64_t need = npix < ((int64_t)1 << 24) ? npix : ((int64_t)1 << 24);
     if (colour_cap < need) return fail(CV_EINVAL, "colour_cap < min(npix, 2^24)");
-    if (flags & ~(uint32_t)CV_GRAPH) return fail(CV_EINVAL, "unknown flags");
+    if (flags & ~(uint32_t)(CV_GRAPH | CV_NO_NGAMUT)) return fail(CV_EINVAL, "unknown flags");
     cvib::FramesCall call;
     std::memset(&call, 0, sizeof call);  // bytewise comparison for the graph cache
+    call.no_ngamut = (flags & CV_NO_NGAMUT) ? 1 : 0;
     int rc;
     if ((rc = cvib::make_grid(grid, &call.gd)) != CV_OK) return rc;
     if ((rc = cvib::make_rule(rule, &call.rd)) != CV_OK) return rc;

@@ -113,23 +113,34 @@ struct ResolveArgs {
     cv_color_summary* summ;   // nullable
     cv_pattern_pair* pbest;   // nullable, [n][7]
     uint16_t* rays;           // nullable, [n][ntheta]
-    int32_t cells, _pad;      // skip wave steps proven out of gamut (CELLS kernels)
-    uint64_t* stats;          // [0..7]: candidates skipped by the cells, summed (nullable)
+    int32_t cells;            // skip wave steps proven out of gamut (CELLS kernels)
+    // 0: n_gamut is not needed (no summaries, or CV_NO_NGAMUT), so steps
+    // proven to hold no high channel are skipped rather than counted
+    int32_t need_ng;
+    uint64_t* stats;          // [0..7]: candidates skipped by the cells; [8..15]: in-gamut pairs of
+                              // steps without a high channel (counted, not encoded); summed (nullable)
 };
 
 // Per-block sum of the lanes' skipped counts into stats (every thread calls
 // it once, at the end).
 template <int NW>
-__device__ __forceinline__ void add_skipped(uint64_t* stats, uint64_t skipped) {
+__device__ __forceinline__ void add_skipped(uint64_t* stats, uint64_t skipped, uint64_t no_high) {
     if (!stats) return;
-    __shared__ uint64_t s_skip[NW];
+    __shared__ uint64_t s_skip[NW], s_noh[NW];
     for (int o = 32; o > 0; o >>= 1) skipped += (uint64_t)__shfl_xor((unsigned long long)skipped, o, 64);
-    if ((threadIdx.x & 63u) == 0) s_skip[threadIdx.x >> 6] = skipped;
+    if ((threadIdx.x & 63u) == 0) {
+        s_skip[threadIdx.x >> 6] = skipped;
+        s_noh[threadIdx.x >> 6] = no_high;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint64_t sum = 0;
-        for (int q = 0; q < NW; ++q) sum += s_skip[q];
+        uint64_t sum = 0, nh = 0;
+        for (int q = 0; q < NW; ++q) {
+            sum += s_skip[q];
+            nh += s_noh[q];
+        }
         if (sum) atomicAdd((unsigned long long*)&stats[blockIdx.x & 7u], (unsigned long long)sum);
+        if (nh) atomicAdd((unsigned long long*)&stats[8 + (blockIdx.x & 7u)], (unsigned long long)nh);
     }
 }
 
@@ -148,7 +159,8 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
                                                const ColorConst& cc, int32_t g_tid, int32_t g_size,
                                                int32_t si, int32_t sj, uint32_t lane, uint32_t* s_pb,
                                                uint32_t* s_ray, uint32_t& cnt, uint32_t& ng,
-                                               uint32_t& best, uint32_t pat[7], uint64_t& skipped) {
+                                               uint32_t& best, uint32_t pat[7], uint64_t& skipped,
+                                               uint64_t& no_high) {
     const bool clip = a.rule.clip != 0u;
     const int32_t per = a.nr * a.W;
     const int32_t iters = (per + g_size - 1) / g_size;
@@ -162,7 +174,7 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
         const uint64_t live_m = __ballot(live);
         const uint64_t both_m = __ballot(in_unit_cube(fp) && in_unit_cube(fm)) & live_m;
         const uint64_t need_m = clip ? live_m : both_m;
-        ng += (uint32_t)__builtin_popcountll(both_m);
+        if (a.need_ng) ng += (uint32_t)__builtin_popcountll(both_m);
         if (need_m != 0ull) {
             float Vp[3], Vm[3];
             codes_w(fp, fm, (need_m >> lane) & 1ull, clip, Vp, Vm);
@@ -181,6 +193,20 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
         }
     };
     if constexpr (CELLS) {
+        // a step proven to hold no high channel holds no survivor: its
+        // in-gamut pairs are counted when n_gamut is needed, else it is skipped
+        auto gamut_step = [&](int32_t i, int32_t j, bool live) {
+            double sn, co;
+            ang.get(j, sn, co);
+            const double rr = (double)(i + 1);
+            float fp[3], fm[3];
+            pair_linear_w(cc, a.g, (rr * a.ra) * sn, (rr * a.rb) * co, fp, fm, cube);
+            const uint32_t nb =
+                (uint32_t)__builtin_popcountll(__ballot(live && in_unit_cube(fp) && in_unit_cube(fm)));
+            ng += nb;
+            if (lane == 0) no_high += nb;
+        };
+        const bool need_ng = a.need_ng != 0;
         const int32_t per4 = ((a.nr + kBandRows - 1) / kBandRows) * kBandRows * a.W;  // whole bands
         const int32_t iters4 = (per4 + g_size - 1) / g_size;
         const float inv_W4 = a.inv_W / (float)kBandRows;  // exact: a power of two
@@ -189,16 +215,21 @@ __device__ __forceinline__ void resolve_colour(const ResolveArgs& a, const Angle
         for (int32_t word = 0; word < (iters4 + 63) >> 6; ++word) {
             const int32_t itl = word * 64 + (int32_t)lane, e0 = itl * g_size + wb;
             const bool any = itl < iters4 && e0 < per4;
-            uint64_t m = uniform_u64(__ballot(band_step_open(cc, a.g, ang, a.ra, a.rb, a.W, inv_W4,
-                                                             min(e0, per4 - 1), min(e0 + 63, per4 - 1), any)));
+            bool high = true;
+            const bool open = band_step_open(cc, a.g, ang, a.ra, a.rb, a.W, inv_W4, min(e0, per4 - 1),
+                                             min(e0 + 63, per4 - 1), any, &a.rule, &high);
+            const uint64_t full = uniform_u64(__ballot(open && high));
+            uint64_t m = need_ng ? uniform_u64(__ballot(open)) : full;
             while (m) {
-                const int32_t e = (word * 64 + (int32_t)__builtin_ctzll(m)) * g_size + g_tid;
+                const int32_t bit = (int32_t)__builtin_ctzll(m);
+                const int32_t e = (word * 64 + bit) * g_size + g_tid;
                 m &= m - 1ull;
                 const BandPos bp = band_pos(min(e, per4 - 1), a.W, inv_W4);
                 const int32_t i = bp.i;
                 const bool live = e < per4 && i < a.nr;
                 evald += (uint64_t)__builtin_popcountll(__ballot(live));
-                step(min(i, a.nr - 1), bp.j, live);
+                if ((full >> bit) & 1ull) step(min(i, a.nr - 1), bp.j, live);
+                else gamut_step(min(i, a.nr - 1), bp.j, live);
             }
         }
         // the colour's candidates less those evaluated (unsigned sums cancel)
@@ -254,7 +285,7 @@ __global__ __launch_bounds__(256, 6) void k_colour_resolve(ResolveArgs a) {
     uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW);
     const uint32_t mult = SYM ? 2u : 1u;
     const int64_t n = (int64_t)*a.n_dev;
-    uint64_t skipped = 0;
+    uint64_t skipped = 0, no_high = 0;
 
     for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
         const int64_t c = a.list ? (int64_t)a.list[k] : k;
@@ -266,7 +297,7 @@ __global__ __launch_bounds__(256, 6) void k_colour_resolve(ResolveArgs a) {
         uint32_t cnt = 0, ng = 0, best = 0;
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
         resolve_colour<RAYS, CELLS>(a, ang, cc, tid, BLOCK, a.si, a.sj, lane, s_pb, s_ray, cnt, ng, best, pat,
-                                    skipped);
+                                    skipped, no_high);
         uint32_t v[10] = {mult * cnt, mult * ng, wave_max_u32(best)};
 #pragma unroll
         for (int q = 0; q < 7; ++q) v[3 + q] = mult * accepted_count(a.rule.mask, q, pat[q]);
@@ -298,7 +329,7 @@ __global__ __launch_bounds__(256, 6) void k_colour_resolve(ResolveArgs a) {
         }
         __syncthreads();
     }
-    add_skipped<NW>(a.stats, skipped);
+    add_skipped<NW>(a.stats, skipped, no_high);
 }
 
 // LDS written by some lanes of a wave visible to its other lanes: a wave's
@@ -325,7 +356,7 @@ __global__ __launch_bounds__(BLOCK) void k_colour_resolve_w(ResolveArgs a) {
     uint32_t* s_pb = s_pbw[w];
     const uint32_t mult = SYM ? 2u : 1u;
     const int64_t n = (int64_t)*a.n_dev;
-    uint64_t skipped = 0;
+    uint64_t skipped = 0, no_high = 0;
 
     for (int64_t k = (int64_t)blockIdx.x * NW + w; k < n; k += (int64_t)gridDim.x * NW) {
         const int64_t c = a.list ? (int64_t)a.list[k] : k;
@@ -337,7 +368,7 @@ __global__ __launch_bounds__(BLOCK) void k_colour_resolve_w(ResolveArgs a) {
         uint32_t cnt = 0, ng = 0, best = 0;
         uint32_t pat[7] = {0, 0, 0, 0, 0, 0, 0};
         resolve_colour<RAYS, CELLS>(a, ang, cc, (int32_t)lane, 64, a.si64, a.sj64, lane, s_pb, s_ray, cnt,
-                                    ng, best, pat, skipped);
+                                    ng, best, pat, skipped, no_high);
         best = wave_max_u32(best);
         wave_lds_sync();
         if (lane == 0 && a.summ) {
@@ -356,7 +387,7 @@ __global__ __launch_bounds__(BLOCK) void k_colour_resolve_w(ResolveArgs a) {
         }
         wave_lds_sync();
     }
-    add_skipped<NW>(a.stats, skipped);  // every wave reaches it once its colours are done
+    add_skipped<NW>(a.stats, skipped, no_high);  // every wave reaches it once its colours are done
 }
 
 // ---------------------------------------------------------------------------
@@ -812,7 +843,7 @@ ResolveArgs resolve_args(cv_context* ctx, const GridDev& gd, const RuleDev& rd, 
     a.rays = nullptr;
     // gamut cells as in the reduce kernel, with exact FP32 index splits
     a.cells = ctx->gamut_cells && !rd.clip && a.W >= kCellMinRays && (int64_t)(a.nr + kBandRows - 1) * a.W < (1 << 24) ? 1 : 0;
-    a._pad = 0;
+    a.need_ng = 1;
     a.stats = ctx->timing ? (uint64_t*)ctx->stats.ptr : nullptr;
     return a;
 }
@@ -839,6 +870,7 @@ int FramesCall::enqueue(cv_context* ctx, hipStream_t s) const {
     a.summ = summ;
     a.pbest = pbest;
     a.rays = rays;
+    a.need_ng = summ && !no_ngamut ? 1 : 0;
     if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
     if ((rc = launch_resolve(ctx, a, sym, variant, s)) != CV_OK) return rc;
     if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
@@ -890,6 +922,7 @@ int tune_resolve(cv_context* ctx, const FramesCall& call, hipStream_t s) {
     a.summ = call.summ;
     a.pbest = call.pbest;
     a.rays = call.rays;
+    a.need_ng = call.summ && !call.no_ngamut ? 1 : 0;
     const bool sym = call.gd.ntheta == call.gd.N;
     int lds_max = 0;
     CV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
@@ -1069,6 +1102,7 @@ int enqueue_surrogate(cv_context* ctx, const SurrogateCall& c, const uint8_t* rg
         ResolveArgs a = resolve_args(ctx, c.gd, c.rd, smisc + 1);
         a.list = list;
         a.summ = (cv_color_summary*)ctx->ssumm.ptr;
+        a.need_ng = 0;  // only the maximum-amplitude pair is taken from these summaries
         if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
         if ((rc = launch_resolve(ctx, a, c.gd.ntheta == c.gd.N, resolve_variant(ctx, c.gd, false), s)) !=
             CV_OK)

@@ -107,6 +107,8 @@ struct FramesCall {
     const void* ws[7];  // context workspaces the call uses (a regrown one voids a cached graph)
     int32_t variant;    // per-colour resolve kernel (see resolve_variant)
     int32_t cells;      // gamut cells on in the context when captured
+    int32_t no_ngamut;  // CV_NO_NGAMUT: summaries without n_gamut
+    int32_t _pad;
     int enqueue(cv_context* ctx, hipStream_t s) const;
     bool same(const FramesCall& o) const;
 };

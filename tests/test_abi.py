@@ -159,7 +159,7 @@ def test_frames_argument_validation(cv):
     assert b"colour_cap" in L.cv_last_error()
     assert call(fb=None) == cv.CV_EINVAL               # the two frames go together
     assert call(fa=None, fb=None, res=d) == cv.CV_EINVAL
-    assert call(flags=0x10) == cv.CV_EINVAL            # unknown flag
+    assert call(flags=0x20) == cv.CV_EINVAL            # unknown flag
 
 
 def test_binding_refuses_host_tensors(cv):

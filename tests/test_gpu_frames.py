@@ -205,3 +205,38 @@ def test_gamut_cells_change_no_frame_output(cv, nt):
             assert torch.equal(getattr(o, k)[:n], getattr(ref, k)[:n]), k
         for k in ("frame_a", "frame_b", "resolved", "pixel_index"):
             assert torch.equal(getattr(o, k), getattr(ref, k)), k
+
+
+@pytest.mark.parametrize("dth,nt", [(1.0, 360), (0.5, 720)])
+def test_frames_without_ngamut(cv, dth, nt):
+    """CV_NO_NGAMUT: steps without a high channel are skipped; every output
+    but the summaries' n_gamut (0) equals the full resolve, for every kernel
+    variant, eager and captured, and without summaries at all."""
+    f = torch.from_numpy(_frames()).cuda()
+    grid = cv.Grid(0.25, 200, dth, nt)
+    rule = cv.Rule(50, 0.5, 0x7F)
+    # patterns 1..7 only: pixels of map value 0 take the summaries' best pair,
+    # which the call without summaries does not have
+    info = torch.from_numpy(np.random.default_rng(4).integers(1, 8, f.numel() // 3).astype(np.uint8)).cuda()
+    ctx = cv.Context(0)
+    ref = cv.frames_resolve(f, grid, rule, info=info, rays=True, ctx=ctx)
+    outs = []
+    for v in (0, 1, 2):
+        ctx.set_resolve_variant(v)
+        outs.append(cv.frames_resolve(f, grid, rule, info=info, rays=True, ctx=ctx, ngamut=False))
+    outs.append(cv.frames_resolve(f, grid, rule, info=info, rays=True, graph=True, ctx=ctx, ngamut=False))
+    nosum = cv.frames_resolve(f, grid, rule, info=info, rays=True, summaries=False, ctx=ctx)
+    torch.cuda.synchronize()
+    n = int(ref.ncolours.item())
+    s_ref = cv.as_records(ref.summaries[:n], cv.SUMMARY_DTYPE)
+    for o in outs + [nosum]:
+        for k in ("pbest", "rays"):
+            assert torch.equal(getattr(o, k)[:n], getattr(ref, k)[:n]), k
+        for k in ("frame_a", "frame_b", "resolved", "pixel_index"):
+            assert torch.equal(getattr(o, k), getattr(ref, k)), k
+    for o in outs:
+        s = cv.as_records(o.summaries[:n], cv.SUMMARY_DTYPE)
+        assert np.all(s["n_gamut"] == 0)
+        for fld in s_ref.dtype.names:
+            if fld != "n_gamut":
+                assert np.array_equal(s[fld], s_ref[fld]), fld
