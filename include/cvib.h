@@ -117,7 +117,8 @@ typedef struct {
  */
 typedef struct {
     uint32_t count;          /* survivors                                   */
-    uint32_t n_gamut;        /* candidates with both colours in gamut       */
+    uint32_t n_gamut;        /* candidates with both colours in gamut (0    */
+                             /* with CV_NO_NGAMUT)                          */
     uint16_t best_i, best_j;
     uint8_t best_plus[3], best_minus[3], best_p, _pad;
     uint32_t per_pattern[7]; /* survivors with pattern p at index p - 1     */
@@ -267,8 +268,11 @@ int cv_pair_reduce_rules(cv_context* ctx, const uint8_t* rgb, int64_t n, const c
  * int64, nullable; needs the frames) counts the pixels that received a pair.
  * Nothing is copied to the host: the call is asynchronous, and with CV_GRAPH
  * it is one graph launch (captured again when an argument changes or a
- * context workspace had to grow).  The caller owns every array; the context
- * owns a 2^24-bit colour bitmap and its scan (about 8 MiB).
+ * context workspace had to grow).  With CV_NO_NGAMUT the summaries' n_gamut
+ * is left 0 and steps that can hold no survivor are not evaluated (every
+ * other output is unchanged; without summ this is always so).  The caller
+ * owns every array; the context owns a 2^24-bit colour bitmap and its scan
+ * (about 8 MiB).
  * Requirements: colour_cap >= min(npix, 2^24); the angle table (8 * (N/4 + 1)
  * bytes when N % 4 == 0, else 16 * (N/2 + 1)) plus, with rays, 4 bytes per
  * evaluated ray (ntheta, or N/2 when theta spans the full turn) must fit in
