@@ -51,11 +51,14 @@ struct RulesArgs {
     const uint8_t* lut;        // [256]: interval of a change d
     uint32_t* hist;            // [n][nint^3]
     uint32_t mult;             // 2 when only half a turn is evaluated
+    RuleDev low;               // v_th: the smallest threshold of the rules (for the high-channel cells)
 };
 
 // With CELLS each wave first decides 64 of its steps at a time (one per lane)
-// and evaluates only those that may hold a pair in gamut; the histogram holds
-// in-gamut candidates only, so skipped steps add nothing to it.
+// and evaluates only those that may hold a pair in gamut with a channel
+// changing by more than the smallest threshold of the rules: a pair without
+// such a channel has no accepted pattern under any rule, so its bin adds to no
+// count (the histogram itself is not an output).
 template <bool SYM, bool CELLS>
 __global__ __launch_bounds__(kRulesBlock) void k_rule_hist(RulesArgs a) {
     extern __shared__ double s_dyn[];
@@ -115,8 +118,10 @@ __global__ __launch_bounds__(kRulesBlock) void k_rule_hist(RulesArgs a) {
             for (int32_t word = 0; word < (iters + 63) >> 6; ++word) {
                 const int32_t itl = word * 64 + (int32_t)lane, e0 = itl * kRulesBlock + wb;
                 const bool any = itl < iters && e0 < len;
-                uint64_t m = uniform_u64(__ballot(step_open(cc, a.g, ang, a.ra, a.rb, a.W, a.inv_W, row0, jb0,
-                                                            min(e0, len - 1), min(e0 + 63, len - 1), any)));
+                bool high = true;
+                const bool open = step_open(cc, a.g, ang, a.ra, a.rb, a.W, a.inv_W, row0, jb0, min(e0, len - 1),
+                                            min(e0 + 63, len - 1), any, false, &a.low, &high);
+                uint64_t m = uniform_u64(__ballot(open && high));
                 while (m) {
                     const int32_t e = (word * 64 + (int32_t)__builtin_ctzll(m)) * kRulesBlock + tid;
                     m &= m - 1ull;
@@ -258,6 +263,8 @@ int run_pair_reduce_rules(cv_context* ctx, const uint8_t* rgb, int64_t n, const 
     a.lut = (const uint8_t*)ctx->rtab.ptr;
     a.hist = (uint32_t*)ctx->rhist.ptr;
     a.mult = sym ? 2u : 1u;
+    a.low = rules[0];
+    for (int32_t r = 1; r < nrules; ++r) a.low.v_th = std::min(a.low.v_th, rules[r].v_th);
     const bool cells = ctx->gamut_cells && !a.clip && W >= kCellMinRays;
     auto k = sym ? (cells ? k_rule_hist<true, true> : k_rule_hist<true, false>)
                  : (cells ? k_rule_hist<false, true> : k_rule_hist<false, false>);
