@@ -203,13 +203,13 @@ def bench_surrogate(cv, W, torch, epochs, steps):
 
     ex = cv.frames_resolve(px, grid, rule, ctx=ctx, ngamut=False)
     ms_exact = timed(lambda: cv.frames_resolve(px, grid, rule, out=ex, ctx=ctx, ngamut=False), max(1, steps - 1))
-    sr = cv.frames_surrogate(px, m, grid, rule, tau=0.0, kbins=6, ctx=ctx)
-    ms_sur = timed(lambda: cv.frames_surrogate(px, m, grid, rule, tau=0.0, kbins=6, out=sr, ctx=ctx), steps)
+    sr = cv.frames_surrogate(px, m, grid, rule, tau=0.0, kbins=3, ctx=ctx)
+    ms_sur = timed(lambda: cv.frames_surrogate(px, m, grid, rule, tau=0.0, kbins=3, out=sr, ctx=ctx), steps)
     # phase times of one surrogate call
     ctx.set_timing(True)
     for ph in (cv.CV_TIME_MLP, cv.CV_TIME_VERIFY, cv.CV_TIME_EVAL, cv.CV_TIME_CALL):
         ctx.kernel_time(ph, reset=True)
-    cv.frames_surrogate(px, m, grid, rule, tau=0.0, kbins=6, out=sr, ctx=ctx)
+    cv.frames_surrogate(px, m, grid, rule, tau=0.0, kbins=3, out=sr, ctx=ctx)
     ph = {k: ctx.kernel_time(v, reset=True)[0] for k, v in
           (("mlp", cv.CV_TIME_MLP), ("verify", cv.CV_TIME_VERIFY), ("fallback", cv.CV_TIME_EVAL),
            ("call", cv.CV_TIME_CALL))}

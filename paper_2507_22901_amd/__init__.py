@@ -656,7 +656,7 @@ class SurrogateResult:
 
 
 def surrogate_infer(colors: torch.Tensor, mlp: MLP, grid: Grid, rule: Rule, tau: float = 0.0,
-                    kbins: int = 6, fallback: bool = True, want_pred: bool = False,
+                    kbins: int = 3, fallback: bool = True, want_pred: bool = False,
                     ctx: Context | None = None) -> SurrogateResult:
     """One verified pair per colour (uint8 [n, 3] on the GPU)."""
     colors = _colours(colors)
@@ -688,7 +688,7 @@ class FramesSurrogateResult:
 
 
 def frames_surrogate(pixels: torch.Tensor, mlp: MLP, grid: Grid, rule: Rule, tau: float = 0.0,
-                     kbins: int = 6, fallback: bool = True, frames: bool = True,
+                     kbins: int = 3, fallback: bool = True, frames: bool = True,
                      out: FramesSurrogateResult | None = None,
                      ctx: Context | None = None) -> FramesSurrogateResult:
     """De-duplicate the colours of `pixels` (uint8 [..., 3]), resolve each
