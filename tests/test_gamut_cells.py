@@ -13,7 +13,8 @@ mathematical statement:
 - a linear channel A f^-1(fx) + C f^-1(fz) + B is bounded term by term.
 Three properties are checked on several hundred blocks of the shapes the
 kernels use (one or two rows of 64 rays, the mirrored range of a half-turn
-row crossing, 16 rows by 4 rays, several whole rows):
+row crossing, 16 rows by 4 rays, several whole rows, and the groups of 256
+rays that the count pass tests before their four steps):
 - containment: every linear channel of both colours of every candidate
   (FP64 oracle) lies inside the block's intervals -- any narrowing fails it,
   whatever the gamut's shape;
@@ -26,6 +27,7 @@ breaks one of them.
 from __future__ import annotations
 
 import numpy as np
+import pytest
 
 import workloads as W
 
@@ -114,14 +116,26 @@ def _blocks(rng, nr, W_):
         b = int(rng.integers(0, nr // 16)); j0 = int(rng.integers(0, W_ - 4))
         out.append(("band", (16 * b, 16 * b + 15, j0, j0 + 3),
                     [(16 * b + q, j) for q in range(16) for j in range(j0, j0 + 4)]))
+    if W_ > 256:
+        # groups of four steps (256 evaluations), as the count pass tests them
+        # before their steps: one row, or a half-turn crossing in mirrored form
+        for _ in range(20):
+            i = int(rng.integers(0, nr)); j0 = int(rng.integers(0, W_ - 256))
+            out.append(("row", (i, i, j0, j0 + 255), [(i, j) for j in range(j0, j0 + 256)]))
+        for _ in range(20):
+            i = int(rng.integers(0, nr - 1)); ja = int(rng.integers(W_ - 255, W_))
+            jb = 255 - (W_ - ja)
+            cand = [(r, j) for r in (i, i + 1) for j in list(range(ja, W_)) + list(range(0, jb + 1))]
+            out.append(("mirrored", (i, i + 1, ja, W_ + jb), cand))
     return out
 
 
-def test_gamut_cell_bound_is_sound_and_useful(oracle):
+@pytest.mark.parametrize("dth,nt", [(1.0, 360), (0.5, 720)])
+def test_gamut_cell_bound_is_sound_and_useful(oracle, dth, nt):
     rng = np.random.default_rng(11)
     cols = np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(12, 15),
                            np.array([[255, 0, 0], [0, 0, 0], [250, 250, 5], [2, 3, 250]], np.uint8)])
-    dr, nr, dth, nt = 0.25, 200, 1.0, 360   # rays of the half-turn: W = 180
+    dr, nr = 0.25, 200   # rays of the half-turn: W = nt / 2
     W_ = nt // 2
     proven = wholly_out = 0
     for ci, rgb in enumerate(cols):
@@ -167,13 +181,14 @@ def test_gamut_cell_bound_whole_rows(oracle):
                 assert not (ev["gamut"] == 3).any()
 
 
-def test_gamut_cell_intervals_contain_every_candidate(oracle):
+@pytest.mark.parametrize("dth,nt", [(1.0, 360), (0.5, 720)])
+def test_gamut_cell_intervals_contain_every_candidate(oracle, dth, nt):
     """Containment: every linear channel of both colours of every candidate
     of a block (FP64 oracle) lies inside the block's intervals.  This holds
     for any colour and block, in or out of gamut, and fails for any bound
     that is too narrow somewhere."""
     rng = np.random.default_rng(14)
-    dr, nr, dth, nt = 0.5, 100, 1.0, 360
+    dr, nr = 0.5, 100
     W_ = nt // 2
     cols = np.concatenate([W.PAPER_COLOUR_ARRAY[:3], W.random_colours(15, 9)])
     for rgb in cols:
