@@ -13,8 +13,8 @@ mathematical statement:
 - a linear channel A f^-1(fx) + C f^-1(fz) + B is bounded term by term.
 Three properties are checked on several hundred blocks of the shapes the
 kernels use (one or two rows of 64 rays, the mirrored range of a half-turn
-row crossing, 16 rows by 4 rays, several whole rows, and the groups of 256
-rays that the count pass tests before their four steps):
+row crossing, 16 rows by 4 rays, several whole rows, and blocks of 256
+rays, one row or a crossing):
 - containment: every linear channel of both colours of every candidate
   (FP64 oracle) lies inside the block's intervals -- any narrowing fails it,
   whatever the gamut's shape;
@@ -117,8 +117,8 @@ def _blocks(rng, nr, W_):
         out.append(("band", (16 * b, 16 * b + 15, j0, j0 + 3),
                     [(16 * b + q, j) for q in range(16) for j in range(j0, j0 + 4)]))
     if W_ > 256:
-        # groups of four steps (256 evaluations), as the count pass tests them
-        # before their steps: one row, or a half-turn crossing in mirrored form
+        # blocks of 256 evaluations: one row, or a half-turn crossing in
+        # mirrored form
         for _ in range(20):
             i = int(rng.integers(0, nr)); j0 = int(rng.integers(0, W_ - 256))
             out.append(("row", (i, i, j0, j0 + 255), [(i, j) for j in range(j0, j0 + 256)]))
