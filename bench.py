@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--epochs", type=float, default=16.0, help="surrogate training epochs")
+    ap.add_argument("--epochs", type=float, default=32.0, help="surrogate training epochs")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only copy 256 MiB on the device three times (the known-size kernel "
                          "that scales FETCH_SIZE / WRITE_SIZE counters to bytes)")
