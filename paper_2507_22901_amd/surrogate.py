@@ -23,7 +23,7 @@ def cube_table(grid: Grid, rule: Rule, ctx=None) -> torch.Tensor:
     return tab
 
 
-def train(mlp: MLP, table: torch.Tensor, train_ids: torch.Tensor, dr: float, epochs: float = 4.0,
+def train(mlp: MLP, table: torch.Tensor, train_ids: torch.Tensor, dr: float, epochs: float = 32.0,
           batch: int = 8192, lr: float = 4e-3, lr_min: float = 2e-5, delta: float = 0.05,
           seed: int = 0, log_every: int = 200, step0: int = 0):
     """Adam with cosine decay from lr to lr_min over the run; rows are the
