@@ -25,17 +25,25 @@ _SO = os.path.join(_HERE, "libcvib_oracle.so")
 _SOURCES = ["cvib_oracle.c", "mlp_oracle.c"]
 
 
+def compile_library(srcs, out: str) -> str:
+    """gcc, FP64, no fast-math, OpenMP: the oracle's one build recipe."""
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+           "-o", tmp] + list(srcs) + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def sources() -> list[str]:
+    return [os.path.join(_HERE, s) for s in _SOURCES]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, no fast-math, OpenMP)."""
-    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    """Compile the oracle."""
     if not force and os.path.exists(_SO):
         return _SO
-    tmp = _SO + ".tmp"
-    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
-           "-o", tmp] + srcs + ["-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, _SO)
-    return _SO
+    return compile_library(sources(), _SO)
 
 
 class Grid(C.Structure):
@@ -51,7 +59,7 @@ class Rule(C.Structure):
 CAND_DTYPE = np.dtype([
     ("vp", "<f8", 3), ("vm", "<f8", 3), ("linp", "<f8", 3), ("linm", "<f8", 3),
     ("Vp", "u1", 3), ("Vm", "u1", 3), ("gamut", "u1"), ("pattern", "u1"),
-    ("valid", "u1"), ("boundary", "u1"), ("_pad", "u1", 4)], align=True)
+    ("valid", "u1"), ("boundary", "u1"), ("dset", "u1"), ("_pad", "u1", 3)], align=True)
 assert CAND_DTYPE.itemsize == 112
 
 REC_DTYPE = np.dtype([("colour", "<u4"), ("i", "<u2"), ("j", "<u2"), ("plus", "u1", 3),
@@ -65,6 +73,15 @@ SUMMARY_DTYPE = np.dtype([
     ("_pad", "u1"), ("per_pattern", "<u4", 7)])
 assert SUMMARY_DTYPE.itemsize == 56
 
+# Ranges of a colour's outputs when each decision-ambiguous candidate may end
+# either way (orc_reduce_bounds); keys are i << 16 | (0xFFFF - j), 0 = none.
+BOUNDS_DTYPE = np.dtype([
+    ("count_lo", "<u4"), ("count_hi", "<u4"), ("pat_lo", "<u4", 7), ("pat_hi", "<u4", 7),
+    ("key_lo", "<u4"), ("key_hi", "<u4"), ("pkey_lo", "<u4", 7), ("pkey_hi", "<u4", 7),
+    ("n_gamut", "<u4"), ("n_boundary", "<u4"), ("n_ambiguous", "<u4"), ("best_band", "u1"),
+    ("pbest_band", "u1", 7), ("_pad", "<u4")])
+assert BOUNDS_DTYPE.itemsize == 152
+
 _lib = None
 
 
@@ -73,31 +90,38 @@ def lib():
     if _lib is None:
         if not os.path.exists(_SO):
             build()
-        L = C.CDLL(_SO)
-        P = C.c_void_p
-        L.orc_matrices.argtypes = [P, P, P]
-        L.orc_decode.argtypes = [C.c_double]
-        L.orc_decode.restype = C.c_double
-        L.orc_encode.argtypes = [C.c_double]
-        L.orc_encode.restype = C.c_double
-        L.orc_rgb8_to_lab.argtypes = [P, C.c_int64, P]
-        L.orc_lab_to_linear.argtypes = [P, C.c_int64, P]
-        L.orc_lab_to_v.argtypes = [P, C.c_int64, P, P]
-        L.orc_eval.argtypes = [P, C.POINTER(Grid), C.POINTER(Rule), C.c_int32, C.c_int32,
-                               C.c_int32, P]
-        L.orc_eval_all.argtypes = [P, C.c_int64, C.POINTER(Grid), C.POINTER(Rule), P, C.c_int32]
-        L.orc_eval_list.argtypes = [P, P, C.c_int64, C.POINTER(Grid), C.POINTER(Rule), P,
-                                    C.c_int32]
-        L.orc_search.argtypes = [P, C.c_int64, C.POINTER(Grid), C.POINTER(Rule), P, C.c_int64,
-                                 P, P, C.c_int32]
-        L.orc_search.restype = C.c_int64
-        L.orc_reduce.argtypes = [P, C.c_int64, C.POINTER(Grid), C.POINTER(Rule), P, P, P,
-                                 C.c_int32]
-        L.orc_max_gamut_radius.argtypes = [P, C.c_int64, C.POINTER(Grid), P, C.c_int32]
-        L.orc_num_threads.restype = C.c_int32
-        _mlp_bind(L)
-        _lib = L
+        _lib = load_library(_SO)
     return _lib
+
+
+def load_library(path: str) -> C.CDLL:
+    """Load a build of the oracle's sources and declare its entry points."""
+    L = C.CDLL(path)
+    P = C.c_void_p
+    L.orc_matrices.argtypes = [P, P, P]
+    L.orc_decode.argtypes = [C.c_double]
+    L.orc_decode.restype = C.c_double
+    L.orc_encode.argtypes = [C.c_double]
+    L.orc_encode.restype = C.c_double
+    L.orc_rgb8_to_lab.argtypes = [P, C.c_int64, P]
+    L.orc_lab_to_linear.argtypes = [P, C.c_int64, P]
+    L.orc_lab_to_v.argtypes = [P, C.c_int64, P, P]
+    L.orc_eval.argtypes = [P, C.POINTER(Grid), C.POINTER(Rule), C.c_int32, C.c_int32,
+                           C.c_int32, P]
+    L.orc_eval_all.argtypes = [P, C.c_int64, C.POINTER(Grid), C.POINTER(Rule), P, C.c_int32]
+    L.orc_eval_list.argtypes = [P, P, C.c_int64, C.POINTER(Grid), C.POINTER(Rule), P,
+                                C.c_int32]
+    L.orc_search.argtypes = [P, C.c_int64, C.POINTER(Grid), C.POINTER(Rule), P, C.c_int64,
+                             P, P, C.c_int32]
+    L.orc_search.restype = C.c_int64
+    L.orc_reduce.argtypes = [P, C.c_int64, C.POINTER(Grid), C.POINTER(Rule), P, P, P,
+                             C.c_int32]
+    L.orc_max_gamut_radius.argtypes = [P, C.c_int64, C.POINTER(Grid), P, C.c_int32]
+    L.orc_reduce_bounds.argtypes = [P, C.c_int64, C.POINTER(Grid), C.POINTER(Rule), P, P, P, P, P,
+                                    C.c_int32]
+    L.orc_num_threads.restype = C.c_int32
+    _mlp_bind(L)
+    return L
 
 
 def _ptr(a: np.ndarray):
@@ -167,11 +191,11 @@ def lab_to_v(lab):
     return v, g
 
 
-def eval_one(color, g, r=None, i=0, j=0, r_zero=False) -> np.ndarray:
+def eval_one(color, g, r=None, i=0, j=0, r_zero=False, L=None) -> np.ndarray:
     rgb = _rgb(color)
     out = np.zeros(1, dtype=CAND_DTYPE)
     ru = _as_rule(r)
-    lib().orc_eval(_ptr(rgb), C.byref(_as_grid(g)), C.byref(ru) if ru else None, int(i),
+    (L or lib()).orc_eval(_ptr(rgb), C.byref(_as_grid(g)), C.byref(ru) if ru else None, int(i),
                    int(j), int(bool(r_zero)), _ptr(out))
     return out[0]
 
@@ -187,13 +211,14 @@ def eval_all(colors, g, r=None, nthreads: int = 0) -> np.ndarray:
     return out
 
 
-def eval_list(colors, idx, g, r=None, nthreads: int = 0) -> np.ndarray:
-    """Candidates named by rows (colour index, i, j) of idx."""
+def eval_list(colors, idx, g, r=None, nthreads: int = 0, L=None) -> np.ndarray:
+    """Candidates named by rows (colour index, i, j) of idx (L: another build
+    of the oracle, from load_library)."""
     rgb = _rgb(colors)
     idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).reshape(-1, 3))
     out = np.zeros(idx.shape[0], dtype=CAND_DTYPE)
     ru = _as_rule(r)
-    lib().orc_eval_list(_ptr(rgb), _ptr(idx), idx.shape[0], C.byref(_as_grid(g)),
+    (L or lib()).orc_eval_list(_ptr(rgb), _ptr(idx), idx.shape[0], C.byref(_as_grid(g)),
                         C.byref(ru) if ru else None, _ptr(out), int(nthreads))
     return out
 
@@ -227,6 +252,29 @@ def reduce(colors, g, r, table: bool = False, nthreads: int = 0):
     lib().orc_reduce(_ptr(rgb), n, C.byref(gg), C.byref(ru), _ptr(summ),
                      _ptr(tc) if table else None, _ptr(tb) if table else None, int(nthreads))
     return (summ, tc, tb) if table else summ
+
+
+def reduce_bounds(colors, g, r, bins: bool = False, rays: bool = False, nthreads: int = 0):
+    """Per colour, the range every reduce output can take when each
+    decision-ambiguous candidate may end either way: BOUNDS_DTYPE [n], and
+    with bins (bins_lo, bins_hi) u8 [n, 36], with rays (rays_lo, rays_hi)
+    u16 [n, ntheta] (largest i + 1 over must / may survivors, 0 = none).
+    Returns a dict with the keys that were asked for."""
+    rgb = _rgb(colors)
+    gg, ru = _as_grid(g), _as_rule(r)
+    n = rgb.shape[0]
+    out = {"bounds": np.zeros(n, dtype=BOUNDS_DTYPE)}
+    bl = bh = rl = rh = None
+    if bins:
+        bl, bh = np.zeros((n, 36), np.uint8), np.zeros((n, 36), np.uint8)
+        out.update(bins_lo=bl, bins_hi=bh)
+    if rays:
+        rl, rh = np.zeros((n, gg.ntheta), np.uint16), np.zeros((n, gg.ntheta), np.uint16)
+        out.update(rays_lo=rl, rays_hi=rh)
+    lib().orc_reduce_bounds(_ptr(rgb), n, C.byref(gg), C.byref(ru), _ptr(out["bounds"]),
+                            _ptr(bl) if bins else None, _ptr(bh) if bins else None,
+                            _ptr(rl) if rays else None, _ptr(rh) if rays else None, int(nthreads))
+    return out
 
 
 def max_gamut_radius(colors, g, nthreads: int = 0) -> np.ndarray:

@@ -82,7 +82,10 @@ typedef struct {
     uint8_t valid;      /* survivor under the rule                            */
     uint8_t boundary;   /* bit0: some channel within the 1e-3 band; bit1: a    */
                         /* value inside the band changes the decision         */
-    uint8_t _pad[4];
+    uint8_t dset;       /* decisions reachable inside the band: bit 0 = not a  */
+                        /* survivor, bit p = survivor of pattern p (0 without */
+                        /* a rule)                                            */
+    uint8_t _pad[3];
 } orc_cand;
 
 /* Survivor record, 16 bytes, emitted in (colour, i, j) order. */
@@ -272,11 +275,15 @@ static int decide_codes(const orc_rule* ru, int clip, int gp, int gm, const int 
     return (ok && p != 0 && ((ru->mask >> (p - 1)) & 1u)) ? 8 + p : 0;
 }
 
-/* Whether moving any channel by less than the band (rounding it to the other
- * side of a nearby tie, or across a nearby gamut edge) changes the decision.
- * Every combination of such moves is tried. */
-static int decision_ambiguous(const orc_rule* ru, int clip, const double vp[3], const double vm[3],
-                              int gp, int gm) {
+/* The decisions (bit 0: not a survivor; bit p: a survivor of pattern p) that
+ * moving channels by less than the band can reach: rounding a channel to the
+ * other side of a nearby tie, or taking a colour across a nearby gamut edge.
+ * Every combination of such moves is tried.  More than one bit set means the
+ * candidate is decision-ambiguous. */
+static int dec_bit(int d) { return d ? 1 << (d - 8) : 1; }
+
+static int decision_set(const orc_rule* ru, int clip, const double vp[3], const double vm[3],
+                        int gp, int gm) {
     const double v[6] = {vp[0], vp[1], vp[2], vm[0], vm[1], vm[2]};
     int nom[6], alt[6];
     int edge_p = 0, edge_m = 0, out_p = 0, out_m = 0;
@@ -296,15 +303,15 @@ static int decision_ambiguous(const orc_rule* ru, int clip, const double vp[3], 
     }
     const int gp_alt = (edge_p && !out_p) ? !gp : gp;
     const int gm_alt = (edge_m && !out_m) ? !gm : gm;
-    const int nominal = decide_codes(ru, clip, gp, gm, nom, nom + 3);
+    int set = dec_bit(decide_codes(ru, clip, gp, gm, nom, nom + 3));
     for (int mask = 1; mask < 256; ++mask) {
         int code[6];
         for (int k = 0; k < 6; ++k) code[k] = ((mask >> k) & 1) ? alt[k] : nom[k];
         const int g1 = ((mask >> 6) & 1) ? gp_alt : gp;
         const int g2 = ((mask >> 7) & 1) ? gm_alt : gm;
-        if (decide_codes(ru, clip, g1, g2, code, code + 3) != nominal) return 1;
+        set |= dec_bit(decide_codes(ru, clip, g1, g2, code, code + 3));
     }
-    return 0;
+    return set;
 }
 
 /* Evaluate candidate (i, j) of target t under rule ru (ru may be NULL: then
@@ -347,20 +354,27 @@ static void eval_cand(const orc_target* t, const orc_grid* g, const orc_rule* ru
     c->boundary = (uint8_t)(clip ? tie : (!any_out && (edge || tie)));
     c->pattern = 0;
     c->valid = 0;
+    c->dset = 0;
+    memset(c->_pad, 0, sizeof c->_pad);
     if (!ru) return;
-    if (c->boundary && decision_ambiguous(ru, clip, c->vp, c->vm, gp, gm)) c->boundary |= 2;
-    if (!(clip || (gp && gm))) return;
-    double lo = (double)ru->v_th * ru->r_novib;
-    int p = 0, ok = 1;
-    for (int k = 0; k < 3; ++k) {
-        int d = abs((int)c->Vp[k] - (int)c->Vm[k]);
-        int hi = d > ru->v_th;
-        int low = (double)d < lo;
-        if (!(hi || low)) ok = 0;
-        p = 2 * p + hi;
+    if ((clip || (gp && gm))) {
+        double lo = (double)ru->v_th * ru->r_novib;
+        int p = 0, ok = 1;
+        for (int k = 0; k < 3; ++k) {
+            int d = abs((int)c->Vp[k] - (int)c->Vm[k]);
+            int hi = d > ru->v_th;
+            int low = (double)d < lo;
+            if (!(hi || low)) ok = 0;
+            p = 2 * p + hi;
+        }
+        if (ok) c->pattern = (uint8_t)p;
+        c->valid = (uint8_t)(ok && p != 0 && ((ru->mask >> (p - 1)) & 1u));
     }
-    if (ok) c->pattern = (uint8_t)p;
-    c->valid = (uint8_t)(ok && p != 0 && ((ru->mask >> (p - 1)) & 1u));
+    c->dset = (uint8_t)(c->valid ? 1 << c->pattern : 1);
+    if (c->boundary) {
+        c->dset = (uint8_t)decision_set(ru, clip, c->vp, c->vm, gp, gm);
+        if (c->dset & (c->dset - 1)) c->boundary |= 2;
+    }
 }
 
 /* Single candidate evaluation, exposed for the tests.  r_zero forces r = 0. */
@@ -522,6 +536,93 @@ void orc_reduce(const uint8_t* rgb, int64_t n, const orc_grid* g, const orc_rule
         if (summ) summ[col] = s;
         if (table_count) table_count[col] = s.count;
         if (table_bins) memcpy(table_bins + 36 * col, bins, 36);
+    }
+}
+
+/* What an evaluation that agrees with this one outside the band may report
+ * for each colour: every output of the reduce as the range it can take when
+ * each decision-ambiguous candidate may end either way (any decision in its
+ * dset).  A candidate that must survive (dset = {p}) counts in both ends; one
+ * that may survive counts in the upper end only.  Keys order the survivors
+ * as the maximum-amplitude rule does: key = i << 16 | (0xFFFF - j), 0 = none. */
+typedef struct {
+    uint32_t count_lo, count_hi;
+    uint32_t pat_lo[7], pat_hi[7];   /* survivors of pattern p at p - 1          */
+    uint32_t key_lo, key_hi;         /* best key over must / may survivors        */
+    uint32_t pkey_lo[7], pkey_hi[7]; /* best key of each pattern                  */
+    uint32_t n_gamut, n_boundary, n_ambiguous;
+    uint8_t best_band;               /* the must-survivor of key_lo is in the band */
+    uint8_t pbest_band[7];           /* (its codes may differ by a rounding)       */
+    uint32_t _pad;
+} orc_bounds;
+
+static uint32_t cand_key(int32_t i, int32_t j) { return ((uint32_t)i << 16) | (0xFFFFu - (uint32_t)j); }
+
+/* Per colour: bounds (nullable); bins_lo / bins_hi [n][36] (nullable) the
+ * per-bin largest i + 1 over must / may survivors (capped at 255);
+ * rays_lo / rays_hi [n][ntheta] (nullable) the same per ray, uncapped. */
+void orc_reduce_bounds(const uint8_t* rgb, int64_t n, const orc_grid* g, const orc_rule* ru,
+                       orc_bounds* bounds, uint8_t* bins_lo, uint8_t* bins_hi, uint16_t* rays_lo,
+                       uint16_t* rays_hi, int32_t nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t col = 0; col < n; ++col) {
+        orc_target t;
+        target_init(&t, rgb + 3 * col);
+        orc_bounds b;
+        memset(&b, 0, sizeof b);
+        uint8_t blo[36], bhi[36];
+        memset(blo, 0, sizeof blo);
+        memset(bhi, 0, sizeof bhi);
+        uint16_t* rlo = rays_lo ? rays_lo + col * g->ntheta : NULL;
+        uint16_t* rhi = rays_hi ? rays_hi + col * g->ntheta : NULL;
+        if (rlo) memset(rlo, 0, sizeof(uint16_t) * (size_t)g->ntheta);
+        if (rhi) memset(rhi, 0, sizeof(uint16_t) * (size_t)g->ntheta);
+        const int64_t turn = llround(360.0 / g->dtheta_deg);
+        for (int32_t i = 0; i < g->nr; ++i) {
+            for (int32_t j = 0; j < g->ntheta; ++j) {
+                orc_cand c;
+                eval_cand(&t, g, ru, i, j, 0, &c);
+                b.n_boundary += c.boundary & 1;
+                b.n_ambiguous += (c.boundary >> 1) & 1;
+                if (c.gamut == 3) b.n_gamut++;
+                const int may = (c.dset & 0xFE) != 0, must = !(c.dset & 1);
+                if (!may) continue;
+                const uint32_t key = cand_key(i, j);
+                const int bin = (int)(((int64_t)j * 36) / turn);
+                const int ridx = i + 1 > 255 ? 255 : i + 1;
+                b.count_hi++;
+                if (ridx > bhi[bin]) bhi[bin] = (uint8_t)ridx;
+                if (rhi && i + 1 > rhi[j]) rhi[j] = (uint16_t)(i + 1);
+                if (key > b.key_hi) b.key_hi = key;
+                if (must) {
+                    b.count_lo++;
+                    if (ridx > blo[bin]) blo[bin] = (uint8_t)ridx;
+                    if (rlo && i + 1 > rlo[j]) rlo[j] = (uint16_t)(i + 1);
+                    if (key > b.key_lo) {
+                        b.key_lo = key;
+                        b.best_band = c.boundary & 1;
+                    }
+                }
+                for (int p = 1; p <= 7; ++p) {
+                    if (!((c.dset >> p) & 1)) continue;
+                    b.pat_hi[p - 1]++;
+                    if (key > b.pkey_hi[p - 1]) b.pkey_hi[p - 1] = key;
+                    if (c.dset == (1 << p)) {
+                        b.pat_lo[p - 1]++;
+                        if (key > b.pkey_lo[p - 1]) {
+                            b.pkey_lo[p - 1] = key;
+                            b.pbest_band[p - 1] = c.boundary & 1;
+                        }
+                    }
+                }
+            }
+        }
+        if (bounds) bounds[col] = b;
+        if (bins_lo) memcpy(bins_lo + 36 * col, blo, 36);
+        if (bins_hi) memcpy(bins_hi + 36 * col, bhi, 36);
     }
 }
 

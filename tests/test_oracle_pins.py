@@ -7,83 +7,16 @@ the published definitions (IEC 61966-2-1 sRGB, CIE 1976 L*a*b*).
 from __future__ import annotations
 
 import os
-from decimal import ROUND_HALF_EVEN, Decimal, getcontext
-
 import numpy as np
 import pytest
 
 import workloads as W
 
-getcontext().prec = 50
-D = Decimal
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-# --------------------------------------------------------------------------
-# An independent arbitrary-precision model of the colour conversions.
-
-def _solve3(A, b):
-    """Gauss-Jordan elimination with partial pivoting (Decimal)."""
-    m = [list(A[r]) + [b[r]] for r in range(3)]
-    for c in range(3):
-        piv = max(range(c, 3), key=lambda r: abs(m[r][c]))
-        m[c], m[piv] = m[piv], m[c]
-        for r in range(3):
-            if r != c:
-                f = m[r][c] / m[c][c]
-                m[r] = [m[r][k] - f * m[c][k] for k in range(4)]
-    return [m[r][3] / m[r][r] for r in range(3)]
-
-
-def _dec_space():
-    prim = [(D("0.64"), D("0.33")), (D("0.30"), D("0.60")), (D("0.15"), D("0.06"))]
-    wx, wy = D("0.3127"), D("0.3290")
-    P = [[x / y for x, y in prim], [D(1)] * 3, [(1 - x - y) / y for x, y in prim]]
-    Wv = [wx / wy, D(1), (1 - wx - wy) / wy]
-    S = _solve3(P, Wv)
-    M = [[P[r][c] * S[c] for c in range(3)] for r in range(3)]
-    # columns of the inverse: solve M x = e_k
-    cols = [_solve3(M, [D(int(k == r)) for r in range(3)]) for k in range(3)]
-    Minv = [[cols[c][r] for c in range(3)] for r in range(3)]
-    return M, Minv, Wv
-
-
-DM, DMINV, DW = _dec_space()
-DELTA = D(6) / D(29)
-
-
-def d_decode(c):
-    return c / D("12.92") if c <= D("0.04045") else ((c + D("0.055")) / D("1.055")) ** D("2.4")
-
-
-def d_encode(l):
-    return D("12.92") * l if l <= D("0.0031308") else D("1.055") * l ** (D(1) / D("2.4")) - D("0.055")
-
-
-def d_f(t):
-    return t ** (D(1) / D(3)) if t > DELTA ** 3 else t / (3 * DELTA ** 2) + D(4) / D(29)
-
-
-def d_finv(u):
-    return u ** 3 if u > DELTA else 3 * DELTA ** 2 * (u - D(4) / D(29))
-
-
-def d_rgb8_to_lab(rgb):
-    lin = [d_decode(D(int(v)) / D(255)) for v in rgb]
-    xyz = [sum(DM[r][k] * lin[k] for k in range(3)) for r in range(3)]
-    f = [d_f(xyz[r] / DW[r]) for r in range(3)]
-    return [116 * f[1] - 16, 500 * (f[0] - f[1]), 200 * (f[1] - f[2])]
-
-
-def d_lab_to_linear(lab):
-    L, a, b = lab
-    fy = (L + 16) / 116
-    xyz = [DW[0] * d_finv(fy + a / 500), DW[1] * d_finv(fy), DW[2] * d_finv(fy - b / 200)]
-    return [sum(DMINV[r][k] * xyz[k] for k in range(3)) for r in range(3)]
-
-
-def d_round(v):
-    return int(v.quantize(D(1), rounding=ROUND_HALF_EVEN))
+from dec_model import (D, DM, d_decode, d_encode, d_lab_to_linear, d_rgb8_to_lab,  # noqa: E402
+                       d_round)
 
 
 # --------------------------------------------------------------------------
