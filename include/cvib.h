@@ -236,6 +236,27 @@ int cv_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
                    void* stream);
 
 /*
+ * cv_pair_reduce without any allocation, for callers that cannot allocate
+ * device memory during the call (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, outputs and
+ * results as cv_pair_reduce, byte for byte.  The workspace is a fixed
+ * 8 MiB device array per GPU (reserved when the library's code object loads,
+ * kept until the process ends, its address looked up once per device by
+ * cv_context_create); a call whose workspace would exceed it returns
+ * CV_ECAPACITY, naming the bytes it would need, without enqueuing anything.
+ * The workspace is 64 bytes per colour plus the angle table, and 192 more
+ * per colour below 2048 colours: e.g. up to ~130,000 colours on the 2-degree
+ * cube grid.  Every call on one GPU shares that array, so calls
+ * that overlap on one GPU (two streams, two threads, two contexts) race and
+ * must be serialised by the caller; each call clears what it needs zeroed.
+ * Kernel timing (cv_context_set_timing) records nothing for these calls.
+ * Errors: CV_EINVAL, CV_ECAPACITY, CV_EHIP, CV_ESTATE.
+ */
+int cv_pair_reduce_noalloc(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,
+                           const cv_rule* rule, cv_color_summary* summ, cv_table_row* table,
+                           void* stream);
+
+/*
  * Summaries of a survivor list (the output of cv_pair_search, either mode):
  * recs (cv_pair, device) with CSR offsets (int64 [n + 1], device) -> summ
  * (cv_color_summary [n], device): count, per-pattern counts and the

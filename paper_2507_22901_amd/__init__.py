@@ -74,7 +74,8 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_surrogate_infer", "cv_frames_surrogate", "cv_context_set_autotune",
            "cv_context_set_resolve_variant", "cv_context_resolve_variant", "cv_pair_reduce_rules",
            "cv_pair_reduce_csr", "cv_context_set_gamut_cells", "cv_context_skipped",
-           "cv_mlp_set_first_sine", "cv_mlp_first_sine", "cv_permute_ids", "cv_context_no_high")
+           "cv_mlp_set_first_sine", "cv_mlp_first_sine", "cv_permute_ids", "cv_context_no_high",
+           "cv_pair_reduce_noalloc")
 CV_NO_FALLBACK = 0x4
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
 CV_RESOLVED_SURROGATE, CV_RESOLVED_EXACT, CV_RESOLVED_NONE = 0, 1, 2
@@ -102,6 +103,7 @@ def lib() -> C.CDLL:
         L.cv_pair_search.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, I64,
                                      P, P, C.POINTER(I64), C.c_uint32, P]
         L.cv_pair_reduce.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P]
+        L.cv_pair_reduce_noalloc.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P]
         L.cv_frames_resolve.argtypes = [P, P, I64, P, C.POINTER(cv_grid), C.POINTER(cv_rule), P,
                                         I64, P, P, P, P, P, P, P, P, C.c_uint32, P]
         L.cv_context_set_timing.argtypes = [P, C.c_int]
@@ -394,6 +396,22 @@ def pair_reduce(colors: torch.Tensor, grid: Grid, rule: Rule, summaries: bool = 
     _check(lib().cv_pair_reduce(ctx.handle, _dptr(colors), n, C.byref(g), C.byref(r), _dptr(summ),
                                 _dptr(tab), _stream()))
     return summ, tab
+
+
+def pair_reduce_noalloc(colors: torch.Tensor, grid: Grid, rule: Rule, summ: torch.Tensor | None,
+                        table: torch.Tensor | None = None, ctx: Context | None = None):
+    """cv_pair_reduce_noalloc: pair_reduce into the caller's outputs (summ
+    uint8 [n, 48], table uint8 [n, 40], either may be None but not both) with
+    no allocation on the library's side; calls on one GPU must not overlap."""
+    colors = _colours(colors)
+    ctx = ctx or context(colors.device.index)
+    n = colors.shape[0]
+    _require(summ, "summ", torch.uint8, 48 * n, colors.device)
+    _require(table, "table", torch.uint8, 40 * n, colors.device)
+    g, r = grid.c(), rule.c()
+    _check(lib().cv_pair_reduce_noalloc(ctx.handle, _dptr(colors), n, C.byref(g), C.byref(r),
+                                        _dptr(summ), _dptr(table), _stream()))
+    return summ, table
 
 
 def pair_reduce_csr(records: torch.Tensor, offsets: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:

@@ -199,6 +199,13 @@ int cv_context_create(int device, cv_context** out) {
         delete c;
         return cvib::hip_fail(e, "hipHostMalloc");
     }
+    // device address of the no-allocation reduce's scratch array on this device
+    int rc = cvib::scratch_init(device);
+    if (rc != CV_OK) {
+        (void)hipHostFree(c->host_misc);
+        delete c;
+        return rc;
+    }
     *out = c;
     return CV_OK;
     CV_GUARD_END
@@ -282,6 +289,27 @@ int cv_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid
         return fail(CV_EINVAL, "table rows need 8 * table + 4 * ntheta <= 48 KiB of LDS");
     DeviceGuard dg(ctx->device);
     return cvib::run_pair_reduce(ctx, rgb, n, gd, rd, summ, table, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
+int cv_pair_reduce_noalloc(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid,
+                           const cv_rule* rule, cv_color_summary* summ, cv_table_row* table,
+                           void* stream) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    if (n < 0 || n > 0xFFFFFFFFll) return fail(CV_EINVAL, "n out of range");
+    if (n > 0 && !rgb) return fail(CV_EINVAL, "rgb is NULL");
+    if (!summ && !table) return fail(CV_EINVAL, "summ and table are both NULL");
+    cvib::GridDev gd;
+    cvib::RuleDev rd;
+    int rc;
+    if ((rc = cvib::make_grid(grid, &gd)) != CV_OK) return rc;
+    if ((rc = cvib::make_rule(rule, &rd)) != CV_OK) return rc;
+    if (table && gd.nr > 255) return fail(CV_EINVAL, "table rows need grid.nr <= 255");
+    if (table && (size_t)gd.tab_len * 8 + (size_t)gd.ntheta * 4 > 48 * 1024)
+        return fail(CV_EINVAL, "table rows need 8 * table + 4 * ntheta <= 48 KiB of LDS");
+    DeviceGuard dg(ctx->device);
+    return cvib::run_pair_reduce_noalloc(ctx, rgb, n, gd, rd, summ, table, (hipStream_t)stream);
     CV_GUARD_END
 }
 

@@ -77,6 +77,14 @@ int run_lab_convert(cv_context* ctx, const void* in, void* out, int64_t n, int d
 int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
                     const RuleDev& rd, cv_pair* out, int64_t capacity, int64_t* offsets,
                     cv_color_summary* summ, int64_t* total_host, uint32_t flags, hipStream_t s);
+// Scratch array of the no-allocation reduce (one per device, kept until the
+// process ends) and its set-up, once per device with the device current.
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+int scratch_init(int device);
+size_t reduce_scratch_bytes(int64_t n, const GridDev& gd);
+int run_pair_reduce_noalloc(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
+                            const RuleDev& rd, cv_color_summary* summ, cv_table_row* table,
+                            hipStream_t s);
 int run_pair_csr_summary(cv_context* ctx, const cv_pair* recs, const int64_t* offsets, int64_t n,
                          cv_color_summary* summ, hipStream_t s);
 int run_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,

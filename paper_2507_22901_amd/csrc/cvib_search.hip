@@ -8,6 +8,8 @@
 // change is above V_th and 0 when it is under V_th * R_novib).
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -1187,26 +1189,33 @@ ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, c
 
 } // namespace
 
-// Per-colour constants and the angle table of a call (shared with the
-// multi-rule pass).
-int prepare_colours(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd, hipStream_t s,
-            TabArgs& tab) {
-    int rc;
-    if ((rc = ctx->ensure(ctx->colors, (size_t)n * sizeof(ColorConst))) != CV_OK) return rc;
-    if ((rc = ctx->ensure(ctx->table, (size_t)gd.tab_len * sizeof(double))) != CV_OK) return rc;
-    hipLaunchKernelGGL(k_angle_table, dim3(blocks_for(gd.N / 2 + 1, 256)), dim3(256), 0, s,
-                       (double*)ctx->table.ptr, gd.N);
+// Per-colour constants and the angle table of a call, written to the given
+// device arrays (colors: ColorConst [n]; table: tab_len doubles).
+static int prepare_colours_at(ColorConst* colors, double* table, const uint8_t* rgb, int64_t n,
+                              const GridDev& gd, hipStream_t s, TabArgs& tab) {
+    hipLaunchKernelGGL(k_angle_table, dim3(blocks_for(gd.N / 2 + 1, 256)), dim3(256), 0, s, table,
+                       gd.N);
     CV_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_color_prologue, dim3(blocks_for(n, 256)), dim3(256), 0, s, rgb,
-                       (ColorConst*)ctx->colors.ptr, n, mat_args());
+    hipLaunchKernelGGL(k_color_prologue, dim3(blocks_for(n, 256)), dim3(256), 0, s, rgb, colors, n,
+                       mat_args());
     CV_HIP(hipGetLastError());
-    tab.tab = (const double*)ctx->table.ptr;
+    tab.tab = table;
     tab.tab_len = gd.tab_len;
     tab.N = gd.N;
     // room for the per-ray maxima of the angle-bin table as well
     tab.dW = direct_rays(gd.ntheta, gd.N, gd.tab_len, (size_t)gd.ntheta * 4);
     tab._pad = 0;
     return CV_OK;
+}
+
+// The same in the context's workspace (shared with the multi-rule pass).
+int prepare_colours(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd, hipStream_t s,
+            TabArgs& tab) {
+    int rc;
+    if ((rc = ctx->ensure(ctx->colors, (size_t)n * sizeof(ColorConst))) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->table, (size_t)gd.tab_len * sizeof(double))) != CV_OK) return rc;
+    return prepare_colours_at((ColorConst*)ctx->colors.ptr, (double*)ctx->table.ptr, rgb, n, gd, s,
+                              tab);
 }
 
 int launch_angle_table(double* tab, int32_t N, hipStream_t s) {
@@ -1569,38 +1578,122 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     return CV_OK;
 }
 
+// Device arrays one reduce call works in.
+struct ReduceWs {
+    ColorConst* colors;  // [n]
+    double* table;       // folded angle table
+    uint64_t* misc;      // 8 words, zeroed by the call
+    SumAcc* acc;         // [n] in atomic mode, zeroed by the call; unused in direct mode
+};
+
+static int reduce_in(cv_context* ctx, const ReduceWs& ws, bool timed, const uint8_t* rgb, int64_t n,
+                     const GridDev& gd, const RuleDev& rd, cv_color_summary* summ,
+                     cv_table_row* table, hipStream_t s) {
+    int rc;
+    TabArgs tab;
+    if ((rc = prepare_colours_at(ws.colors, ws.table, rgb, n, gd, s, tab)) != CV_OK) return rc;
+    const bool sym = gd.ntheta == gd.N;
+    const int32_t W = sym ? gd.N / 2 : gd.ntheta;
+    const int64_t per = (int64_t)gd.nr * W;  // evaluations per colour
+    const ReducePlan pl = plan_reduce(n, per, 0);
+    if ((rc = zero_u64(ws.misc, 8, s)) != CV_OK) return rc;
+    if (!pl.direct && (rc = zero_u64(ws.acc, n * (int64_t)(sizeof(SumAcc) / 8), s)) != CV_OK)
+        return rc;
+    ReduceArgs a = reduce_args(ctx, tab, gd, rd, W, pl, n);
+    a.cc = ws.colors;
+    a.misc = ws.misc;
+    a.acc = pl.direct ? nullptr : ws.acc;
+    if (!timed) a.stats = nullptr;
+    a.summ = summ;
+    a.table = table;
+    if (timed && (rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
+    if (timed && (rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
+    if ((rc = launch_reduce(ctx, a, table != nullptr, pl.direct, sym, false, s)) != CV_OK) return rc;
+    if (timed && (rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
+    if (!pl.direct) {
+        hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 128)), dim3(128), 0, s, a.cc,
+                           (const SumAcc*)ws.acc, n, a.g, rd, tab, gd.ra, gd.rb, summ, table);
+        CV_HIP(hipGetLastError());
+    }
+    if (timed && (rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
+    if (timed && ctx->timing && (rc = ctx->collect()) != CV_OK) return rc;
+    return CV_OK;
+}
+
 int run_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
                     const RuleDev& rd, cv_color_summary* summ, cv_table_row* table,
                     hipStream_t s) {
     if (n == 0) return CV_OK;
     int rc;
-    TabArgs tab;
-    if ((rc = prepare_colours(ctx, rgb, n, gd, s, tab)) != CV_OK) return rc;
-    const bool sym = gd.ntheta == gd.N;
-    const int32_t W = sym ? gd.N / 2 : gd.ntheta;
-    const int64_t per = (int64_t)gd.nr * W;  // evaluations per colour
-    const ReducePlan pl = plan_reduce(n, per, 0);
+    if ((rc = ctx->ensure(ctx->colors, (size_t)n * sizeof(ColorConst))) != CV_OK) return rc;
+    if ((rc = ctx->ensure(ctx->table, (size_t)gd.tab_len * sizeof(double))) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->misc, 64)) != CV_OK) return rc;
-    if ((rc = zero_u64(ctx->misc.ptr, 8, s)) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->acc, (size_t)n * sizeof(SumAcc))) != CV_OK) return rc;
-    if (!pl.direct &&
-        (rc = zero_u64(ctx->acc.ptr, n * (int64_t)(sizeof(SumAcc) / 8), s)) != CV_OK)
-        return rc;
-    ReduceArgs a = reduce_args(ctx, tab, gd, rd, W, pl, n);
-    a.summ = summ;
-    a.table = table;
-    if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
-    if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
-    if ((rc = launch_reduce(ctx, a, table != nullptr, pl.direct, sym, false, s)) != CV_OK) return rc;
-    if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
-    if (!pl.direct) {
-        hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 128)), dim3(128), 0, s, a.cc,
-                           (const SumAcc*)ctx->acc.ptr, n, a.g, rd, tab, gd.ra, gd.rb, summ, table);
-        CV_HIP(hipGetLastError());
-    }
-    if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
-    if (ctx->timing && (rc = ctx->collect()) != CV_OK) return rc;
+    const ReduceWs ws{(ColorConst*)ctx->colors.ptr, (double*)ctx->table.ptr, (uint64_t*)ctx->misc.ptr,
+                      (SumAcc*)ctx->acc.ptr};
+    return reduce_in(ctx, ws, true, rgb, n, gd, rd, summ, table, s);
+}
+
+// ---------------------------------------------------------------------------
+// The reduce without allocation: its workspace is this file-scope array, one
+// copy per device, whose device address is looked up once per device when a
+// context is created.  Host code uses only that address, never the array's
+// name (in host code the name is a host-side stand-in).
+
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+int scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(CV_EINVAL, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return CV_OK;
+    void* p = nullptr;
+    CV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(CV_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch[device] = p;
     return CV_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t reduce_scratch_bytes(int64_t n, const GridDev& gd) {
+    const bool sym = gd.ntheta == gd.N;
+    const int64_t per = (int64_t)gd.nr * (sym ? gd.N / 2 : gd.ntheta);
+    const ReducePlan pl = plan_reduce(n, per, 0);
+    return align256(8 * sizeof(uint64_t)) + align256((size_t)gd.tab_len * sizeof(double)) +
+           align256((size_t)n * sizeof(ColorConst)) + (pl.direct ? 0 : (size_t)n * sizeof(SumAcc));
+}
+
+int run_pair_reduce_noalloc(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
+                            const RuleDev& rd, cv_color_summary* summ, cv_table_row* table,
+                            hipStream_t s) {
+    if (n == 0) return CV_OK;
+    const size_t need = reduce_scratch_bytes(n, gd);
+    if (need > kScratchBytes)
+        return fail(CV_ECAPACITY, "this call needs " + std::to_string(need) +
+                                      " bytes of scratch; the no-allocation reduce holds " +
+                                      std::to_string(kScratchBytes));
+    uint8_t* base;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = (uint8_t*)g_scratch[ctx->device];
+    }
+    if (!base) return fail(CV_ESTATE, "scratch address of this device not set up");
+    size_t o = 0;
+    ReduceWs ws;
+    ws.misc = (uint64_t*)(base + o);
+    o += align256(8 * sizeof(uint64_t));
+    ws.table = (double*)(base + o);
+    o += align256((size_t)gd.tab_len * sizeof(double));
+    ws.colors = (ColorConst*)(base + o);
+    o += align256((size_t)n * sizeof(ColorConst));
+    ws.acc = (SumAcc*)(base + o);
+    return reduce_in(ctx, ws, false, rgb, n, gd, rd, summ, table, s);
 }
 
 } // namespace cvib
