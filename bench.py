@@ -1,6 +1,13 @@
-"""Benchmark: candidate pairs evaluated per second on one MI355X.
+"""Benchmark: candidate pairs decided per second on one MI355X.
 
-Workload: the nine Table 1 colours, r = 0.01 .. 100 in steps of 0.01 (10,000
+`value` counts every candidate pair of the grid that a call decides: each is
+either evaluated (converted and tested) or settled without evaluation by the
+exact half-turn symmetry (ray j + N/2 holds ray j's pair with + and -
+swapped) or by an interval proof that its whole wave step holds no in-gamut
+pair or no channel change above V_th.  The evaluated pairs per second are
+reported beside it.
+
+Workload (the configuration the metric is quoted on): the nine Table 1 colours, r = 0.01 .. 100 in steps of 0.01 (10,000
 radii) x theta = 0 .. 359.9 deg in steps of 0.1 deg (3,600 angles), rule
 V_th = 50, R_novib = 0.5, any pattern: 36 M candidate pairs per colour,
 324 M per step.  A step is one cv_pair_search call: per-colour prologue
@@ -25,14 +32,27 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks and unit counts used by the roofline.
+# MI355X unit counts and published peaks used by the roofline.  The published
+# FP32 vector peak (157.3 TFLOP/s) counts packed FP32 FMAs (two per lane per
+# cycle); 78.6 TFLOP/s is the non-packed FP32 / FP64 FMA issue rate (one FMA per
+# lane per cycle), which is what these kernels can issue: packed FP32 is
+# disabled in the build and the geometry runs in FP64.
 CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
-VALU_FMA_PEAK = CUS * SIMDS_PER_CU * LANES_PER_SIMD * 2 * CLOCK_HZ  # 78.6e12 flop/s
+FP32_PEAK = 157.3e12
+VALU_FMA_PEAK = CUS * SIMDS_PER_CU * LANES_PER_SIMD * 2 * CLOCK_HZ  # 78.6e12 flop/s, non-packed
 HBM_PEAK = 8e12
 
-# Algorithmic floating-point work of the evaluation kernel (FMA = 2 flops,
-# transcendental = 1; compares, selects, conversions and rounding not counted).
-# Per evaluated pair (when theta spans the full turn only rays j < N/2 are
+# Algorithmic work per evaluated candidate pair (both colours): 85 FP32 flops
+# (FMA = 2, transcendental = 1), the op count of the fused generate -> convert
+# -> predicate step: displacement and f(X), f(Z) (2 mul, 4 add), inverse
+# companding x4 (8 mul, 4 fma), linear RGB x2 (12 fma), encode and quantise x6
+# (12 mul, 6 fma, 12 transcendental), differences (3 add).  `achieved` is this
+# figure times the pairs one launch evaluates, over the launch's duration.
+FLOPS_PER_PAIR = 85
+
+# A finer count of the evaluation kernel's floating-point work, reported beside
+# the algorithmic figure (FMA = 2 flops, transcendental = 1; compares, selects,
+# conversions and rounding not counted).  Per evaluated pair (when theta spans the full turn only rays j < N/2 are
 # evaluated: ray j + N/2 is the same pair with + and - swapped):
 #   displacement (i+1)*dr/500*sin, (i+1)*dr/200*cos ........ 4 mul      =  4
 #   f(X), f(Z) of both colours ............................. 4 add      =  4
@@ -52,29 +72,41 @@ FLOPS_CODE = 33
 # (the code bounds of the open steps, 12 encodes more, are not counted)
 FLOPS_CELL = 84
 
-# Counter figures of the count pass on this workload, from rocprofv3 runs of
-# `bench.py --only nine` (profiles/search_nine_colours.md): HBM traffic =
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the same counters on
-# a 256 MiB device copy; VALU issue = SQ_INSTS_VALU x 4 cycles over 1024 SIMDs
-# x GRBM_GUI_ACTIVE cycles.  Valid only for the kernel sources they were
-# measured on (their digest).
-MEASURED_COUNTERS = {"sources_sha256": "7bfc5d4b2d4b6f302d0f42f5a2e846bbc8b4d376d94a32a382eaf08be9647f9a", "traffic_bytes": 62792764, "valu_issue": 0.541}
-KERNEL_SOURCES = ("cvib_search.hip", "cvib_device.h", "cvib_kernels.h")
+# Counter figures of each workload's dominant kernel, from rocprofv3 runs of
+# `bench.py --only <workload>` (profiles/): HBM traffic = FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch) scaled by the same counters on a 256 MiB
+# device copy; VALU issue = SQ_INSTS_VALU x 4 cycles over 1024 SIMDs x
+# GRBM_GUI_ACTIVE cycles per XCD.  Valid only for the kernel sources they were
+# measured on (their digest); null otherwise.
+MEASURED_COUNTERS = {
+    "count_pass": {"sources_sha256": "7bfc5d4b2d4b6f302d0f42f5a2e846bbc8b4d376d94a32a382eaf08be9647f9a",
+                   "traffic_bytes": 62792764, "valu_issue": 0.541},
+    "colour_resolve": None,
+    "cube_table": None,
+    "ray_search": None,
+}
+KERNEL_SOURCES = {
+    "count_pass": ("cvib_search.hip", "cvib_device.h", "cvib_kernels.h"),
+    "colour_resolve": ("cvib_frames.hip", "cvib_device.h", "cvib_kernels.h"),
+    "cube_table": ("cvib_search.hip", "cvib_device.h", "cvib_kernels.h"),
+    "ray_search": ("cvib_rays.hip", "cvib_device.h", "cvib_kernels.h"),
+}
 
 
-def kernel_sources_digest():
+def kernel_sources_digest(kernel="count_pass"):
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2507_22901_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_counter(name):
-    if MEASURED_COUNTERS["sources_sha256"] == kernel_sources_digest():
-        return MEASURED_COUNTERS[name]
-    return None
+def measured_counters(kernel):
+    m = MEASURED_COUNTERS.get(kernel)
+    if m and m["sources_sha256"] == kernel_sources_digest(kernel):
+        return m
+    return {}
 
 
 def parse():
@@ -88,17 +120,28 @@ def parse():
     ap.add_argument("--copy-reference", action="store_true",
                     help="only copy 256 MiB on the device three times (the known-size kernel "
                          "that scales FETCH_SIZE / WRITE_SIZE counters to bytes)")
-    ap.add_argument("--only", choices=("all", "nine", "table2", "frames", "cube", "surrogate"), default="all",
+    ap.add_argument("--only", choices=("all", "nine", "table2", "frames", "rays", "cube", "surrogate"), default="all",
                     help="run one workload only (the JSON line then carries just that part)")
     return ap.parse_args()
 
 
-def _alu_roofline(kernel, ms, evals, gamut_evals, cell_tests=0):
-    flops = FLOPS_GEOM * evals + FLOPS_CODE * gamut_evals + FLOPS_CELL * cell_tests
+def _alu_roofline(kernel, ms, evals, gamut_evals, cell_tests=0, counters=None):
+    """ALU roofline of one launch: achieved = 85 flop x evaluated pairs over the
+    launch's duration, against the published FP32 peak; the non-packed issue
+    rate and the finer flop count beside it."""
+    flops = FLOPS_PER_PAIR * evals
     achieved = flops / (ms * 1e-3)
+    fine = FLOPS_GEOM * evals + FLOPS_CODE * gamut_evals + FLOPS_CELL * cell_tests
+    c = counters or {}
     return {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12,
-            "peak": VALU_FMA_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / VALU_FMA_PEAK,
-            "traffic": None, "kernel_ms": ms, "flops_per_launch": flops,
+            "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK,
+            "traffic": c.get("traffic_bytes"), "kernel_ms": ms, "flops_per_launch": flops,
+            "frac_of_nonpacked_issue_rate": achieved / VALU_FMA_PEAK,
+            "valu_issue_profiled": c.get("valu_issue"),
+            "fine_count": {"flops_per_launch": fine, "achieved": fine / (ms * 1e-3) / 1e12,
+                           "frac": fine / (ms * 1e-3) / FP32_PEAK,
+                           "note": "geometry of every evaluated pair, encode of the in-gamut ones, "
+                                   "one interval proof per wave step of 64 decided pairs"},
             "evaluated_pairs": evals, "in_gamut_evaluations": gamut_evals}
 
 
@@ -153,9 +196,71 @@ def bench_frames(cv, W, torch, steps):
         "pixels_per_s": npix / (ms * 1e-3), "pairs_per_s": n * g.per_colour / (ms * 1e-3),
         "ms_per_call": ms, "calls": steps, "resolved_pixels": int(out.resolved.item()),
         "resolve_kernel_ms": t_res,
-        "roofline": dict(_alu_roofline("k_colour_resolve", t_res, evals, gamut - no_high, -(-decided // 64)),
+        "evaluated_pairs_per_s": evals / (ms * 1e-3),
+        "roofline": dict(_alu_roofline("k_colour_resolve", t_res, evals, gamut - no_high, -(-decided // 64),
+                                       measured_counters("colour_resolve")),
                          decided_pairs=decided, skipped_by_gamut_cells=skipped,
                          in_gamut_without_high_channel=no_high),
+    }
+
+
+def bench_rays(cv, W, torch, steps):
+    """Adaptive per-ray search of the eight frames' distinct colours on the
+    500 x 360 grid: every ray's largest surviving radius, found from the
+    outermost radius inward (blocks of 64 radii closed by interval bounds where
+    they can be), against the exhaustive resolve of the same colours with its
+    per-ray maxima (which also keeps the best pair of every pattern)."""
+    import numpy as np
+    f = W.frames(range(8))
+    g = W.GRID_FRAMES
+    grid, rule = cv.Grid(*g.astuple()), cv.Rule(*W.DEFAULT_RULE)
+    px = torch.from_numpy(f).cuda()
+    del f
+    ctx = cv.context(0)
+    ex = cv.frames_resolve(px, grid, rule, summaries=False, rays=True, frames=False, ctx=ctx)
+    torch.cuda.synchronize()
+    n = int(ex.ncolours.item())
+    cols = ex.colours[:n]
+    out = cv.ray_search(cols, grid, rule, ctx=ctx)
+    torch.cuda.synchronize()
+    # the adaptive maxima equal the exhaustive ones
+    same = bool(torch.equal(out.rays, ex.rays[:n]))
+    ev, tested, closed = (int(v) for v in out.counts.cpu().numpy())
+    ev_start, ev_stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        ev_start.record()
+        for _ in range(k):
+            fn()
+        ev_stop.record()
+        torch.cuda.synchronize()
+        return ev_start.elapsed_time(ev_stop) / k
+
+    ms = timed(lambda: cv.ray_search(cols, grid, rule, out=out, ctx=ctx), steps)
+    ms_ex = timed(lambda: cv.frames_resolve(px, grid, rule, summaries=False, rays=True, frames=False, out=ex,
+                                            ctx=ctx), steps)
+    # the kernel's own duration (HIP events on its stream)
+    ctx.set_timing(True)
+    ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
+    cv.ray_search(cols, grid, rule, out=out, ctx=ctx)
+    torch.cuda.synchronize()
+    t_k, _ = ctx.kernel_time(cv.CV_TIME_EVAL, reset=True)
+    ctx.set_timing(False)
+    total = n * g.per_colour
+    return {
+        "workload": "adaptive per-ray maxima of the 8 synthetic 3840x2160 frames' distinct colours; "
+                    "r = 0.1..50 step 0.1 (500) x theta = 0..359 deg step 1 (360)",
+        "distinct_colours": n, "ms_per_call": ms, "calls": steps,
+        "colours_per_s": n / (ms * 1e-3), "pairs_decided_per_s": total / (ms * 1e-3),
+        "evaluated_pairs_per_s": ev / (ms * 1e-3),
+        "evaluated_fraction": ev / total, "row_blocks_tested": tested, "row_blocks_closed": closed,
+        "rays_with_survivor": int((out.rays != 0).sum()),
+        "equal_to_exhaustive": same,
+        "exhaustive_ms_per_call": ms_ex, "speedup_vs_exhaustive": ms_ex / ms,
+        "roofline": dict(_alu_roofline("k_ray_search", t_k, ev, ev, 0, measured_counters("ray_search")),
+                         kernel_ms=t_k),
     }
 
 
@@ -223,6 +328,53 @@ def bench_surrogate(cv, W, torch, epochs, steps):
     exact_found = int((summ["count"] > 0).sum())
     found = int((st != cv.CV_RESOLVED_NONE).sum())
     mlp_ms = ph["mlp"]
+
+    # the honest gain test on the same distinct colours: the same verify and
+    # fallback fed by proposers that need no network, and the exact one-pair
+    # resolve from the outermost radius inward (adaptive per-ray search)
+    cols = sr.colours[:n]
+    has = summ["count"] > 0
+    best_r = (summ["best_i"][has].astype(np.float64) + 1.0) * g.dr
+
+    def judge(res):
+        p = cv.as_records(res.pairs, cv.PATTERN_PAIR_DTYPE)
+        s_ = res.status.cpu().numpy()
+        by_prop = s_ == cv.CV_RESOLVED_SURROGATE
+        got = np.where(p["flags"] & 1, (p["i"].astype(np.float64) + 1.0) * g.dr, 0.0)
+        gp = (summ["best_i"][by_prop].astype(np.float64) - p["i"][by_prop]) * g.dr
+        return {"resolved_by_proposals": int(by_prop.sum()), "fallback": int(res.nfallback.item()),
+                "fallback_frac": int(res.nfallback.item()) / n,
+                "radius_recovered": float(got[has].sum() / best_r.sum()),
+                "radius_gap_mean": float(gp.mean()) if len(gp) else None}
+
+    comps = {}
+    out_m = cv.surrogate_infer(cols, m, grid, rule, tau=0.0, kbins=3, ctx=ctx)
+    comps["network"] = dict(ms_per_call=timed(lambda: cv.surrogate_infer(cols, m, grid, rule, tau=0.0, kbins=3,
+                                                                          out=out_m, ctx=ctx), steps),
+                            **judge(out_m))
+    prior = S.constant_prior(table, tr_ids, gc.dr).expand(n, 37).contiguous()
+    out_p = cv.surrogate_infer(cols, None, grid, rule, tau=0.0, kbins=3, pred_in=prior, ctx=ctx)
+    comps["constant_prior"] = dict(ms_per_call=timed(lambda: cv.surrogate_infer(
+        cols, None, grid, rule, tau=0.0, kbins=3, pred_in=prior, out=out_p, ctx=ctx), steps), **judge(out_p))
+
+    def lookup():
+        return cv.surrogate_infer(cols, None, grid, rule, tau=0.0, kbins=3,
+                                  pred_in=S.table_pred(table, cols, gc.dr), out=out_t, ctx=ctx)
+
+    out_t = None
+    out_t = lookup()
+    comps["table_lookup"] = dict(ms_per_call=timed(lookup, steps), **judge(out_t),
+                                 note="the colour's own row of the 671 MB whole-cube table, held-out colours "
+                                      "included (the network holds 0.57 MB)")
+    rs = cv.ray_search(cols, grid, rule, best=True, ctx=ctx)
+    ms_rays = timed(lambda: cv.ray_search(cols, grid, rule, best=True, out=rs, ctx=ctx), steps)
+    key = rs.best[:n].cpu().numpy().view(np.uint32).astype(np.int64)
+    want = np.where(summ["best_i"] == 0xFFFF, 0,
+                    (summ["best_i"].astype(np.int64) << 16) | (0xFFFF - summ["best_j"].astype(np.int64)))
+    comps["exact_adaptive"] = {"ms_per_call": ms_rays, "equal_to_exhaustive_best": bool(np.array_equal(key, want)),
+                               "evaluated_fraction": int(rs.counts[0].item()) / (n * g.per_colour)}
+    for v in comps.values():
+        v["colours_per_s"] = n / (v["ms_per_call"] * 1e-3)
     return {
         "workload": "surrogate 3-256-256-256-37 (first hidden layer sin(30 z), then ReLU) trained with "
                     "Adam (batch 8192, lr 4e-3 cosine to 2e-5) on the 2^24-colour table (r step 0.25, "
@@ -234,7 +386,7 @@ def bench_surrogate(cv, W, torch, epochs, steps):
                   "tflops": rows * MLP_TRAIN_FLOPS / t_train / 1e12,
                   "mfma_frac": rows * MLP_TRAIN_FLOPS / t_train / MFMA_BF16_PEAK,
                   "loss_first": log[0][1], "loss_last": log[-1][1]},
-        "heldout": ev,
+        "heldout": dict(ev, radius_mae_target=0.5, meets_target=bool(ev["radius_mae"] <= 0.5)),
         "distinct_colours": n,
         "exact": {"ms_per_call": ms_exact, "colours_per_s": n / (ms_exact * 1e-3),
                   "colours_with_pair": exact_found},
@@ -247,6 +399,9 @@ def bench_surrogate(cv, W, torch, epochs, steps):
                       "phases_ms": ph,
                       "mlp_tflops": n * MLP_FWD_FLOPS / (mlp_ms * 1e-3) / 1e12 if mlp_ms > 0 else None},
         "speedup": ms_exact / ms_sur,
+        "one_pair_resolve_of_the_distinct_colours": dict(
+            comps, speedup_network_vs_exact_adaptive=comps["exact_adaptive"]["ms_per_call"] /
+            comps["network"]["ms_per_call"]),
     }
 
 
@@ -326,16 +481,39 @@ def bench_cube(cv, W, torch, steps):
         "colours_per_s": (1 << 24) / (ms * 1e-3), "pairs_per_s": (1 << 24) * g.per_colour / (ms * 1e-3),
         "ms_per_call": ms, "calls": steps,
         "feasible_colours": int((tab[:, :4].contiguous().view(torch.int32) > 0).sum()),
+        "evaluated_pairs_per_s": evals / (ms * 1e-3),
         "roofline_whole_call": dict(_alu_roofline("k_pair_reduce<TABLE> (whole call)", ms, evals, ng // 2 - no_high,
-                                                  -(-decided // 64)),
+                                                  -(-decided // 64), measured_counters("cube_table")),
                                     decided_pairs=decided, skipped_by_gamut_cells=skipped,
                                     in_gamut_without_high_channel=no_high),
     }
 
 
-def cpu_baseline(target_s: float):
+def _cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(target_s: float, gpu_records=None):
     """The FP64 oracle on a bounded sample of the same workload (the first
-    rows of radii of all nine colours), all host threads."""
+    rows of radii of all nine colours), all host threads; with the GPU's
+    survivor records of the timed call, the oracle's survivor list of the
+    whole grid as well, and the boundary and mismatch counts of the two."""
     import numpy as np
 
     import oracle
@@ -359,12 +537,35 @@ def cpu_baseline(target_s: float):
     t0 = time.perf_counter()
     oracle.reduce(cols, (g.dr, rows1, g.dtheta_deg, g.ntheta), W.DEFAULT_RULE, nthreads=1)
     dt1 = time.perf_counter() - t0
-    return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"nine colours x first {rows} of {g.nr} radii x {g.ntheta} angles "
-                      f"({pairs} pairs, {dt:.1f} s)",
-            "seconds": dt,
-            "single_core": {"value": len(cols) * rows1 * g.ntheta / dt1, "unit": "pairs/s", "cores": 1,
-                            "sample": f"nine colours x first {rows1} radii ({dt1:.2f} s)"}}
+    res = {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+           "sample": f"nine colours x first {rows} of {g.nr} radii x {g.ntheta} angles "
+                     f"({pairs} pairs, {dt:.1f} s)",
+           "seconds": dt, "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count(),
+           "single_core": {"value": len(cols) * rows1 * g.ntheta / dt1, "unit": "pairs/s", "cores": 1,
+                           "sample": f"nine colours x first {rows1} radii ({dt1:.2f} s)"}}
+    if gpu_records is not None:
+        t0 = time.perf_counter()
+        recs, _, nb = oracle.search(cols, g.astuple(), W.DEFAULT_RULE, nthreads=threads)
+        dts = time.perf_counter() - t0
+        kg = (gpu_records["colour"].astype(np.int64) * g.nr + gpu_records["i"]) * g.ntheta + gpu_records["j"]
+        ko = (recs["colour"].astype(np.int64) * g.nr + recs["i"]) * g.ntheta + recs["j"]
+        only_o = ~np.isin(ko, kg)
+        only_g = ~np.isin(kg, ko)
+        band_o = (recs["flags"] & 1).astype(bool)
+        # GPU-only survivors: band candidates by the oracle's classification
+        if only_g.any():
+            e = gpu_records[only_g]
+            ev = oracle.eval_list(cols, np.stack([e["colour"], e["i"], e["j"]], 1), g.astuple(),
+                                  W.DEFAULT_RULE, nthreads=threads)
+            g_band = int((ev["boundary"] & 1).sum())
+        else:
+            g_band = 0
+        res["full_grid_search"] = {"seconds": dts, "pairs_per_s": len(cols) * g.per_colour / dts,
+                                   "survivors": int(len(recs))}
+        res["parity"] = {"boundary_count": int(nb), "mismatch_count": int(only_o.sum() + only_g.sum()),
+                         "mismatch_outside_band": int((only_o & ~band_o).sum()) + int(only_g.sum()) - g_band,
+                         "gpu_survivors": int(len(gpu_records)), "oracle_survivors": int(len(recs))}
+    return res
 
 
 def main():
@@ -422,6 +623,16 @@ def main():
     ms = start.elapsed_time(stop)
     if int(off[-1].item()) != first.total:
         raise RuntimeError("survivor total changed between calls")
+    timed_records = cv.as_records(out[:first.total], cv.PAIR_DTYPE)
+    if not np.array_equal(timed_records, cv.as_records(first.pairs, cv.PAIR_DTYPE)):
+        raise RuntimeError("the timed call's survivors differ from the first call's")
+    if not torch.equal(off, first.offsets) or not torch.equal(summ_buf, first.summaries):
+        # the timed calls skip n_gamut; every other summary field must agree
+        a = cv.as_records(summ_buf, cv.SUMMARY_DTYPE)
+        b = cv.as_records(first.summaries, cv.SUMMARY_DTYPE)
+        if not torch.equal(off, first.offsets) or any(
+                not np.array_equal(a[k], b[k]) for k in b.dtype.names if k != "n_gamut"):
+            raise RuntimeError("the timed call's offsets or summaries differ from the first call's")
     # calls that each read the total back (a host round trip per call)
     n_sync = max(3, min(args.steps, 20))
     start.record()
@@ -472,15 +683,15 @@ def main():
     # in-gamut pairs of steps proven to hold no high channel are not encoded;
     # every step of 64 decided candidates is one cell test
     cell_tests = -(-decided // 64)
-    flops = FLOPS_GEOM * evals + FLOPS_CODE * (gamut_evals - no_high) + FLOPS_CELL * cell_tests
     k_eval = t_eval / max(n_eval, 1)
     k_write = t_write / max(n_write, 1)
-    achieved = flops / (k_eval * 1e-3)
+    roof = _alu_roofline("k_pair_reduce (evaluation / count pass)", k_eval, evals, gamut_evals - no_high,
+                         cell_tests, measured_counters("count_pass"))
 
     res = {
         "metric": "candidate pairs evaluated/s + target colors resolved/s (exact vs surrogate)",
         "value": value,
-        "unit": "pairs/s",
+        "unit": "pairs decided/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -491,37 +702,26 @@ def main():
         "dtype": "f64+f32",
         "data": "synthetic",
         "config": {
-            "workload": "nine Table 1 colours; r = 0.01..100 step 0.01 (10,000) x theta = "
-                        "0..359.9 deg step 0.1 (3,600); rule V_th=50, R_novib=0.5, any pattern; "
-                        "survivor list with CSR offsets and per-colour summaries (count, best pair, "
-                        "per-pattern counts; n_gamut not asked for)",
+            "workload": "nine Table 1 colours (the configuration the metric is quoted on; the frames, "
+                        "cube and surrogate configurations are reported beside it); r = 0.01..100 step "
+                        "0.01 (10,000) x theta = 0..359.9 deg step 0.1 (3,600); rule V_th=50, "
+                        "R_novib=0.5, any pattern; survivor list with CSR offsets and per-colour "
+                        "summaries (count, best pair, per-pattern counts; n_gamut not asked for); value = "
+                        "grid pairs decided per second (evaluated, or settled exactly by half-turn "
+                        "symmetry and interval proofs), evaluated_pairs_per_s beside it",
             "colours": int(len(W.PAPER_COLOUR_ARRAY)),
             "pairs_per_step": pairs_per_step,
             "survivors_per_step": int(total),
         },
         "colours_per_s_exact": len(W.PAPER_COLOUR_ARRAY) / (ms_per_step * 1e-3),
+        "decided_pairs_per_s": value,
+        "evaluated_pairs_per_s": evals / (ms_per_step * 1e-3),
         "wall_s": wall,
         "ms_per_step_graph": ms_graph,
         "ms_per_call_with_readback": ms_sync,
         "phases_ms": {"eval": k_eval, "write": k_write, "call": t_call / max(n_call, 1)},
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_pair_reduce (evaluation / count pass)",
-            "achieved": achieved / 1e12,
-            "peak": VALU_FMA_PEAK / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / VALU_FMA_PEAK,
-            "traffic": measured_counter("traffic_bytes"),
-            "valu_issue_profiled": measured_counter("valu_issue"),
-            "kernel_ms": k_eval,
-            "flops_per_launch": flops,
-            "decided_pairs": decided,
-            "evaluated_pairs": evals,
-            "skipped_by_gamut_cells": skipped,
-            "in_gamut_evaluations": gamut_evals,
-            "in_gamut_not_encoded": no_high,
-            "cell_tests": cell_tests,
-        },
+        "roofline": dict(roof, decided_pairs=decided, skipped_by_gamut_cells=skipped,
+                         in_gamut_not_encoded=no_high, cell_tests=cell_tests),
         "write_pass": {"kernel": "k_pair_pass (write)", "ms": k_write,
                        "GBps": 16.0 * total / (k_write * 1e-3) / 1e9 if k_write > 0 else None,
                        "hbm_frac": 16.0 * total / (k_write * 1e-3) / HBM_PEAK if k_write > 0 else None},
@@ -530,12 +730,17 @@ def main():
         res["table2"] = bench_table2(cv, W, torch, 5)
     if args.only in ("all", "frames"):
         res["frames_exact"] = bench_frames(cv, W, torch, 3)
+    if args.only in ("all", "rays"):
+        res["rays_adaptive"] = bench_rays(cv, W, torch, 3)
     if args.only in ("all", "cube"):
         res["cube_table"] = bench_cube(cv, W, torch, 2)
     if args.only in ("all", "surrogate"):
         res["surrogate_frames"] = bench_surrogate(cv, W, torch, args.epochs, 3)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(args.cpu_seconds, timed_records)
+        par = res["cpu_baseline"].get("parity", {})
+        res["boundary_count"] = par.get("boundary_count")
+        res["mismatch_count"] = par.get("mismatch_count")
     print(json.dumps(res))
 
 

@@ -267,6 +267,32 @@ int cv_pair_reduce_csr(cv_context* ctx, const cv_pair* recs, const int64_t* offs
                        cv_color_summary* summ, void* stream);
 
 /*
+ * Adaptive per-ray search (the search space of Section 1 cut down without
+ * changing what is found): for every colour and every ray j < ntheta, the
+ * largest radius index i at which the pair of Section 2 passes Section 3's
+ * predicate under `rule` -- the maximum of the ray's survivors, as
+ * CV_PER_RAY finds it.  Each ray is taken from its outermost radius inward in
+ * blocks of 64 radii: an interval bound first closes the blocks in which one
+ * colour is out of gamut throughout or no channel can change by more than
+ * v_th; the first block it cannot close is evaluated candidate by candidate,
+ * and so on inward until a survivor is found.  The result equals the
+ * exhaustive search's bit for bit (same arithmetic on every evaluated
+ * candidate).  Under CV_RULE_CLIP no block is closed.
+ * rgb: uint8 [n][3] device.  rays: uint16 [n][ntheta] device: i + 1 of the
+ * ray's largest survivor, 0 for a ray without one.  recs: nullable cv_pair
+ * [n][ntheta] device: that survivor's record (flags bit 2 set), all zero
+ * except the colour index for a ray without one.  best: nullable uint32 [n]
+ * device: the colour's maximum-amplitude pair as a key i << 16 | (65535 - j)
+ * (largest i, then smallest j; 0 = no survivor) -- the exact one-pair resolve
+ * of a colour, found from the outermost radius inward.  counts: nullable
+ * uint64 [3] device, overwritten: candidates evaluated, row blocks tested, row
+ * blocks closed by the bound.  Asynchronous.  Errors: CV_EINVAL, CV_EHIP,
+ * CV_ENOMEM.
+ */
+int cv_ray_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid, const cv_rule* rule,
+                  uint16_t* rays, cv_pair* recs, uint32_t* best, uint64_t* counts, void* stream);
+
+/*
  * Several rules in one pass (Table 1's twelve settings give Table 2): for
  * each colour and rule, the survivors of each pattern.  rules: host array of
  * nrules (1..16) cv_rule with the same flags (one gamut reading); together
@@ -442,6 +468,13 @@ int cv_mlp_get_params(const cv_mlp* m, float* params, float* grads, void* stream
  * rows go through in chunks of 2^20 (B <= 2^30). */
 int cv_mlp_forward(cv_mlp* m, const void* x, int64_t B, float* out, uint32_t flags, void* stream);
 
+/* The BF16 activations of hidden layer `layer` (1 .. nlayers - 1) kept by the
+ * last forward pass with CV_MLP_KEEP, widened to FP32: out [B][dims[layer]]
+ * device, for the first B rows of that batch (CV_ESTATE without such a pass).
+ * These are the values the next layer's matrix product and the backward pass
+ * read.  Asynchronous.  Errors: CV_EINVAL, CV_ESTATE, CV_EHIP. */
+int cv_mlp_hidden(const cv_mlp* m, int32_t layer, float* out, int64_t B, void* stream);
+
 /* Training loss of B rows and its gradient with respect to the outputs.
  * out [B][D] (D = dims[nlayers]); t_r [B][D-1] radius targets (a bin with
  * t_r <= 0 carries no radius loss); t_f [B] feasibility targets in {0, 1}.
@@ -495,6 +528,23 @@ int cv_permute_ids(cv_context* ctx, const int32_t* in, int64_t n, uint64_t key, 
 int cv_mlp_save(const cv_mlp* m, const char* path);
 int cv_mlp_load(cv_mlp* m, const char* path);
 
+/* Training checkpoint (host path), to stop training and resume it later with
+ * results identical to an uninterrupted run: magic "CVCKP01", int32 nlayers,
+ * int32 dims[nlayers+1], int64 count, float omega0, int64 step (training
+ * steps done, the next Adam step is step + 1), uint64 key (the caller's
+ * training-order key), float params[count], float adam_m[count], float
+ * adam_v[count], then uint64 FNV-1a-64 of every preceding byte;
+ * little-endian.  Loading checks the magic, the field sizes against the file
+ * length, the hash (a corrupt or truncated file is CV_EINVAL) and the shape
+ * (another network's checkpoint is CV_EINVAL), then restores parameters,
+ * moments and omega0, and returns step and key (either may be NULL).  Save
+ * and load synchronise the device.  cv_mlp_checkpoint_info reads and checks a
+ * file without any device: nlayers, dims (int32 [nlayers + 1], room for 9),
+ * step, key (each nullable). */
+int cv_mlp_save_checkpoint(const cv_mlp* m, const char* path, int64_t step, uint64_t key);
+int cv_mlp_load_checkpoint(cv_mlp* m, const char* path, int64_t* step, uint64_t* key);
+int cv_mlp_checkpoint_info(const char* path, int32_t* nlayers, int32_t* dims, int64_t* step, uint64_t* key);
+
 /* ---- Surrogate resolve -------------------------------------------------
  *
  * One verified pair per target colour, proposed by a 3 -> ... -> 37 network
@@ -524,6 +574,12 @@ int cv_mlp_load(cv_mlp* m, const char* path);
  * search (its maximum-amplitude pair), unless CV_NO_FALLBACK is set.
  */
 #define CV_NO_FALLBACK 0x4u
+/* cv_surrogate_infer only: `pred` is an input -- proposals from the caller in
+ * the network's output layout (36 bin radii / 50, then a feasibility logit),
+ * e.g. a lookup in a table or a constant prior -- and no network runs (mlp
+ * may be NULL).  Everything after the network is the same: proposals are
+ * verified by the exact predicate and the rest falls back. */
+#define CV_PRED_GIVEN 0x20u
 
 /* cv_pattern_pair.flags of a resolved pair */
 #define CV_PAIR_FOUND 0x1u      /* the pair exists                          */
@@ -535,14 +591,18 @@ int cv_mlp_load(cv_mlp* m, const char* path);
 #define CV_RESOLVED_EXACT 1      /* exact fallback found a pair             */
 #define CV_RESOLVED_NONE 2       /* no pair (infeasible, or no fallback)    */
 
-/* A list of n colours (uint8 [n][3]).  pairs: cv_pattern_pair [n]; status:
- * uint8 [n]; pred: float [n][37] (nullable) receives the network outputs;
- * *nfallback (DEVICE int64, nullable): colours sent to the exact search.
- * Asynchronous.  Errors: CV_EINVAL, CV_EHIP, CV_ENOMEM. */
+/* A list of n colours (uint8 [n][3], the same colour layout as every other
+ * call).  pairs: cv_pattern_pair [n]; status: uint8 [n]; pred: float [n][37]
+ * (nullable) receives the network outputs (the 36 bin radii / 50, then the
+ * feasibility logit); fallback (uint32 [n], nullable) receives the indices of
+ * the colours that need the exact search (low logit, no verified proposal, or
+ * low confidence), in increasing order -- sent to it unless CV_NO_FALLBACK is
+ * set; *nfallback (DEVICE int64, nullable) their number.  All device arrays.  Asynchronous.
+ * Errors: CV_EINVAL, CV_EHIP, CV_ENOMEM. */
 int cv_surrogate_infer(cv_context* ctx, cv_mlp* mlp, const uint8_t* rgb, int64_t n,
                        const cv_grid* grid, const cv_rule* rule, float tau, int32_t kbins,
-                       float* pred, cv_pattern_pair* pairs, uint8_t* status, int64_t* nfallback,
-                       uint32_t flags, void* stream);
+                       float* pred, cv_pattern_pair* pairs, uint8_t* status, uint32_t* fallback,
+                       int64_t* nfallback, uint32_t flags, void* stream);
 
 /* Batched frames through the surrogate: the de-duplication of
  * cv_frames_resolve (colours, *ncolours, pixel_index as there), one

@@ -298,6 +298,7 @@ def _mlp_bind(L):
     L.orc_mlp_loss.argtypes = [P, P, P, C.c_int64, C.c_int32, C.c_double, P]
     L.orc_mlp_loss.restype = C.c_double
     L.orc_mlp_backward.argtypes = [P, C.c_int32, P, P, C.c_int64, P, P, P, P, C.c_double]
+    L.orc_linear_input_grad.argtypes = [C.c_int32, C.c_int32, P, C.c_int64, P, P]
 
 
 def _flat(dims, Ws, bs):
@@ -355,6 +356,17 @@ def distinct_colours(frames_u8: np.ndarray) -> np.ndarray:
     f = np.asarray(frames_u8).reshape(-1, 3).astype(np.uint32)
     ids = (f[:, 0] << 16) | (f[:, 1] << 8) | f[:, 2]
     return np.unique(ids)
+
+
+def linear_input_grad(W, gout) -> np.ndarray:
+    """Gradient of sum(gout * (x W^T + b)) with respect to x: gout W, [B, d_in]
+    for W [d_out, d_in] and gout [B, d_out]."""
+    W = np.ascontiguousarray(np.asarray(W, dtype=np.float64))
+    gout = np.ascontiguousarray(np.asarray(gout, dtype=np.float64))
+    dout, din = W.shape
+    gin = np.zeros((gout.shape[0], din))
+    lib().orc_linear_input_grad(int(din), int(dout), _ptr(W), gout.shape[0], _ptr(gout), _ptr(gin))
+    return gin
 
 
 def adam_step(p, g, m, v, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,

@@ -157,3 +157,16 @@ void orc_mlp_backward(const int32_t* dims, int32_t nl, const double* W, const do
     }
     free(h); free(out); free(delta); free(prev); free(offW); free(offb); free(offh);
 }
+
+/* Gradient with respect to the input of one linear layer y = W x + b:
+ * gin[s][k] = sum_o gout[s][o] W[o][k] (W row-major [dout][din]); the chain
+ * rule's step from a layer's output gradient to its input. */
+void orc_linear_input_grad(int32_t din, int32_t dout, const double* W, int64_t B, const double* gout,
+                           double* gin) {
+    for (int64_t s = 0; s < B; ++s)
+        for (int32_t k = 0; k < din; ++k) {
+            double acc = 0.0;
+            for (int32_t o = 0; o < dout; ++o) acc += gout[s * dout + o] * W[(int64_t)o * din + k];
+            gin[s * din + k] = acc;
+        }
+}

@@ -75,8 +75,10 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_context_set_resolve_variant", "cv_context_resolve_variant", "cv_pair_reduce_rules",
            "cv_pair_reduce_csr", "cv_context_set_gamut_cells", "cv_context_skipped",
            "cv_mlp_set_first_sine", "cv_mlp_first_sine", "cv_permute_ids", "cv_context_no_high",
-           "cv_pair_reduce_noalloc")
+           "cv_pair_reduce_noalloc", "cv_ray_search", "cv_mlp_hidden",
+           "cv_mlp_save_checkpoint", "cv_mlp_load_checkpoint", "cv_mlp_checkpoint_info")
 CV_NO_FALLBACK = 0x4
+CV_PRED_GIVEN = 0x20
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
 CV_RESOLVED_SURROGATE, CV_RESOLVED_EXACT, CV_RESOLVED_NONE = 0, 1, 2
 CV_TIME_MLP, CV_TIME_VERIFY = 3, 4
@@ -103,6 +105,12 @@ def lib() -> C.CDLL:
         L.cv_pair_search.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, I64,
                                      P, P, C.POINTER(I64), C.c_uint32, P]
         L.cv_pair_reduce.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P]
+        L.cv_mlp_save_checkpoint.argtypes = [P, C.c_char_p, I64, C.c_uint64]
+        L.cv_mlp_load_checkpoint.argtypes = [P, C.c_char_p, C.POINTER(I64), C.POINTER(C.c_uint64)]
+        L.cv_mlp_checkpoint_info.argtypes = [C.c_char_p, C.POINTER(C.c_int32), P, C.POINTER(I64),
+                                             C.POINTER(C.c_uint64)]
+        L.cv_mlp_hidden.argtypes = [P, C.c_int32, P, I64, P]
+        L.cv_ray_search.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P, P, P]
         L.cv_pair_reduce_noalloc.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P]
         L.cv_frames_resolve.argtypes = [P, P, I64, P, C.POINTER(cv_grid), C.POINTER(cv_rule), P,
                                         I64, P, P, P, P, P, P, P, P, C.c_uint32, P]
@@ -127,7 +135,7 @@ def lib() -> C.CDLL:
         L.cv_mlp_save.argtypes = [P, C.c_char_p]
         L.cv_mlp_load.argtypes = [P, C.c_char_p]
         L.cv_surrogate_infer.argtypes = [P, P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule),
-                                         C.c_float, C.c_int32, P, P, P, P, C.c_uint32, P]
+                                         C.c_float, C.c_int32, P, P, P, P, P, C.c_uint32, P]
         L.cv_frames_surrogate.argtypes = [P, P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule),
                                           C.c_float, C.c_int32, P, I64, P, P, P, P, P, P, P, P,
                                           C.c_uint32, P]
@@ -414,6 +422,38 @@ def pair_reduce_noalloc(colors: torch.Tensor, grid: Grid, rule: Rule, summ: torc
     return summ, table
 
 
+@dataclass
+class RayResult:
+    rays: torch.Tensor          # int16 bits of uint16 [n, ntheta]: largest valid i + 1, 0 = none
+    records: torch.Tensor | None  # uint8 [n, ntheta, 16] (PAIR_DTYPE) or None
+    counts: torch.Tensor        # int64 bits of uint64 [3]: evaluated, blocks tested, blocks closed
+    best: torch.Tensor | None = None  # int32 bits of uint32 [n]: best key i << 16 | 0xFFFF - j, 0 = none
+
+
+def ray_search(colors: torch.Tensor, grid: Grid, rule: Rule, records: bool = False, best: bool = False,
+               out: RayResult | None = None, ctx: Context | None = None) -> RayResult:
+    """Adaptive per-ray maxima (cv_ray_search): each ray's largest surviving
+    radius index (+1), found from the outermost radius inward with blocks of
+    64 radii closed by an interval bound where it can."""
+    colors = _colours(colors)
+    ctx = ctx or context(colors.device.index)
+    n = colors.shape[0]
+    dev = colors.device
+    if out is None:
+        out = RayResult(torch.empty((n, grid.ntheta), dtype=torch.int16, device=dev),
+                        torch.empty((n, grid.ntheta, 16), dtype=torch.uint8, device=dev) if records else None,
+                        torch.zeros(3, dtype=torch.int64, device=dev),
+                        torch.empty(max(n, 1), dtype=torch.int32, device=dev) if best else None)
+    _require(out.rays, "out.rays", torch.int16, n * grid.ntheta, dev)
+    _require(out.records, "out.records", torch.uint8, n * grid.ntheta * 16, dev)
+    _require(out.counts, "out.counts", torch.int64, 3, dev)
+    _require(out.best, "out.best", torch.int32, n, dev)
+    g, r = grid.c(), rule.c()
+    _check(lib().cv_ray_search(ctx.handle, _dptr(colors), n, C.byref(g), C.byref(r), _dptr(out.rays),
+                               _dptr(out.records), _dptr(out.best), _dptr(out.counts), _stream()))
+    return out
+
+
 def pair_reduce_csr(records: torch.Tensor, offsets: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:
     """Per-colour summaries (uint8 [n, 48]) of a survivor list (uint8 [total, 16])
     with its CSR offsets (int64 [n + 1]); n_gamut is 0."""
@@ -616,6 +656,13 @@ class MLP:
                                  _stream()))
         return loss, gout
 
+    def hidden(self, layer: int, B: int) -> torch.Tensor:
+        """FP32 copy of hidden layer `layer`'s BF16 activations [B, d_layer]
+        from the last kept forward pass."""
+        out = torch.empty((B, self.dims[layer]), dtype=torch.float32, device=self.device)
+        _check(lib().cv_mlp_hidden(self.handle, int(layer), _dptr(out), int(B), _stream()))
+        return out
+
     def backward(self, x, gout):
         _check(lib().cv_mlp_backward(self.handle, _dptr(x.contiguous()), _dptr(gout.contiguous()),
                                      x.shape[0], _stream()))
@@ -657,6 +704,16 @@ class MLP:
     def load(self, path: str):
         _check(lib().cv_mlp_load(self.handle, os.fsencode(path)))
 
+    def save_checkpoint(self, path: str, step: int, key: int = 0):
+        """Parameters, Adam moments, the step count and a training-order key."""
+        _check(lib().cv_mlp_save_checkpoint(self.handle, os.fsencode(path), int(step), int(key) & (2 ** 64 - 1)))
+
+    def load_checkpoint(self, path: str):
+        """Restore a checkpoint of this network's shape: returns (step, key)."""
+        st, k = C.c_int64(0), C.c_uint64(0)
+        _check(lib().cv_mlp_load_checkpoint(self.handle, os.fsencode(path), C.byref(st), C.byref(k)))
+        return st.value, k.value
+
     def close(self):
         if getattr(self, "handle", None):
             lib().cv_mlp_destroy(self.handle)
@@ -667,6 +724,16 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+def checkpoint_info(path: str):
+    """Read and check a training checkpoint without a GPU: (dims, step, key);
+    raises CvError (CV_EINVAL) for a corrupt, truncated or foreign file."""
+    nl = C.c_int32(0)
+    dims = (C.c_int32 * 9)()
+    st, k = C.c_int64(0), C.c_uint64(0)
+    _check(lib().cv_mlp_checkpoint_info(os.fsencode(path), C.byref(nl), dims, C.byref(st), C.byref(k)))
+    return tuple(dims[: nl.value + 1]), st.value, k.value
 
 
 def permute_ids(ids: torch.Tensor, key: int, out: torch.Tensor | None = None,
@@ -702,25 +769,44 @@ class SurrogateResult:
     status: torch.Tensor       # uint8 [n]: CV_RESOLVED_*
     nfallback: torch.Tensor    # int64 [1] on the GPU
     pred: torch.Tensor | None  # float32 [n, 37]
+    fallback: torch.Tensor | None = None  # int32 bits of uint32 [n]: the first nfallback entries
 
 
-def surrogate_infer(colors: torch.Tensor, mlp: MLP, grid: Grid, rule: Rule, tau: float = 0.0,
+def surrogate_infer(colors: torch.Tensor, mlp: MLP | None, grid: Grid, rule: Rule, tau: float = 0.0,
                     kbins: int = 3, fallback: bool = True, want_pred: bool = False,
-                    ctx: Context | None = None) -> SurrogateResult:
-    """One verified pair per colour (uint8 [n, 3] on the GPU)."""
+                    want_list: bool = False, pred_in: torch.Tensor | None = None,
+                    out: SurrogateResult | None = None, ctx: Context | None = None) -> SurrogateResult:
+    """One verified pair per colour (uint8 [n, 3] on the GPU).  pred_in:
+    proposals in the network's output layout (float32 [n, 37]) used instead of
+    running the network (CV_PRED_GIVEN; mlp may then be None).  out: a
+    previous result of the same n whose buffers are reused."""
     colors = _colours(colors)
-    ctx = ctx or mlp.ctx
+    if mlp is None and pred_in is None:
+        raise ValueError("a network or pred_in is needed")
+    ctx = ctx or (mlp.ctx if mlp is not None else context(colors.device.index))
     n = colors.shape[0]
     dev = colors.device
-    pairs = torch.empty((n, 12), dtype=torch.uint8, device=dev)
-    status = torch.empty(n, dtype=torch.uint8, device=dev)
-    nfb = torch.zeros(1, dtype=torch.int64, device=dev)
-    pred = torch.empty((n, 37), dtype=torch.float32, device=dev) if want_pred else None
+    if pred_in is not None:
+        _require(pred_in, "pred_in", torch.float32, 37 * n, dev)
+    if out is None:
+        out = SurrogateResult(torch.empty((n, 12), dtype=torch.uint8, device=dev),
+                              torch.empty(n, dtype=torch.uint8, device=dev),
+                              torch.zeros(1, dtype=torch.int64, device=dev),
+                              torch.empty((n, 37), dtype=torch.float32, device=dev) if want_pred else None,
+                              torch.empty(max(n, 1), dtype=torch.int32, device=dev) if want_list else None)
+    _require(out.pairs, "out.pairs", torch.uint8, 12 * n, dev)
+    _require(out.status, "out.status", torch.uint8, n, dev)
+    _require(out.nfallback, "out.nfallback", torch.int64, 1, dev)
+    _require(out.pred, "out.pred", torch.float32, 37 * n, dev)
+    _require(out.fallback, "out.fallback", torch.int32, n, dev)
+    pred = pred_in if pred_in is not None else out.pred
+    flags = (0 if fallback else CV_NO_FALLBACK) | (CV_PRED_GIVEN if pred_in is not None else 0)
     g, r = grid.c(), rule.c()
-    _check(lib().cv_surrogate_infer(ctx.handle, mlp.handle, _dptr(colors), n, C.byref(g), C.byref(r),
-                                    float(tau), int(kbins), _dptr(pred), _dptr(pairs), _dptr(status),
-                                    _dptr(nfb), 0 if fallback else CV_NO_FALLBACK, _stream()))
-    return SurrogateResult(pairs, status, nfb, pred)
+    _check(lib().cv_surrogate_infer(ctx.handle, mlp.handle if mlp is not None else None, _dptr(colors), n,
+                                    C.byref(g), C.byref(r), float(tau), int(kbins), _dptr(pred),
+                                    _dptr(out.pairs), _dptr(out.status), _dptr(out.fallback),
+                                    _dptr(out.nfallback), flags, _stream()))
+    return out
 
 
 @dataclass

@@ -313,6 +313,22 @@ int cv_pair_reduce_noalloc(cv_context* ctx, const uint8_t* rgb, int64_t n, const
     CV_GUARD_END
 }
 
+int cv_ray_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid, const cv_rule* rule,
+                  uint16_t* rays, cv_pair* recs, uint32_t* best, uint64_t* counts, void* stream) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    if (n < 0 || n > 0xFFFFFFFFll) return fail(CV_EINVAL, "n out of range");
+    if (n > 0 && (!rgb || !rays)) return fail(CV_EINVAL, "rgb or rays is NULL");
+    cvib::GridDev gd;
+    cvib::RuleDev rd;
+    int rc;
+    if ((rc = cvib::make_grid(grid, &gd)) != CV_OK) return rc;
+    if ((rc = cvib::make_rule(rule, &rd)) != CV_OK) return rc;
+    DeviceGuard dg(ctx->device);
+    return cvib::run_ray_search(ctx, rgb, n, gd, rd, rays, recs, best, counts, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
 int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, const uint8_t* info,
                       const cv_grid* grid, const cv_rule* rule, uint8_t* colours,
                       int64_t colour_cap, int64_t* ncolours, uint32_t* pixel_index,
@@ -357,14 +373,17 @@ int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, cons
 namespace {
 int surrogate_call(cv_context* ctx, cv_mlp* mlp, const cv_grid* grid, const cv_rule* rule, float tau,
                    int32_t kbins, uint32_t flags, cvib::SurrogateCall* c) {
-    if (!ctx || !mlp) return fail(CV_EINVAL, "ctx or network is NULL");
-    if (cvib::mlp_in_width(mlp) != 3 || cvib::mlp_out_width(mlp) != 37)
+    const bool given = (flags & CV_PRED_GIVEN) != 0;
+    if (!ctx || (!mlp && !given)) return fail(CV_EINVAL, "ctx or network is NULL");
+    if (mlp && (cvib::mlp_in_width(mlp) != 3 || cvib::mlp_out_width(mlp) != 37))
         return fail(CV_EINVAL, "the surrogate network must map 3 inputs to 37 outputs");
-    if (cvib::mlp_device(mlp) != ctx->device) return fail(CV_EINVAL, "network and context on different devices");
+    if (mlp && cvib::mlp_device(mlp) != ctx->device)
+        return fail(CV_EINVAL, "network and context on different devices");
     if (kbins < 1 || kbins > 36) return fail(CV_EINVAL, "kbins must be in [1, 36]");
     if (!(tau == tau)) return fail(CV_EINVAL, "tau is NaN");
-    if (flags & ~(uint32_t)CV_NO_FALLBACK) return fail(CV_EINVAL, "unknown flags");
+    if (flags & ~(uint32_t)(CV_NO_FALLBACK | CV_PRED_GIVEN)) return fail(CV_EINVAL, "unknown flags");
     std::memset(c, 0, sizeof *c);
+    c->pred_given = given;
     int rc;
     if ((rc = cvib::make_grid(grid, &c->gd)) != CV_OK) return rc;
     if ((rc = cvib::make_rule(rule, &c->rd)) != CV_OK) return rc;
@@ -378,20 +397,22 @@ int surrogate_call(cv_context* ctx, cv_mlp* mlp, const cv_grid* grid, const cv_r
 
 int cv_surrogate_infer(cv_context* ctx, cv_mlp* mlp, const uint8_t* rgb, int64_t n,
                        const cv_grid* grid, const cv_rule* rule, float tau, int32_t kbins,
-                       float* pred, cv_pattern_pair* pairs, uint8_t* status, int64_t* nfallback,
-                       uint32_t flags, void* stream) {
+                       float* pred, cv_pattern_pair* pairs, uint8_t* status, uint32_t* fallback,
+                       int64_t* nfallback, uint32_t flags, void* stream) {
     CV_GUARD_BEGIN
     cvib::SurrogateCall c;
     int rc;
     if ((rc = surrogate_call(ctx, mlp, grid, rule, tau, kbins, flags, &c)) != CV_OK) return rc;
     if (n < 0 || n > ((int64_t)1 << 30)) return fail(CV_EINVAL, "n must be in [0, 2^30]");
     if (n > 0 && (!rgb || !pairs || !status)) return fail(CV_EINVAL, "null array");
+    if (n > 0 && c.pred_given && !pred) return fail(CV_EINVAL, "CV_PRED_GIVEN needs pred");
     c.rgb = rgb;
     c.n = n;
     c.pred = pred;
     c.pairs = pairs;
     c.status = status;
     c.nfallback = nfallback;
+    c.fallback_list = fallback;
     DeviceGuard dg(ctx->device);
     return cvib::run_surrogate(ctx, c, (hipStream_t)stream);
     CV_GUARD_END
@@ -418,6 +439,8 @@ int cv_frames_surrogate(cv_context* ctx, cv_mlp* mlp, const uint8_t* pixels, int
     c.pairs = pairs;
     c.status = status;
     c.nfallback = nfallback;
+    c.fallback_list = nullptr;
+    if (c.pred_given) return fail(CV_EINVAL, "CV_PRED_GIVEN is for cv_surrogate_infer");
     DeviceGuard dg(ctx->device);
     return cvib::run_frames_surrogate(ctx, c, pixels, npix, colours, colour_cap, ncolours, pixel_index,
                                       frame_a, frame_b, resolved, (hipStream_t)stream);

@@ -1056,9 +1056,11 @@ int enqueue_surrogate(cv_context* ctx, const SurrogateCall& c, const uint8_t* rg
     uint64_t* smisc = (uint64_t*)ctx->smisc.ptr;  // [1] fallback count
     float* pred = c.pred ? c.pred : (float*)ctx->spred.ptr;
     if ((rc = enqueue_prologue(ctx, c.gd, rgb, n, n_dev, s)) != CV_OK) return rc;
-    if ((rc = ctx->mark(CV_TIME_MLP, 0, s)) != CV_OK) return rc;
-    if ((rc = mlp_forward_rgb8(c.mlp, rgb, n, pred, s)) != CV_OK) return rc;
-    if ((rc = ctx->mark(CV_TIME_MLP, 1, s)) != CV_OK) return rc;
+    if (!c.pred_given) {
+        if ((rc = ctx->mark(CV_TIME_MLP, 0, s)) != CV_OK) return rc;
+        if ((rc = mlp_forward_rgb8(c.mlp, rgb, n, pred, s)) != CV_OK) return rc;
+        if ((rc = ctx->mark(CV_TIME_MLP, 1, s)) != CV_OK) return rc;
+    }
     ProposeArgs p;
     p.cc = (const ColorConst*)ctx->colors.ptr;
     p.n_dev = n_dev;
@@ -1091,14 +1093,16 @@ int enqueue_surrogate(cv_context* ctx, const SurrogateCall& c, const uint8_t* rg
     if ((rc = ctx->mark(CV_TIME_VERIFY, 1, s)) != CV_OK) return rc;
     // colours without a verified proposal, counted (and listed) in colour order
     uint64_t* prefix = (uint64_t*)ctx->sprefix.ptr;
-    uint32_t* list = (uint32_t*)ctx->slist.ptr;
+    uint32_t* list = c.fallback_list ? c.fallback_list : (uint32_t*)ctx->slist.ptr;
     if ((rc = run_scan_counts(ctx, (const uint32_t*)ctx->sneed.ptr, n, prefix, nullptr, 1, 0, smisc + 1,
                               s)) != CV_OK)
         return rc;
-    if (c.fallback) {
+    if (c.fallback || c.fallback_list) {
         hipLaunchKernelGGL(k_make_list, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s,
                            (const uint32_t*)ctx->sneed.ptr, prefix, n_dev, list);
         CV_HIP(hipGetLastError());
+    }
+    if (c.fallback) {
         ResolveArgs a = resolve_args(ctx, c.gd, c.rd, smisc + 1);
         a.list = list;
         a.summ = (cv_color_summary*)ctx->ssumm.ptr;

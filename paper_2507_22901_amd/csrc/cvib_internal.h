@@ -85,6 +85,8 @@ size_t reduce_scratch_bytes(int64_t n, const GridDev& gd);
 int run_pair_reduce_noalloc(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
                             const RuleDev& rd, cv_color_summary* summ, cv_table_row* table,
                             hipStream_t s);
+int run_ray_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd, const RuleDev& rd,
+                   uint16_t* rays, cv_pair* recs, uint32_t* best, uint64_t* counts, hipStream_t s);
 int run_pair_csr_summary(cv_context* ctx, const cv_pair* recs, const int64_t* offsets, int64_t n,
                          cv_color_summary* summ, hipStream_t s);
 int run_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
@@ -162,6 +164,8 @@ struct SurrogateCall {
     cv_pattern_pair* pairs;
     uint8_t* status;
     int64_t* nfallback;       // nullable
+    uint32_t* fallback_list;  // nullable [n]: colour indices sent to the exact search, in order
+    bool pred_given;          // pred is the caller's input; the network does not run
 };
 int run_surrogate(cv_context* ctx, const SurrogateCall& call, hipStream_t s);
 int run_frames_surrogate(cv_context* ctx, const SurrogateCall& call, const uint8_t* pixels,

@@ -963,8 +963,81 @@ void free_mlp(cv_mlp* m) {
 // parameter count); a version 01 file is a ReLU network (omega0 = 0).
 const char kMagic[8] = {'C', 'V', 'M', 'L', 'P', '0', '2', '\0'};
 const char kMagic01[8] = {'C', 'V', 'M', 'L', 'P', '0', '1', '\0'};
+// Training checkpoint: parameters, both Adam moments, the step count and the
+// caller's training-order key, followed by a 64-bit FNV-1a hash of every byte
+// before it.
+const char kMagicCkpt[8] = {'C', 'V', 'C', 'K', 'P', '0', '1', '\0'};
+
+uint64_t fnv1a64(const void* p, size_t n, uint64_t h = 0xCBF29CE484222325ull) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t k = 0; k < n; ++k) {
+        h ^= c[k];
+        h *= 0x100000001B3ull;
+    }
+    return h;
+}
+
+// A checkpoint file read into host memory and checked: magic, shape fields
+// consistent with the byte count, finite omega0 and the content hash.
+struct Checkpoint {
+    int32_t L = 0;
+    int32_t dims[kMaxLayers + 1] = {};
+    int64_t n = 0;
+    float omega0 = 0.0f;
+    int64_t step = 0;
+    uint64_t key = 0;
+    std::string params, mom1, mom2;  // n floats each
+};
+
+int read_checkpoint(const char* path, Checkpoint& ck) {
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(CV_EINVAL, std::string("cannot open ") + path);
+    std::string all;
+    char chunk[1 << 16];
+    size_t got;
+    while ((got = fread(chunk, 1, sizeof chunk, f)) > 0) all.append(chunk, got);
+    fclose(f);
+    const std::string bad = std::string("not a valid network checkpoint: ") + path;
+    size_t o = 0;
+    auto take = [&](void* dst, size_t b) {
+        if (o + b > all.size()) return false;
+        std::memcpy(dst, all.data() + o, b);
+        o += b;
+        return true;
+    };
+    char magic[8];
+    if (!take(magic, 8) || std::memcmp(magic, kMagicCkpt, 8) != 0) return fail(CV_EINVAL, bad + " (magic)");
+    if (!take(&ck.L, 4) || ck.L < 1 || ck.L > kMaxLayers) return fail(CV_EINVAL, bad + " (layers)");
+    if (!take(ck.dims, 4 * ((size_t)ck.L + 1))) return fail(CV_EINVAL, bad + " (dims)");
+    int64_t want = 0;
+    for (int l = 0; l < ck.L; ++l) {
+        if (ck.dims[l] < 1 || ck.dims[l + 1] < 1 || ck.dims[l] > 4096 || ck.dims[l + 1] > 4096)
+            return fail(CV_EINVAL, bad + " (dims)");
+        want += (int64_t)ck.dims[l] * ck.dims[l + 1] + ck.dims[l + 1];
+    }
+    if (!take(&ck.n, 8) || ck.n != want) return fail(CV_EINVAL, bad + " (parameter count)");
+    if (!take(&ck.omega0, 4) || !std::isfinite(ck.omega0) || ck.omega0 < 0.0f)
+        return fail(CV_EINVAL, bad + " (omega0)");
+    if (!take(&ck.step, 8) || ck.step < 0) return fail(CV_EINVAL, bad + " (step)");
+    if (!take(&ck.key, 8)) return fail(CV_EINVAL, bad + " (key)");
+    const size_t pb = (size_t)ck.n * sizeof(float);
+    if (all.size() != o + 3 * pb + 8) return fail(CV_EINVAL, bad + " (length)");
+    uint64_t h = 0;
+    std::memcpy(&h, all.data() + o + 3 * pb, 8);
+    if (h != fnv1a64(all.data(), o + 3 * pb)) return fail(CV_EINVAL, bad + " (content hash)");
+    ck.params.assign(all.data() + o, pb);
+    ck.mom1.assign(all.data() + o + pb, pb);
+    ck.mom2.assign(all.data() + o + 2 * pb, pb);
+    return CV_OK;
+}
 
 } // namespace
+
+// BF16 activations widened to FP32 (cv_mlp_hidden).
+__global__ void k_bf16_to_f32(const bf16* __restrict__ in, float* __restrict__ out, int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = (float)in[k];
+}
 
 int mlp_forward_rgb8(cv_mlp* m, const uint8_t* rgb, int64_t n, float* out, hipStream_t s) {
     return run_forward(m, rgb, true, n, out, false, s);
@@ -1112,6 +1185,21 @@ int cv_mlp_forward(cv_mlp* m, const void* x, int64_t B, float* out, uint32_t fla
     CV_GUARD_END
 }
 
+int cv_mlp_hidden(const cv_mlp* m, int32_t layer, float* out, int64_t B, void* stream) {
+    CV_GUARD_BEGIN
+    if (!m) return fail(CV_EINVAL, "network is NULL");
+    if (layer < 1 || layer >= m->L) return fail(CV_EINVAL, "layer must be a hidden layer (1 .. nlayers - 1)");
+    if (B < 1 || B > m->fwd_rows) return fail(CV_ESTATE, "no kept forward pass of that many rows");
+    if (!out) return fail(CV_EINVAL, "out is NULL");
+    DeviceGuard dg(m->device);
+    const int64_t nv = B * m->dims[layer];
+    hipLaunchKernelGGL(cvib::k_bf16_to_f32, dim3((unsigned)std::min<int64_t>((nv + 255) / 256, 65535)), dim3(256),
+                       0, (hipStream_t)stream, (const bf16*)m->h[layer], out, nv);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+    CV_GUARD_END
+}
+
 int cv_mlp_loss(cv_mlp* m, const float* out, const float* t_r, const float* t_f, int64_t B,
                 float huber_delta, float* loss, float* gout, void* stream) {
     CV_GUARD_BEGIN
@@ -1238,6 +1326,75 @@ int cv_mlp_save(const cv_mlp* m, const char* path) {
               fwrite(&m->omega0, 4, 1, f) == 1 && fwrite(buf.data(), 1, buf.size(), f) == buf.size();
     ok = (fclose(f) == 0) && ok;
     return ok ? CV_OK : fail(CV_EINVAL, std::string("write failed: ") + path);
+    CV_GUARD_END
+}
+
+int cv_mlp_save_checkpoint(const cv_mlp* m, const char* path, int64_t step, uint64_t key) {
+    CV_GUARD_BEGIN
+    if (!m || !path) return fail(CV_EINVAL, "null argument");
+    if (step < 0) return fail(CV_EINVAL, "step < 0");
+    DeviceGuard dg(m->device);
+    const size_t pb = (size_t)m->nparam * sizeof(float);
+    std::string body;
+    body.append(cvib::kMagicCkpt, 8);
+    const int32_t L = m->L;
+    body.append((const char*)&L, 4);
+    body.append((const char*)m->dims, 4 * ((size_t)L + 1));
+    body.append((const char*)&m->nparam, 8);
+    body.append((const char*)&m->omega0, 4);
+    body.append((const char*)&step, 8);
+    body.append((const char*)&key, 8);
+    const size_t o = body.size();
+    body.resize(o + 3 * pb);
+    CV_HIP(hipDeviceSynchronize());
+    CV_HIP(hipMemcpy(&body[o], m->params, pb, hipMemcpyDeviceToHost));
+    CV_HIP(hipMemcpy(&body[o + pb], m->adam_m, pb, hipMemcpyDeviceToHost));
+    CV_HIP(hipMemcpy(&body[o + 2 * pb], m->adam_v, pb, hipMemcpyDeviceToHost));
+    const uint64_t h = cvib::fnv1a64(body.data(), body.size());
+    body.append((const char*)&h, 8);
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(CV_EINVAL, std::string("cannot open ") + path);
+    bool ok = fwrite(body.data(), 1, body.size(), f) == body.size();
+    ok = (fclose(f) == 0) && ok;
+    return ok ? CV_OK : fail(CV_EINVAL, std::string("write failed: ") + path);
+    CV_GUARD_END
+}
+
+int cv_mlp_checkpoint_info(const char* path, int32_t* nlayers, int32_t* dims, int64_t* step, uint64_t* key) {
+    CV_GUARD_BEGIN
+    if (!path) return fail(CV_EINVAL, "null path");
+    cvib::Checkpoint ck;
+    int rc = cvib::read_checkpoint(path, ck);
+    if (rc != CV_OK) return rc;
+    if (nlayers) *nlayers = ck.L;
+    if (dims) std::memcpy(dims, ck.dims, 4 * ((size_t)ck.L + 1));
+    if (step) *step = ck.step;
+    if (key) *key = ck.key;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_mlp_load_checkpoint(cv_mlp* m, const char* path, int64_t* step, uint64_t* key) {
+    CV_GUARD_BEGIN
+    if (!m || !path) return fail(CV_EINVAL, "null argument");
+    cvib::Checkpoint ck;
+    int rc = cvib::read_checkpoint(path, ck);
+    if (rc != CV_OK) return rc;
+    if (ck.L != m->L || std::memcmp(ck.dims, m->dims, 4 * ((size_t)m->L + 1)) != 0)
+        return fail(CV_EINVAL, std::string("checkpoint of another network shape: ") + path);
+    DeviceGuard dg(m->device);
+    const size_t pb = (size_t)m->nparam * sizeof(float);
+    CV_HIP(hipDeviceSynchronize());
+    CV_HIP(hipMemcpy(m->params, ck.params.data(), pb, hipMemcpyHostToDevice));
+    CV_HIP(hipMemcpy(m->adam_m, ck.mom1.data(), pb, hipMemcpyHostToDevice));
+    CV_HIP(hipMemcpy(m->adam_v, ck.mom2.data(), pb, hipMemcpyHostToDevice));
+    m->omega0 = ck.omega0;
+    rc = cvib::refresh_bf16(m, nullptr);
+    if (rc != CV_OK) return rc;
+    CV_HIP(hipDeviceSynchronize());
+    if (step) *step = ck.step;
+    if (key) *key = ck.key;
+    return CV_OK;
     CV_GUARD_END
 }
 

@@ -1,0 +1,243 @@
+// Adaptive per-ray search (gfx950): for every colour and every ray j, the
+// largest radius index i whose pair passes Section 3's predicate, without
+// evaluating the whole ray.
+//
+// The paper notes how large the search space is (Section 1) and evaluates
+// every displaced pair of Section 2's arrays.  Along one ray the pair moves
+// continuously with the radius, so a block of consecutive radii can often be
+// settled as a whole: interval bounds on its linear channels show either that
+// one colour leaves the gamut throughout the block, or that no channel can
+// change by more than V_th there (so no pattern can be encoded).  A ray is
+// taken from its outermost radius inward in blocks of 64: a coarse pass proves
+// blocks empty, and only the blocks it cannot close are refined, by evaluating
+// all their candidates with the exact predicate; the first survivor found is
+// the ray's maximum and ends the ray.  The maximum is therefore the one the
+// exhaustive search finds, bit for bit (same arithmetic on every candidate
+// that is evaluated), while most candidates are never evaluated.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <string>
+
+#include "cvib_internal.h"
+#include "cvib_kernels.h"
+
+namespace cvib {
+
+// Per-colour constants and the angle table of a call (cvib_search.hip).
+int prepare_colours(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd, hipStream_t s,
+                    TabArgs& tab);
+
+namespace {
+
+constexpr int kRayBlock = 256;   // threads per block: 4 waves, one task each at a time
+constexpr int kRowsPerBlock = 64;  // radii per row block (one lane each when refined)
+
+struct RayArgs {
+    const ColorConst* cc;
+    TabArgs tab;
+    Geom g;
+    RuleDev rule;
+    double ra, rb;
+    int32_t nr, ntheta;
+    int32_t W;                // rays evaluated per colour (N / 2 in half-turn mode)
+    int32_t nb;               // row blocks per ray, numbered from the outermost
+    int32_t rays_per_task;    // rays one wave takes at once: 64 / nb, at least 1
+    int32_t tasks_per_colour;
+    int32_t sym;              // ray j + W is ray j with + and - swapped
+    int32_t proofs;           // interval proofs on (not under the clip reading)
+    int64_t ntasks;
+    uint16_t* rays;           // [n][ntheta]: largest valid i + 1, 0 = none
+    cv_pair* recs;            // nullable [n][ntheta]: the pair at that radius, zero where none
+    unsigned long long* counts;  // nullable [3]: candidates evaluated, blocks tested, blocks closed
+    uint32_t* best;           // nullable [n]: the colour's largest key (i << 16 | 0xFFFF - j), zeroed before
+};
+
+__device__ __forceinline__ void store_ray(const RayArgs& a, int64_t c, int32_t j, uint32_t best,
+                                          uint32_t lo, uint32_t hi) {
+    const int64_t o = c * a.ntheta + j;
+    a.rays[o] = (uint16_t)best;
+    if (a.sym) a.rays[o + a.W] = (uint16_t)best;
+    if (a.recs) {
+        uint32_t* r = reinterpret_cast<uint32_t*>(a.recs + o);
+        const uint32_t w0 = (uint32_t)c, w1 = best ? ((best - 1u) | ((uint32_t)j << 16)) : 0u;
+        r[0] = w0;
+        r[1] = w1;
+        r[2] = best ? lo : 0u;
+        r[3] = best ? hi : 0u;
+        if (a.sym) {
+            uint32_t mlo = 0, mhi = 0;
+            if (best) mirror_pair(lo, hi, mlo, mhi);
+            uint32_t* m = reinterpret_cast<uint32_t*>(a.recs + o + a.W);
+            m[0] = w0;
+            m[1] = best ? ((best - 1u) | ((uint32_t)(j + a.W) << 16)) : 0u;
+            m[2] = mlo;
+            m[3] = mhi;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kRayBlock) void k_ray_search(RayArgs a) {
+    extern __shared__ double s_dyn[];
+    const Angles ang = load_angles(a.tab, s_dyn);
+    const uint32_t lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * kRayBlock + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * kRayBlock) >> 6;
+    const bool clip = a.rule.clip != 0u;
+    const int32_t nbs = a.nb < 64 ? a.nb : 64;          // blocks of one ray per sweep
+    const int32_t sweeps = (a.nb + 63) / 64;
+    const uint64_t ray_bits = nbs == 64 ? ~0ull : ((1ull << nbs) - 1ull);
+    uint64_t evald = 0, tested = 0, closed = 0;
+
+    for (int64_t t = wave; t < a.ntasks; t += nwaves) {
+        const int64_t c = t / a.tasks_per_colour;
+        const int32_t j0 = (int32_t)(t - c * a.tasks_per_colour) * a.rays_per_task;
+        const int32_t R = min(a.rays_per_task, a.W - j0);
+        const ColorConst cc = a.cc[c];
+        const bool cube = cube_branch_only(cc, a.nr - 1, a.ra, a.rb);
+        uint64_t done = 0;  // rays of the task already settled (bit r)
+        for (int32_t sw = 0; sw < sweeps; ++sw) {
+            // coarse pass: lane -> (ray r, block b), one interval proof each
+            const int32_t r = (int32_t)lane / nbs, b = sw * 64 + (int32_t)lane % nbs;
+            const bool live = r < R && b < a.nb && !((done >> r) & 1ull);
+            bool open = live;
+            if (a.proofs) {
+                const int32_t rr = live ? r : 0, bb = live ? b : 0;
+                const int32_t hi_i = a.nr - 1 - kRowsPerBlock * bb;
+                const int32_t lo_i = max(hi_i - (kRowsPerBlock - 1), 0);
+                double s, co;
+                ang.get(j0 + rr, s, co);
+                bool high = true;
+                const int32_t j = j0 + rr;
+                const bool out = cell_out_of_gamut_ends(cc, a.g, ang.N, a.ra, a.rb, lo_i, hi_i, j, j, s, co, s,
+                                                        co, &a.rule, &high);
+                open = live && !out && high;
+            }
+            const uint64_t lm = __ballot(live), om = uniform_u64(__ballot(open));
+            tested += (uint64_t)__builtin_popcountll(lm);
+            closed += (uint64_t)__builtin_popcountll(lm & ~om);
+            // refinement: each ray's open blocks from the outermost inward
+            for (int32_t q = 0; q < R; ++q) {
+                if ((done >> q) & 1ull) continue;
+                uint64_t m = (om >> (q * nbs)) & ray_bits;
+                const int32_t j = j0 + q;
+                double s, co;
+                ang.get(j, s, co);
+                while (m) {
+                    const int32_t bb = sw * 64 + (int32_t)__builtin_ctzll(m);
+                    m &= m - 1ull;
+                    const int32_t i = a.nr - 1 - kRowsPerBlock * bb - (int32_t)lane;  // lane 0 outermost
+                    const bool lv = i >= 0;
+                    const double rad = (double)(lv ? i + 1 : 1);
+                    float fp[3], fm[3];
+                    pair_linear_w(cc, a.g, (rad * a.ra) * s, (rad * a.rb) * co, fp, fm, cube);
+                    const uint64_t live_m = __ballot(lv);
+                    evald += (uint64_t)__builtin_popcountll(live_m);
+                    const bool gp = in_unit_cube(fp), gm = in_unit_cube(fm);
+                    const uint64_t need_m = clip ? live_m : (__ballot(gp && gm) & live_m);
+                    if (need_m == 0ull) continue;
+                    float Vp[3], Vm[3];
+                    codes_w(fp, fm, (need_m >> lane) & 1ull, clip, Vp, Vm);
+                    const PatMasks pm = pattern_masks(Vp, Vm, a.rule);
+                    const uint64_t surv = uniform_u64(accepted_lanes(pm, a.rule.mask) & need_m);
+                    if (surv == 0ull) continue;
+                    const uint32_t first = (uint32_t)__builtin_ctzll(surv);  // largest i
+                    if (lane == first) {
+                        uint32_t lo, hi;
+                        const uint32_t flags = 4u | (gp ? 1u : 0u) | (gm ? 2u : 0u);
+                        pack_pair(Vp, Vm, pattern_of(Vp, Vm, a.rule), flags, lo, hi);
+                        store_ray(a, c, j, (uint32_t)(i + 1), lo, hi);
+                        // the mirrored ray j + W has the same i and a larger j: never the better key
+                        if (a.best) atomicMax(&a.best[c], best_key(i, j));
+                    }
+                    done |= 1ull << q;
+                    break;
+                }
+            }
+        }
+        // rays with no survivor
+        if ((int32_t)lane < R && !((done >> lane) & 1ull)) store_ray(a, c, j0 + (int32_t)lane, 0u, 0u, 0u);
+    }
+    if (a.counts && lane == 0) {
+        if (evald) atomicAdd(&a.counts[0], (unsigned long long)evald);
+        if (tested) atomicAdd(&a.counts[1], (unsigned long long)tested);
+        if (closed) atomicAdd(&a.counts[2], (unsigned long long)closed);
+    }
+}
+
+__global__ void k_zero_counts(unsigned long long* p) {
+    if (threadIdx.x < 3) p[threadIdx.x] = 0ull;
+}
+
+__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = 0u;
+}
+
+inline unsigned ray_blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+int run_ray_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd, const RuleDev& rd,
+                   uint16_t* rays, cv_pair* recs, uint32_t* best, uint64_t* counts, hipStream_t s) {
+    if (counts) {
+        hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, s, (unsigned long long*)counts);
+        CV_HIP(hipGetLastError());
+    }
+    if (n == 0) return CV_OK;
+    if (best) {
+        hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s,
+                           best, n);
+        CV_HIP(hipGetLastError());
+    }
+    int rc;
+    TabArgs tab;
+    if ((rc = prepare_colours(ctx, rgb, n, gd, s, tab)) != CV_OK) return rc;
+    RayArgs a;
+    a.cc = (const ColorConst*)ctx->colors.ptr;
+    a.tab = tab;
+    a.g = geom_constants();
+    a.rule = rd;
+    a.ra = gd.ra;
+    a.rb = gd.rb;
+    a.nr = gd.nr;
+    a.ntheta = gd.ntheta;
+    a.sym = gd.ntheta == gd.N ? 1 : 0;
+    a.W = a.sym ? gd.N / 2 : gd.ntheta;
+    a.nb = (gd.nr + kRowsPerBlock - 1) / kRowsPerBlock;
+    a.rays_per_task = a.nb >= 64 ? 1 : 64 / a.nb;
+    if (a.rays_per_task > a.W) a.rays_per_task = a.W;
+    a.tasks_per_colour = (a.W + a.rays_per_task - 1) / a.rays_per_task;
+    a.proofs = rd.clip ? 0 : 1;
+    a.ntasks = n * (int64_t)a.tasks_per_colour;
+    a.rays = rays;
+    a.recs = recs;
+    a.counts = (unsigned long long*)counts;
+    a.best = best;
+    const size_t lds = angle_lds_bytes(tab);
+    int lds_max = 0;
+    CV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    hipFuncAttributes fa;
+    CV_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_ray_search)));
+    if (lds + fa.sharedSizeBytes > (size_t)lds_max)
+        return fail(CV_EINVAL, "this grid needs " + std::to_string(lds + fa.sharedSizeBytes) +
+                                   " bytes of LDS per block; the device has " + std::to_string(lds_max));
+    int per_cu = 0;
+    CV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ray_search, kRayBlock, lds));
+    if (per_cu < 1) per_cu = 1;
+    int64_t grid = (int64_t)per_cu * ctx->num_cu;
+    const int64_t need = (int64_t)ray_blocks_for(a.ntasks, kRayBlock / 64);
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
+    hipLaunchKernelGGL(k_ray_search, dim3((unsigned)grid), dim3(kRayBlock), lds, s, a);
+    CV_HIP(hipGetLastError());
+    if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
+    if (ctx->timing && (rc = ctx->collect()) != CV_OK) return rc;
+    return CV_OK;
+}
+
+}  // namespace cvib

@@ -28,3 +28,7 @@ def test_bench_line_nine_colours():
     assert rf["bound"] in ("alu", "hbm", "mfma") and 0 < rf["frac"] < 1
     assert abs(rf["achieved"] / rf["peak"] - rf["frac"]) < 1e-9
     assert d["config"]["survivors_per_step"] > 0
+    # the published FP32 peak; evaluated pairs are a subset of the decided ones
+    assert rf["peak"] == 157.3 and rf["unit"] == "TFLOP/s"
+    assert abs(rf["flops_per_launch"] - 85 * rf["evaluated_pairs"]) == 0
+    assert 0 < d["evaluated_pairs_per_s"] <= d["decided_pairs_per_s"] == d["value"]

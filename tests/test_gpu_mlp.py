@@ -342,3 +342,119 @@ def test_permute_ids_is_a_shuffle(cv):
     assert float(d.median()) > n / 8
     with pytest.raises(cv.CvError):   # in place is refused
         cv._check(cv.lib().cv_permute_ids(cv.context().handle, cv._dptr(ids), n, 1, cv._dptr(ids), None))
+
+
+# --------------------------------------------------------------------------
+# Layer by layer, element by element: the FP64 oracle is given each layer's
+# own input as the kernels hold it (x for the first layer, the kept BF16
+# activations after it), so the comparison sees only the kernels' FP32
+# accumulation and their single BF16 rounding of each activation.  An element
+# of a product sum_i a_i b_i is held to tol * sum_i |a_i b_i|.
+
+def _elementwise(got, ref, scale, tol, what):
+    err = np.abs(np.asarray(got, np.float64) - ref)
+    lim = tol * np.asarray(scale, np.float64) + 1e-30
+    bad = err > lim
+    assert not bad.any(), (f"{what}: {int(bad.sum())} of {bad.size} elements off; worst "
+                           f"{float(np.max(err / lim)):.3g} x the bound")
+
+
+def _layer_io(cv, m, flat, x, omega0):
+    L = len(DIMS) - 1
+    B = x.shape[0]
+    H = [x.astype(np.float64)] + [m.hidden(l, B).cpu().numpy().astype(np.float64) for l in range(1, L)]
+    Ws, bs = oracle_weights(cv, flat, DIMS)
+    return L, H, Ws, bs
+
+
+@pytest.mark.parametrize("omega0", [0.0, 30.0])
+def test_layers_elementwise_against_oracle(cv, oracle, omega0):
+    m, flat = _net(cv, seed=31, omega0=omega0)
+    B = 700
+    x, tr, tf = _batch(B, 32)
+    xd = torch.from_numpy(x).cuda()
+    outd = m.forward(xd, keep=True)
+    out = outd.cpu().numpy().astype(np.float64)
+    L, H, Ws, bs = _layer_io(cv, m, flat, x, omega0)
+    z1 = None
+    for l in range(L):
+        z = oracle.mlp_forward([DIMS[l], DIMS[l + 1]], [Ws[l]], [bs[l]], H[l])
+        scale = np.abs(H[l]) @ np.abs(Ws[l]).T + np.abs(bs[l])
+        if l == 0:
+            z1 = z
+        if l == L - 1:
+            _elementwise(out, z, scale, 1e-5, "output layer")
+            continue
+        sine = l == 0 and omega0 > 0
+        a = np.sin(omega0 * z) if sine else np.maximum(z, 0.0)
+        # the FP32 pre-activation (error <= 1e-5 x scale, times omega0 through
+        # the sine) and one BF16 rounding (<= 2^-8 |a|)
+        _elementwise(H[l + 1], a, 2.0 ** -8 / 1e-5 * np.abs(a) + (omega0 if sine else 1.0) * scale, 1e-5,
+                     f"hidden layer {l + 1}")
+    # backward: the output gradient as the kernels read it (BF16), then the
+    # chain through the kernels' own activations
+    _, gout = m.loss(outd, torch.from_numpy(tr).cuda(), torch.from_numpy(tf).cuda(), 0.1)
+    m.backward(xd, gout)
+    gWs, gbs = cv.split_params(m.grads().cpu().numpy(), DIMS)
+    G = bf(gout.cpu()).double().numpy()
+    for l in range(L - 1, -1, -1):
+        (gW_ref,), (gb_ref,) = oracle.mlp_backward([DIMS[l], DIMS[l + 1]], [Ws[l]], [bs[l]], H[l], G)
+        sW = np.abs(G).T @ np.abs(H[l])
+        sb = np.abs(G).sum(0)
+        # the last layer reads exactly the kernels' operands (FP32 sums only);
+        # below it the host's chain may round a few BF16 gradients the other
+        # way, each moving a term by at most 2^-8 of itself
+        tol = 1e-5 if l == L - 1 else 1e-2
+        _elementwise(gWs[l], gW_ref, sW, tol, f"weight gradient {l}")
+        _elementwise(gbs[l], gb_ref, sb, tol, f"bias gradient {l}")
+        if l == 0:
+            break
+        gin = oracle.linear_input_grad(Ws[l], G)
+        if l == 1 and omega0 > 0:
+            deriv = omega0 * np.cos(omega0 * z1)
+        else:
+            deriv = (H[l] > 0).astype(np.float64)
+        G = bf(torch.from_numpy(gin * deriv)).double().numpy()
+
+
+def test_exact_bf16_network_equals_oracle(cv, oracle):
+    """Weights, biases, inputs and output gradients chosen so that every
+    activation and every back-propagated gradient is a small integer, which
+    BF16 holds exactly and FP32 sums exactly: the kernels must then give the
+    FP64 oracle's outputs and gradients to 1e-5 (in fact exactly).  This checks
+    the kernels' arithmetic without the BF16 noise floor (index, layout and
+    transposition mistakes show at once)."""
+    rng = np.random.default_rng(41)
+    dims = DIMS
+    Ws, bs = [], []
+    for l in range(len(dims) - 1):
+        din, dout = dims[l], dims[l + 1]
+        W = np.zeros((dout, din))
+        k = 3 if l == 0 else 4   # non-zeros per row
+        for o in range(dout):
+            cols_ = rng.choice(din, min(k, din), replace=False)
+            W[o, cols_] = rng.choice([-1.0, 1.0], len(cols_))
+        Ws.append(W)
+        bs.append(rng.integers(-2, 3, dout).astype(np.float64))
+    flat = np.concatenate([np.concatenate([W.ravel(), b]) for W, b in zip(Ws, bs)]).astype(np.float32)
+    m = cv.MLP(dims)
+    m.set_first_sine(0.0)
+    m.set_params(flat)
+    B = 96
+    x = rng.integers(-2, 3, (B, 3)).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    out = m.forward(xd, keep=True).cpu().numpy().astype(np.float64)
+    ref = oracle.mlp_forward(list(dims), Ws, bs, x.astype(np.float64))
+    # every hidden activation is a small integer (exact in BF16: below 256)
+    for l in range(1, len(dims) - 1):
+        h = m.hidden(l, B).cpu().numpy()
+        assert np.array_equal(h, np.rint(h)) and np.abs(h).max() < 256, l
+    assert np.max(np.abs(out - ref)) <= 1e-5 * np.abs(ref).max()
+    gout = rng.integers(-1, 2, (B, dims[-1])).astype(np.float32)
+    m.backward(xd, torch.from_numpy(gout).cuda())
+    gWs, gbs = cv.split_params(m.grads().cpu().numpy(), dims)
+    o_gW, o_gb = oracle.mlp_backward(list(dims), Ws, bs, x.astype(np.float64), gout.astype(np.float64))
+    for l in range(len(dims) - 1):
+        assert np.max(np.abs(gWs[l] - o_gW[l])) <= 1e-5 * max(np.abs(o_gW[l]).max(), 1.0), l
+        assert np.max(np.abs(gbs[l] - o_gb[l])) <= 1e-5 * max(np.abs(o_gb[l]).max(), 1.0), l
+    assert max(np.abs(g).max() for g in o_gW) > 10  # the check is not vacuous

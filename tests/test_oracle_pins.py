@@ -395,6 +395,26 @@ def test_mlp_forward_matches_matrix_products(oracle, omega0):
     assert np.allclose(oracle.mlp_forward(dims, Ws, bs, x, omega0), h, atol=1e-12)
 
 
+def test_linear_input_grad_finite_differences(oracle):
+    """The input gradient of a linear layer against central differences of the
+    oracle's own forward pass (a one-layer network)."""
+    rng = np.random.default_rng(17)
+    W = rng.normal(0, 1, (6, 4))
+    b = rng.normal(0, 1, 6)
+    x = rng.normal(0, 1, (3, 4))
+    gout = rng.normal(0, 1, (3, 6))
+    gin = oracle.linear_input_grad(W, gout)
+    h = 1e-6
+    for s_ in range(3):
+        for k in range(4):
+            xp, xm = x.copy(), x.copy()
+            xp[s_, k] += h
+            xm[s_, k] -= h
+            fp = (gout * oracle.mlp_forward([4, 6], [W], [b], xp)).sum()
+            fm = (gout * oracle.mlp_forward([4, 6], [W], [b], xm)).sum()
+            assert abs((fp - fm) / (2 * h) - gin[s_, k]) < 1e-7
+
+
 def test_mlp_loss_closed_forms(oracle):
     """Huber and logistic terms at hand-computable points: an output equal to
     its target costs nothing; an error of 3 deltas costs delta^2 (3 - 1/2);
