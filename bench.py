@@ -79,11 +79,14 @@ FLOPS_CELL = 84
 # GRBM_GUI_ACTIVE cycles per XCD.  Valid only for the kernel sources they were
 # measured on (their digest); null otherwise.
 MEASURED_COUNTERS = {
-    "count_pass": {"sources_sha256": "7bfc5d4b2d4b6f302d0f42f5a2e846bbc8b4d376d94a32a382eaf08be9647f9a",
-                   "traffic_bytes": 62792764, "valu_issue": 0.541},
-    "colour_resolve": None,
-    "cube_table": None,
-    "ray_search": None,
+    "count_pass": {"sources_sha256": "4b22cfb973e485e1fd3c473ba709f3fe7cb44b97f3ffa6dd6e73175b74706758",
+                   "traffic_bytes": 62760767, "valu_issue": 0.541},
+    "colour_resolve": {"sources_sha256": "45e09672734ade086c4b8eb88e5b32bf058bad65ba08f13119e2ec9723ed46b0",
+                   "traffic_bytes": 7275424193, "valu_issue": 0.974},
+    "cube_table": {"sources_sha256": "4b22cfb973e485e1fd3c473ba709f3fe7cb44b97f3ffa6dd6e73175b74706758",
+                   "traffic_bytes": 3566921540, "valu_issue": 0.948},
+    "ray_search": {"sources_sha256": "6d0528e242ff118e1584b4863e146ee703b6bc7a4d9dc6e6fe88d7ed6a29db6d",
+                   "traffic_bytes": 6098304309, "valu_issue": 0.839},
 }
 KERNEL_SOURCES = {
     "count_pass": ("cvib_search.hip", "cvib_device.h", "cvib_kernels.h"),
