@@ -65,15 +65,26 @@ struct GemmArgs {
     int64_t ldm;
     int32_t nstore;            // result columns written (<= N)
     // EPI_SINE_BF16: the derivative omega0 cos(omega0 z) of a sinusoidal first
-    // layer, z = b0 + W0 x recomputed from the FP32 inputs x [M][d0]
+    // layer, stored by the forward pass [M][ldd] (dsin), or else recomputed
+    // from z = b0 + W0 x and the FP32 inputs x [M][d0]
+    const float* dsin;
+    int64_t ldd;
     const float* x0;
     const float* w0;
     const float* b0;
     int32_t d0;
     float omega0;
+    // bf16 epilogues: the result also transposed, [N][ldct] (nullable), for
+    // the weight-gradient products, whose operands must be k-contiguous
+    bf16* cbt;
+    int64_t ldct;
+    // EPI_PARTIAL_F32 with A k-contiguous: blocks of the first column tile
+    // also write the row sums of A over their k range (bias gradients),
+    // [blockIdx.z][M] (nullable)
+    float* bpart;
 };
 
-constexpr int kDepth = 32, kPitch = 40;
+constexpr int kDepth = 32;
 
 // Network input of an 8-bit code: v * fl(1/255) - 1/2, the product and the
 // difference each rounded to FP32 (never contracted into one FMA), the same
@@ -90,11 +101,14 @@ __device__ __forceinline__ float first_act(float z, float omega0) {
     return omega0 > 0.0f ? sinf(omega0 * z) : fmaxf(z, 0.0f);
 }
 
-// A tile of R rows x 32 k of one operand, global -> registers: PER 8-element
-// chunks per thread (R * 4 / 256 of them).  KC: stored [row][k]; else [k][row].
-template <bool KC, int R>
+// A tile of R rows x KD k of one operand, global -> registers: PER 8-element
+// chunks per thread (R * KD / 8 / 256 of them).  KC: stored [row][k] (a chunk
+// that runs past ke is loaded element by element, so k need not be a multiple
+// of 8); else [k][row].
+template <bool KC, int R, int KD>
 struct TileLoad {
-    static constexpr int PER = R * 4 / 256;
+    static constexpr int PER = R * KD / 8 / 256;
+    static constexpr int CPR = KD / 8;  // chunks per row (KC)
     bf16x8 v[PER];
     __device__ __forceinline__ void load(const bf16* __restrict__ P, int64_t ld, int32_t r0, int32_t rows,
                                          int32_t k0, int32_t ke, int tid) {
@@ -103,9 +117,17 @@ struct TileLoad {
             const int u = tid + 256 * q;
             v[q] = bf16x8{};
             if constexpr (KC) {
-                const int r = u >> 2, c = (u & 3) * 8;
-                if (r0 + r < rows && k0 + c < ke)
-                    v[q] = *reinterpret_cast<const bf16x8*>(P + (int64_t)(r0 + r) * ld + k0 + c);
+                const int r = u / CPR, c = (u % CPR) * 8;
+                if (r0 + r < rows && k0 + c < ke) {
+                    const bf16* src = P + (int64_t)(r0 + r) * ld + k0 + c;
+                    if (k0 + c + 8 <= ke) {
+                        v[q] = *reinterpret_cast<const bf16x8*>(src);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e)
+                            if (k0 + c + e < ke) v[q][e] = src[e];
+                    }
+                }
             } else {
                 const int kr = u / (R / 8), c = (u % (R / 8)) * 8;
                 if (k0 + kr < ke && r0 + c < rows)
@@ -113,111 +135,172 @@ struct TileLoad {
             }
         }
     }
-    // registers -> LDS tile [row][k] (k contiguous, pitch kPitch)
+    // registers -> LDS tile [row][k] (k contiguous, pitch KD + 8)
     __device__ __forceinline__ void store(bf16* s, int tid) const {
+        constexpr int pitch = KD + 8;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int u = tid + 256 * q;
             if constexpr (KC) {
-                const int r = u >> 2, c = (u & 3) * 8;
-                *reinterpret_cast<bf16x8*>(s + r * kPitch + c) = v[q];
+                const int r = u / CPR, c = (u % CPR) * 8;
+                *reinterpret_cast<bf16x8*>(s + r * pitch + c) = v[q];
             } else {
                 const int kr = u / (R / 8), c = (u % (R / 8)) * 8;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) s[(c + e) * kPitch + kr] = v[q][e];
+                for (int e = 0; e < 8; ++e) s[(c + e) * pitch + kr] = v[q][e];
             }
         }
     }
 };
 
 // BM x BN outputs per block of 4 waves (2 x 2), each wave (BM/2) x (BN/2) as
-// MFMA tiles of 16 x 16; the next 32-deep slice of both operands is fetched
-// into registers while the current one is multiplied from LDS.
-template <bool A_KC, bool B_KC, int EPI, int BM, int BN>
+// MFMA tiles of 16 x 16; KD-deep k steps (one barrier pair each, KD / 32 MFMA
+// passes), the next step of both operands fetched into registers while the
+// current one is multiplied from LDS.  The k order (32-deep slices in
+// ascending order, each one MFMA) does not depend on KD.
+template <bool A_KC, bool B_KC, int EPI, int BM, int BN, int KD>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     constexpr int TM = BM / 32, TN = BN / 32;  // MFMA tiles per wave
-    __shared__ __attribute__((aligned(16))) bf16 sA[BM * kPitch];
-    __shared__ __attribute__((aligned(16))) bf16 sB[BN * kPitch];
+    constexpr int pitch = KD + 8;
+    __shared__ __attribute__((aligned(16))) bf16 sA[BM * pitch];
+    __shared__ __attribute__((aligned(16))) bf16 sB[BN * pitch];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int32_t m0 = (int32_t)blockIdx.x * BM, n0 = (int32_t)blockIdx.y * BN;
     const int32_t kb = (int32_t)blockIdx.z * a.kchunk;
     const int32_t ke = min(a.K, kb + a.kchunk);
+    // bias-gradient row sums of A (first column tile only): thread -> row
+    // tid / 4 (BM = 64), a quarter of each k step
+    constexpr bool ROWSUM = EPI == EPI_PARTIAL_F32 && A_KC && BM == 64;
+    const bool rowsum = ROWSUM && a.bpart != nullptr && blockIdx.y == 0;
+    float rsum = 0.0f;
     f32x4 acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int fr = lane & 15, fk = (lane >> 4) * 8;
-    TileLoad<A_KC, BM> la;
-    TileLoad<B_KC, BN> lb;
+    TileLoad<A_KC, BM, KD> la;
+    TileLoad<B_KC, BN, KD> lb;
     la.load(a.A, a.lda, m0, a.M, kb, ke, tid);
     lb.load(a.B, a.ldb, n0, a.N, kb, ke, tid);
-    for (int32_t k0 = kb; k0 < ke; k0 += kDepth) {
+    for (int32_t k0 = kb; k0 < ke; k0 += KD) {
         la.store(sA, tid);
         lb.store(sB, tid);
         __syncthreads();
-        if (k0 + kDepth < ke) {  // next slice in flight during the products
-            la.load(a.A, a.lda, m0, a.M, k0 + kDepth, ke, tid);
-            lb.load(a.B, a.ldb, n0, a.N, k0 + kDepth, ke, tid);
+        if (k0 + KD < ke) {  // next step in flight during the products
+            la.load(a.A, a.lda, m0, a.M, k0 + KD, ke, tid);
+            lb.load(a.B, a.ldb, n0, a.N, k0 + KD, ke, tid);
         }
-        bf16x8 fa[TM], fb[TN];
+        if constexpr (ROWSUM) {
+            if (rowsum) {
+                const bf16* row = sA + (tid >> 2) * pitch + (tid & 3) * (KD / 4);
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
-            fa[i] = *reinterpret_cast<const bf16x8*>(sA + ((BM / 2) * wm + 16 * i + fr) * kPitch + fk);
+                for (int e = 0; e < KD / 4; ++e) rsum += (float)row[e];
+            }
+        }
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-            fb[j] = *reinterpret_cast<const bf16x8*>(sB + ((BN / 2) * wn + 16 * j + fr) * kPitch + fk);
+        for (int kk = 0; kk < KD; kk += kDepth) {
+            bf16x8 fa[TM], fb[TN];
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+            for (int i = 0; i < TM; ++i)
+                fa[i] = *reinterpret_cast<const bf16x8*>(sA + ((BM / 2) * wm + 16 * i + fr) * pitch + kk + fk);
 #pragma unroll
             for (int j = 0; j < TN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+                fb[j] = *reinterpret_cast<const bf16x8*>(sB + ((BN / 2) * wn + 16 * j + fr) * pitch + kk + fk);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
+    }
+    if constexpr (ROWSUM) {
+        if (rowsum) {
+            rsum += __shfl_xor(rsum, 1, 64);
+            rsum += __shfl_xor(rsum, 2, 64);
+            const int32_t m = m0 + (tid >> 2);
+            if ((tid & 3) == 0 && m < a.M) a.bpart[(int64_t)blockIdx.z * a.M + m] = rsum;
+        }
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+        for (int j = 0; j < TN; ++j) {
+            const int32_t mb = m0 + (BM / 2) * wm + 16 * i + (lane >> 4) * 4;  // 4 consecutive rows
+            const int32_t n = n0 + (BN / 2) * wn + 16 * j + fr;
+            if (n >= a.nstore) continue;
+            bf16 r[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int32_t m = m0 + (BM / 2) * wm + 16 * i + (lane >> 4) * 4 + e;
-                const int32_t n = n0 + (BN / 2) * wn + 16 * j + fr;
-                if (m >= a.M || n >= a.nstore) continue;
+                const int32_t m = mb + e;
                 const float v = acc[i][j][e];
+                r[e] = (bf16)0.0f;
+                if (m >= a.M) continue;
                 if constexpr (EPI == EPI_RELU_BF16) {
-                    a.cb[(int64_t)m * a.ldc + n] = (bf16)fmaxf(v + a.bias[n], 0.0f);
+                    r[e] = (bf16)fmaxf(v + a.bias[n], 0.0f);
+                    a.cb[(int64_t)m * a.ldc + n] = r[e];
                 } else if constexpr (EPI == EPI_BIAS_F32) {
                     a.cf[(int64_t)m * a.ldc + n] = v + a.bias[n];
                 } else if constexpr (EPI == EPI_MASK_BF16) {
                     const float h = (float)a.mask[(int64_t)m * a.ldm + n];
-                    a.cb[(int64_t)m * a.ldc + n] = (bf16)(h > 0.0f ? v : 0.0f);
+                    r[e] = (bf16)(h > 0.0f ? v : 0.0f);
+                    a.cb[(int64_t)m * a.ldc + n] = r[e];
                 } else if constexpr (EPI == EPI_SINE_BF16) {
-                    float z = a.b0[n];
-                    for (int32_t c = 0; c < a.d0; ++c) z = fmaf(a.w0[n * a.d0 + c], a.x0[(int64_t)m * a.d0 + c], z);
-                    a.cb[(int64_t)m * a.ldc + n] = (bf16)(v * (a.omega0 * cosf(a.omega0 * z)));
+                    float d;
+                    if (a.dsin) {
+                        d = a.dsin[(int64_t)m * a.ldd + n];
+                    } else {
+                        float z = a.b0[n];
+                        for (int32_t c = 0; c < a.d0; ++c) z = fmaf(a.w0[n * a.d0 + c], a.x0[(int64_t)m * a.d0 + c], z);
+                        d = a.omega0 * cosf(a.omega0 * z);
+                    }
+                    r[e] = (bf16)(v * d);
+                    a.cb[(int64_t)m * a.ldc + n] = r[e];
                 } else {
                     a.cf[(int64_t)blockIdx.z * a.zstride + (int64_t)m * a.ldc + n] = v;
                 }
             }
+            if constexpr (EPI == EPI_RELU_BF16 || EPI == EPI_MASK_BF16 || EPI == EPI_SINE_BF16) {
+                if (a.cbt) {
+                    bf16* dst = a.cbt + (int64_t)n * a.ldct + mb;
+                    if (mb + 3 < a.M) {
+                        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                        *reinterpret_cast<bf16x4*>(dst) = bf16x4{r[0], r[1], r[2], r[3]};
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (mb + e < a.M) dst[e] = r[e];
+                    }
+                }
+            }
+        }
 }
 
-// Rows from which the larger tiles pay (enough blocks to fill the chip).
+// Rows from which the larger tiles pay (enough blocks to fill the chip;
+// measured: at 8192 rows the 64 x 64 tiles are faster).
 constexpr int32_t kBigTileRows = 32768;
 
 template <bool A_KC, bool B_KC, int EPI>
 int gemm(const GemmArgs& a, int32_t splits, hipStream_t s) {
     // vector loads need 8-element alignment along every contiguous dimension
-    const bool ok = (a.lda % 8 == 0) && (a.ldb % 8 == 0) && (A_KC ? a.K % 8 == 0 : a.M % 8 == 0) &&
-                    (B_KC ? a.K % 8 == 0 : a.N % 8 == 0) && a.kchunk % kDepth == 0 && a.M > 0 &&
-                    a.N > 0 && a.K > 0 && splits >= 1 && (int64_t)splits * a.kchunk >= a.K;
+    // (a k-contiguous operand may end in a partial chunk); transposed results
+    // are stored 4 rows at a time
+    const bool ok = (a.lda % 8 == 0) && (a.ldb % 8 == 0) && (A_KC || a.M % 8 == 0) &&
+                    (B_KC || a.N % 8 == 0) && a.kchunk % kDepth == 0 && a.M > 0 && a.N > 0 && a.K > 0 &&
+                    splits >= 1 && (int64_t)splits * a.kchunk >= a.K && (!a.cbt || a.ldct % 4 == 0) &&
+                    (!a.bpart || A_KC);
     if (!ok) return fail(CV_ESTATE, "internal: matrix product shape");
-    if (a.M >= kBigTileRows && splits == 1) {
-        const dim3 grid((unsigned)((a.M + 127) / 128), (unsigned)((a.N + 127) / 128), 1);
-        hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI, 128, 128>), grid, dim3(256), 0, s, a);
+    const bool deep = a.kchunk % 64 == 0;
+    if (a.M >= kBigTileRows && splits == 1 && !a.bpart) {
+        const dim3 grid((unsigned)((a.M + 127) / 128), (unsigned)((a.N + 63) / 64), 1);
+        if (deep) hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI, 128, 64, 64>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI, 128, 64, 32>), grid, dim3(256), 0, s, a);
     } else {
         const dim3 grid((unsigned)((a.M + 63) / 64), (unsigned)((a.N + 63) / 64), (unsigned)splits);
-        hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI, 64, 64>), grid, dim3(256), 0, s, a);
+        if (deep) hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI, 64, 64, 64>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI, 64, 64, 32>), grid, dim3(256), 0, s, a);
     }
     CV_HIP(hipGetLastError());
     return CV_OK;
@@ -233,7 +316,7 @@ template <bool RGB8>
 __global__ __launch_bounds__(256) void k_input_layer(const void* __restrict__ xin, int64_t B, int32_t d0,
                                                      int32_t d1, const float* __restrict__ W0,
                                                      const float* __restrict__ b0, float omega0,
-                                                     bf16* __restrict__ H1) {
+                                                     bf16* __restrict__ H1, float* __restrict__ dsin) {
     __shared__ float s_w[kMaxHidden * (kMaxIn + 1)];
     for (int k = threadIdx.x; k < d1 * d0; k += 256) s_w[k] = W0[k];
     for (int k = threadIdx.x; k < d1; k += 256) s_w[d1 * d0 + k] = b0[k];
@@ -256,6 +339,9 @@ __global__ __launch_bounds__(256) void k_input_layer(const void* __restrict__ xi
             float acc = s_w[d1 * d0 + o];
             for (int32_t c = 0; c < d0; ++c) acc = fmaf(s_w[o * d0 + c], x[c], acc);
             v[e] = (bf16)first_act(acc, omega0);
+            // kept for the backward pass: the sine's derivative, as the
+            // backward epilogue would recompute it
+            if (dsin && omega0 > 0.0f) dsin[s * d1 + o] = omega0 * cosf(omega0 * acc);
         }
         *reinterpret_cast<bf16x8*>(H1 + s * d1 + o0) = v;
     }
@@ -450,7 +536,7 @@ __global__ void k_input_grad_sum(const float* __restrict__ part, int32_t splits,
 // bias gradient from the column partials pb [z][rows] (the next rows threads).
 __global__ void k_sum_grads(const float* __restrict__ pw, int32_t wsplits, int64_t zstride, int32_t rows,
                             int32_t cols, int64_t ldp, float* __restrict__ gw, const float* __restrict__ pb,
-                            int32_t bsplits, float* __restrict__ gb) {
+                            int32_t bsplits, int64_t ldpb, float* __restrict__ gb) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nw = (int64_t)rows * cols;
     if (t < nw) {
@@ -463,7 +549,7 @@ __global__ void k_sum_grads(const float* __restrict__ pw, int32_t wsplits, int64
         const int32_t o = (int32_t)(t - nw);
         float acc = 0.0f;
 #pragma unroll 8
-        for (int32_t z = 0; z < bsplits; ++z) acc += pb[(int64_t)z * rows + o];
+        for (int32_t z = 0; z < bsplits; ++z) acc += pb[(int64_t)z * ldpb + o];
         gb[o] = acc;
     }
 }
@@ -487,6 +573,16 @@ __global__ void k_weights_bf16(const float* __restrict__ W, int32_t d, int32_t d
     if (t >= (int64_t)dp * din) return;
     const int32_t o = (int32_t)(t / din);
     Wb[t] = (bf16)(o < d ? W[t] : 0.0f);
+}
+
+// FP32 master weights W [d][din] -> BF16 transposed copy [din][dp], columns
+// d..dp-1 zero (the fused training step's k-contiguous fragments).
+__global__ void k_weights_bf16_t(const float* __restrict__ W, int32_t d, int32_t dp, int32_t din,
+                                 bf16* __restrict__ Wt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)dp * din) return;
+    const int32_t i = (int32_t)(t / dp), o = (int32_t)(t - (int64_t)i * dp);
+    Wt[t] = (bf16)(o < d ? W[(int64_t)o * din + i] : 0.0f);
 }
 
 // Loss of a batch and its gradient with respect to the outputs.  Per sample s
@@ -584,6 +680,443 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
         if (i >= cp.off[l] && i < cp.off[l] + cp.cnt[l]) cp.dst[l][i - cp.off[l]] = (bf16)pi;
 }
 
+// ---------------------------------------------------------------------------
+// Fused training step of the surrogate's shape (3 inputs, three hidden layers
+// of 256, 37 outputs padded to 64): four kinds of launch per step instead of
+// about twenty.
+//  1. k_train_forward: per block of kTrainRows rows, the input layer and the
+//     three matrix-core layers with the activations in LDS (the arithmetic of
+//     k_mlp_infer_fused), then the loss and its gradient in the output
+//     layer's epilogue (the arithmetic of k_loss).  It writes the activations
+//     row-major (the ReLU masks of the backward pass) and transposed (the
+//     weight gradients' k-contiguous operands), the sine's derivative, the
+//     BF16 output gradient in both layouts, and the block's loss sum.
+//  2. k_train_backward: per block, the gradient through the three layers with
+//     the gradients in LDS and the weights' transposed BF16 copies as
+//     k-contiguous fragments; it writes each layer's gradient transposed and
+//     the block's sums for the bias gradients and the input layer's gradient.
+//  3. the three weight-gradient products (k_gemm, split over the batch);
+//  4. k_sum_adam: every parameter's gradient summed from its partials in a
+//     fixed order, the Adam step, and both BF16 copies of the weights.
+constexpr int kTrainRows = 32, kTW = 256, kTPitch = kTW + 8;
+
+struct TrainFwdArgs {
+    const float* x;            // [B][3]
+    int64_t B;
+    float omega0;
+    const float* W0;           // [256][3] FP32
+    const float* b0;
+    const bf16* W1;            // [256][256]
+    const float* b1;
+    const bf16* W2;
+    const float* b2;
+    const bf16* W3;            // [64][256], rows 37..63 zero
+    const float* b3;
+    const float* tr;           // [B][36]
+    const float* tf;           // [B]
+    float delta;
+    bf16* h1; bf16* h2; bf16* h3;      // [B][256]
+    bf16* h1t; bf16* h2t; bf16* h3t;   // [256][ldt]
+    int64_t ldt;
+    float* dsin;               // [B][256] (sine first layer only)
+    bf16* gout;                // [B][64]
+    bf16* goutt;               // [64][ldt]
+    float* lpart;              // [gridDim.x]
+};
+
+// A block's activations sH [kTrainRows][kTPitch] to global memory, row-major
+// [B][256] and transposed [256][ldt].
+__device__ __forceinline__ void store_acts(const bf16* sH, int64_t r0, int32_t rows, int64_t B, bf16* h,
+                                           bf16* ht, int64_t ldt, int tid) {
+    for (int u = tid; u < kTrainRows * (kTW / 8); u += 256) {
+        const int r = u / (kTW / 8), c = (u % (kTW / 8)) * 8;
+        if (r < rows) *reinterpret_cast<bf16x8*>(h + (r0 + r) * kTW + c) = *reinterpret_cast<const bf16x8*>(sH + r * kTPitch + c);
+    }
+    for (int u = tid; u < kTW * (kTrainRows / 8); u += 256) {
+        const int o = u / (kTrainRows / 8), rc = (u % (kTrainRows / 8)) * 8;
+        bf16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = sH[(rc + e) * kTPitch + o];
+        bf16* d = ht + (int64_t)o * ldt + r0 + rc;
+        if (r0 + rc + 8 <= B) {
+            *reinterpret_cast<bf16x8*>(d) = v;
+        } else {
+            for (int e = 0; e < 8 && r0 + rc + e < B; ++e) d[e] = v[e];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_train_forward(TrainFwdArgs a) {
+    constexpr int TM = kTrainRows / 16;  // MFMA row tiles per wave
+    __shared__ __attribute__((aligned(16))) bf16 sH[kTrainRows * kTPitch];
+    __shared__ float s_w0[kTW * 4];
+    __shared__ float s_red[256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    for (int k = tid; k < kTW * 3; k += 256) s_w0[k] = a.W0[k];
+    for (int k = tid; k < kTW; k += 256) s_w0[kTW * 3 + k] = a.b0[k];
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * kTrainRows;
+    const int32_t rows = (int32_t)min((int64_t)kTrainRows, a.B - r0);
+    // input layer (k_input_layer's arithmetic): thread -> row tid / 8, 32 columns
+    {
+        const int row = tid >> 3, c0 = (tid & 7) * 32;
+        float x[3] = {0.f, 0.f, 0.f};
+        if (row < rows)
+            for (int c = 0; c < 3; ++c) x[c] = a.x[(r0 + row) * 3 + c];
+        for (int q = 0; q < 4; ++q) {
+            bf16x8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int o = c0 + 8 * q + e;
+                float acc = s_w0[kTW * 3 + o];
+                for (int c = 0; c < 3; ++c) acc = fmaf(s_w0[o * 3 + c], x[c], acc);
+                v[e] = (bf16)first_act(acc, a.omega0);
+                if (a.dsin && row < rows) a.dsin[(r0 + row) * kTW + o] = a.omega0 * cosf(a.omega0 * acc);
+            }
+            *reinterpret_cast<bf16x8*>(sH + row * kTPitch + c0 + 8 * q) = v;
+        }
+    }
+    __syncthreads();
+    store_acts(sH, r0, rows, a.B, a.h1, a.h1t, a.ldt, tid);
+    // hidden layers: wave w -> columns 64 w .. 64 w + 63 of every row
+    for (int layer = 0; layer < 2; ++layer) {
+        const bf16* Wl = layer == 0 ? a.W1 : a.W2;
+        const float* bl = layer == 0 ? a.b1 : a.b2;
+        f32x4 acc[TM][4];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        bf16x8 fb[4], fbn[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            fb[j] = *reinterpret_cast<const bf16x8*>(Wl + (int64_t)(64 * w + 16 * j + fr) * kTW + fk);
+        for (int k0 = 0; k0 < kTW; k0 += kDepth) {
+            if (k0 + kDepth < kTW) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    fbn[j] = *reinterpret_cast<const bf16x8*>(Wl + (int64_t)(64 * w + 16 * j + fr) * kTW + k0 + kDepth + fk);
+            }
+            bf16x8 fa[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                fa[i] = *reinterpret_cast<const bf16x8*>(sH + (16 * i + fr) * kTPitch + k0 + fk);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) fb[j] = fbn[j];
+        }
+        __syncthreads();  // every wave has read the layer's input
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int mm = 16 * i + (lane >> 4) * 4 + e, n = 64 * w + 16 * j + fr;
+                    sH[mm * kTPitch + n] = (bf16)fmaxf(acc[i][j][e] + bl[n], 0.0f);
+                }
+        __syncthreads();
+        store_acts(sH, r0, rows, a.B, layer == 0 ? a.h2 : a.h3, layer == 0 ? a.h2t : a.h3t, a.ldt, tid);
+    }
+    // output layer (64 columns, wave w -> 16 w .. 16 w + 15), then the loss
+    // and its gradient (k_loss's arithmetic) in the epilogue
+    float ls = 0.0f;
+    {
+        f32x4 acc[TM];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < kTW; k0 += kDepth) {
+            const bf16x8 fb = *reinterpret_cast<const bf16x8*>(a.W3 + (int64_t)(16 * w + fr) * kTW + k0 + fk);
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const bf16x8 fa = *reinterpret_cast<const bf16x8*>(sH + (16 * i + fr) * kTPitch + k0 + fk);
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i], 0, 0, 0);
+            }
+        }
+        const int32_t R = 36;
+        const float invR = 1.0f / (float)R, invB = 1.0f / (float)a.B;
+        const int n = 16 * w + fr;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int mb = 16 * i + (lane >> 4) * 4;
+            bf16 gv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int mm = mb + e;
+                float g = 0.0f;
+                if (mm < rows) {
+                    const int64_t srow = r0 + mm;
+                    const float z = acc[i][e] + a.b3[n < 37 ? n : 0];
+                    if (n < R) {
+                        const float t = a.tr[srow * R + n];
+                        if (t > 0.0f) {
+                            const float er = z - t, ae = fabsf(er);
+                            ls += (ae <= a.delta ? 0.5f * er * er : a.delta * (ae - 0.5f * a.delta)) * invR;
+                            g = (ae <= a.delta ? er : copysignf(a.delta, er)) * invR;
+                        }
+                    } else if (n == R) {
+                        const float f = a.tf[srow];
+                        ls += fmaxf(z, 0.0f) - z * f + log1pf(expf(-fabsf(z)));
+                        g = 1.0f / (1.0f + expf(-z)) - f;
+                    }
+                    g *= invB;
+                    a.gout[srow * 64 + n] = (bf16)g;
+                }
+                gv[e] = (bf16)g;
+            }
+            bf16* d = a.goutt + (int64_t)n * a.ldt + r0 + mb;
+            if (mb + 3 < rows) {
+                typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                *reinterpret_cast<bf16x4*>(d) = bf16x4{gv[0], gv[1], gv[2], gv[3]};
+            } else {
+                for (int e = 0; e < 4; ++e)
+                    if (mb + e < rows) d[e] = gv[e];
+            }
+        }
+    }
+    s_red[tid] = ls;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) s_red[tid] += s_red[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) a.lpart[blockIdx.x] = s_red[0];
+}
+
+struct TrainBwdArgs {
+    int64_t B;
+    int64_t ldt;
+    float omega0;
+    const bf16* gout;          // [B][64]
+    const bf16* W3t;           // [256][64]
+    const bf16* W2t;           // [256][256]
+    const bf16* W1t;           // [256][256]
+    const bf16* h1; const bf16* h2; const bf16* h3;  // [B][256]
+    const float* dsin;         // [B][256] or null (ReLU first layer)
+    const float* x;            // [B][3]
+    bf16* g3t; bf16* g2t;      // [256][ldt]: gradients of layers 3 and 2's pre-activations, transposed
+    float* pb3;                // [nblk][64]: sums of the output gradient (output bias)
+    float* pb2;                // [nblk][256]
+    float* pb1;                // [nblk][256]
+    float* p0;                 // [nblk][256][4]: sum G1 x_c (c < 3), sum G1
+};
+
+// One backward layer of a block: C [kTrainRows][256] = A [rows][K] (LDS,
+// pitch lda) x Wt[n][k] (global, k-contiguous), then the derivative of the
+// activation below: the ReLU mask of Hm (row-major [B][256]) or the sine's
+// stored derivative dsin.  Results rounded to BF16 go to sOut (LDS, pitch
+// kTPitch, when non-null) and transposed to gt (when non-null); each wave's
+// column sums of the rounded values over the block's rows go to pb; with x,
+// also the input layer's sums p0.
+template <int K>
+__device__ __forceinline__ void train_back_layer(const bf16* sA, int lda, const bf16* __restrict__ Wt,
+                                                 const bf16* __restrict__ Hm, const float* __restrict__ dsin,
+                                                 bf16* sOut, bf16* __restrict__ gt, int64_t ldt, float* __restrict__ pb,
+                                                 const float* sx, float* __restrict__ p0, int64_t r0, int32_t rows,
+                                                 int lane, int w) {
+    constexpr int TM = kTrainRows / 16;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    f32x4 acc[TM][4];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 fb[4], fbn[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) fb[j] = *reinterpret_cast<const bf16x8*>(Wt + (int64_t)(64 * w + 16 * j + fr) * K + fk);
+    for (int k0 = 0; k0 < K; k0 += kDepth) {
+        if (k0 + kDepth < K) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                fbn[j] = *reinterpret_cast<const bf16x8*>(Wt + (int64_t)(64 * w + 16 * j + fr) * K + k0 + kDepth + fk);
+        }
+        bf16x8 fa[TM];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) fa[i] = *reinterpret_cast<const bf16x8*>(sA + (16 * i + fr) * lda + k0 + fk);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fb[j] = fbn[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int n = 64 * w + 16 * j + fr;
+        float cs = 0.0f, cx[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int mb = 16 * i + (lane >> 4) * 4;
+            bf16 r[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int mm = mb + e;
+                r[e] = (bf16)0.0f;
+                if (mm < rows) {
+                    const float v = acc[i][j][e];
+                    if (dsin) {
+                        r[e] = (bf16)(v * dsin[(r0 + mm) * kTW + n]);
+                    } else {
+                        const float h = (float)Hm[(r0 + mm) * kTW + n];
+                        r[e] = (bf16)(h > 0.0f ? v : 0.0f);
+                    }
+                }
+                const float rv = (float)r[e];
+                cs += rv;
+                if (p0) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) cx[c] = fmaf(rv, sx[mm * 4 + c], cx[c]);
+                }
+                if (sOut) sOut[mm * kTPitch + n] = r[e];
+            }
+            if (gt) {
+                bf16* d = gt + (int64_t)n * ldt + r0 + mb;
+                if (mb + 3 < rows) {
+                    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                    *reinterpret_cast<bf16x4*>(d) = bf16x4{r[0], r[1], r[2], r[3]};
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (mb + e < rows) d[e] = r[e];
+                }
+            }
+        }
+        // the four lane groups hold the other rows of column n
+        cs += __shfl_xor(cs, 16, 64);
+        cs += __shfl_xor(cs, 32, 64);
+        if (p0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cx[c] += __shfl_xor(cx[c], 16, 64);
+                cx[c] += __shfl_xor(cx[c], 32, 64);
+            }
+        }
+        if (lane < 16) {
+            if (p0) {
+                p0[(int64_t)n * 4 + 0] = cx[0];
+                p0[(int64_t)n * 4 + 1] = cx[1];
+                p0[(int64_t)n * 4 + 2] = cx[2];
+                p0[(int64_t)n * 4 + 3] = cs;
+            } else {
+                pb[n] = cs;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_train_backward(TrainBwdArgs a) {
+    __shared__ __attribute__((aligned(16))) bf16 sA[kTrainRows * kTPitch];
+    __shared__ __attribute__((aligned(16))) bf16 sB[kTrainRows * kTPitch];
+    __shared__ float s_x[kTrainRows * 4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * kTrainRows;
+    const int32_t rows = (int32_t)min((int64_t)kTrainRows, a.B - r0);
+    const int64_t blk = blockIdx.x;
+    // the output gradient [rows][64] into sA (pitch 72), zero beyond the batch
+    constexpr int kGP = 72;
+    for (int u = tid; u < kTrainRows * 8; u += 256) {
+        const int r = u >> 3, c = (u & 7) * 8;
+        bf16x8 v = bf16x8{};
+        if (r < rows) v = *reinterpret_cast<const bf16x8*>(a.gout + (r0 + r) * 64 + c);
+        *reinterpret_cast<bf16x8*>(sA + r * kGP + c) = v;
+    }
+    for (int u = tid; u < kTrainRows * 4; u += 256) {
+        const int r = u >> 2, c = u & 3;
+        s_x[u] = (r < rows && c < 3) ? a.x[(r0 + r) * 3 + c] : 0.0f;
+    }
+    __syncthreads();
+    // output bias: column sums of the output gradient
+    if (tid < 64) {
+        float cs = 0.0f;
+        for (int r = 0; r < kTrainRows; ++r) cs += (float)sA[r * kGP + tid];
+        a.pb3[blk * 64 + tid] = cs;
+    }
+    // layer 3: G3 = (Gout W3) . [H3 > 0] -> sB, G3^T; bias of the third hidden layer's input
+    train_back_layer<64>(sA, kGP, a.W3t, a.h3, nullptr, sB, a.g3t, a.ldt, a.pb2 + blk * kTW, nullptr, nullptr,
+                         r0, rows, lane, w);
+    __syncthreads();
+    // layer 2: G2 = (G3 W2) . [H2 > 0] -> sA, G2^T
+    train_back_layer<kTW>(sB, kTPitch, a.W2t, a.h2, nullptr, sA, a.g2t, a.ldt, a.pb1 + blk * kTW, nullptr,
+                          nullptr, r0, rows, lane, w);
+    __syncthreads();
+    // layer 1: G1 = (G2 W1) . act'(z1); the input layer's sums
+    train_back_layer<kTW>(sA, kTPitch, a.W1t, a.h1, a.dsin, nullptr, nullptr, a.ldt, nullptr, s_x,
+                          a.p0 + blk * kTW * 4, r0, rows, lane, w);
+}
+
+struct SumAdamArgs {
+    float* p; float* g; float* m; float* v;
+    int64_t n;
+    float lr, b1, b2, eps, c1, c2;
+    int64_t woff[4], boff[4];
+    int32_t din[4], dout[4], dpad[4];   // per layer l: inputs, outputs, padded outputs
+    const float* wpart[4];     // l = 1..3: [wsplits][dpad][din]
+    int32_t wsplits;
+    const float* bpart[4];     // l = 1..3: [nblk][bw[l]] (bias of layer l)
+    int32_t bw[4];
+    const float* p0;           // [nblk][256][4]
+    int32_t nblk;
+    bf16* wb[4]; bf16* wbt[4];
+    const float* lpart; float* loss; int64_t B;
+};
+
+// Thread i: parameter i's gradient from its partials (fixed order), Adam, and
+// the BF16 copies; block 0 also sums the loss partials (k_loss_total's way).
+__global__ __launch_bounds__(256) void k_sum_adam(SumAdamArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && a.loss) {
+        __shared__ double s_sum[256];
+        double acc = 0.0;
+        for (int32_t k = (int32_t)threadIdx.x; k < a.nblk; k += 256) acc += a.lpart[k];
+        s_sum[threadIdx.x] = acc;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) s_sum[threadIdx.x] += s_sum[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *a.loss = (float)(s_sum[0] / (double)a.B);
+    }
+    if (i >= a.n) return;
+    int l = 3;
+    while (l > 0 && i < a.woff[l]) --l;
+    float gi = 0.0f;
+    if (i < a.boff[l]) {  // weight W_l[o][c]
+        const int64_t k = i - a.woff[l];
+        const int32_t o = (int32_t)(k / a.din[l]), c = (int32_t)(k - (int64_t)o * a.din[l]);
+        if (l == 0) {
+            for (int32_t b = 0; b < a.nblk; ++b) gi += a.p0[((int64_t)b * 256 + o) * 4 + c];
+        } else {
+            const int64_t zs = (int64_t)a.dpad[l] * a.din[l];
+            for (int32_t z = 0; z < a.wsplits; ++z) gi += a.wpart[l][z * zs + (int64_t)o * a.din[l] + c];
+        }
+    } else {  // bias b_l[o]
+        const int32_t o = (int32_t)(i - a.boff[l]);
+        if (l == 0) {
+            for (int32_t b = 0; b < a.nblk; ++b) gi += a.p0[((int64_t)b * 256 + o) * 4 + 3];
+        } else {
+            for (int32_t b = 0; b < a.nblk; ++b) gi += a.bpart[l][(int64_t)b * a.bw[l] + o];
+        }
+    }
+    a.g[i] = gi;
+    const float mi = a.b1 * a.m[i] + (1.0f - a.b1) * gi;
+    const float vi = a.b2 * a.v[i] + (1.0f - a.b2) * gi * gi;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    const float pi = a.p[i] - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
+    a.p[i] = pi;
+    if (l > 0 && i < a.boff[l]) {
+        const int64_t k = i - a.woff[l];
+        const int32_t o = (int32_t)(k / a.din[l]), c = (int32_t)(k - (int64_t)o * a.din[l]);
+        a.wb[l][k] = (bf16)pi;
+        a.wbt[l][(int64_t)c * a.dpad[l] + o] = (bf16)pi;
+    }
+}
+
 // Training rows from a table of the whole cube: x = RGB / 255 - 1/2 of colour
 // id, radius targets ridx * dr / 50 per bin (0 = no valid radius), feasibility
 // = count > 0.
@@ -669,10 +1202,18 @@ struct cv_mlp {
     float* adam_m = nullptr;
     float* adam_v = nullptr;
     bf16* wb[cvib::kMaxLayers] = {};    // BF16 W_l, l >= 1, [dpad_{l+1}][d_l]
+    bf16* wbt[cvib::kMaxLayers] = {};   // BF16 W_l transposed, l >= 1, [d_l][dpad_{l+1}] (fused training)
     int64_t bcap = 0;                   // rows of the activation buffers
     bf16* h[cvib::kMaxLayers] = {};     // post-ReLU H_l, l = 1..L-1, [bcap][d_l]
     bf16* g[2] = {nullptr, nullptr};    // back-propagated gradients [bcap][gw]
     int32_t gw = 0;                     // widest padded layer
+    // k-contiguous copies for the weight-gradient products, rows of length ldt
+    // (the kept batch rounded up to 8): H_l transposed [d_l][ldt] and the
+    // back-propagated gradients transposed [gw][ldt]
+    bf16* ht[cvib::kMaxLayers] = {};
+    bf16* gt[3] = {nullptr, nullptr, nullptr};
+    int64_t ldt = 0;
+    float* dsin = nullptr;              // sinusoidal first layer: omega0 cos(omega0 z) [bcap][d1]
     float* part = nullptr;              // split partials
     size_t part_bytes = 0;
     float* lpart = nullptr;             // loss partials
@@ -685,6 +1226,8 @@ struct cv_mlp {
     float* ttf = nullptr;   // [tcap]
     float* tout = nullptr;  // [tcap][37]
     float* tloss = nullptr; // [1]: loss of a step that is not logged
+    float* fpart = nullptr;  // fused training step: per-block bias, input-layer and loss partials
+    size_t fpart_bytes = 0;
 };
 
 namespace cvib {
@@ -716,10 +1259,25 @@ int ensure_rows(cv_mlp* m, int64_t rows) {
         if (q) CV_HIP(hipFree(q));
         q = nullptr;
     }
+    for (int l = 1; l < m->L; ++l) {
+        if (m->ht[l]) CV_HIP(hipFree(m->ht[l]));
+        m->ht[l] = nullptr;
+    }
+    for (bf16*& q : m->gt) {
+        if (q) CV_HIP(hipFree(q));
+        q = nullptr;
+    }
+    if (m->dsin) CV_HIP(hipFree(m->dsin));
+    m->dsin = nullptr;
     m->bcap = 0;
-    for (int l = 1; l < m->L; ++l)
+    const size_t r8 = (size_t)((rows + 7) / 8 * 8);
+    for (int l = 1; l < m->L; ++l) {
         CV_HIP(hipMalloc((void**)&m->h[l], (size_t)rows * m->dims[l] * sizeof(bf16)));
+        CV_HIP(hipMalloc((void**)&m->ht[l], r8 * m->dims[l] * sizeof(bf16)));
+    }
     for (bf16*& q : m->g) CV_HIP(hipMalloc((void**)&q, (size_t)rows * m->gw * sizeof(bf16)));
+    for (bf16*& q : m->gt) CV_HIP(hipMalloc((void**)&q, r8 * m->gw * sizeof(bf16)));
+    CV_HIP(hipMalloc((void**)&m->dsin, (size_t)rows * m->dims[1] * sizeof(float)));
     m->bcap = rows;
     return CV_OK;
 }
@@ -728,18 +1286,62 @@ int ensure_part(cv_mlp* m, size_t bytes) {
     return grow((void**)&m->part, &m->part_bytes, bytes);
 }
 
+// dst [cols][ldd] = src [rows][lds] transposed, through 64 x 64 LDS tiles:
+// rows read and written 16 bytes per thread (lds, ldd and cols multiples of 8).
+__global__ __launch_bounds__(256) void k_transpose_bf16(const bf16* __restrict__ src, int64_t rows, int32_t cols,
+                                                        int64_t lds, bf16* __restrict__ dst, int64_t ldd) {
+    __shared__ bf16 t[64][72];
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int32_t c0 = (int32_t)blockIdx.y * 64;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int u = threadIdx.x + 256 * q, r = u >> 3, c = (u & 7) * 8;
+        bf16x8 v = bf16x8{};
+        if (r0 + r < rows && c0 + c < cols) v = *reinterpret_cast<const bf16x8*>(src + (r0 + r) * lds + c0 + c);
+        *reinterpret_cast<bf16x8*>(&t[r][c]) = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int u = threadIdx.x + 256 * q, c = u >> 3, r = (u & 7) * 8;  // dst row c, columns r .. r + 7
+        if (c0 + c >= cols || r0 + r >= rows) continue;
+        bf16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = t[r + e][c];
+        bf16* d = dst + (int64_t)(c0 + c) * ldd + r0 + r;
+        if (r0 + r + 8 <= rows) {
+            *reinterpret_cast<bf16x8*>(d) = v;
+        } else {
+            for (int e = 0; e < 8 && r0 + r + e < rows; ++e) d[e] = v[e];
+        }
+    }
+}
+
+int transpose_bf16(const bf16* src, int64_t rows, int32_t cols, int64_t lds, bf16* dst, int64_t ldd,
+                   hipStream_t s) {
+    if (rows == 0) return CV_OK;
+    if (lds % 8 || ldd % 8 || cols % 8) return fail(CV_ESTATE, "internal: transpose alignment");
+    hipLaunchKernelGGL(k_transpose_bf16, dim3((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64)),
+                       dim3(256), 0, s, src, rows, cols, lds, dst, ldd);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
 int refresh_bf16(cv_mlp* m, hipStream_t s) {
     for (int l = 1; l < m->L; ++l) {
         const int64_t n = (int64_t)m->dpad[l + 1] * m->dims[l];
         hipLaunchKernelGGL(k_weights_bf16, dim3(blocks(n, 256)), dim3(256), 0, s,
                            m->params + m->woff[l], m->dims[l + 1], m->dpad[l + 1], m->dims[l], m->wb[l]);
+        hipLaunchKernelGGL(k_weights_bf16_t, dim3(blocks(n, 256)), dim3(256), 0, s,
+                           m->params + m->woff[l], m->dims[l + 1], m->dpad[l + 1], m->dims[l], m->wbt[l]);
     }
     CV_HIP(hipGetLastError());
     return CV_OK;
 }
 
 // Hidden layers and the output layer for rows already in H_1.
-int forward_tail(cv_mlp* m, bf16* const* H, int64_t rows, float* out, hipStream_t s) {
+int forward_tail(cv_mlp* m, bf16* const* H, bf16* const* Ht, int64_t ldt, int64_t rows, float* out,
+                 hipStream_t s) {
     int rc;
     for (int l = 1; l < m->L; ++l) {
         GemmArgs a = {};
@@ -756,6 +1358,8 @@ int forward_tail(cv_mlp* m, bf16* const* H, int64_t rows, float* out, hipStream_
         if (l + 1 < m->L) {
             a.cb = H[l + 1];
             a.ldc = m->dims[l + 1];
+            a.cbt = Ht ? Ht[l + 1] : nullptr;
+            a.ldct = ldt;
             rc = gemm<true, true, EPI_RELU_BF16>(a, 1, s);
         } else {
             a.cf = out;
@@ -797,50 +1401,67 @@ int run_forward(cv_mlp* m, const void* x, bool rgb8, int64_t rows, float* out, b
         const void* xs = rgb8 ? (const void*)((const uint8_t*)x + r0 * 3)
                               : (const void*)((const float*)x + r0 * m->dims[0]);
         const unsigned ib = blocks(nr * (m->dims[1] / 8), 256);
+        // a kept pass also writes what the weight-gradient products read:
+        // the activations transposed and the sine's derivative
+        float* ds = keep ? m->dsin : nullptr;
+        const int64_t ldt = (nr + 7) / 8 * 8;
         if (rgb8)
             hipLaunchKernelGGL(k_input_layer<true>, dim3(ib), dim3(256), 0, s, xs, nr, m->dims[0],
-                               m->dims[1], m->params + m->woff[0], m->params + m->boff[0], m->omega0, m->h[1]);
+                               m->dims[1], m->params + m->woff[0], m->params + m->boff[0], m->omega0, m->h[1],
+                               ds);
         else
             hipLaunchKernelGGL(k_input_layer<false>, dim3(ib), dim3(256), 0, s, xs, nr, m->dims[0],
-                               m->dims[1], m->params + m->woff[0], m->params + m->boff[0], m->omega0, m->h[1]);
+                               m->dims[1], m->params + m->woff[0], m->params + m->boff[0], m->omega0, m->h[1],
+                               ds);
         CV_HIP(hipGetLastError());
-        if ((rc = forward_tail(m, m->h, nr, out + r0 * m->dims[m->L], s)) != CV_OK) return rc;
+        if (keep && (rc = transpose_bf16(m->h[1], nr, m->dims[1], m->dims[1], m->ht[1], ldt, s)) != CV_OK)
+            return rc;
+        if ((rc = forward_tail(m, m->h, keep ? m->ht : nullptr, ldt, nr, out + r0 * m->dims[m->L], s)) != CV_OK)
+            return rc;
     }
     m->fwd_rows = keep ? rows : -1;
+    m->ldt = keep ? (rows + 7) / 8 * 8 : 0;
     return CV_OK;
 }
 
 // gout: FP32 [B][dims_L]; or nullptr when run_loss has already put the BF16
-// gradient in g[0].
+// gradient in g[0].  The weight gradients take k-contiguous operands: the
+// kept activations transposed (forward pass) and the back-propagated
+// gradients transposed (each layer's epilogue writes both layouts); the
+// blocks of a weight-gradient product's first column tile also sum the
+// gradient over their rows, which gives the bias gradient's split partials.
 int run_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, hipStream_t s) {
     int rc;
     const int32_t L = m->L;
+    const int64_t ldt = m->ldt;
+    if (ldt < B) return fail(CV_ESTATE, "internal: no transposed activations for this batch");
     const int32_t splits = (int32_t)((B + kSplitRows - 1) / kSplitRows);
-    const int32_t csplits = (int32_t)((B + kColRows - 1) / kColRows);  // column reductions
-    // partials: a layer's weight partials followed by its column partials
-    size_t need = 0;
-    for (int l = 0; l < L; ++l) {
-        const size_t w = (size_t)splits * m->dpad[l + 1] * (l == 0 ? 0 : m->dims[l]);
-        const size_t c = (size_t)csplits * m->dpad[l + 1] * (l == 0 ? (m->dims[0] + 1) : 1);
-        need = std::max(need, w + c);
-    }
+    const int32_t csplits = (int32_t)((B + kColRows - 1) / kColRows);  // input layer column reductions
+    // partials: a layer's weight partials followed by its bias partials
+    size_t need = (size_t)csplits * m->dpad[1] * (m->dims[0] + 1);
+    for (int l = 1; l < L; ++l)
+        need = std::max(need, (size_t)splits * m->dpad[l + 1] * (m->dims[l] + 1));
     if ((rc = ensure_part(m, need * sizeof(float))) != CV_OK) return rc;
     bf16* Gc = m->g[0];  // gradient w.r.t. the pre-activations of layer l's output
     bf16* Gn = m->g[1];
+    bf16* Gct = m->gt[0];  // the same, transposed [dpad][ldt]
+    bf16* Gnt = m->gt[1];
     if (gout) {
         hipLaunchKernelGGL(k_grad_to_bf16, dim3(blocks(B * m->dpad[L], 256)), dim3(256), 0, s, gout, B,
                            m->dims[L], m->dpad[L], Gc);
         CV_HIP(hipGetLastError());
     }
+    if ((rc = transpose_bf16(Gc, B, m->dpad[L], m->dpad[L], Gct, ldt, s)) != CV_OK) return rc;
     int32_t ldg = m->dpad[L];
     for (int l = L - 1; l >= 1; --l) {
         const int32_t dout = m->dims[l + 1], dop = m->dpad[l + 1], din = m->dims[l];
-        // weight gradient: dW_l[o][i] = sum_s G[s][o] H_l[s][i]
+        // weight gradient: dW_l[o][i] = sum_s G[s][o] H_l[s][i], from G^T and H_l^T
+        float* pb = m->part + (size_t)splits * dop * din;
         GemmArgs a = {};
-        a.A = Gc;
-        a.lda = ldg;
-        a.B = m->h[l];
-        a.ldb = din;
+        a.A = Gct;
+        a.lda = ldt;
+        a.B = m->ht[l];
+        a.ldb = ldt;
         a.M = dop;
         a.N = din;
         a.K = (int32_t)B;
@@ -849,16 +1470,13 @@ int run_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, hipStr
         a.ldc = din;
         a.zstride = (int64_t)dop * din;
         a.nstore = din;
-        if ((rc = gemm<false, false, EPI_PARTIAL_F32>(a, splits, s)) != CV_OK) return rc;
-        // bias gradient: column partials after the weight partials, then both sums in one launch
-        float* pb = m->part + (size_t)splits * dop * din;
-        hipLaunchKernelGGL(k_colgrad, dim3((unsigned)((dout + 63) / 64), (unsigned)csplits), dim3(256), 0,
-                           s, Gc, (int64_t)ldg, (const float*)nullptr, 0, B, dout, pb);
+        a.bpart = pb;
+        if ((rc = gemm<true, true, EPI_PARTIAL_F32>(a, splits, s)) != CV_OK) return rc;
         hipLaunchKernelGGL(k_sum_grads, dim3(blocks((int64_t)dout * din + dout, 256)), dim3(256), 0, s,
                            m->part, splits, (int64_t)dop * din, dout, din, (int64_t)din, m->grads + m->woff[l],
-                           pb, csplits, m->grads + m->boff[l]);
+                           pb, splits, (int64_t)dop, m->grads + m->boff[l]);
         CV_HIP(hipGetLastError());
-        // input gradient through W_l and the ReLU of H_l
+        // input gradient through W_l and the ReLU of H_l (or the sine's derivative)
         GemmArgs d = {};
         d.A = Gc;
         d.lda = ldg;
@@ -870,14 +1488,14 @@ int run_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, hipStr
         d.kchunk = dop;
         d.cb = Gn;
         d.ldc = din;
+        d.cbt = l > 1 ? Gnt : nullptr;  // the input layer's gradient is reduced on the vector ALUs
+        d.ldct = ldt;
         d.mask = m->h[l];
         d.ldm = din;
         d.nstore = din;
         if (l == 1 && m->omega0 > 0.0f) {
-            d.x0 = x;
-            d.w0 = m->params + m->woff[0];
-            d.b0 = m->params + m->boff[0];
-            d.d0 = m->dims[0];
+            d.dsin = m->dsin;
+            d.ldd = din;
             d.omega0 = m->omega0;
             rc = gemm<true, false, EPI_SINE_BF16>(d, 1, s);
         } else {
@@ -885,6 +1503,7 @@ int run_backward(cv_mlp* m, const float* x, const float* gout, int64_t B, hipStr
         }
         if (rc != CV_OK) return rc;
         std::swap(Gc, Gn);
+        std::swap(Gct, Gnt);
         ldg = din;
     }
     // input layer
@@ -947,15 +1566,154 @@ int ensure_train(cv_mlp* m, int64_t B) {
     return CV_OK;
 }
 
+// One training step of the surrogate's shape through the fused kernels (see
+// k_train_forward): nb rows of colour ids, loss of the step to *loss.
+int train_step_fused(cv_mlp* m, const int32_t* ids, int64_t nb, const cv_table_row* table, double dr,
+                     float delta, float lr, int64_t t, float* loss, hipStream_t s) {
+    int rc;
+    const int64_t ldt = (nb + 7) / 8 * 8;
+    const int32_t nblk = (int32_t)((nb + kTrainRows - 1) / kTrainRows);
+    const int32_t splits = (int32_t)((nb + kSplitRows - 1) / kSplitRows);
+    // weight partials of the three matrix-core layers side by side
+    const int64_t zw3 = (int64_t)m->dpad[4] * m->dims[3], zw2 = (int64_t)m->dpad[3] * m->dims[2],
+                  zw1 = (int64_t)m->dpad[2] * m->dims[1];
+    if ((rc = ensure_part(m, (size_t)splits * (zw3 + zw2 + zw1) * sizeof(float))) != CV_OK) return rc;
+    const size_t per_blk = 64 + 256 + 256 + 256 * 4 + 1;
+    if ((rc = grow((void**)&m->fpart, &m->fpart_bytes, (size_t)nblk * per_blk * sizeof(float))) != CV_OK) return rc;
+    float* pw3 = m->part;
+    float* pw2 = pw3 + (size_t)splits * zw3;
+    float* pw1 = pw2 + (size_t)splits * zw2;
+    float* pb3 = m->fpart;
+    float* pb2 = pb3 + (size_t)nblk * 64;
+    float* pb1 = pb2 + (size_t)nblk * 256;
+    float* p0 = pb1 + (size_t)nblk * 256;
+    float* lp = p0 + (size_t)nblk * 256 * 4;
+    hipLaunchKernelGGL(k_table_batch, dim3(blocks(nb, 256)), dim3(256), 0, s, ids, table, nb, (float)(dr / 50.0),
+                       m->tx, m->ttr, m->ttf);
+    CV_HIP(hipGetLastError());
+    TrainFwdArgs f;
+    f.x = m->tx;
+    f.B = nb;
+    f.omega0 = m->omega0;
+    f.W0 = m->params + m->woff[0];
+    f.b0 = m->params + m->boff[0];
+    f.W1 = m->wb[1];
+    f.b1 = m->params + m->boff[1];
+    f.W2 = m->wb[2];
+    f.b2 = m->params + m->boff[2];
+    f.W3 = m->wb[3];
+    f.b3 = m->params + m->boff[3];
+    f.tr = m->ttr;
+    f.tf = m->ttf;
+    f.delta = delta;
+    f.h1 = m->h[1];
+    f.h2 = m->h[2];
+    f.h3 = m->h[3];
+    f.h1t = m->ht[1];
+    f.h2t = m->ht[2];
+    f.h3t = m->ht[3];
+    f.ldt = ldt;
+    f.dsin = m->omega0 > 0.0f ? m->dsin : nullptr;
+    f.gout = m->g[0];
+    f.goutt = m->gt[0];
+    f.lpart = lp;
+    hipLaunchKernelGGL(k_train_forward, dim3((unsigned)nblk), dim3(256), 0, s, f);
+    CV_HIP(hipGetLastError());
+    TrainBwdArgs b;
+    b.B = nb;
+    b.ldt = ldt;
+    b.omega0 = m->omega0;
+    b.gout = m->g[0];
+    b.W3t = m->wbt[3];
+    b.W2t = m->wbt[2];
+    b.W1t = m->wbt[1];
+    b.h1 = m->h[1];
+    b.h2 = m->h[2];
+    b.h3 = m->h[3];
+    b.dsin = f.dsin;
+    b.x = m->tx;
+    b.g3t = m->gt[1];
+    b.g2t = m->gt[2];
+    b.pb3 = pb3;
+    b.pb2 = pb2;
+    b.pb1 = pb1;
+    b.p0 = p0;
+    hipLaunchKernelGGL(k_train_backward, dim3((unsigned)nblk), dim3(256), 0, s, b);
+    CV_HIP(hipGetLastError());
+    // weight gradients dW_l[o][i] = sum_s G[s][o] H_l[s][i] from the transposed operands
+    const bf16* As[4] = {nullptr, m->gt[2], m->gt[1], m->gt[0]};
+    float* Ps[4] = {nullptr, pw1, pw2, pw3};
+    for (int l = 1; l <= 3; ++l) {
+        GemmArgs a = {};
+        a.A = As[l];
+        a.lda = ldt;
+        a.B = m->ht[l];
+        a.ldb = ldt;
+        a.M = m->dpad[l + 1];
+        a.N = m->dims[l];
+        a.K = (int32_t)nb;
+        a.kchunk = (int32_t)kSplitRows;
+        a.cf = Ps[l];
+        a.ldc = m->dims[l];
+        a.zstride = (int64_t)m->dpad[l + 1] * m->dims[l];
+        a.nstore = m->dims[l];
+        if ((rc = gemm<true, true, EPI_PARTIAL_F32>(a, splits, s)) != CV_OK) return rc;
+    }
+    SumAdamArgs d;
+    d.p = m->params;
+    d.g = m->grads;
+    d.m = m->adam_m;
+    d.v = m->adam_v;
+    d.n = m->nparam;
+    d.lr = lr;
+    d.b1 = 0.9f;
+    d.b2 = 0.999f;
+    d.eps = 1e-8f;
+    d.c1 = (float)(1.0 / (1.0 - pow(0.9, (double)t)));
+    d.c2 = (float)(1.0 / (1.0 - pow(0.999, (double)t)));
+    for (int l = 0; l < 4; ++l) {
+        d.woff[l] = m->woff[l];
+        d.boff[l] = m->boff[l];
+        d.din[l] = m->dims[l];
+        d.dout[l] = m->dims[l + 1];
+        d.dpad[l] = m->dpad[l + 1];
+        d.wpart[l] = Ps[l];
+        d.wb[l] = m->wb[l];
+        d.wbt[l] = m->wbt[l];
+    }
+    d.wsplits = splits;
+    d.bpart[0] = nullptr;
+    d.bpart[1] = pb1;
+    d.bpart[2] = pb2;
+    d.bpart[3] = pb3;
+    d.bw[0] = 0;
+    d.bw[1] = 256;
+    d.bw[2] = 256;
+    d.bw[3] = 64;
+    d.p0 = p0;
+    d.nblk = nblk;
+    d.lpart = lp;
+    d.loss = loss;
+    d.B = nb;
+    hipLaunchKernelGGL(k_sum_adam, dim3(blocks(m->nparam, 256)), dim3(256), 0, s, d);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
 void free_mlp(cv_mlp* m) {
     void* ps[] = {m->params, m->grads, m->adam_m, m->adam_v, m->g[0], m->g[1], m->part, m->lpart,
-                  m->tx, m->ttr, m->ttf, m->tout, m->tloss};
+                  m->tx, m->ttr, m->ttf, m->tout, m->tloss, m->fpart};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     for (int l = 0; l < kMaxLayers; ++l) {
         if (m->wb[l]) (void)hipFree(m->wb[l]);
+        if (m->wbt[l]) (void)hipFree(m->wbt[l]);
         if (m->h[l]) (void)hipFree(m->h[l]);
+        if (m->ht[l]) (void)hipFree(m->ht[l]);
     }
+    for (bf16* q : m->gt)
+        if (q) (void)hipFree(q);
+    if (m->dsin) (void)hipFree(m->dsin);
     delete m;
 }
 
@@ -1090,8 +1848,10 @@ int cv_mlp_create(cv_context* ctx, const int32_t* dims, int32_t nlayers, cv_mlp*
     float** arrs[] = {&m->params, &m->grads, &m->adam_m, &m->adam_v};
     for (float** a : arrs)
         if (e == hipSuccess) e = hipMalloc((void**)a, pb);
-    for (int l = 1; l < nlayers && e == hipSuccess; ++l)
+    for (int l = 1; l < nlayers && e == hipSuccess; ++l) {
         e = hipMalloc((void**)&m->wb[l], (size_t)m->dpad[l + 1] * dims[l] * sizeof(bf16));
+        if (e == hipSuccess) e = hipMalloc((void**)&m->wbt[l], (size_t)m->dpad[l + 1] * dims[l] * sizeof(bf16));
+    }
     for (float** a : arrs)
         if (e == hipSuccess) e = hipMemset(*a, 0, pb);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -1252,8 +2012,20 @@ int cv_mlp_train_steps(cv_mlp* m, const int32_t* ids, int64_t n, const cv_table_
     if ((rc = cvib::ensure_train(m, B)) != CV_OK) return rc;
     if ((rc = cvib::ensure_rows(m, B)) != CV_OK) return rc;
     const int64_t steps = (n + batch - 1) / batch;
+    const bool fused = cvib::fused_shape(m) && m->dims[4] == 37;
+    if (fused && (rc = cvib::refresh_bf16(m, s)) != CV_OK) return rc;  // the transposed copies follow the parameters
     for (int64_t k = 0; k < steps; ++k) {
         const int64_t r0 = k * batch, nb = std::min(batch, n - r0);
+        if (fused) {
+            const int64_t t = step0 + k;
+            const double frac =
+                total_steps > 1 ? (double)std::min(t, total_steps - 1) / (double)(total_steps - 1) : 0.0;
+            const float lr = (float)(lr_min + 0.5 * (lr_max - lr_min) * (1.0 + cos(M_PI * frac)));
+            float* lp = loss_log ? loss_log + k : m->tloss;
+            if ((rc = cvib::train_step_fused(m, ids + r0, nb, table, dr, huber_delta, lr, t + 1, lp, s)) != CV_OK)
+                return rc;
+            continue;
+        }
         hipLaunchKernelGGL(cvib::k_table_batch, dim3(cvib::blocks(nb, 256)), dim3(256), 0, s, ids + r0,
                            table, nb, (float)(dr / 50.0), m->tx, m->ttr, m->ttf);
         CV_HIP(hipGetLastError());

@@ -588,6 +588,11 @@ struct ReduceArgs {
 // only the open steps of its mask, deriving (i, j) from the step index.
 // Large-chunk blocks of eight waves hold the register budget of six waves per
 // SIMD, so that three blocks share a CU.
+// Coarse cells of the count pass: at most this many 64-ray columns per row and
+// this many listed steps per tile (else every step takes its own proof).
+constexpr int32_t kMaxCols = 256;
+constexpr int32_t kMaxListed = 2048;
+
 template <int BLOCK, bool TABLE, bool DIRECT, bool SYM, bool SEG, bool CELLS>
 __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceArgs a) {
     constexpr int NW = BLOCK / 64;
@@ -597,6 +602,11 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
     __shared__ uint32_t s_bins[36];
     __shared__ uint32_t s_seg[SEG ? MAX_SEG : 1];
     __shared__ int64_t s_tick;
+    // coarse cells of the step proofs (CELLS kernels that deal out steps)
+    constexpr bool LISTS = CELLS && !(DIRECT && !SEG);
+    __shared__ uint8_t s_colv[LISTS ? kMaxCols : 1];
+    __shared__ uint16_t s_list[LISTS ? kMaxListed : 1];
+    __shared__ int32_t s_nlist;
 
     const int tid = threadIdx.x;
     const uint32_t lane = (uint32_t)tid & 63u;
@@ -640,22 +650,73 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
         const int32_t iters = (len + BLOCK - 1) / BLOCK;
         const int32_t nwords = (iters + 63) >> 6;
         if constexpr (CELLS && !(DIRECT && !SEG)) {
-            // Which wave steps hold a candidate that may be in gamut: the
-            // tile's steps (it, wv) are dealt out densely, one per lane; the
-            // 64 evaluations of a step (one or two rows, several when W < 64)
-            // form its cell, and an open step sets its bit in wave wv's mask
-            // (zeroed with the tile's other LDS).
-            for (int32_t s0 = w * 64; s0 < iters * NW; s0 += BLOCK) {
-                const int32_t sidx = s0 + (int32_t)lane;
+            // Which wave steps hold a candidate that may be in gamut.  Step s
+            // = (it, wv) = it NW + wv covers evaluations 64 s .. 64 s + 63 of
+            // the tile (one or two rows, several when W < 64); they form its
+            // cell, and an open step sets its bit in wave wv's mask (zeroed
+            // with the tile's other LDS).
+            // Coarse level first: the tile's rows by 64 consecutive rays
+            // (columns) are proven as a whole, one column per thread; a step
+            // all of whose columns are proven out of gamut (or, without
+            // n_gamut, unable to hold a high channel) needs no proof of its
+            // own.  The other steps are listed and dealt out densely, one per
+            // lane, so that no wave spends a round on closed steps.
+            const int32_t nsteps = iters * NW;
+            const int32_t ncol = (a.W + 63) >> 6;
+            const bool coarse = ncol >= 2 && ncol <= kMaxCols && nsteps <= kMaxListed;
+            const bool need_ng = a.need_ng != 0;
+            int32_t nlisted = nsteps;
+            if (coarse) {
+                const int32_t rlast = row0 + (jb0 + len - 1) / a.W;
+                for (int32_t q = tid; q < ncol; q += BLOCK) {
+                    bool high = true;
+                    const bool out = cell_out_of_gamut(cc, a.g, ang, a.ra, a.rb, row0, rlast, 64 * q,
+                                                       min(64 * q + 63, a.W - 1), &a.rule, &high);
+                    s_colv[q] = out ? 1 : (high ? 0 : 2);  // 1: out of gamut, 2: no high channel
+                }
+                if (tid == 0) s_nlist = 0;
+                __syncthreads();
+                for (int32_t sx = tid; sx < nsteps; sx += BLOCK) {
+                    const int32_t e0 = 64 * sx;
+                    if (e0 >= len) continue;
+                    const int32_t e1 = min(e0 + 63, len - 1);
+                    int32_t ia, ja, ib, jb;
+                    divmod_small(jb0 + e0, a.W, a.inv_W, ia, ja);
+                    divmod_small(jb0 + e1, a.W, a.inv_W, ib, jb);
+                    // columns of the step's candidates: one row, or the end of
+                    // one and the start of the next (64 rays never span more)
+                    uint32_t all = 3u;  // bit 0: every column out; bit 1: every column out or no-high
+                    const int32_t qa = ja >> 6, qb = (ib == ia ? jb : a.W - 1) >> 6;
+                    for (int32_t q = qa; q <= qb; ++q) {
+                        const uint32_t v = s_colv[q];
+                        all &= (v == 1u ? 3u : (v == 2u ? 2u : 0u));
+                    }
+                    if (ib != ia)
+                        for (int32_t q = 0; q <= (jb >> 6); ++q) {
+                            const uint32_t v = s_colv[q];
+                            all &= (v == 1u ? 3u : (v == 2u ? 2u : 0u));
+                        }
+                    if ((all & 1u) || ((all & 2u) && !need_ng)) {
+                        skipped += (uint64_t)(e1 - e0 + 1);
+                    } else {
+                        s_list[atomicAdd(&s_nlist, 1)] = (uint16_t)sx;
+                    }
+                }
+                __syncthreads();
+                nlisted = s_nlist;
+            }
+            for (int32_t s0 = w * 64; s0 < nlisted; s0 += BLOCK) {
+                const int32_t li = s0 + (int32_t)lane;
+                const int32_t sidx = coarse ? (int32_t)s_list[min(li, nlisted - 1)] : li;
                 const int32_t it = sidx / NW, wv = sidx - it * NW;
                 const int32_t e0 = it * BLOCK + wv * 64;
-                const bool any = sidx < iters * NW && e0 < len;
+                const bool any = li < nlisted && e0 < len;
                 const int32_t e1 = min(e0 + 63, len - 1);
                 bool high = true;
                 const bool open = step_open(cc, a.g, ang, a.ra, a.rb, a.W, a.inv_W, row0, jb0, min(e0, len - 1),
                                             e1, any, SYM, &a.rule, &high);
                 // without n_gamut, a step without a high channel needs nothing
-                const bool take = open && (high || a.need_ng != 0);
+                const bool take = open && (high || need_ng);
                 if (any && !take) skipped += (uint64_t)(e1 - e0 + 1);
                 if (take)
                     atomicOr((unsigned long long*)&s_open[wv * a.cell_words + (it >> 6)], 1ull << (it & 63));

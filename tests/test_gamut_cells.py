@@ -13,8 +13,8 @@ mathematical statement:
 - a linear channel A f^-1(fx) + C f^-1(fz) + B is bounded term by term.
 Three properties are checked on several hundred blocks of the shapes the
 kernels use (one or two rows of 64 rays, the mirrored range of a half-turn
-row crossing, 16 rows by 4 rays, several whole rows, and blocks of 256
-rays, one row or a crossing):
+row crossing, 16 rows by 4 rays, several whole rows, up to 24 rows by 64
+rays, and blocks of 256 rays, one row or a crossing):
 - containment: every linear channel of both colours of every candidate
   (FP64 oracle) lies inside the block's intervals -- any narrowing fails it,
   whatever the gamut's shape;
@@ -116,6 +116,11 @@ def _blocks(rng, nr, W_):
         b = int(rng.integers(0, nr // 16)); j0 = int(rng.integers(0, W_ - 4))
         out.append(("band", (16 * b, 16 * b + 15, j0, j0 + 3),
                     [(16 * b + q, j) for q in range(16) for j in range(j0, j0 + 4)]))
+    for _ in range(30):
+        # the count pass's coarse cells: the rows of a tile by 64 rays
+        i0 = int(rng.integers(0, nr - 24)); i1 = i0 + int(rng.integers(1, 24))
+        j0 = 64 * int(rng.integers(0, (W_ - 1) // 64 + 1)); j1 = min(j0 + 63, W_ - 1)
+        out.append(("column", (i0, i1, j0, j1), [(i, j) for i in range(i0, i1 + 1) for j in range(j0, j1 + 1)]))
     if W_ > 256:
         # blocks of 256 evaluations: one row, or a half-turn crossing in
         # mirrored form

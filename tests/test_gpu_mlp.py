@@ -238,35 +238,63 @@ def test_backward_needs_kept_forward(cv):
         m.backward(x, g)
 
 
-def test_train_steps_equals_single_calls(cv):
-    """The library's training loop does what the single calls do: table batch,
-    kept forward, loss, backward, Adam with the cosine rate.  Losses agree bit
-    for bit; parameters within a few units in the last place, since the host's
-    cos in the rate schedule may round differently from Python's."""
+@pytest.mark.parametrize("omega0", [0.0, 30.0])
+def test_train_steps_equals_single_calls(cv, omega0):
+    """The library's training loop (for the surrogate's shape, the fused
+    kernels: forward with the loss, backward through the layers, the weight
+    gradients, the summed gradients with Adam) does what the single calls do:
+    table batch, kept forward, loss, backward, Adam with the cosine rate.
+    First step: the matrix-core layers' weight gradients are equal bit for bit
+    (same operands, same k order, same split sums); the biases' and the input
+    layer's gradients are sums over the batch in another grouping (within
+    1e-5 of the largest); the losses agree to 1e-6.  Those rounding
+    differences then move the two runs apart through Adam's normalised steps
+    (a gradient near zero can send a parameter's step the other way): over
+    five steps the losses stay within 2e-3, the median parameter within 1% of
+    the learning rate and every parameter within 2 lr per step."""
     import math
     g = torch.Generator(device="cuda").manual_seed(3)
     table = torch.randint(0, 256, (1 << 24, 40), dtype=torch.uint8, device="cuda", generator=g)
     ids = torch.randint(0, 1 << 24, (5000,), dtype=torch.int32, device="cuda", generator=g)
-    a, flat = _net(cv, seed=21)
-    b = cv.MLP(DIMS)
+    a, flat = _net(cv, dims=cv.SURROGATE_DIMS, seed=21, omega0=omega0)
+    b = cv.MLP(cv.SURROGATE_DIMS)
+    b.set_first_sine(omega0)
     b.set_params(flat)
     batch, total, dr, delta, lr0, lr1 = 1024, 5, 0.25, 0.05, 2e-3, 2e-5
-    losses = a.train_steps(ids, table, dr, batch, delta, lr0, lr1, 0, total)
     manual = []
+    grads_first = None
     for k in range(total):
         x, tr, tf = b.table_batch(ids[k * batch:(k + 1) * batch], table, dr)
         out = b.forward(x, keep=True)
         loss, gout = b.loss(out, tr, tf, delta)
         b.backward(x, gout)
+        if k == 0:
+            grads_first = b.grads().clone()
         # the loop's schedule: double arithmetic on the FP32 rates it was given
         frac = k / (total - 1)
         f0, f1 = float(np.float32(lr0)), float(np.float32(lr1))
         lr = f1 + 0.5 * (f0 - f1) * (1.0 + math.cos(math.pi * frac))
         b.adam_step(float(np.float32(lr)), k + 1)
         manual.append(loss)
-    assert torch.equal(losses, torch.cat(manual))
+    manual = torch.cat(manual)
+    losses = [a.train_steps(ids[:batch], table, dr, batch, delta, lr0, lr1, 0, total)]
+    ga = a.grads()
+    gws_a, gbs_a = cv.split_params(ga.cpu().numpy(), cv.SURROGATE_DIMS)
+    gws_b, gbs_b = cv.split_params(grads_first.cpu().numpy(), cv.SURROGATE_DIMS)
+    for l in range(1, 4):
+        assert np.array_equal(gws_a[l], gws_b[l]), l
+    scale = max(np.abs(grads_first.cpu().numpy()).max(), 1e-30)
+    for l in range(4):
+        assert np.max(np.abs(gbs_a[l] - gbs_b[l])) <= 1e-5 * scale, l
+    assert np.max(np.abs(gws_a[0] - gws_b[0])) <= 1e-5 * scale
+    assert abs(float(losses[0][0]) - float(manual[0])) <= 1e-6 * abs(float(manual[0]))
+    losses.append(a.train_steps(ids[batch:], table, dr, batch, delta, lr0, lr1, 1, total))
+    losses = torch.cat(losses)
+    assert torch.allclose(losses, manual, rtol=2e-3, atol=0.0)
     pa, pb = a.params(), b.params()
-    assert torch.max(torch.abs(pa - pb)).item() <= 4 * np.finfo(np.float32).eps * torch.max(torch.abs(pb)).item()
+    d = torch.abs(pa - pb)
+    assert float(d.max()) <= 2 * lr0 * total
+    assert float(d.median()) <= 1e-2 * lr0
 
 
 @pytest.mark.parametrize("omega0", [0.0, 30.0])
