@@ -500,7 +500,9 @@ int cv_adam_step(cv_mlp* m, float lr, float beta1, float beta2, float eps, int64
  * decays by a cosine from lr_max at step 0 to lr_min at step total_steps - 1
  * (steps counted from step0 across calls; Adam's t = step + 1).  The last
  * batch may be short.  loss_log (device float [ceil(n / batch)], nullable)
- * receives each step's loss.  Asynchronous. */
+ * receives each step's loss.  The call leaves no kept forward pass
+ * (cv_mlp_hidden and cv_mlp_backward return CV_ESTATE until the next forward
+ * with CV_MLP_KEEP).  Asynchronous. */
 int cv_mlp_train_steps(cv_mlp* m, const int32_t* ids, int64_t n, const cv_table_row* table, double dr,
                        int64_t batch, float huber_delta, float lr_max, float lr_min, int64_t step0,
                        int64_t total_steps, float* loss_log, void* stream);

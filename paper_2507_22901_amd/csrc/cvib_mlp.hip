@@ -32,7 +32,7 @@ constexpr int kMaxLayers = 8;
 constexpr int kMaxIn = 4;          // input width handled by the vector-ALU layer
 constexpr int kMaxHidden = 1024;
 constexpr int kMaxOut = 256;
-constexpr int64_t kSplitRows = 256;   // batch rows per split of a weight-gradient reduction
+constexpr int32_t kSplitRows = 512;   // batch rows per split of a weight-gradient reduction
 constexpr int64_t kInferChunk = 1 << 20;  // rows per forward chunk when nothing is kept
 
 int32_t pad32(int32_t d) { return (d + 31) / 32 * 32; }
@@ -158,21 +158,22 @@ struct TileLoad {
 // passes), the next step of both operands fetched into registers while the
 // current one is multiplied from LDS.  The k order (32-deep slices in
 // ascending order, each one MFMA) does not depend on KD.
+// Tile (bx, by) of split bz.
 template <bool A_KC, bool B_KC, int EPI, int BM, int BN, int KD>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs& a, int32_t bx, int32_t by, int32_t bz) {
     constexpr int TM = BM / 32, TN = BN / 32;  // MFMA tiles per wave
     constexpr int pitch = KD + 8;
     __shared__ __attribute__((aligned(16))) bf16 sA[BM * pitch];
     __shared__ __attribute__((aligned(16))) bf16 sB[BN * pitch];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
-    const int32_t m0 = (int32_t)blockIdx.x * BM, n0 = (int32_t)blockIdx.y * BN;
-    const int32_t kb = (int32_t)blockIdx.z * a.kchunk;
+    const int32_t m0 = bx * BM, n0 = by * BN;
+    const int32_t kb = bz * a.kchunk;
     const int32_t ke = min(a.K, kb + a.kchunk);
     // bias-gradient row sums of A (first column tile only): thread -> row
     // tid / 4 (BM = 64), a quarter of each k step
     constexpr bool ROWSUM = EPI == EPI_PARTIAL_F32 && A_KC && BM == 64;
-    const bool rowsum = ROWSUM && a.bpart != nullptr && blockIdx.y == 0;
+    const bool rowsum = ROWSUM && a.bpart != nullptr && by == 0;
     float rsum = 0.0f;
     f32x4 acc[TM][TN];
 #pragma unroll
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
             rsum += __shfl_xor(rsum, 1, 64);
             rsum += __shfl_xor(rsum, 2, 64);
             const int32_t m = m0 + (tid >> 2);
-            if ((tid & 3) == 0 && m < a.M) a.bpart[(int64_t)blockIdx.z * a.M + m] = rsum;
+            if ((tid & 3) == 0 && m < a.M) a.bpart[(int64_t)bz * a.M + m] = rsum;
         }
     }
 #pragma unroll
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
                     r[e] = (bf16)(v * d);
                     a.cb[(int64_t)m * a.ldc + n] = r[e];
                 } else {
-                    a.cf[(int64_t)blockIdx.z * a.zstride + (int64_t)m * a.ldc + n] = v;
+                    a.cf[(int64_t)bz * a.zstride + (int64_t)m * a.ldc + n] = v;
                 }
             }
             if constexpr (EPI == EPI_RELU_BF16 || EPI == EPI_MASK_BF16 || EPI == EPI_SINE_BF16) {
@@ -276,6 +277,27 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
                 }
             }
         }
+}
+
+template <bool A_KC, bool B_KC, int EPI, int BM, int BN, int KD>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+    gemm_tile<A_KC, B_KC, EPI, BM, BN, KD>(a, (int32_t)blockIdx.x, (int32_t)blockIdx.y, (int32_t)blockIdx.z);
+}
+
+// Up to three products of one kind in one launch: blockIdx.z = problem *
+// splits + split; blocks beyond a problem's row tiles return at once.
+struct GemmBatch {
+    GemmArgs g[3];
+    int32_t splits;
+    int32_t mtiles[3];
+};
+
+template <bool A_KC, bool B_KC, int EPI, int BM, int BN, int KD>
+__global__ __launch_bounds__(256) void k_gemm_batch(GemmBatch b) {
+    const int32_t p = (int32_t)blockIdx.z / b.splits, z = (int32_t)blockIdx.z - p * b.splits;
+    if ((int32_t)blockIdx.x >= b.mtiles[p]) return;
+    const GemmArgs& a = p == 0 ? b.g[0] : p == 1 ? b.g[1] : b.g[2];
+    gemm_tile<A_KC, B_KC, EPI, BM, BN, KD>(a, (int32_t)blockIdx.x, (int32_t)blockIdx.y, z);
 }
 
 // Rows from which the larger tiles pay (enough blocks to fill the chip;
@@ -302,6 +324,32 @@ int gemm(const GemmArgs& a, int32_t splits, hipStream_t s) {
         if (deep) hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI, 64, 64, 64>), grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI, 64, 64, 32>), grid, dim3(256), 0, s, a);
     }
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
+// The three weight-gradient products of a fused training step in one launch:
+// kWgBM x kWgBN tiles, k (the batch) split every kSplitRows rows (as in the
+// unfused backward pass, so that both give the same sums), partials per split
+// (EPI_PARTIAL_F32), both operands k-contiguous.
+constexpr int kWgBM = 64, kWgBN = 64;
+
+int gemm_wgrad3(const GemmArgs (&g)[3], int32_t splits, hipStream_t s) {
+    GemmBatch b = {};
+    int32_t mt = 0, nt = 0;
+    for (int p = 0; p < 3; ++p) {
+        const GemmArgs& a = g[p];
+        const bool ok = a.lda % 8 == 0 && a.ldb % 8 == 0 && a.kchunk % 64 == 0 && a.M > 0 && a.N > 0 && a.K > 0 &&
+                        (int64_t)splits * a.kchunk >= a.K && !a.bpart;
+        if (!ok) return fail(CV_ESTATE, "internal: weight-gradient product shape");
+        b.g[p] = a;
+        b.mtiles[p] = (a.M + kWgBM - 1) / kWgBM;
+        mt = std::max(mt, b.mtiles[p]);
+        nt = std::max(nt, (a.N + kWgBN - 1) / kWgBN);
+    }
+    b.splits = splits;
+    hipLaunchKernelGGL((k_gemm_batch<true, true, EPI_PARTIAL_F32, kWgBM, kWgBN, 64>),
+                       dim3((unsigned)mt, (unsigned)nt, (unsigned)(3 * splits)), dim3(256), 0, s, b);
     CV_HIP(hipGetLastError());
     return CV_OK;
 }
@@ -575,14 +623,28 @@ __global__ void k_weights_bf16(const float* __restrict__ W, int32_t d, int32_t d
     Wb[t] = (bf16)(o < d ? W[t] : 0.0f);
 }
 
-// FP32 master weights W [d][din] -> BF16 transposed copy [din][dp], columns
-// d..dp-1 zero (the fused training step's k-contiguous fragments).
-__global__ void k_weights_bf16_t(const float* __restrict__ W, int32_t d, int32_t dp, int32_t din,
-                                 bf16* __restrict__ Wt) {
+// Offset of element (n, k) of an [N][32 KS] matrix-core operand in the
+// fragment-packed layout of the fused training step: per 16-row tile and
+// 32-deep k step, the 64 lanes' 8-element fragments (lane n % 16 +
+// 16 ((k % 32) / 8)) back to back, so that a wave's fragment load is 1 KB
+// contiguous (twice as fast as 16 row pieces of 64 bytes).  N a multiple of
+// 16.
+__device__ __forceinline__ int64_t frag_off(int32_t n, int32_t k, int32_t KS) {
+    return ((int64_t)((n >> 4) * KS + (k >> 5)) * 64 + (n & 15) + 16 * ((k & 31) >> 3)) * 8 + (k & 7);
+}
+
+// FP32 master weights W [d][din] -> the packed BF16 operands of the fused
+// training step: Wf (forward, n = output padded to dp, k = input) and Wb
+// (backward, n = input, k = output padded to dp); padding zero.  din a
+// multiple of 32.
+__global__ void k_weights_packed(const float* __restrict__ W, int32_t d, int32_t dp, int32_t din,
+                                 bf16* __restrict__ Wf, bf16* __restrict__ Wb) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)dp * din) return;
-    const int32_t i = (int32_t)(t / dp), o = (int32_t)(t - (int64_t)i * dp);
-    Wt[t] = (bf16)(o < d ? W[(int64_t)o * din + i] : 0.0f);
+    const int32_t o = (int32_t)(t / din), c = (int32_t)(t - (int64_t)o * din);
+    const bf16 v = (bf16)(o < d ? W[t] : 0.0f);
+    Wf[frag_off(o, c, din / 32)] = v;
+    Wb[frag_off(c, o, dp / 32)] = v;
 }
 
 // Loss of a batch and its gradient with respect to the outputs.  Per sample s
@@ -682,57 +744,86 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 
 // ---------------------------------------------------------------------------
 // Fused training step of the surrogate's shape (3 inputs, three hidden layers
-// of 256, 37 outputs padded to 64): four kinds of launch per step instead of
-// about twenty.
-//  1. k_train_forward: per block of kTrainRows rows, the input layer and the
+// of 256, 37 outputs padded to 64): four launches per step instead of about
+// twenty.
+//  1. k_train_forward: per block of kTrainRows rows, the training rows from
+//     the cube table (k_table_batch's arithmetic), the input layer and the
 //     three matrix-core layers with the activations in LDS (the arithmetic of
 //     k_mlp_infer_fused), then the loss and its gradient in the output
 //     layer's epilogue (the arithmetic of k_loss).  It writes the activations
-//     row-major (the ReLU masks of the backward pass) and transposed (the
-//     weight gradients' k-contiguous operands), the sine's derivative, the
-//     BF16 output gradient in both layouts, and the block's loss sum.
+//     transposed (the weight gradients' k-contiguous operands and the
+//     backward pass's ReLU masks), the BF16 output gradient in both layouts,
+//     and the block's loss sum.
 //  2. k_train_backward: per block, the gradient through the three layers with
-//     the gradients in LDS and the weights' transposed BF16 copies as
-//     k-contiguous fragments; it writes each layer's gradient transposed and
-//     the block's sums for the bias gradients and the input layer's gradient.
-//  3. the three weight-gradient products (k_gemm, split over the batch);
+//     the gradients in LDS (the sine's derivative recomputed from the inputs,
+//     bit for bit the forward's); it writes each layer's gradient transposed
+//     and the block's sums for the bias gradients and the input layer's
+//     gradient.
+//  3. the three weight-gradient products in one launch (k_gemm_batch, split
+//     over the batch);
 //  4. k_sum_adam: every parameter's gradient summed from its partials in a
 //     fixed order, the Adam step, and both BF16 copies of the weights.
-constexpr int kTrainRows = 32, kTW = 256, kTPitch = kTW + 8;
+// A block of the first two has 16 waves: wave w owns the 16 columns
+// 16 w .. 16 w + 15 of every hidden layer for the block's 32 rows (two MFMA
+// row tiles) and holds all eight 32-deep weight fragments of its columns in
+// registers, fetched while the previous layer's epilogue runs, so a layer
+// waits for one round of loads.  A batch of 8192 rows gives one block per
+// CU; the waves per block are what hide the latencies.
+constexpr int kTrainRows = 32, kTW = 256, kTPitch = kTW + 8, kTThreads = 1024, kTWaves = kTThreads / 64;
+constexpr int kTK = kTW / kDepth;  // 32-deep k steps of a hidden layer
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 struct TrainFwdArgs {
-    const float* x;            // [B][3]
+    const int32_t* ids;          // [B] colour ids (low 24 bits)
+    const cv_table_row* table;   // [2^24]
+    float rscale;                // radius target per index step (dr / 50)
     int64_t B;
     float omega0;
-    const float* W0;           // [256][3] FP32
+    const float* W0;             // [256][3] FP32
     const float* b0;
-    const bf16* W1;            // [256][256]
+    const bf16* W1;              // [256][256], packed (frag_off)
     const float* b1;
     const bf16* W2;
     const float* b2;
-    const bf16* W3;            // [64][256], rows 37..63 zero
+    const bf16* W3;              // [64][256] packed, rows 37..63 zero
     const float* b3;
-    const float* tr;           // [B][36]
-    const float* tf;           // [B]
     float delta;
-    bf16* h1; bf16* h2; bf16* h3;      // [B][256]
     bf16* h1t; bf16* h2t; bf16* h3t;   // [256][ldt]
     int64_t ldt;
-    float* dsin;               // [B][256] (sine first layer only)
-    bf16* gout;                // [B][64]
-    bf16* goutt;               // [64][ldt]
-    float* lpart;              // [gridDim.x]
+    bf16* gout;                  // [B][64]
+    bf16* goutt;                 // [64][ldt]
+    float* lpart;                // [gridDim.x]
 };
 
-// A block's activations sH [kTrainRows][kTPitch] to global memory, row-major
-// [B][256] and transposed [256][ldt].
-__device__ __forceinline__ void store_acts(const bf16* sH, int64_t r0, int32_t rows, int64_t B, bf16* h,
-                                           bf16* ht, int64_t ldt, int tid) {
-    for (int u = tid; u < kTrainRows * (kTW / 8); u += 256) {
-        const int r = u / (kTW / 8), c = (u % (kTW / 8)) * 8;
-        if (r < rows) *reinterpret_cast<bf16x8*>(h + (r0 + r) * kTW + c) = *reinterpret_cast<const bf16x8*>(sH + r * kTPitch + c);
-    }
-    for (int u = tid; u < kTW * (kTrainRows / 8); u += 256) {
+// The KS fragments (kDepth deep each) of row n of a packed operand (see
+// frag_off): the B operands of one 16-column MFMA tile over k < 32 KS.
+template <int KS>
+__device__ __forceinline__ void load_frags(bf16x8 (&fb)[KS], const bf16* __restrict__ Wp, int n, int fk) {
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+        fb[k] = *reinterpret_cast<const bf16x8*>(Wp + ((int64_t)((n >> 4) * KS + k) * 64 + (n & 15) + 2 * fk) * 8);
+}
+
+// acc[i] = rows 16 (i0 + i) .. + 15 of sA (LDS, pitch lda) times the
+// fragments, k ascending (k_gemm's order).
+template <int TM, int KS>
+__device__ __forceinline__ void tile_products(f32x4 (&acc)[TM], const bf16* sA, int lda, int i0,
+                                              const bf16x8 (&fb)[KS], int fr, int fk) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(sA + (16 * (i0 + i) + fr) * lda + kDepth * k + fk);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[k], acc[i], 0, 0, 0);
+        }
+}
+
+// A block's activations sH [kTrainRows][kTPitch] to global memory,
+// transposed [256][ldt].
+__device__ __forceinline__ void store_acts(const bf16* sH, int64_t r0, int64_t B, bf16* ht, int64_t ldt, int tid) {
+    for (int u = tid; u < kTW * (kTrainRows / 8); u += kTThreads) {
         const int o = u / (kTrainRows / 8), rc = (u % (kTrainRows / 8)) * 8;
         bf16x8 v;
 #pragma unroll
@@ -746,288 +837,268 @@ __device__ __forceinline__ void store_acts(const bf16* sH, int64_t r0, int32_t r
     }
 }
 
-__global__ __launch_bounds__(256) void k_train_forward(TrainFwdArgs a) {
+__global__ __launch_bounds__(kTThreads) void k_train_forward(TrainFwdArgs a) {
     constexpr int TM = kTrainRows / 16;  // MFMA row tiles per wave
     __shared__ __attribute__((aligned(16))) bf16 sH[kTrainRows * kTPitch];
     __shared__ float s_w0[kTW * 4];
-    __shared__ float s_red[256];
+    __shared__ float s_x[kTrainRows * 4];
+    __shared__ uint32_t s_row[kTrainRows * 10];  // the rows' table entries (cv_table_row, 40 bytes)
+    __shared__ float s_red[kTWaves];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int fr = lane & 15, fk = (lane >> 4) * 8;
-    for (int k = tid; k < kTW * 3; k += 256) s_w0[k] = a.W0[k];
-    for (int k = tid; k < kTW; k += 256) s_w0[kTW * 3 + k] = a.b0[k];
-    __syncthreads();
+    const int n = 16 * w + fr;  // this lane's column of the hidden layers
     const int64_t r0 = (int64_t)blockIdx.x * kTrainRows;
     const int32_t rows = (int32_t)min((int64_t)kTrainRows, a.B - r0);
-    // input layer (k_input_layer's arithmetic): thread -> row tid / 8, 32 columns
-    {
-        const int row = tid >> 3, c0 = (tid & 7) * 32;
-        float x[3] = {0.f, 0.f, 0.f};
-        if (row < rows)
-            for (int c = 0; c < 3; ++c) x[c] = a.x[(r0 + row) * 3 + c];
-        for (int q = 0; q < 4; ++q) {
-            bf16x8 v;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int o = c0 + 8 * q + e;
-                float acc = s_w0[kTW * 3 + o];
-                for (int c = 0; c < 3; ++c) acc = fmaf(s_w0[o * 3 + c], x[c], acc);
-                v[e] = (bf16)first_act(acc, a.omega0);
-                if (a.dsin && row < rows) a.dsin[(r0 + row) * kTW + o] = a.omega0 * cosf(a.omega0 * acc);
-            }
-            *reinterpret_cast<bf16x8*>(sH + row * kTPitch + c0 + 8 * q) = v;
-        }
+    // Loads in the order they are waited for (the counters are in order): the
+    // input layer's weights and the ids, then the W1 fragments, then the
+    // rows' table entries (thread -> 4 bytes of row tid / 10), which only the
+    // loss needs and which reach LDS just before it.
+    const float w0v = tid < kTW * 3 ? a.W0[tid] : a.b0[tid - kTW * 3];
+    const int rr = tid / 10;
+    uint32_t rid = 0;
+    if (tid < kTrainRows * 10 && rr < rows) rid = (uint32_t)a.ids[r0 + rr] & 0xFFFFFFu;
+    bf16x8 fb[kTK];
+    load_frags(fb, a.W1, n, fk);
+    const float bias1 = a.b1[n], bias2 = a.b2[n];
+    uint32_t tword = 0;
+    if (tid < kTrainRows * 10) tword = reinterpret_cast<const uint32_t*>(a.table + rid)[tid - 10 * rr];
+    s_w0[tid] = w0v;
+    // the block's training rows (k_table_batch's arithmetic)
+    if (tid < kTrainRows * 10 && tid == 10 * rr) {
+        s_x[rr * 4 + 0] = rgb_input(rid >> 16);
+        s_x[rr * 4 + 1] = rgb_input((rid >> 8) & 255u);
+        s_x[rr * 4 + 2] = rgb_input(rid & 255u);
+        s_x[rr * 4 + 3] = 0.0f;
     }
     __syncthreads();
-    store_acts(sH, r0, rows, a.B, a.h1, a.h1t, a.ldt, tid);
-    // hidden layers: wave w -> columns 64 w .. 64 w + 63 of every row
-    for (int layer = 0; layer < 2; ++layer) {
-        const bf16* Wl = layer == 0 ? a.W1 : a.W2;
-        const float* bl = layer == 0 ? a.b1 : a.b2;
-        f32x4 acc[TM][4];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        bf16x8 fb[4], fbn[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            fb[j] = *reinterpret_cast<const bf16x8*>(Wl + (int64_t)(64 * w + 16 * j + fr) * kTW + fk);
-        for (int k0 = 0; k0 < kTW; k0 += kDepth) {
-            if (k0 + kDepth < kTW) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    fbn[j] = *reinterpret_cast<const bf16x8*>(Wl + (int64_t)(64 * w + 16 * j + fr) * kTW + k0 + kDepth + fk);
-            }
-            bf16x8 fa[TM];
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-                fa[i] = *reinterpret_cast<const bf16x8*>(sH + (16 * i + fr) * kTPitch + k0 + fk);
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) fb[j] = fbn[j];
-        }
-        __syncthreads();  // every wave has read the layer's input
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int mm = 16 * i + (lane >> 4) * 4 + e, n = 64 * w + 16 * j + fr;
-                    sH[mm * kTPitch + n] = (bf16)fmaxf(acc[i][j][e] + bl[n], 0.0f);
-                }
-        __syncthreads();
-        store_acts(sH, r0, rows, a.B, layer == 0 ? a.h2 : a.h3, layer == 0 ? a.h2t : a.h3t, a.ldt, tid);
-    }
-    // output layer (64 columns, wave w -> 16 w .. 16 w + 15), then the loss
-    // and its gradient (k_loss's arithmetic) in the epilogue
-    float ls = 0.0f;
+    // input layer (k_input_layer's arithmetic): thread -> row tid / 32, 8 columns
     {
-        f32x4 acc[TM];
+        const int row = tid >> 5, c0 = (tid & 31) * 8;
+        const float x0 = s_x[row * 4 + 0], x1 = s_x[row * 4 + 1], x2 = s_x[row * 4 + 2];
+        bf16x8 v;
 #pragma unroll
-        for (int i = 0; i < TM; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < kTW; k0 += kDepth) {
-            const bf16x8 fb = *reinterpret_cast<const bf16x8*>(a.W3 + (int64_t)(16 * w + fr) * kTW + k0 + fk);
-#pragma unroll
-            for (int i = 0; i < TM; ++i) {
-                const bf16x8 fa = *reinterpret_cast<const bf16x8*>(sH + (16 * i + fr) * kTPitch + k0 + fk);
-                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i], 0, 0, 0);
-            }
+        for (int e = 0; e < 8; ++e) {
+            const int o = c0 + e;
+            float acc = s_w0[kTW * 3 + o];
+            acc = fmaf(s_w0[o * 3 + 0], x0, acc);
+            acc = fmaf(s_w0[o * 3 + 1], x1, acc);
+            acc = fmaf(s_w0[o * 3 + 2], x2, acc);
+            v[e] = (bf16)first_act(acc, a.omega0);
         }
-        const int32_t R = 36;
-        const float invR = 1.0f / (float)R, invB = 1.0f / (float)a.B;
-        const int n = 16 * w + fr;
+        *reinterpret_cast<bf16x8*>(sH + row * kTPitch + c0) = v;
+    }
+    __syncthreads();
+    store_acts(sH, r0, a.B, a.h1t, a.ldt, tid);
+    // hidden layers 2 and 3
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            const int mb = 16 * i + (lane >> 4) * 4;
-            bf16 gv[4];
+    for (int layer = 0; layer < 2; ++layer) {
+        f32x4 acc[TM];
+        tile_products<TM, kTK>(acc, sH, kTPitch, 0, fb, fr, fk);
+        // the next layer's fragments in flight during the epilogue
+        if (layer == 0) load_frags(fb, a.W2, n, fk);
+        else if (w < 8) load_frags(fb, a.W3, 16 * (w & 3) + fr, fk);
+        __syncthreads();  // every wave has read the layer's input
+        const float bias = layer == 0 ? bias1 : bias2;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int mm = mb + e;
-                float g = 0.0f;
-                if (mm < rows) {
-                    const int64_t srow = r0 + mm;
-                    const float z = acc[i][e] + a.b3[n < 37 ? n : 0];
-                    if (n < R) {
-                        const float t = a.tr[srow * R + n];
-                        if (t > 0.0f) {
-                            const float er = z - t, ae = fabsf(er);
-                            ls += (ae <= a.delta ? 0.5f * er * er : a.delta * (ae - 0.5f * a.delta)) * invR;
-                            g = (ae <= a.delta ? er : copysignf(a.delta, er)) * invR;
-                        }
-                    } else if (n == R) {
-                        const float f = a.tf[srow];
-                        ls += fmaxf(z, 0.0f) - z * f + log1pf(expf(-fabsf(z)));
-                        g = 1.0f / (1.0f + expf(-z)) - f;
+                const int mm = 16 * i + (lane >> 4) * 4 + e;
+                sH[mm * kTPitch + n] = (bf16)fmaxf(acc[i][e] + bias, 0.0f);
+            }
+        if (layer == 1 && tid < kTrainRows * 10) s_row[tid] = tword;
+        __syncthreads();
+        store_acts(sH, r0, a.B, layer == 0 ? a.h2t : a.h3t, a.ldt, tid);
+    }
+    // output layer: waves 0..7, wave w -> row tile w / 4, columns 16 (w % 4) ..;
+    // the loss and its gradient (k_loss's arithmetic) in the epilogue
+    float ls = 0.0f;
+    if (w < 8) {
+        const int i = w >> 2, no = 16 * (w & 3) + fr;
+        f32x4 acc[1];
+        tile_products<1, kTK>(acc, sH, kTPitch, i, fb, fr, fk);
+        const int32_t R = 36;
+        const float invR = 1.0f / (float)R, invB = 1.0f / (float)a.B;
+        const float bias = a.b3[no < 37 ? no : 0];
+        const int mb = 16 * i + (lane >> 4) * 4;
+        bf16 gv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int mm = mb + e;
+            float g = 0.0f;
+            if (mm < rows) {
+                const int64_t srow = r0 + mm;
+                const float z = acc[0][e] + bias;
+                const cv_table_row* trow = reinterpret_cast<const cv_table_row*>(s_row + 10 * mm);
+                if (no < R) {
+                    const float t = (float)trow->bin_ridx[no] * a.rscale;
+                    if (t > 0.0f) {
+                        const float er = z - t, ae = fabsf(er);
+                        ls += (ae <= a.delta ? 0.5f * er * er : a.delta * (ae - 0.5f * a.delta)) * invR;
+                        g = (ae <= a.delta ? er : copysignf(a.delta, er)) * invR;
                     }
-                    g *= invB;
-                    a.gout[srow * 64 + n] = (bf16)g;
+                } else if (no == R) {
+                    const float f = trow->count > 0 ? 1.0f : 0.0f;
+                    ls += fmaxf(z, 0.0f) - z * f + log1pf(expf(-fabsf(z)));
+                    g = 1.0f / (1.0f + expf(-z)) - f;
                 }
-                gv[e] = (bf16)g;
+                g *= invB;
+                a.gout[srow * 64 + no] = (bf16)g;
             }
-            bf16* d = a.goutt + (int64_t)n * a.ldt + r0 + mb;
-            if (mb + 3 < rows) {
-                typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-                *reinterpret_cast<bf16x4*>(d) = bf16x4{gv[0], gv[1], gv[2], gv[3]};
-            } else {
-                for (int e = 0; e < 4; ++e)
-                    if (mb + e < rows) d[e] = gv[e];
-            }
+            gv[e] = (bf16)g;
+        }
+        bf16* d = a.goutt + (int64_t)no * a.ldt + r0 + mb;
+        if (mb + 3 < rows) {
+            *reinterpret_cast<bf16x4*>(d) = bf16x4{gv[0], gv[1], gv[2], gv[3]};
+        } else {
+            for (int e = 0; e < 4; ++e)
+                if (mb + e < rows) d[e] = gv[e];
         }
     }
-    s_red[tid] = ls;
+    // the block's loss: each wave's sum, then the waves in order
+    for (int off = 32; off > 0; off >>= 1) ls += __shfl_xor(ls, off, 64);
+    if (lane == 0) s_red[w] = ls;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (tid < h) s_red[tid] += s_red[tid + h];
-        __syncthreads();
+    if (tid == 0) {
+        float t = 0.0f;
+        for (int q = 0; q < kTWaves; ++q) t += s_red[q];
+        a.lpart[blockIdx.x] = t;
     }
-    if (tid == 0) a.lpart[blockIdx.x] = s_red[0];
 }
 
 struct TrainBwdArgs {
     int64_t B;
     int64_t ldt;
-    float omega0;
-    const bf16* gout;          // [B][64]
-    const bf16* W3t;           // [256][64]
-    const bf16* W2t;           // [256][256]
-    const bf16* W1t;           // [256][256]
-    const bf16* h1; const bf16* h2; const bf16* h3;  // [B][256]
-    const float* dsin;         // [B][256] or null (ReLU first layer)
-    const float* x;            // [B][3]
-    bf16* g3t; bf16* g2t;      // [256][ldt]: gradients of layers 3 and 2's pre-activations, transposed
-    float* pb3;                // [nblk][64]: sums of the output gradient (output bias)
-    float* pb2;                // [nblk][256]
-    float* pb1;                // [nblk][256]
-    float* p0;                 // [nblk][256][4]: sum G1 x_c (c < 3), sum G1
+    const int32_t* ids;          // [B] colour ids (the inputs x)
+    const bf16* gout;            // [B][64]
+    const bf16* W3t;             // W3 transposed [256][64], packed (frag_off)
+    const bf16* W2t;             // [256][256] packed
+    const bf16* W1t;             // [256][256] packed
+    const bf16* h1t; const bf16* h2t; const bf16* h3t;  // [256][ldt]: the ReLU masks
+    float omega0;                // > 0: sinusoidal first layer
+    const float* W0;             // [256][3] FP32
+    const float* b0;
+    bf16* g3t; bf16* g2t;        // [256][ldt]: gradients of layers 3 and 2's pre-activations, transposed
+    float* pb3;                  // [nblk][64]: sums of the output gradient (output bias)
+    float* pb2;                  // [nblk][256]
+    float* pb1;                  // [nblk][256]
+    float* p0;                   // [nblk][256][4]: sum G1 x_c (c < 3), sum G1
 };
 
-// One backward layer of a block: C [kTrainRows][256] = A [rows][K] (LDS,
-// pitch lda) x Wt[n][k] (global, k-contiguous), then the derivative of the
-// activation below: the ReLU mask of Hm (row-major [B][256]) or the sine's
-// stored derivative dsin.  Results rounded to BF16 go to sOut (LDS, pitch
-// kTPitch, when non-null) and transposed to gt (when non-null); each wave's
-// column sums of the rounded values over the block's rows go to pb; with x,
-// also the input layer's sums p0.
-template <int K>
-__device__ __forceinline__ void train_back_layer(const bf16* sA, int lda, const bf16* __restrict__ Wt,
-                                                 const bf16* __restrict__ Hm, const float* __restrict__ dsin,
-                                                 bf16* sOut, bf16* __restrict__ gt, int64_t ldt, float* __restrict__ pb,
-                                                 const float* sx, float* __restrict__ p0, int64_t r0, int32_t rows,
-                                                 int lane, int w) {
-    constexpr int TM = kTrainRows / 16;
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
-    f32x4 acc[TM][4];
+// The activation derivative of a lane's results (rows 16 i + 4 (lane / 16) + e
+// of column n): the ReLU mask from the transposed activations ht; zero beyond
+// the batch.
+__device__ __forceinline__ void load_deriv(float (&d)[kTrainRows / 16][4], const bf16* __restrict__ ht,
+                                           int64_t ldt, int64_t r0, int32_t rows, int n, int lane) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < kTrainRows / 16; ++i) {
+        const int mb = 16 * i + (lane >> 4) * 4;
+        if (mb + 3 < rows) {
+            const bf16x4 h = *reinterpret_cast<const bf16x4*>(ht + (int64_t)n * ldt + r0 + mb);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    bf16x8 fb[4], fbn[4];
+            for (int e = 0; e < 4; ++e) d[i][e] = (float)h[e];
+        } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) fb[j] = *reinterpret_cast<const bf16x8*>(Wt + (int64_t)(64 * w + 16 * j + fr) * K + fk);
-    for (int k0 = 0; k0 < K; k0 += kDepth) {
-        if (k0 + kDepth < K) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                fbn[j] = *reinterpret_cast<const bf16x8*>(Wt + (int64_t)(64 * w + 16 * j + fr) * K + k0 + kDepth + fk);
-        }
-        bf16x8 fa[TM];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) fa[i] = *reinterpret_cast<const bf16x8*>(sA + (16 * i + fr) * lda + k0 + fk);
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) fb[j] = fbn[j];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int n = 64 * w + 16 * j + fr;
-        float cs = 0.0f, cx[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            const int mb = 16 * i + (lane >> 4) * 4;
-            bf16 r[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int mm = mb + e;
-                r[e] = (bf16)0.0f;
-                if (mm < rows) {
-                    const float v = acc[i][j][e];
-                    if (dsin) {
-                        r[e] = (bf16)(v * dsin[(r0 + mm) * kTW + n]);
-                    } else {
-                        const float h = (float)Hm[(r0 + mm) * kTW + n];
-                        r[e] = (bf16)(h > 0.0f ? v : 0.0f);
-                    }
-                }
-                const float rv = (float)r[e];
-                cs += rv;
-                if (p0) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) cx[c] = fmaf(rv, sx[mm * 4 + c], cx[c]);
-                }
-                if (sOut) sOut[mm * kTPitch + n] = r[e];
-            }
-            if (gt) {
-                bf16* d = gt + (int64_t)n * ldt + r0 + mb;
-                if (mb + 3 < rows) {
-                    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-                    *reinterpret_cast<bf16x4*>(d) = bf16x4{r[0], r[1], r[2], r[3]};
-                } else {
-                    for (int e = 0; e < 4; ++e)
-                        if (mb + e < rows) d[e] = r[e];
-                }
-            }
-        }
-        // the four lane groups hold the other rows of column n
-        cs += __shfl_xor(cs, 16, 64);
-        cs += __shfl_xor(cs, 32, 64);
-        if (p0) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                cx[c] += __shfl_xor(cx[c], 16, 64);
-                cx[c] += __shfl_xor(cx[c], 32, 64);
-            }
-        }
-        if (lane < 16) {
-            if (p0) {
-                p0[(int64_t)n * 4 + 0] = cx[0];
-                p0[(int64_t)n * 4 + 1] = cx[1];
-                p0[(int64_t)n * 4 + 2] = cx[2];
-                p0[(int64_t)n * 4 + 3] = cs;
-            } else {
-                pb[n] = cs;
-            }
+            for (int e = 0; e < 4; ++e) d[i][e] = mb + e < rows ? (float)ht[(int64_t)n * ldt + r0 + mb + e] : 0.0f;
         }
     }
 }
 
-__global__ __launch_bounds__(256) void k_train_backward(TrainBwdArgs a) {
+// Epilogue of one backward layer for column n: the products times the
+// activation derivative (sine: the factor; else the ReLU mask), rounded to
+// BF16, to sOut (LDS, when non-null) and transposed to gt (when non-null);
+// the column's sums over the block's rows to pb, or with x (sx) the input
+// layer's sums to p0.
+__device__ __forceinline__ void back_epilogue(const f32x4 (&acc)[kTrainRows / 16], const float (&d)[kTrainRows / 16][4],
+                                              bool sine, bf16* sOut, bf16* __restrict__ gt, int64_t ldt,
+                                              float* __restrict__ pb, const float* sx, float* __restrict__ p0,
+                                              int64_t r0, int32_t rows, int n, int lane) {
+    float cs = 0.0f, cx[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < kTrainRows / 16; ++i) {
+        const int mb = 16 * i + (lane >> 4) * 4;
+        bf16 r[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int mm = mb + e;
+            r[e] = (bf16)0.0f;
+            if (mm < rows) {
+                const float v = acc[i][e];
+                r[e] = sine ? (bf16)(v * d[i][e]) : (bf16)(d[i][e] > 0.0f ? v : 0.0f);
+            }
+            const float rv = (float)r[e];
+            cs += rv;
+            if (p0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) cx[c] = fmaf(rv, sx[mm * 4 + c], cx[c]);
+            }
+            if (sOut) sOut[mm * kTPitch + n] = r[e];
+        }
+        if (gt) {
+            bf16* dst = gt + (int64_t)n * ldt + r0 + mb;
+            if (mb + 3 < rows) {
+                *reinterpret_cast<bf16x4*>(dst) = bf16x4{r[0], r[1], r[2], r[3]};
+            } else {
+                for (int e = 0; e < 4; ++e)
+                    if (mb + e < rows) dst[e] = r[e];
+            }
+        }
+    }
+    // the four lane groups hold the other rows of column n
+    cs += __shfl_xor(cs, 16, 64);
+    cs += __shfl_xor(cs, 32, 64);
+    if (p0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx[c] += __shfl_xor(cx[c], 16, 64);
+            cx[c] += __shfl_xor(cx[c], 32, 64);
+        }
+    }
+    if (lane < 16) {
+        if (p0) {
+            p0[(int64_t)n * 4 + 0] = cx[0];
+            p0[(int64_t)n * 4 + 1] = cx[1];
+            p0[(int64_t)n * 4 + 2] = cx[2];
+            p0[(int64_t)n * 4 + 3] = cs;
+        } else {
+            pb[n] = cs;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kTThreads) void k_train_backward(TrainBwdArgs a) {
+    constexpr int TM = kTrainRows / 16;
+    constexpr int kGP = 72;  // pitch of the output gradient in LDS
     __shared__ __attribute__((aligned(16))) bf16 sA[kTrainRows * kTPitch];
     __shared__ __attribute__((aligned(16))) bf16 sB[kTrainRows * kTPitch];
     __shared__ float s_x[kTrainRows * 4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    const int n = 16 * w + fr;
     const int64_t r0 = (int64_t)blockIdx.x * kTrainRows;
     const int32_t rows = (int32_t)min((int64_t)kTrainRows, a.B - r0);
     const int64_t blk = blockIdx.x;
-    // the output gradient [rows][64] into sA (pitch 72), zero beyond the batch
-    constexpr int kGP = 72;
-    for (int u = tid; u < kTrainRows * 8; u += 256) {
-        const int r = u >> 3, c = (u & 7) * 8;
-        bf16x8 v = bf16x8{};
-        if (r < rows) v = *reinterpret_cast<const bf16x8*>(a.gout + (r0 + r) * 64 + c);
-        *reinterpret_cast<bf16x8*>(sA + r * kGP + c) = v;
-    }
-    for (int u = tid; u < kTrainRows * 4; u += 256) {
-        const int r = u >> 2, c = u & 3;
-        s_x[u] = (r < rows && c < 3) ? a.x[(r0 + r) * 3 + c] : 0.0f;
+    // loads in the order they are waited for: the output gradient and the
+    // ids (LDS before the first barrier), then the weight fragments and masks
+    bf16x8 gv = bf16x8{};
+    const int gr = tid >> 3, gc = (tid & 7) * 8;
+    if (tid < kTrainRows * 8 && gr < rows) gv = *reinterpret_cast<const bf16x8*>(a.gout + (r0 + gr) * 64 + gc);
+    uint32_t xid = 0;
+    if (tid < kTrainRows && tid < rows) xid = (uint32_t)a.ids[r0 + tid] & 0xFFFFFFu;
+    bf16x8 f3[64 / kDepth], f2[kTK];
+    load_frags(f3, a.W3t, n, fk);
+    load_frags(f2, a.W2t, n, fk);
+    float d[TM][4];
+    load_deriv(d, a.h3t, a.ldt, r0, rows, n, lane);
+    // this lane's column of the input layer (the sine's derivative)
+    const float w00 = a.W0[n * 3 + 0], w01 = a.W0[n * 3 + 1], w02 = a.W0[n * 3 + 2], b0n = a.b0[n];
+    // the output gradient [rows][64] into sA (pitch kGP), zero beyond the batch
+    if (tid < kTrainRows * 8) *reinterpret_cast<bf16x8*>(sA + gr * kGP + gc) = gv;
+    if (tid < kTrainRows) {
+        s_x[tid * 4 + 0] = rgb_input(xid >> 16);
+        s_x[tid * 4 + 1] = rgb_input((xid >> 8) & 255u);
+        s_x[tid * 4 + 2] = rgb_input(xid & 255u);
+        s_x[tid * 4 + 3] = 0.0f;
     }
     __syncthreads();
     // output bias: column sums of the output gradient
@@ -1036,22 +1107,42 @@ __global__ __launch_bounds__(256) void k_train_backward(TrainBwdArgs a) {
         for (int r = 0; r < kTrainRows; ++r) cs += (float)sA[r * kGP + tid];
         a.pb3[blk * 64 + tid] = cs;
     }
-    // layer 3: G3 = (Gout W3) . [H3 > 0] -> sB, G3^T; bias of the third hidden layer's input
-    train_back_layer<64>(sA, kGP, a.W3t, a.h3, nullptr, sB, a.g3t, a.ldt, a.pb2 + blk * kTW, nullptr, nullptr,
-                         r0, rows, lane, w);
+    f32x4 acc[TM];
+    // layer 3: G3 = (Gout W3) . [H3 > 0] -> sB, G3^T; bias of the third hidden layer
+    tile_products<TM, 64 / kDepth>(acc, sA, kGP, 0, f3, fr, fk);
+    back_epilogue(acc, d, false, sB, a.g3t, a.ldt, a.pb2 + blk * kTW, nullptr, nullptr, r0, rows, n, lane);
+    bf16x8 f1[kTK];
+    load_frags(f1, a.W1t, n, fk);
+    load_deriv(d, a.h2t, a.ldt, r0, rows, n, lane);
     __syncthreads();
     // layer 2: G2 = (G3 W2) . [H2 > 0] -> sA, G2^T
-    train_back_layer<kTW>(sB, kTPitch, a.W2t, a.h2, nullptr, sA, a.g2t, a.ldt, a.pb1 + blk * kTW, nullptr,
-                          nullptr, r0, rows, lane, w);
+    tile_products<TM, kTK>(acc, sB, kTPitch, 0, f2, fr, fk);
+    back_epilogue(acc, d, false, sA, a.g2t, a.ldt, a.pb1 + blk * kTW, nullptr, nullptr, r0, rows, n, lane);
+    const bool sine = a.omega0 > 0.0f;
+    if (sine) {
+        // omega0 cos(omega0 z), z = b0 + W0 x: the forward's operations in its order
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int mm = 16 * i + (lane >> 4) * 4 + e;
+                float z = b0n;
+                z = fmaf(w00, s_x[mm * 4 + 0], z);
+                z = fmaf(w01, s_x[mm * 4 + 1], z);
+                z = fmaf(w02, s_x[mm * 4 + 2], z);
+                d[i][e] = mm < rows ? a.omega0 * cosf(a.omega0 * z) : 0.0f;
+            }
+    } else {
+        load_deriv(d, a.h1t, a.ldt, r0, rows, n, lane);
+    }
     __syncthreads();
     // layer 1: G1 = (G2 W1) . act'(z1); the input layer's sums
-    train_back_layer<kTW>(sA, kTPitch, a.W1t, a.h1, a.dsin, nullptr, nullptr, a.ldt, nullptr, s_x,
-                          a.p0 + blk * kTW * 4, r0, rows, lane, w);
+    tile_products<TM, kTK>(acc, sA, kTPitch, 0, f1, fr, fk);
+    back_epilogue(acc, d, sine, nullptr, nullptr, a.ldt, nullptr, s_x, a.p0 + blk * kTW * 4, r0, rows, n, lane);
 }
 
 struct SumAdamArgs {
     float* p; float* g; float* m; float* v;
-    int64_t n;
     float lr, b1, b2, eps, c1, c2;
     int64_t woff[4], boff[4];
     int32_t din[4], dout[4], dpad[4];   // per layer l: inputs, outputs, padded outputs
@@ -1061,14 +1152,37 @@ struct SumAdamArgs {
     int32_t bw[4];
     const float* p0;           // [nblk][256][4]
     int32_t nblk;
-    bf16* wb[4]; bf16* wbt[4];
+    int32_t wblocks;           // blocks of the matrix-core weights
+    int32_t nlong;             // parameters summed over the row blocks
+    bf16* wb[4]; bf16* wpf[4]; bf16* wpb[4];
     const float* lpart; float* loss; int64_t B;
 };
 
-// Thread i: parameter i's gradient from its partials (fixed order), Adam, and
-// the BF16 copies; block 0 also sums the loss partials (k_loss_total's way).
+// Adam on parameter i with gradient gi; l >= 1: weight k of layer l (its BF16
+// copies follow), else none.
+__device__ __forceinline__ void adam_one(const SumAdamArgs& a, int64_t i, float gi, int l, int64_t k) {
+    a.g[i] = gi;
+    const float mi = a.b1 * a.m[i] + (1.0f - a.b1) * gi;
+    const float vi = a.b2 * a.v[i] + (1.0f - a.b2) * gi * gi;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    const float pi = a.p[i] - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
+    a.p[i] = pi;
+    if (l > 0) {
+        const int32_t o = (int32_t)(k / a.din[l]), c = (int32_t)(k - (int64_t)o * a.din[l]);
+        a.wb[l][k] = (bf16)pi;
+        a.wpf[l][frag_off(o, c, a.din[l] / 32)] = (bf16)pi;
+        a.wpb[l][frag_off(c, o, a.dpad[l] / 32)] = (bf16)pi;
+    }
+}
+
+// Blocks below wblocks: thread -> one weight of the matrix-core layers, its
+// gradient the sum of wsplits partials (coalesced over the threads).  The
+// blocks after: wave -> one parameter whose gradient sums one partial per row
+// block (the input layer's weights and every bias): lane j adds the partials
+// j, j + 64, .. in order, then the lanes in a fixed tree (lane 0's result).
+// Block 0 also sums the loss partials (k_loss_total's way).
 __global__ __launch_bounds__(256) void k_sum_adam(SumAdamArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (blockIdx.x == 0 && a.loss) {
         __shared__ double s_sum[256];
         double acc = 0.0;
@@ -1081,40 +1195,56 @@ __global__ __launch_bounds__(256) void k_sum_adam(SumAdamArgs a) {
         }
         if (threadIdx.x == 0) *a.loss = (float)(s_sum[0] / (double)a.B);
     }
-    if (i >= a.n) return;
-    int l = 3;
-    while (l > 0 && i < a.woff[l]) --l;
+    if ((int32_t)blockIdx.x < a.wblocks) {
+        const int64_t i = a.woff[1] + (int64_t)blockIdx.x * 256 + threadIdx.x;
+        if (i >= a.boff[3]) return;
+        const int l = i < a.woff[2] ? 1 : i < a.woff[3] ? 2 : 3;
+        if (i >= a.boff[l]) return;  // a bias: summed below
+        const int64_t k = i - a.woff[l];
+        const int64_t zs = (int64_t)a.dpad[l] * a.din[l];
+        const float* src = a.wpart[l] + k;
+        float gi = 0.0f;
+        int32_t z = 0;
+        for (; z + 16 <= a.wsplits; z += 16) {  // 16 loads in flight, added in order
+            float v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = src[(int64_t)(z + q) * zs];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) gi += v[q];
+        }
+        for (; z < a.wsplits; ++z) gi += src[(int64_t)z * zs];
+        adam_one(a, i, gi, l, k);
+        return;
+    }
+    const int lane = threadIdx.x & 63;
+    int32_t q = ((int32_t)blockIdx.x - a.wblocks) * 4 + (int32_t)(threadIdx.x >> 6);
+    if (q >= a.nlong) return;
+    // parameter q: W0 [dout0][din0], b0, then b1, b2, b3
+    const float* src;
+    int64_t stride, i;
+    const int32_t nw0 = a.dout[0] * a.din[0];
+    if (q < nw0) {
+        const int32_t o = q / a.din[0], c = q - o * a.din[0];
+        src = a.p0 + (int64_t)o * 4 + c;
+        stride = 256 * 4;
+        i = a.woff[0] + q;
+    } else if (q < nw0 + a.dout[0]) {
+        const int32_t o = q - nw0;
+        src = a.p0 + (int64_t)o * 4 + 3;
+        stride = 256 * 4;
+        i = a.boff[0] + o;
+    } else {
+        q -= nw0 + a.dout[0];
+        int l = 1;
+        while (l < 3 && q >= a.dout[l]) q -= a.dout[l++];
+        src = a.bpart[l] + q;
+        stride = a.bw[l];
+        i = a.boff[l] + q;
+    }
     float gi = 0.0f;
-    if (i < a.boff[l]) {  // weight W_l[o][c]
-        const int64_t k = i - a.woff[l];
-        const int32_t o = (int32_t)(k / a.din[l]), c = (int32_t)(k - (int64_t)o * a.din[l]);
-        if (l == 0) {
-            for (int32_t b = 0; b < a.nblk; ++b) gi += a.p0[((int64_t)b * 256 + o) * 4 + c];
-        } else {
-            const int64_t zs = (int64_t)a.dpad[l] * a.din[l];
-            for (int32_t z = 0; z < a.wsplits; ++z) gi += a.wpart[l][z * zs + (int64_t)o * a.din[l] + c];
-        }
-    } else {  // bias b_l[o]
-        const int32_t o = (int32_t)(i - a.boff[l]);
-        if (l == 0) {
-            for (int32_t b = 0; b < a.nblk; ++b) gi += a.p0[((int64_t)b * 256 + o) * 4 + 3];
-        } else {
-            for (int32_t b = 0; b < a.nblk; ++b) gi += a.bpart[l][(int64_t)b * a.bw[l] + o];
-        }
-    }
-    a.g[i] = gi;
-    const float mi = a.b1 * a.m[i] + (1.0f - a.b1) * gi;
-    const float vi = a.b2 * a.v[i] + (1.0f - a.b2) * gi * gi;
-    a.m[i] = mi;
-    a.v[i] = vi;
-    const float pi = a.p[i] - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
-    a.p[i] = pi;
-    if (l > 0 && i < a.boff[l]) {
-        const int64_t k = i - a.woff[l];
-        const int32_t o = (int32_t)(k / a.din[l]), c = (int32_t)(k - (int64_t)o * a.din[l]);
-        a.wb[l][k] = (bf16)pi;
-        a.wbt[l][(int64_t)c * a.dpad[l] + o] = (bf16)pi;
-    }
+    for (int32_t b = lane; b < a.nblk; b += 64) gi += src[(int64_t)b * stride];
+    for (int off = 32; off > 0; off >>= 1) gi += __shfl_xor(gi, off, 64);
+    if (lane == 0) adam_one(a, i, gi, 0, 0);
 }
 
 // Training rows from a table of the whole cube: x = RGB / 255 - 1/2 of colour
@@ -1202,7 +1332,8 @@ struct cv_mlp {
     float* adam_m = nullptr;
     float* adam_v = nullptr;
     bf16* wb[cvib::kMaxLayers] = {};    // BF16 W_l, l >= 1, [dpad_{l+1}][d_l]
-    bf16* wbt[cvib::kMaxLayers] = {};   // BF16 W_l transposed, l >= 1, [d_l][dpad_{l+1}] (fused training)
+    bf16* wpf[cvib::kMaxLayers] = {};   // W_l packed for the fused training step (frag_off), l >= 1, when d_l % 32 == 0:
+    bf16* wpb[cvib::kMaxLayers] = {};   //   forward [dpad_{l+1}][d_l] and backward (transposed) [d_l][dpad_{l+1}]
     int64_t bcap = 0;                   // rows of the activation buffers
     bf16* h[cvib::kMaxLayers] = {};     // post-ReLU H_l, l = 1..L-1, [bcap][d_l]
     bf16* g[2] = {nullptr, nullptr};    // back-propagated gradients [bcap][gw]
@@ -1332,8 +1463,9 @@ int refresh_bf16(cv_mlp* m, hipStream_t s) {
         const int64_t n = (int64_t)m->dpad[l + 1] * m->dims[l];
         hipLaunchKernelGGL(k_weights_bf16, dim3(blocks(n, 256)), dim3(256), 0, s,
                            m->params + m->woff[l], m->dims[l + 1], m->dpad[l + 1], m->dims[l], m->wb[l]);
-        hipLaunchKernelGGL(k_weights_bf16_t, dim3(blocks(n, 256)), dim3(256), 0, s,
-                           m->params + m->woff[l], m->dims[l + 1], m->dpad[l + 1], m->dims[l], m->wbt[l]);
+        if (m->dims[l] % 32 == 0)
+            hipLaunchKernelGGL(k_weights_packed, dim3(blocks(n, 256)), dim3(256), 0, s, m->params + m->woff[l],
+                               m->dims[l + 1], m->dpad[l + 1], m->dims[l], m->wpf[l], m->wpb[l]);
     }
     CV_HIP(hipGetLastError());
     return CV_OK;
@@ -1588,63 +1720,58 @@ int train_step_fused(cv_mlp* m, const int32_t* ids, int64_t nb, const cv_table_r
     float* pb1 = pb2 + (size_t)nblk * 256;
     float* p0 = pb1 + (size_t)nblk * 256;
     float* lp = p0 + (size_t)nblk * 256 * 4;
-    hipLaunchKernelGGL(k_table_batch, dim3(blocks(nb, 256)), dim3(256), 0, s, ids, table, nb, (float)(dr / 50.0),
-                       m->tx, m->ttr, m->ttf);
-    CV_HIP(hipGetLastError());
     TrainFwdArgs f;
-    f.x = m->tx;
+    f.ids = ids;
+    f.table = table;
+    f.rscale = (float)(dr / 50.0);
     f.B = nb;
     f.omega0 = m->omega0;
     f.W0 = m->params + m->woff[0];
     f.b0 = m->params + m->boff[0];
-    f.W1 = m->wb[1];
+    f.W1 = m->wpf[1];
     f.b1 = m->params + m->boff[1];
-    f.W2 = m->wb[2];
+    f.W2 = m->wpf[2];
     f.b2 = m->params + m->boff[2];
-    f.W3 = m->wb[3];
+    f.W3 = m->wpf[3];
     f.b3 = m->params + m->boff[3];
-    f.tr = m->ttr;
-    f.tf = m->ttf;
     f.delta = delta;
-    f.h1 = m->h[1];
-    f.h2 = m->h[2];
-    f.h3 = m->h[3];
     f.h1t = m->ht[1];
     f.h2t = m->ht[2];
     f.h3t = m->ht[3];
     f.ldt = ldt;
-    f.dsin = m->omega0 > 0.0f ? m->dsin : nullptr;
     f.gout = m->g[0];
     f.goutt = m->gt[0];
     f.lpart = lp;
-    hipLaunchKernelGGL(k_train_forward, dim3((unsigned)nblk), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_train_forward, dim3((unsigned)nblk), dim3(kTThreads), 0, s, f);
     CV_HIP(hipGetLastError());
     TrainBwdArgs b;
     b.B = nb;
     b.ldt = ldt;
-    b.omega0 = m->omega0;
+    b.ids = ids;
     b.gout = m->g[0];
-    b.W3t = m->wbt[3];
-    b.W2t = m->wbt[2];
-    b.W1t = m->wbt[1];
-    b.h1 = m->h[1];
-    b.h2 = m->h[2];
-    b.h3 = m->h[3];
-    b.dsin = f.dsin;
-    b.x = m->tx;
+    b.W3t = m->wpb[3];
+    b.W2t = m->wpb[2];
+    b.W1t = m->wpb[1];
+    b.h1t = m->ht[1];
+    b.h2t = m->ht[2];
+    b.h3t = m->ht[3];
+    b.omega0 = m->omega0;
+    b.W0 = m->params + m->woff[0];
+    b.b0 = m->params + m->boff[0];
     b.g3t = m->gt[1];
     b.g2t = m->gt[2];
     b.pb3 = pb3;
     b.pb2 = pb2;
     b.pb1 = pb1;
     b.p0 = p0;
-    hipLaunchKernelGGL(k_train_backward, dim3((unsigned)nblk), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_train_backward, dim3((unsigned)nblk), dim3(kTThreads), 0, s, b);
     CV_HIP(hipGetLastError());
     // weight gradients dW_l[o][i] = sum_s G[s][o] H_l[s][i] from the transposed operands
     const bf16* As[4] = {nullptr, m->gt[2], m->gt[1], m->gt[0]};
     float* Ps[4] = {nullptr, pw1, pw2, pw3};
+    GemmArgs wg[3] = {};
     for (int l = 1; l <= 3; ++l) {
-        GemmArgs a = {};
+        GemmArgs& a = wg[l - 1];
         a.A = As[l];
         a.lda = ldt;
         a.B = m->ht[l];
@@ -1652,19 +1779,18 @@ int train_step_fused(cv_mlp* m, const int32_t* ids, int64_t nb, const cv_table_r
         a.M = m->dpad[l + 1];
         a.N = m->dims[l];
         a.K = (int32_t)nb;
-        a.kchunk = (int32_t)kSplitRows;
+        a.kchunk = kSplitRows;
         a.cf = Ps[l];
         a.ldc = m->dims[l];
         a.zstride = (int64_t)m->dpad[l + 1] * m->dims[l];
         a.nstore = m->dims[l];
-        if ((rc = gemm<true, true, EPI_PARTIAL_F32>(a, splits, s)) != CV_OK) return rc;
     }
+    if ((rc = gemm_wgrad3(wg, splits, s)) != CV_OK) return rc;
     SumAdamArgs d;
     d.p = m->params;
     d.g = m->grads;
     d.m = m->adam_m;
     d.v = m->adam_v;
-    d.n = m->nparam;
     d.lr = lr;
     d.b1 = 0.9f;
     d.b2 = 0.999f;
@@ -1679,7 +1805,8 @@ int train_step_fused(cv_mlp* m, const int32_t* ids, int64_t nb, const cv_table_r
         d.dpad[l] = m->dpad[l + 1];
         d.wpart[l] = Ps[l];
         d.wb[l] = m->wb[l];
-        d.wbt[l] = m->wbt[l];
+        d.wpf[l] = m->wpf[l];
+        d.wpb[l] = m->wpb[l];
     }
     d.wsplits = splits;
     d.bpart[0] = nullptr;
@@ -1692,10 +1819,12 @@ int train_step_fused(cv_mlp* m, const int32_t* ids, int64_t nb, const cv_table_r
     d.bw[3] = 64;
     d.p0 = p0;
     d.nblk = nblk;
+    d.wblocks = (int32_t)blocks(m->boff[3] - m->woff[1], 256);
+    d.nlong = m->dims[1] * m->dims[0] + m->dims[1] + m->dims[2] + m->dims[3] + m->dims[4];
     d.lpart = lp;
     d.loss = loss;
     d.B = nb;
-    hipLaunchKernelGGL(k_sum_adam, dim3(blocks(m->nparam, 256)), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_sum_adam, dim3((unsigned)(d.wblocks + (d.nlong + 3) / 4)), dim3(256), 0, s, d);
     CV_HIP(hipGetLastError());
     return CV_OK;
 }
@@ -1707,7 +1836,8 @@ void free_mlp(cv_mlp* m) {
         if (p) (void)hipFree(p);
     for (int l = 0; l < kMaxLayers; ++l) {
         if (m->wb[l]) (void)hipFree(m->wb[l]);
-        if (m->wbt[l]) (void)hipFree(m->wbt[l]);
+        if (m->wpf[l]) (void)hipFree(m->wpf[l]);
+        if (m->wpb[l]) (void)hipFree(m->wpb[l]);
         if (m->h[l]) (void)hipFree(m->h[l]);
         if (m->ht[l]) (void)hipFree(m->ht[l]);
     }
@@ -1850,7 +1980,8 @@ int cv_mlp_create(cv_context* ctx, const int32_t* dims, int32_t nlayers, cv_mlp*
         if (e == hipSuccess) e = hipMalloc((void**)a, pb);
     for (int l = 1; l < nlayers && e == hipSuccess; ++l) {
         e = hipMalloc((void**)&m->wb[l], (size_t)m->dpad[l + 1] * dims[l] * sizeof(bf16));
-        if (e == hipSuccess) e = hipMalloc((void**)&m->wbt[l], (size_t)m->dpad[l + 1] * dims[l] * sizeof(bf16));
+        if (e == hipSuccess) e = hipMalloc((void**)&m->wpf[l], (size_t)m->dpad[l + 1] * dims[l] * sizeof(bf16));
+        if (e == hipSuccess) e = hipMalloc((void**)&m->wpb[l], (size_t)m->dpad[l + 1] * dims[l] * sizeof(bf16));
     }
     for (float** a : arrs)
         if (e == hipSuccess) e = hipMemset(*a, 0, pb);
@@ -2013,7 +2144,7 @@ int cv_mlp_train_steps(cv_mlp* m, const int32_t* ids, int64_t n, const cv_table_
     if ((rc = cvib::ensure_rows(m, B)) != CV_OK) return rc;
     const int64_t steps = (n + batch - 1) / batch;
     const bool fused = cvib::fused_shape(m) && m->dims[4] == 37;
-    if (fused && (rc = cvib::refresh_bf16(m, s)) != CV_OK) return rc;  // the transposed copies follow the parameters
+    if (fused && (rc = cvib::refresh_bf16(m, s)) != CV_OK) return rc;  // the packed copies follow the parameters
     for (int64_t k = 0; k < steps; ++k) {
         const int64_t r0 = k * batch, nb = std::min(batch, n - r0);
         if (fused) {
@@ -2022,6 +2153,7 @@ int cv_mlp_train_steps(cv_mlp* m, const int32_t* ids, int64_t n, const cv_table_
                 total_steps > 1 ? (double)std::min(t, total_steps - 1) / (double)(total_steps - 1) : 0.0;
             const float lr = (float)(lr_min + 0.5 * (lr_max - lr_min) * (1.0 + cos(M_PI * frac)));
             float* lp = loss_log ? loss_log + k : m->tloss;
+            m->fwd_rows = -1;
             if ((rc = cvib::train_step_fused(m, ids + r0, nb, table, dr, huber_delta, lr, t + 1, lp, s)) != CV_OK)
                 return rc;
             continue;
@@ -2041,6 +2173,7 @@ int cv_mlp_train_steps(cv_mlp* m, const int32_t* ids, int64_t n, const cv_table_
         const float lr = (float)(lr_min + 0.5 * (lr_max - lr_min) * (1.0 + cos(M_PI * frac)));
         if ((rc = cvib::run_adam(m, lr, 0.9f, 0.999f, 1e-8f, t + 1, s)) != CV_OK) return rc;
     }
+    m->fwd_rows = -1;  // the activation buffers now hold a training step's state, not a kept forward
     return CV_OK;
     CV_GUARD_END
 }
