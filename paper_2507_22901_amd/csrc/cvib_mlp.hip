@@ -744,55 +744,62 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 
 // ---------------------------------------------------------------------------
 // Fused training step of the surrogate's shape (3 inputs, three hidden layers
-// of 256, 37 outputs padded to 64): four launches per step instead of about
+// of 256, 37 outputs padded to 64): three launches per step instead of about
 // twenty.
-//  1. k_train_forward: per block of kTrainRows rows, the training rows from
-//     the cube table (k_table_batch's arithmetic), the input layer and the
-//     three matrix-core layers with the activations in LDS (the arithmetic of
-//     k_mlp_infer_fused), then the loss and its gradient in the output
-//     layer's epilogue (the arithmetic of k_loss).  It writes the activations
-//     transposed (the weight gradients' k-contiguous operands and the
-//     backward pass's ReLU masks), the BF16 output gradient in both layouts,
-//     and the block's loss sum.
-//  2. k_train_backward: per block, the gradient through the three layers with
-//     the gradients in LDS (the sine's derivative recomputed from the inputs,
-//     bit for bit the forward's); it writes each layer's gradient transposed
-//     and the block's sums for the bias gradients and the input layer's
-//     gradient.
-//  3. the three weight-gradient products in one launch (k_gemm_batch, split
+//  1. k_train_step: per block of kTrainRows rows, the training rows from the
+//     cube table (k_table_batch's arithmetic), the input layer and the three
+//     matrix-core layers (the arithmetic of k_mlp_infer_fused), the loss and
+//     its gradient in the output layer's epilogue (the arithmetic of k_loss),
+//     then the gradient back through the three layers (the arithmetic of the
+//     unfused backward pass; the sine's derivative recomputed from the
+//     inputs, bit for bit the forward's).  Activations and gradients stay in
+//     LDS, each layer's in a buffer of its own (a gradient overwrites the
+//     activation whose ReLU mask it consumed, element by element).  It
+//     writes the activations and the gradients transposed (the weight
+//     gradients' k-contiguous operands) and the block's sums for the loss,
+//     the bias gradients and the input layer's gradient.
+//  2. the three weight-gradient products in one launch (k_gemm_batch, split
 //     over the batch);
-//  4. k_sum_adam: every parameter's gradient summed from its partials in a
-//     fixed order, the Adam step, and both BF16 copies of the weights.
-// A block of the first two has 16 waves: wave w owns the 16 columns
-// 16 w .. 16 w + 15 of every hidden layer for the block's 32 rows (two MFMA
-// row tiles) and holds all eight 32-deep weight fragments of its columns in
-// registers, fetched while the previous layer's epilogue runs, so a layer
-// waits for one round of loads.  A batch of 8192 rows gives one block per
-// CU; the waves per block are what hide the latencies.
+//  3. k_sum_adam: every parameter's gradient summed from its partials in a
+//     fixed order, the Adam step, and the weights' BF16 copies.
+// A block has 16 waves: wave w owns the 16 columns 16 w .. 16 w + 15 of every
+// hidden layer for the block's 32 rows (two MFMA row tiles) and holds all
+// eight 32-deep weight fragments of its columns in registers, fetched while
+// the previous layer's epilogue runs, so a layer waits for one round of
+// loads.  A batch of 8192 rows gives one block per CU; the waves per block
+// are what hide the latencies.
 constexpr int kTrainRows = 32, kTW = 256, kTPitch = kTW + 8, kTThreads = 1024, kTWaves = kTThreads / 64;
 constexpr int kTK = kTW / kDepth;  // 32-deep k steps of a hidden layer
+constexpr int kGP = 72;            // LDS pitch of the output gradient [32][64]
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-struct TrainFwdArgs {
+struct TrainArgs {
     const int32_t* ids;          // [B] colour ids (low 24 bits)
     const cv_table_row* table;   // [2^24]
     float rscale;                // radius target per index step (dr / 50)
     int64_t B;
-    float omega0;
+    float omega0;                // > 0: sinusoidal first layer
+    float delta;                 // Huber threshold
     const float* W0;             // [256][3] FP32
     const float* b0;
-    const bf16* W1;              // [256][256], packed (frag_off)
+    const bf16* W1;              // forward operands, packed (frag_off): [256][256]
     const float* b1;
     const bf16* W2;
     const float* b2;
-    const bf16* W3;              // [64][256] packed, rows 37..63 zero
+    const bf16* W3;              // [64][256], rows 37..63 zero
     const float* b3;
-    float delta;
-    bf16* h1t; bf16* h2t; bf16* h3t;   // [256][ldt]
+    const bf16* W3t;             // backward operands, packed: W3 transposed [256][64]
+    const bf16* W2t;             // [256][256]
+    const bf16* W1t;
     int64_t ldt;
-    bf16* gout;                  // [B][64]
-    bf16* goutt;                 // [64][ldt]
-    float* lpart;                // [gridDim.x]
+    bf16* h1t; bf16* h2t; bf16* h3t;   // activations transposed [256][ldt]
+    bf16* goutt;                 // output gradient transposed [64][ldt]
+    bf16* g3t; bf16* g2t;        // gradients of layers 3 and 2's pre-activations, transposed [256][ldt]
+    float* lpart;                // [nblk]: the block's loss sum
+    float* pb3;                  // [nblk][64]: sums of the output gradient (output bias)
+    float* pb2;                  // [nblk][256]
+    float* pb1;                  // [nblk][256]
+    float* p0;                   // [nblk][256][4]: sum G1 x_c (c < 3), sum G1
 };
 
 // The KS fragments (kDepth deep each) of row n of a packed operand (see
@@ -833,173 +840,6 @@ __device__ __forceinline__ void store_acts(const bf16* sH, int64_t r0, int64_t B
             *reinterpret_cast<bf16x8*>(d) = v;
         } else {
             for (int e = 0; e < 8 && r0 + rc + e < B; ++e) d[e] = v[e];
-        }
-    }
-}
-
-__global__ __launch_bounds__(kTThreads) void k_train_forward(TrainFwdArgs a) {
-    constexpr int TM = kTrainRows / 16;  // MFMA row tiles per wave
-    __shared__ __attribute__((aligned(16))) bf16 sH[kTrainRows * kTPitch];
-    __shared__ float s_w0[kTW * 4];
-    __shared__ float s_x[kTrainRows * 4];
-    __shared__ uint32_t s_row[kTrainRows * 10];  // the rows' table entries (cv_table_row, 40 bytes)
-    __shared__ float s_red[kTWaves];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
-    const int n = 16 * w + fr;  // this lane's column of the hidden layers
-    const int64_t r0 = (int64_t)blockIdx.x * kTrainRows;
-    const int32_t rows = (int32_t)min((int64_t)kTrainRows, a.B - r0);
-    // Loads in the order they are waited for (the counters are in order): the
-    // input layer's weights and the ids, then the W1 fragments, then the
-    // rows' table entries (thread -> 4 bytes of row tid / 10), which only the
-    // loss needs and which reach LDS just before it.
-    const float w0v = tid < kTW * 3 ? a.W0[tid] : a.b0[tid - kTW * 3];
-    const int rr = tid / 10;
-    uint32_t rid = 0;
-    if (tid < kTrainRows * 10 && rr < rows) rid = (uint32_t)a.ids[r0 + rr] & 0xFFFFFFu;
-    bf16x8 fb[kTK];
-    load_frags(fb, a.W1, n, fk);
-    const float bias1 = a.b1[n], bias2 = a.b2[n];
-    uint32_t tword = 0;
-    if (tid < kTrainRows * 10) tword = reinterpret_cast<const uint32_t*>(a.table + rid)[tid - 10 * rr];
-    s_w0[tid] = w0v;
-    // the block's training rows (k_table_batch's arithmetic)
-    if (tid < kTrainRows * 10 && tid == 10 * rr) {
-        s_x[rr * 4 + 0] = rgb_input(rid >> 16);
-        s_x[rr * 4 + 1] = rgb_input((rid >> 8) & 255u);
-        s_x[rr * 4 + 2] = rgb_input(rid & 255u);
-        s_x[rr * 4 + 3] = 0.0f;
-    }
-    __syncthreads();
-    // input layer (k_input_layer's arithmetic): thread -> row tid / 32, 8 columns
-    {
-        const int row = tid >> 5, c0 = (tid & 31) * 8;
-        const float x0 = s_x[row * 4 + 0], x1 = s_x[row * 4 + 1], x2 = s_x[row * 4 + 2];
-        bf16x8 v;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int o = c0 + e;
-            float acc = s_w0[kTW * 3 + o];
-            acc = fmaf(s_w0[o * 3 + 0], x0, acc);
-            acc = fmaf(s_w0[o * 3 + 1], x1, acc);
-            acc = fmaf(s_w0[o * 3 + 2], x2, acc);
-            v[e] = (bf16)first_act(acc, a.omega0);
-        }
-        *reinterpret_cast<bf16x8*>(sH + row * kTPitch + c0) = v;
-    }
-    __syncthreads();
-    store_acts(sH, r0, a.B, a.h1t, a.ldt, tid);
-    // hidden layers 2 and 3
-#pragma unroll
-    for (int layer = 0; layer < 2; ++layer) {
-        f32x4 acc[TM];
-        tile_products<TM, kTK>(acc, sH, kTPitch, 0, fb, fr, fk);
-        // the next layer's fragments in flight during the epilogue
-        if (layer == 0) load_frags(fb, a.W2, n, fk);
-        else if (w < 8) load_frags(fb, a.W3, 16 * (w & 3) + fr, fk);
-        __syncthreads();  // every wave has read the layer's input
-        const float bias = layer == 0 ? bias1 : bias2;
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int mm = 16 * i + (lane >> 4) * 4 + e;
-                sH[mm * kTPitch + n] = (bf16)fmaxf(acc[i][e] + bias, 0.0f);
-            }
-        if (layer == 1 && tid < kTrainRows * 10) s_row[tid] = tword;
-        __syncthreads();
-        store_acts(sH, r0, a.B, layer == 0 ? a.h2t : a.h3t, a.ldt, tid);
-    }
-    // output layer: waves 0..7, wave w -> row tile w / 4, columns 16 (w % 4) ..;
-    // the loss and its gradient (k_loss's arithmetic) in the epilogue
-    float ls = 0.0f;
-    if (w < 8) {
-        const int i = w >> 2, no = 16 * (w & 3) + fr;
-        f32x4 acc[1];
-        tile_products<1, kTK>(acc, sH, kTPitch, i, fb, fr, fk);
-        const int32_t R = 36;
-        const float invR = 1.0f / (float)R, invB = 1.0f / (float)a.B;
-        const float bias = a.b3[no < 37 ? no : 0];
-        const int mb = 16 * i + (lane >> 4) * 4;
-        bf16 gv[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int mm = mb + e;
-            float g = 0.0f;
-            if (mm < rows) {
-                const int64_t srow = r0 + mm;
-                const float z = acc[0][e] + bias;
-                const cv_table_row* trow = reinterpret_cast<const cv_table_row*>(s_row + 10 * mm);
-                if (no < R) {
-                    const float t = (float)trow->bin_ridx[no] * a.rscale;
-                    if (t > 0.0f) {
-                        const float er = z - t, ae = fabsf(er);
-                        ls += (ae <= a.delta ? 0.5f * er * er : a.delta * (ae - 0.5f * a.delta)) * invR;
-                        g = (ae <= a.delta ? er : copysignf(a.delta, er)) * invR;
-                    }
-                } else if (no == R) {
-                    const float f = trow->count > 0 ? 1.0f : 0.0f;
-                    ls += fmaxf(z, 0.0f) - z * f + log1pf(expf(-fabsf(z)));
-                    g = 1.0f / (1.0f + expf(-z)) - f;
-                }
-                g *= invB;
-                a.gout[srow * 64 + no] = (bf16)g;
-            }
-            gv[e] = (bf16)g;
-        }
-        bf16* d = a.goutt + (int64_t)no * a.ldt + r0 + mb;
-        if (mb + 3 < rows) {
-            *reinterpret_cast<bf16x4*>(d) = bf16x4{gv[0], gv[1], gv[2], gv[3]};
-        } else {
-            for (int e = 0; e < 4; ++e)
-                if (mb + e < rows) d[e] = gv[e];
-        }
-    }
-    // the block's loss: each wave's sum, then the waves in order
-    for (int off = 32; off > 0; off >>= 1) ls += __shfl_xor(ls, off, 64);
-    if (lane == 0) s_red[w] = ls;
-    __syncthreads();
-    if (tid == 0) {
-        float t = 0.0f;
-        for (int q = 0; q < kTWaves; ++q) t += s_red[q];
-        a.lpart[blockIdx.x] = t;
-    }
-}
-
-struct TrainBwdArgs {
-    int64_t B;
-    int64_t ldt;
-    const int32_t* ids;          // [B] colour ids (the inputs x)
-    const bf16* gout;            // [B][64]
-    const bf16* W3t;             // W3 transposed [256][64], packed (frag_off)
-    const bf16* W2t;             // [256][256] packed
-    const bf16* W1t;             // [256][256] packed
-    const bf16* h1t; const bf16* h2t; const bf16* h3t;  // [256][ldt]: the ReLU masks
-    float omega0;                // > 0: sinusoidal first layer
-    const float* W0;             // [256][3] FP32
-    const float* b0;
-    bf16* g3t; bf16* g2t;        // [256][ldt]: gradients of layers 3 and 2's pre-activations, transposed
-    float* pb3;                  // [nblk][64]: sums of the output gradient (output bias)
-    float* pb2;                  // [nblk][256]
-    float* pb1;                  // [nblk][256]
-    float* p0;                   // [nblk][256][4]: sum G1 x_c (c < 3), sum G1
-};
-
-// The activation derivative of a lane's results (rows 16 i + 4 (lane / 16) + e
-// of column n): the ReLU mask from the transposed activations ht; zero beyond
-// the batch.
-__device__ __forceinline__ void load_deriv(float (&d)[kTrainRows / 16][4], const bf16* __restrict__ ht,
-                                           int64_t ldt, int64_t r0, int32_t rows, int n, int lane) {
-#pragma unroll
-    for (int i = 0; i < kTrainRows / 16; ++i) {
-        const int mb = 16 * i + (lane >> 4) * 4;
-        if (mb + 3 < rows) {
-            const bf16x4 h = *reinterpret_cast<const bf16x4*>(ht + (int64_t)n * ldt + r0 + mb);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) d[i][e] = (float)h[e];
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) d[i][e] = mb + e < rows ? (float)ht[(int64_t)n * ldt + r0 + mb + e] : 0.0f;
         }
     }
 }
@@ -1066,58 +906,169 @@ __device__ __forceinline__ void back_epilogue(const f32x4 (&acc)[kTrainRows / 16
     }
 }
 
-__global__ __launch_bounds__(kTThreads) void k_train_backward(TrainBwdArgs a) {
-    constexpr int TM = kTrainRows / 16;
-    constexpr int kGP = 72;  // pitch of the output gradient in LDS
-    __shared__ __attribute__((aligned(16))) bf16 sA[kTrainRows * kTPitch];
-    __shared__ __attribute__((aligned(16))) bf16 sB[kTrainRows * kTPitch];
+// The ReLU masks of a lane's results (rows 16 i + 4 (lane / 16) + e of
+// column n) from a layer's activations in LDS.
+__device__ __forceinline__ void lds_mask(float (&d)[kTrainRows / 16][4], const bf16* sH, int n, int lane) {
+#pragma unroll
+    for (int i = 0; i < kTrainRows / 16; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[i][e] = (float)sH[(16 * i + (lane >> 4) * 4 + e) * kTPitch + n];
+}
+
+__global__ __launch_bounds__(kTThreads) void k_train_step(TrainArgs a) {
+    constexpr int TM = kTrainRows / 16;  // MFMA row tiles per wave
+    __shared__ __attribute__((aligned(16))) bf16 sH1[kTrainRows * kTPitch];
+    __shared__ __attribute__((aligned(16))) bf16 sH2[kTrainRows * kTPitch];
+    __shared__ __attribute__((aligned(16))) bf16 sH3[kTrainRows * kTPitch];
+    __shared__ __attribute__((aligned(16))) bf16 sG[kTrainRows * kGP];
+    __shared__ float s_w0[kTW * 4];
     __shared__ float s_x[kTrainRows * 4];
+    __shared__ uint32_t s_row[kTrainRows * 10];  // the rows' table entries (cv_table_row, 40 bytes)
+    __shared__ float s_red[kTWaves];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int fr = lane & 15, fk = (lane >> 4) * 8;
-    const int n = 16 * w + fr;
+    const int n = 16 * w + fr;  // this lane's column of the hidden layers
     const int64_t r0 = (int64_t)blockIdx.x * kTrainRows;
     const int32_t rows = (int32_t)min((int64_t)kTrainRows, a.B - r0);
     const int64_t blk = blockIdx.x;
-    // loads in the order they are waited for: the output gradient and the
-    // ids (LDS before the first barrier), then the weight fragments and masks
-    bf16x8 gv = bf16x8{};
-    const int gr = tid >> 3, gc = (tid & 7) * 8;
-    if (tid < kTrainRows * 8 && gr < rows) gv = *reinterpret_cast<const bf16x8*>(a.gout + (r0 + gr) * 64 + gc);
-    uint32_t xid = 0;
-    if (tid < kTrainRows && tid < rows) xid = (uint32_t)a.ids[r0 + tid] & 0xFFFFFFu;
+    // Loads in the order they are waited for (the counters are in order): the
+    // input layer's weights and the ids, then the W1 fragments, then the
+    // rows' table entries (thread -> 4 bytes of row tid / 10), which only the
+    // loss needs and which reach LDS just before it.
+    const float w0v = tid < kTW * 3 ? a.W0[tid] : a.b0[tid - kTW * 3];
+    const int rr = tid / 10;
+    uint32_t rid = 0;
+    if (tid < kTrainRows * 10 && rr < rows) rid = (uint32_t)a.ids[r0 + rr] & 0xFFFFFFu;
+    bf16x8 fb[kTK];
+    load_frags(fb, a.W1, n, fk);
+    const float bias1 = a.b1[n], bias2 = a.b2[n];
+    uint32_t tword = 0;
+    if (tid < kTrainRows * 10) tword = reinterpret_cast<const uint32_t*>(a.table + rid)[tid - 10 * rr];
+    s_w0[tid] = w0v;
+    // the block's training rows (k_table_batch's arithmetic)
+    if (tid < kTrainRows * 10 && tid == 10 * rr) {
+        s_x[rr * 4 + 0] = rgb_input(rid >> 16);
+        s_x[rr * 4 + 1] = rgb_input((rid >> 8) & 255u);
+        s_x[rr * 4 + 2] = rgb_input(rid & 255u);
+        s_x[rr * 4 + 3] = 0.0f;
+    }
+    __syncthreads();
+    // input layer (k_input_layer's arithmetic): thread -> row tid / 32, 8 columns
+    {
+        const int row = tid >> 5, c0 = (tid & 31) * 8;
+        const float x0 = s_x[row * 4 + 0], x1 = s_x[row * 4 + 1], x2 = s_x[row * 4 + 2];
+        bf16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int o = c0 + e;
+            float acc = s_w0[kTW * 3 + o];
+            acc = fmaf(s_w0[o * 3 + 0], x0, acc);
+            acc = fmaf(s_w0[o * 3 + 1], x1, acc);
+            acc = fmaf(s_w0[o * 3 + 2], x2, acc);
+            v[e] = (bf16)first_act(acc, a.omega0);
+        }
+        *reinterpret_cast<bf16x8*>(sH1 + row * kTPitch + c0) = v;
+    }
+    __syncthreads();
+    store_acts(sH1, r0, a.B, a.h1t, a.ldt, tid);
+    f32x4 acc[TM];
+    // hidden layer 2 (sH1 -> sH2), then 3 (sH2 -> sH3)
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+        const bf16* sIn = layer == 0 ? sH1 : sH2;
+        bf16* sOut = layer == 0 ? sH2 : sH3;
+        tile_products<TM, kTK>(acc, sIn, kTPitch, 0, fb, fr, fk);
+        // the next layer's fragments in flight during the epilogue
+        if (layer == 0) load_frags(fb, a.W2, n, fk);
+        else if (w < 8) load_frags(fb, a.W3, 16 * (w & 3) + fr, fk);
+        const float bias = layer == 0 ? bias1 : bias2;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int mm = 16 * i + (lane >> 4) * 4 + e;
+                sOut[mm * kTPitch + n] = (bf16)fmaxf(acc[i][e] + bias, 0.0f);
+            }
+        if (layer == 1 && tid < kTrainRows * 10) s_row[tid] = tword;
+        __syncthreads();
+        store_acts(sOut, r0, a.B, layer == 0 ? a.h2t : a.h3t, a.ldt, tid);
+    }
+    // output layer: waves 0..7, wave w -> row tile w / 4, columns 16 (w % 4) ..;
+    // the loss and its gradient (k_loss's arithmetic) in the epilogue, the
+    // gradient to sG (zero beyond the batch and in the padding columns)
     bf16x8 f3[64 / kDepth], f2[kTK];
     load_frags(f3, a.W3t, n, fk);
+    float ls = 0.0f;
+    if (w < 8) {
+        const int i = w >> 2, no = 16 * (w & 3) + fr;
+        f32x4 ao[1];
+        tile_products<1, kTK>(ao, sH3, kTPitch, i, fb, fr, fk);
+        const int32_t R = 36;
+        const float invR = 1.0f / (float)R, invB = 1.0f / (float)a.B;
+        const float bias = a.b3[no < 37 ? no : 0];
+        const int mb = 16 * i + (lane >> 4) * 4;
+        bf16 gv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int mm = mb + e;
+            float g = 0.0f;
+            if (mm < rows) {
+                const float z = ao[0][e] + bias;
+                const cv_table_row* trow = reinterpret_cast<const cv_table_row*>(s_row + 10 * mm);
+                if (no < R) {
+                    const float t = (float)trow->bin_ridx[no] * a.rscale;
+                    if (t > 0.0f) {
+                        const float er = z - t, ae = fabsf(er);
+                        ls += (ae <= a.delta ? 0.5f * er * er : a.delta * (ae - 0.5f * a.delta)) * invR;
+                        g = (ae <= a.delta ? er : copysignf(a.delta, er)) * invR;
+                    }
+                } else if (no == R) {
+                    const float f = trow->count > 0 ? 1.0f : 0.0f;
+                    ls += fmaxf(z, 0.0f) - z * f + log1pf(expf(-fabsf(z)));
+                    g = 1.0f / (1.0f + expf(-z)) - f;
+                }
+                g *= invB;
+            }
+            gv[e] = (bf16)g;
+            sG[mm * kGP + no] = gv[e];
+        }
+        bf16* d = a.goutt + (int64_t)no * a.ldt + r0 + mb;
+        if (mb + 3 < rows) {
+            *reinterpret_cast<bf16x4*>(d) = bf16x4{gv[0], gv[1], gv[2], gv[3]};
+        } else {
+            for (int e = 0; e < 4; ++e)
+                if (mb + e < rows) d[e] = gv[e];
+        }
+    }
     load_frags(f2, a.W2t, n, fk);
+    // the block's loss: each wave's sum, then the waves in order
+    for (int off = 32; off > 0; off >>= 1) ls += __shfl_xor(ls, off, 64);
+    if (lane == 0) s_red[w] = ls;
     float d[TM][4];
-    load_deriv(d, a.h3t, a.ldt, r0, rows, n, lane);
-    // this lane's column of the input layer (the sine's derivative)
-    const float w00 = a.W0[n * 3 + 0], w01 = a.W0[n * 3 + 1], w02 = a.W0[n * 3 + 2], b0n = a.b0[n];
-    // the output gradient [rows][64] into sA (pitch kGP), zero beyond the batch
-    if (tid < kTrainRows * 8) *reinterpret_cast<bf16x8*>(sA + gr * kGP + gc) = gv;
-    if (tid < kTrainRows) {
-        s_x[tid * 4 + 0] = rgb_input(xid >> 16);
-        s_x[tid * 4 + 1] = rgb_input((xid >> 8) & 255u);
-        s_x[tid * 4 + 2] = rgb_input(xid & 255u);
-        s_x[tid * 4 + 3] = 0.0f;
-    }
+    lds_mask(d, sH3, n, lane);
     __syncthreads();
-    // output bias: column sums of the output gradient
-    if (tid < 64) {
-        float cs = 0.0f;
-        for (int r = 0; r < kTrainRows; ++r) cs += (float)sA[r * kGP + tid];
-        a.pb3[blk * 64 + tid] = cs;
+    if (tid == 0) {
+        float t = 0.0f;
+        for (int q = 0; q < kTWaves; ++q) t += s_red[q];
+        a.lpart[blk] = t;
     }
-    f32x4 acc[TM];
-    // layer 3: G3 = (Gout W3) . [H3 > 0] -> sB, G3^T; bias of the third hidden layer
-    tile_products<TM, 64 / kDepth>(acc, sA, kGP, 0, f3, fr, fk);
-    back_epilogue(acc, d, false, sB, a.g3t, a.ldt, a.pb2 + blk * kTW, nullptr, nullptr, r0, rows, n, lane);
+    // output bias: column sums of the output gradient
+    if (tid >= 64 && tid < 128) {
+        const int c = tid - 64;
+        float cs = 0.0f;
+        for (int r = 0; r < kTrainRows; ++r) cs += (float)sG[r * kGP + c];
+        a.pb3[blk * 64 + c] = cs;
+    }
+    // backward layer 3: G3 = (Gout W3) . [H3 > 0] -> sH3 (over H3), G3^T; bias of the third hidden layer
+    tile_products<TM, 64 / kDepth>(acc, sG, kGP, 0, f3, fr, fk);
     bf16x8 f1[kTK];
     load_frags(f1, a.W1t, n, fk);
-    load_deriv(d, a.h2t, a.ldt, r0, rows, n, lane);
+    back_epilogue(acc, d, false, sH3, a.g3t, a.ldt, a.pb2 + blk * kTW, nullptr, nullptr, r0, rows, n, lane);
+    lds_mask(d, sH2, n, lane);
     __syncthreads();
-    // layer 2: G2 = (G3 W2) . [H2 > 0] -> sA, G2^T
-    tile_products<TM, kTK>(acc, sB, kTPitch, 0, f2, fr, fk);
-    back_epilogue(acc, d, false, sA, a.g2t, a.ldt, a.pb1 + blk * kTW, nullptr, nullptr, r0, rows, n, lane);
+    // backward layer 2: G2 = (G3 W2) . [H2 > 0] -> sH2 (over H2), G2^T
+    tile_products<TM, kTK>(acc, sH3, kTPitch, 0, f2, fr, fk);
+    back_epilogue(acc, d, false, sH2, a.g2t, a.ldt, a.pb1 + blk * kTW, nullptr, nullptr, r0, rows, n, lane);
     const bool sine = a.omega0 > 0.0f;
     if (sine) {
         // omega0 cos(omega0 z), z = b0 + W0 x: the forward's operations in its order
@@ -1126,18 +1077,18 @@ __global__ __launch_bounds__(kTThreads) void k_train_backward(TrainBwdArgs a) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int mm = 16 * i + (lane >> 4) * 4 + e;
-                float z = b0n;
-                z = fmaf(w00, s_x[mm * 4 + 0], z);
-                z = fmaf(w01, s_x[mm * 4 + 1], z);
-                z = fmaf(w02, s_x[mm * 4 + 2], z);
+                float z = s_w0[kTW * 3 + n];
+                z = fmaf(s_w0[n * 3 + 0], s_x[mm * 4 + 0], z);
+                z = fmaf(s_w0[n * 3 + 1], s_x[mm * 4 + 1], z);
+                z = fmaf(s_w0[n * 3 + 2], s_x[mm * 4 + 2], z);
                 d[i][e] = mm < rows ? a.omega0 * cosf(a.omega0 * z) : 0.0f;
             }
     } else {
-        load_deriv(d, a.h1t, a.ldt, r0, rows, n, lane);
+        lds_mask(d, sH1, n, lane);
     }
     __syncthreads();
-    // layer 1: G1 = (G2 W1) . act'(z1); the input layer's sums
-    tile_products<TM, kTK>(acc, sA, kTPitch, 0, f1, fr, fk);
+    // backward layer 1: G1 = (G2 W1) . act'(z1); the input layer's sums
+    tile_products<TM, kTK>(acc, sH2, kTPitch, 0, f1, fr, fk);
     back_epilogue(acc, d, sine, nullptr, nullptr, a.ldt, nullptr, s_x, a.p0 + blk * kTW * 4, r0, rows, n, lane);
 }
 
@@ -1720,12 +1671,13 @@ int train_step_fused(cv_mlp* m, const int32_t* ids, int64_t nb, const cv_table_r
     float* pb1 = pb2 + (size_t)nblk * 256;
     float* p0 = pb1 + (size_t)nblk * 256;
     float* lp = p0 + (size_t)nblk * 256 * 4;
-    TrainFwdArgs f;
+    TrainArgs f;
     f.ids = ids;
     f.table = table;
     f.rscale = (float)(dr / 50.0);
     f.B = nb;
     f.omega0 = m->omega0;
+    f.delta = delta;
     f.W0 = m->params + m->woff[0];
     f.b0 = m->params + m->boff[0];
     f.W1 = m->wpf[1];
@@ -1734,37 +1686,22 @@ int train_step_fused(cv_mlp* m, const int32_t* ids, int64_t nb, const cv_table_r
     f.b2 = m->params + m->boff[2];
     f.W3 = m->wpf[3];
     f.b3 = m->params + m->boff[3];
-    f.delta = delta;
+    f.W3t = m->wpb[3];
+    f.W2t = m->wpb[2];
+    f.W1t = m->wpb[1];
+    f.ldt = ldt;
     f.h1t = m->ht[1];
     f.h2t = m->ht[2];
     f.h3t = m->ht[3];
-    f.ldt = ldt;
-    f.gout = m->g[0];
     f.goutt = m->gt[0];
+    f.g3t = m->gt[1];
+    f.g2t = m->gt[2];
     f.lpart = lp;
-    hipLaunchKernelGGL(k_train_forward, dim3((unsigned)nblk), dim3(kTThreads), 0, s, f);
-    CV_HIP(hipGetLastError());
-    TrainBwdArgs b;
-    b.B = nb;
-    b.ldt = ldt;
-    b.ids = ids;
-    b.gout = m->g[0];
-    b.W3t = m->wpb[3];
-    b.W2t = m->wpb[2];
-    b.W1t = m->wpb[1];
-    b.h1t = m->ht[1];
-    b.h2t = m->ht[2];
-    b.h3t = m->ht[3];
-    b.omega0 = m->omega0;
-    b.W0 = m->params + m->woff[0];
-    b.b0 = m->params + m->boff[0];
-    b.g3t = m->gt[1];
-    b.g2t = m->gt[2];
-    b.pb3 = pb3;
-    b.pb2 = pb2;
-    b.pb1 = pb1;
-    b.p0 = p0;
-    hipLaunchKernelGGL(k_train_backward, dim3((unsigned)nblk), dim3(kTThreads), 0, s, b);
+    f.pb3 = pb3;
+    f.pb2 = pb2;
+    f.pb1 = pb1;
+    f.p0 = p0;
+    hipLaunchKernelGGL(k_train_step, dim3((unsigned)nblk), dim3(kTThreads), 0, s, f);
     CV_HIP(hipGetLastError());
     // weight gradients dW_l[o][i] = sum_s G[s][o] H_l[s][i] from the transposed operands
     const bf16* As[4] = {nullptr, m->gt[2], m->gt[1], m->gt[0]};
