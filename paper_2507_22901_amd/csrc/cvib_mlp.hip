@@ -94,12 +94,27 @@ __device__ __forceinline__ float rgb_input(uint32_t v) {
     return (float)v * (1.0f / 255.0f) - 0.5f;
 }
 
+// Sine and cosine of x (radians) on the hardware's sine and cosine units,
+// whose argument is in turns: x / 2 pi reduced to [-1/2, 1/2] by taking off
+// the nearest integer.  For |x| <= 2^10 the error stays below 1e-5 (the
+// reduction's FP32 rounding, about 2^-24 |x| / 2 pi turns, and the units'
+// own), far below the BF16 rounding that the activation gets next; a full
+// range reduction would cost the input layer several times its arithmetic.
+__device__ __forceinline__ float to_turns(float x) {
+    const float t = x * 0.159154943f;  // 1 / 2 pi
+    return t - rintf(t);
+}
+__device__ __forceinline__ float sin_hw(float x) { return __builtin_amdgcn_sinf(to_turns(x)); }
+__device__ __forceinline__ float cos_hw(float x) { return __builtin_amdgcn_cosf(to_turns(x)); }
+
 // Activation of the first hidden layer: ReLU, or sin(omega0 z) when omega0 > 0
 // (a sinusoidal layer, which lets the network follow finer detail of its
-// three inputs).  Every later hidden layer is ReLU.
+// three inputs).  Every later hidden layer is ReLU.  Every kernel takes the
+// activation and its derivative omega0 cos(omega0 z) from these functions.
 __device__ __forceinline__ float first_act(float z, float omega0) {
-    return omega0 > 0.0f ? sinf(omega0 * z) : fmaxf(z, 0.0f);
+    return omega0 > 0.0f ? sin_hw(omega0 * z) : fmaxf(z, 0.0f);
 }
+__device__ __forceinline__ float first_deriv_sine(float z, float omega0) { return omega0 * cos_hw(omega0 * z); }
 
 // A tile of R rows x KD k of one operand, global -> registers: PER 8-element
 // chunks per thread (R * KD / 8 / 256 of them).  KC: stored [row][k] (a chunk
@@ -255,7 +270,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int32_t bx, int32_t
                     } else {
                         float z = a.b0[n];
                         for (int32_t c = 0; c < a.d0; ++c) z = fmaf(a.w0[n * a.d0 + c], a.x0[(int64_t)m * a.d0 + c], z);
-                        d = a.omega0 * cosf(a.omega0 * z);
+                        d = first_deriv_sine(z, a.omega0);
                     }
                     r[e] = (bf16)(v * d);
                     a.cb[(int64_t)m * a.ldc + n] = r[e];
@@ -290,15 +305,9 @@ struct GemmBatch {
     GemmArgs g[3];
     int32_t splits;
     int32_t mtiles[3];
+    int32_t ntiles[3];
+    int32_t toff[4];           // first tile of each problem within a split; toff[3] = tiles per split
 };
-
-template <bool A_KC, bool B_KC, int EPI, int BM, int BN, int KD>
-__global__ __launch_bounds__(256) void k_gemm_batch(GemmBatch b) {
-    const int32_t p = (int32_t)blockIdx.z / b.splits, z = (int32_t)blockIdx.z - p * b.splits;
-    if ((int32_t)blockIdx.x >= b.mtiles[p]) return;
-    const GemmArgs& a = p == 0 ? b.g[0] : p == 1 ? b.g[1] : b.g[2];
-    gemm_tile<A_KC, B_KC, EPI, BM, BN, KD>(a, (int32_t)blockIdx.x, (int32_t)blockIdx.y, z);
-}
 
 // Rows from which the larger tiles pay (enough blocks to fill the chip;
 // measured: at 8192 rows the 64 x 64 tiles are faster).
@@ -328,28 +337,106 @@ int gemm(const GemmArgs& a, int32_t splits, hipStream_t s) {
     return CV_OK;
 }
 
-// The three weight-gradient products of a fused training step in one launch:
-// kWgBM x kWgBN tiles, k (the batch) split every kSplitRows rows (as in the
-// unfused backward pass, so that both give the same sums), partials per split
-// (EPI_PARTIAL_F32), both operands k-contiguous.
+// The three weight-gradient products of a fused training step in one launch
+// (k_wgrad): k (the batch) split every kSplitRows rows, as in the unfused
+// backward pass, so that both give the same sums.
 constexpr int kWgBM = 64, kWgBN = 64;
+
+// One block: a 64 x 64 tile of one product over one split (EPI_PARTIAL_F32,
+// both operands k-contiguous), on a one-dimensional grid mapped to the chip's
+// eight XCDs: workgroups go to the XCDs in turn (workgroup L to XCD L % 8), so
+// workgroup L takes split L % 8 + 8 q with q = (L / 8) / tiles, tile
+// (L / 8) % tiles.  Every tile of a split then runs on one XCD and the
+// split's operands come into that XCD's L2 once.  With kWgAllLoads every
+// load of the split is issued at the start (kSplitRows / 64 stages of 64-deep
+// tiles held in registers) and the stages pass through a double-buffered LDS
+// tile one barrier each; else k_gemm's pipeline (one stage ahead).  The k
+// order is k_gemm's (ascending 32-deep slices), so the partials equal its bit
+// for bit.
+constexpr int kWgStages = kSplitRows / 64;
+constexpr bool kWgAllLoads = true;
+
+__global__ __launch_bounds__(256, 2) void k_wgrad(GemmBatch b) {
+    constexpr int BM = 64, BN = 64, KD = 64, pitch = KD + 8;
+    const int32_t L = (int32_t)blockIdx.x, xcd = L & 7, j = L >> 3;
+    const int32_t z = xcd + 8 * (j / b.toff[3]), t = j % b.toff[3];
+    if (z >= b.splits) return;
+    const int32_t p = t < b.toff[1] ? 0 : t < b.toff[2] ? 1 : 2;
+    const GemmArgs& a = p == 0 ? b.g[0] : p == 1 ? b.g[1] : b.g[2];
+    const int32_t tl = t - b.toff[p], bx = tl / b.ntiles[p], by = tl - bx * b.ntiles[p];
+    if constexpr (!kWgAllLoads) {
+        gemm_tile<true, true, EPI_PARTIAL_F32, 64, 64, 64>(a, bx, by, z);
+        return;
+    }
+    __shared__ __attribute__((aligned(16))) bf16 sA[2][BM * pitch];
+    __shared__ __attribute__((aligned(16))) bf16 sB[2][BN * pitch];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    const int32_t m0 = bx * BM, n0 = by * BN;
+    const int32_t kb = z * a.kchunk, ke = min(a.K, kb + a.kchunk);
+    TileLoad<true, BM, KD> la[kWgStages];
+    TileLoad<true, BN, KD> lb[kWgStages];
+#pragma unroll
+    for (int st = 0; st < kWgStages; ++st) {
+        la[st].load(a.A, a.lda, m0, a.M, kb + st * KD, ke, tid);
+        lb[st].load(a.B, a.ldb, n0, a.N, kb + st * KD, ke, tid);
+    }
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int st = 0; st < kWgStages; ++st) {
+        if (kb + st * KD >= ke) break;  // the same for the whole block
+        la[st].store(sA[st & 1], tid);
+        lb[st].store(sB[st & 1], tid);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KD; kk += kDepth) {
+            bf16x8 fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                fa[i] = *reinterpret_cast<const bf16x8*>(sA[st & 1] + (32 * wm + 16 * i + fr) * pitch + kk + fk);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                fb[j] = *reinterpret_cast<const bf16x8*>(sB[st & 1] + (32 * wn + 16 * j + fr) * pitch + kk + fk);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int32_t mb = m0 + 32 * wm + 16 * i + (lane >> 4) * 4;
+            const int32_t n = n0 + 32 * wn + 16 * j + fr;
+            if (n >= a.nstore) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (mb + e < a.M) a.cf[(int64_t)z * a.zstride + (int64_t)(mb + e) * a.ldc + n] = acc[i][j][e];
+        }
+}
 
 int gemm_wgrad3(const GemmArgs (&g)[3], int32_t splits, hipStream_t s) {
     GemmBatch b = {};
-    int32_t mt = 0, nt = 0;
     for (int p = 0; p < 3; ++p) {
         const GemmArgs& a = g[p];
-        const bool ok = a.lda % 8 == 0 && a.ldb % 8 == 0 && a.kchunk % 64 == 0 && a.M > 0 && a.N > 0 && a.K > 0 &&
-                        (int64_t)splits * a.kchunk >= a.K && !a.bpart;
+        const bool ok = a.lda % 8 == 0 && a.ldb % 8 == 0 && a.kchunk == kSplitRows && a.M > 0 && a.N > 0 &&
+                        a.K > 0 && (int64_t)splits * a.kchunk >= a.K && !a.bpart;
         if (!ok) return fail(CV_ESTATE, "internal: weight-gradient product shape");
         b.g[p] = a;
         b.mtiles[p] = (a.M + kWgBM - 1) / kWgBM;
-        mt = std::max(mt, b.mtiles[p]);
-        nt = std::max(nt, (a.N + kWgBN - 1) / kWgBN);
+        b.ntiles[p] = (a.N + kWgBN - 1) / kWgBN;
+        b.toff[p + 1] = b.toff[p] + b.mtiles[p] * b.ntiles[p];
     }
     b.splits = splits;
-    hipLaunchKernelGGL((k_gemm_batch<true, true, EPI_PARTIAL_F32, kWgBM, kWgBN, 64>),
-                       dim3((unsigned)mt, (unsigned)nt, (unsigned)(3 * splits)), dim3(256), 0, s, b);
+    const int64_t nblocks = (int64_t)8 * ((splits + 7) / 8) * b.toff[3];
+    hipLaunchKernelGGL(k_wgrad, dim3((unsigned)nblocks), dim3(256), 0, s, b);
     CV_HIP(hipGetLastError());
     return CV_OK;
 }
@@ -389,60 +476,103 @@ __global__ __launch_bounds__(256) void k_input_layer(const void* __restrict__ xi
             v[e] = (bf16)first_act(acc, omega0);
             // kept for the backward pass: the sine's derivative, as the
             // backward epilogue would recompute it
-            if (dsin && omega0 > 0.0f) dsin[s * d1 + o] = omega0 * cosf(omega0 * acc);
+            if (dsin && omega0 > 0.0f) dsin[s * d1 + o] = first_deriv_sine(acc, omega0);
         }
         *reinterpret_cast<bf16x8*>(H1 + s * d1 + o0) = v;
     }
 }
 
+// Offset of element (n, k) of an [N][32 KS] matrix-core operand in the
+// fragment-packed layout of the fused training step: per 16-row tile and
+// 32-deep k step, the 64 lanes' 8-element fragments (lane n % 16 +
+// 16 ((k % 32) / 8)) back to back, so that a wave's fragment load is 1 KB
+// contiguous (twice as fast as 16 row pieces of 64 bytes).  N a multiple of
+// 16.
+__device__ __forceinline__ int64_t frag_off(int32_t n, int32_t k, int32_t KS) {
+    return ((int64_t)((n >> 4) * KS + (k >> 5)) * 64 + (n & 15) + 16 * ((k & 31) >> 3)) * 8 + (k & 7);
+}
+
+// The 8-element fragment of lane (n % 16, k step ks) of a packed operand:
+// fragments of one 16-row tile and k step are 1 KB contiguous over the wave.
+__device__ __forceinline__ bf16x8 packed_frag(const bf16* __restrict__ Wp, int32_t KS, int32_t n, int32_t ks, int fk) {
+    return *reinterpret_cast<const bf16x8*>(Wp + ((int64_t)((n >> 4) * KS + ks) * 64 + (n & 15) + 2 * fk) * 8);
+}
+
 // ---------------------------------------------------------------------------
 // Fused inference of the surrogate's shape (inputs <= 4, three hidden layers
-// of 256, outputs <= 64) from 8-bit colours: a block of four waves takes 64
-// rows through every layer with the activations in LDS, so nothing but the
-// colours and the outputs touches HBM (the weights stay in L2).
+// of 256, outputs <= 64) from 8-bit colours: a block of eight waves takes
+// kFusedRows rows through every layer with the activations in LDS, so
+// nothing but the colours and the outputs touches HBM (the weights stay in
+// L2).
 //   - input layer: per element on the vector ALUs, as k_input_layer<true>
-//     (ReLU or the sinusoid);
-//   - hidden layers: each wave computes 64 rows x 64 columns as 4 x 4 MFMA
-//     tiles, the A fragments from LDS, the B fragments (weights, [n][k]) from
-//     global memory one 32-deep slice ahead; then a barrier, and the
-//     bias + ReLU results overwrite the activations in LDS;
-//   - output layer: wave w computes columns 16w .. 16w + 15.
+//     (ReLU or the sinusoid), thread t -> column t % 256, half the rows;
+//   - hidden layers: wave w computes columns 64 (w % 4) .. + 63 of rows
+//     64 (w / 4) .. + 63 (4 x 4 MFMA tiles), the A fragments from LDS, the B
+//     fragments from the packed weights (frag_off) one 32-deep step ahead;
+//     the two waves of a column group read the same fragments, the second
+//     from L1.  Then a barrier, and the bias + ReLU results overwrite the
+//     activations in LDS;
+//   - output layer: wave w computes columns 16 (w % 4) .. + 15 of rows
+//     64 (w / 4) .. + 63.
 // Same instruction, fragment layout, k order and epilogue arithmetic as
 // k_gemm, so the results equal the unfused pass bit for bit.
-constexpr int kFusedRows = 64, kFusedWidth = 256, kFusedPitch = kFusedWidth + 8;
+constexpr int kFusedRows = 128, kFusedWidth = 256, kFusedPitch = kFusedWidth + 8;
 
-__global__ __launch_bounds__(256) void k_mlp_infer_fused(const uint8_t* __restrict__ rgb, int64_t B, int32_t d0,
-                                                         int32_t dout, const float* __restrict__ W0,
-                                                         const float* __restrict__ b0, float omega0,
-                                                         const bf16* __restrict__ W1, const float* __restrict__ b1,
-                                                         const bf16* __restrict__ W2, const float* __restrict__ b2,
-                                                         const bf16* __restrict__ W3, const float* __restrict__ b3,
-                                                         float* __restrict__ out) {
+__global__ __launch_bounds__(512) void k_mlp_infer_fused(const uint8_t* __restrict__ rgb, int64_t B, int32_t d0,
+                                                            int32_t dout, const float* __restrict__ W0,
+                                                            const float* __restrict__ b0, float omega0,
+                                                            const bf16* __restrict__ W1, const float* __restrict__ b1,
+                                                            const bf16* __restrict__ W2, const float* __restrict__ b2,
+                                                            const bf16* __restrict__ W3, const float* __restrict__ b3,
+                                                            float* __restrict__ out) {
+    constexpr int TM = 4, KS = kFusedWidth / kDepth;  // row tiles per wave, k steps
     __shared__ __attribute__((aligned(16))) bf16 sH[kFusedRows * kFusedPitch];
-    __shared__ float s_w0[kFusedWidth * (kMaxIn + 1)];
+    __shared__ float s_x[kFusedRows * kMaxIn];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int fr = lane & 15, fk = (lane >> 4) * 8;
-    for (int k = tid; k < kFusedWidth * d0; k += 256) s_w0[k] = W0[k];
-    for (int k = tid; k < kFusedWidth; k += 256) s_w0[kFusedWidth * d0 + k] = b0[k];
-    __syncthreads();
+    const int rg = 64 * (w >> 2), cg = w & 3;  // the wave's first row, column group
     const int64_t r0 = (int64_t)blockIdx.x * kFusedRows;
     const int32_t rows = (int32_t)min((int64_t)kFusedRows, B - r0);
-    // input layer: thread t -> row t / 4, columns 64 (t % 4) .. + 63
+    for (int k = tid; k < kFusedRows * kMaxIn; k += 512) {
+        const int r = k / kMaxIn, c = k - r * kMaxIn;
+        s_x[k] = (r < rows && c < d0) ? rgb_input(rgb[(r0 + r) * 3 + c]) : 0.0f;
+    }
+    // input layer: thread t -> columns 2 (t % 128) and the next of rows
+    // 32 (t / 128) .. + 31, their weights in registers
     {
-        const int row = tid >> 2, c0 = (tid & 3) * 64;
-        float x[kMaxIn] = {0.f, 0.f, 0.f, 0.f};
-        if (row < rows)
-            for (int32_t c = 0; c < d0; ++c) x[c] = rgb_input(rgb[(r0 + row) * 3 + c]);
-        for (int q = 0; q < 8; ++q) {
-            bf16x8 v;
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        const int o = 2 * (tid & 127), rb = 32 * (tid >> 7);
+        float wa[kMaxIn], wb[kMaxIn];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int o = c0 + 8 * q + e;
-                float acc = s_w0[kFusedWidth * d0 + o];
-                for (int32_t c = 0; c < d0; ++c) acc = fmaf(s_w0[o * d0 + c], x[c], acc);
-                v[e] = (bf16)first_act(acc, omega0);
+        for (int c = 0; c < kMaxIn; ++c) {
+            wa[c] = c < d0 ? W0[o * d0 + c] : 0.0f;
+            wb[c] = c < d0 ? W0[(o + 1) * d0 + c] : 0.0f;
+        }
+        const float ba = b0[o], bb = b0[o + 1];
+        __syncthreads();
+        if (d0 == 3) {
+            for (int r = rb; r < rb + 32; ++r) {
+                const float x0 = s_x[r * kMaxIn + 0], x1 = s_x[r * kMaxIn + 1], x2 = s_x[r * kMaxIn + 2];
+                float za = ba, zb = bb;
+                za = fmaf(wa[0], x0, za);
+                zb = fmaf(wb[0], x0, zb);
+                za = fmaf(wa[1], x1, za);
+                zb = fmaf(wb[1], x1, zb);
+                za = fmaf(wa[2], x2, za);
+                zb = fmaf(wb[2], x2, zb);
+                *reinterpret_cast<bf16x2*>(sH + r * kFusedPitch + o) =
+                    bf16x2{(bf16)first_act(za, omega0), (bf16)first_act(zb, omega0)};
             }
-            *reinterpret_cast<bf16x8*>(sH + row * kFusedPitch + c0 + 8 * q) = v;
+        } else {
+            for (int r = rb; r < rb + 32; ++r) {
+                float za = ba, zb = bb;
+                for (int32_t c = 0; c < d0; ++c) {
+                    za = fmaf(wa[c < kMaxIn ? c : 0], s_x[r * kMaxIn + c], za);
+                    zb = fmaf(wb[c < kMaxIn ? c : 0], s_x[r * kMaxIn + c], zb);
+                }
+                *reinterpret_cast<bf16x2*>(sH + r * kFusedPitch + o) =
+                    bf16x2{(bf16)first_act(za, omega0), (bf16)first_act(zb, omega0)};
+            }
         }
     }
     __syncthreads();
@@ -450,65 +580,69 @@ __global__ __launch_bounds__(256) void k_mlp_infer_fused(const uint8_t* __restri
     for (int layer = 0; layer < 2; ++layer) {
         const bf16* Wl = layer == 0 ? W1 : W2;
         const float* bl = layer == 0 ? b1 : b2;
-        f32x4 acc[4][4];
+        f32x4 acc[TM][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
         bf16x8 fb[4], fbn[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            fb[j] = *reinterpret_cast<const bf16x8*>(Wl + (int64_t)(64 * w + 16 * j + fr) * kFusedWidth + fk);
-        for (int k0 = 0; k0 < kFusedWidth; k0 += kDepth) {
-            if (k0 + kDepth < kFusedWidth) {
+        for (int j = 0; j < 4; ++j) fb[j] = packed_frag(Wl, KS, 64 * cg + 16 * j + fr, 0, fk);
+        for (int ks = 0; ks < KS; ++ks) {
+            if (ks + 1 < KS) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    fbn[j] = *reinterpret_cast<const bf16x8*>(Wl + (int64_t)(64 * w + 16 * j + fr) * kFusedWidth +
-                                                              k0 + kDepth + fk);
+                for (int j = 0; j < 4; ++j) fbn[j] = packed_frag(Wl, KS, 64 * cg + 16 * j + fr, ks + 1, fk);
             }
-            bf16x8 fa[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                fa[i] = *reinterpret_cast<const bf16x8*>(sH + (16 * i + fr) * kFusedPitch + k0 + fk);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TM; ++i) {
+                const bf16x8 fa =
+                    *reinterpret_cast<const bf16x8*>(sH + (rg + 16 * i + fr) * kFusedPitch + kDepth * ks + fk);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
+            }
 #pragma unroll
             for (int j = 0; j < 4; ++j) fb[j] = fbn[j];
         }
+        float bias[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bias[j] = bl[64 * cg + 16 * j + fr];
         __syncthreads();  // every wave has read the layer's input
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int m = 16 * i + (lane >> 4) * 4 + e, n = 64 * w + 16 * j + fr;
-                    sH[m * kFusedPitch + n] = (bf16)fmaxf(acc[i][j][e] + bl[n], 0.0f);
+                    const int m = rg + 16 * i + (lane >> 4) * 4 + e, n = 64 * cg + 16 * j + fr;
+                    sH[m * kFusedPitch + n] = (bf16)fmaxf(acc[i][j][e] + bias[j], 0.0f);
                 }
         __syncthreads();
     }
     // output layer: 64 columns (dout <= 64, rows of W3 padded with zeros)
     {
-        f32x4 acc[4];
+        const int n = 16 * cg + fr;
+        f32x4 acc[TM];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < kFusedWidth; k0 += kDepth) {
-            const bf16x8 fb = *reinterpret_cast<const bf16x8*>(W3 + (int64_t)(16 * w + fr) * kFusedWidth + k0 + fk);
+        for (int i = 0; i < TM; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        bf16x8 fb = packed_frag(W3, KS, n, 0, fk), fbn = fb;
+        for (int ks = 0; ks < KS; ++ks) {
+            if (ks + 1 < KS) fbn = packed_frag(W3, KS, n, ks + 1, fk);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const bf16x8 fa = *reinterpret_cast<const bf16x8*>(sH + (16 * i + fr) * kFusedPitch + k0 + fk);
+            for (int i = 0; i < TM; ++i) {
+                const bf16x8 fa =
+                    *reinterpret_cast<const bf16x8*>(sH + (rg + 16 * i + fr) * kFusedPitch + kDepth * ks + fk);
                 acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i], 0, 0, 0);
             }
+            fb = fbn;
         }
+        const float bias = n < dout ? b3[n] : 0.0f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int m = 16 * i + (lane >> 4) * 4 + e, n = 16 * w + fr;
-                if (m < rows && n < dout) out[(r0 + m) * dout + n] = acc[i][e] + b3[n];
+                const int m = rg + 16 * i + (lane >> 4) * 4 + e;
+                if (m < rows && n < dout) out[(r0 + m) * dout + n] = acc[i][e] + bias;
             }
     }
 }
@@ -623,16 +757,6 @@ __global__ void k_weights_bf16(const float* __restrict__ W, int32_t d, int32_t d
     Wb[t] = (bf16)(o < d ? W[t] : 0.0f);
 }
 
-// Offset of element (n, k) of an [N][32 KS] matrix-core operand in the
-// fragment-packed layout of the fused training step: per 16-row tile and
-// 32-deep k step, the 64 lanes' 8-element fragments (lane n % 16 +
-// 16 ((k % 32) / 8)) back to back, so that a wave's fragment load is 1 KB
-// contiguous (twice as fast as 16 row pieces of 64 bytes).  N a multiple of
-// 16.
-__device__ __forceinline__ int64_t frag_off(int32_t n, int32_t k, int32_t KS) {
-    return ((int64_t)((n >> 4) * KS + (k >> 5)) * 64 + (n & 15) + 16 * ((k & 31) >> 3)) * 8 + (k & 7);
-}
-
 // FP32 master weights W [d][din] -> the packed BF16 operands of the fused
 // training step: Wf (forward, n = output padded to dp, k = input) and Wb
 // (backward, n = input, k = output padded to dp); padding zero.  din a
@@ -724,6 +848,11 @@ struct BF16Copies {
     int64_t off[kMaxLayers] = {};
     int64_t cnt[kMaxLayers] = {};
     bf16* dst[kMaxLayers] = {};
+    // packed copies (frag_off; nullable): forward [dp][din], backward [din][dp]
+    bf16* pf[kMaxLayers] = {};
+    bf16* pb[kMaxLayers] = {};
+    int32_t din[kMaxLayers] = {};
+    int32_t dp[kMaxLayers] = {};
 };
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -739,7 +868,15 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
     const float pi = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
     p[i] = pi;
     for (int32_t l = 0; l < cp.n; ++l)
-        if (i >= cp.off[l] && i < cp.off[l] + cp.cnt[l]) cp.dst[l][i - cp.off[l]] = (bf16)pi;
+        if (i >= cp.off[l] && i < cp.off[l] + cp.cnt[l]) {
+            const int64_t k = i - cp.off[l];
+            cp.dst[l][k] = (bf16)pi;
+            if (cp.pf[l]) {
+                const int32_t o = (int32_t)(k / cp.din[l]), c = (int32_t)(k - (int64_t)o * cp.din[l]);
+                cp.pf[l][frag_off(o, c, cp.din[l] / 32)] = (bf16)pi;
+                cp.pb[l][frag_off(c, o, cp.dp[l] / 32)] = (bf16)pi;
+            }
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -758,8 +895,8 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 //     writes the activations and the gradients transposed (the weight
 //     gradients' k-contiguous operands) and the block's sums for the loss,
 //     the bias gradients and the input layer's gradient.
-//  2. the three weight-gradient products in one launch (k_gemm_batch, split
-//     over the batch);
+//  2. the three weight-gradient products in one launch (k_wgrad, split over
+//     the batch);
 //  3. k_sum_adam: every parameter's gradient summed from its partials in a
 //     fixed order, the Adam step, and the weights' BF16 copies.
 // A block has 16 waves: wave w owns the 16 columns 16 w .. 16 w + 15 of every
@@ -1081,7 +1218,7 @@ __global__ __launch_bounds__(kTThreads) void k_train_step(TrainArgs a) {
                 z = fmaf(s_w0[n * 3 + 0], s_x[mm * 4 + 0], z);
                 z = fmaf(s_w0[n * 3 + 1], s_x[mm * 4 + 1], z);
                 z = fmaf(s_w0[n * 3 + 2], s_x[mm * 4 + 2], z);
-                d[i][e] = mm < rows ? a.omega0 * cosf(a.omega0 * z) : 0.0f;
+                d[i][e] = mm < rows ? first_deriv_sine(z, a.omega0) : 0.0f;
             }
     } else {
         lds_mask(d, sH1, n, lane);
@@ -1109,15 +1246,17 @@ struct SumAdamArgs {
     const float* lpart; float* loss; int64_t B;
 };
 
-// Adam on parameter i with gradient gi; l >= 1: weight k of layer l (its BF16
-// copies follow), else none.
-__device__ __forceinline__ void adam_one(const SumAdamArgs& a, int64_t i, float gi, int l, int64_t k) {
+// Adam on parameter i with gradient gi and its moments and value m0, v0, p0
+// (loaded before the gradient's sum, so that their latency overlaps it); l >=
+// 1: weight k of layer l (its BF16 copies follow), else none.
+__device__ __forceinline__ void adam_one(const SumAdamArgs& a, int64_t i, float gi, int l, int64_t k, float m0,
+                                         float v0, float p0) {
     a.g[i] = gi;
-    const float mi = a.b1 * a.m[i] + (1.0f - a.b1) * gi;
-    const float vi = a.b2 * a.v[i] + (1.0f - a.b2) * gi * gi;
+    const float mi = a.b1 * m0 + (1.0f - a.b1) * gi;
+    const float vi = a.b2 * v0 + (1.0f - a.b2) * gi * gi;
     a.m[i] = mi;
     a.v[i] = vi;
-    const float pi = a.p[i] - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
+    const float pi = p0 - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
     a.p[i] = pi;
     if (l > 0) {
         const int32_t o = (int32_t)(k / a.din[l]), c = (int32_t)(k - (int64_t)o * a.din[l]);
@@ -1153,6 +1292,7 @@ __global__ __launch_bounds__(256) void k_sum_adam(SumAdamArgs a) {
         if (i >= a.boff[l]) return;  // a bias: summed below
         const int64_t k = i - a.woff[l];
         const int64_t zs = (int64_t)a.dpad[l] * a.din[l];
+        const float m0 = a.m[i], v0 = a.v[i], p0 = a.p[i];
         const float* src = a.wpart[l] + k;
         float gi = 0.0f;
         int32_t z = 0;
@@ -1164,7 +1304,7 @@ __global__ __launch_bounds__(256) void k_sum_adam(SumAdamArgs a) {
             for (int q = 0; q < 16; ++q) gi += v[q];
         }
         for (; z < a.wsplits; ++z) gi += src[(int64_t)z * zs];
-        adam_one(a, i, gi, l, k);
+        adam_one(a, i, gi, l, k, m0, v0, p0);
         return;
     }
     const int lane = threadIdx.x & 63;
@@ -1192,10 +1332,11 @@ __global__ __launch_bounds__(256) void k_sum_adam(SumAdamArgs a) {
         stride = a.bw[l];
         i = a.boff[l] + q;
     }
+    const float m0 = a.m[i], v0 = a.v[i], p0 = a.p[i];
     float gi = 0.0f;
     for (int32_t b = lane; b < a.nblk; b += 64) gi += src[(int64_t)b * stride];
     for (int off = 32; off > 0; off >>= 1) gi += __shfl_xor(gi, off, 64);
-    if (lane == 0) adam_one(a, i, gi, 0, 0);
+    if (lane == 0) adam_one(a, i, gi, 0, 0, m0, v0, p0);
 }
 
 // Training rows from a table of the whole cube: x = RGB / 255 - 1/2 of colour
@@ -1468,10 +1609,10 @@ int run_forward(cv_mlp* m, const void* x, bool rgb8, int64_t rows, float* out, b
     int rc;
     if (rgb8 && !keep && fused_shape(m)) {
         if (rows == 0) return CV_OK;
-        const bf16* W3 = m->wb[3];  // 64 rows, zero beyond dims[4]
-        hipLaunchKernelGGL(k_mlp_infer_fused, dim3((unsigned)((rows + kFusedRows - 1) / kFusedRows)), dim3(256),
+        const bf16* W3 = m->wpf[3];  // 64 rows, zero beyond dims[4]
+        hipLaunchKernelGGL(k_mlp_infer_fused, dim3((unsigned)((rows + kFusedRows - 1) / kFusedRows)), dim3(512),
                            0, s, (const uint8_t*)x, rows, m->dims[0], m->dims[4], m->params + m->woff[0],
-                           m->params + m->boff[0], m->omega0, m->wb[1], m->params + m->boff[1], m->wb[2],
+                           m->params + m->boff[0], m->omega0, m->wpf[1], m->params + m->boff[1], m->wpf[2],
                            m->params + m->boff[2], W3, m->params + m->boff[3], out);
         CV_HIP(hipGetLastError());
         m->fwd_rows = -1;
@@ -1623,6 +1764,12 @@ int run_adam(cv_mlp* m, float lr, float b1, float b2, float eps, int64_t t, hipS
         cp.off[cp.n] = m->woff[l];
         cp.cnt[cp.n] = (int64_t)m->dims[l + 1] * m->dims[l];
         cp.dst[cp.n] = m->wb[l];
+        if (m->dims[l] % 32 == 0) {
+            cp.pf[cp.n] = m->wpf[l];
+            cp.pb[cp.n] = m->wpb[l];
+            cp.din[cp.n] = m->dims[l];
+            cp.dp[cp.n] = m->dpad[l + 1];
+        }
         ++cp.n;
     }
     hipLaunchKernelGGL(k_adam, dim3(blocks(m->nparam, 256)), dim3(256), 0, s, m->params, m->grads,
