@@ -342,91 +342,29 @@ int gemm(const GemmArgs& a, int32_t splits, hipStream_t s) {
 // backward pass, so that both give the same sums.
 constexpr int kWgBM = 64, kWgBN = 64;
 
-// One block: a 64 x 64 tile of one product over one split (EPI_PARTIAL_F32,
-// both operands k-contiguous), on a one-dimensional grid mapped to the chip's
-// eight XCDs: workgroups go to the XCDs in turn (workgroup L to XCD L % 8), so
-// workgroup L takes split L % 8 + 8 q with q = (L / 8) / tiles, tile
-// (L / 8) % tiles.  Every tile of a split then runs on one XCD and the
-// split's operands come into that XCD's L2 once.  With kWgAllLoads every
-// load of the split is issued at the start (kSplitRows / 64 stages of 64-deep
-// tiles held in registers) and the stages pass through a double-buffered LDS
-// tile one barrier each; else k_gemm's pipeline (one stage ahead).  The k
-// order is k_gemm's (ascending 32-deep slices), so the partials equal its bit
-// for bit.
-constexpr int kWgStages = kSplitRows / 64;
-constexpr bool kWgAllLoads = true;
-
-__global__ __launch_bounds__(256, 2) void k_wgrad(GemmBatch b) {
-    constexpr int BM = 64, BN = 64, KD = 64, pitch = KD + 8;
+// One block: a 64 x 64 tile of one product over one split (k_gemm's tile,
+// EPI_PARTIAL_F32, both operands k-contiguous, one stage of 64 k ahead), on a
+// one-dimensional grid mapped to the chip's eight XCDs: workgroups go to the
+// XCDs in turn (workgroup L to XCD L % 8), so workgroup L takes split
+// L % 8 + 8 q with q = (L / 8) / tiles, tile (L / 8) % tiles.  Every tile of
+// a split then runs on one XCD and the split's operands come into that XCD's
+// L2 once.  (Issuing all of a split's loads at once, held in registers, was
+// slower: 13.7 against 12.8 us for the surrogate's 8192-row step.)
+__global__ __launch_bounds__(256) void k_wgrad(GemmBatch b) {
     const int32_t L = (int32_t)blockIdx.x, xcd = L & 7, j = L >> 3;
     const int32_t z = xcd + 8 * (j / b.toff[3]), t = j % b.toff[3];
     if (z >= b.splits) return;
     const int32_t p = t < b.toff[1] ? 0 : t < b.toff[2] ? 1 : 2;
     const GemmArgs& a = p == 0 ? b.g[0] : p == 1 ? b.g[1] : b.g[2];
     const int32_t tl = t - b.toff[p], bx = tl / b.ntiles[p], by = tl - bx * b.ntiles[p];
-    if constexpr (!kWgAllLoads) {
-        gemm_tile<true, true, EPI_PARTIAL_F32, 64, 64, 64>(a, bx, by, z);
-        return;
-    }
-    __shared__ __attribute__((aligned(16))) bf16 sA[2][BM * pitch];
-    __shared__ __attribute__((aligned(16))) bf16 sB[2][BN * pitch];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
-    const int32_t m0 = bx * BM, n0 = by * BN;
-    const int32_t kb = z * a.kchunk, ke = min(a.K, kb + a.kchunk);
-    TileLoad<true, BM, KD> la[kWgStages];
-    TileLoad<true, BN, KD> lb[kWgStages];
-#pragma unroll
-    for (int st = 0; st < kWgStages; ++st) {
-        la[st].load(a.A, a.lda, m0, a.M, kb + st * KD, ke, tid);
-        lb[st].load(a.B, a.ldb, n0, a.N, kb + st * KD, ke, tid);
-    }
-    f32x4 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int st = 0; st < kWgStages; ++st) {
-        if (kb + st * KD >= ke) break;  // the same for the whole block
-        la[st].store(sA[st & 1], tid);
-        lb[st].store(sB[st & 1], tid);
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < KD; kk += kDepth) {
-            bf16x8 fa[2], fb[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-                fa[i] = *reinterpret_cast<const bf16x8*>(sA[st & 1] + (32 * wm + 16 * i + fr) * pitch + kk + fk);
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                fb[j] = *reinterpret_cast<const bf16x8*>(sB[st & 1] + (32 * wn + 16 * j + fr) * pitch + kk + fk);
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int32_t mb = m0 + 32 * wm + 16 * i + (lane >> 4) * 4;
-            const int32_t n = n0 + 32 * wn + 16 * j + fr;
-            if (n >= a.nstore) continue;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (mb + e < a.M) a.cf[(int64_t)z * a.zstride + (int64_t)(mb + e) * a.ldc + n] = acc[i][j][e];
-        }
+    gemm_tile<true, true, EPI_PARTIAL_F32, 64, 64, 64>(a, bx, by, z);
 }
 
 int gemm_wgrad3(const GemmArgs (&g)[3], int32_t splits, hipStream_t s) {
     GemmBatch b = {};
     for (int p = 0; p < 3; ++p) {
         const GemmArgs& a = g[p];
-        const bool ok = a.lda % 8 == 0 && a.ldb % 8 == 0 && a.kchunk == kSplitRows && a.M > 0 && a.N > 0 &&
+        const bool ok = a.lda % 8 == 0 && a.ldb % 8 == 0 && a.kchunk % 64 == 0 && a.M > 0 && a.N > 0 &&
                         a.K > 0 && (int64_t)splits * a.kchunk >= a.K && !a.bpart;
         if (!ok) return fail(CV_ESTATE, "internal: weight-gradient product shape");
         b.g[p] = a;
