@@ -390,7 +390,8 @@ int cv_context_no_high(cv_context* ctx, int64_t* in_gamut_host, int reset);
 
 /*
  * Kernel choice for the per-colour resolve (cv_frames_resolve and the exact
- * fallback of the surrogate calls): variant 0 gives one colour to a block of
+ * fallback of the surrogate calls; the project's autotuner, which also picks
+ * the tiling of the chunked reduce below): variant 0 gives one colour to a block of
  * four waves, 1 one colour to each wave with four waves per block, 2 the
  * same with eight waves per block.  All give identical results.  With
  * autotuning on, the first cv_frames_resolve call of a grid shape (nr,
@@ -405,6 +406,37 @@ int cv_context_set_autotune(cv_context* ctx, int on);
 int cv_context_set_resolve_variant(cv_context* ctx, int variant);
 int cv_context_resolve_variant(cv_context* ctx, const cv_grid* grid, int rays, int* variant_host,
                                int* tuned_host);
+
+/*
+ * Tiling of the chunked reduce (the count pass of cv_pair_search, and
+ * cv_pair_reduce when the colours are too few for one block each): about
+ * `tiles` tiles per call, each a run of one colour's (i, j) grid.  Every
+ * tiling gives identical results.  With autotuning on, the first eager call
+ * of a shape (count pass or reduce, colour count, nr, ntheta, N) times the
+ * tilings 1024, 2048, 4096, 8192 and 16384 (two runs each; the last leaves
+ * the call's outputs) and keeps the fastest in the context; a captured
+ * (CV_GRAPH) call uses the choice made so far.  cv_context_set_tile_target
+ * forces a tiling (64 .. 2^20) or returns to the tuned one (0; 4096 untuned).
+ * cv_context_tile_target reports the tiling a call of that shape would use
+ * (search != 0: the count pass) and (tuned_host, nullable) whether it came
+ * from tuning.  Errors: CV_EINVAL.
+ */
+int cv_context_set_tile_target(cv_context* ctx, int32_t tiles);
+int cv_context_tile_target(cv_context* ctx, int64_t n, const cv_grid* grid, int search, int32_t* tiles_host,
+                           int* tuned_host);
+
+/*
+ * On-disk cache of the tuned choices (resolve variants and tilings): a text
+ * file whose first line names the format, the GPU architecture and its
+ * compute-unit count, then one line per choice ("resolve <key> <variant>" or
+ * "tiles <key> <tiles>", keys in hex).  Setting a path loads the choices of a
+ * file written for this GPU model (a file of another model is left unread and
+ * is rewritten at the next tuning), creates the file if it is missing, and
+ * has every later tuning rewrite it (through a temporary file and a rename).
+ * NULL or "" detaches the file.  Errors: CV_EINVAL (a file that is not a
+ * tuning file, or a path that cannot be written), CV_EHIP.
+ */
+int cv_context_set_tune_file(cv_context* ctx, const char* path);
 
 #define CV_TIME_EVAL 0
 #define CV_TIME_WRITE 1

@@ -76,7 +76,8 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_pair_reduce_csr", "cv_context_set_gamut_cells", "cv_context_skipped",
            "cv_mlp_set_first_sine", "cv_mlp_first_sine", "cv_permute_ids", "cv_context_no_high",
            "cv_pair_reduce_noalloc", "cv_ray_search", "cv_mlp_hidden",
-           "cv_mlp_save_checkpoint", "cv_mlp_load_checkpoint", "cv_mlp_checkpoint_info")
+           "cv_mlp_save_checkpoint", "cv_mlp_load_checkpoint", "cv_mlp_checkpoint_info",
+           "cv_context_set_tile_target", "cv_context_tile_target", "cv_context_set_tune_file")
 CV_NO_FALLBACK = 0x4
 CV_PRED_GIVEN = 0x20
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
@@ -141,6 +142,10 @@ def lib() -> C.CDLL:
                                           C.c_uint32, P]
         L.cv_context_set_autotune.argtypes = [P, C.c_int]
         L.cv_context_set_resolve_variant.argtypes = [P, C.c_int]
+        L.cv_context_set_tile_target.argtypes = [P, C.c_int32]
+        L.cv_context_tile_target.argtypes = [P, I64, C.POINTER(cv_grid), C.c_int, C.POINTER(C.c_int32),
+                                             C.POINTER(C.c_int)]
+        L.cv_context_set_tune_file.argtypes = [P, C.c_char_p]
         L.cv_context_resolve_variant.argtypes = [P, C.POINTER(cv_grid), C.c_int, C.POINTER(C.c_int),
                                                  C.POINTER(C.c_int)]
         L.cv_pair_reduce_rules.argtypes = [P, P, I64, C.POINTER(cv_grid), P, C.c_int32, P, P]
@@ -229,8 +234,26 @@ class Context:
         return v.value
 
     def set_autotune(self, on: bool = True):
-        """Time the per-colour resolve variants on the first call of each grid shape."""
+        """Time the per-colour resolve variants and the chunked reduce's tilings on
+        the first call of each shape."""
         _check(lib().cv_context_set_autotune(self.handle, int(bool(on))))
+
+    def set_tile_target(self, tiles: int = 0):
+        """Force the chunked reduce's tiles per call (64 .. 2^20), or return to tuning (0)."""
+        _check(lib().cv_context_set_tile_target(self.handle, int(tiles)))
+
+    def tile_target(self, n: int, grid: "Grid", search: bool = True):
+        """(tiles a call of this shape would use, whether they were tuned); search:
+        the count pass of pair_search, else pair_reduce."""
+        v, t = C.c_int32(0), C.c_int(0)
+        g = grid.c()
+        _check(lib().cv_context_tile_target(self.handle, int(n), C.byref(g), int(bool(search)), C.byref(v),
+                                            C.byref(t)))
+        return v.value, bool(t.value)
+
+    def set_tune_file(self, path: str | None):
+        """Keep the tuned choices in a file (loaded now if written for this GPU model)."""
+        _check(lib().cv_context_set_tune_file(self.handle, path.encode() if path else None))
 
     def set_resolve_variant(self, variant: int = -1):
         """Force a per-colour resolve variant (0, 1, 2) or return to tuning (-1)."""

@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <cstdio>
 #include <cstring>
 #include <exception>
 #include <string>
@@ -129,6 +130,47 @@ int make_rule(const cv_rule* r, RuleDev* out) {
 }
 
 } // namespace cvib
+
+namespace {
+
+// First line of a tuning file: format tag, GPU architecture and compute-unit
+// count (choices made on one GPU model are not reused on another).
+std::string tune_header(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "";
+    std::string arch(prop.gcnArchName);
+    for (char& ch : arch)
+        if (ch == ' ') ch = '_';
+    return "cvib-tune 1 " + arch + " " + std::to_string(prop.multiProcessorCount);
+}
+
+bool tile_choice(int32_t v) {
+    for (int32_t t : cvib::kTileTargets)
+        if (t == v) return true;
+    return false;
+}
+
+} // namespace
+
+int cv_context::save_tuning() {
+    if (tune_file.empty()) return CV_OK;
+    const std::string head = tune_header(device);
+    if (head.empty()) return cvib::fail(CV_EHIP, "hipGetDeviceProperties");
+    const std::string tmp = tune_file + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return cvib::fail(CV_EINVAL, "cannot write the tuning file " + tmp);
+    bool ok = fprintf(f, "%s\n", head.c_str()) > 0;
+    for (const auto& kv : resolve_tuned)
+        ok = ok && fprintf(f, "resolve %016llx %d\n", (unsigned long long)kv.first, kv.second) > 0;
+    for (const auto& kv : tiles_tuned)
+        ok = ok && fprintf(f, "tiles %016llx %d\n", (unsigned long long)kv.first, (int)kv.second) > 0;
+    ok = (fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), tune_file.c_str()) != 0) {
+        std::remove(tmp.c_str());
+        return cvib::fail(CV_EINVAL, "cannot write the tuning file " + tune_file);
+    }
+    return CV_OK;
+}
 
 int cv_context::ensure(cvib::Buffer& b, size_t bytes) {
     if (bytes == 0) bytes = 8;
@@ -481,6 +523,91 @@ int cv_context_set_autotune(cv_context* ctx, int on) {
     if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
     ctx->autotune = on != 0;
     return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_context_set_tile_target(cv_context* ctx, int32_t tiles) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    if (tiles != 0 && (tiles < 64 || tiles > (1 << 20))) return fail(CV_EINVAL, "tiles must be 0 or in [64, 2^20]");
+    ctx->tiles_forced = tiles;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_context_tile_target(cv_context* ctx, int64_t n, const cv_grid* grid, int search, int32_t* tiles_host,
+                           int* tuned_host) {
+    CV_GUARD_BEGIN
+    if (!ctx || !tiles_host) return fail(CV_EINVAL, "null argument");
+    if (n < 0) return fail(CV_EINVAL, "n < 0");
+    cvib::GridDev gd;
+    int rc;
+    if ((rc = cvib::make_grid(grid, &gd)) != CV_OK) return rc;
+    const uint64_t key = cvib::tiles_key(search ? 1 : 0, n, gd);
+    *tiles_host = cvib::tiles_target(ctx, key);
+    if (tuned_host) *tuned_host = ctx->tiles_forced == 0 && ctx->tiles_tuned.count(key) ? 1 : 0;
+    return CV_OK;
+    CV_GUARD_END
+}
+
+int cv_context_set_tune_file(cv_context* ctx, const char* path) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    if (!path || !*path) {
+        ctx->tune_file.clear();
+        return CV_OK;
+    }
+    const std::string head = tune_header(ctx->device);
+    if (head.empty()) return fail(CV_EHIP, "hipGetDeviceProperties");
+    std::map<uint64_t, int> res;
+    std::map<uint64_t, int32_t> til;
+    FILE* f = fopen(path, "r");
+    if (f) {
+        char line[512];
+        bool first = true, mine = false, bad = false;
+        while (fgets(line, sizeof line, f)) {
+            std::string t(line);
+            while (!t.empty() && (t.back() == '\n' || t.back() == '\r')) t.pop_back();
+            if (first) {
+                first = false;
+                if (t.rfind("cvib-tune ", 0) != 0) {
+                    bad = true;
+                    break;
+                }
+                mine = t == head;  // another GPU's choices are left unread
+                if (!mine) break;
+                continue;
+            }
+            if (t.empty()) continue;
+            char kind[16];
+            unsigned long long key = 0;
+            int v = 0;
+            char extra = 0;
+            if (sscanf(t.c_str(), "%15s %llx %d %c", kind, &key, &v, &extra) != 3) {
+                bad = true;
+                break;
+            }
+            if (std::strcmp(kind, "resolve") == 0 && v >= 0 && v < cvib::kResolveVariants) {
+                res[(uint64_t)key] = v;
+            } else if (std::strcmp(kind, "tiles") == 0 && tile_choice(v)) {
+                til[(uint64_t)key] = v;
+            } else {
+                bad = true;
+                break;
+            }
+        }
+        fclose(f);
+        if (bad) return fail(CV_EINVAL, std::string("not a tuning file: ") + path);
+    }
+    ctx->tune_file = path;
+    const int rc = ctx->save_tuning();  // creates the file, or checks that it can be written
+    if (rc != CV_OK) {
+        ctx->tune_file.clear();
+        return rc;
+    }
+    for (const auto& kv : res) ctx->resolve_tuned[kv.first] = kv.second;
+    for (const auto& kv : til) ctx->tiles_tuned[kv.first] = kv.second;
+    return ctx->save_tuning();
     CV_GUARD_END
 }
 

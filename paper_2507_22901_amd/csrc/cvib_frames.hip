@@ -950,7 +950,10 @@ int tune_resolve(cv_context* ctx, const FramesCall& call, hipStream_t s) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (rc == CV_OK) ctx->resolve_tuned[key] = best_v;
+    if (rc == CV_OK) {
+        ctx->resolve_tuned[key] = best_v;
+        rc = ctx->save_tuning();
+    }
     return rc;
 }
 

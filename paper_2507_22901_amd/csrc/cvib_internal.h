@@ -138,8 +138,18 @@ struct SearchCall {
     const void* ws[9];  // context workspaces the call uses
     uint32_t flags;
     int32_t cells;
+    int32_t tiles;      // tiles per call of the count pass (plan_reduce's target)
+    int32_t _pad;
     bool same(const SearchCall& o) const;
 };
+
+// Tiles per call of the chunked reduce kernels (the count pass of
+// cv_pair_search, and cv_pair_reduce when colours are few): the default and
+// the choices the autotuner times.
+constexpr int32_t kTilesDefault = 4096;
+constexpr int32_t kTileTargets[5] = {1024, 2048, 4096, 8192, 16384};
+uint64_t tiles_key(int search, int64_t n, const GridDev& gd);
+int32_t tiles_target(cv_context* ctx, uint64_t key);
 
 int run_pair_reduce_rules(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
                           const RuleDev* rules, int32_t nrules, uint32_t* counts, hipStream_t s);
@@ -213,6 +223,13 @@ struct cv_context {
     uint64_t no_high_base = 0;
     // per-colour resolve kernel choice: forced (-1 = none), or tuned per grid shape
     bool autotune = false;
+    // tiles per call of the chunked reduce: forced (0 = none), or tuned per
+    // call shape (count pass or reduce, colours, grid)
+    int32_t tiles_forced = 0;
+    std::map<uint64_t, int32_t> tiles_tuned;
+    // on-disk cache of the tuned choices (cv_context_set_tune_file; empty = none)
+    std::string tune_file;
+    int save_tuning();  // rewrite tune_file with every tuned choice (nothing without one)
     int resolve_forced = -1;
     std::map<uint64_t, int> resolve_tuned;
     hipStream_t cap_stream = nullptr;        // stream used for graph capture

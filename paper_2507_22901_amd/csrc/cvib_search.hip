@@ -1171,9 +1171,12 @@ int launch_reduce(cv_context* ctx, const ReduceArgs& a, bool table, bool direct,
 }
 
 // Tiling of the reduce-only kernel: one tile per colour when there are many
-// colours of moderate size (direct mode), else chunks merged by atomics.  With
-// seg_len > 0 the chunks start on multiples of seg_len and hold at most 2048
-// segments (count pass of the search).
+// colours of moderate size (direct mode), else chunks merged by atomics,
+// about `target` tiles in all (at least 16 blocks of evaluations each; the
+// autotuner's choice, kTilesDefault otherwise).  With seg_len > 0 the chunks
+// start on multiples of seg_len and hold at most 2048 segments (count pass of
+// the search).  Every tiling gives the same results: the merges are integer
+// sums and maxima, and the survivors' order follows the segments.
 struct ReducePlan {
     bool direct;
     int64_t chunk;
@@ -1181,14 +1184,14 @@ struct ReducePlan {
     int64_t ntiles;
 };
 
-ReducePlan plan_reduce(int64_t n, int64_t per, int32_t seg_len) {
+ReducePlan plan_reduce(int64_t n, int64_t per, int32_t seg_len, int32_t target = kTilesDefault) {
     ReducePlan p;
     const int64_t max_chunk = seg_len > 0 ? (int64_t)2048 * seg_len : (int64_t)1 << 30;
     p.direct = n >= 2048 && per <= (1 << 20) && per <= max_chunk;
     if (p.direct) {
         p.chunk = per;
     } else {
-        const int64_t want_tiles_per_colour = (4096 + n - 1) / n;
+        const int64_t want_tiles_per_colour = (target + n - 1) / n;
         int64_t chunk = (per + want_tiles_per_colour - 1) / want_tiles_per_colour;
         if (chunk < 16 * kReduceBlock) chunk = 16 * kReduceBlock;
         const int64_t unit = seg_len > 0 ? seg_len : kReduceBlock;
@@ -1199,6 +1202,66 @@ ReducePlan plan_reduce(int64_t n, int64_t per, int32_t seg_len) {
     p.tpc = (int32_t)((per + p.chunk - 1) / p.chunk);
     p.ntiles = (int64_t)p.tpc * n;
     return p;
+}
+
+// Key of a call shape for the tiling tuner: count pass or reduce, colours,
+// grid size (FNV-1a over the values).
+uint64_t tiles_key_of(int search, int64_t n, const GridDev& gd) {
+    const int64_t v[5] = {search, n, gd.nr, gd.ntheta, gd.N};
+    uint64_t h = 1469598103934665603ull;
+    for (int64_t x : v)
+        for (int b = 0; b < 8; ++b) {
+            h ^= (uint64_t)((x >> (8 * b)) & 0xFF);
+            h *= 1099511628211ull;
+        }
+    return h;
+}
+
+int32_t tiles_target_of(cv_context* ctx, uint64_t key) {
+    if (ctx->tiles_forced > 0) return ctx->tiles_forced;
+    const auto it = ctx->tiles_tuned.find(key);
+    return it == ctx->tiles_tuned.end() ? kTilesDefault : it->second;
+}
+
+// Time fn(target) for every tiling choice (one untimed run each first) and
+// keep the fastest for `key`; the last run leaves the call's outputs in
+// place (every tiling writes the same).  Timing events of the context are off
+// meanwhile.
+template <class F>
+int tune_tiles(cv_context* ctx, uint64_t key, hipStream_t s, F fn) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CV_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    int rc = CV_OK;
+    int32_t best = kTilesDefault;
+    float best_ms = 0.0f;
+    bool have = false;
+    for (int32_t t : kTileTargets) {
+        if ((rc = fn(t)) != CV_OK) break;
+        float ms = 0.0f;
+        if ((he = hipEventRecord(e0, s)) == hipSuccess && (rc = fn(t)) == CV_OK &&
+            (he = hipEventRecord(e1, s)) == hipSuccess && (he = hipEventSynchronize(e1)) == hipSuccess)
+            he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess && rc == CV_OK) rc = hip_fail(he, "timing a tiling");
+        if (rc != CV_OK) break;
+        if (!have || ms < best_ms) {
+            best_ms = ms;
+            best = t;
+            have = true;
+        }
+    }
+    ctx->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != CV_OK) return rc;
+    ctx->tiles_tuned[key] = best;
+    return ctx->save_tuning();
 }
 
 ReduceArgs reduce_args(cv_context* ctx, const TabArgs& tab, const GridDev& gd, const RuleDev& rd,
@@ -1452,7 +1515,7 @@ int enqueue_search(cv_context* ctx, const SearchCall& c, hipStream_t s) {
     const int32_t W = h.W, seg_len = h.seg_len, spc = h.spc;
     const int64_t per = h.per, nsegs = h.nsegs;
     const bool emit = (flags & CV_EMIT_ALL) != 0;
-    const ReducePlan pl = plan_reduce(n, per, seg_len);
+    const ReducePlan pl = plan_reduce(n, per, seg_len, c.tiles);
     // colour constants, angle table, ticket and totals, accumulators: one launch
     TabArgs tab;
     tab.tab = (const double*)ctx->table.ptr;
@@ -1594,6 +1657,21 @@ int run_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     for (int k = 0; k < 9; ++k) call.ws[k] = ws[k]->ptr;
     call.flags = flags & (uint32_t)(CV_EMIT_ALL | CV_NO_NGAMUT);
     call.cells = ctx->gamut_cells ? 1 : 0;
+    // the count pass's tiling: tuned on the first eager call of a shape
+    const uint64_t tkey = tiles_key_of(1, n, gd);
+    {
+        const SearchShape h = search_shape(n, gd);
+        if (ctx->autotune && ctx->tiles_forced == 0 && !ctx->tiles_tuned.count(tkey) && !(flags & CV_GRAPH) &&
+            !plan_reduce(n, h.per, h.seg_len).direct) {
+            SearchCall tc = call;
+            if ((rc = tune_tiles(ctx, tkey, s, [&](int32_t t) {
+                     tc.tiles = t;
+                     return enqueue_search(ctx, tc, s);
+                 })) != CV_OK)
+                return rc;
+        }
+    }
+    call.tiles = tiles_target_of(ctx, tkey);
     if (!(flags & CV_GRAPH)) {
         if ((rc = enqueue_search(ctx, call, s)) != CV_OK) return rc;
     } else {
@@ -1649,14 +1727,14 @@ struct ReduceWs {
 
 static int reduce_in(cv_context* ctx, const ReduceWs& ws, bool timed, const uint8_t* rgb, int64_t n,
                      const GridDev& gd, const RuleDev& rd, cv_color_summary* summ,
-                     cv_table_row* table, hipStream_t s) {
+                     cv_table_row* table, int32_t tiles, hipStream_t s) {
     int rc;
     TabArgs tab;
     if ((rc = prepare_colours_at(ws.colors, ws.table, rgb, n, gd, s, tab)) != CV_OK) return rc;
     const bool sym = gd.ntheta == gd.N;
     const int32_t W = sym ? gd.N / 2 : gd.ntheta;
     const int64_t per = (int64_t)gd.nr * W;  // evaluations per colour
-    const ReducePlan pl = plan_reduce(n, per, 0);
+    const ReducePlan pl = plan_reduce(n, per, 0, tiles);
     if ((rc = zero_u64(ws.misc, 8, s)) != CV_OK) return rc;
     if (!pl.direct && (rc = zero_u64(ws.acc, n * (int64_t)(sizeof(SumAcc) / 8), s)) != CV_OK)
         return rc;
@@ -1692,7 +1770,15 @@ int run_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDe
     if ((rc = ctx->ensure(ctx->acc, (size_t)n * sizeof(SumAcc))) != CV_OK) return rc;
     const ReduceWs ws{(ColorConst*)ctx->colors.ptr, (double*)ctx->table.ptr, (uint64_t*)ctx->misc.ptr,
                       (SumAcc*)ctx->acc.ptr};
-    return reduce_in(ctx, ws, true, rgb, n, gd, rd, summ, table, s);
+    // chunked tilings are tuned on the first call of a shape
+    const uint64_t tkey = tiles_key_of(0, n, gd);
+    const int64_t per = (int64_t)gd.nr * (gd.ntheta == gd.N ? gd.N / 2 : gd.ntheta);
+    if (ctx->autotune && ctx->tiles_forced == 0 && !ctx->tiles_tuned.count(tkey) && !plan_reduce(n, per, 0).direct &&
+        (rc = tune_tiles(ctx, tkey, s, [&](int32_t t) {
+             return reduce_in(ctx, ws, false, rgb, n, gd, rd, summ, table, t, s);
+         })) != CV_OK)
+        return rc;
+    return reduce_in(ctx, ws, true, rgb, n, gd, rd, summ, table, tiles_target_of(ctx, tkey), s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1754,7 +1840,12 @@ int run_pair_reduce_noalloc(cv_context* ctx, const uint8_t* rgb, int64_t n, cons
     ws.colors = (ColorConst*)(base + o);
     o += align256((size_t)n * sizeof(ColorConst));
     ws.acc = (SumAcc*)(base + o);
-    return reduce_in(ctx, ws, false, rgb, n, gd, rd, summ, table, s);
+    return reduce_in(ctx, ws, false, rgb, n, gd, rd, summ, table, tiles_target_of(ctx, tiles_key_of(0, n, gd)), s);
 }
 
+} // namespace cvib
+
+namespace cvib {
+uint64_t tiles_key(int search, int64_t n, const GridDev& gd) { return tiles_key_of(search, n, gd); }
+int32_t tiles_target(cv_context* ctx, uint64_t key) { return tiles_target_of(ctx, key); }
 } // namespace cvib

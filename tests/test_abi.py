@@ -225,6 +225,18 @@ def test_resolve_variant_validation(cv):
     assert L.cv_context_resolve_variant(None, None, 0, C.byref(v), None) == cv.CV_EINVAL
 
 
+def test_tuner_validation(cv):
+    L = cv.lib()
+    d = C.cast((C.c_uint8 * 4096)(), C.c_void_p)
+    assert L.cv_context_set_tile_target(None, 0) == cv.CV_EINVAL
+    assert L.cv_context_set_tile_target(d, 5) == cv.CV_EINVAL
+    assert L.cv_context_set_tile_target(d, (1 << 20) + 1) == cv.CV_EINVAL
+    t = C.c_int32(0)
+    assert L.cv_context_tile_target(None, 1, None, 1, C.byref(t), None) == cv.CV_EINVAL
+    assert L.cv_context_tile_target(d, 1, None, 1, None, None) == cv.CV_EINVAL
+    assert L.cv_context_set_tune_file(None, b"tune.txt") == cv.CV_EINVAL
+
+
 def test_rules_validation(cv):
     L = cv.lib()
     d = C.cast((C.c_uint8 * 4096)(), C.c_void_p)
