@@ -23,6 +23,7 @@
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace cvib {
@@ -282,8 +283,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int32_t bx, int32_t
                 if (a.cbt) {
                     bf16* dst = a.cbt + (int64_t)n * a.ldct + mb;
                     if (mb + 3 < a.M) {
-                        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-                        *reinterpret_cast<bf16x4*>(dst) = bf16x4{r[0], r[1], r[2], r[3]};
+                                                *reinterpret_cast<bf16x4*>(dst) = bf16x4{r[0], r[1], r[2], r[3]};
                     } else {
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
@@ -445,10 +445,12 @@ __device__ __forceinline__ bf16x8 packed_frag(const bf16* __restrict__ Wp, int32
 //   - input layer: per element on the vector ALUs, as k_input_layer<true>
 //     (ReLU or the sinusoid), thread t -> column t % 256, half the rows;
 //   - hidden layers: wave w computes columns 64 (w % 4) .. + 63 of rows
-//     64 (w / 4) .. + 63 (4 x 4 MFMA tiles), the A fragments from LDS, the B
-//     fragments from the packed weights (frag_off) one 32-deep step ahead;
-//     the two waves of a column group read the same fragments, the second
-//     from L1.  Then a barrier, and the bias + ReLU results overwrite the
+//     64 (w / 4) .. + 63 (4 x 4 MFMA tiles), the weights (packed, frag_off)
+//     as the A operand so that a lane's results are four consecutive
+//     columns of one row (one 8-byte LDS store); the two waves of a column
+//     group read the same fragments, the second from L1, and two blocks
+//     share a CU so that one's loads and barriers overlap the other's
+//     products.  Then a barrier, and the bias + ReLU results overwrite the
 //     activations in LDS;
 //   - output layer: wave w computes columns 16 (w % 4) .. + 15 of rows
 //     64 (w / 4) .. + 63.
@@ -456,7 +458,7 @@ __device__ __forceinline__ bf16x8 packed_frag(const bf16* __restrict__ Wp, int32
 // k_gemm, so the results equal the unfused pass bit for bit.
 constexpr int kFusedRows = 128, kFusedWidth = 256, kFusedPitch = kFusedWidth + 8;
 
-__global__ __launch_bounds__(512) void k_mlp_infer_fused(const uint8_t* __restrict__ rgb, int64_t B, int32_t d0,
+__global__ __launch_bounds__(512, 4) void k_mlp_infer_fused(const uint8_t* __restrict__ rgb, int64_t B, int32_t d0,
                                                             int32_t dout, const float* __restrict__ W0,
                                                             const float* __restrict__ b0, float omega0,
                                                             const bf16* __restrict__ W1, const float* __restrict__ b1,
@@ -466,9 +468,11 @@ __global__ __launch_bounds__(512) void k_mlp_infer_fused(const uint8_t* __restri
     constexpr int TM = 4, KS = kFusedWidth / kDepth;  // row tiles per wave, k steps
     __shared__ __attribute__((aligned(16))) bf16 sH[kFusedRows * kFusedPitch];
     __shared__ float s_x[kFusedRows * kMaxIn];
+    __shared__ __attribute__((aligned(16))) float s_bias[2 * kFusedWidth];  // hidden layers 2 and 3
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     const int rg = 64 * (w >> 2), cg = w & 3;  // the wave's first row, column group
+    s_bias[tid] = tid < kFusedWidth ? b1[tid] : b2[tid - kFusedWidth];
     const int64_t r0 = (int64_t)blockIdx.x * kFusedRows;
     const int32_t rows = (int32_t)min((int64_t)kFusedRows, B - r0);
     for (int k = tid; k < kFusedRows * kMaxIn; k += 512) {
@@ -517,44 +521,42 @@ __global__ __launch_bounds__(512) void k_mlp_infer_fused(const uint8_t* __restri
     // hidden layers
     for (int layer = 0; layer < 2; ++layer) {
         const bf16* Wl = layer == 0 ? W1 : W2;
-        const float* bl = layer == 0 ? b1 : b2;
+        const float* bl = s_bias + layer * kFusedWidth;
         f32x4 acc[TM][4];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        bf16x8 fb[4], fbn[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) fb[j] = packed_frag(Wl, KS, 64 * cg + 16 * j + fr, 0, fk);
+        // two blocks share a CU: the other hides this one's fragment loads
+#pragma unroll 2
         for (int ks = 0; ks < KS; ++ks) {
-            if (ks + 1 < KS) {
+            bf16x8 fb[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) fbn[j] = packed_frag(Wl, KS, 64 * cg + 16 * j + fr, ks + 1, fk);
-            }
+            for (int j = 0; j < 4; ++j) fb[j] = packed_frag(Wl, KS, 64 * cg + 16 * j + fr, ks, fk);
+            // weights as the A operand: a lane's results are four consecutive
+            // columns of one row, stored with one 8-byte LDS write
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
                 const bf16x8 fa =
                     *reinterpret_cast<const bf16x8*>(sH + (rg + 16 * i + fr) * kFusedPitch + kDepth * ks + fk);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[j], fa, acc[i][j], 0, 0, 0);
             }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) fb[j] = fbn[j];
         }
-        float bias[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bias[j] = bl[64 * cg + 16 * j + fr];
         __syncthreads();  // every wave has read the layer's input
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int j = 0; j < 4; ++j) {
+            const int n = 64 * cg + 16 * j + (lane >> 4) * 4;
+            const float4 bias = *reinterpret_cast<const float4*>(bl + n);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int m = rg + 16 * i + (lane >> 4) * 4 + e, n = 64 * cg + 16 * j + fr;
-                    sH[m * kFusedPitch + n] = (bf16)fmaxf(acc[i][j][e] + bias[j], 0.0f);
-                }
+            for (int i = 0; i < TM; ++i) {
+                const int m = rg + 16 * i + fr;
+                const bf16x4 v = {(bf16)fmaxf(acc[i][j][0] + bias.x, 0.0f), (bf16)fmaxf(acc[i][j][1] + bias.y, 0.0f),
+                                  (bf16)fmaxf(acc[i][j][2] + bias.z, 0.0f), (bf16)fmaxf(acc[i][j][3] + bias.w, 0.0f)};
+                *reinterpret_cast<bf16x4*>(sH + m * kFusedPitch + n) = v;
+            }
+        }
         __syncthreads();
     }
     // output layer: 64 columns (dout <= 64, rows of W3 padded with zeros)
@@ -846,7 +848,6 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 constexpr int kTrainRows = 32, kTW = 256, kTPitch = kTW + 8, kTThreads = 1024, kTWaves = kTThreads / 64;
 constexpr int kTK = kTW / kDepth;  // 32-deep k steps of a hidden layer
 constexpr int kGP = 72;            // LDS pitch of the output gradient [32][64]
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 struct TrainArgs {
     const int32_t* ids;          // [B] colour ids (low 24 bits)
