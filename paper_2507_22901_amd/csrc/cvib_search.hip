@@ -607,6 +607,11 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
     __shared__ uint8_t s_colv[LISTS ? kMaxCols : 1];
     __shared__ uint16_t s_list[LISTS ? kMaxListed : 1];
     __shared__ int32_t s_nlist;
+    // with the coarse cells: the open steps, in proof order (bit 15: may hold
+    // a high channel), dealt to the waves in turn, so that every wave of the
+    // block gets as many as the others whatever rows they fall in
+    __shared__ uint16_t s_olist[LISTS ? kMaxListed : 1];
+    __shared__ int32_t s_nopen;
 
     const int tid = threadIdx.x;
     const uint32_t lane = (uint32_t)tid & 63u;
@@ -649,6 +654,7 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
         const int32_t jb0 = begin - row0 * a.W;  // ray of the tile's first evaluation
         const int32_t iters = (len + BLOCK - 1) / BLOCK;
         const int32_t nwords = (iters + 63) >> 6;
+        bool coarse_tile = false;  // the open steps are in s_olist (else in the per-wave masks)
         if constexpr (CELLS && !(DIRECT && !SEG)) {
             // Which wave steps hold a candidate that may be in gamut.  Step s
             // = (it, wv) = it NW + wv covers evaluations 64 s .. 64 s + 63 of
@@ -664,6 +670,7 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
             const int32_t nsteps = iters * NW;
             const int32_t ncol = (a.W + 63) >> 6;
             const bool coarse = ncol >= 2 && ncol <= kMaxCols && nsteps <= kMaxListed;
+            coarse_tile = coarse;
             const bool need_ng = a.need_ng != 0;
             int32_t nlisted = nsteps;
             if (coarse) {
@@ -674,7 +681,10 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                                                        min(64 * q + 63, a.W - 1), &a.rule, &high);
                     s_colv[q] = out ? 1 : (high ? 0 : 2);  // 1: out of gamut, 2: no high channel
                 }
-                if (tid == 0) s_nlist = 0;
+                if (tid == 0) {
+                    s_nlist = 0;
+                    s_nopen = 0;
+                }
                 __syncthreads();
                 for (int32_t sx = tid; sx < nsteps; sx += BLOCK) {
                     const int32_t e0 = 64 * sx;
@@ -718,10 +728,18 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                 // without n_gamut, a step without a high channel needs nothing
                 const bool take = open && (high || need_ng);
                 if (any && !take) skipped += (uint64_t)(e1 - e0 + 1);
-                if (take)
-                    atomicOr((unsigned long long*)&s_open[wv * a.cell_words + (it >> 6)], 1ull << (it & 63));
-                if (open && high)
-                    atomicOr((unsigned long long*)&s_full[wv * a.cell_words + (it >> 6)], 1ull << (it & 63));
+                if (coarse) {
+                    const uint64_t tk = __ballot(take);
+                    int32_t basew = 0;
+                    if (lane == 0 && tk) basew = atomicAdd(&s_nopen, (int32_t)__builtin_popcountll(tk));
+                    basew = __shfl(basew, 0, 64);
+                    if (take) s_olist[basew + (int32_t)rank_below(tk)] = (uint16_t)(sidx | ((open && high) ? 0x8000 : 0));
+                } else {
+                    if (take)
+                        atomicOr((unsigned long long*)&s_open[wv * a.cell_words + (it >> 6)], 1ull << (it & 63));
+                    if (open && high)
+                        atomicOr((unsigned long long*)&s_full[wv * a.cell_words + (it >> 6)], 1ull << (it & 63));
+                }
             }
             __syncthreads();
         }
@@ -829,8 +847,20 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
             }
             if (lane == 0) skipped += (w == 0 ? (uint64_t)len : 0ull) - evald;
         } else if constexpr (CELLS) {
-            // the open steps of this wave, (i, j) from the step index
-            for (int32_t word = 0; word < nwords; ++word) {
+            const int32_t nopen = (LISTS && coarse_tile) ? s_nopen : 0;
+            // the open steps dealt in turn (coarse cells), (i, j) from the step index
+            for (int32_t q = w; q < nopen; q += NW) {
+                const uint32_t ent = s_olist[q];
+                const int32_t sidx = (int32_t)(ent & 0x7FFFu);
+                const int32_t it = sidx / NW, wv = sidx - it * NW;
+                const int32_t e = it * BLOCK + wv * 64 + (int32_t)lane;
+                int32_t i, j;
+                divmod_small(jb0 + min(e, len - 1), a.W, a.inv_W, i, j);
+                if (ent & 0x8000u) step(i + row0, j, e, e < len);
+                else gamut_step(i + row0, j, e < len);
+            }
+            // else the open steps of this wave, (i, j) from the step index
+            for (int32_t word = 0; word < (coarse_tile ? 0 : nwords); ++word) {
                 uint64_t steps = uniform_u64(s_open[w * a.cell_words + word]);
                 const uint64_t full = uniform_u64(s_full[w * a.cell_words + word]);
                 while (steps) {
