@@ -79,12 +79,12 @@ FLOPS_CELL = 84
 # GRBM_GUI_ACTIVE cycles per XCD.  Valid only for the kernel sources they were
 # measured on (their digest); null otherwise.
 MEASURED_COUNTERS = {
-    "count_pass": {"sources_sha256": "2731c18f21375281b953052a216af69508295257a4a88037bc093411ff9ecbac",
-                   "traffic_bytes": 49374049, "valu_issue": 0.510},
+    "count_pass": {"sources_sha256": "7f819a3d585b0b1d191b0a5dd09005670345c7b20ec497c51ea20abe8ac8d1ff",
+                   "traffic_bytes": 55112478, "valu_issue": 0.532},
     "colour_resolve": {"sources_sha256": "45e09672734ade086c4b8eb88e5b32bf058bad65ba08f13119e2ec9723ed46b0",
                    "traffic_bytes": 7275424193, "valu_issue": 0.974},
-    "cube_table": {"sources_sha256": "2731c18f21375281b953052a216af69508295257a4a88037bc093411ff9ecbac",
-                   "traffic_bytes": 3571960016, "valu_issue": 0.947},
+    "cube_table": {"sources_sha256": "7f819a3d585b0b1d191b0a5dd09005670345c7b20ec497c51ea20abe8ac8d1ff",
+                   "traffic_bytes": 3568505768, "valu_issue": 0.947},
     "ray_search": {"sources_sha256": "6d0528e242ff118e1584b4863e146ee703b6bc7a4d9dc6e6fe88d7ed6a29db6d",
                    "traffic_bytes": 6098304309, "valu_issue": 0.839},
 }
