@@ -903,28 +903,23 @@ __device__ __forceinline__ void tile_products(f32x4 (&acc)[TM], const bf16* sA, 
         }
 }
 
-// A block's activations sH [kTrainRows][kTPitch] to global memory,
-// transposed [256][ldt].
-__device__ __forceinline__ void store_acts(const bf16* sH, int64_t r0, int64_t B, bf16* ht, int64_t ldt, int tid) {
-    for (int u = tid; u < kTW * (kTrainRows / 8); u += kTThreads) {
-        const int o = u / (kTrainRows / 8), rc = (u % (kTrainRows / 8)) * 8;
-        bf16x8 v;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = sH[(rc + e) * kTPitch + o];
-        bf16* d = ht + (int64_t)o * ldt + r0 + rc;
-        if (r0 + rc + 8 <= B) {
-            *reinterpret_cast<bf16x8*>(d) = v;
-        } else {
-            for (int e = 0; e < 8 && r0 + rc + e < B; ++e) d[e] = v[e];
-        }
-    }
+// Rows mb .. mb + 3 of one column of a transposed operand (dst = its row
+// at mb), written whole: the operands' rows are padded to whole blocks of
+// kTrainRows, and what lands past the batch is never read.  The kernel's
+// global stores have no branch around them, so that the compiler knows how
+// many memory operations follow each load and never waits for a store when
+// it waits for a load (the counters count both).
+__device__ __forceinline__ void store_col4(bf16* __restrict__ dst, const bf16 (&r)[4]) {
+    *reinterpret_cast<bf16x4*>(dst) = bf16x4{r[0], r[1], r[2], r[3]};
 }
 
 // Epilogue of one backward layer for column n: the products times the
 // activation derivative (sine: the factor; else the ReLU mask), rounded to
-// BF16, to sOut (LDS, when non-null) and transposed to gt (when non-null);
-// the column's sums over the block's rows to pb, or with x (sx) the input
-// layer's sums to p0.
+// BF16.  Not FIRST: to sOut (LDS) and transposed to gt, the column's sums
+// over the block's rows to pb.  FIRST (the first hidden layer): with x (sx)
+// the input layer's sums to p0.  Every lane stores the column's sums (the
+// four lanes of a column hold the same values), so no branch holds a store.
+template <bool FIRST>
 __device__ __forceinline__ void back_epilogue(const f32x4 (&acc)[kTrainRows / 16], const float (&d)[kTrainRows / 16][4],
                                               bool sine, bf16* sOut, bf16* __restrict__ gt, int64_t ldt,
                                               float* __restrict__ pb, const float* sx, float* __restrict__ p0,
@@ -944,41 +939,33 @@ __device__ __forceinline__ void back_epilogue(const f32x4 (&acc)[kTrainRows / 16
             }
             const float rv = (float)r[e];
             cs += rv;
-            if (p0) {
+            if constexpr (FIRST) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) cx[c] = fmaf(rv, sx[mm * 4 + c], cx[c]);
-            }
-            if (sOut) sOut[mm * kTPitch + n] = r[e];
-        }
-        if (gt) {
-            bf16* dst = gt + (int64_t)n * ldt + r0 + mb;
-            if (mb + 3 < rows) {
-                *reinterpret_cast<bf16x4*>(dst) = bf16x4{r[0], r[1], r[2], r[3]};
             } else {
-                for (int e = 0; e < 4; ++e)
-                    if (mb + e < rows) dst[e] = r[e];
+                sOut[mm * kTPitch + n] = r[e];
             }
         }
+        if constexpr (!FIRST) store_col4(gt + (int64_t)n * ldt + r0 + mb, r);
     }
-    // the four lane groups hold the other rows of column n
+    // the four lane groups hold the other rows of column n (each lane adds
+    // the same pairs: the same value on all four)
     cs += __shfl_xor(cs, 16, 64);
     cs += __shfl_xor(cs, 32, 64);
-    if (p0) {
+    if constexpr (FIRST) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             cx[c] += __shfl_xor(cx[c], 16, 64);
             cx[c] += __shfl_xor(cx[c], 32, 64);
         }
     }
-    if (lane < 16) {
-        if (p0) {
-            p0[(int64_t)n * 4 + 0] = cx[0];
-            p0[(int64_t)n * 4 + 1] = cx[1];
-            p0[(int64_t)n * 4 + 2] = cx[2];
-            p0[(int64_t)n * 4 + 3] = cs;
-        } else {
-            pb[n] = cs;
-        }
+    if constexpr (FIRST) {
+        p0[(int64_t)n * 4 + 0] = cx[0];
+        p0[(int64_t)n * 4 + 1] = cx[1];
+        p0[(int64_t)n * 4 + 2] = cx[2];
+        p0[(int64_t)n * 4 + 3] = cs;
+    } else {
+        pb[n] = cs;
     }
 }
 
@@ -991,6 +978,16 @@ __device__ __forceinline__ void lds_mask(float (&d)[kTrainRows / 16][4], const b
         for (int e = 0; e < 4; ++e) d[i][e] = (float)sH[(16 * i + (lane >> 4) * 4 + e) * kTPitch + n];
 }
 
+// The same masks from bits kept by the forward pass (bit b0 + 4 i + e set
+// where that activation is positive): the lane's forward results are the
+// same rows of the same column.
+__device__ __forceinline__ void bit_mask(float (&d)[kTrainRows / 16][4], uint32_t bits, int b0) {
+#pragma unroll
+    for (int i = 0; i < kTrainRows / 16; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[i][e] = (bits >> (b0 + 4 * i + e)) & 1u ? 1.0f : 0.0f;
+}
+
 __global__ __launch_bounds__(kTThreads) void k_train_step(TrainArgs a) {
     constexpr int TM = kTrainRows / 16;  // MFMA row tiles per wave
     __shared__ __attribute__((aligned(16))) bf16 sH1[kTrainRows * kTPitch];
@@ -998,7 +995,7 @@ __global__ __launch_bounds__(kTThreads) void k_train_step(TrainArgs a) {
     __shared__ __attribute__((aligned(16))) bf16 sH3[kTrainRows * kTPitch];
     __shared__ __attribute__((aligned(16))) bf16 sG[kTrainRows * kGP];
     __shared__ float s_w0[kTW * 4];
-    __shared__ float s_x[kTrainRows * 4];
+    __shared__ __attribute__((aligned(16))) float s_x[kTrainRows * 4];
     __shared__ uint32_t s_row[kTrainRows * 10];  // the rows' table entries (cv_table_row, 40 bytes)
     __shared__ float s_red[kTWaves];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -1010,44 +1007,52 @@ __global__ __launch_bounds__(kTThreads) void k_train_step(TrainArgs a) {
     // Loads in the order they are waited for (the counters are in order): the
     // input layer's weights and the ids, then the W1 fragments, then the
     // rows' table entries (thread -> 4 bytes of row tid / 10), which only the
-    // loss needs and which reach LDS just before it.
+    // loss needs and which reach LDS just before it.  Every thread loads (an
+    // id of the block's last row, the first word of entry 0 past the rows):
+    // no branch holds a load, so none is waited for before its use.
     const float w0v = tid < kTW * 3 ? a.W0[tid] : a.b0[tid - kTW * 3];
     const int rr = tid / 10;
-    uint32_t rid = 0;
-    if (tid < kTrainRows * 10 && rr < rows) rid = (uint32_t)a.ids[r0 + rr] & 0xFFFFFFu;
+    const uint32_t idw = (uint32_t)a.ids[r0 + min(rr, rows - 1)];
+    __builtin_amdgcn_sched_barrier(0);  // these two first: the first barrier waits for them alone
     bf16x8 fb[kTK];
     load_frags(fb, a.W1, n, fk);
-    const float bias1 = a.b1[n], bias2 = a.b2[n];
-    uint32_t tword = 0;
-    if (tid < kTrainRows * 10) tword = reinterpret_cast<const uint32_t*>(a.table + rid)[tid - 10 * rr];
+    const int no = 16 * (w & 3) + fr;  // the output column of waves 0..7
+    const float bias1 = a.b1[n], bias2 = a.b2[n], bias3 = a.b3[no < 37 ? no : 0];
+    const bool rowthread = tid < kTrainRows * 10;
+    const uint32_t rid = rowthread && rr < rows ? idw & 0xFFFFFFu : 0u;
+    const uint32_t tword = reinterpret_cast<const uint32_t*>(a.table + rid)[rowthread ? tid - 10 * rr : 0];
     s_w0[tid] = w0v;
     // the block's training rows (k_table_batch's arithmetic)
-    if (tid < kTrainRows * 10 && tid == 10 * rr) {
+    if (rowthread && tid == 10 * rr) {
         s_x[rr * 4 + 0] = rgb_input(rid >> 16);
         s_x[rr * 4 + 1] = rgb_input((rid >> 8) & 255u);
         s_x[rr * 4 + 2] = rgb_input(rid & 255u);
         s_x[rr * 4 + 3] = 0.0f;
     }
     __syncthreads();
-    // input layer (k_input_layer's arithmetic): thread -> row tid / 32, 8 columns
+    // input layer (k_input_layer's arithmetic): thread -> column tid % 256,
+    // 8 rows (consecutive columns over the lanes: no LDS bank conflicts),
+    // stored transposed as one 16-byte chunk
+    static_assert(kTW * (kTrainRows / 8) == kTThreads, "input layer: one thread per column and 8 rows");
     {
-        const int row = tid >> 5, c0 = (tid & 31) * 8;
-        const float x0 = s_x[row * 4 + 0], x1 = s_x[row * 4 + 1], x2 = s_x[row * 4 + 2];
+        const int o = tid & (kTW - 1), rg = (tid / kTW) * 8;
+        const float w00 = s_w0[o * 3 + 0], w01 = s_w0[o * 3 + 1], w02 = s_w0[o * 3 + 2], bo = s_w0[kTW * 3 + o];
         bf16x8 v;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const int o = c0 + e;
-            float acc = s_w0[kTW * 3 + o];
-            acc = fmaf(s_w0[o * 3 + 0], x0, acc);
-            acc = fmaf(s_w0[o * 3 + 1], x1, acc);
-            acc = fmaf(s_w0[o * 3 + 2], x2, acc);
+            const float4 x = *reinterpret_cast<const float4*>(s_x + (rg + e) * 4);
+            float acc = bo;
+            acc = fmaf(w00, x.x, acc);
+            acc = fmaf(w01, x.y, acc);
+            acc = fmaf(w02, x.z, acc);
             v[e] = (bf16)first_act(acc, a.omega0);
+            sH1[(rg + e) * kTPitch + o] = v[e];
         }
-        *reinterpret_cast<bf16x8*>(sH1 + row * kTPitch + c0) = v;
+        *reinterpret_cast<bf16x8*>(a.h1t + (int64_t)o * a.ldt + r0 + rg) = v;
     }
     __syncthreads();
-    store_acts(sH1, r0, a.B, a.h1t, a.ldt, tid);
     f32x4 acc[TM];
+    uint32_t mbits = 0;  // ReLU masks of the lane's results in hidden layers 2 (bits 0..7) and 3 (8..15)
     // hidden layer 2 (sH1 -> sH2), then 3 (sH2 -> sH3)
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
@@ -1056,18 +1061,23 @@ __global__ __launch_bounds__(kTThreads) void k_train_step(TrainArgs a) {
         tile_products<TM, kTK>(acc, sIn, kTPitch, 0, fb, fr, fk);
         // the next layer's fragments in flight during the epilogue
         if (layer == 0) load_frags(fb, a.W2, n, fk);
-        else if (w < 8) load_frags(fb, a.W3, 16 * (w & 3) + fr, fk);
+        else if (w < 8) load_frags(fb, a.W3, no, fk);
         const float bias = layer == 0 ? bias1 : bias2;
+        bf16* ht = (layer == 0 ? a.h2t : a.h3t) + (int64_t)n * a.ldt + r0;
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i) {
+            const int mb = 16 * i + (lane >> 4) * 4;
+            bf16 r[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int mm = 16 * i + (lane >> 4) * 4 + e;
-                sOut[mm * kTPitch + n] = (bf16)fmaxf(acc[i][e] + bias, 0.0f);
+                r[e] = (bf16)fmaxf(acc[i][e] + bias, 0.0f);
+                sOut[(mb + e) * kTPitch + n] = r[e];
+                if ((float)r[e] > 0.0f) mbits |= 1u << (8 * layer + 4 * i + e);
             }
+            store_col4(ht + mb, r);
+        }
         if (layer == 1 && tid < kTrainRows * 10) s_row[tid] = tword;
         __syncthreads();
-        store_acts(sOut, r0, a.B, layer == 0 ? a.h2t : a.h3t, a.ldt, tid);
     }
     // output layer: waves 0..7, wave w -> row tile w / 4, columns 16 (w % 4) ..;
     // the loss and its gradient (k_loss's arithmetic) in the epilogue, the
@@ -1076,12 +1086,12 @@ __global__ __launch_bounds__(kTThreads) void k_train_step(TrainArgs a) {
     load_frags(f3, a.W3t, n, fk);
     float ls = 0.0f;
     if (w < 8) {
-        const int i = w >> 2, no = 16 * (w & 3) + fr;
+        const int i = w >> 2;
         f32x4 ao[1];
         tile_products<1, kTK>(ao, sH3, kTPitch, i, fb, fr, fk);
         const int32_t R = 36;
         const float invR = 1.0f / (float)R, invB = 1.0f / (float)a.B;
-        const float bias = a.b3[no < 37 ? no : 0];
+        const float bias = bias3;
         const int mb = 16 * i + (lane >> 4) * 4;
         bf16 gv[4];
 #pragma unroll
@@ -1108,20 +1118,14 @@ __global__ __launch_bounds__(kTThreads) void k_train_step(TrainArgs a) {
             gv[e] = (bf16)g;
             sG[mm * kGP + no] = gv[e];
         }
-        bf16* d = a.goutt + (int64_t)no * a.ldt + r0 + mb;
-        if (mb + 3 < rows) {
-            *reinterpret_cast<bf16x4*>(d) = bf16x4{gv[0], gv[1], gv[2], gv[3]};
-        } else {
-            for (int e = 0; e < 4; ++e)
-                if (mb + e < rows) d[e] = gv[e];
-        }
+        store_col4(a.goutt + (int64_t)no * a.ldt + r0 + mb, gv);
     }
     load_frags(f2, a.W2t, n, fk);
     // the block's loss: each wave's sum, then the waves in order
     for (int off = 32; off > 0; off >>= 1) ls += __shfl_xor(ls, off, 64);
     if (lane == 0) s_red[w] = ls;
     float d[TM][4];
-    lds_mask(d, sH3, n, lane);
+    bit_mask(d, mbits, 8);
     __syncthreads();
     if (tid == 0) {
         float t = 0.0f;
@@ -1139,12 +1143,12 @@ __global__ __launch_bounds__(kTThreads) void k_train_step(TrainArgs a) {
     tile_products<TM, 64 / kDepth>(acc, sG, kGP, 0, f3, fr, fk);
     bf16x8 f1[kTK];
     load_frags(f1, a.W1t, n, fk);
-    back_epilogue(acc, d, false, sH3, a.g3t, a.ldt, a.pb2 + blk * kTW, nullptr, nullptr, r0, rows, n, lane);
-    lds_mask(d, sH2, n, lane);
+    back_epilogue<false>(acc, d, false, sH3, a.g3t, a.ldt, a.pb2 + blk * kTW, nullptr, nullptr, r0, rows, n, lane);
+    bit_mask(d, mbits, 0);
     __syncthreads();
     // backward layer 2: G2 = (G3 W2) . [H2 > 0] -> sH2 (over H2), G2^T
     tile_products<TM, kTK>(acc, sH3, kTPitch, 0, f2, fr, fk);
-    back_epilogue(acc, d, false, sH2, a.g2t, a.ldt, a.pb1 + blk * kTW, nullptr, nullptr, r0, rows, n, lane);
+    back_epilogue<false>(acc, d, false, sH2, a.g2t, a.ldt, a.pb1 + blk * kTW, nullptr, nullptr, r0, rows, n, lane);
     const bool sine = a.omega0 > 0.0f;
     if (sine) {
         // omega0 cos(omega0 z), z = b0 + W0 x: the forward's operations in its order
@@ -1165,7 +1169,7 @@ __global__ __launch_bounds__(kTThreads) void k_train_step(TrainArgs a) {
     __syncthreads();
     // backward layer 1: G1 = (G2 W1) . act'(z1); the input layer's sums
     tile_products<TM, kTK>(acc, sH2, kTPitch, 0, f1, fr, fk);
-    back_epilogue(acc, d, sine, nullptr, nullptr, a.ldt, nullptr, s_x, a.p0 + blk * kTW * 4, r0, rows, n, lane);
+    back_epilogue<true>(acc, d, sine, nullptr, nullptr, a.ldt, nullptr, s_x, a.p0 + blk * kTW * 4, r0, rows, n, lane);
 }
 
 struct SumAdamArgs {
@@ -1370,7 +1374,7 @@ struct cv_mlp {
     bf16* g[2] = {nullptr, nullptr};    // back-propagated gradients [bcap][gw]
     int32_t gw = 0;                     // widest padded layer
     // k-contiguous copies for the weight-gradient products, rows of length ldt
-    // (the kept batch rounded up to 8): H_l transposed [d_l][ldt] and the
+    // (the kept batch rounded up to 8; allocated for the batch rounded up to a whole block of the fused step): H_l transposed [d_l][ldt] and the
     // back-propagated gradients transposed [gw][ldt]
     bf16* ht[cvib::kMaxLayers] = {};
     bf16* gt[3] = {nullptr, nullptr, nullptr};
@@ -1432,13 +1436,14 @@ int ensure_rows(cv_mlp* m, int64_t rows) {
     if (m->dsin) CV_HIP(hipFree(m->dsin));
     m->dsin = nullptr;
     m->bcap = 0;
-    const size_t r8 = (size_t)((rows + 7) / 8 * 8);
+    // transposed rows: the batch rounded up to whole blocks of the fused step
+    const size_t rt = (size_t)((rows + kTrainRows - 1) / kTrainRows * kTrainRows);
     for (int l = 1; l < m->L; ++l) {
         CV_HIP(hipMalloc((void**)&m->h[l], (size_t)rows * m->dims[l] * sizeof(bf16)));
-        CV_HIP(hipMalloc((void**)&m->ht[l], r8 * m->dims[l] * sizeof(bf16)));
+        CV_HIP(hipMalloc((void**)&m->ht[l], rt * m->dims[l] * sizeof(bf16)));
     }
     for (bf16*& q : m->g) CV_HIP(hipMalloc((void**)&q, (size_t)rows * m->gw * sizeof(bf16)));
-    for (bf16*& q : m->gt) CV_HIP(hipMalloc((void**)&q, r8 * m->gw * sizeof(bf16)));
+    for (bf16*& q : m->gt) CV_HIP(hipMalloc((void**)&q, rt * m->gw * sizeof(bf16)));
     CV_HIP(hipMalloc((void**)&m->dsin, (size_t)rows * m->dims[1] * sizeof(float)));
     m->bcap = rows;
     return CV_OK;
@@ -1740,7 +1745,9 @@ int ensure_train(cv_mlp* m, int64_t B) {
 int train_step_fused(cv_mlp* m, const int32_t* ids, int64_t nb, const cv_table_row* table, double dr,
                      float delta, float lr, int64_t t, float* loss, hipStream_t s) {
     int rc;
-    const int64_t ldt = (nb + 7) / 8 * 8;
+    // transposed rows padded to whole blocks (k_train_step writes every row of a block)
+    const int64_t ldt = (nb + kTrainRows - 1) / kTrainRows * kTrainRows;
+    if (nb > m->bcap) return fail(CV_ESTATE, "internal: training buffers smaller than the batch");
     const int32_t nblk = (int32_t)((nb + kTrainRows - 1) / kTrainRows);
     const int32_t splits = (int32_t)((nb + kSplitRows - 1) / kSplitRows);
     // weight partials of the three matrix-core layers side by side
