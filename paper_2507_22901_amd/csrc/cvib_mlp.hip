@@ -299,10 +299,31 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     gemm_tile<A_KC, B_KC, EPI, BM, BN, KD>(a, (int32_t)blockIdx.x, (int32_t)blockIdx.y, (int32_t)blockIdx.z);
 }
 
+struct SumAdamArgs {
+    float* p; float* g; float* m; float* v;
+    float lr, b1, b2, eps, c1, c2;
+    int64_t woff[4], boff[4];
+    int32_t din[4], dout[4], dpad[4];   // per layer l: inputs, outputs, padded outputs
+    const float* wpart[4];     // l = 1..3: [wsplits][dpad][din]
+    int32_t wsplits;
+    const float* bpart[4];     // l = 1..3: [nblk][bw[l]] (bias of layer l)
+    int32_t bw[4];
+    const float* p0;           // [nblk][256][4]
+    int32_t nblk;
+    int32_t nlong;             // parameters summed over the row blocks
+    bf16* wb[4]; bf16* wpf[4]; bf16* wpb[4];
+    const float* lpart; float* loss; int64_t B;
+};
+
+// The input layer's weights and every bias: gradients summed over the row
+// blocks, and their Adam step (block blk of ceil(nlong / 4); defined below).
+__device__ void sum_adam_long(const SumAdamArgs& a, int32_t blk);
+
 // Up to three products of one kind in one launch: blockIdx.z = problem *
 // splits + split; blocks beyond a problem's row tiles return at once.
 struct GemmBatch {
     GemmArgs g[3];
+    int32_t lblocks;           // k_wgrad: leading blocks that run sum_adam_long (a multiple of 8)
     int32_t splits;
     int32_t mtiles[3];
     int32_t ntiles[3];
@@ -349,9 +370,18 @@ constexpr int kWgBM = 64, kWgBN = 64;
 // L % 8 + 8 q with q = (L / 8) / tiles, tile (L / 8) % tiles.  Every tile of
 // a split then runs on one XCD and the split's operands come into that XCD's
 // L2 once.  (Issuing all of a split's loads at once, held in registers, was
-// slower: 13.7 against 12.8 us for the surrogate's 8192-row step.)
-__global__ __launch_bounds__(256) void k_wgrad(GemmBatch b) {
-    const int32_t L = (int32_t)blockIdx.x, xcd = L & 7, j = L >> 3;
+// slower: 13.7 against 12.8 us for the surrogate's 8192-row step.)  The
+// first b.lblocks blocks instead sum the gradients of the input layer and the
+// biases over the training step's row blocks and take their Adam step
+// (sum_adam_long), which needs only the step's own partials: that work runs
+// beside the products rather than in a launch of its own.  lblocks is a
+// multiple of 8, so the XCD of every product block stays L % 8.
+__global__ __launch_bounds__(256) void k_wgrad(GemmBatch b, SumAdamArgs sa) {
+    if ((int32_t)blockIdx.x < b.lblocks) {
+        sum_adam_long(sa, (int32_t)blockIdx.x);
+        return;
+    }
+    const int32_t L = (int32_t)blockIdx.x - b.lblocks, xcd = L & 7, j = L >> 3;
     const int32_t z = xcd + 8 * (j / b.toff[3]), t = j % b.toff[3];
     if (z >= b.splits) return;
     const int32_t p = t < b.toff[1] ? 0 : t < b.toff[2] ? 1 : 2;
@@ -360,8 +390,10 @@ __global__ __launch_bounds__(256) void k_wgrad(GemmBatch b) {
     gemm_tile<true, true, EPI_PARTIAL_F32, 64, 64, 64>(a, bx, by, z);
 }
 
-int gemm_wgrad3(const GemmArgs (&g)[3], int32_t splits, hipStream_t s) {
+int gemm_wgrad3(const GemmArgs (&g)[3], int32_t splits, const SumAdamArgs& sa, int32_t lblocks, hipStream_t s) {
+    if (lblocks < 0 || lblocks % 8 != 0) return fail(CV_ESTATE, "internal: leading blocks of the weight gradients");
     GemmBatch b = {};
+    b.lblocks = lblocks;
     for (int p = 0; p < 3; ++p) {
         const GemmArgs& a = g[p];
         const bool ok = a.lda % 8 == 0 && a.ldb % 8 == 0 && a.kchunk % 64 == 0 && a.M > 0 && a.N > 0 &&
@@ -373,8 +405,8 @@ int gemm_wgrad3(const GemmArgs (&g)[3], int32_t splits, hipStream_t s) {
         b.toff[p + 1] = b.toff[p] + b.mtiles[p] * b.ntiles[p];
     }
     b.splits = splits;
-    const int64_t nblocks = (int64_t)8 * ((splits + 7) / 8) * b.toff[3];
-    hipLaunchKernelGGL(k_wgrad, dim3((unsigned)nblocks), dim3(256), 0, s, b);
+    const int64_t nblocks = lblocks + (int64_t)8 * ((splits + 7) / 8) * b.toff[3];
+    hipLaunchKernelGGL(k_wgrad, dim3((unsigned)nblocks), dim3(256), 0, s, b, sa);
     CV_HIP(hipGetLastError());
     return CV_OK;
 }
@@ -1172,51 +1204,55 @@ __global__ __launch_bounds__(kTThreads) void k_train_step(TrainArgs a) {
     back_epilogue<true>(acc, d, sine, nullptr, nullptr, a.ldt, nullptr, s_x, a.p0 + blk * kTW * 4, r0, rows, n, lane);
 }
 
-struct SumAdamArgs {
-    float* p; float* g; float* m; float* v;
-    float lr, b1, b2, eps, c1, c2;
-    int64_t woff[4], boff[4];
-    int32_t din[4], dout[4], dpad[4];   // per layer l: inputs, outputs, padded outputs
-    const float* wpart[4];     // l = 1..3: [wsplits][dpad][din]
-    int32_t wsplits;
-    const float* bpart[4];     // l = 1..3: [nblk][bw[l]] (bias of layer l)
-    int32_t bw[4];
-    const float* p0;           // [nblk][256][4]
-    int32_t nblk;
-    int32_t wblocks;           // blocks of the matrix-core weights
-    int32_t nlong;             // parameters summed over the row blocks
-    bf16* wb[4]; bf16* wpf[4]; bf16* wpb[4];
-    const float* lpart; float* loss; int64_t B;
-};
 
-// Adam on parameter i with gradient gi and its moments and value m0, v0, p0
-// (loaded before the gradient's sum, so that their latency overlaps it); l >=
-// 1: weight k of layer l (its BF16 copies follow), else none.
-__device__ __forceinline__ void adam_one(const SumAdamArgs& a, int64_t i, float gi, int l, int64_t k, float m0,
-                                         float v0, float p0) {
-    a.g[i] = gi;
-    const float mi = a.b1 * m0 + (1.0f - a.b1) * gi;
-    const float vi = a.b2 * v0 + (1.0f - a.b2) * gi * gi;
-    a.m[i] = mi;
-    a.v[i] = vi;
-    const float pi = p0 - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
-    a.p[i] = pi;
-    if (l > 0) {
-        const int32_t o = (int32_t)(k / a.din[l]), c = (int32_t)(k - (int64_t)o * a.din[l]);
-        a.wb[l][k] = (bf16)pi;
-        a.wpf[l][frag_off(o, c, a.din[l] / 32)] = (bf16)pi;
-        a.wpb[l][frag_off(c, o, a.dpad[l] / 32)] = (bf16)pi;
-    }
+// One Adam step: new moments mi, vi and value pi from gradient gi and the
+// old moments and value m0, v0, p0.
+__device__ __forceinline__ void adam_math(const SumAdamArgs& a, float gi, float m0, float v0, float p0, float& mi,
+                                          float& vi, float& pi) {
+    mi = a.b1 * m0 + (1.0f - a.b1) * gi;
+    vi = a.b2 * v0 + (1.0f - a.b2) * gi * gi;
+    pi = p0 - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
 }
 
-// Blocks below wblocks: thread -> one weight of the matrix-core layers, its
-// gradient the sum of wsplits partials (coalesced over the threads).  The
-// blocks after: wave -> one parameter whose gradient sums one partial per row
-// block (the input layer's weights and every bias): lane j adds the partials
-// j, j + 64, .. in order, then the lanes in a fixed tree (lane 0's result).
-// Block 0 also sums the loss partials (k_loss_total's way).
-__global__ __launch_bounds__(256) void k_sum_adam(SumAdamArgs a) {
-    if (blockIdx.x == 0 && a.loss) {
+// Adam on parameter i with gradient gi and its moments and value m0, v0, p0
+// (loaded before the gradient's sum, so that their latency overlaps it).
+__device__ __forceinline__ void adam_one(const SumAdamArgs& a, int64_t i, float gi, float m0, float v0, float p0) {
+    float mi, vi, pi;
+    adam_math(a, gi, m0, v0, p0, mi, vi, pi);
+    a.g[i] = gi;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    a.p[i] = pi;
+}
+
+// Adam on parameters i .. i + 3, weights k .. k + 3 of matrix-core layer l
+// (k a multiple of 4, so the four share a row of W_l and sit together in
+// its row-major and forward packed copies), with their BF16 copies.
+__device__ __forceinline__ void adam_four(const SumAdamArgs& a, int64_t i, const float4& g4, int l, int64_t k,
+                                          const float4& m4, const float4& v4, const float4& p4) {
+    const float gs[4] = {g4.x, g4.y, g4.z, g4.w}, ms[4] = {m4.x, m4.y, m4.z, m4.w},
+                vs[4] = {v4.x, v4.y, v4.z, v4.w}, ps[4] = {p4.x, p4.y, p4.z, p4.w};
+    float mi[4], vi[4], pi[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) adam_math(a, gs[e], ms[e], vs[e], ps[e], mi[e], vi[e], pi[e]);
+    *reinterpret_cast<float4*>(a.g + i) = g4;
+    *reinterpret_cast<float4*>(a.m + i) = make_float4(mi[0], mi[1], mi[2], mi[3]);
+    *reinterpret_cast<float4*>(a.v + i) = make_float4(vi[0], vi[1], vi[2], vi[3]);
+    *reinterpret_cast<float4*>(a.p + i) = make_float4(pi[0], pi[1], pi[2], pi[3]);
+    const int32_t o = (int32_t)(k / a.din[l]), c = (int32_t)(k - (int64_t)o * a.din[l]);
+    const bf16x4 h = {(bf16)pi[0], (bf16)pi[1], (bf16)pi[2], (bf16)pi[3]};
+    *reinterpret_cast<bf16x4*>(a.wb[l] + k) = h;
+    *reinterpret_cast<bf16x4*>(a.wpf[l] + frag_off(o, c, a.din[l] / 32)) = h;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a.wpb[l][frag_off(c + e, o, a.dpad[l] / 32)] = h[e];
+}
+
+// Wave -> one parameter whose gradient sums one partial per row block (the
+// input layer's weights and every bias): lane j adds the partials j, j + 64,
+// .. in order, then the lanes in a fixed tree (lane 0's result).  Block 0
+// also sums the loss partials (k_loss_total's way).
+__device__ void sum_adam_long(const SumAdamArgs& a, int32_t blk) {
+    if (blk == 0 && a.loss) {
         __shared__ double s_sum[256];
         double acc = 0.0;
         for (int32_t k = (int32_t)threadIdx.x; k < a.nblk; k += 256) acc += a.lpart[k];
@@ -1228,30 +1264,8 @@ __global__ __launch_bounds__(256) void k_sum_adam(SumAdamArgs a) {
         }
         if (threadIdx.x == 0) *a.loss = (float)(s_sum[0] / (double)a.B);
     }
-    if ((int32_t)blockIdx.x < a.wblocks) {
-        const int64_t i = a.woff[1] + (int64_t)blockIdx.x * 256 + threadIdx.x;
-        if (i >= a.boff[3]) return;
-        const int l = i < a.woff[2] ? 1 : i < a.woff[3] ? 2 : 3;
-        if (i >= a.boff[l]) return;  // a bias: summed below
-        const int64_t k = i - a.woff[l];
-        const int64_t zs = (int64_t)a.dpad[l] * a.din[l];
-        const float m0 = a.m[i], v0 = a.v[i], p0 = a.p[i];
-        const float* src = a.wpart[l] + k;
-        float gi = 0.0f;
-        int32_t z = 0;
-        for (; z + 16 <= a.wsplits; z += 16) {  // 16 loads in flight, added in order
-            float v[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = src[(int64_t)(z + q) * zs];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) gi += v[q];
-        }
-        for (; z < a.wsplits; ++z) gi += src[(int64_t)z * zs];
-        adam_one(a, i, gi, l, k, m0, v0, p0);
-        return;
-    }
     const int lane = threadIdx.x & 63;
-    int32_t q = ((int32_t)blockIdx.x - a.wblocks) * 4 + (int32_t)(threadIdx.x >> 6);
+    int32_t q = blk * 4 + (int32_t)(threadIdx.x >> 6);
     if (q >= a.nlong) return;
     // parameter q: W0 [dout0][din0], b0, then b1, b2, b3
     const float* src;
@@ -1279,7 +1293,45 @@ __global__ __launch_bounds__(256) void k_sum_adam(SumAdamArgs a) {
     float gi = 0.0f;
     for (int32_t b = lane; b < a.nblk; b += 64) gi += src[(int64_t)b * stride];
     for (int off = 32; off > 0; off >>= 1) gi += __shfl_xor(gi, off, 64);
-    if (lane == 0) adam_one(a, i, gi, 0, 0, m0, v0, p0);
+    if (lane == 0) adam_one(a, i, gi, m0, v0, p0);
+}
+
+// Thread -> four consecutive weights of the matrix-core layers, each gradient
+// the sum of wsplits partials in split order (16-byte loads, coalesced over
+// the threads), then their Adam step.  The biases between the layers' weights
+// are left to sum_adam_long.
+__global__ __launch_bounds__(256) void k_sum_adam(SumAdamArgs a) {
+    const int64_t i = a.woff[1] + ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i >= a.boff[3]) return;
+    const int l = i < a.woff[2] ? 1 : i < a.woff[3] ? 2 : 3;
+    if (i >= a.boff[l]) return;  // a bias
+    const int64_t k = i - a.woff[l];
+    const int64_t zs = (int64_t)a.dpad[l] * a.din[l];
+    const float4 m0 = *reinterpret_cast<const float4*>(a.m + i), v0 = *reinterpret_cast<const float4*>(a.v + i),
+                 p0 = *reinterpret_cast<const float4*>(a.p + i);
+    const float* src = a.wpart[l] + k;
+    float4 gi = make_float4(0.f, 0.f, 0.f, 0.f);
+    int32_t z = 0;
+    for (; z + 8 <= a.wsplits; z += 8) {  // 8 loads in flight, added in order
+        float4 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = *reinterpret_cast<const float4*>(src + (int64_t)(z + q) * zs);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            gi.x += v[q].x;
+            gi.y += v[q].y;
+            gi.z += v[q].z;
+            gi.w += v[q].w;
+        }
+    }
+    for (; z < a.wsplits; ++z) {
+        const float4 v = *reinterpret_cast<const float4*>(src + (int64_t)z * zs);
+        gi.x += v.x;
+        gi.y += v.y;
+        gi.z += v.z;
+        gi.w += v.w;
+    }
+    adam_four(a, i, gi, l, k, m0, v0, p0);
 }
 
 // Training rows from a table of the whole cube: x = RGB / 255 - 1/2 of colour
@@ -1815,7 +1867,6 @@ int train_step_fused(cv_mlp* m, const int32_t* ids, int64_t nb, const cv_table_r
         a.zstride = (int64_t)m->dpad[l + 1] * m->dims[l];
         a.nstore = m->dims[l];
     }
-    if ((rc = gemm_wgrad3(wg, splits, s)) != CV_OK) return rc;
     SumAdamArgs d;
     d.p = m->params;
     d.g = m->grads;
@@ -1849,12 +1900,17 @@ int train_step_fused(cv_mlp* m, const int32_t* ids, int64_t nb, const cv_table_r
     d.bw[3] = 64;
     d.p0 = p0;
     d.nblk = nblk;
-    d.wblocks = (int32_t)blocks(m->boff[3] - m->woff[1], 256);
     d.nlong = m->dims[1] * m->dims[0] + m->dims[1] + m->dims[2] + m->dims[3] + m->dims[4];
     d.lpart = lp;
     d.loss = loss;
     d.B = nb;
-    hipLaunchKernelGGL(k_sum_adam, dim3((unsigned)(d.wblocks + (d.nlong + 3) / 4)), dim3(256), 0, s, d);
+    // four weights per thread: every layer's weights start and end on a multiple of 4
+    for (int l = 1; l <= 3; ++l)
+        if (m->woff[l] % 4 != 0 || (m->boff[l] - m->woff[l]) % 4 != 0 || m->dims[l] % 4 != 0)
+            return fail(CV_ESTATE, "internal: weight blocks not in fours");
+    if ((rc = gemm_wgrad3(wg, splits, d, (d.nlong + 31) / 32 * 8, s)) != CV_OK) return rc;
+    hipLaunchKernelGGL(k_sum_adam, dim3((unsigned)blocks((m->boff[3] - m->woff[1] + 3) / 4, 256)), dim3(256), 0, s,
+                       d);
     CV_HIP(hipGetLastError());
     return CV_OK;
 }
