@@ -81,12 +81,12 @@ FLOPS_CELL = 84
 MEASURED_COUNTERS = {
     "count_pass": {"sources_sha256": "7f819a3d585b0b1d191b0a5dd09005670345c7b20ec497c51ea20abe8ac8d1ff",
                    "traffic_bytes": 55112478, "valu_issue": 0.532},
-    "colour_resolve": {"sources_sha256": "45e09672734ade086c4b8eb88e5b32bf058bad65ba08f13119e2ec9723ed46b0",
-                   "traffic_bytes": 7275424193, "valu_issue": 0.974},
+    "colour_resolve": {"sources_sha256": "585bbeb7203dbd6afabab7bef8648cf1e7cdcce0b4a1061a305583976c30c752",
+                   "traffic_bytes": 8561481792, "valu_issue": 0.975},
     "cube_table": {"sources_sha256": "7f819a3d585b0b1d191b0a5dd09005670345c7b20ec497c51ea20abe8ac8d1ff",
                    "traffic_bytes": 3568505768, "valu_issue": 0.947},
     "ray_search": {"sources_sha256": "6d0528e242ff118e1584b4863e146ee703b6bc7a4d9dc6e6fe88d7ed6a29db6d",
-                   "traffic_bytes": 6098304309, "valu_issue": 0.839},
+                   "traffic_bytes": 6319238829, "valu_issue": 0.84},
 }
 KERNEL_SOURCES = {
     "count_pass": ("cvib_search.hip", "cvib_device.h", "cvib_kernels.h"),
@@ -154,11 +154,10 @@ def bench_frames(cv, W, torch, steps):
     pattern, per-ray maxima, summaries without n_gamut) and render the two
     frames; one hipGraph launch per step, frames resident in HBM."""
     import numpy as np
-    f = W.frames(range(8))
-    info = np.tile(W.info_map(0).reshape(-1), len(f))
+    px = cv.frames_generate(range(8))  # on the device (cv_frames_generate's recipe)
+    info = np.tile(W.info_map(0).reshape(-1), px.shape[0])
     g = W.GRID_FRAMES
     grid, rule = cv.Grid(*g.astuple()), cv.Rule(*W.DEFAULT_RULE)
-    px = torch.from_numpy(f).cuda()
     inf = torch.from_numpy(info).cuda()
     ctx = cv.context(0)
     # one eager call with n_gamut: the in-gamut count and the in-gamut pairs of
@@ -193,7 +192,7 @@ def bench_frames(cv, W, torch, steps):
     evals = decided - skipped  # the rest lie in steps proven out of gamut or without a high channel
     npix = px.shape[0] * px.shape[1] * px.shape[2]
     return {
-        "workload": "8 synthetic 3840x2160 frames (seeds 0..7), 16x16-pixel information map; "
+        "workload": "8 synthetic 3840x2160 frames (generated on the device, seeds 0..7, 64 sites, noise 4), 16x16-pixel information map; "
                     "r = 0.1..50 step 0.1 (500) x theta = 0..359 deg step 1 (360)",
         "colours_per_s_exact": n / (ms * 1e-3), "distinct_colours": n, "pixels": npix,
         "pixels_per_s": npix / (ms * 1e-3), "pairs_per_s": n * g.per_colour / (ms * 1e-3),
@@ -214,11 +213,9 @@ def bench_rays(cv, W, torch, steps):
     they can be), against the exhaustive resolve of the same colours with its
     per-ray maxima (which also keeps the best pair of every pattern)."""
     import numpy as np
-    f = W.frames(range(8))
+    px = cv.frames_generate(range(8))
     g = W.GRID_FRAMES
     grid, rule = cv.Grid(*g.astuple()), cv.Rule(*W.DEFAULT_RULE)
-    px = torch.from_numpy(f).cuda()
-    del f
     ctx = cv.context(0)
     ex = cv.frames_resolve(px, grid, rule, summaries=False, rays=True, frames=False, ctx=ctx)
     torch.cuda.synchronize()
@@ -296,9 +293,7 @@ def bench_surrogate(cv, W, torch, epochs, steps):
     rows = nsteps * 8192
     ev = S.evaluate(m, table, te_ids, gc.dr)
     # frames
-    f = W.frames(range(100, 116))
-    px = torch.from_numpy(f).cuda()
-    del f
+    px = cv.frames_generate(range(100, 116))
     g = W.GRID_FRAMES
     grid, rule = cv.Grid(*g.astuple()), cv.Rule(*W.DEFAULT_RULE)
     ctx = m.ctx
@@ -386,7 +381,7 @@ def bench_surrogate(cv, W, torch, epochs, steps):
     return {
         "workload": "surrogate 3-256-256-256-37 (first hidden layer sin(30 z), then ReLU) trained with "
                     "Adam (batch 8192, lr 2e-3 cosine to 2e-5, Huber 0.2) on the 2^24-colour table (r step 0.25, "
-                    "theta step 2 deg; 90/10 split, seed 0); 16 synthetic 3840x2160 frames "
+                    "theta step 2 deg; 90/10 split, seed 0); 16 synthetic 3840x2160 frames generated on the device "
                     "(seeds 100..115) on r = 0.1..50 step 0.1 x theta step 1 deg",
         "table_s": t_table,
         "train": {"epochs": epochs, "steps": nsteps, "batch": 8192, "seconds": t_train,

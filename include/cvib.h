@@ -343,6 +343,31 @@ int cv_frames_resolve(cv_context* ctx, const uint8_t* pixels, int64_t npix, cons
                       void* stream);
 
 /*
+ * Synthetic frames for the batched calls (the paper's display frames are not
+ * given; these stand in for them): n frames of height x width sRGB8 pixels,
+ * frame f from seeds[f] (host array), written back to back to out (DEVICE
+ * uint8 [n][height][width][3], owned by the caller).  Each frame is smooth
+ * per-channel gradients, plus a constant offset per region of the nearest of
+ * `sites` random sites, plus a rounded noise of amplitude `noise`.  All its
+ * arithmetic is integer and every random word is Philox4x64-10 (Salmon et
+ * al., SC'11) of a fixed counter under the key (seeds[f], 0), so that the
+ * bytes are the same on any implementation of that definition:
+ *   words(0, 0, 0, 0): per channel c from byte c of words 0, 1, 2:
+ *     g0 = 64 + b % 129, gx = b % 129 - 64, gy = b % 129 - 64;
+ *   words(1, s, 0, 0), site s: x = word0 % width, y = word1 % height,
+ *     v_c = (byte c of word2) % 97 - 48;
+ *   words(2, y, x, 0), pixel (x, y): n_c = (sum of bytes 4c..4c+3 of words
+ *     0 and 1 as 16 little-endian bytes - 510) * noise / 128;
+ *   channel c = clamp(g0 + gx x / width + gy y / height + v_c(nearest site)
+ *     + n_c, 0, 255), the nearest site by squared distance with ties to the
+ *     lowest index, every division truncating toward zero.
+ * height and width in [1, 16384], sites in [1, 256], noise in [0, 255].
+ * Asynchronous (one launch per frame).  Errors: CV_EINVAL, CV_EHIP.
+ */
+int cv_frames_generate(cv_context* ctx, const uint64_t* seeds, int64_t n, int32_t height, int32_t width,
+                       int32_t sites, int32_t noise, uint8_t* out, void* stream);
+
+/*
  * Kernel timing for measurement.  When enabled, the library brackets its
  * kernels with HIP events on the caller's stream and accumulates the elapsed
  * time per phase:

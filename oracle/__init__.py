@@ -22,7 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libcvib_oracle.so")
-_SOURCES = ["cvib_oracle.c", "mlp_oracle.c"]
+_SOURCES = ["cvib_oracle.c", "mlp_oracle.c", "frame_oracle.c"]
 
 
 def compile_library(srcs, out: str) -> str:
@@ -121,6 +121,9 @@ def load_library(path: str) -> C.CDLL:
                                     C.c_int32]
     L.orc_num_threads.restype = C.c_int32
     _mlp_bind(L)
+    L.orc_philox4x64.argtypes = [P, P, P]
+    L.orc_gen_frame.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P]
+    L.orc_gen_frame.restype = C.c_int32
     return L
 
 
@@ -379,3 +382,26 @@ def adam_step(p, g, m, v, t: int, lr: float, beta1: float = 0.9, beta2: float = 
     mhat = m / (1.0 - beta1 ** t)
     vhat = v / (1.0 - beta2 ** t)
     return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# --------------------------------------------------------------------------
+# Twin of the library's synthetic frame generator (frame_oracle.c).
+
+def philox4x64(counter, key) -> np.ndarray:
+    """Philox4x64-10 (Salmon et al., SC'11) of one 4-word counter under a
+    2-word key: uint64 [4]."""
+    ctr = np.ascontiguousarray(np.asarray(counter, dtype=np.uint64).reshape(4))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint64).reshape(2))
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64(_ptr(ctr), _ptr(k), _ptr(out))
+    return out
+
+
+def gen_frame(seed: int, height: int, width: int, sites: int = 64, noise: int = 4) -> np.ndarray:
+    """One synthetic frame, uint8 [height, width, 3] (the recipe in
+    frame_oracle.c)."""
+    out = np.zeros((height, width, 3), dtype=np.uint8)
+    rc = lib().orc_gen_frame(C.c_uint64(int(seed)), int(height), int(width), int(sites), int(noise), _ptr(out))
+    if rc != 0:
+        raise ValueError("bad frame size, site count or noise")
+    return out

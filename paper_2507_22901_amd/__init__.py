@@ -77,7 +77,8 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_mlp_set_first_sine", "cv_mlp_first_sine", "cv_permute_ids", "cv_context_no_high",
            "cv_pair_reduce_noalloc", "cv_ray_search", "cv_mlp_hidden",
            "cv_mlp_save_checkpoint", "cv_mlp_load_checkpoint", "cv_mlp_checkpoint_info",
-           "cv_context_set_tile_target", "cv_context_tile_target", "cv_context_set_tune_file")
+           "cv_context_set_tile_target", "cv_context_tile_target", "cv_context_set_tune_file",
+           "cv_frames_generate")
 CV_NO_FALLBACK = 0x4
 CV_PRED_GIVEN = 0x20
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
@@ -112,6 +113,7 @@ def lib() -> C.CDLL:
                                              C.POINTER(C.c_uint64)]
         L.cv_mlp_hidden.argtypes = [P, C.c_int32, P, I64, P]
         L.cv_ray_search.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P, P, P]
+        L.cv_frames_generate.argtypes = [P, P, I64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P]
         L.cv_pair_reduce_noalloc.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P]
         L.cv_frames_resolve.argtypes = [P, P, I64, P, C.POINTER(cv_grid), C.POINTER(cv_rule), P,
                                         I64, P, P, P, P, P, P, P, P, C.c_uint32, P]
@@ -331,6 +333,25 @@ def rgb8_to_lab(rgb: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:
     out = torch.empty((rgb.shape[0], 3), dtype=torch.float32, device=rgb.device)
     _check(lib().cv_lab_convert(ctx.handle, _dptr(rgb), _dptr(out), rgb.shape[0], CV_RGB8_TO_LAB,
                                 _stream()))
+    return out
+
+
+def frames_generate(seeds, height: int = 2160, width: int = 3840, sites: int = 64, noise: int = 4,
+                    device: int = 0, ctx: Context | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Synthetic sRGB8 frames on the device, uint8 [len(seeds), height, width, 3]
+    (cv_frames_generate: integer recipe on Philox4x64-10 words keyed by each
+    seed).  `out`, if given, must be a contiguous uint8 CUDA tensor of that
+    shape."""
+    sd = np.ascontiguousarray(np.asarray(list(seeds), dtype=np.uint64))
+    n = int(sd.shape[0])
+    shape = (n, int(height), int(width), 3)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.uint8, device=f"cuda:{device}")
+    elif (out.dtype != torch.uint8 or not out.is_cuda or not out.is_contiguous() or tuple(out.shape) != shape):
+        raise ValueError(f"out must be a contiguous uint8 CUDA tensor of shape {shape}")
+    ctx = ctx or context(out.device.index)
+    _check(lib().cv_frames_generate(ctx.handle, sd.ctypes.data, n, int(height), int(width), int(sites),
+                                    int(noise), _dptr(out), _stream()))
     return out
 
 

@@ -162,6 +162,26 @@ def test_frames_argument_validation(cv):
     assert call(flags=0x20) == cv.CV_EINVAL            # unknown flag
 
 
+def test_frames_generate_validation(cv):
+    L = cv.lib()
+    d = C.cast((C.c_uint8 * 4096)(), C.c_void_p)
+    seeds = (C.c_uint64 * 2)(1, 2)
+
+    def call(ctx=d, sd=seeds, n=1, h=4, w=4, sites=8, noise=4, out=d):
+        return L.cv_frames_generate(ctx, sd, n, h, w, sites, noise, out, None)
+    assert call(ctx=None) == cv.CV_EINVAL
+    assert call(sd=None) == cv.CV_EINVAL
+    assert call(out=None) == cv.CV_EINVAL
+    assert call(n=-1) == cv.CV_EINVAL
+    for h, w in ((0, 4), (4, 0), (16385, 4), (4, 16385)):
+        assert call(h=h, w=w) == cv.CV_EINVAL
+    for sites in (0, 257):
+        assert call(sites=sites) == cv.CV_EINVAL
+    for noise in (-1, 256):
+        assert call(noise=noise) == cv.CV_EINVAL
+    assert b"noise" in L.cv_last_error()
+
+
 def test_binding_refuses_host_tensors(cv):
     import torch
     with pytest.raises(ValueError):
