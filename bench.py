@@ -333,8 +333,10 @@ def bench_surrogate(cv, W, torch, epochs, steps):
     mlp_ms = ph["mlp"]
 
     # the honest gain test on the same distinct colours: the same verify and
-    # fallback fed by proposers that need no network, and the exact one-pair
-    # resolve from the outermost radius inward (adaptive per-ray search)
+    # fallback fed by proposers that need no network, and two exact one-pair
+    # resolves from the outermost radius inward: the adaptive per-ray search,
+    # and the search that stops at the first level of 64 radii holding a
+    # survivor (the fastest exact one-pair resolve here)
     cols = sr.colours[:n]
     has = summ["count"] > 0
     best_r = (summ["best_i"][has].astype(np.float64) + 1.0) * g.dr
@@ -376,6 +378,11 @@ def bench_surrogate(cv, W, torch, epochs, steps):
                     (summ["best_i"].astype(np.int64) << 16) | (0xFFFF - summ["best_j"].astype(np.int64)))
     comps["exact_adaptive"] = {"ms_per_call": ms_rays, "equal_to_exhaustive_best": bool(np.array_equal(key, want)),
                                "evaluated_fraction": int(rs.counts[0].item()) / (n * g.per_colour)}
+    bp = cv.best_pair_search(cols, grid, rule, ctx=ctx)
+    ms_bp = timed(lambda: cv.best_pair_search(cols, grid, rule, out=bp, ctx=ctx), steps)
+    key_bp = bp.best[:n].cpu().numpy().view(np.uint32).astype(np.int64)
+    comps["exact_early_exit"] = {"ms_per_call": ms_bp, "equal_to_exhaustive_best": bool(np.array_equal(key_bp, want)),
+                                 "evaluated_fraction": int(bp.counts[0].item()) / (n * g.per_colour)}
     for v in comps.values():
         v["colours_per_s"] = n / (v["ms_per_call"] * 1e-3)
     return {
@@ -406,6 +413,8 @@ def bench_surrogate(cv, W, torch, epochs, steps):
         "speedup": ms_exact / ms_sur,
         "one_pair_resolve_of_the_distinct_colours": dict(
             comps, speedup_network_vs_exact_adaptive=comps["exact_adaptive"]["ms_per_call"] /
+            comps["network"]["ms_per_call"],
+            speedup_network_vs_exact_early_exit=comps["exact_early_exit"]["ms_per_call"] /
             comps["network"]["ms_per_call"]),
     }
 

@@ -293,6 +293,25 @@ int cv_ray_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid*
                   uint16_t* rays, cv_pair* recs, uint32_t* best, uint64_t* counts, void* stream);
 
 /*
+ * Exact one-pair resolve (the maximum-amplitude survivor of Sections 2-3 for
+ * each colour, as the exhaustive search defines it: largest i, then smallest
+ * j), with a global early exit: the radii are taken in levels of 64 from the
+ * outermost inward; at each level every ray's block is closed by the interval
+ * bound of cv_ray_search where it can, the others are evaluated with the
+ * search's arithmetic, and the walk stops at the first level holding a
+ * survivor.  Under CV_RULE_CLIP no block is closed.
+ * rgb: uint8 [n][3] device.  best: nullable uint32 [n] device, the key
+ * i << 16 | (65535 - j) (0 = no survivor).  pairs: nullable cv_pair [n]
+ * device, that survivor's record (flags bit 2 set; all zero except the colour
+ * index for a colour without one).  At least one of best and pairs.  counts:
+ * nullable uint64 [3] device, overwritten: candidates evaluated, (ray, level)
+ * blocks tested, blocks closed by the bound.  Asynchronous.
+ * Errors: CV_EINVAL, CV_EHIP, CV_ENOMEM.
+ */
+int cv_best_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid, const cv_rule* rule,
+                        uint32_t* best, cv_pair* pairs, uint64_t* counts, void* stream);
+
+/*
  * Several rules in one pass (Table 1's twelve settings give Table 2): for
  * each colour and rule, the survivors of each pattern.  rules: host array of
  * nrules (1..16) cv_rule with the same flags (one gamut reading); together

@@ -78,7 +78,7 @@ EXPORTS = ("cv_context_create", "cv_context_destroy", "cv_last_error", "cv_lab_c
            "cv_pair_reduce_noalloc", "cv_ray_search", "cv_mlp_hidden",
            "cv_mlp_save_checkpoint", "cv_mlp_load_checkpoint", "cv_mlp_checkpoint_info",
            "cv_context_set_tile_target", "cv_context_tile_target", "cv_context_set_tune_file",
-           "cv_frames_generate")
+           "cv_frames_generate", "cv_best_pair_search")
 CV_NO_FALLBACK = 0x4
 CV_PRED_GIVEN = 0x20
 CV_PAIR_FOUND, CV_PAIR_SURROGATE, CV_PAIR_FALLBACK = 0x1, 0x2, 0x4
@@ -114,6 +114,7 @@ def lib() -> C.CDLL:
         L.cv_mlp_hidden.argtypes = [P, C.c_int32, P, I64, P]
         L.cv_ray_search.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P, P, P]
         L.cv_frames_generate.argtypes = [P, P, I64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P]
+        L.cv_best_pair_search.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P, P]
         L.cv_pair_reduce_noalloc.argtypes = [P, P, I64, C.POINTER(cv_grid), C.POINTER(cv_rule), P, P, P]
         L.cv_frames_resolve.argtypes = [P, P, I64, P, C.POINTER(cv_grid), C.POINTER(cv_rule), P,
                                         I64, P, P, P, P, P, P, P, P, C.c_uint32, P]
@@ -495,6 +496,35 @@ def ray_search(colors: torch.Tensor, grid: Grid, rule: Rule, records: bool = Fal
     g, r = grid.c(), rule.c()
     _check(lib().cv_ray_search(ctx.handle, _dptr(colors), n, C.byref(g), C.byref(r), _dptr(out.rays),
                                _dptr(out.records), _dptr(out.best), _dptr(out.counts), _stream()))
+    return out
+
+
+@dataclass
+class BestPairResult:
+    best: torch.Tensor     # int32 view of uint32 [n]: i << 16 | (65535 - j), 0 = none
+    pairs: torch.Tensor    # uint8 [n, 16]: cv_pair records
+    counts: torch.Tensor   # int64 [3]: evaluated, blocks tested, blocks closed
+
+
+def best_pair_search(colors: torch.Tensor, grid: Grid, rule: Rule, out: BestPairResult | None = None,
+                     ctx: Context | None = None) -> BestPairResult:
+    """Exact one-pair resolve with a global early exit (cv_best_pair_search):
+    each colour's maximum-amplitude survivor, from the outermost radii inward,
+    stopping at the first level of 64 radii that holds one."""
+    colors = _colours(colors)
+    ctx = ctx or context(colors.device.index)
+    n = colors.shape[0]
+    dev = colors.device
+    if out is None:
+        out = BestPairResult(torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+                             torch.empty((max(n, 1), 16), dtype=torch.uint8, device=dev),
+                             torch.zeros(3, dtype=torch.int64, device=dev))
+    _require(out.best, "out.best", torch.int32, n, dev)
+    _require(out.pairs, "out.pairs", torch.uint8, n * 16, dev)
+    _require(out.counts, "out.counts", torch.int64, 3, dev)
+    g, r = grid.c(), rule.c()
+    _check(lib().cv_best_pair_search(ctx.handle, _dptr(colors), n, C.byref(g), C.byref(r), _dptr(out.best),
+                                     _dptr(out.pairs), _dptr(out.counts), _stream()))
     return out
 
 

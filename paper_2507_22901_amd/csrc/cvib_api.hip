@@ -264,7 +264,7 @@ int cv_context_destroy(cv_context* ctx) {
     cvib::Buffer* bufs[] = {&ctx->colors, &ctx->table, &ctx->seg_cnt, &ctx->seg_prefix,
                             &ctx->scan,   &ctx->acc,   &ctx->misc,    &ctx->fbits,
                             &ctx->fcnt,   &ctx->fprefix, &ctx->fmisc, &ctx->spred,
-                            &ctx->sneed,  &ctx->sprefix, &ctx->slist, &ctx->ssumm, &ctx->smisc,
+                            &ctx->sneed,  &ctx->sprefix, &ctx->slist, &ctx->smisc,
                             &ctx->rtab,   &ctx->rhist,   &ctx->rays,    &ctx->stats,
                             &ctx->seg_mask};
     for (cvib::Buffer* b : bufs)
@@ -368,6 +368,23 @@ int cv_ray_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid*
     if ((rc = cvib::make_rule(rule, &rd)) != CV_OK) return rc;
     DeviceGuard dg(ctx->device);
     return cvib::run_ray_search(ctx, rgb, n, gd, rd, rays, recs, best, counts, (hipStream_t)stream);
+    CV_GUARD_END
+}
+
+int cv_best_pair_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const cv_grid* grid, const cv_rule* rule,
+                        uint32_t* best, cv_pair* pairs, uint64_t* counts, void* stream) {
+    CV_GUARD_BEGIN
+    if (!ctx) return fail(CV_EINVAL, "ctx is NULL");
+    if (n < 0 || n > 0xFFFFFFFFll) return fail(CV_EINVAL, "n out of range");
+    if (!best && !pairs) return fail(CV_EINVAL, "best and pairs are both NULL");
+    if (n > 0 && !rgb) return fail(CV_EINVAL, "rgb is NULL");
+    cvib::GridDev gd;
+    cvib::RuleDev rd;
+    int rc;
+    if ((rc = cvib::make_grid(grid, &gd)) != CV_OK) return rc;
+    if ((rc = cvib::make_rule(rule, &rd)) != CV_OK) return rc;
+    DeviceGuard dg(ctx->device);
+    return cvib::run_best_pair(ctx, rgb, n, gd, rd, best, pairs, counts, (hipStream_t)stream);
     CV_GUARD_END
 }
 

@@ -669,31 +669,6 @@ __global__ void k_make_list(const uint32_t* __restrict__ need, const uint64_t* _
         if (need[c]) list[prefix[c]] = (uint32_t)c;
 }
 
-// The exact search's maximum-amplitude pair for every fallback colour.
-__global__ void k_fallback_finish(const uint32_t* __restrict__ list, const uint64_t* __restrict__ nlist,
-                                  const cv_color_summary* __restrict__ summ,
-                                  cv_pattern_pair* __restrict__ pairs, uint8_t* __restrict__ status) {
-    const int64_t n = (int64_t)*nlist;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
-        const uint32_t c = list[k];
-        const cv_color_summary& sm = summ[c];
-        cv_pattern_pair r = {};
-        if (sm.best_i != 0xFFFFu) {
-            r.i = sm.best_i;
-            r.j = sm.best_j;
-            for (int q = 0; q < 3; ++q) {
-                r.plus[q] = sm.best_plus[q];
-                r.minus[q] = sm.best_minus[q];
-            }
-            r.pattern = sm.best_p;
-            r.flags = CV_PAIR_FOUND | CV_PAIR_FALLBACK;
-        }
-        pairs[c] = r;
-        status[c] = sm.best_i != 0xFFFFu ? (uint8_t)CV_RESOLVED_EXACT : (uint8_t)CV_RESOLVED_NONE;
-    }
-}
-
 // Two frames from one pair per colour.
 __global__ void k_render_pairs(const uint8_t* __restrict__ px, int64_t npix,
                                const uint32_t* __restrict__ index,
@@ -1047,7 +1022,6 @@ int ensure_surrogate(cv_context* ctx, const SurrogateCall& c, int64_t n) {
     if ((rc = ctx->ensure(ctx->sneed, (size_t)m * 4)) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->sprefix, (size_t)m * 8)) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->slist, (size_t)m * 4)) != CV_OK) return rc;
-    if ((rc = ctx->ensure(ctx->ssumm, (size_t)m * sizeof(cv_color_summary))) != CV_OK) return rc;
     if ((rc = ctx->ensure(ctx->smisc, 64)) != CV_OK) return rc;
     return CV_OK;
 }
@@ -1106,18 +1080,11 @@ int enqueue_surrogate(cv_context* ctx, const SurrogateCall& c, const uint8_t* rg
         CV_HIP(hipGetLastError());
     }
     if (c.fallback) {
-        ResolveArgs a = resolve_args(ctx, c.gd, c.rd, smisc + 1);
-        a.list = list;
-        a.summ = (cv_color_summary*)ctx->ssumm.ptr;
-        a.need_ng = 0;  // only the maximum-amplitude pair is taken from these summaries
+        // the exact maximum-amplitude pair of each listed colour: the one-pair
+        // search with a global early exit (cvib_rays.hip)
         if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
-        if ((rc = launch_resolve(ctx, a, c.gd.ntheta == c.gd.N, resolve_variant(ctx, c.gd, false), s)) !=
-            CV_OK)
-            return rc;
+        if ((rc = run_best_pair_list(ctx, c.gd, c.rd, list, smisc + 1, n, c.pairs, c.status, s)) != CV_OK) return rc;
         if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
-        hipLaunchKernelGGL(k_fallback_finish, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, list,
-                           smisc + 1, (const cv_color_summary*)ctx->ssumm.ptr, c.pairs, c.status);
-        CV_HIP(hipGetLastError());
     }
     if (c.nfallback) hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, smisc + 1, c.nfallback);
     CV_HIP(hipGetLastError());

@@ -87,6 +87,14 @@ int run_pair_reduce_noalloc(cv_context* ctx, const uint8_t* rgb, int64_t n, cons
                             hipStream_t s);
 int run_ray_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd, const RuleDev& rd,
                    uint16_t* rays, cv_pair* recs, uint32_t* best, uint64_t* counts, hipStream_t s);
+int run_best_pair(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd, const RuleDev& rd,
+                  uint32_t* best, cv_pair* pairs, uint64_t* counts, hipStream_t s);
+// The exact search's maximum-amplitude pair of the colours list[k], k < *n_dev
+// (n_max bounds it), on the colour constants and angle table the context
+// holds for the call, into pairs[colour] (flags CV_PAIR_FOUND |
+// CV_PAIR_FALLBACK) and status[colour].
+int run_best_pair_list(cv_context* ctx, const GridDev& gd, const RuleDev& rd, const uint32_t* list,
+                       const uint64_t* n_dev, int64_t n_max, cv_pattern_pair* pairs, uint8_t* status, hipStream_t s);
 int run_pair_csr_summary(cv_context* ctx, const cv_pair* recs, const int64_t* offsets, int64_t n,
                          cv_color_summary* summ, hipStream_t s);
 int run_pair_reduce(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd,
@@ -210,7 +218,6 @@ struct cv_context {
     cvib::Buffer sneed;       // surrogate: 1 = exact fallback, per colour
     cvib::Buffer sprefix;     // surrogate: fallback list positions
     cvib::Buffer slist;       // surrogate: fallback colour indices
-    cvib::Buffer ssumm;       // surrogate: exact summaries of fallback colours
     cvib::Buffer smisc;       // surrogate: [0] colour count, [1] fallback count
     cvib::Buffer rays;        // per-ray search: largest i + 1 per evaluated ray
     cvib::Buffer rtab;        // multi-rule: interval table, classes, masks

@@ -52,6 +52,14 @@ struct RayArgs {
     cv_pair* recs;            // nullable [n][ntheta]: the pair at that radius, zero where none
     unsigned long long* counts;  // nullable [3]: candidates evaluated, blocks tested, blocks closed
     uint32_t* best;           // nullable [n]: the colour's largest key (i << 16 | 0xFFFF - j), zeroed before
+    cv_pair* pairs;           // k_best_pair, nullable [n]: the pair of that key (flags 0 where none)
+    int64_t n;                // k_best_pair: colours (with n_dev: an upper bound of *n_dev)
+    // k_best_pair over a list (the surrogate's exact fallback): colour list[k]
+    // for k < *n_dev, its pair to ppairs[colour] and status[colour]
+    const uint32_t* list;
+    const uint64_t* n_dev;
+    cv_pattern_pair* ppairs;
+    uint8_t* status;
 };
 
 __device__ __forceinline__ void store_ray(const RayArgs& a, int64_t c, int32_t j, uint32_t best,
@@ -166,6 +174,120 @@ __global__ __launch_bounds__(kRayBlock) void k_ray_search(RayArgs a) {
     }
 }
 
+// Exact one-pair resolve with a global early exit: the maximum-amplitude pair
+// (largest i, then smallest j) of every colour.  One wave per colour takes the
+// levels of 64 radii from the outermost inward; at each level every ray's
+// block is proven empty where the interval bound can (lane -> ray), and the
+// open ones are evaluated with the search's arithmetic (lane -> radius, lane 0
+// outermost), each only above the largest i found so far at that level.  The
+// first level with a survivor holds the colour's largest i, so the walk stops
+// there; the key is then the exhaustive search's best, bit for bit.  The
+// mirrored rays of the half-turn hold the same radii at larger j: never better.
+__global__ __launch_bounds__(kRayBlock) void k_best_pair(RayArgs a) {
+    extern __shared__ double s_dyn[];
+    const Angles ang = load_angles(a.tab, s_dyn);
+    const uint32_t lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * kRayBlock + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * kRayBlock) >> 6;
+    const bool clip = a.rule.clip != 0u;
+    uint64_t evald = 0, tested = 0, closed = 0;
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n;
+    for (int64_t k = wave; k < n; k += nwaves) {
+        const int64_t c = a.list ? (int64_t)a.list[k] : k;
+        const ColorConst cc = a.cc[c];
+        const bool cube = cube_branch_only(cc, a.nr - 1, a.ra, a.rb);
+        uint32_t best = 0, blo = 0, bhi = 0;  // the same in every lane
+        for (int32_t bb = 0; bb < a.nb && best == 0u; ++bb) {
+            const int32_t hi_i = a.nr - 1 - kRowsPerBlock * bb;
+            const int32_t lo_i = max(hi_i - (kRowsPerBlock - 1), 0);
+            int32_t floor_i = -1;  // radii at or below this cannot beat the level's best so far
+            for (int32_t j0 = 0; j0 < a.W && floor_i < hi_i; j0 += 64) {
+                const int32_t jl = j0 + (int32_t)lane;
+                const bool live = jl < a.W;
+                bool open = live;
+                if (a.proofs) {
+                    const int32_t jj = live ? jl : 0;
+                    double s, co;
+                    ang.get(jj, s, co);
+                    bool high = true;
+                    const bool out = cell_out_of_gamut_ends(cc, a.g, ang.N, a.ra, a.rb, lo_i, hi_i, jj, jj, s, co, s,
+                                                            co, &a.rule, &high);
+                    open = live && !out && high;
+                }
+                const uint64_t lm = __ballot(live);
+                uint64_t om = uniform_u64(__ballot(open));
+                tested += (uint64_t)__builtin_popcountll(lm);
+                closed += (uint64_t)__builtin_popcountll(lm & ~om);
+                while (om) {
+                    const int32_t j = j0 + (int32_t)__builtin_ctzll(om);
+                    om &= om - 1ull;
+                    if (hi_i <= floor_i) break;  // no radius of the level above the best found
+                    double s, co;
+                    ang.get(j, s, co);
+                    const int32_t i = hi_i - (int32_t)lane;
+                    const bool lv = i >= lo_i && i > floor_i;
+                    const double rad = (double)(lv ? i + 1 : 1);
+                    float fp[3], fm[3];
+                    pair_linear_w(cc, a.g, (rad * a.ra) * s, (rad * a.rb) * co, fp, fm, cube);
+                    const uint64_t live_m = __ballot(lv);
+                    evald += (uint64_t)__builtin_popcountll(live_m);
+                    const bool gp = in_unit_cube(fp), gm = in_unit_cube(fm);
+                    const uint64_t need_m = clip ? live_m : (__ballot(gp && gm) & live_m);
+                    if (need_m == 0ull) continue;
+                    float Vp[3], Vm[3];
+                    codes_w(fp, fm, (need_m >> lane) & 1ull, clip, Vp, Vm);
+                    const PatMasks pm = pattern_masks(Vp, Vm, a.rule);
+                    const uint64_t surv = uniform_u64(accepted_lanes(pm, a.rule.mask) & need_m);
+                    if (surv == 0ull) continue;
+                    const int32_t first = (int32_t)__builtin_ctzll(surv);  // largest i of this ray
+                    uint32_t lo, hi;
+                    const uint32_t flags = 4u | (gp ? 1u : 0u) | (gm ? 2u : 0u);
+                    pack_pair(Vp, Vm, pattern_of(Vp, Vm, a.rule), flags, lo, hi);
+                    // a larger i than the level's best so far (rays come in increasing j)
+                    floor_i = hi_i - first;
+                    best = best_key(floor_i, j);
+                    blo = (uint32_t)__shfl((int)lo, first, 64);
+                    bhi = (uint32_t)__shfl((int)hi, first, 64);
+                }
+            }
+        }
+        if (lane == 0) {
+            if (a.ppairs) {
+                // cv_pattern_pair: i, j, then the record's codes and pattern (bytes 8..14 of cv_pair)
+                cv_pattern_pair r = {};
+                if (best) {
+                    r.i = (uint16_t)(best >> 16);
+                    r.j = (uint16_t)(0xFFFFu - (best & 0xFFFFu));
+                    r.plus[0] = (uint8_t)blo;
+                    r.plus[1] = (uint8_t)(blo >> 8);
+                    r.plus[2] = (uint8_t)(blo >> 16);
+                    r.minus[0] = (uint8_t)(blo >> 24);
+                    r.minus[1] = (uint8_t)bhi;
+                    r.minus[2] = (uint8_t)(bhi >> 8);
+                    r.pattern = (uint8_t)(bhi >> 16);
+                    r.flags = CV_PAIR_FOUND | CV_PAIR_FALLBACK;
+                }
+                a.ppairs[c] = r;
+                a.status[c] = best ? (uint8_t)CV_RESOLVED_EXACT : (uint8_t)CV_RESOLVED_NONE;
+            }
+            if (a.best) a.best[c] = best;
+            if (a.pairs) {
+                uint32_t* r = reinterpret_cast<uint32_t*>(a.pairs + c);
+                const uint32_t bi = best >> 16, bj = 0xFFFFu - (best & 0xFFFFu);
+                r[0] = (uint32_t)c;
+                r[1] = best ? (bi | (bj << 16)) : 0u;
+                r[2] = best ? blo : 0u;
+                r[3] = best ? bhi : 0u;
+            }
+        }
+    }
+    if (a.counts && lane == 0) {
+        if (evald) atomicAdd(&a.counts[0], (unsigned long long)evald);
+        if (tested) atomicAdd(&a.counts[1], (unsigned long long)tested);
+        if (closed) atomicAdd(&a.counts[2], (unsigned long long)closed);
+    }
+}
+
 __global__ void k_zero_counts(unsigned long long* p) {
     if (threadIdx.x < 3) p[threadIdx.x] = 0ull;
 }
@@ -234,6 +356,88 @@ int run_ray_search(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev
     if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
     hipLaunchKernelGGL(k_ray_search, dim3((unsigned)grid), dim3(kRayBlock), lds, s, a);
     CV_HIP(hipGetLastError());
+    if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
+    if (ctx->timing && (rc = ctx->collect()) != CV_OK) return rc;
+    return CV_OK;
+}
+
+namespace {
+
+// Launch k_best_pair on the colour constants and angle table of the context
+// (already prepared for the call's colours).
+int launch_best_pair(cv_context* ctx, RayArgs& a, const GridDev& gd, const RuleDev& rd, int64_t n_max,
+                     hipStream_t s) {
+    a.g = geom_constants();
+    a.rule = rd;
+    a.ra = gd.ra;
+    a.rb = gd.rb;
+    a.nr = gd.nr;
+    a.ntheta = gd.ntheta;
+    a.sym = gd.ntheta == gd.N ? 1 : 0;
+    a.W = a.sym ? gd.N / 2 : gd.ntheta;
+    a.nb = (gd.nr + kRowsPerBlock - 1) / kRowsPerBlock;
+    a.proofs = rd.clip ? 0 : 1;
+    const size_t lds = angle_lds_bytes(a.tab);
+    int lds_max = 0;
+    CV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    hipFuncAttributes fa;
+    CV_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_best_pair)));
+    if (lds + fa.sharedSizeBytes > (size_t)lds_max)
+        return fail(CV_EINVAL, "this grid needs " + std::to_string(lds + fa.sharedSizeBytes) +
+                                   " bytes of LDS per block; the device has " + std::to_string(lds_max));
+    int per_cu = 0;
+    CV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_best_pair, kRayBlock, lds));
+    if (per_cu < 1) per_cu = 1;
+    int64_t grid = (int64_t)per_cu * ctx->num_cu;
+    const int64_t need = (int64_t)ray_blocks_for(n_max, kRayBlock / 64);
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_best_pair, dim3((unsigned)grid), dim3(kRayBlock), lds, s, a);
+    CV_HIP(hipGetLastError());
+    return CV_OK;
+}
+
+}  // namespace
+
+int run_best_pair_list(cv_context* ctx, const GridDev& gd, const RuleDev& rd, const uint32_t* list,
+                       const uint64_t* n_dev, int64_t n_max, cv_pattern_pair* pairs, uint8_t* status, hipStream_t s) {
+    if (n_max == 0) return CV_OK;
+    RayArgs a = {};
+    a.cc = (const ColorConst*)ctx->colors.ptr;
+    a.tab.tab = (const double*)ctx->table.ptr;
+    a.tab.tab_len = gd.tab_len;
+    a.tab.N = gd.N;
+    a.tab.dW = direct_rays(gd.ntheta, gd.N, gd.tab_len, 0);
+    a.tab._pad = 0;
+    a.list = list;
+    a.n_dev = n_dev;
+    a.n = n_max;
+    a.ppairs = pairs;
+    a.status = status;
+    return launch_best_pair(ctx, a, gd, rd, n_max, s);
+}
+
+int run_best_pair(cv_context* ctx, const uint8_t* rgb, int64_t n, const GridDev& gd, const RuleDev& rd,
+                  uint32_t* best, cv_pair* pairs, uint64_t* counts, hipStream_t s) {
+    if (counts) {
+        hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, s, (unsigned long long*)counts);
+        CV_HIP(hipGetLastError());
+    }
+    if (n == 0) return CV_OK;
+    int rc;
+    TabArgs tab;
+    if ((rc = prepare_colours(ctx, rgb, n, gd, s, tab)) != CV_OK) return rc;
+    RayArgs a = {};
+    a.cc = (const ColorConst*)ctx->colors.ptr;
+    a.tab = tab;
+    a.counts = (unsigned long long*)counts;
+    a.best = best;
+    a.pairs = pairs;
+    a.n = n;
+    if ((rc = ctx->mark(CV_TIME_CALL, 0, s)) != CV_OK) return rc;
+    if ((rc = ctx->mark(CV_TIME_EVAL, 0, s)) != CV_OK) return rc;
+    if ((rc = launch_best_pair(ctx, a, gd, rd, n, s)) != CV_OK) return rc;
     if ((rc = ctx->mark(CV_TIME_EVAL, 1, s)) != CV_OK) return rc;
     if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;
     if (ctx->timing && (rc = ctx->collect()) != CV_OK) return rc;

@@ -182,6 +182,19 @@ def test_frames_generate_validation(cv):
     assert b"noise" in L.cv_last_error()
 
 
+def test_best_pair_validation(cv):
+    L = cv.lib()
+    d = C.cast((C.c_uint8 * 4096)(), C.c_void_p)
+    g = cv.Grid(0.1, 10, 1.0, 360).c()
+    r = cv.Rule().c()
+    assert L.cv_best_pair_search(None, d, 4, C.byref(g), C.byref(r), d, d, None, None) == cv.CV_EINVAL
+    assert L.cv_best_pair_search(d, d, 4, C.byref(g), C.byref(r), None, None, None, None) == cv.CV_EINVAL
+    assert L.cv_best_pair_search(d, None, 4, C.byref(g), C.byref(r), d, None, None, None) == cv.CV_EINVAL
+    assert L.cv_best_pair_search(d, d, -1, C.byref(g), C.byref(r), d, None, None, None) == cv.CV_EINVAL
+    gbad = cv.Grid(0.1, 10, 7.0, 360).c()   # 360 / 7 is not an integer
+    assert L.cv_best_pair_search(d, d, 4, C.byref(gbad), C.byref(r), d, None, None, None) == cv.CV_EINVAL
+
+
 def test_binding_refuses_host_tensors(cv):
     import torch
     with pytest.raises(ValueError):
