@@ -81,12 +81,12 @@ FLOPS_CELL = 84
 MEASURED_COUNTERS = {
     "count_pass": {"sources_sha256": "7f819a3d585b0b1d191b0a5dd09005670345c7b20ec497c51ea20abe8ac8d1ff",
                    "traffic_bytes": 55112478, "valu_issue": 0.532},
-    "colour_resolve": {"sources_sha256": "585bbeb7203dbd6afabab7bef8648cf1e7cdcce0b4a1061a305583976c30c752",
-                   "traffic_bytes": 8561481792, "valu_issue": 0.975},
+    "colour_resolve": {"sources_sha256": "04438a0f94241811bb714d6b488b4ffba26705a5cfcd1437997e0da74518f907",
+                   "traffic_bytes": 8628745906, "valu_issue": 0.975},
     "cube_table": {"sources_sha256": "7f819a3d585b0b1d191b0a5dd09005670345c7b20ec497c51ea20abe8ac8d1ff",
                    "traffic_bytes": 3568505768, "valu_issue": 0.947},
-    "ray_search": {"sources_sha256": "6d0528e242ff118e1584b4863e146ee703b6bc7a4d9dc6e6fe88d7ed6a29db6d",
-                   "traffic_bytes": 6319238829, "valu_issue": 0.84},
+    "ray_search": {"sources_sha256": "d973da2cb9c984fd438736b2f24fb8e84a32e06c2ac38259eff87d5743401e00",
+                   "traffic_bytes": 6321631877, "valu_issue": 0.839},
 }
 KERNEL_SOURCES = {
     "count_pass": ("cvib_search.hip", "cvib_device.h", "cvib_kernels.h"),
