@@ -381,8 +381,12 @@ def bench_surrogate(cv, W, torch, epochs, steps):
     bp = cv.best_pair_search(cols, grid, rule, ctx=ctx)
     ms_bp = timed(lambda: cv.best_pair_search(cols, grid, rule, out=bp, ctx=ctx), steps)
     key_bp = bp.best[:n].cpu().numpy().view(np.uint32).astype(np.int64)
+    ev_bp = int(bp.counts[0].item())
     comps["exact_early_exit"] = {"ms_per_call": ms_bp, "equal_to_exhaustive_best": bool(np.array_equal(key_bp, want)),
-                                 "evaluated_fraction": int(bp.counts[0].item()) / (n * g.per_colour)}
+                                 "evaluated_fraction": ev_bp / (n * g.per_colour),
+                                 # 85 flop per evaluated pair over the whole call, against the FP32 peak
+                                 "achieved_tflops": FLOPS_PER_PAIR * ev_bp / (ms_bp * 1e-3) / 1e12,
+                                 "frac_of_fp32_peak": FLOPS_PER_PAIR * ev_bp / (ms_bp * 1e-3) / FP32_PEAK}
     for v in comps.values():
         v["colours_per_s"] = n / (v["ms_per_call"] * 1e-3)
     return {
