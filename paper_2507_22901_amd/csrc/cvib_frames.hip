@@ -20,6 +20,58 @@ constexpr int64_t kCubeWords = kCube / 32;      // bitmap words
 // ---------------------------------------------------------------------------
 // De-duplication through a 2^24-bit bitmap of colour ids R<<16 | G<<8 | B.
 
+// Pixels are 3 bytes; the pixel index and the surrogate's renderer take them
+// four at a time, 12 bytes as three aligned words when the arrays allow it
+// (else byte by byte), and the last npix % 4 pixels one by one.  (The bitmap
+// marking and the exact renderer, whose reads depend on atomics or branch per
+// pixel, measured slower that way and keep one pixel per thread.)
+struct Quad {
+    uint32_t w[3];
+};
+
+__device__ __forceinline__ Quad load_quad(const uint8_t* __restrict__ px, int64_t q, bool aligned) {
+    Quad r;
+    if (aligned) {
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(px + 12 * q);
+        r.w[0] = p[0];
+        r.w[1] = p[1];
+        r.w[2] = p[2];
+    } else {
+        const uint8_t* p = px + 12 * q;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            r.w[k] = (uint32_t)p[4 * k] | ((uint32_t)p[4 * k + 1] << 8) | ((uint32_t)p[4 * k + 2] << 16) |
+                     ((uint32_t)p[4 * k + 3] << 24);
+    }
+    return r;
+}
+
+__device__ __forceinline__ void store_quad(uint8_t* __restrict__ out, int64_t q, const Quad& v, bool aligned) {
+    if (aligned) {
+        uint32_t* p = reinterpret_cast<uint32_t*>(out + 12 * q);
+        p[0] = v.w[0];
+        p[1] = v.w[1];
+        p[2] = v.w[2];
+    } else {
+        uint8_t* p = out + 12 * q;
+#pragma unroll
+        for (int b = 0; b < 12; ++b) p[b] = (uint8_t)(v.w[b >> 2] >> (8 * (b & 3)));
+    }
+}
+
+// Byte b of a quad, and colour k's id R<<16 | G<<8 | B.
+__device__ __forceinline__ uint32_t quad_byte(const Quad& v, int b) { return (v.w[b >> 2] >> (8 * (b & 3))) & 255u; }
+__device__ __forceinline__ uint32_t quad_id(const Quad& v, int k) {
+    return (quad_byte(v, 3 * k) << 16) | (quad_byte(v, 3 * k + 1) << 8) | quad_byte(v, 3 * k + 2);
+}
+__device__ __forceinline__ void quad_set(Quad& v, int b, uint32_t x) {
+    const int sh = 8 * (b & 3);
+    v.w[b >> 2] = (v.w[b >> 2] & ~(255u << sh)) | ((x & 255u) << sh);
+}
+__device__ __forceinline__ uint32_t pixel_id(const uint8_t* __restrict__ px, int64_t p) {
+    return ((uint32_t)px[3 * p] << 16) | ((uint32_t)px[3 * p + 1] << 8) | px[3 * p + 2];
+}
+
 __global__ void k_bitmap_mark(const uint8_t* __restrict__ px, int64_t npix,
                               uint32_t* __restrict__ bits) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -56,15 +108,35 @@ __global__ void k_bitmap_compact(const uint32_t* __restrict__ bits,
     }
 }
 
-// Index of each pixel's colour in the sorted list.
+// Index of each pixel's colour in the sorted list (idx16: the index array is
+// 16-byte aligned, four indices written as one store).
+__device__ __forceinline__ uint32_t colour_index(const uint32_t* __restrict__ bits, const uint64_t* __restrict__ prefix,
+                                                 uint32_t id) {
+    const uint32_t w = id >> 5, b = id & 31u;
+    return (uint32_t)prefix[w] + (uint32_t)__builtin_popcount(bits[w] & ((1u << b) - 1u));
+}
+
 __global__ void k_pixel_index(const uint8_t* __restrict__ px, int64_t npix,
                               const uint32_t* __restrict__ bits,
-                              const uint64_t* __restrict__ prefix, uint32_t* __restrict__ index) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
-        const uint32_t id = ((uint32_t)px[3 * p] << 16) | ((uint32_t)px[3 * p + 1] << 8) | px[3 * p + 2];
-        const uint32_t w = id >> 5, b = id & 31u;
-        index[p] = (uint32_t)prefix[w] + (uint32_t)__builtin_popcount(bits[w] & ((1u << b) - 1u));
+                              const uint64_t* __restrict__ prefix, uint32_t* __restrict__ index, bool aligned,
+                              bool idx16) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x, nq = npix >> 2;
+    for (int64_t q = t; q < nq; q += stride) {
+        const Quad v = load_quad(px, q, aligned);
+        uint32_t r[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[k] = colour_index(bits, prefix, quad_id(v, k));
+        if (idx16) {
+            *reinterpret_cast<uint4*>(index + 4 * q) = make_uint4(r[0], r[1], r[2], r[3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) index[4 * q + k] = r[k];
+        }
+    }
+    if (t < (npix & 3)) {
+        const int64_t p = 4 * nq + t;
+        index[p] = colour_index(bits, prefix, pixel_id(px, p));
     }
 }
 
@@ -670,13 +742,46 @@ __global__ void k_make_list(const uint32_t* __restrict__ need, const uint64_t* _
 }
 
 // Two frames from one pair per colour.
+// Two frames from one pair per colour (the surrogate's): aligned and idx16 as
+// in k_render.
 __global__ void k_render_pairs(const uint8_t* __restrict__ px, int64_t npix,
                                const uint32_t* __restrict__ index,
                                const cv_pattern_pair* __restrict__ pairs, uint8_t* __restrict__ fa,
-                               uint8_t* __restrict__ fb, unsigned long long* __restrict__ resolved) {
+                               uint8_t* __restrict__ fb, unsigned long long* __restrict__ resolved, bool aligned,
+                               bool idx16) {
     uint32_t got = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x, nq = npix >> 2;
+    for (int64_t qd = t; qd < nq; qd += stride) {
+        const Quad v = load_quad(px, qd, aligned);
+        Quad QA = v, QB = v;
+        uint32_t ks[4];
+        if (idx16) {
+            const uint4 u = *reinterpret_cast<const uint4*>(index + 4 * qd);
+            ks[0] = u.x;
+            ks[1] = u.y;
+            ks[2] = u.z;
+            ks[3] = u.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ks[k] = index[4 * qd + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const cv_pattern_pair& r = pairs[ks[k]];
+            if (r.flags & CV_PAIR_FOUND) {
+                for (int c = 0; c < 3; ++c) {
+                    quad_set(QA, 3 * k + c, r.plus[c]);
+                    quad_set(QB, 3 * k + c, r.minus[c]);
+                }
+                ++got;
+            }
+        }
+        store_quad(fa, qd, QA, aligned);
+        store_quad(fb, qd, QB, aligned);
+    }
+    if (t < (npix & 3)) {
+        const int64_t p = 4 * nq + t;
         const cv_pattern_pair& r = pairs[index[p]];
         const bool ok = (r.flags & CV_PAIR_FOUND) != 0;
         for (int c = 0; c < 3; ++c) {
@@ -764,6 +869,7 @@ int enqueue_dedupe(cv_context* ctx, const uint8_t* pixels, int64_t npix, uint8_t
     uint64_t* misc = (uint64_t*)ctx->fmisc.ptr;  // [0] colour count
     hipLaunchKernelGGL(k_zero_words, dim3(1024), dim3(256), 0, s, (uint64_t*)bits, kCubeWords / 2);
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, misc, (int64_t)8);
+    const bool px4 = ((uintptr_t)pixels & 3u) == 0, idx16 = ((uintptr_t)pixel_index & 15u) == 0;
     hipLaunchKernelGGL(k_bitmap_mark, dim3(grid_for(npix, 256, 8192)), dim3(256), 0, s, pixels,
                        npix, bits);
     hipLaunchKernelGGL(k_bitmap_popc, dim3((unsigned)(kCubeWords / 256)), dim3(256), 0, s, bits, cnt);
@@ -772,8 +878,8 @@ int enqueue_dedupe(cv_context* ctx, const uint8_t* pixels, int64_t npix, uint8_t
         return rc;
     hipLaunchKernelGGL(k_bitmap_compact, dim3((unsigned)(kCubeWords / 256)), dim3(256), 0, s, bits,
                        prefix, colours);
-    hipLaunchKernelGGL(k_pixel_index, dim3(grid_for(npix, 256, 8192)), dim3(256), 0, s, pixels, npix,
-                       bits, prefix, pixel_index);
+    hipLaunchKernelGGL(k_pixel_index, dim3(grid_for((npix + 3) / 4, 256, 8192)), dim3(256), 0, s, pixels, npix,
+                       bits, prefix, pixel_index, px4, idx16);
     hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, misc, ncolours);
     CV_HIP(hipGetLastError());
     return CV_OK;
@@ -1139,9 +1245,10 @@ int run_frames_surrogate(cv_context* ctx, const SurrogateCall& c, const uint8_t*
     if (frame_a) {
         if (resolved)
             hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, (uint64_t*)resolved, (int64_t)1);
-        hipLaunchKernelGGL(k_render_pairs, dim3(grid_for(npix, 256, 8192)), dim3(256), 0, s, pixels, npix,
-                           pixel_index, (const cv_pattern_pair*)c.pairs, frame_a, frame_b,
-                           (unsigned long long*)resolved);
+        const bool al = (((uintptr_t)pixels | (uintptr_t)frame_a | (uintptr_t)frame_b) & 3u) == 0;
+        hipLaunchKernelGGL(k_render_pairs, dim3(grid_for((npix + 3) / 4, 256, 8192)), dim3(256), 0, s, pixels,
+                           npix, pixel_index, (const cv_pattern_pair*)c.pairs, frame_a, frame_b,
+                           (unsigned long long*)resolved, al, ((uintptr_t)pixel_index & 15u) == 0);
         CV_HIP(hipGetLastError());
     }
     if ((rc = ctx->mark(CV_TIME_CALL, 1, s)) != CV_OK) return rc;

@@ -229,3 +229,29 @@ def test_reused_buffers_are_checked(cv):
         cv.pair_search(cols, grid, rule, offsets=torch.empty(5, dtype=torch.int64, device="cuda"))
     with pytest.raises(ValueError):
         cv.pair_search(cols, grid, rule, summ_out=torch.empty((5, 48), dtype=torch.int8, device="cuda"))
+
+
+def test_unaligned_and_ragged_pixel_arrays(cv):
+    """The per-pixel kernels take four pixels (12 bytes) at a time as words
+    from 4-byte aligned arrays, byte by byte from others, and the last
+    npix % 4 pixels one by one: pixel and information arrays that start off a
+    word, with pixel counts that are not multiples of 4, give the outputs of
+    aligned copies (which the tests above hold to the oracle and to a host
+    composition of the frames)."""
+    f = _frames()
+    base = torch.from_numpy(f.reshape(-1, 3)).cuda()
+    grid, rule = cv.Grid(0.5, 70, 2.0, 180), cv.Rule(50, 0.5, 0x7F)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    for start, npix in ((1, 1021), (0, 1023), (3, 4094), (2, 4097), (5, 3)):
+        view = base[start:start + npix]          # starts 3 * start bytes in
+        info_all = torch.randint(0, 8, (npix + 1,), dtype=torch.uint8, device="cuda", generator=g)
+        a = cv.frames_resolve(view, grid, rule, info=info_all[1:])
+        b = cv.frames_resolve(view.clone(), grid, rule, info=info_all[1:].clone())
+        torch.cuda.synchronize()
+        n = int(b.ncolours.item())
+        assert int(a.ncolours.item()) == n, (start, npix)
+        for x, y in ((a.colours[:n], b.colours[:n]), (a.pixel_index, b.pixel_index),
+                     (a.frame_a, b.frame_a), (a.frame_b, b.frame_b), (a.resolved, b.resolved)):
+            assert torch.equal(x, y), (start, npix)
+        # the index points at each pixel's own colour, ragged tail included
+        assert torch.equal(a.colours[a.pixel_index.long()], view)

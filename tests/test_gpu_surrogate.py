@@ -207,3 +207,23 @@ def test_fallback_list_and_given_proposals(cv, trained):
     # reusing the result's buffers gives the same again
     c = cv.surrogate_infer(cols, trained["mlp"], grid, rule, tau=0.0, want_pred=True, want_list=True, out=a)
     assert c is a and torch.equal(c.pairs, b.pairs)
+
+
+def test_frames_surrogate_unaligned_pixels(cv, trained):
+    """The surrogate's renderer on a pixel array that starts off a word, with a
+    pixel count that is not a multiple of 4: the same outputs as an aligned
+    copy, and the frames are the host composition of the pairs."""
+    f = W.frames([13], height=40, width=61).reshape(-1, 3)
+    base = torch.from_numpy(f).cuda()
+    view = base[1:1 + 2437]
+    grid, rule = cv.Grid(*W.GRID_FRAMES.astuple()), cv.Rule(*W.DEFAULT_RULE)
+    a = cv.frames_surrogate(view, trained["mlp"], grid, rule, tau=0.0)
+    b = cv.frames_surrogate(view.clone(), trained["mlp"], grid, rule, tau=0.0)
+    torch.cuda.synchronize()
+    for x, y in ((a.pixel_index, b.pixel_index), (a.frame_a, b.frame_a), (a.frame_b, b.frame_b),
+                 (a.resolved, b.resolved)):
+        assert torch.equal(x, y)
+    pb = a.pairs[a.pixel_index.long()]
+    has = (pb[:, 11] & 1).bool()
+    assert torch.equal(a.frame_a, torch.where(has[:, None], pb[:, 4:7], view))
+    assert torch.equal(a.frame_b, torch.where(has[:, None], pb[:, 7:10], view))
