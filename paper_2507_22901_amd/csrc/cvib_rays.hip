@@ -218,10 +218,45 @@ __global__ __launch_bounds__(kRayBlock) void k_best_pair(RayArgs a) {
                 uint64_t om = uniform_u64(__ballot(open));
                 tested += (uint64_t)__builtin_popcountll(lm);
                 closed += (uint64_t)__builtin_popcountll(lm & ~om);
-                while (om) {
+                while (om && floor_i < hi_i) {
+                    // Past the level's first survivor, the open rays left only
+                    // need the radii above it: when those rows are fewer than
+                    // the rays, take them row by row (lane -> ray, the chunk's
+                    // rays together) and stop at the first row with a
+                    // survivor (its smallest j); else ray by ray.
+                    if (floor_i >= 0 && hi_i - floor_i < __builtin_popcountll(om)) {
+                        const bool mine = (om >> lane) & 1ull;
+                        double s, co;
+                        ang.get(mine ? jl : j0 + (int32_t)__builtin_ctzll(om), s, co);
+                        for (int32_t i = hi_i; i > floor_i; --i) {
+                            const double rad = (double)(i + 1);
+                            float fp[3], fm[3];
+                            pair_linear_w(cc, a.g, (rad * a.ra) * s, (rad * a.rb) * co, fp, fm, cube);
+                            const uint64_t live_m = __ballot(mine);
+                            evald += (uint64_t)__builtin_popcountll(live_m);
+                            const bool gp = in_unit_cube(fp), gm = in_unit_cube(fm);
+                            const uint64_t need_m = clip ? live_m : (__ballot(gp && gm) & live_m);
+                            if (need_m == 0ull) continue;
+                            float Vp[3], Vm[3];
+                            codes_w(fp, fm, (need_m >> lane) & 1ull, clip, Vp, Vm);
+                            const PatMasks pm = pattern_masks(Vp, Vm, a.rule);
+                            const uint64_t surv = uniform_u64(accepted_lanes(pm, a.rule.mask) & need_m);
+                            if (surv == 0ull) continue;
+                            const int32_t first = (int32_t)__builtin_ctzll(surv);  // smallest j of the row
+                            uint32_t lo, hi;
+                            const uint32_t flags = 4u | (gp ? 1u : 0u) | (gm ? 2u : 0u);
+                            pack_pair(Vp, Vm, pattern_of(Vp, Vm, a.rule), flags, lo, hi);
+                            floor_i = i;
+                            best = best_key(i, j0 + first);
+                            blo = (uint32_t)__shfl((int)lo, first, 64);
+                            bhi = (uint32_t)__shfl((int)hi, first, 64);
+                            break;
+                        }
+                        om = 0ull;
+                        break;
+                    }
                     const int32_t j = j0 + (int32_t)__builtin_ctzll(om);
                     om &= om - 1ull;
-                    if (hi_i <= floor_i) break;  // no radius of the level above the best found
                     double s, co;
                     ang.get(j, s, co);
                     const int32_t i = hi_i - (int32_t)lane;
