@@ -194,18 +194,19 @@ struct ResolveArgs {
 };
 
 // Per-block sum of the lanes' skipped counts into stats (every thread calls
-// it once, at the end).
+// it once, at the end; w = the wave of the block).
 template <int NW>
-__device__ __forceinline__ void add_skipped(uint64_t* stats, uint64_t skipped, uint64_t no_high) {
+__device__ __forceinline__ void add_skipped(uint64_t* stats, uint64_t skipped, uint64_t no_high, int w) {
     if (!stats) return;
     __shared__ uint64_t s_skip[NW], s_noh[NW];
+    const uint32_t lane = lane_id_fresh();
     for (int o = 32; o > 0; o >>= 1) skipped += (uint64_t)__shfl_xor((unsigned long long)skipped, o, 64);
-    if ((threadIdx.x & 63u) == 0) {
-        s_skip[threadIdx.x >> 6] = skipped;
-        s_noh[threadIdx.x >> 6] = no_high;
+    if (lane == 0) {
+        s_skip[w] = skipped;
+        s_noh[w] = no_high;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (w == 0 && lane == 0) {
         uint64_t sum = 0, nh = 0;
         for (int q = 0; q < NW; ++q) {
             sum += s_skip[q];
@@ -350,9 +351,7 @@ __global__ __launch_bounds__(256, 6) void k_colour_resolve(ResolveArgs a) {
     extern __shared__ double s_dyn[];
     __shared__ uint32_t s_red[NW][10];
     __shared__ uint32_t s_pb[7];
-    const int tid = threadIdx.x;
-    const uint32_t lane = (uint32_t)tid & 63u;
-    const int w = tid >> 6;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // the wave of the block
     const Angles ang = load_angles(a.tab, s_dyn);
     uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW);
     const uint32_t mult = SYM ? 2u : 1u;
@@ -360,6 +359,10 @@ __global__ __launch_bounds__(256, 6) void k_colour_resolve(ResolveArgs a) {
     uint64_t skipped = 0, no_high = 0;
 
     for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+        // the thread's indices taken afresh every colour (nothing derived
+        // from them stays live across the colours)
+        const uint32_t lane = lane_id_fresh();
+        const int tid = w * 64 + (int)lane;
         const int64_t c = a.list ? (int64_t)a.list[k] : k;
         if (RAYS)
             for (int q = tid; q < a.W; q += BLOCK) s_ray[q] = 0;
@@ -401,7 +404,7 @@ __global__ __launch_bounds__(256, 6) void k_colour_resolve(ResolveArgs a) {
         }
         __syncthreads();
     }
-    add_skipped<NW>(a.stats, skipped, no_high);
+    add_skipped<NW>(a.stats, skipped, no_high, w);
 }
 
 // LDS written by some lanes of a wave visible to its other lanes: a wave's
@@ -459,7 +462,7 @@ __global__ __launch_bounds__(BLOCK) void k_colour_resolve_w(ResolveArgs a) {
         }
         wave_lds_sync();
     }
-    add_skipped<NW>(a.stats, skipped, no_high);  // every wave reaches it once its colours are done
+    add_skipped<NW>(a.stats, skipped, no_high, w);  // every wave reaches it once its colours are done
 }
 
 // ---------------------------------------------------------------------------

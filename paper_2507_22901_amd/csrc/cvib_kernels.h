@@ -16,6 +16,16 @@ __device__ __forceinline__ uint32_t lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 
+// The lane index from an mbcnt the compiler can neither hoist nor merge:
+// taken at the top of a persistent loop's body, the per-lane values derived
+// from it (LDS addresses, lane tests) are recomputed every iteration instead
+// of being kept live across the loop, where they would spill to scratch.
+__device__ __forceinline__ uint32_t lane_id_fresh() {
+    uint32_t l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return l;
+}
+
 // A value known to be equal in every lane, moved to a scalar register.
 __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);

@@ -613,9 +613,7 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
     __shared__ uint16_t s_olist[LISTS ? kMaxListed : 1];
     __shared__ int32_t s_nopen;
 
-    const int tid = threadIdx.x;
-    const uint32_t lane = (uint32_t)tid & 63u;
-    const int w = tid >> 6;
+    const int w_s = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // the wave of the block
     const Angles ang = load_angles(a.tab, s_dyn);
     uint32_t* s_ray = reinterpret_cast<uint32_t*>(s_dyn + a.tab.tab_len + 2 * a.tab.dW);
     uint64_t* s_open =
@@ -629,6 +627,11 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
     uint64_t no_high = 0;  // in-gamut pairs of steps without a high channel (lane 0)
 
     for (;;) {
+        // the thread's indices taken afresh every tile (nothing derived from
+        // them stays live across the tiles)
+        const uint32_t lane = lane_id_fresh();
+        const int w = w_s;
+        const int tid = w * 64 + (int)lane;
         if (tid == 0) s_tick = (int64_t)atomicAdd((unsigned long long*)&a.misc[0], 1ull);
         if constexpr (TABLE) {
             for (int k = tid; k < a.W; k += BLOCK) s_ray[k] = 0;
@@ -973,6 +976,9 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
     }
     // every thread left the loop at the same ticket, after a barrier
     if (a.stats) {
+        const uint32_t lane = lane_id();
+        const int w = w_s;
+        const int tid = w * 64 + (int)lane;
         __shared__ uint64_t s_skip[NW], s_noh[NW];
         for (int o = 32; o > 0; o >>= 1) skipped += (uint64_t)__shfl_xor((unsigned long long)skipped, o, 64);
         if (lane == 0) {
