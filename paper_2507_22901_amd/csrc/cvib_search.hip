@@ -628,10 +628,12 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
 
     for (;;) {
         // the thread's indices taken afresh every tile (nothing derived from
-        // them stays live across the tiles)
-        const uint32_t lane = lane_id_fresh();
-        const int w = w_s;
-        const int tid = w * 64 + (int)lane;
+        // them stays live across the tiles); the wave index as a vector
+        // value, as threadIdx.x >> 6 would give it, schedules the tile's
+        // loops best
+        const int tid = w_s * 64 + (int)lane_id_fresh();
+        const uint32_t lane = (uint32_t)tid & 63u;
+        const int w = tid >> 6;
         if (tid == 0) s_tick = (int64_t)atomicAdd((unsigned long long*)&a.misc[0], 1ull);
         if constexpr (TABLE) {
             for (int k = tid; k < a.W; k += BLOCK) s_ray[k] = 0;
