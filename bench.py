@@ -79,14 +79,14 @@ FLOPS_CELL = 84
 # GRBM_GUI_ACTIVE cycles per XCD.  Valid only for the kernel sources they were
 # measured on (their digest); null otherwise.
 MEASURED_COUNTERS = {
-    "count_pass": {"sources_sha256": "7f819a3d585b0b1d191b0a5dd09005670345c7b20ec497c51ea20abe8ac8d1ff",
-                   "traffic_bytes": 55112478, "valu_issue": 0.532},
-    "colour_resolve": {"sources_sha256": "04438a0f94241811bb714d6b488b4ffba26705a5cfcd1437997e0da74518f907",
-                   "traffic_bytes": 8628745906, "valu_issue": 0.975},
-    "cube_table": {"sources_sha256": "7f819a3d585b0b1d191b0a5dd09005670345c7b20ec497c51ea20abe8ac8d1ff",
-                   "traffic_bytes": 3568505768, "valu_issue": 0.947},
-    "ray_search": {"sources_sha256": "d973da2cb9c984fd438736b2f24fb8e84a32e06c2ac38259eff87d5743401e00",
-                   "traffic_bytes": 6321631877, "valu_issue": 0.839},
+    "count_pass": {"sources_sha256": "0fd9b231ad124d4a9bb82ff0840449b3858a0a563c60bd125ec71ead0bf5fb9b",
+                   "traffic_bytes": 7068439, "valu_issue": 0.546},
+    "colour_resolve": {"sources_sha256": "5f04fba42aaf06dba46d463ff3ca8adc7ca872cd8390d3d0e828ca9737aa9518",
+                   "traffic_bytes": 4325181759, "valu_issue": 0.973},
+    "cube_table": {"sources_sha256": "0fd9b231ad124d4a9bb82ff0840449b3858a0a563c60bd125ec71ead0bf5fb9b",
+                   "traffic_bytes": 3569567526, "valu_issue": 0.989},
+    "ray_search": {"sources_sha256": "a7cd1841ca69f53284b22c5515058c139ee817c02bf9ec88e30ac6633cb2a932",
+                   "traffic_bytes": 6319763013, "valu_issue": 0.837},
 }
 KERNEL_SOURCES = {
     "count_pass": ("cvib_search.hip", "cvib_device.h", "cvib_kernels.h"),
@@ -390,7 +390,7 @@ def bench_surrogate(cv, W, torch, epochs, steps):
     for v in comps.values():
         v["colours_per_s"] = n / (v["ms_per_call"] * 1e-3)
     return {
-        "workload": "surrogate 3-256-256-256-37 (first hidden layer sin(30 z), then ReLU) trained with "
+        "workload": "surrogate 3-256-256-256-37 (first hidden layer sin(20 z), then ReLU) trained with "
                     "Adam (batch 8192, lr 2e-3 cosine to 2e-5, Huber 0.2) on the 2^24-colour table (r step 0.25, "
                     "theta step 2 deg; 90/10 split, seed 0); 16 synthetic 3840x2160 frames generated on the device "
                     "(seeds 100..115) on r = 0.1..50 step 0.1 x theta step 1 deg",

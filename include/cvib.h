@@ -497,7 +497,7 @@ int cv_context_kernel_time(cv_context* ctx, int phase, double* ms_host, int64_t*
  * ReLU after every layer but the last; the first hidden layer may instead be
  * sinusoidal, sin(omega0 z) (cv_mlp_set_first_sine).  The surrogate of the
  * exact search is 3 -> 256 -> 256 -> 256 -> 37 with a sinusoidal first layer
- * (omega0 = 30): input RGB / 255 - 1/2, outputs the largest
+ * (omega0 = 20): input RGB / 255 - 1/2, outputs the largest
  * valid radius of each of the 36 angle bins divided by 50 (the table of
  * cv_pair_reduce) and a feasibility logit.  The paper describes no learned
  * part; the network only proposes pairs that the exact predicate re-checks

@@ -87,7 +87,7 @@ CV_TIME_MLP, CV_TIME_VERIFY = 3, 4
 CV_MLP_KEEP = 0x1
 CV_MLP_RGB8 = 0x2
 SURROGATE_DIMS = (3, 256, 256, 256, 37)
-SURROGATE_OMEGA0 = 30.0   # first hidden layer sin(30 z)
+SURROGATE_OMEGA0 = 20.0   # first hidden layer sin(20 z)
 
 _lib = None
 
@@ -826,7 +826,7 @@ def permute_ids(ids: torch.Tensor, key: int, out: torch.Tensor | None = None,
 
 def surrogate_network(seed: int = 0, ctx: Context | None = None) -> MLP:
     """The untrained surrogate network: 3 -> 256 -> 256 -> 256 -> 37 with a
-    sinusoidal first layer (omega0 = 30), initialised from `seed`."""
+    sinusoidal first layer (omega0 = 20), initialised from `seed`."""
     m = MLP(SURROGATE_DIMS, ctx)
     m.set_first_sine(SURROGATE_OMEGA0)
     m.set_params(init_params(SURROGATE_DIMS, seed, first_sine=True))
