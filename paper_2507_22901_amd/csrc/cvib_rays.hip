@@ -176,10 +176,12 @@ __global__ __launch_bounds__(kRayBlock) void k_ray_search(RayArgs a) {
 
 // Exact one-pair resolve with a global early exit: the maximum-amplitude pair
 // (largest i, then smallest j) of every colour.  One wave per colour takes the
-// levels of 64 radii from the outermost inward; at each level every ray's
-// block is proven empty where the interval bound can (lane -> ray), and the
-// open ones are evaluated with the search's arithmetic (lane -> radius, lane 0
-// outermost), each only above the largest i found so far at that level.  The
+// levels of 64 radii from the outermost inward; eight levels by eight angular
+// sectors are first proven as coarse cells, then at each level every ray of
+// an open sector has its block proven empty where the interval bound can
+// (lane -> ray), and the open ones are evaluated with the search's arithmetic
+// (lane -> radius, lane 0 outermost), each only above the largest i found so
+// far at that level.  The
 // first level with a survivor holds the colour's largest i, so the walk stops
 // there; the key is then the exhaustive search's best, bit for bit.  The
 // mirrored rays of the half-turn hold the same radii at larger j: never better.
@@ -197,22 +199,50 @@ __global__ __launch_bounds__(kRayBlock) void k_best_pair(RayArgs a) {
         const ColorConst cc = a.cc[c];
         const bool cube = cube_branch_only(cc, a.nr - 1, a.ra, a.rb);
         uint32_t best = 0, blo = 0, bhi = 0;  // the same in every lane
+        uint64_t cells = ~0ull;               // coarse cells of the current eight levels (bit 8 level + sector)
         for (int32_t bb = 0; bb < a.nb && best == 0u; ++bb) {
             const int32_t hi_i = a.nr - 1 - kRowsPerBlock * bb;
             const int32_t lo_i = max(hi_i - (kRowsPerBlock - 1), 0);
+            if (a.proofs && (bb & 7) == 0) {
+                // Coarse cells of levels bb .. bb + 7: lane -> (level bb + lane / 8,
+                // sector lane % 8 of the rays, those j with 8 j / W = sector),
+                // one interval proof each; a level whose sectors are all proven
+                // is skipped, and a step of 64 rays that all lie in proven
+                // sectors takes no per-ray proof.
+                const int32_t lv = bb + ((int32_t)lane >> 3), sec = (int32_t)lane & 7;
+                const int32_t js0 = (sec * a.W + 7) >> 3, js1 = ((sec + 1) * a.W + 7) / 8 - 1;
+                const int32_t chi = a.nr - 1 - kRowsPerBlock * lv, clo = max(chi - (kRowsPerBlock - 1), 0);
+                const bool any = lv < a.nb && js0 <= js1;
+                double s0, c0, s1, c1;
+                ang.get(any ? js0 : 0, s0, c0);
+                ang.get(any ? js1 : 0, s1, c1);
+                bool high = true;
+                const bool out = cell_out_of_gamut_ends(cc, a.g, ang.N, a.ra, a.rb, any ? clo : 0,
+                                                        any ? chi : 0, any ? js0 : 0, any ? js1 : 0, s0, c0, s1,
+                                                        c1, &a.rule, &high);
+                cells = uniform_u64(__ballot(any && !out && high));
+            }
+            const uint32_t lvcells = a.proofs ? (uint32_t)(cells >> (8 * (bb & 7))) & 0xFFu : 0xFFu;
+            if (lvcells == 0u) {
+                // every sector of the level proven: no survivor at this level
+                tested += (uint64_t)a.W;
+                closed += (uint64_t)a.W;
+                continue;
+            }
             int32_t floor_i = -1;  // radii at or below this cannot beat the level's best so far
             for (int32_t j0 = 0; j0 < a.W && floor_i < hi_i; j0 += 64) {
                 const int32_t jl = j0 + (int32_t)lane;
                 const bool live = jl < a.W;
-                bool open = live;
-                if (a.proofs) {
+                const bool in_open = live && ((lvcells >> ((8 * jl) / a.W)) & 1u);
+                bool open = in_open;
+                if (a.proofs && __ballot(in_open) != 0ull) {
                     const int32_t jj = live ? jl : 0;
                     double s, co;
                     ang.get(jj, s, co);
                     bool high = true;
                     const bool out = cell_out_of_gamut_ends(cc, a.g, ang.N, a.ra, a.rb, lo_i, hi_i, jj, jj, s, co, s,
                                                             co, &a.rule, &high);
-                    open = live && !out && high;
+                    open = in_open && !out && high;
                 }
                 const uint64_t lm = __ballot(live);
                 uint64_t om = uniform_u64(__ballot(open));
