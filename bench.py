@@ -85,8 +85,8 @@ MEASURED_COUNTERS = {
                    "traffic_bytes": 4325181759, "valu_issue": 0.973},
     "cube_table": {"sources_sha256": "0fd9b231ad124d4a9bb82ff0840449b3858a0a563c60bd125ec71ead0bf5fb9b",
                    "traffic_bytes": 3569567526, "valu_issue": 0.989},
-    "ray_search": {"sources_sha256": "a7cd1841ca69f53284b22c5515058c139ee817c02bf9ec88e30ac6633cb2a932",
-                   "traffic_bytes": 6319763013, "valu_issue": 0.837},
+    "ray_search": {"sources_sha256": "b92aeef109e78ea8c4d7c5bbfbad9e5f540b4519acaa6e329edf5bebb5731aba",
+                   "traffic_bytes": 6321723100, "valu_issue": 0.841},
 }
 KERNEL_SOURCES = {
     "count_pass": ("cvib_search.hip", "cvib_device.h", "cvib_kernels.h"),
