@@ -634,7 +634,12 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
         const int tid = w_s * 64 + (int)lane_id_fresh();
         const uint32_t lane = (uint32_t)tid & 63u;
         const int w = tid >> 6;
-        if (tid == 0) s_tick = (int64_t)atomicAdd((unsigned long long*)&a.misc[0], 1ull);
+        // the ticket, -1 once the tiles are dealt (tested by thread 0 alone,
+        // so that the tile count is not held in every lane across the loop)
+        if (tid == 0) {
+            const int64_t tk = (int64_t)atomicAdd((unsigned long long*)&a.misc[0], 1ull);
+            s_tick = tk < a.ntiles ? tk : -1;
+        }
         if constexpr (TABLE) {
             for (int k = tid; k < a.W; k += BLOCK) s_ray[k] = 0;
         }
@@ -648,9 +653,13 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
         }
         __syncthreads();
         const int64_t t = uniform_i64(s_tick);
-        if (t >= a.ntiles) break;
-        const int64_t c = t / a.tiles_per_colour;
-        const int32_t lt = (int32_t)(t - c * a.tiles_per_colour);
+        if (t < 0) break;
+        // the divisor taken afresh every tile: its reciprocal is not hoisted
+        // into a register held across the loop
+        int32_t tpc = a.tiles_per_colour;
+        asm volatile("" : "+s"(tpc));
+        const int64_t c = t / tpc;
+        const int32_t lt = (int32_t)(t - c * tpc);
         const ColorConst cc = a.cc[c];
         const int32_t begin = lt * a.chunk;
         const int32_t len = min(a.chunk, a.nr * a.W - begin);
@@ -737,7 +746,7 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                     const uint64_t tk = __ballot(take);
                     int32_t basew = 0;
                     if (lane == 0 && tk) basew = atomicAdd(&s_nopen, (int32_t)__builtin_popcountll(tk));
-                    basew = __shfl(basew, 0, 64);
+                    basew = __builtin_amdgcn_readlane(basew, 0);
                     if (take) s_olist[basew + (int32_t)rank_below(tk)] = (uint16_t)(sidx | ((open && high) ? 0x8000 : 0));
                 } else {
                     if (take)
@@ -789,12 +798,13 @@ __global__ __launch_bounds__(BLOCK, (DIRECT ? 1 : 6)) void k_pair_reduce(ReduceA
                     uint64_t rem = surv_m;
                     while (rem) {
                         const int32_t first = __builtin_ctzll(rem);
-                        const int32_t sid = __shfl(sl, first, 64);
+                        const int32_t sid = __builtin_amdgcn_readlane(sl, first);
                         const uint64_t m = __ballot(sl == sid) & rem;
                         if (a.seg_mask) {
                             // 64 consecutive evaluations meet at most two passes of a segment,
                             // and the lanes' passes rise with the lane
-                            const int32_t k0 = __shfl(kb, first, 64), k1 = __shfl(kb, 63 - __builtin_clzll(m), 64);
+                            const int32_t k0 = __builtin_amdgcn_readlane(kb, first),
+                                          k1 = __builtin_amdgcn_readlane(kb, 63 - __builtin_clzll(m));
                             if (lane == 0)
                                 atomicOr((unsigned long long*)&s_mask[sid], (1ull << k0) | (1ull << k1));
                         }
