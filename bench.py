@@ -79,12 +79,12 @@ FLOPS_CELL = 84
 # GRBM_GUI_ACTIVE cycles per XCD.  Valid only for the kernel sources they were
 # measured on (their digest); null otherwise.
 MEASURED_COUNTERS = {
-    "count_pass": {"sources_sha256": "0fd9b231ad124d4a9bb82ff0840449b3858a0a563c60bd125ec71ead0bf5fb9b",
-                   "traffic_bytes": 7068439, "valu_issue": 0.546},
+    "count_pass": {"sources_sha256": "8d5db1ca4e1ecbf2eb7bf84b3a44d0095d508d13799ae4b1c566f99ee45db1f1",
+                   "traffic_bytes": 1954010, "valu_issue": 0.55},
     "colour_resolve": {"sources_sha256": "5f04fba42aaf06dba46d463ff3ca8adc7ca872cd8390d3d0e828ca9737aa9518",
                    "traffic_bytes": 4325181759, "valu_issue": 0.973},
-    "cube_table": {"sources_sha256": "0fd9b231ad124d4a9bb82ff0840449b3858a0a563c60bd125ec71ead0bf5fb9b",
-                   "traffic_bytes": 3569567526, "valu_issue": 0.989},
+    "cube_table": {"sources_sha256": "8d5db1ca4e1ecbf2eb7bf84b3a44d0095d508d13799ae4b1c566f99ee45db1f1",
+                   "traffic_bytes": 3568624747, "valu_issue": 0.988},
     "ray_search": {"sources_sha256": "b92aeef109e78ea8c4d7c5bbfbad9e5f540b4519acaa6e329edf5bebb5731aba",
                    "traffic_bytes": 6321723100, "valu_issue": 0.841},
 }
