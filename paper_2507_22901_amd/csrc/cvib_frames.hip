@@ -558,6 +558,27 @@ constexpr float kSweepMargin = 5.0f;  // Delta E
 constexpr float kShortfall = 10.0f;   // Delta E
 __constant__ float kLadder[kDeltas] = {1.0f, 0.0f, -1.0f, -2.5f, -5.0f, -10.0f};
 
+// Largest value over the wave, returned in every lane; the whole wave must be
+// active.  Within each row of 16 lanes by DPP (swap neighbours, swap pairs,
+// mirror within 8, mirror within 16), then the four rows' maxima read as
+// scalars: no LDS round trips, unlike a shuffle tree.
+__device__ __forceinline__ uint32_t wave_max_full(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+    const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return max(max(r0, r1), max(r2, r3));
+}
+
+// A float of a lane given by a wave-uniform index, as a scalar.
+__device__ __forceinline__ float lane_float(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
 // Exact predicate of candidate (i, j) for one lane; false when not live.
 __device__ __forceinline__ bool verify_candidate(const ColorConst& cc, const Angles& ang, const Geom& g,
                                                  const RuleDev& rule, double ra, double rb, int32_t i,
@@ -588,7 +609,7 @@ __device__ __forceinline__ uint32_t climb_ray(const ColorConst& cc, const Angles
     for (int32_t blk = 0, i0 = i_start; blk < kClimbBlocks && i0 < nr; ++blk, i0 += 64) {
         const int32_t i = i0 + lane;
         const bool ok = verify_candidate(cc, ang, g, rule, ra, rb, min(i, nr - 1), j, i < nr);
-        const uint32_t top = wave_max_u32(ok ? best_key(i, j) : 0u);
+        const uint32_t top = wave_max_full(ok ? best_key(i, j) : 0u);
         if (top == 0u) break;
         best = max(best, top);
     }
@@ -634,15 +655,15 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
             // rank of every bin by predicted radius (ties: lower bin first)
             int rank = 0;
             for (int q = 0; q < nb; ++q) {
-                const float rq = __shfl(rk, q);
+                const float rq = lane_float(rk, q);
                 rank += (rq > rk || (rq == rk && q < lane)) ? 1 : 0;
             }
             const int kb = min(a.kbins, nb);
-            top_pred = __shfl(rk, (int)__builtin_ctzll(__ballot(lane < nb && rank == 0)));
+            top_pred = lane_float(rk, (int)__builtin_ctzll(__ballot(lane < nb && rank == 0)));
             for (int b = 0; b < kb; ++b) {
                 const uint64_t sel = __ballot(lane < nb && rank == b);
                 const int bin = (int)__builtin_ctzll(sel);
-                const float rh = __shfl(rk, bin);
+                const float rh = lane_float(rk, bin);
                 // rays of the bin: floor(36 j / N) = bin
                 const int32_t j_lo = (bin * a.tab.N + kBins - 1) / kBins;
                 const int32_t j_hi = min(((bin + 1) * a.tab.N + kBins - 1) / kBins, a.ntheta);
@@ -659,7 +680,7 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
                     const int32_t j = j_lo + (u < ncand ? q : 0);
                     const bool live = u < ncand && i >= 0 && i < a.nr;
                     const bool ok = verify_candidate(cc, ang, a.g, a.rule, a.ra, a.rb, i, j, live);
-                    bb = max(bb, wave_max_u32(ok ? best_key(i, j) : 0u));
+                    bb = max(bb, wave_max_full(ok ? best_key(i, j) : 0u));
                 }
                 best = max(best, bb);
             }
@@ -671,7 +692,7 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
                     const int bin = (int)__builtin_ctzll(sel);
                     // past the proposed bins, only those whose predicted radius
                     // comes within kSweepMargin of the kept one (ranks fall)
-                    if (b >= kb && __shfl(rk, bin) + kSweepMargin <= (float)((best >> 16) + 1) * a.dr) break;
+                    if (b >= kb && lane_float(rk, bin) + kSweepMargin <= (float)((best >> 16) + 1) * a.dr) break;
                     const int32_t j_lo = (bin * a.tab.N + kBins - 1) / kBins;
                     const int32_t j_hi = min(((bin + 1) * a.tab.N + kBins - 1) / kBins, a.ntheta);
                     const int32_t nrays = j_hi - j_lo;
@@ -684,7 +705,7 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
                         const int32_t j = j_lo + min(q, nrays - 1);
                         const bool ok = verify_candidate(cc, ang, a.g, a.rule, a.ra, a.rb, min(i, a.nr - 1), j,
                                                          live);
-                        const uint32_t top = wave_max_u32(ok ? best_key(i, j) : 0u);
+                        const uint32_t top = wave_max_full(ok ? best_key(i, j) : 0u);
                         if (top == 0u) continue;
                         best = climb_ray(cc, ang, a.g, a.rule, a.ra, a.rb, a.nr,
                                          (int32_t)(0xFFFFu - (top & 0xFFFFu)), (int32_t)(top >> 16) + 1,
@@ -699,7 +720,7 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
                     const bool live = j >= 0 && j < jend && j != bj && i < a.nr;
                     const bool ok = verify_candidate(cc, ang, a.g, a.rule, a.ra, a.rb, min(i, a.nr - 1),
                                                      live ? j : bj, live);
-                    const uint32_t top = wave_max_u32(ok ? best_key(i, j) : 0u);
+                    const uint32_t top = wave_max_full(ok ? best_key(i, j) : 0u);
                     if (top == 0u) break;
                     best = climb_ray(cc, ang, a.g, a.rule, a.ra, a.rb, a.nr, (int32_t)(0xFFFFu - (top & 0xFFFFu)),
                                      (int32_t)(top >> 16) + 1, max(best, top));
