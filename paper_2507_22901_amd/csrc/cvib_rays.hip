@@ -185,16 +185,18 @@ __global__ __launch_bounds__(kRayBlock) void k_ray_search(RayArgs a) {
 // first level with a survivor holds the colour's largest i, so the walk stops
 // there; the key is then the exhaustive search's best, bit for bit.  The
 // mirrored rays of the half-turn hold the same radii at larger j: never better.
-__global__ __launch_bounds__(kRayBlock) void k_best_pair(RayArgs a) {
+// Six waves per SIMD (80 registers; a 20-byte spill reloaded per colour) run
+// faster than the five that its unbounded allocation (91) would allow.
+__global__ __launch_bounds__(kRayBlock, 6) void k_best_pair(RayArgs a) {
     extern __shared__ double s_dyn[];
     const Angles ang = load_angles(a.tab, s_dyn);
-    const uint32_t lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * kRayBlock + threadIdx.x) >> 6;
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * kRayBlock + threadIdx.x) >> 6));
     const int64_t nwaves = ((int64_t)gridDim.x * kRayBlock) >> 6;
     const bool clip = a.rule.clip != 0u;
     uint64_t evald = 0, tested = 0, closed = 0;
     const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n;
     for (int64_t k = wave; k < n; k += nwaves) {
+        const uint32_t lane = lane_id_fresh();  // taken afresh per colour (nothing derived from it held across)
         const int64_t c = a.list ? (int64_t)a.list[k] : k;
         const ColorConst cc = a.cc[c];
         const bool cube = cube_branch_only(cc, a.nr - 1, a.ra, a.rb);
@@ -346,6 +348,7 @@ __global__ __launch_bounds__(kRayBlock) void k_best_pair(RayArgs a) {
             }
         }
     }
+    const uint32_t lane = lane_id_fresh();
     if (a.counts && lane == 0) {
         if (evald) atomicAdd(&a.counts[0], (unsigned long long)evald);
         if (tested) atomicAdd(&a.counts[1], (unsigned long long)tested);
