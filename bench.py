@@ -81,12 +81,12 @@ FLOPS_CELL = 84
 MEASURED_COUNTERS = {
     "count_pass": {"sources_sha256": "8d5db1ca4e1ecbf2eb7bf84b3a44d0095d508d13799ae4b1c566f99ee45db1f1",
                    "traffic_bytes": 1954010, "valu_issue": 0.55},
-    "colour_resolve": {"sources_sha256": "5f04fba42aaf06dba46d463ff3ca8adc7ca872cd8390d3d0e828ca9737aa9518",
-                   "traffic_bytes": 4325181759, "valu_issue": 0.973},
+    "colour_resolve": {"sources_sha256": "a4ffdde22cb3de37cf578ab32320ad947b83443dca00787081c9cdf764e43b32",
+                   "traffic_bytes": 4325316222, "valu_issue": 0.977},
     "cube_table": {"sources_sha256": "8d5db1ca4e1ecbf2eb7bf84b3a44d0095d508d13799ae4b1c566f99ee45db1f1",
                    "traffic_bytes": 3568624747, "valu_issue": 0.988},
-    "ray_search": {"sources_sha256": "b92aeef109e78ea8c4d7c5bbfbad9e5f540b4519acaa6e329edf5bebb5731aba",
-                   "traffic_bytes": 6321723100, "valu_issue": 0.841},
+    "ray_search": {"sources_sha256": "3c2cec7d752e03cb2114e6688051e5a3378cc20c9faaa7fedd732776bb89eaaa",
+                   "traffic_bytes": 6322466458, "valu_issue": 0.84},
 }
 KERNEL_SOURCES = {
     "count_pass": ("cvib_search.hip", "cvib_device.h", "cvib_kernels.h"),
