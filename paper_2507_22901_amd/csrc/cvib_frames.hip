@@ -79,8 +79,10 @@ __global__ void k_bitmap_mark(const uint8_t* __restrict__ px, int64_t npix,
         const uint32_t id = ((uint32_t)px[3 * p] << 16) | ((uint32_t)px[3 * p + 1] << 8) | px[3 * p + 2];
         const uint32_t bit = 1u << (id & 31u);
         uint32_t* word = bits + (id >> 5);
-        // most pixels repeat a colour already marked: read first, then set
-        if ((__builtin_nontemporal_load(word) & bit) == 0u) atomicOr(word, bit);
+        // most pixels repeat a colour already marked: read first (a cached
+        // load; a stale zero only costs a redundant atomic, and a set bit is
+        // final), then set
+        if ((*word & bit) == 0u) atomicOr(word, bit);
     }
 }
 
