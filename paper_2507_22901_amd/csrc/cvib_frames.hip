@@ -584,12 +584,12 @@ __device__ __forceinline__ float lane_float(float v, int src) {
 // Exact predicate of candidate (i, j) for one lane; false when not live.
 __device__ __forceinline__ bool verify_candidate(const ColorConst& cc, const Angles& ang, const Geom& g,
                                                  const RuleDev& rule, double ra, double rb, int32_t i,
-                                                 int32_t j, bool live) {
+                                                 int32_t j, bool live, bool cube) {
     double sn, co;
     ang.get(j, sn, co);
     const double rr = (double)(i + 1);
     float fp[3], fm[3];
-    pair_linear_w(cc, g, (rr * ra) * sn, (rr * rb) * co, fp, fm);
+    pair_linear_w(cc, g, (rr * ra) * sn, (rr * rb) * co, fp, fm, cube);
     const bool both = live && in_unit_cube(fp) && in_unit_cube(fm);
     const bool need = rule.clip ? live : both;
     bool ok = false;
@@ -606,11 +606,11 @@ __device__ __forceinline__ bool verify_candidate(const ColorConst& cc, const Ang
 // Wave-uniform arguments and result.
 __device__ __forceinline__ uint32_t climb_ray(const ColorConst& cc, const Angles& ang, const Geom& g,
                                               const RuleDev& rule, double ra, double rb, int32_t nr,
-                                              int32_t j, int32_t i_start, uint32_t best) {
+                                              int32_t j, int32_t i_start, uint32_t best, bool cube) {
     const int lane = threadIdx.x & 63;
     for (int32_t blk = 0, i0 = i_start; blk < kClimbBlocks && i0 < nr; ++blk, i0 += 64) {
         const int32_t i = i0 + lane;
-        const bool ok = verify_candidate(cc, ang, g, rule, ra, rb, min(i, nr - 1), j, i < nr);
+        const bool ok = verify_candidate(cc, ang, g, rule, ra, rb, min(i, nr - 1), j, i < nr, cube);
         const uint32_t top = wave_max_full(ok ? best_key(i, j) : 0u);
         if (top == 0u) break;
         best = max(best, top);
@@ -651,6 +651,8 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
         if (lane < nb) rk = half ? 25.0f * (p[lane] + p[lane + kBins / 2]) : 50.0f * p[lane];
         const float logit = p[kBins];
         const ColorConst cc = a.cc[c];
+        // the cube branch of the inverse companding holds over the whole grid
+        const bool cube = cube_branch_only(cc, a.nr - 1, a.ra, a.rb);
         uint32_t best = 0;
         float top_pred = 0.0f;  // the largest predicted bin radius (Delta E)
         if (logit >= a.tau) {
@@ -681,14 +683,14 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
                     const int32_t i = (int32_t)rintf(rr_t) - 1;
                     const int32_t j = j_lo + (u < ncand ? q : 0);
                     const bool live = u < ncand && i >= 0 && i < a.nr;
-                    const bool ok = verify_candidate(cc, ang, a.g, a.rule, a.ra, a.rb, i, j, live);
+                    const bool ok = verify_candidate(cc, ang, a.g, a.rule, a.ra, a.rb, i, j, live, cube);
                     bb = max(bb, wave_max_full(ok ? best_key(i, j) : 0u));
                 }
                 best = max(best, bb);
             }
             if (best) {
                 best = climb_ray(cc, ang, a.g, a.rule, a.ra, a.rb, a.nr, (int32_t)(0xFFFFu - (best & 0xFFFFu)),
-                                 (int32_t)(best >> 16) + 1, best);
+                                 (int32_t)(best >> 16) + 1, best, cube);
                 for (int b = 0; b < nb; ++b) {
                     const uint64_t sel = __ballot(lane < nb && rank == b);
                     const int bin = (int)__builtin_ctzll(sel);
@@ -706,12 +708,12 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
                         const bool live = lane < span * per && q < nrays && i < a.nr;
                         const int32_t j = j_lo + min(q, nrays - 1);
                         const bool ok = verify_candidate(cc, ang, a.g, a.rule, a.ra, a.rb, min(i, a.nr - 1), j,
-                                                         live);
+                                                         live, cube);
                         const uint32_t top = wave_max_full(ok ? best_key(i, j) : 0u);
                         if (top == 0u) continue;
                         best = climb_ray(cc, ang, a.g, a.rule, a.ra, a.rb, a.nr,
                                          (int32_t)(0xFFFFu - (top & 0xFFFFu)), (int32_t)(top >> 16) + 1,
-                                         max(best, top));
+                                         max(best, top), cube);
                     }
                 }
                 // mirrors of the second half-turn never win the tie on j
@@ -721,11 +723,11 @@ __global__ __launch_bounds__(256, 6) void k_propose_verify(ProposeArgs a) {
                     const int32_t j = bj + (lane & 15) - 8, i = bi + 1 + (lane >> 4);
                     const bool live = j >= 0 && j < jend && j != bj && i < a.nr;
                     const bool ok = verify_candidate(cc, ang, a.g, a.rule, a.ra, a.rb, min(i, a.nr - 1),
-                                                     live ? j : bj, live);
+                                                     live ? j : bj, live, cube);
                     const uint32_t top = wave_max_full(ok ? best_key(i, j) : 0u);
                     if (top == 0u) break;
                     best = climb_ray(cc, ang, a.g, a.rule, a.ra, a.rb, a.nr, (int32_t)(0xFFFFu - (top & 0xFFFFu)),
-                                     (int32_t)(top >> 16) + 1, max(best, top));
+                                     (int32_t)(top >> 16) + 1, max(best, top), cube);
                 }
             }
         }
