@@ -81,8 +81,8 @@ FLOPS_CELL = 84
 MEASURED_COUNTERS = {
     "count_pass": {"sources_sha256": "8d5db1ca4e1ecbf2eb7bf84b3a44d0095d508d13799ae4b1c566f99ee45db1f1",
                    "traffic_bytes": 1954010, "valu_issue": 0.55},
-    "colour_resolve": {"sources_sha256": "5cdf9c591f94ac3444dc5766b65866d1b6e464477acc78a9d9eb900aa12475c0",
-                   "traffic_bytes": 4325089749, "valu_issue": 0.977},
+    "colour_resolve": {"sources_sha256": "650461c7c89fcababf2c873334a000b1df8a0d66044c0a87e950d6eef70190c8",
+                   "traffic_bytes": 4324917436, "valu_issue": 0.979},
     "cube_table": {"sources_sha256": "8d5db1ca4e1ecbf2eb7bf84b3a44d0095d508d13799ae4b1c566f99ee45db1f1",
                    "traffic_bytes": 3568624747, "valu_issue": 0.988},
     "ray_search": {"sources_sha256": "3c2cec7d752e03cb2114e6688051e5a3378cc20c9faaa7fedd732776bb89eaaa",
